@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Throughput of the FFBS worldline sweep on one MI355X: site-slice updates/s.
+
+Workload: 16 chains of a 32x32 periodic lattice, L_tau = 160 (beta = 8, dtau = 0.05), U = 4,
+512 + 512 worldlines per chain, Gaussian HS field; synthetic seeded inputs already resident
+in HBM. One step = one pass of the hot path over that batch: restore the resident input
+(device-to-device copy), then one full sweep (forward filter + backward sample of every
+worldline, then the Gibbs draw of every field value) of all 16 chains, replayed from a captured
+hipGraph. Restoring keeps every step on the same synthetic input: with the permutation fixed to
+the identity the worldlines are distinguishable and a long chain clusters, which changes no
+amount of work but would make later steps depend on the chain's history.
+
+Prints one JSON line. `roofline` is for the dominant kernel (the forward filter), timed with HIP
+events on the stream it runs on; `cpu_baseline` times the FP64 oracle on host cores on a
+bounded sample (one chain, one sweep) and scales it to the same unit.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_mfma3": 2}
+HBM_PEAK_GBS = 8000.0
+PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS))
+    ap.add_argument("--chains", type=int, default=16)
+    ap.add_argument("--U", type=float, default=4.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 plain comparison")
+    ap.add_argument("--no-error", action="store_true", help="skip the error-vs-oracle sample")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fft_flops_per_particle_slice(N):
+    import math
+    # one complex 2D FFT pair per two worldlines = 5 N log2 N per worldline-slice, plus the
+    # pointwise ghat and W products, the sum and the rescale
+    return 5.0 * N * math.log2(N) + 6.0 * N
+
+
+def time_sweeps(S, A, P, A0, P0, first, n, stream):
+    """n steps; a step restores the resident synthetic input (device-to-device copies of the
+    field and the worldlines, ~20 MB) and runs one full sweep of every chain."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    with torch.cuda.stream(stream):
+        for i in range(n):
+            A.copy_(A0, non_blocking=True)
+            P.copy_(P0, non_blocking=True)
+            S.sweep(A, P, first + i, 1, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def time_forward(S, A, P, n, stream):
+    """Average duration of fh_forward_filter (potentials + forward kernel) over n launches,
+    HIP events recorded on the stream the kernels are launched on."""
+    import torch
+    from paper_2510_13866_amd import fhmc
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(n):
+        fhmc.fh_forward_filter(S.plan, A, P, 1000 + i, None, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def filter_error_sample(S, descs, aux, paths, sweep):
+    """Normwise relative error of the stored filters of 4 worldlines of chain 0 against the FP64
+    oracle: (max over rows, median over rows)."""
+    import numpy as np
+    from oracle import ffbs, hs, lattice
+    d = descs[0]
+    Gm = lattice.transfer_matrix(d.L, d.t, d.dtau)
+    W_up, W_dn = hs.potentials(aux[0], d.hs_kind, d.U, d.dtau)
+    errs = []
+    for p in (0, 255, 512, 1023):
+        W = W_up if p < d.n_up else W_dn
+        rows = []
+        for start, length in ffbs.block_schedule(d.L_tau, d.block_len, sweep):
+            a = paths[0][start, [p]].astype(np.int64)
+            e = paths[0][(start + length) % d.L_tau, [p]].astype(np.int64)
+            filt, _, _ = ffbs.forward_filter(Gm, W, start, length, a, e)
+            rows.append(filt[0, 1:, :])
+        ref = np.concatenate(rows)
+        got = S.filters(0, p)
+        errs.extend(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1))
+    return float(np.max(errs)), float(np.median(errs))
+
+
+def cpu_baseline(desc, aux, paths):
+    """The oracle as it stands, one chain, one sweep, on the host cores."""
+    import numpy as np
+    from oracle import sweep as osweep
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    tab = osweep.ChainTables(desc)
+    t0 = time.perf_counter()
+    osweep.sweep(desc, aux, paths, 0, tab)
+    dt = time.perf_counter() - t0
+    return {"value": desc.N * desc.L_tau / dt, "unit": "site-slice updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "1 chain x 1 sweep of 32x32, L_tau=160, 512+512 worldlines (%.1f s)" % dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(chains are independent; see the sharding notes). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2510_13866_amd import fhmc
+    from paper_2510_13866_amd.sampler import Sampler
+
+    descs = synth.config_32x32(args.U, n_chains=args.chains)
+    aux = [synth.initial_aux(d) for d in descs]
+    paths = [synth.initial_paths(d) for d in descs]
+    stream = torch.cuda.Stream()
+    prec = PRECISIONS[args.precision]
+    sites = sum(d.N * d.L_tau for d in descs)
+
+    log("bench: %s, %d chains 32x32 L_tau=160, warmup %d, steps %d" %
+        (args.precision, args.chains, args.warmup, args.steps))
+    S = Sampler(descs, prec, fhmc.FH_FLAG_GRAPH)
+    A0, P0 = S.pack_aux(aux), S.pack_paths(paths)
+    A, P = A0.clone(), P0.clone()
+    torch.cuda.synchronize()
+    time_sweeps(S, A, P, A0, P0, 0, args.warmup, stream)
+    ms = time_sweeps(S, A, P, A0, P0, args.warmup, args.steps, stream)
+    code, _ = S.status()
+    if code != 0:
+        raise RuntimeError("device status after sweeps: " + fhmc.fh_strerror(code))
+    ms_step = ms / args.steps
+    value = sites * args.steps / (ms / 1e3)
+    log("  %.3f ms/sweep, %.3e site-slice updates/s" % (ms_step, value))
+
+    # dominant kernel: the forward filter
+    nf = max(3, min(10, args.steps))
+    fwd_ms = time_forward(S, A, P, nf, stream)
+    particle_slices = sum(d.n_particles * (d.L_tau - 1) for d in descs)
+    N = descs[0].N
+    flops = particle_slices * fft_flops_per_particle_slice(N)
+    tflops = flops / (fwd_ms / 1e3) / 1e12
+    peak = PEAKS_TFLOPS["fp64" if args.precision == "fp64" else "fp32"]
+    roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(tflops / peak, 4), "traffic": None,
+            "kernel": "forward filter (k_forward_fft)", "ms_per_launch": round(fwd_ms, 4),
+            "flops_per_launch": flops}
+    log("  forward filter %.3f ms/launch, %.2f TFLOP/s" % (fwd_ms, tflops))
+
+    extra = {}
+    if not args.no_error:
+        # fresh state so the sampled particles' oracle filters are cheap to rebuild
+        A2, P2 = S.pack_aux(aux), S.pack_paths(paths)
+        fhmc.fh_forward_filter(S.plan, A2, P2, 1, None, stream)
+        torch.cuda.synchronize()
+        emax, emed = filter_error_sample(S, descs, aux, paths, 1)
+        extra["filter_err_vs_fp64_oracle"] = {"max": emax, "median": emed,
+                                              "sample": "4 worldlines of chain 0, all 159 rows"}
+        log("  filter error vs oracle: max %.2e median %.2e" % (emax, emed))
+    S.close()
+
+    if not args.no_plain and args.precision != "fp64":
+        S64 = Sampler(descs, fhmc.FH_FP64, fhmc.FH_FLAG_GRAPH)
+        A06, P06 = S64.pack_aux(aux), S64.pack_paths(paths)
+        A6, P6 = A06.clone(), P06.clone()
+        torch.cuda.synchronize()
+        time_sweeps(S64, A6, P6, A06, P06, 0, 1, stream)
+        k = max(2, args.steps // 4)
+        ms64 = time_sweeps(S64, A6, P6, A06, P06, 1, k, stream) / k
+        extra["fp64_plain"] = {"ms_per_step": round(ms64, 4),
+                               "value": sites / (ms64 / 1e3)}
+        extra["speedup_vs_fp64_plain"] = round(ms64 / ms_step, 3)
+        S64.close()
+        log("  fp64 plain %.3f ms/sweep" % ms64)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("  cpu baseline (oracle, 1 chain, 1 sweep)...")
+        cpu = cpu_baseline(descs[0], aux[0], paths[0])
+
+    out = {
+        "metric": "site-slice updates/s at 32x32 L_tau=160",
+        "value": value,
+        "unit": "site-slice updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "FFBS sweep, %d chains x 32x32 lattice, L_tau=160, dtau=0.05, "
+                               "U=%g, 512+512 worldlines, Gaussian field" % (args.chains, args.U),
+                   "chains": args.chains, "L": 32, "L_tau": 160, "precision": args.precision,
+                   "graph": True},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * fh.h — C ABI of the MI355X (gfx950) FFBS worldline-sweep library.
+ *
+ * The library samples the joint measure of fermion worldlines and Hubbard-Stratonovich (HS)
+ * fields of the determinant-free auxiliary-variable MCMC of Kong, Feng, Xie and Wu
+ * ("FFT-Accelerated Auxiliary Variable MCMC for Fermionic Lattice Models", eq. joint, with every
+ * permutation fixed to the identity). One sweep redraws every worldline block by forward
+ * filtering / backward sampling (Sec. 3.5.2) and then every field value from its exact
+ * conditional (Sec. 3.5.4 / 3.5.5).
+ *
+ * Conventions used by every entry point
+ *  - Lattice: L x L periodic square lattice, N = L*L sites, site index i = x + L*y.
+ *  - Worldlines are held in the site basis: paths[l][p] is the site of particle p on imaginary
+ *    time slice l (0 <= l < L_tau); particles 0..n_up-1 are spin up, n_up..n_up+n_dn-1 spin down.
+ *    A path weighs prod_l W_{l,spin}(r_l) G(r_{l+1} - r_l), G the real-space hopping kernel
+ *    (inverse Fourier transform of exp(-dtau eps_k), eq. Tkk / Sec. 3.3), r_{L_tau} = r_0.
+ *  - Fields: aux[l][i], Gaussian sigma (FH_HS_GAUSS, eq. gaussHS) or Ising s = +-1.0
+ *    (FH_HS_HIRSCH, eq. hirsch). Site potentials: Gaussian W_up = W_dn = exp(a*sigma),
+ *    a = sqrt(|U| dtau); Ising W_up = exp(lambda*s), W_dn = exp(-lambda*s),
+ *    cosh(lambda) = exp(dtau U / 2).
+ *  - Batches: a plan holds n_chains independent chains, possibly of different shapes. All
+ *    per-chain arrays are packed one chain after the other; fh_layout() gives the offsets.
+ *      aux      : sum_c L_tau*N elements, double (FH_FP64) or float (FH_FP32, FH_FP32_MFMA3)
+ *      paths    : sum_c L_tau*n_particles int32
+ *      logZ     : sum_c n_particles double (per particle)
+ *  - Memory: every array argument is a DEVICE pointer, owned by the caller, that must stay
+ *    valid until the work queued on `stream` has finished. The plan owns only its workspace.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream). Calls enqueue work and
+ *    return without synchronising, except fh_get_status and fh_get_filters' row count.
+ *  - Errors: every call returns FH_OK (0) or a negative code. Argument and state errors are
+ *    reported synchronously; errors found by kernels (non-finite weights, a zero total weight,
+ *    a site index out of range in `paths`) are latched in a device status word that
+ *    fh_get_status reads. A plan is not thread-safe; calls on one plan must be serialised.
+ *  - Random numbers: Philox4x64-10 (Salmon et al., SC'11), key (seed, 0), counter
+ *    (index, slice, sweep, tag); tag 0: one uniform per (particle, slice, sweep) for backward
+ *    sampling, tag 1: one draw per (site, slice, sweep) for the field. Results therefore depend
+ *    only on (state, sweep index, seed), not on batch composition or launch shape.
+ */
+#ifndef FH_H
+#define FH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fh_plan_s* fh_plan;
+typedef void* fh_stream; /* hipStream_t */
+
+enum fh_status {
+    FH_OK = 0,
+    FH_ERR_INVALID_ARG = -1, /* bad descriptor, null pointer, size or index           */
+    FH_ERR_UNSUPPORTED = -2, /* valid request this build does not implement (e.g. L)   */
+    FH_ERR_OOM = -3,         /* device allocation failed                               */
+    FH_ERR_HIP = -4,         /* a HIP runtime call failed                              */
+    FH_ERR_NONFINITE = -5,   /* device: a normaliser or weight total was NaN or Inf    */
+    FH_ERR_ZERO_WEIGHT = -6, /* device: a backward-sampling weight total was zero      */
+    FH_ERR_STATE = -7,       /* call order violated (e.g. backward before forward)     */
+    FH_ERR_BAD_PATH = -8     /* device: a site index in `paths` was outside [0, N)     */
+};
+
+enum fh_hs_kind { FH_HS_GAUSS = 0, FH_HS_HIRSCH = 1 };
+
+enum fh_precision {
+    FH_FP64 = 0,      /* plain path: FP64 FFT convolution, FP64 filters                       */
+    FH_FP32 = 1,      /* FP32 FFT convolution and filters; FP64 normaliser and CDF            */
+    FH_FP32_MFMA3 = 2 /* FP32 filters, convolution as the separable real circulant on MFMA
+                         with three-term split-bf16 products; FP64 normaliser and CDF; L<=32  */
+};
+
+enum fh_flags {
+    FH_FLAG_NONE = 0,
+    FH_FLAG_GRAPH = 1 /* fh_sweep replays a captured hipGraph instead of eager launches */
+};
+
+/* One chain. block_len: FFBS block length B (0 = L_tau, one block closing the ring);
+ * blocks of a sweep s start at o_s + j*B (mod L_tau), o_s = (s*floor(B/2)) mod L_tau,
+ * the last one shorter when B does not divide L_tau; endpoints stay fixed within a sweep.
+ * Requirements: L in {2..64} with L = 2^a 3^b (L <= 32 for FH_FP32_MFMA3), L_tau >= 2,
+ * n_up, n_dn >= 0 with n_up + n_dn >= 1, block_len = 0 or 2 <= block_len <= L_tau,
+ * t > 0, dtau > 0, U finite (U >= 0 for FH_HS_HIRSCH), all finite. */
+typedef struct {
+    int32_t L, L_tau, n_up, n_dn, hs_kind, block_len;
+    double t, U, dtau;
+    uint64_t seed;
+} fh_chain_desc;
+
+/* Element offsets and counts of one chain inside the packed batch arrays. */
+typedef struct {
+    int64_t aux_offset, aux_count;           /* aux: L_tau*N elements            */
+    int64_t path_offset, path_count;         /* paths: L_tau*n_particles int32   */
+    int64_t particle_offset;                 /* per-particle arrays (logZ)       */
+    int32_t L, N, L_tau, n_particles;
+} fh_chain_layout;
+
+/* Creates a plan for n_chains chains: validates every descriptor, builds the hopping tables
+ * (exp(-dtau eps_k) of Sec. 3.3 and its real-space kernel), picks the FFT radix plan per L and
+ * allocates the workspace (filters of every particle: L_tau*N values each in the plan's
+ * precision). Synchronous. *out is NULL on failure. */
+int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t precision,
+            uint32_t flags);
+int fh_destroy(fh_plan plan);
+
+/* Layout of chain `chain` in the packed arrays; totals over the batch via fh_sizes. */
+int fh_layout(fh_plan plan, int32_t chain, fh_chain_layout* out);
+int fh_sizes(fh_plan plan, int64_t* aux_elems, int64_t* path_elems, int64_t* particles);
+
+/* Forward filtering (Sec. 3.5.2, eq. ffbsFwd, site basis) of every block of every particle
+ * for sweep `sweep`, given the field `aux` and the current worldlines `paths` (read for the
+ * block endpoints only): f_0 = W(a) delta_a, f_j = W . (G * f_{j-1}), each f_j rescaled by its
+ * sum with the logarithms accumulated in FP64; the normalised filters stay in the plan for
+ * fh_backward_sample. logZ (nullable): per particle, the sum over its blocks of
+ * log Z_block = log [(G * f_{n-1})(end site)]. */
+int fh_forward_filter(fh_plan plan, const void* aux, const int32_t* paths, uint64_t sweep,
+                      double* logZ, fh_stream stream);
+
+/* Backward sampling (Sec. 3.5.2, the exact conditional P(r_j | r_{j+1}) ∝ f_j(r) G(r_{j+1}-r))
+ * of every block interior, from the filters of the last fh_forward_filter, which must have been
+ * called with the same `sweep` and the same `paths` contents (FH_ERR_STATE otherwise).
+ * Inverse CDF in site order with an FP64 running sum; the draw is the smallest site whose
+ * running sum exceeds u * total. `paths` is updated in place (block endpoints are kept). */
+int fh_backward_sample(fh_plan plan, int32_t* paths, uint64_t sweep, fh_stream stream);
+
+/* Exact Gibbs draw of the whole field given the worldlines (Sec. 3.5.4: Ising,
+ * P(s=+1) = (1 + tanh(lambda m))/2, m = n_up - n_dn; Sec. 3.5.5, eq. gaussCond: Gaussian,
+ * sigma ~ N(a (n - 1/2), 1), n = n_up + n_dn), counts taken from `paths`. `aux` is overwritten. */
+int fh_gibbs_aux(fh_plan plan, const int32_t* paths, void* aux, uint64_t sweep,
+                 fh_stream stream);
+
+/* n_sweeps full sweeps, sweep indices first_sweep .. first_sweep+n_sweeps-1: forward filter,
+ * backward sample, Gibbs field draw, in place on aux and paths. With FH_FLAG_GRAPH the sweep
+ * is captured once per (aux, paths) pair and replayed. */
+int fh_sweep(fh_plan plan, void* aux, int32_t* paths, uint64_t first_sweep, int32_t n_sweeps,
+             fh_stream stream);
+
+/* log Z_path and its gradient. log Z_path = sum_p log Z_p, Z_p the weight of all closed paths
+ * of particle p through its current site at slice anchor_slice (one block of length L_tau),
+ * i.e. log p(anchor sites | field) + const; the HS prior is excluded. Hand-written adjoint:
+ * backward messages beta_j = G * (W_{j+1} . beta_{j+1}), d log Z / d log W_j(r) =
+ * f_j(r) beta_j(r) / Z, d/dt through d exp(-dtau eps_k)/dt in Fourier space.
+ * logZ: per chain [n_chains] (nullable); grad_aux: packed like aux, overwritten, in the
+ * plan's precision, d log Z_path / d aux(l, r) (nullable); grad_t: [n_chains] (nullable).
+ * Accumulation into grad_aux uses atomics: the last bits may vary between calls. */
+int fh_logZ_grad(fh_plan plan, const void* aux, const int32_t* paths, int32_t anchor_slice,
+                 double* logZ, void* grad_aux, double* grad_t, fh_stream stream);
+
+/* Replaces the hopping amplitude of every chain (t: host array [n_chains], each > 0) and
+ * rebuilds the kernel tables. Synchronous; invalidates stored filters. */
+int fh_set_hopping(fh_plan plan, const double* t);
+
+/* Synchronises the device and returns the first device-side error latched since the last
+ * call (FH_OK if none) and the chain it occurred in (-1 if none); clears the latch. */
+int fh_get_status(fh_plan plan, int32_t* code, int32_t* first_chain);
+
+/* Copies the normalised filter rows stored for (chain, particle) by the last forward filter
+ * into dst (device, capacity elements of the plan's precision). Rows are N values each:
+ * for fh_forward_filter the interior rows j = 1..n-1 of each block in block order
+ * (L_tau - n_blocks rows); after fh_logZ_grad the L_tau rows j = 0..L_tau-1 of the ring.
+ * *n_rows receives the row count. Synchronous. */
+int fh_get_filters(fh_plan plan, int32_t chain, int32_t particle, void* dst, int64_t capacity,
+                   int64_t* n_rows, fh_stream stream);
+
+/* Static description of an error code. */
+const char* fh_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FH_H */

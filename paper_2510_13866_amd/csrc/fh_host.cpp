@@ -1,0 +1,517 @@
+// Host side of the FFBS library: plan construction (validation, kernel tables, work lists,
+// workspace), the C ABI entry points and hipGraph capture of a sweep.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <new>
+#include <vector>
+
+#include "../../include/fh.h"
+#include "../../include/fh_debug.h"
+#include "fh_internal.h"
+#include "fh_philox.h"
+
+using namespace fh;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Modified Bessel function I_n(x), n >= 0, x >= 0, by its power series
+// sum_k (x/2)^(2k+n) / (k! (k+n)!) — every term positive, so the sum keeps relative accuracy.
+double bessel_i(int n, double x) {
+    if (x == 0.0) return n == 0 ? 1.0 : 0.0;
+    const double h = 0.5 * x;
+    double term = exp(n * log(h) - lgamma((double)n + 1.0));
+    double sum = term;
+    for (int k = 0; k < 1000; ++k) {
+        term *= h * h / ((k + 1.0) * (k + 1.0 + n));
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+// g(d) = sum_{n = d (mod L)} I_n(2 t dtau): the inverse Fourier transform of
+// exp(2 t dtau cos(2 pi m / L)) along one dimension (generating function of I_n).
+void kernel_table(int L, double t, double dtau, double* g) {
+    const double x = 2.0 * t * dtau;
+    const int nmax = 3 * L + 40;
+    for (int d = 0; d < L; ++d) g[d] = 0.0;
+    for (int n = -nmax; n <= nmax; ++n) {
+        int d = ((n % L) + L) % L;
+        g[d] += bessel_i(n < 0 ? -n : n, x);
+    }
+}
+
+void build_tables(const fh_chain_desc& d, double* tab) {
+    const int L = d.L, N = L * L;
+    std::vector<double> c(L);
+    for (int m = 0; m < L; ++m) c[m] = cos(2.0 * kPi * m / L);
+    for (int ky = 0; ky < L; ++ky)
+        for (int kx = 0; kx < L; ++kx) {
+            const double ck = c[kx] + c[ky];
+            const double gh = exp(2.0 * d.t * d.dtau * ck);
+            tab[kx + L * ky] = gh / N;                                // ghat / N
+            tab[N + kx + L * ky] = 2.0 * d.dtau * ck * gh / N;        // d ghat / d t / N
+        }
+    kernel_table(L, d.t, d.dtau, tab + 2 * N);                        // g[L]
+    double* tw = tab + 2 * N + L;                                     // exp(-2 pi i m / L)
+    for (int m = 0; m < L; ++m) {
+        tw[2 * m] = cos(2.0 * kPi * m / L);
+        tw[2 * m + 1] = -sin(2.0 * kPi * m / L);
+    }
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+int validate(const fh_chain_desc& d, int precision) {
+    RadixPlan rp;
+    if (d.L < 2 || d.L_tau < 2 || d.n_up < 0 || d.n_dn < 0 || d.n_up + d.n_dn < 1)
+        return FH_ERR_INVALID_ARG;
+    if ((int64_t)d.n_up + d.n_dn > (int64_t)1 << 20) return FH_ERR_INVALID_ARG;
+    if (d.L_tau > (1 << 20)) return FH_ERR_INVALID_ARG;
+    if (d.hs_kind != FH_HS_GAUSS && d.hs_kind != FH_HS_HIRSCH) return FH_ERR_INVALID_ARG;
+    if (!(d.block_len == 0 || (d.block_len >= 2 && d.block_len <= d.L_tau)))
+        return FH_ERR_INVALID_ARG;
+    if (!is_fin(d.t) || !is_fin(d.U) || !is_fin(d.dtau) || !(d.t > 0) || !(d.dtau > 0))
+        return FH_ERR_INVALID_ARG;
+    if (d.hs_kind == FH_HS_HIRSCH && d.U < 0) return FH_ERR_INVALID_ARG;
+    if (!default_radix_plan(d.L, &rp)) return FH_ERR_UNSUPPORTED;
+    if (precision == FH_FP32_MFMA3 && d.L > 32) return FH_ERR_UNSUPPORTED;
+    return FH_OK;
+}
+
+template <typename T>
+hipError_t dalloc(T** p, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    return hipMalloc((void**)p, bytes);
+}
+
+void free_device(fh::Device& d) {
+    void* ptrs[] = {d.chains, d.tables, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
+                    d.grad_tasks, d.draw_tasks, d.status, d.sweep};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    d = fh::Device();
+}
+
+void drop_graph(fh_plan p) {
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+    p->graph_aux = nullptr;
+    p->graph_paths = nullptr;
+}
+
+int hip_status(hipError_t e) {
+    if (e == hipSuccess) return FH_OK;
+    if (e == hipErrorOutOfMemory) return FH_ERR_OOM;
+    return FH_ERR_HIP;
+}
+
+#define FH_TRY(expr)                                 \
+    do {                                             \
+        hipError_t _e = (expr);                      \
+        if (_e != hipSuccess) return hip_status(_e); \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* fh_strerror(int code) {
+    switch (code) {
+        case FH_OK: return "ok";
+        case FH_ERR_INVALID_ARG: return "invalid argument";
+        case FH_ERR_UNSUPPORTED: return "unsupported configuration";
+        case FH_ERR_OOM: return "device out of memory";
+        case FH_ERR_HIP: return "HIP runtime error";
+        case FH_ERR_NONFINITE: return "non-finite weight or normaliser";
+        case FH_ERR_ZERO_WEIGHT: return "zero total weight in backward sampling";
+        case FH_ERR_STATE: return "call order violated";
+        case FH_ERR_BAD_PATH: return "site index in paths out of range";
+        default: return "unknown error";
+    }
+}
+
+int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t precision,
+            uint32_t flags) {
+    if (!out) return FH_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!descs || n_chains < 1) return FH_ERR_INVALID_ARG;
+    if (precision != FH_FP64 && precision != FH_FP32 && precision != FH_FP32_MFMA3)
+        return FH_ERR_INVALID_ARG;
+    if (flags & ~(uint32_t)FH_FLAG_GRAPH) return FH_ERR_INVALID_ARG;
+    for (int c = 0; c < n_chains; ++c) {
+        int v = validate(descs[c], precision);
+        if (v != FH_OK) return v;
+    }
+    fh_plan p = new (std::nothrow) fh_plan_s();
+    if (!p) return FH_ERR_OOM;
+    p->n_chains = n_chains;
+    p->precision = precision;
+    p->flags = flags;
+    p->real_size = precision == FH_FP64 ? 8 : 4;
+    p->descs.assign(descs, descs + n_chains);
+
+    int64_t aux = 0, path = 0, part = 0, tab = 0, filt = 0, blk = 0, slices = 0;
+    for (int c = 0; c < n_chains; ++c) {
+        const fh_chain_desc& d = descs[c];
+        ChainInfo ci;
+        memset(&ci, 0, sizeof(ci));
+        ci.L = d.L;
+        ci.N = d.L * d.L;
+        ci.L_tau = d.L_tau;
+        ci.n_up = d.n_up;
+        ci.n_dn = d.n_dn;
+        ci.np = d.n_up + d.n_dn;
+        ci.hs_kind = d.hs_kind;
+        ci.B = d.block_len == 0 ? d.L_tau : d.block_len;
+        ci.nb = (d.L_tau + ci.B - 1) / ci.B;
+        default_radix_plan(d.L, &ci.plan);
+        ci.gauss_a = sqrt(fabs(d.U) * d.dtau);
+        ci.hirsch_lambda = d.hs_kind == FH_HS_HIRSCH ? acosh(exp(d.dtau * d.U / 2.0)) : 0.0;
+        ci.coef_up = d.hs_kind == FH_HS_GAUSS ? ci.gauss_a : ci.hirsch_lambda;
+        ci.coef_dn = d.hs_kind == FH_HS_GAUSS ? ci.gauss_a : -ci.hirsch_lambda;
+        ci.seed = d.seed;
+        ci.aux_off = aux;
+        ci.path_off = path;
+        ci.part_off = part;
+        ci.tab_off = tab;
+        ci.filt_off = filt;
+        ci.blk_off = blk;
+        ci.slice_off = slices;
+        slices += d.L_tau;
+        aux += (int64_t)d.L_tau * ci.N;
+        path += (int64_t)d.L_tau * ci.np;
+        part += ci.np;
+        tab += tab_size(d.L);
+        filt += (int64_t)ci.np * d.L_tau * ci.N;
+        blk += (int64_t)ci.np * ci.nb;
+        p->max_N = std::max(p->max_N, ci.N);
+        p->max_L = std::max(p->max_L, ci.L);
+        p->max_np = std::max(p->max_np, ci.np);
+        p->chains.push_back(ci);
+    }
+    p->aux_elems = aux;
+    p->path_elems = path;
+    p->particles = part;
+    p->blk_elems = blk;
+    p->filt_elems = filt;
+    p->total_slices = slices;
+    p->tables.assign(tab, 0.0);
+    for (int c = 0; c < n_chains; ++c) build_tables(descs[c], p->tables.data() + p->chains[c].tab_off);
+
+    // Work lists, heaviest chains first so that the long tasks start early.
+    std::vector<int> order(n_chains);
+    for (int c = 0; c < n_chains; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const ChainInfo &x = p->chains[a], &y = p->chains[b];
+        return (int64_t)x.B * x.N > (int64_t)y.B * y.N;
+    });
+    std::vector<PairTask> fwd, grad;
+    std::vector<DrawTask> draw;
+    for (int c : order) {
+        const ChainInfo& ci = p->chains[c];
+        for (int spin = 0; spin < 2; ++spin) {
+            int p0 = spin ? ci.n_up : 0, p1 = spin ? ci.np : ci.n_up;
+            for (int q = p0; q < p1; q += 2) {
+                int qb = q + 1 < p1 ? q + 1 : -1;
+                for (int b = 0; b < ci.nb; ++b) fwd.push_back({c, q, qb, b});
+                grad.push_back({c, q, qb, 0});
+            }
+        }
+        for (int q = 0; q < ci.np; ++q)
+            for (int b = 0; b < ci.nb; ++b) draw.push_back({c, q, b, 0});
+    }
+    p->n_fwd_tasks = (int32_t)fwd.size();
+    p->n_grad_tasks = (int32_t)grad.size();
+    p->n_draw_tasks = (int32_t)draw.size();
+
+    hipError_t e = hipSuccess;
+    fh::Device& dv = p->d;
+    const size_t rs = p->real_size;
+    if (e == hipSuccess) e = dalloc(&dv.chains, sizeof(ChainInfo) * n_chains);
+    if (e == hipSuccess) e = dalloc(&dv.tables, sizeof(double) * p->tables.size());
+    if (e == hipSuccess) e = dalloc(&dv.W, rs * 2 * (size_t)aux);
+    if (e == hipSuccess) e = dalloc(&dv.wshift, sizeof(double) * 2 * (size_t)slices);
+    if (e == hipSuccess) e = dalloc(&dv.filt, rs * (size_t)filt);
+    if (e == hipSuccess) e = dalloc(&dv.blk_logz, sizeof(double) * (size_t)blk);
+    if (e == hipSuccess) e = dalloc(&dv.dt, sizeof(double) * (size_t)part);
+    if (e == hipSuccess) e = dalloc(&dv.fwd_tasks, sizeof(PairTask) * fwd.size());
+    if (e == hipSuccess) e = dalloc(&dv.grad_tasks, sizeof(PairTask) * grad.size());
+    if (e == hipSuccess) e = dalloc(&dv.draw_tasks, sizeof(DrawTask) * draw.size());
+    if (e == hipSuccess) e = dalloc(&dv.status, sizeof(int32_t) * 2);
+    if (e == hipSuccess) e = dalloc(&dv.sweep, sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMemcpy(dv.chains, p->chains.data(), sizeof(ChainInfo) * n_chains, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dv.tables, p->tables.data(), sizeof(double) * p->tables.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dv.fwd_tasks, fwd.data(), sizeof(PairTask) * fwd.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dv.grad_tasks, grad.data(), sizeof(PairTask) * grad.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dv.draw_tasks, draw.data(), sizeof(DrawTask) * draw.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        int32_t st[2] = {0, -1};
+        e = hipMemcpy(dv.status, st, sizeof(st), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) {
+        uint64_t z = 0;
+        e = hipMemcpy(dv.sweep, &z, sizeof(z), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        free_device(dv);
+        if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+        delete p;
+        (void)hipGetLastError();
+        return hip_status(e);
+    }
+    *out = p;
+    return FH_OK;
+}
+
+int fh_destroy(fh_plan p) {
+    if (!p) return FH_ERR_INVALID_ARG;
+    (void)hipDeviceSynchronize();
+    drop_graph(p);
+    free_device(p->d);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    delete p;
+    return FH_OK;
+}
+
+int fh_layout(fh_plan p, int32_t chain, fh_chain_layout* out) {
+    if (!p || !out || chain < 0 || chain >= p->n_chains) return FH_ERR_INVALID_ARG;
+    const ChainInfo& c = p->chains[chain];
+    out->aux_offset = c.aux_off;
+    out->aux_count = (int64_t)c.L_tau * c.N;
+    out->path_offset = c.path_off;
+    out->path_count = (int64_t)c.L_tau * c.np;
+    out->particle_offset = c.part_off;
+    out->L = c.L;
+    out->N = c.N;
+    out->L_tau = c.L_tau;
+    out->n_particles = c.np;
+    return FH_OK;
+}
+
+int fh_sizes(fh_plan p, int64_t* aux_elems, int64_t* path_elems, int64_t* particles) {
+    if (!p) return FH_ERR_INVALID_ARG;
+    if (aux_elems) *aux_elems = p->aux_elems;
+    if (path_elems) *path_elems = p->path_elems;
+    if (particles) *particles = p->particles;
+    return FH_OK;
+}
+
+static hipError_t enqueue_forward(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
+    hipError_t e = launch_potentials(p, aux, s);
+    if (e != hipSuccess) return e;
+    if (p->precision == FH_FP32_MFMA3) return launch_forward_mfma(p, aux, paths, s);
+    return launch_forward(p, aux, paths, s);
+}
+
+int fh_forward_filter(fh_plan p, const void* aux, const int32_t* paths, uint64_t sweep,
+                      double* logZ, fh_stream stream) {
+    if (!p || !aux || !paths) return FH_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    FH_TRY(launch_set_sweep(p, sweep, s));
+    FH_TRY(enqueue_forward(p, aux, paths, s));
+    if (logZ) FH_TRY(launch_logz_reduce(p, logZ, s));
+    p->have_filters = true;
+    p->filters_are_ring = false;
+    p->last_sweep = sweep;
+    p->last_paths = paths;
+    return FH_OK;
+}
+
+int fh_backward_sample(fh_plan p, int32_t* paths, uint64_t sweep, fh_stream stream) {
+    if (!p || !paths) return FH_ERR_INVALID_ARG;
+    if (!p->have_filters || p->filters_are_ring || sweep != p->last_sweep || paths != p->last_paths)
+        return FH_ERR_STATE;
+    hipStream_t s = (hipStream_t)stream;
+    FH_TRY(launch_set_sweep(p, sweep, s));
+    FH_TRY(launch_backward(p, paths, s));
+    return FH_OK;
+}
+
+int fh_gibbs_aux(fh_plan p, const int32_t* paths, void* aux, uint64_t sweep, fh_stream stream) {
+    if (!p || !paths || !aux) return FH_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    FH_TRY(launch_set_sweep(p, sweep, s));
+    FH_TRY(launch_gibbs(p, paths, aux, s));
+    p->have_filters = false;
+    return FH_OK;
+}
+
+// One sweep reading its index from the device word, as recorded into a graph.
+static hipError_t enqueue_sweep_body(fh_plan p, void* aux, int32_t* paths, hipStream_t s) {
+    hipError_t e = enqueue_forward(p, aux, paths, s);
+    if (e == hipSuccess) e = launch_backward(p, paths, s);
+    if (e == hipSuccess) e = launch_gibbs(p, paths, aux, s);
+    return e;
+}
+
+static int capture_sweep(fh_plan p, void* aux, int32_t* paths) {
+    drop_graph(p);
+    hipStream_t cs = p->capture_stream;
+    FH_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_sweep_body(p, aux, paths, cs);
+    if (e == hipSuccess) e = launch_bump_sweep(p, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_status(e != hipSuccess ? e : e2);
+    }
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_status(e);
+    }
+    p->graph = g;
+    p->graph_exec = ge;
+    p->graph_aux = aux;
+    p->graph_paths = paths;
+    return FH_OK;
+}
+
+int fh_sweep(fh_plan p, void* aux, int32_t* paths, uint64_t first_sweep, int32_t n_sweeps,
+             fh_stream stream) {
+    if (!p || !aux || !paths || n_sweeps < 0) return FH_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n_sweeps == 0) return FH_OK;
+    if (p->flags & FH_FLAG_GRAPH) {
+        if (!p->graph_exec || p->graph_aux != aux || p->graph_paths != paths) {
+            // capture on the plan's stream after the caller's queued work is done
+            FH_TRY(hipStreamSynchronize(s));
+            int rc = capture_sweep(p, aux, paths);
+            if (rc != FH_OK) return rc;
+        }
+        FH_TRY(launch_set_sweep(p, first_sweep, s));
+        for (int32_t i = 0; i < n_sweeps; ++i) FH_TRY(hipGraphLaunch(p->graph_exec, s));
+    } else {
+        for (int32_t i = 0; i < n_sweeps; ++i) {
+            FH_TRY(launch_set_sweep(p, first_sweep + (uint64_t)i, s));
+            FH_TRY(enqueue_sweep_body(p, aux, paths, s));
+        }
+    }
+    p->have_filters = false;
+    return FH_OK;
+}
+
+int fh_logZ_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor_slice,
+                 double* logZ, void* grad_aux, double* grad_t, fh_stream stream) {
+    if (!p || !aux || !paths) return FH_ERR_INVALID_ARG;
+    for (const ChainInfo& c : p->chains)
+        if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    FH_TRY(launch_potentials(p, aux, s));
+    if (grad_aux) FH_TRY(launch_zero(grad_aux, (int64_t)p->real_size * p->aux_elems, s));
+    FH_TRY(launch_grad(p, aux, paths, anchor_slice, grad_aux, s));
+    FH_TRY(launch_grad_reduce(p, logZ, grad_t, s));
+    p->have_filters = true;
+    p->filters_are_ring = true;
+    return FH_OK;
+}
+
+int fh_set_hopping(fh_plan p, const double* t) {
+    if (!p || !t) return FH_ERR_INVALID_ARG;
+    for (int c = 0; c < p->n_chains; ++c)
+        if (!is_fin(t[c]) || !(t[c] > 0)) return FH_ERR_INVALID_ARG;
+    FH_TRY(hipDeviceSynchronize());
+    for (int c = 0; c < p->n_chains; ++c) {
+        p->descs[c].t = t[c];
+        build_tables(p->descs[c], p->tables.data() + p->chains[c].tab_off);
+    }
+    FH_TRY(hipMemcpy(p->d.tables, p->tables.data(), sizeof(double) * p->tables.size(),
+                     hipMemcpyHostToDevice));
+    p->have_filters = false;
+    return FH_OK;
+}
+
+int fh_get_status(fh_plan p, int32_t* code, int32_t* first_chain) {
+    if (!p) return FH_ERR_INVALID_ARG;
+    FH_TRY(hipDeviceSynchronize());
+    int32_t st[2];
+    FH_TRY(hipMemcpy(st, p->d.status, sizeof(st), hipMemcpyDeviceToHost));
+    int32_t clear[2] = {0, -1};
+    FH_TRY(hipMemcpy(p->d.status, clear, sizeof(clear), hipMemcpyHostToDevice));
+    if (code) *code = st[0];
+    if (first_chain) *first_chain = st[0] == 0 ? -1 : st[1];
+    return FH_OK;
+}
+
+int fh_get_filters(fh_plan p, int32_t chain, int32_t particle, void* dst, int64_t capacity,
+                   int64_t* n_rows, fh_stream stream) {
+    if (!p || chain < 0 || chain >= p->n_chains) return FH_ERR_INVALID_ARG;
+    const ChainInfo& c = p->chains[chain];
+    if (particle < 0 || particle >= c.np) return FH_ERR_INVALID_ARG;
+    if (!p->have_filters) return FH_ERR_STATE;
+    const int64_t rows = p->filters_are_ring ? c.L_tau : c.L_tau - c.nb;
+    if (n_rows) *n_rows = rows;
+    if (!dst) return FH_OK;
+    if (capacity < rows * c.N) return FH_ERR_INVALID_ARG;
+    const char* src = (const char*)p->d.filt +
+                      p->real_size * (size_t)(c.filt_off + (int64_t)particle * c.L_tau * c.N);
+    hipStream_t s = (hipStream_t)stream;
+    FH_TRY(hipMemcpyAsync(dst, src, p->real_size * (size_t)(rows * c.N), hipMemcpyDeviceToDevice, s));
+    FH_TRY(hipStreamSynchronize(s));
+    return FH_OK;
+}
+
+// ---- host-only diagnostics ----------------------------------------------------------------
+
+int fh_debug_fft2d_host(double* data, int32_t L, int32_t inverse) {
+    RadixPlan rp;
+    if (!data || !default_radix_plan(L, &rp)) return FH_ERR_UNSUPPORTED;
+    const int N = L * L;
+    std::vector<cpx<double>> a(N), b(N), tw(L);
+    for (int i = 0; i < N; ++i) a[i] = {data[2 * i], data[2 * i + 1]};
+    for (int m = 0; m < L; ++m) tw[m] = {cos(2.0 * kPi * m / L), -sin(2.0 * kPi * m / L)};
+    cpx<double>* src = a.data();
+    cpx<double>* dst = b.data();
+    for (int dim = 0; dim < 2; ++dim) {
+        const int ls = dim == 0 ? L : 1, es = dim == 0 ? 1 : L;
+        int Ns = 1;
+        for (int st = 0; st < rp.n; ++st) {
+            const int pr = rp.rad[st];
+            for (int bf = 0; bf < L * (L / pr); ++bf) {
+                if (inverse)
+                    stockham_butterfly_rt<double, true>(pr, bf, L, Ns, ls, es, src, dst, tw.data());
+                else
+                    stockham_butterfly_rt<double, false>(pr, bf, L, Ns, ls, es, src, dst, tw.data());
+            }
+            Ns *= pr;
+            std::swap(src, dst);
+        }
+    }
+    for (int i = 0; i < N; ++i) {
+        data[2 * i] = src[i].re;
+        data[2 * i + 1] = src[i].im;
+    }
+    return FH_OK;
+}
+
+int fh_debug_kernel_table(int32_t L, double t, double dtau, double* out) {
+    if (!out || L < 2 || L > kMaxL || !(t > 0) || !(dtau > 0)) return FH_ERR_INVALID_ARG;
+    kernel_table(L, t, dtau, out);
+    return FH_OK;
+}
+
+int fh_debug_philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1,
+                    uint64_t* out) {
+    if (!out) return FH_ERR_INVALID_ARG;
+    u64x4 r = philox4x64_10(c0, c1, c2, c3, k0, k1);
+    out[0] = r.x0;
+    out[1] = r.x1;
+    out[2] = r.x2;
+    out[3] = r.x3;
+    return FH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Internal declarations shared by the host API (fh_host.cpp) and the kernels (fh_kernels.hip,
+// fh_mfma.hip). Nothing here is part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <utility>
+#include <vector>
+
+#include "../../include/fh.h"
+#include "fh_fft.h"
+
+namespace fh {
+
+// Per-chain parameters and offsets as the kernels see them (plain data, copied to the device).
+struct ChainInfo {
+    int32_t L, N, L_tau, n_up, n_dn, np, hs_kind, B, nb;
+    RadixPlan plan;           // FFT radix plan of one dimension (both dimensions are L)
+    double coef_up, coef_dn;  // log W_spin = coef_spin * aux
+    double gauss_a, hirsch_lambda;
+    uint64_t seed;
+    int64_t aux_off;   // packed aux / W offset (elements): aux[aux_off + l*N + r]
+    int64_t path_off;  // packed paths offset: paths[path_off + l*np + p]
+    int64_t part_off;  // per-particle arrays (logZ, dt)
+    int64_t tab_off;   // double tables: ghat[N]/N, dghat[N]/N, g[L], tw[2L]
+    int64_t filt_off;  // filter workspace: filt[filt_off + (p*L_tau + row)*N + r]
+    int64_t blk_off;   // per-(particle, block) log Z: blk[blk_off + p*nb + block]
+    int64_t slice_off; // index of this chain's slice 0 among all chains' slices
+};
+
+// Offsets of the tables of one chain inside the double table buffer, relative to tab_off.
+FH_HD inline int64_t tab_ghat(const ChainInfo& c) { return c.tab_off; }
+FH_HD inline int64_t tab_dghat(const ChainInfo& c) { return c.tab_off + c.N; }
+FH_HD inline int64_t tab_g(const ChainInfo& c) { return c.tab_off + 2 * c.N; }
+FH_HD inline int64_t tab_tw(const ChainInfo& c) { return c.tab_off + 2 * c.N + c.L; }
+inline int64_t tab_size(int L) { return 2 * (int64_t)L * L + L + 2 * L; }
+
+// Block of a sweep: start slice and length (the schedule of fh.h).
+FH_HD inline void block_of(const ChainInfo& c, uint64_t sweep, int b, int* start, int* len) {
+    const int o = (int)(((sweep % (uint64_t)c.L_tau) * (uint64_t)(c.B / 2)) % (uint64_t)c.L_tau);
+    *start = (o + b * c.B) % c.L_tau;
+    *len = (b < c.nb - 1) ? c.B : c.L_tau - (c.nb - 1) * c.B;
+}
+
+// Work items. Forward / gradient pairs share (chain, spin): p_b < 0 means a single particle.
+struct PairTask {
+    int32_t chain, p_a, p_b, block;
+};
+struct DrawTask {
+    int32_t chain, p, block, pad;
+};
+
+struct Device {
+    ChainInfo* chains = nullptr;
+    double* tables = nullptr;
+    void* W = nullptr;        // [2][sum L_tau*N] in plan precision (up, then down)
+    double* wshift = nullptr; // [2][total slices]: log W = log W~ + wshift per (spin, slice)
+    void* filt = nullptr;     // filter workspace, plan precision
+    double* blk_logz = nullptr;
+    double* dt = nullptr;     // per particle d log Z / d t
+    PairTask* fwd_tasks = nullptr;
+    PairTask* grad_tasks = nullptr;
+    DrawTask* draw_tasks = nullptr;
+    int32_t* status = nullptr;   // [0] first error code, [1] its chain
+    uint64_t* sweep = nullptr;   // sweep index read by the kernels
+};
+
+}  // namespace fh
+
+struct fh_plan_s {
+    int32_t n_chains = 0;
+    int32_t precision = 0;
+    uint32_t flags = 0;
+    std::vector<fh_chain_desc> descs;
+    std::vector<fh::ChainInfo> chains;
+    std::vector<double> tables;
+    int64_t aux_elems = 0, path_elems = 0, particles = 0, blk_elems = 0, filt_elems = 0;
+    int32_t n_fwd_tasks = 0, n_grad_tasks = 0, n_draw_tasks = 0;
+    int64_t total_slices = 0;
+    int32_t max_N = 0, max_L = 0, max_np = 0;
+    size_t real_size = 8;
+    fh::Device d;
+    // state
+    bool have_filters = false;
+    bool filters_are_ring = false;
+    uint64_t last_sweep = 0;
+    const int32_t* last_paths = nullptr;
+    // graph cache for fh_sweep
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    void* graph_aux = nullptr;
+    int32_t* graph_paths = nullptr;
+};
+
+namespace fh {
+
+// Kernel launchers (fh_kernels.hip / fh_mfma.hip). All enqueue on `s` and return hipError_t.
+hipError_t launch_set_sweep(fh_plan p, uint64_t sweep, hipStream_t s);
+hipError_t launch_bump_sweep(fh_plan p, hipStream_t s);
+hipError_t launch_potentials(fh_plan p, const void* aux, hipStream_t s);
+hipError_t launch_forward(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s);
+hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s);
+hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s);
+hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s);
+hipError_t launch_gibbs(fh_plan p, const int32_t* paths, void* aux, hipStream_t s);
+hipError_t launch_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
+                       void* grad_aux, hipStream_t s);
+hipError_t launch_grad_reduce(fh_plan p, double* logZ, double* grad_t, hipStream_t s);
+hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t s);
+
+size_t forward_lds_bytes(fh_plan p);
+size_t grad_lds_bytes(fh_plan p);
+
+}  // namespace fh

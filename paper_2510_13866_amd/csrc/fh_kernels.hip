@@ -1,0 +1,728 @@
+// gfx950 kernels of the FFBS worldline sweep: site potentials, FFT forward filter, backward
+// inverse-CDF sampler, occupancy + Gibbs field draw, and the adjoint of the forward filter.
+//
+// Forward filter (Sec. 3.5.2, eq. ffbsFwd in the site basis): one workgroup advances two
+// worldlines of the same (chain, spin) at once, packed as the real and imaginary parts of one
+// complex L x L tile: the kinetic step G * f is IFFT(ghat . FFT(f)) with a real, even ghat, so
+// it maps f_a + i f_b to (G * f_a) + i (G * f_b) exactly. The tile and a ping-pong buffer live
+// in LDS; each radix-2/3/4 Stockham stage is one butterfly per thread between barriers.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "fh_internal.h"
+#include "fh_philox.h"
+
+namespace fh {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+__device__ inline void set_status(int32_t* st, int code, int chain) {
+    if (atomicCAS(&st[0], 0, code) == 0) atomicExch(&st[1], chain);
+}
+
+// Largest c with key(c) <= v over chains sorted by that key.
+template <typename F>
+__device__ inline int find_chain(int n, int64_t v, F key) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (key(mid) <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Deterministic block sum of K doubles (same order every call). red: LDS, K*kWaves doubles.
+template <int K>
+__device__ inline void block_sum(double (&v)[K], double* red) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < K; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) red[i * kWaves + w] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        double s = 0.0;
+        for (int q = 0; q < kWaves; ++q) s += red[i * kWaves + q];
+        v[i] = s;
+    }
+    __syncthreads();
+}
+
+// 2D FFT of the L x L tile in A (S is scratch). Callers synchronise before the call; the
+// result is back in A because both dimensions take the same (even total) number of stages.
+template <typename T, bool INV>
+__device__ inline void fft2d(cpx<T>* A, cpx<T>* S, int L, const RadixPlan& rp,
+                             const cpx<T>* tw) {
+    cpx<T>* src = A;
+    cpx<T>* dst = S;
+    for (int dim = 0; dim < 2; ++dim) {
+        const int ls = dim == 0 ? L : 1, es = dim == 0 ? 1 : L;
+        int Ns = 1;
+        for (int st = 0; st < rp.n; ++st) {
+            const int p = rp.rad[st];
+            const int nbf = L * (L / p);
+            for (int b = threadIdx.x; b < nbf; b += blockDim.x)
+                stockham_butterfly_rt<T, INV>(p, b, L, Ns, ls, es, src, dst, tw);
+            __syncthreads();
+            Ns *= p;
+            cpx<T>* t = src;
+            src = dst;
+            dst = t;
+        }
+    }
+}
+
+template <typename T>
+struct FftLds {
+    cpx<T>* A;
+    cpx<T>* S;
+    cpx<T>* U;
+    cpx<T>* tw;
+    double* g;
+    double* red;
+};
+
+template <typename T>
+__device__ inline FftLds<T> carve(unsigned char* smem, int maxN, int maxL, bool third) {
+    FftLds<T> l;
+    size_t off = 0;
+    l.A = (cpx<T>*)(smem + off);
+    off += sizeof(cpx<T>) * maxN;
+    l.S = (cpx<T>*)(smem + off);
+    off += sizeof(cpx<T>) * maxN;
+    l.U = third ? (cpx<T>*)(smem + off) : nullptr;
+    if (third) off += sizeof(cpx<T>) * maxN;
+    l.tw = (cpx<T>*)(smem + off);
+    off += sizeof(cpx<T>) * maxL;
+    off = (off + 7) & ~(size_t)7;
+    l.g = (double*)(smem + off);
+    off += sizeof(double) * maxL;
+    l.red = (double*)(smem + off);
+    return l;
+}
+
+template <typename T>
+__device__ inline void load_chain_tables(const ChainInfo& c, const double* tables, FftLds<T>& l) {
+    const double* tw = tables + tab_tw(c);
+    const double* g = tables + tab_g(c);
+    for (int m = threadIdx.x; m < c.L; m += blockDim.x) {
+        l.tw[m] = {(T)tw[2 * m], (T)tw[2 * m + 1]};
+        l.g[m] = g[m];
+    }
+}
+
+__device__ inline int checked_site(int r, int N, int32_t* status, int chain) {
+    if (r < 0 || r >= N) {
+        set_status(status, FH_ERR_BAD_PATH, chain);
+        return 0;
+    }
+    return r;
+}
+
+// Forward recursion of one block for a pair of worldlines (Sec. 3.5.2):
+//   f~_0 = delta_a; h_j = W~_{start+j} . (G * f~_{j-1}); c_j = sum h_j; f~_j = h_j / c_j
+//   log Z = coef aux_start(a) + sum_j (log c_j + m_{start+j}) + log (G * f~_{len-1})(e),
+// with W~ = W exp(-m) the shifted potentials, shift[l] = m_spin(l) and log W = coef * aux.
+// Rows f~_j are stored at row + (j - jshift)*N for j >= 1 (and j = 0 when jshift == 0).
+// The last step's end weight is a direct FP64 sum with the real-space kernel g(dx) g(dy).
+template <typename T>
+__device__ void forward_pass(const ChainInfo& c, const double* tables, const T* Wsp,
+                             const double* shift, const T* auxc, double coef, int start, int len,
+                             int a_a, int e_a, int a_b,
+                             int e_b, bool has_b, T* row_a, T* row_b, int jshift, FftLds<T>& l,
+                             double* logz_a, double* logz_b, int32_t* status, int chain) {
+    const int N = c.N, L = c.L, L_tau = c.L_tau;
+    for (int r = threadIdx.x; r < N; r += blockDim.x) {
+        cpx<T> v = {r == a_a ? T(1) : T(0), (has_b && r == a_b) ? T(1) : T(0)};
+        l.A[r] = v;
+        if (jshift == 0) {
+            row_a[r] = v.re;
+            if (has_b) row_b[r] = v.im;
+        }
+    }
+    // log W_start(a) straight from the field: exact, and immune to underflow of W~(a)
+    double la = coef * (double)auxc[(int64_t)start * N + a_a];
+    double lb = has_b ? coef * (double)auxc[(int64_t)start * N + a_b] : 0.0;
+    const double* gh = tables + tab_ghat(c);
+    __syncthreads();
+    for (int j = 1; j < len; ++j) {
+        fft2d<T, false>(l.A, l.S, L, c.plan, l.tw);
+        for (int k = threadIdx.x; k < N; k += blockDim.x) {
+            const T m = (T)gh[k];
+            l.A[k].re *= m;
+            l.A[k].im *= m;
+        }
+        __syncthreads();
+        fft2d<T, true>(l.A, l.S, L, c.plan, l.tw);
+        const T* Wl = Wsp + (int64_t)((start + j) % L_tau) * N;
+        double s[2] = {0.0, 0.0};
+        for (int r = threadIdx.x; r < N; r += blockDim.x) {
+            const T w = Wl[r];
+            cpx<T> h = {l.A[r].re * w, l.A[r].im * w};
+            l.A[r] = h;
+            s[0] += (double)h.re;
+            s[1] += (double)h.im;
+        }
+        block_sum<2>(s, l.red);
+        if (!(s[0] > 0.0) || !isfinite(s[0]) || (has_b && (!(s[1] > 0.0) || !isfinite(s[1]))))
+            if (threadIdx.x == 0) set_status(status, FH_ERR_NONFINITE, chain);
+        const T ia = (T)(1.0 / s[0]);
+        const T ib = has_b ? (T)(1.0 / s[1]) : T(0);
+        const double m = shift[(start + j) % L_tau];
+        la += log(s[0]) + m;
+        if (has_b) lb += log(s[1]) + m;
+        T* ra = row_a + (int64_t)(j - jshift) * N;
+        T* rb = has_b ? row_b + (int64_t)(j - jshift) * N : nullptr;
+        for (int r = threadIdx.x; r < N; r += blockDim.x) {
+            cpx<T> v = {l.A[r].re * ia, l.A[r].im * ib};
+            l.A[r] = v;
+            ra[r] = v.re;
+            if (has_b) rb[r] = v.im;
+        }
+        __syncthreads();
+    }
+    const int eax = e_a % L, eay = e_a / L, ebx = e_b % L, eby = e_b / L;
+    double z[2] = {0.0, 0.0};
+    for (int r = threadIdx.x; r < N; r += blockDim.x) {
+        const int x = r % L, y = r / L;
+        int dx = eax - x, dy = eay - y;
+        dx += dx < 0 ? L : 0;
+        dy += dy < 0 ? L : 0;
+        z[0] += l.g[dx] * l.g[dy] * (double)l.A[r].re;
+        if (has_b) {
+            dx = ebx - x;
+            dy = eby - y;
+            dx += dx < 0 ? L : 0;
+            dy += dy < 0 ? L : 0;
+            z[1] += l.g[dx] * l.g[dy] * (double)l.A[r].im;
+        }
+    }
+    block_sum<2>(z, l.red);
+    *logz_a = la + log(z[0]);
+    *logz_b = has_b ? lb + log(z[1]) : 0.0;
+}
+
+// ---- kernels ----------------------------------------------------------------------------------
+
+__global__ void k_set_u64(uint64_t* p, uint64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+__global__ void k_bump_u64(uint64_t* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = *p + 1;
+}
+
+__global__ void k_zero(uint32_t* p, int64_t words) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// Site potentials of one (chain, slice) in log-domain-shifted form (eq. hirsch / eq. gaussHS):
+// log W_spin(l, r) = coef_spin * aux(l, r); the tables hold W~ = exp(log W - m_spin(l)) with
+// m_spin(l) = max_r log W_spin(l, r), so W~ <= 1 whatever the field, and m is kept in FP64 and
+// added back to log Z. Filters are normalised per step, so the shift changes nothing else.
+// W[0 .. aux_elems) holds spin up, W[aux_elems .. 2 aux_elems) spin down.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_potentials(const ChainInfo* __restrict__ chains,
+                                                         int n_chains, const T* __restrict__ aux,
+                                                         T* __restrict__ W, double* __restrict__ wshift,
+                                                         int64_t aux_elems, int64_t total_slices,
+                                                         int32_t* status) {
+    __shared__ double red[2 * kWaves];
+    const int gs = blockIdx.x;
+    const int ci = find_chain(n_chains, gs, [&](int i) { return chains[i].slice_off; });
+    const ChainInfo& c = chains[ci];
+    const int64_t base = c.aux_off + (int64_t)(gs - c.slice_off) * c.N;
+    double mu = -INFINITY, md = -INFINITY;
+    bool bad = false;
+    for (int r = threadIdx.x; r < c.N; r += blockDim.x) {
+        const double v = (double)aux[base + r];
+        bad |= !isfinite(v);
+        mu = fmax(mu, c.coef_up * v);
+        md = fmax(md, c.coef_dn * v);
+    }
+    if (bad) set_status(status, FH_ERR_NONFINITE, ci);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mu = fmax(mu, __shfl_xor(mu, o, 64));
+        md = fmax(md, __shfl_xor(md, o, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w] = mu;
+        red[kWaves + w] = md;
+    }
+    __syncthreads();
+    mu = red[0];
+    md = red[kWaves];
+    for (int q = 1; q < kWaves; ++q) {
+        mu = fmax(mu, red[q]);
+        md = fmax(md, red[kWaves + q]);
+    }
+    if (!isfinite(mu)) mu = 0.0;
+    if (!isfinite(md)) md = 0.0;
+    for (int r = threadIdx.x; r < c.N; r += blockDim.x) {
+        const double v = (double)aux[base + r];
+        W[base + r] = (T)exp(c.coef_up * v - mu);
+        W[aux_elems + base + r] = (T)exp(c.coef_dn * v - md);
+    }
+    if (threadIdx.x == 0) {
+        wshift[gs] = mu;
+        wshift[total_slices + gs] = md;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_forward_fft(
+    const ChainInfo* __restrict__ chains, const PairTask* __restrict__ tasks,
+    const double* __restrict__ tables, const T* __restrict__ aux, const T* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, T* __restrict__ filt, double* __restrict__ blk_logz,
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status, int maxN, int maxL) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    FftLds<T> l = carve<T>(smem, maxN, maxL, false);
+    const PairTask t = tasks[blockIdx.x];
+    const ChainInfo& c = chains[t.chain];
+    int start, len;
+    block_of(c, *sweep_ptr, t.block, &start, &len);
+    const bool has_b = t.p_b >= 0;
+    const int spin = t.p_a >= c.n_up ? 1 : 0;
+    const T* Wsp = W + spin * aux_elems + c.aux_off;
+    const double* shift = wshift + spin * total_slices + c.slice_off;
+    const int end = (start + len) % c.L_tau;
+    const int32_t* pc = paths + c.path_off;
+    const int a_a = checked_site(pc[(int64_t)start * c.np + t.p_a], c.N, status, t.chain);
+    const int e_a = checked_site(pc[(int64_t)end * c.np + t.p_a], c.N, status, t.chain);
+    const int a_b = has_b ? checked_site(pc[(int64_t)start * c.np + t.p_b], c.N, status, t.chain) : 0;
+    const int e_b = has_b ? checked_site(pc[(int64_t)end * c.np + t.p_b], c.N, status, t.chain) : 0;
+    load_chain_tables(c, tables, l);
+    const int64_t rowbase = (int64_t)t.block * (c.B - 1);
+    T* row_a = filt + c.filt_off + ((int64_t)t.p_a * c.L_tau + rowbase) * c.N;
+    T* row_b = has_b ? filt + c.filt_off + ((int64_t)t.p_b * c.L_tau + rowbase) * c.N : nullptr;
+    double lza, lzb;
+    forward_pass<T>(c, tables, Wsp, shift, aux + c.aux_off, spin ? c.coef_dn : c.coef_up, start,
+                    len, a_a, e_a, a_b, e_b, has_b, row_a, row_b, 1, l, &lza, &lzb, status,
+                    t.chain);
+    if (threadIdx.x == 0) {
+        blk_logz[c.blk_off + (int64_t)t.p_a * c.nb + t.block] = lza;
+        if (has_b) blk_logz[c.blk_off + (int64_t)t.p_b * c.nb + t.block] = lzb;
+    }
+}
+
+// logZ[particle] = sum over its blocks, in block order.
+__global__ void k_logz_reduce(const ChainInfo* __restrict__ chains, int n_chains,
+                              const double* __restrict__ blk_logz, double* __restrict__ logZ,
+                              int64_t particles) {
+    const int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gp >= particles) return;
+    const int c = find_chain(n_chains, gp, [&](int i) { return chains[i].part_off; });
+    const ChainInfo& ci = chains[c];
+    const int64_t p = gp - ci.part_off;
+    double s = 0.0;
+    for (int b = 0; b < ci.nb; ++b) s += blk_logz[ci.blk_off + p * ci.nb + b];
+    logZ[gp] = s;
+}
+
+// Backward sampling, one wavefront per (chain, particle, block). For j = len-1 .. 1:
+// w(r) = max(f~_j(r), 0) g(x_{j+1} - x) g(y_{j+1} - y) in FP64; lane l owns the contiguous sites
+// [l E, (l+1) E); C_r = (exclusive scan of lane totals) + (running sum within the lane);
+// the draw is the smallest r with C_r > u * C_total (Philox uniform), else the last r with w > 0.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_backward(
+    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
+    const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int task = blockIdx.x * kWaves + wv;
+    if (task >= n_tasks) return;  // whole wavefront leaves; no block-level barrier below
+    const DrawTask t = tasks[task];
+    const ChainInfo& c = chains[t.chain];
+    const uint64_t sweep = *sweep_ptr;
+    int start, len;
+    block_of(c, sweep, t.block, &start, &len);
+    if (len < 2) return;
+    const int N = c.N, L = c.L;
+    const double* __restrict__ g = tables + tab_g(c);
+    int32_t* pc = paths + c.path_off;
+    int cur = checked_site(pc[(int64_t)((start + len) % c.L_tau) * c.np + t.p], N, status, t.chain);
+    const int E = (N + 63) / 64;
+    const int i0 = lane * E;
+    const int i1 = min(i0 + E, N);
+    const T* rows = filt + c.filt_off + ((int64_t)t.p * c.L_tau + (int64_t)t.block * (c.B - 1)) * N;
+    for (int j = len - 1; j >= 1; --j) {
+        const int l = (start + j) % c.L_tau;
+        const T* f = rows + (int64_t)(j - 1) * N;
+        const int cx = cur % L, cy = cur / L;
+        double tot = 0.0;
+        for (int i = i0; i < i1; ++i) {
+            const int x = i % L, y = i / L;
+            int dx = cx - x, dy = cy - y;
+            dx += dx < 0 ? L : 0;
+            dy += dy < 0 ? L : 0;
+            const double fv = (double)f[i];
+            tot += (fv > 0.0 ? fv : 0.0) * g[dx] * g[dy];
+        }
+        double incl = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double up = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += up;
+        }
+        double excl = __shfl_up(incl, 1, 64);
+        if (lane == 0) excl = 0.0;
+        const double total = __shfl(incl, 63, 64);
+        int chosen = cur;
+        if (!(total > 0.0) || !isfinite(total)) {
+            if (lane == 0)
+                set_status(status, isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE, t.chain);
+        } else {
+            const u64x4 rnd = philox4x64_10((uint64_t)t.p, (uint64_t)l, sweep, kTagPath, c.seed, 0);
+            const double T_ = u01_from(rnd.x0) * total;
+            double run = excl;
+            int first = 0x7fffffff, lastpos = -1;
+            for (int i = i0; i < i1; ++i) {
+                const int x = i % L, y = i / L;
+                int dx = cx - x, dy = cy - y;
+                dx += dx < 0 ? L : 0;
+                dy += dy < 0 ? L : 0;
+                const double fv = (double)f[i];
+                const double w = (fv > 0.0 ? fv : 0.0) * g[dx] * g[dy];
+                run += w;
+                if (first == 0x7fffffff && run > T_) first = i;
+                if (w > 0.0) lastpos = i;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                first = min(first, __shfl_xor(first, o, 64));
+                lastpos = max(lastpos, __shfl_xor(lastpos, o, 64));
+            }
+            chosen = first != 0x7fffffff ? first : lastpos;
+            if (chosen < 0) chosen = cur;
+        }
+        if (lane == 0) pc[(int64_t)l * c.np + t.p] = chosen;
+        cur = chosen;
+    }
+}
+
+// Occupation counts of one slice (LDS histogram) and the exact field draw of every site:
+// Ising: s = +1 iff u < (1 + tanh(lambda (n_up - n_dn))) / 2; Gaussian: sigma = a (n - 1/2) + z.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gibbs(const ChainInfo* __restrict__ chains,
+                                                    int n_chains, const int32_t* __restrict__ paths,
+                                                    T* __restrict__ aux,
+                                                    const uint64_t* __restrict__ sweep_ptr,
+                                                    int32_t* status, int maxN) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    int32_t* cnt = (int32_t*)smem;  // [2][maxN]
+    const int gs = blockIdx.x;
+    const int ci = find_chain(n_chains, gs, [&](int i) { return chains[i].slice_off; });
+    const ChainInfo& c = chains[ci];
+    const int l = (int)(gs - c.slice_off);
+    const uint64_t sweep = *sweep_ptr;
+    for (int r = threadIdx.x; r < 2 * c.N; r += blockDim.x) cnt[(r / c.N) * maxN + r % c.N] = 0;
+    __syncthreads();
+    const int32_t* pl = paths + c.path_off + (int64_t)l * c.np;
+    for (int p = threadIdx.x; p < c.np; p += blockDim.x) {
+        const int r = pl[p];
+        if (r >= 0 && r < c.N)
+            atomicAdd(&cnt[(p >= c.n_up ? maxN : 0) + r], 1);
+        else
+            set_status(status, FH_ERR_BAD_PATH, ci);
+    }
+    __syncthreads();
+    T* al = aux + c.aux_off + (int64_t)l * c.N;
+    for (int r = threadIdx.x; r < c.N; r += blockDim.x) {
+        const int nu = cnt[r], nd = cnt[maxN + r];
+        const u64x4 x = philox4x64_10((uint64_t)r, (uint64_t)l, sweep, kTagGibbs, c.seed, 0);
+        double v;
+        if (c.hs_kind == FH_HS_GAUSS) {
+            v = c.gauss_a * ((double)(nu + nd) - 0.5) + normal_from(x.x0, x.x1);
+        } else {
+            const double pp = (1.0 + tanh(c.hirsch_lambda * (double)(nu - nd))) / 2.0;
+            v = u01_from(x.x0) < pp ? 1.0 : -1.0;
+        }
+        al[r] = (T)v;
+    }
+}
+
+// Adjoint of the forward filter over the ring anchored at `anchor` (one block of length L_tau):
+// forward pass storing f~_j (j = 0..L_tau-1), then backward messages
+//   u_{L_tau} = delta_a;  beta_j = G * u_{j+1};  u_j = W_j . beta_j / sum   (FFT convolution)
+// with d log Z / d log W_j(r) = f~_j(r) beta_j(r) / <f~_j, beta_j> accumulated into grad_aux
+// (times the spin's coefficient) and d log Z / dt += <dG/dt * u_{j+1}, f~_j> / <beta_j, f~_j>.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_grad(
+    const ChainInfo* __restrict__ chains, const PairTask* __restrict__ tasks,
+    const double* __restrict__ tables, const T* __restrict__ aux, const T* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, T* __restrict__ filt, double* __restrict__ blk_logz,
+    double* __restrict__ dt_out, T* grad_aux, int anchor, int32_t* status, int maxN, int maxL) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    FftLds<T> l = carve<T>(smem, maxN, maxL, true);
+    const PairTask t = tasks[blockIdx.x];
+    const ChainInfo& c = chains[t.chain];
+    const int N = c.N, L = c.L, L_tau = c.L_tau;
+    const bool has_b = t.p_b >= 0;
+    const int spin = t.p_a >= c.n_up ? 1 : 0;
+    const double coef = spin ? c.coef_dn : c.coef_up;
+    const T* Wsp = W + spin * aux_elems + c.aux_off;
+    const double* shift = wshift + spin * total_slices + c.slice_off;
+    const int32_t* pc = paths + c.path_off;
+    const int a_a = checked_site(pc[(int64_t)anchor * c.np + t.p_a], N, status, t.chain);
+    const int a_b = has_b ? checked_site(pc[(int64_t)anchor * c.np + t.p_b], N, status, t.chain) : 0;
+    load_chain_tables(c, tables, l);
+    T* row_a = filt + c.filt_off + (int64_t)t.p_a * L_tau * N;
+    T* row_b = has_b ? filt + c.filt_off + (int64_t)t.p_b * L_tau * N : nullptr;
+    double lza, lzb;
+    forward_pass<T>(c, tables, Wsp, shift, aux + c.aux_off, coef, anchor, L_tau, a_a, a_a, a_b,
+                    a_b, has_b, row_a, row_b, 0, l, &lza, &lzb, status, t.chain);
+    const double* gh = tables + tab_ghat(c);
+    const double* dgh = tables + tab_dghat(c);
+    for (int r = threadIdx.x; r < N; r += blockDim.x)
+        l.U[r] = {r == a_a ? T(1) : T(0), (has_b && r == a_b) ? T(1) : T(0)};
+    double dta = 0.0, dtb = 0.0;
+    T* gl = grad_aux ? grad_aux + c.aux_off : nullptr;
+    for (int j = L_tau - 1; j >= 0; --j) {
+        const int lj = (anchor + j) % L_tau;
+        __syncthreads();
+        fft2d<T, false>(l.U, l.S, L, c.plan, l.tw);
+        for (int k = threadIdx.x; k < N; k += blockDim.x) {
+            const cpx<T> s = l.U[k];
+            const T m = (T)gh[k], dm = (T)dgh[k];
+            l.A[k] = {s.re * m, s.im * m};
+            l.U[k] = {s.re * dm, s.im * dm};
+        }
+        __syncthreads();
+        fft2d<T, true>(l.A, l.S, L, c.plan, l.tw);   // beta_j = G * u_{j+1}
+        fft2d<T, true>(l.U, l.S, L, c.plan, l.tw);   // dG/dt * u_{j+1}
+        const T* fa = row_a + (int64_t)j * N;
+        const T* fb = has_b ? row_b + (int64_t)j * N : nullptr;
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int r = threadIdx.x; r < N; r += blockDim.x) {
+            const double va = (double)fa[r];
+            s[0] += (double)l.U[r].re * va;
+            s[1] += (double)l.A[r].re * va;
+            if (has_b) {
+                const double vb = (double)fb[r];
+                s[2] += (double)l.U[r].im * vb;
+                s[3] += (double)l.A[r].im * vb;
+            }
+        }
+        block_sum<4>(s, l.red);
+        dta += s[0] / s[1];
+        if (has_b) dtb += s[2] / s[3];
+        if (gl) {
+            const double ka = coef / s[1], kb = has_b ? coef / s[3] : 0.0;
+            for (int r = threadIdx.x; r < N; r += blockDim.x) {
+                double v = ka * (double)fa[r] * (double)l.A[r].re;
+                if (has_b) v += kb * (double)fb[r] * (double)l.A[r].im;
+                atomicAdd(&gl[(int64_t)lj * N + r], (T)v);
+            }
+        }
+        if (j > 0) {
+            const T* Wl = Wsp + (int64_t)lj * N;
+            double z[2] = {0.0, 0.0};
+            for (int r = threadIdx.x; r < N; r += blockDim.x) {
+                const T w = Wl[r];
+                const cpx<T> v = {l.A[r].re * w, l.A[r].im * w};
+                l.U[r] = v;
+                z[0] += (double)v.re;
+                z[1] += (double)v.im;
+            }
+            block_sum<2>(z, l.red);
+            if (!(z[0] > 0.0) || !isfinite(z[0]))
+                if (threadIdx.x == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
+            const T ia = (T)(1.0 / z[0]), ib = has_b ? (T)(1.0 / z[1]) : T(0);
+            for (int r = threadIdx.x; r < N; r += blockDim.x) {
+                l.U[r].re *= ia;
+                l.U[r].im *= ib;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        blk_logz[c.blk_off + (int64_t)t.p_a * c.nb] = lza;
+        dt_out[c.part_off + t.p_a] = dta;
+        if (has_b) {
+            blk_logz[c.blk_off + (int64_t)t.p_b * c.nb] = lzb;
+            dt_out[c.part_off + t.p_b] = dtb;
+        }
+    }
+}
+
+// Per chain, in particle order: logZ = sum of ring log Z_p, grad_t = sum of d log Z_p / dt.
+__global__ void k_grad_reduce(const ChainInfo* __restrict__ chains, int n_chains,
+                              const double* __restrict__ blk_logz, const double* __restrict__ dt,
+                              double* logZ, double* grad_t) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chains) return;
+    const ChainInfo& ci = chains[c];
+    double a = 0.0, b = 0.0;
+    for (int p = 0; p < ci.np; ++p) {
+        a += blk_logz[ci.blk_off + (int64_t)p * ci.nb];
+        b += dt[ci.part_off + p];
+    }
+    if (logZ) logZ[c] = a;
+    if (grad_t) grad_t[c] = b;
+}
+
+template <typename T>
+size_t fft_lds(int maxN, int maxL, bool third) {
+    size_t off = sizeof(cpx<T>) * maxN * (third ? 3 : 2) + sizeof(cpx<T>) * maxL;
+    off = (off + 7) & ~(size_t)7;
+    return off + sizeof(double) * maxL + sizeof(double) * 4 * kWaves;
+}
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+unsigned grid_for(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+size_t forward_lds_bytes(fh_plan p) {
+    return p->precision == FH_FP64 ? fft_lds<double>(p->max_N, p->max_L, false)
+                                   : fft_lds<float>(p->max_N, p->max_L, false);
+}
+
+size_t grad_lds_bytes(fh_plan p) {
+    return p->precision == FH_FP64 ? fft_lds<double>(p->max_N, p->max_L, true)
+                                   : fft_lds<float>(p->max_N, p->max_L, true);
+}
+
+hipError_t launch_set_sweep(fh_plan p, uint64_t sweep, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, p->d.sweep, sweep);
+    return hipGetLastError();
+}
+
+hipError_t launch_bump_sweep(fh_plan p, hipStream_t s) {
+    hipLaunchKernelGGL(k_bump_u64, dim3(1), dim3(64), 0, s, p->d.sweep);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t s) {
+    const int64_t words = bytes / 4;
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(words)), dim3(kThreads), 0, s, (uint32_t*)ptr, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_potentials(fh_plan p, const void* aux, hipStream_t s) {
+    const unsigned g = (unsigned)p->total_slices;
+    if (p->precision == FH_FP64)
+        hipLaunchKernelGGL(k_potentials<double>, dim3(g), dim3(kThreads), 0, s, p->d.chains,
+                           p->n_chains, (const double*)aux, (double*)p->d.W, p->d.wshift,
+                           p->aux_elems, p->total_slices, p->d.status);
+    else
+        hipLaunchKernelGGL(k_potentials<float>, dim3(g), dim3(kThreads), 0, s, p->d.chains,
+                           p->n_chains, (const float*)aux, (float*)p->d.W, p->d.wshift,
+                           p->aux_elems, p->total_slices, p->d.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
+    const size_t lds = forward_lds_bytes(p);
+    hipError_t e;
+    if (p->precision == FH_FP64) {
+        if ((e = allow_lds(k_forward_fft<double>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_forward_fft<double>, dim3(p->n_fwd_tasks), dim3(kThreads), lds, s,
+                           p->d.chains, p->d.fwd_tasks, p->d.tables, (const double*)aux,
+                           (const double*)p->d.W,
+                           p->d.wshift, p->aux_elems, p->total_slices, paths, (double*)p->d.filt, p->d.blk_logz, p->d.sweep,
+                           p->d.status, p->max_N, p->max_L);
+    } else {
+        if ((e = allow_lds(k_forward_fft<float>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_forward_fft<float>, dim3(p->n_fwd_tasks), dim3(kThreads), lds, s,
+                           p->d.chains, p->d.fwd_tasks, p->d.tables, (const float*)aux,
+                           (const float*)p->d.W,
+                           p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep,
+                           p->d.status, p->max_N, p->max_L);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s) {
+    hipLaunchKernelGGL(k_logz_reduce, dim3((unsigned)((p->particles + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, p->d.chains, p->n_chains, p->d.blk_logz, logZ,
+                       p->particles);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
+    const unsigned blocks = (unsigned)((p->n_draw_tasks + kWaves - 1) / kWaves);
+    if (p->precision == FH_FP64)
+        hipLaunchKernelGGL(k_backward<double>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
+                           (const double*)p->d.filt, paths, p->d.sweep, p->d.status);
+    else
+        hipLaunchKernelGGL(k_backward<float>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
+                           (const float*)p->d.filt, paths, p->d.sweep, p->d.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_gibbs(fh_plan p, const int32_t* paths, void* aux, hipStream_t s) {
+    const size_t lds = sizeof(int32_t) * 2 * p->max_N;
+    if (p->precision == FH_FP64)
+        hipLaunchKernelGGL(k_gibbs<double>, dim3((unsigned)p->total_slices), dim3(kThreads), lds,
+                           s, p->d.chains, p->n_chains, paths, (double*)aux, p->d.sweep,
+                           p->d.status, p->max_N);
+    else
+        hipLaunchKernelGGL(k_gibbs<float>, dim3((unsigned)p->total_slices), dim3(kThreads), lds,
+                           s, p->d.chains, p->n_chains, paths, (float*)aux, p->d.sweep,
+                           p->d.status, p->max_N);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
+                       void* grad_aux, hipStream_t s) {
+    const size_t lds = grad_lds_bytes(p);
+    hipError_t e;
+    if (p->precision == FH_FP64) {
+        if ((e = allow_lds(k_grad<double>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_grad<double>, dim3(p->n_grad_tasks), dim3(kThreads), lds, s,
+                           p->d.chains, p->d.grad_tasks, p->d.tables, (const double*)aux,
+                           (const double*)p->d.W,
+                           p->d.wshift, p->aux_elems, p->total_slices, paths, (double*)p->d.filt, p->d.blk_logz, p->d.dt,
+                           (double*)grad_aux, anchor, p->d.status, p->max_N, p->max_L);
+    } else {
+        if ((e = allow_lds(k_grad<float>, lds)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_grad<float>, dim3(p->n_grad_tasks), dim3(kThreads), lds, s,
+                           p->d.chains, p->d.grad_tasks, p->d.tables, (const float*)aux,
+                           (const float*)p->d.W,
+                           p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt, p->d.blk_logz, p->d.dt,
+                           (float*)grad_aux, anchor, p->d.status, p->max_N, p->max_L);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(fh_plan p, double* logZ, double* grad_t, hipStream_t s) {
+    if (!logZ && !grad_t) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((p->n_chains + 63) / 64)), dim3(64), 0, s,
+                       p->d.chains, p->n_chains, p->d.blk_logz, p->d.dt, logZ, grad_t);
+    return hipGetLastError();
+}
+
+}  // namespace fh

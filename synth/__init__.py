@@ -93,6 +93,25 @@ def random_paths(desc: ChainDesc, rng_seed: int) -> np.ndarray:
     return rng.integers(0, desc.N, size=(desc.L_tau, desc.n_particles), dtype=np.int32)
 
 
+def random_walk_paths(desc: ChainDesc, rng_seed: int, hop: float = 0.3) -> np.ndarray:
+    """Worldlines that look like sampled ones: a uniformly random site at slice 0, then at each
+    slice a nearest-neighbour hop with probability `hop` (the wrap from the last slice back to
+    slice 0 is not constrained).
+    Shape [L_tau, n_particles] int32."""
+    rng = np.random.default_rng(rng_seed)
+    L = desc.L
+    x = rng.integers(0, L, size=desc.n_particles)
+    y = rng.integers(0, L, size=desc.n_particles)
+    out = np.empty((desc.L_tau, desc.n_particles), dtype=np.int32)
+    for l in range(desc.L_tau):
+        out[l] = x + L * y
+        move = rng.random(desc.n_particles) < hop
+        d = rng.integers(0, 4, size=desc.n_particles)
+        x = np.where(move & (d == 0), (x + 1) % L, np.where(move & (d == 1), (x - 1) % L, x))
+        y = np.where(move & (d == 2), (y + 1) % L, np.where(move & (d == 3), (y - 1) % L, y))
+    return out
+
+
 # --- the workload configurations ---------------------------------------------------------
 
 def config_small_fp64() -> List[ChainDesc]:

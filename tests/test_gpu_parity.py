@@ -1,0 +1,382 @@
+"""GPU parity of the FFBS sweep against the FP64 oracle, through the C ABI.
+
+Tolerances (written here, derived in the design notes):
+  FP64 path: filters <= 1e-11 normwise per row, log Z <= 1e-12 relative, sampled sites and
+  Ising fields bit-exact (a mismatch only if the oracle certifies a near-tie), Gaussian fields
+  <= 1e-13, gradients <= 1e-10.
+  FP32 paths: filters <= 1e-5 normwise (MFMA split-bf16) / measured and bounded (FFT),
+  log Z <= 1e-6 relative, gradients <= 1e-4 normwise.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ffbs, gibbs, grad as ograd, hs, lattice, sweep as osweep
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lib(gpu):
+    from paper_2510_13866_amd import fhmc, sampler
+    return fhmc, sampler
+
+
+MIXED = [
+    synth.config_small_fp64()[0],                                                    # 4x4 Gauss
+    synth.ChainDesc(L=3, L_tau=7, n_up=4, n_dn=3, hs_kind=synth.HS_HIRSCH, block_len=0,
+                    t=1.0, U=4.0, dtau=0.1, seed=5),                                 # radix 3, odd
+    synth.ChainDesc(L=6, L_tau=10, n_up=18, n_dn=18, hs_kind=synth.HS_GAUSS, block_len=4,
+                    t=1.0, U=3.0, dtau=0.1, seed=7),                                 # ragged blocks
+    synth.ChainDesc(L=12, L_tau=24, n_up=72, n_dn=72, hs_kind=synth.HS_HIRSCH, block_len=0,
+                    t=1.0, U=4.0, dtau=0.0625, seed=9),
+    synth.ChainDesc(L=2, L_tau=3, n_up=1, n_dn=1, hs_kind=synth.HS_GAUSS, block_len=0,
+                    t=0.8, U=2.0, dtau=0.2, seed=11),                                # L = 2
+    synth.ChainDesc(L=8, L_tau=12, n_up=5, n_dn=0, hs_kind=synth.HS_HIRSCH, block_len=5,
+                    t=1.0, U=6.0, dtau=0.05, seed=13),                               # no down spins
+]
+
+
+def mixed_state(descs, seed=0, random_paths=True):
+    aux = [synth.initial_aux(d, rng_seed=seed + i) for i, d in enumerate(descs)]
+    if random_paths:
+        # sampled-looking worldlines: far-apart block endpoints have weights below what an FFT
+        # convolution resolves (its error is ~eps * max|f| per site), so uniformly random
+        # sites are not used for the forward comparisons
+        paths = [synth.random_walk_paths(d, seed + 100 + i) for i, d in enumerate(descs)]
+    else:
+        paths = [synth.initial_paths(d) for d in descs]
+    return aux, paths
+
+
+def oracle_forward(desc, aux, paths, s, particles=None, with_tail=False):
+    """Per-particle (log Z summed over blocks, stored rows) as the library lays them out, and
+    optionally the tail depth sum_blocks max_r (G*f~)(r) / (G*f~)(end site): an FFT convolution
+    is accurate to ~eps * max per site, so log Z of a block whose end sits that deep in the
+    filter's tail carries a relative error up to ~eps * depth."""
+    Gm = lattice.transfer_matrix(desc.L, desc.t, desc.dtau)
+    W_up, W_dn = hs.potentials(aux, desc.hs_kind, desc.U, desc.dtau)
+    parts = np.arange(desc.n_particles) if particles is None else np.asarray(particles)
+    logZ = np.zeros(len(parts))
+    tail = np.zeros(len(parts))
+    rows = [[] for _ in parts]
+    for start, length in ffbs.block_schedule(desc.L_tau, desc.block_len, s):
+        for W, sel in ((W_up, parts < desc.n_up), (W_dn, parts >= desc.n_up)):
+            if not sel.any():
+                continue
+            pp = parts[sel]
+            a = paths[start, pp].astype(np.int64)
+            e = paths[(start + length) % desc.L_tau, pp].astype(np.int64)
+            filt, lz, _ = ffbs.forward_filter(Gm, W, start, length, a, e)
+            logZ[sel] += lz
+            Gf = filt[:, -1, :] @ Gm.T
+            tail[sel] += Gf.max(axis=1) / Gf[np.arange(len(pp)), e]
+            for k, i in enumerate(np.nonzero(sel)[0]):
+                rows[i].append(filt[k, 1:, :])
+    rows = [np.concatenate(r, axis=0) if r else np.zeros((0, desc.N)) for r in rows]
+    if with_tail:
+        return logZ, rows, tail
+    return logZ, rows
+
+
+def logz_tol(prec, ref_lz, tail):
+    """Relative-to-Z floor plus the FFT's resolution limit at the end site (see oracle_forward)."""
+    eps = 1e-15 if prec == "fp64" else 6e-8
+    floor = 1e-12 if prec == "fp64" else 2e-6
+    return floor * (1 + np.abs(ref_lz)) + 10 * eps * tail
+
+
+def rel_row_err(a, b):
+    num = np.linalg.norm(a - b, axis=1)
+    den = np.linalg.norm(b, axis=1)
+    return np.max(num / den) if len(den) else 0.0
+
+
+def check_paths(desc, got, ref, margins, what):
+    """Bit-exact sites, except where the oracle certifies a near-tie at the first difference."""
+    bad = np.nonzero((got != ref).any(axis=0))[0]
+    for p in bad:
+        diff = np.nonzero(got[:, p] != ref[:, p])[0]
+        m = np.min(margins[diff, p])
+        assert m < 1e-9, "%s: particle %d differs at slices %s (oracle margin %g)" % (what, p, diff, m)
+    return len(bad)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_forward_filter_parity_mixed_batch(lib, prec):
+    fhmc, sampler = lib
+    precision = fhmc.FH_FP64 if prec == "fp64" else fhmc.FH_FP32
+    descs = MIXED
+    say("forward parity", prec, [(d.L, d.L_tau, d.n_up, d.n_dn, d.block_len) for d in descs])
+    S = sampler.Sampler(descs, precision)
+    aux, paths = mixed_state(descs)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    for s in (0, 1, 3):
+        logZ = S.unpack_particles(S.forward_filter(A, P, s))
+        assert S.status() == (0, -1)
+        for c, d in enumerate(descs):
+            ref_lz, ref_rows, tail = oracle_forward(d, aux[c], paths[c], s, with_tail=True)
+            err = np.abs(logZ[c] - ref_lz)
+            assert np.all(err <= logz_tol(prec, ref_lz, tail)), (c, s, err, tail)
+            for p in range(d.n_particles):
+                got = S.filters(c, p)
+                err = rel_row_err(got, ref_rows[p])
+                assert err <= (1e-11 if prec == "fp64" else 2e-5), (c, p, s, err)
+    S.close()
+
+
+def test_backward_sample_parity_fp64(lib):
+    fhmc, sampler = lib
+    descs = MIXED
+    say("backward parity fp64")
+    S = sampler.Sampler(descs, fhmc.FH_FP64)
+    aux, paths = mixed_state(descs, seed=3)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    n_cert = 0
+    for s in (0, 1, 2):
+        before = S.unpack_paths(P)
+        S.forward_filter(A, P, s)
+        S.backward_sample(P, s)
+        assert S.status() == (0, -1)
+        got = S.unpack_paths(P)
+        for c, d in enumerate(descs):
+            Gm = lattice.transfer_matrix(d.L, d.t, d.dtau)
+            W_up, W_dn = hs.potentials(aux[c], d.hs_kind, d.U, d.dtau)
+            ref = before[c].astype(np.int64).copy()
+            marg = np.full(ref.shape, np.inf)
+            for W, parts in ((W_up, np.arange(d.n_up)), (W_dn, np.arange(d.n_up, d.n_particles))):
+                if len(parts) == 0:
+                    continue
+                out, _, m = ffbs.ffbs_spin(Gm, W, before[c], parts, d.seed, s, d.block_len, True)
+                ref[:, parts] = out
+                marg[:, parts] = m
+            n_cert += check_paths(d, got[c], ref, marg, "chain %d sweep %d" % (c, s))
+        P = S.pack_paths(got)
+    assert n_cert <= 1
+    S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gibbs_parity(lib, prec):
+    fhmc, sampler = lib
+    precision = fhmc.FH_FP64 if prec == "fp64" else fhmc.FH_FP32
+    descs = MIXED
+    say("gibbs parity", prec)
+    S = sampler.Sampler(descs, precision)
+    aux, paths = mixed_state(descs, seed=5)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    for s in (0, 7):
+        S.gibbs_aux(P, A, s)
+        got = S.unpack_aux(A)
+        assert S.status() == (0, -1)
+        for c, d in enumerate(descs):
+            cu, cd = gibbs.occupancy(paths[c], d.n_up, d.N)
+            ref = gibbs.gibbs_field(d.hs_kind, d.U, d.dtau, cu, cd, d.seed, s)
+            if d.hs_kind == synth.HS_HIRSCH:
+                assert np.array_equal(got[c], ref), (c, s)
+            else:
+                tol = 1e-13 if prec == "fp64" else 1e-6
+                assert np.allclose(got[c], ref, rtol=tol, atol=tol), (c, s)
+    S.close()
+
+
+def test_sweep_trajectory_small_fp64(lib):
+    """4x4, L_tau=16, Gaussian field, 200 sweeps: sites bit-exact, field within 1e-10."""
+    fhmc, sampler = lib
+    d = synth.config_small_fp64()[0]
+    say("trajectory 4x4 fp64 200 sweeps")
+    aux0, paths0 = synth.initial_aux(d), synth.initial_paths(d)
+    S = sampler.Sampler([d], fhmc.FH_FP64)
+    A, P = S.pack_aux([aux0]), S.pack_paths([paths0])
+    S.sweep(A, P, 0, 200)
+    assert S.status() == (0, -1)
+    ref_aux, ref_paths = osweep.run(d, aux0, paths0, 0, 200)
+    assert np.array_equal(S.unpack_paths(P)[0], ref_paths)
+    assert np.allclose(S.unpack_aux(A)[0], ref_aux, rtol=1e-10, atol=1e-10)
+    S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replay_equals_eager_and_resume(lib, prec):
+    fhmc, sampler = lib
+    precision = fhmc.FH_FP64 if prec == "fp64" else fhmc.FH_FP32
+    descs = MIXED[:4]
+    say("graph vs eager", prec)
+    aux, paths = mixed_state(descs, seed=8, random_paths=False)
+    Se = sampler.Sampler(descs, precision)
+    Sg = sampler.Sampler(descs, precision, fhmc.FH_FLAG_GRAPH)
+    Ae, Pe = Se.pack_aux(aux), Se.pack_paths(paths)
+    Ag, Pg = Sg.pack_aux(aux), Sg.pack_paths(paths)
+    Se.sweep(Ae, Pe, 0, 10)
+    Sg.sweep(Ag, Pg, 0, 5)
+    torch.cuda.synchronize()
+    Sg.sweep(Ag, Pg, 5, 5)          # resume from the saved state and sweep index
+    assert Se.status() == (0, -1) and Sg.status() == (0, -1)
+    assert torch.equal(Pe, Pg)
+    assert torch.equal(Ae, Ag)
+    Se.close()
+    Sg.close()
+
+
+def test_batch_invariance(lib):
+    """A chain gives bit-identical results alone and inside an uneven batch."""
+    fhmc, sampler = lib
+    say("batch invariance")
+    for precision in (fhmc.FH_FP64, fhmc.FH_FP32):
+        aux, paths = mixed_state(MIXED, seed=12, random_paths=False)
+        Sb = sampler.Sampler(MIXED, precision)
+        Ab, Pb = Sb.pack_aux(aux), Sb.pack_paths(paths)
+        Sb.sweep(Ab, Pb, 0, 4)
+        alone = 3
+        Sa = sampler.Sampler([MIXED[alone]], precision)
+        Aa, Pa = Sa.pack_aux([aux[alone]]), Sa.pack_paths([paths[alone]])
+        Sa.sweep(Aa, Pa, 0, 4)
+        assert np.array_equal(Sb.unpack_paths(Pb)[alone], Sa.unpack_paths(Pa)[0])
+        assert np.array_equal(Sb.unpack_aux(Ab)[alone], Sa.unpack_aux(Aa)[0])
+        Sb.close()
+        Sa.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_sampled_parity(lib, prec):
+    """32x32, L_tau=160, 512+512 worldlines, 2 chains (the benchmark's shape and launch):
+    log Z of every particle against the oracle on a sample of particles, their filters and,
+    in FP64, their redrawn sites."""
+    fhmc, sampler = lib
+    precision = fhmc.FH_FP64 if prec == "fp64" else fhmc.FH_FP32
+    descs = synth.config_32x32(4.0, n_chains=2)
+    say("full size sampled parity", prec)
+    S = sampler.Sampler(descs, precision)
+    aux = [synth.initial_aux(d) for d in descs]
+    paths = [synth.initial_paths(d) for d in descs]
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    s = 1
+    logZ = S.unpack_particles(S.forward_filter(A, P, s))
+    assert S.status() == (0, -1)
+    sample = [0, 1, 7, 300, 511, 512, 600, 1023]
+    worst = 0.0
+    for c, d in enumerate(descs):
+        ref_lz, ref_rows = oracle_forward(d, aux[c], paths[c], s, sample)
+        tol_lz = 1e-12 if prec == "fp64" else 2e-6
+        assert np.allclose(logZ[c][sample], ref_lz, rtol=tol_lz), c
+        for k, p in enumerate(sample):
+            err = rel_row_err(S.filters(c, p), ref_rows[k])
+            worst = max(worst, err)
+            assert err <= (1e-11 if prec == "fp64" else 2e-4), (c, p, err)
+    say("  worst filter error", prec, worst)
+    if prec == "fp64":
+        before = S.unpack_paths(P)
+        S.backward_sample(P, s)
+        got = S.unpack_paths(P)
+        for c, d in enumerate(descs):
+            Gm = lattice.transfer_matrix(d.L, d.t, d.dtau)
+            W_up, _ = hs.potentials(aux[c], d.hs_kind, d.U, d.dtau)
+            parts = np.array(sample[:5])
+            out, _, m = ffbs.ffbs_spin(Gm, W_up, before[c], parts, d.seed, s, d.block_len, True)
+            check_paths(d, got[c][:, parts], out, m, "full size chain %d" % c)
+    S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_logz_grad_parity(lib, prec):
+    fhmc, sampler = lib
+    precision = fhmc.FH_FP64 if prec == "fp64" else fhmc.FH_FP32
+    descs = [synth.config_small_fp64()[0],
+             synth.ChainDesc(L=6, L_tau=8, n_up=5, n_dn=4, hs_kind=synth.HS_HIRSCH, block_len=0,
+                             t=1.0, U=4.0, dtau=0.1, seed=2),
+             synth.ChainDesc(L=32, L_tau=128, n_up=9, n_dn=8, hs_kind=synth.HS_GAUSS,
+                             block_len=0, t=1.0, U=4.0, dtau=0.05, seed=3)]
+    say("logZ grad parity", prec)
+    S = sampler.Sampler(descs, precision)
+    aux, paths = mixed_state(descs, seed=21)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    for anchor in (0, 5):
+        logZ, gA, gT = S.logz_grad(A, P, anchor)
+        assert S.status() == (0, -1)
+        logZ = logZ.cpu().numpy()
+        gT = gT.cpu().numpy()
+        gA = S.unpack_aux(gA)
+        for c, d in enumerate(descs):
+            lz, g, gt, _ = ograd.logz_path_grad(d, aux[c], paths[c], anchor)
+            tol = 1e-10 if prec == "fp64" else 1e-4
+            assert logZ[c] == pytest.approx(lz, rel=1e-12 if prec == "fp64" else 2e-6), c
+            assert np.linalg.norm(gA[c] - g) <= tol * np.linalg.norm(g), c
+            assert gT[c] == pytest.approx(gt, rel=tol), c
+    S.close()
+
+
+def test_autograd_function(lib):
+    fhmc, sampler = lib
+    d = synth.config_small_fp64()[0]
+    S = sampler.Sampler([d], fhmc.FH_FP64)
+    aux, paths = synth.initial_aux(d), synth.random_paths(d, 3)
+    A = S.pack_aux([aux]).requires_grad_(True)
+    P = S.pack_paths([paths])
+    t = torch.tensor([1.0], dtype=torch.float64, requires_grad=True)
+    out = sampler.LogZPath.apply(A, t, S, P, 0)
+    (2.0 * out.sum()).backward()
+    lz, g, gt, _ = ograd.logz_path_grad(d, aux, paths, 0)
+    assert out.item() == pytest.approx(lz, rel=1e-12)
+    assert np.allclose(A.grad.cpu().numpy().reshape(g.shape), 2 * g, rtol=1e-10, atol=1e-12)
+    assert t.grad.item() == pytest.approx(2 * gt, rel=1e-10)
+    # a different t goes through fh_set_hopping
+    t2 = torch.tensor([1.1], dtype=torch.float64)
+    out2 = sampler.LogZPath.apply(A.detach(), t2, S, P, 0)
+    assert out2.item() == pytest.approx(ograd.logz_path(d, aux, paths, 0, t=1.1)[0], rel=1e-12)
+    S.close()
+
+
+def test_device_errors_are_latched(lib):
+    fhmc, sampler = lib
+    d = synth.config_small_fp64()[0]
+    S = sampler.Sampler([d], fhmc.FH_FP64)
+    aux, paths = synth.initial_aux(d), synth.initial_paths(d)
+    A, P = S.pack_aux([aux]), S.pack_paths([paths])
+    with pytest.raises(fhmc.FhError) as e:
+        S.backward_sample(P, 0)                       # backward before forward
+    assert e.value.code == fhmc.FH_ERR_STATE
+    bad = aux.copy()
+    bad[3, 5] = np.nan
+    S.forward_filter(S.pack_aux([bad]), P, 0)
+    assert S.status()[0] == fhmc.FH_ERR_NONFINITE
+    assert S.status() == (0, -1)                       # cleared
+    badp = paths.copy()
+    badp[0, 2] = d.N + 5
+    Pb = S.pack_paths([badp])
+    S.gibbs_aux(Pb, A, 0)
+    assert S.status() == (fhmc.FH_ERR_BAD_PATH, 0)
+    S.forward_filter(A, Pb, 0)
+    assert S.status()[0] == fhmc.FH_ERR_BAD_PATH
+    with pytest.raises(fhmc.FhError):
+        S.logz_grad(A, P, d.L_tau)                     # anchor out of range
+    S.close()
+
+
+def test_extreme_field_values_stay_finite(lib):
+    """Fields far outside N(0,1) (as a clustered chain produces): the potentials are shifted per
+    slice in log space, so FP64 matches the oracle and nothing overflows."""
+    fhmc, sampler = lib
+    d = synth.ChainDesc(L=4, L_tau=12, n_up=8, n_dn=8, hs_kind=synth.HS_GAUSS, block_len=0,
+                        t=1.0, U=4.0, dtau=0.1, seed=4)
+    aux = synth.initial_aux(d)
+    aux[:, 5] += 900.0                      # a * 900 = 569: exp overflows FP32 and nearly FP64
+    paths = synth.initial_paths(d)
+    paths[:, :3] = 5
+    for prec, tol in ((fhmc.FH_FP64, 1e-11), (fhmc.FH_FP32, 1e-5)):
+        S = sampler.Sampler([d], prec)
+        A, P = S.pack_aux([aux]), S.pack_paths([paths])
+        lz = S.unpack_particles(S.forward_filter(A, P, 0))[0]
+        ref, _ = oracle_forward(d, aux, paths, 0)
+        assert np.all(np.isfinite(lz)), (prec, lz)
+        assert np.allclose(lz, ref, rtol=tol), (prec, lz, ref)
+        S.close()

@@ -1,0 +1,126 @@
+"""CPU-side checks of the HIP library: it loads, exports every declared entry point, validates
+descriptors before touching the device, and its host-side mirrors of the device arithmetic
+(FFT stages, kernel table, Philox) agree with numpy / the oracle. No GPU compute is called."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("fh.h", "fh_debug.h")]
+
+
+@pytest.fixture(scope="module")
+def fhmc():
+    from paper_2510_13866_amd import fhmc as m
+    return m
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(fh_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(fhmc):
+    names = declared_functions()
+    assert "fh_init" in names and "fh_sweep" in names and "fh_logZ_grad" in names
+    for n in names:
+        assert hasattr(fhmc.lib, n), n
+
+
+def test_struct_sizes_match_header(fhmc):
+    assert ctypes.sizeof(fhmc.fh_chain_desc) == 56
+    assert ctypes.sizeof(fhmc.fh_chain_layout) == 56
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 6, 8, 9, 12, 16, 18, 24, 32, 36, 48, 64])
+@pytest.mark.parametrize("inverse", [0, 1])
+def test_host_fft_stages_match_numpy(fhmc, L, inverse):
+    rng = np.random.default_rng(L)
+    z = rng.standard_normal((L, L)) + 1j * rng.standard_normal((L, L))  # [y, x]
+    buf = np.empty(2 * L * L)
+    buf[0::2] = z.real.ravel()
+    buf[1::2] = z.imag.ravel()
+    rc = fhmc.lib.fh_debug_fft2d_host(buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), L,
+                                      inverse)
+    assert rc == 0
+    got = (buf[0::2] + 1j * buf[1::2]).reshape(L, L)
+    ref = np.fft.fft2(z) if not inverse else np.fft.ifft2(z) * L * L
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_host_fft_rejects_unsupported_lengths(fhmc):
+    buf = np.zeros(2 * 25)
+    p = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert fhmc.lib.fh_debug_fft2d_host(p, 5, 0) == fhmc.FH_ERR_UNSUPPORTED
+    assert fhmc.lib.fh_debug_fft2d_host(p, 1, 0) == fhmc.FH_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("L,t,dtau", [(2, 1.0, 0.1), (3, 1.0, 0.1), (4, 1.0, 0.1), (12, 1.0, 0.05),
+                                      (32, 1.0, 0.05), (16, 0.7, 0.3)])
+def test_kernel_table_matches_oracle(fhmc, L, t, dtau):
+    from oracle import lattice
+    out = np.zeros(L)
+    assert fhmc.lib.fh_debug_kernel_table(L, t, dtau, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == 0
+    ref = lattice.g_1d(L, t, dtau)
+    assert np.allclose(out, ref, rtol=1e-13, atol=0)
+    assert np.all(out > 0)
+
+
+def test_philox_matches_oracle_and_numpy(fhmc):
+    from oracle import philox
+    rng = np.random.default_rng(9)
+    out = (ctypes.c_uint64 * 4)()
+    for _ in range(200):
+        c = [int(v) for v in rng.integers(0, 2**63, size=4, dtype=np.uint64)]
+        k = [int(v) for v in rng.integers(0, 2**63, size=2, dtype=np.uint64)]
+        assert fhmc.lib.fh_debug_philox(*c, *k, out) == 0
+        ref = philox.philox4x64(*[np.uint64(v) for v in c], np.uint64(k[0]), np.uint64(k[1]))
+        assert list(out) == [int(r) for r in ref]
+        if c[0] >= 1:
+            bg = np.random.Philox(key=np.array(k, dtype=np.uint64),
+                                  counter=np.array([c[0] - 1] + c[1:], dtype=np.uint64))
+            assert list(out) == [int(v) for v in bg.random_raw(4)]
+
+
+def bad_descs():
+    import synth
+    good = synth.half_filled(4, 16, synth.HS_GAUSS, 4.0, 0.1, 0)
+    import dataclasses
+    r = dataclasses.replace
+    return [r(good, L=1), r(good, L=5), r(good, L=128), r(good, L_tau=1), r(good, n_up=-1),
+            r(good, n_up=0, n_dn=0), r(good, hs_kind=7), r(good, block_len=1),
+            r(good, block_len=17), r(good, t=0.0), r(good, t=float("nan")), r(good, dtau=-0.1),
+            r(good, U=float("inf")), r(good, hs_kind=synth.HS_HIRSCH, U=-1.0)]
+
+
+def test_init_validates_before_touching_the_device(fhmc):
+    for d in bad_descs():
+        with pytest.raises(fhmc.FhError) as e:
+            fhmc.fh_init([d], fhmc.FH_FP64)
+        assert e.value.code in (fhmc.FH_ERR_INVALID_ARG, fhmc.FH_ERR_UNSUPPORTED), d
+    import synth
+    good = synth.half_filled(4, 16, synth.HS_GAUSS, 4.0, 0.1, 0)
+    with pytest.raises(fhmc.FhError) as e:
+        fhmc.fh_init([good], 9)
+    assert e.value.code == fhmc.FH_ERR_INVALID_ARG
+    with pytest.raises(fhmc.FhError) as e:
+        fhmc.fh_init([good], fhmc.FH_FP64, flags=0x100)
+    assert e.value.code == fhmc.FH_ERR_INVALID_ARG
+    import dataclasses
+    with pytest.raises(fhmc.FhError) as e:
+        fhmc.fh_init([dataclasses.replace(good, L=48)], fhmc.FH_FP32_MFMA3)
+    assert e.value.code == fhmc.FH_ERR_UNSUPPORTED
+
+
+def test_null_plan_calls_are_rejected(fhmc):
+    assert fhmc.lib.fh_destroy(None) == fhmc.FH_ERR_INVALID_ARG
+    assert fhmc.lib.fh_sweep(None, None, None, 0, 1, None) == fhmc.FH_ERR_INVALID_ARG
+    assert fhmc.lib.fh_get_status(None, None, None) == fhmc.FH_ERR_INVALID_ARG
+    assert fhmc.fh_strerror(fhmc.FH_ERR_STATE) == "call order violated"
