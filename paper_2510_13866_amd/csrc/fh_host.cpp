@@ -67,6 +67,44 @@ void build_tables(const fh_chain_desc& d, double* tab) {
     }
 }
 
+uint16_t bf16_rne(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+double bf16_val(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+// Split-bf16 operand of the circulant C[i][j] = g(i - j mod L) (zero outside L x L, 32 x 32
+// tile) in the lane order the MFMA forward filter consumes: term t (x = h + m + l), K chunk q,
+// lane, element e holds term_t(C[R][lane % 32]) with R = 16q + 8(e/4) + 4(lane/32) + e%4.
+void build_cmat(int L, const double* g, uint16_t* out) {
+    if (L > 32) {
+        memset(out, 0, sizeof(uint16_t) * kCmatPerChain);
+        return;
+    }
+    for (int q = 0; q < 2; ++q)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int e = 0; e < 8; ++e) {
+                const int R = 16 * q + 8 * (e / 4) + 4 * (lane / 32) + e % 4;
+                const int n = lane % 32;
+                const double v = (R < L && n < L) ? g[((R - n) % L + L) % L] : 0.0;
+                const uint16_t h = bf16_rne((float)v);
+                const double r1 = v - bf16_val(h);
+                const uint16_t m = bf16_rne((float)r1);
+                const double r2 = r1 - bf16_val(m);
+                const uint16_t l = bf16_rne((float)r2);
+                const uint16_t terms[3] = {h, m, l};
+                for (int t = 0; t < 3; ++t) out[((t * 2 + q) * 64 + lane) * 8 + e] = terms[t];
+            }
+}
+
 bool is_fin(double v) { return std::isfinite(v); }
 
 int validate(const fh_chain_desc& d, int precision) {
@@ -93,7 +131,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 }
 
 void free_device(fh::Device& d) {
-    void* ptrs[] = {d.chains, d.tables, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
+    void* ptrs[] = {d.chains, d.tables, d.cmat, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
                     d.grad_tasks, d.draw_tasks, d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -206,7 +244,11 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->filt_elems = filt;
     p->total_slices = slices;
     p->tables.assign(tab, 0.0);
-    for (int c = 0; c < n_chains; ++c) build_tables(descs[c], p->tables.data() + p->chains[c].tab_off);
+    p->cmat.assign((size_t)kCmatPerChain * n_chains, 0);
+    for (int c = 0; c < n_chains; ++c) {
+        build_tables(descs[c], p->tables.data() + p->chains[c].tab_off);
+        build_cmat(descs[c].L, p->tables.data() + tab_g(p->chains[c]), p->cmat.data() + (size_t)kCmatPerChain * c);
+    }
 
     // Work lists, heaviest chains first so that the long tasks start early.
     std::vector<int> order(n_chains);
@@ -239,6 +281,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     const size_t rs = p->real_size;
     if (e == hipSuccess) e = dalloc(&dv.chains, sizeof(ChainInfo) * n_chains);
     if (e == hipSuccess) e = dalloc(&dv.tables, sizeof(double) * p->tables.size());
+    if (e == hipSuccess) e = dalloc(&dv.cmat, sizeof(uint16_t) * p->cmat.size());
     if (e == hipSuccess) e = dalloc(&dv.W, rs * 2 * (size_t)aux);
     if (e == hipSuccess) e = dalloc(&dv.wshift, sizeof(double) * 2 * (size_t)slices);
     if (e == hipSuccess) e = dalloc(&dv.filt, rs * (size_t)filt);
@@ -251,6 +294,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.sweep, sizeof(uint64_t));
     if (e == hipSuccess) e = hipMemcpy(dv.chains, p->chains.data(), sizeof(ChainInfo) * n_chains, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.tables, p->tables.data(), sizeof(double) * p->tables.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dv.cmat, p->cmat.data(), sizeof(uint16_t) * p->cmat.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.fwd_tasks, fwd.data(), sizeof(PairTask) * fwd.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.grad_tasks, grad.data(), sizeof(PairTask) * grad.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.draw_tasks, draw.data(), sizeof(DrawTask) * draw.size(), hipMemcpyHostToDevice);
@@ -427,8 +471,12 @@ int fh_set_hopping(fh_plan p, const double* t) {
     for (int c = 0; c < p->n_chains; ++c) {
         p->descs[c].t = t[c];
         build_tables(p->descs[c], p->tables.data() + p->chains[c].tab_off);
+        build_cmat(p->descs[c].L, p->tables.data() + tab_g(p->chains[c]),
+                   p->cmat.data() + (size_t)kCmatPerChain * c);
     }
     FH_TRY(hipMemcpy(p->d.tables, p->tables.data(), sizeof(double) * p->tables.size(),
+                     hipMemcpyHostToDevice));
+    FH_TRY(hipMemcpy(p->d.cmat, p->cmat.data(), sizeof(uint16_t) * p->cmat.size(),
                      hipMemcpyHostToDevice));
     p->have_filters = false;
     return FH_OK;

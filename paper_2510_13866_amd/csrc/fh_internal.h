@@ -36,6 +36,7 @@ FH_HD inline int64_t tab_dghat(const ChainInfo& c) { return c.tab_off + c.N; }
 FH_HD inline int64_t tab_g(const ChainInfo& c) { return c.tab_off + 2 * c.N; }
 FH_HD inline int64_t tab_tw(const ChainInfo& c) { return c.tab_off + 2 * c.N + c.L; }
 inline int64_t tab_size(int L) { return 2 * (int64_t)L * L + L + 2 * L; }
+constexpr int kCmatPerChain = 3 * 2 * 64 * 8;
 
 // Block of a sweep: start slice and length (the schedule of fh.h).
 FH_HD inline void block_of(const ChainInfo& c, uint64_t sweep, int b, int* start, int* len) {
@@ -55,6 +56,7 @@ struct DrawTask {
 struct Device {
     ChainInfo* chains = nullptr;
     double* tables = nullptr;
+    uint16_t* cmat = nullptr;  // per chain: split-bf16 circulant operand [3][2][64][8]
     void* W = nullptr;        // [2][sum L_tau*N] in plan precision (up, then down)
     double* wshift = nullptr; // [2][total slices]: log W = log W~ + wshift per (spin, slice)
     void* filt = nullptr;     // filter workspace, plan precision
@@ -76,6 +78,7 @@ struct fh_plan_s {
     std::vector<fh_chain_desc> descs;
     std::vector<fh::ChainInfo> chains;
     std::vector<double> tables;
+    std::vector<uint16_t> cmat;
     int64_t aux_elems = 0, path_elems = 0, particles = 0, blk_elems = 0, filt_elems = 0;
     int32_t n_fwd_tasks = 0, n_grad_tasks = 0, n_draw_tasks = 0;
     int64_t total_slices = 0;

@@ -1,5 +1,202 @@
-// Placeholder until the MFMA forward filter lands.
+// Forward filter on the matrix cores (FH_FP32_MFMA3): the kinetic step as the separable real
+// circulant H = C F C with C[i][j] = g(i - j mod L), computed with v_mfma_f32_32x32x16_bf16
+// and three-term split-bf16 operands.
+//
+// Why a circulant and not an FFT here: the kernel G(d) = g(d_x) g(d_y) is positive, so the
+// direct products carry relative (not max-relative) rounding error and FP32 filters stay far
+// inside 1e-5 over hundreds of slices, where FP32 FFT round-off drifts coherently past it.
+//
+// Layout. One wavefront owns one worldline's L x L filter zero-padded to a 32 x 32 tile, in
+// the MFMA accumulator layout: lane l, register v holds X[rho(l, v)][l % 32] with
+// rho = 8 (v / 4) + 4 (l / 32) + v % 4. Handing those registers straight back as the A operand
+// (chunk q takes registers 8q .. 8q+7) makes the instruction see A[m][kappa] = X[R(kappa)][m]
+// with R(16q + 8h + e) = 16q + 8 (e / 4) + 4h + e % 4, so with B[kappa][n] = C[R(kappa)][n]
+// it computes X^T C. Two such products give (F^T C)^T C = C F C: no transpose, no LDS.
+//
+// Precision. F (each step) and C (once, on the host) are split into bf16 terms
+// x = x_h + x_m + x_l (8 bits each, exact to ~2^-27); the six products of combined order up to
+// 2^-18 (hh, hm, hl, mh, mm, lh) are accumulated in FP32. Fewer terms leave either a coherent
+// bias of the kernel's mass (log Z drifts ~1e-4 over 160 slices) or a filter drift ~4e-5.
+// The normaliser is summed in FP64 and log Z accumulated in FP64.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
 #include "fh_internal.h"
+
 namespace fh {
-hipError_t launch_forward_mfma(fh_plan, const void*, const int32_t*, hipStream_t) { return hipErrorNotSupported; }
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+
+__device__ inline int tile_row(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+
+__device__ inline void set_status(int32_t* st, int code, int chain) {
+    if (atomicCAS(&st[0], 0, code) == 0) atomicExch(&st[1], chain);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+struct Split3 {
+    bf16x8 h[2], m[2], l[2];
+};
+
+// x = h + m + l per element, each term rounded to bf16 (round to nearest even).
+__device__ inline void split3(const f32x16& x, Split3& s) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float v = x[8 * q + e];
+            const __bf16 bh = (__bf16)v;
+            const float r1 = v - (float)bh;
+            const __bf16 bm = (__bf16)r1;
+            const float r2 = r1 - (float)bm;
+            s.h[q][e] = bh;
+            s.m[q][e] = bm;
+            s.l[q][e] = (__bf16)r2;
+        }
+}
+
+__device__ inline f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// X (accumulator layout) -> X^T C, six split products, smaller terms first; the two K chunks
+// go to independent accumulators.
+__device__ inline f32x16 circ_step(const f32x16& x, const Split3& C) {
+    Split3 s;
+    split3(x, s);
+    f32x16 a0 = {}, a1 = {};
+    a0 = mfma(s.l[0], C.h[0], a0);
+    a1 = mfma(s.l[1], C.h[1], a1);
+    a0 = mfma(s.m[0], C.m[0], a0);
+    a1 = mfma(s.m[1], C.m[1], a1);
+    a0 = mfma(s.m[0], C.h[0], a0);
+    a1 = mfma(s.m[1], C.h[1], a1);
+    a0 = mfma(s.h[0], C.l[0], a0);
+    a1 = mfma(s.h[1], C.l[1], a1);
+    a0 = mfma(s.h[0], C.m[0], a0);
+    a1 = mfma(s.h[1], C.m[1], a1);
+    a0 = mfma(s.h[0], C.h[0], a0);
+    a1 = mfma(s.h[1], C.h[1], a1);
+    return a0 + a1;
+}
+
+// One wavefront per (chain, worldline, block): the forward recursion of one block
+//   f~_0 = delta_a; h_j = W~_{start+j} . (C f~_{j-1} C); c_j = sum h_j; f~_j = h_j / c_j
+//   log Z = coef aux_start(a) + sum_j (log c_j + m_{start+j}) + log (C f~_{len-1} C)(e)
+// storing f~_j (j >= 1) as FP32 rows of N values, like the FFT path.
+__global__ __launch_bounds__(kThreads) void k_forward_mfma(
+    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
+    const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, float* __restrict__ filt, double* __restrict__ blk_logz,
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int task = blockIdx.x * kWaves + wv;
+    if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
+    const DrawTask t = tasks[task];
+    const ChainInfo& c = chains[t.chain];
+    int start, len;
+    block_of(c, *sweep_ptr, t.block, &start, &len);
+    const int L = c.L, N = c.N, L_tau = c.L_tau;
+    const int spin = t.p >= c.n_up ? 1 : 0;
+    const float* Wsp = W + spin * aux_elems + c.aux_off;
+    const double* shift = wshift + spin * total_slices + c.slice_off;
+    const double coef = spin ? c.coef_dn : c.coef_up;
+    const int32_t* pc = paths + c.path_off;
+    int a = pc[(int64_t)start * c.np + t.p];
+    int e = pc[(int64_t)((start + len) % L_tau) * c.np + t.p];
+    if (a < 0 || a >= N || e < 0 || e >= N) {
+        if (lane == 0) set_status(status, FH_ERR_BAD_PATH, t.chain);
+        a = (a < 0 || a >= N) ? 0 : a;
+        e = (e < 0 || e >= N) ? 0 : e;
+    }
+    // circulant operand, three bf16 terms, two K chunks: 16 bytes per (term, chunk, lane)
+    Split3 C;
+    {
+        const uint4* cm = (const uint4*)(cmat + (size_t)t.chain * 3 * 2 * 64 * 8);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            uint4 vh = cm[(0 * 2 + q) * 64 + lane];
+            uint4 vm = cm[(1 * 2 + q) * 64 + lane];
+            uint4 vl = cm[(2 * 2 + q) * 64 + lane];
+            C.h[q] = __builtin_bit_cast(bf16x8, vh);
+            C.m[q] = __builtin_bit_cast(bf16x8, vm);
+            C.l[q] = __builtin_bit_cast(bf16x8, vl);
+        }
+    }
+    const int x = lane & 31;
+    const bool xin = x < L;
+    const int ax = a % L, ay = a / L;
+    f32x16 F;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) F[v] = (x == ax && tile_row(lane, v) == ay) ? 1.0f : 0.0f;
+    double la = coef * (double)aux[c.aux_off + (int64_t)start * N + a];
+    float* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+    for (int j = 1; j < len; ++j) {
+        const int l = (start + j) % L_tau;
+        const float* Wl = Wsp + (int64_t)l * N;
+        float w[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int y = tile_row(lane, v);
+            const bool in = xin && y < L;
+            const float wv = Wl[in ? y * L + x : 0];  // always an in-bounds address
+            w[v] = in ? wv : 0.0f;
+        }
+        const f32x16 X = circ_step(F, C);
+        const f32x16 H = circ_step(X, C);
+        float s = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            F[v] = H[v] * w[v];
+            s += F[v];
+        }
+        const double tot = wave_sum((double)s);
+        if (!(tot > 0.0) || !isfinite(tot))
+            if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
+        const float inv = (float)(1.0 / tot);
+        la += log(tot) + shift[l];
+        float* row = rows + (int64_t)(j - 1) * N;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            F[v] *= inv;
+            const int y = tile_row(lane, v);
+            if (xin && y < L) row[y * L + x] = F[v];
+        }
+    }
+    // end weight (C f~ C)(e)
+    const f32x16 X = circ_step(F, C);
+    const f32x16 H = circ_step(X, C);
+    const int ex = e % L, ey = e / L;
+    const int ve = (ey >> 3) * 4 + (ey & 3);
+    const int le = ex + 32 * ((ey >> 2) & 1);
+    float hv = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+        if (v == ve) hv = H[v];
+    hv = __shfl(hv, le, 64);
+    if (lane == 0) blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log((double)hv);
+}
+
+}  // namespace
+
+hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
+    const unsigned blocks = (unsigned)((p->n_draw_tasks + kWaves - 1) / kWaves);
+    hipLaunchKernelGGL(k_forward_mfma, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                       p->d.draw_tasks, p->n_draw_tasks, p->d.cmat, (const float*)aux,
+                       (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices, paths,
+                       (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
+    return hipGetLastError();
+}
+
 }  // namespace fh

@@ -32,6 +32,13 @@ def lib(gpu):
     return fhmc, sampler
 
 
+PRECS = {"fp64": 0, "fp32": 1, "mfma3": 2}
+# normwise filter tolerance per precision: FP64 plain, FP32 FFT (its round-off drifts
+# coherently over many slices, measured ~5e-5 at 160 slices), FP32 split-bf16 MFMA circulant
+FILTER_TOL = {"fp64": 1e-11, "fp32": 2e-5, "mfma3": 1e-5}
+FILTER_TOL_FULL = {"fp64": 1e-11, "fp32": 2e-4, "mfma3": 1e-5}
+
+
 MIXED = [
     synth.config_small_fp64()[0],                                                    # 4x4 Gauss
     synth.ChainDesc(L=3, L_tau=7, n_up=4, n_dn=3, hs_kind=synth.HS_HIRSCH, block_len=0,
@@ -90,8 +97,9 @@ def oracle_forward(desc, aux, paths, s, particles=None, with_tail=False):
 
 
 def logz_tol(prec, ref_lz, tail):
-    """Relative-to-Z floor plus the FFT's resolution limit at the end site (see oracle_forward)."""
-    eps = 1e-15 if prec == "fp64" else 6e-8
+    """Relative-to-Z floor plus the FFT's resolution limit at the end site (see oracle_forward).
+    The MFMA circulant works with positive products only, so it has no such limit."""
+    eps = {"fp64": 1e-15, "fp32": 6e-8, "mfma3": 0.0}[prec]
     floor = 1e-12 if prec == "fp64" else 2e-6
     return floor * (1 + np.abs(ref_lz)) + 10 * eps * tail
 
@@ -112,10 +120,10 @@ def check_paths(desc, got, ref, margins, what):
     return len(bad)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mfma3"])
 def test_forward_filter_parity_mixed_batch(lib, prec):
     fhmc, sampler = lib
-    precision = fhmc.FH_FP64 if prec == "fp64" else fhmc.FH_FP32
+    precision = PRECS[prec]
     descs = MIXED
     say("forward parity", prec, [(d.L, d.L_tau, d.n_up, d.n_dn, d.block_len) for d in descs])
     S = sampler.Sampler(descs, precision)
@@ -131,7 +139,7 @@ def test_forward_filter_parity_mixed_batch(lib, prec):
             for p in range(d.n_particles):
                 got = S.filters(c, p)
                 err = rel_row_err(got, ref_rows[p])
-                assert err <= (1e-11 if prec == "fp64" else 2e-5), (c, p, s, err)
+                assert err <= FILTER_TOL[prec], (c, p, s, err)
     S.close()
 
 
@@ -206,10 +214,10 @@ def test_sweep_trajectory_small_fp64(lib):
     S.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mfma3"])
 def test_graph_replay_equals_eager_and_resume(lib, prec):
     fhmc, sampler = lib
-    precision = fhmc.FH_FP64 if prec == "fp64" else fhmc.FH_FP32
+    precision = PRECS[prec]
     descs = MIXED[:4]
     say("graph vs eager", prec)
     aux, paths = mixed_state(descs, seed=8, random_paths=False)
@@ -232,7 +240,7 @@ def test_batch_invariance(lib):
     """A chain gives bit-identical results alone and inside an uneven batch."""
     fhmc, sampler = lib
     say("batch invariance")
-    for precision in (fhmc.FH_FP64, fhmc.FH_FP32):
+    for precision in (fhmc.FH_FP64, fhmc.FH_FP32, fhmc.FH_FP32_MFMA3):
         aux, paths = mixed_state(MIXED, seed=12, random_paths=False)
         Sb = sampler.Sampler(MIXED, precision)
         Ab, Pb = Sb.pack_aux(aux), Sb.pack_paths(paths)
@@ -247,13 +255,13 @@ def test_batch_invariance(lib):
         Sa.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mfma3"])
 def test_full_size_sampled_parity(lib, prec):
     """32x32, L_tau=160, 512+512 worldlines, 2 chains (the benchmark's shape and launch):
     log Z of every particle against the oracle on a sample of particles, their filters and,
     in FP64, their redrawn sites."""
     fhmc, sampler = lib
-    precision = fhmc.FH_FP64 if prec == "fp64" else fhmc.FH_FP32
+    precision = PRECS[prec]
     descs = synth.config_32x32(4.0, n_chains=2)
     say("full size sampled parity", prec)
     S = sampler.Sampler(descs, precision)
@@ -272,7 +280,7 @@ def test_full_size_sampled_parity(lib, prec):
         for k, p in enumerate(sample):
             err = rel_row_err(S.filters(c, p), ref_rows[k])
             worst = max(worst, err)
-            assert err <= (1e-11 if prec == "fp64" else 2e-4), (c, p, err)
+            assert err <= FILTER_TOL_FULL[prec], (c, p, err)
     say("  worst filter error", prec, worst)
     if prec == "fp64":
         before = S.unpack_paths(P)
@@ -372,7 +380,7 @@ def test_extreme_field_values_stay_finite(lib):
     aux[:, 5] += 900.0                      # a * 900 = 569: exp overflows FP32 and nearly FP64
     paths = synth.initial_paths(d)
     paths[:, :3] = 5
-    for prec, tol in ((fhmc.FH_FP64, 1e-11), (fhmc.FH_FP32, 1e-5)):
+    for prec, tol in ((fhmc.FH_FP64, 1e-11), (fhmc.FH_FP32, 1e-5), (fhmc.FH_FP32_MFMA3, 1e-5)):
         S = sampler.Sampler([d], prec)
         A, P = S.pack_aux([aux]), S.pack_paths([paths])
         lz = S.unpack_particles(S.forward_filter(A, P, 0))[0]
