@@ -419,6 +419,132 @@ __global__ __launch_bounds__(kThreads) void k_backward(
     }
 }
 
+// Backward sampling for N <= 1024 (at most 16 sites per lane), same draw rule as k_backward:
+// the lane's weights stay in registers between the scan and the search, the next filter row is
+// loaded while the current one is searched, g lives in LDS, and lane k computes the Philox
+// uniform of draw s = 64 b + k once per 64 draws (broadcast with a shuffle when used).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_backward_fast(
+    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
+    const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    constexpr int E = 16;
+    __shared__ double gsh[kWaves][kMaxL];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int task = blockIdx.x * kWaves + wv;
+    const bool active = task < n_tasks;
+    DrawTask t = {0, 0, 0, 0};
+    if (active) {
+        t = tasks[task];
+        const ChainInfo& c0 = chains[t.chain];
+        for (int m = lane; m < c0.L; m += 64) gsh[wv][m] = tables[tab_g(c0) + m];
+    }
+    __syncthreads();  // the only barrier; every wave reaches it
+    if (!active) return;
+    const ChainInfo& c = chains[t.chain];
+    const uint64_t sweep = *sweep_ptr;
+    int start, len;
+    block_of(c, sweep, t.block, &start, &len);
+    if (len < 2) return;
+    const int N = c.N, L = c.L, L_tau = c.L_tau;
+    const double* g = gsh[wv];
+    int32_t* pc = paths + c.path_off;
+    int cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np + t.p], N, status, t.chain);
+    const int per = (N + 63) / 64;  // sites per lane (<= E)
+    const int i0 = lane * per;
+    const int cnt = max(0, min(per, N - i0));
+    const int x0 = cnt > 0 ? i0 % L : 0, y0 = cnt > 0 ? i0 / L : 0;
+    const T* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+    T fv[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) fv[k] = k < cnt ? rows[(int64_t)(len - 2) * N + i0 + k] : T(0);
+    double ureg = 0.0;
+    for (int s = 0; s < len - 1; ++s) {
+        const int j = len - 1 - s;
+        if ((s & 63) == 0) {
+            const int jj = j - lane;
+            ureg = 0.0;
+            if (jj >= 1) {
+                const u64x4 r = philox4x64_10((uint64_t)t.p, (uint64_t)((start + jj) % L_tau),
+                                              sweep, kTagPath, c.seed, 0);
+                ureg = u01_from(r.x0);
+            }
+        }
+        const double u = __shfl(ureg, s & 63, 64);
+        T f[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) f[k] = fv[k];
+        if (j >= 2) {
+            const T* nxt = rows + (int64_t)(j - 2) * N + i0;
+#pragma unroll
+            for (int k = 0; k < E; ++k) fv[k] = k < cnt ? nxt[k] : T(0);
+        }
+        const int cx = cur % L, cy = cur / L;
+        double w[E];
+        double tot = 0.0;
+        {
+            int x = x0, y = y0;
+            int dy = cy - y;
+            dy += dy < 0 ? L : 0;
+            double gy = g[dy];
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                double wk = 0.0;
+                if (k < cnt) {
+                    int dx = cx - x;
+                    dx += dx < 0 ? L : 0;
+                    const double fk = (double)f[k];
+                    wk = (fk > 0.0 ? fk : 0.0) * (gy * g[dx]);
+                    if (++x == L) {
+                        x = 0;
+                        ++y;
+                        dy = cy - y;
+                        dy += dy < 0 ? L : 0;
+                        gy = g[dy];
+                    }
+                }
+                w[k] = wk;
+                tot += wk;
+            }
+        }
+        double incl = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double up = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += up;
+        }
+        double run = __shfl_up(incl, 1, 64);
+        if (lane == 0) run = 0.0;
+        const double total = __shfl(incl, 63, 64);
+        int chosen = cur;
+        if (!(total > 0.0) || !isfinite(total)) {
+            if (lane == 0)
+                set_status(status, isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE, t.chain);
+        } else {
+            const double T_ = u * total;
+            int first = -1;
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                run += w[k];
+                if (first < 0 && k < cnt && run > T_) first = i0 + k;
+            }
+            const uint64_t found = __ballot(first >= 0);
+            if (found) {
+                chosen = __shfl(first, __ffsll((unsigned long long)found) - 1, 64);
+            } else {
+                int lastpos = -1;
+#pragma unroll
+                for (int k = 0; k < E; ++k)
+                    if (k < cnt && w[k] > 0.0) lastpos = i0 + k;
+                const uint64_t has = __ballot(lastpos >= 0);
+                if (has) chosen = __shfl(lastpos, 63 - __clzll((long long)has), 64);
+            }
+        }
+        if (lane == 0) pc[(int64_t)((start + j) % L_tau) * c.np + t.p] = chosen;
+        cur = chosen;
+    }
+}
+
 // Occupation counts of one slice (LDS histogram) and the exact field draw of every site:
 // Ising: s = +1 iff u < (1 + tanh(lambda (n_up - n_dn))) / 2; Gaussian: sigma = a (n - 1/2) + z.
 template <typename T>
@@ -672,6 +798,17 @@ hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s) {
 
 hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
     const unsigned blocks = (unsigned)((p->n_draw_tasks + kWaves - 1) / kWaves);
+    if (p->max_N <= 1024) {
+        if (p->precision == FH_FP64)
+            hipLaunchKernelGGL(k_backward_fast<double>, dim3(blocks), dim3(kThreads), 0, s,
+                               p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
+                               (const double*)p->d.filt, paths, p->d.sweep, p->d.status);
+        else
+            hipLaunchKernelGGL(k_backward_fast<float>, dim3(blocks), dim3(kThreads), 0, s,
+                               p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
+                               (const float*)p->d.filt, paths, p->d.sweep, p->d.status);
+        return hipGetLastError();
+    }
     if (p->precision == FH_FP64)
         hipLaunchKernelGGL(k_backward<double>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.draw_tasks, p->n_draw_tasks, p->d.tables,

@@ -17,7 +17,7 @@
 // x = x_h + x_m + x_l (8 bits each, exact to ~2^-27); the six products of combined order up to
 // 2^-18 (hh, hm, hl, mh, mm, lh) are accumulated in FP32. Fewer terms leave either a coherent
 // bias of the kernel's mass (log Z drifts ~1e-4 over 160 slices) or a filter drift ~4e-5.
-// The normaliser is summed in FP64 and log Z accumulated in FP64.
+// The per-step normaliser is a DPP wavefront sum in FP32; log Z is accumulated in FP64.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -38,63 +38,71 @@ __device__ inline void set_status(int32_t* st, int code, int chain) {
     if (atomicCAS(&st[0], 0, code) == 0) atomicExch(&st[1], chain);
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 struct Split3 {
     bf16x8 h[2], m[2], l[2];
 };
 
-// x = h + m + l per element, each term rounded to bf16 (round to nearest even).
-__device__ inline void split3(const f32x16& x, Split3& s) {
+// Registers 8q .. 8q+7 of x as x = h + m + l, each term rounded to bf16 (nearest even).
+__device__ inline void split3_chunk(const f32x16& x, int q, bf16x8& h, bf16x8& m, bf16x8& l) {
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float v = x[8 * q + e];
-            const __bf16 bh = (__bf16)v;
-            const float r1 = v - (float)bh;
-            const __bf16 bm = (__bf16)r1;
-            const float r2 = r1 - (float)bm;
-            s.h[q][e] = bh;
-            s.m[q][e] = bm;
-            s.l[q][e] = (__bf16)r2;
-        }
+    for (int e = 0; e < 8; ++e) {
+        const float v = x[8 * q + e];
+        const __bf16 bh = (__bf16)v;
+        const float r1 = v - (float)bh;
+        const __bf16 bm = (__bf16)r1;
+        const float r2 = r1 - (float)bm;
+        h[e] = bh;
+        m[e] = bm;
+        l[e] = (__bf16)r2;
+    }
 }
 
 __device__ inline f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-// X (accumulator layout) -> X^T C, six split products, smaller terms first; the two K chunks
-// go to independent accumulators.
+// X (accumulator layout) -> X^T C: six split products per K chunk, smaller terms first.
 __device__ inline f32x16 circ_step(const f32x16& x, const Split3& C) {
-    Split3 s;
-    split3(x, s);
-    f32x16 a0 = {}, a1 = {};
-    a0 = mfma(s.l[0], C.h[0], a0);
-    a1 = mfma(s.l[1], C.h[1], a1);
-    a0 = mfma(s.m[0], C.m[0], a0);
-    a1 = mfma(s.m[1], C.m[1], a1);
-    a0 = mfma(s.m[0], C.h[0], a0);
-    a1 = mfma(s.m[1], C.h[1], a1);
-    a0 = mfma(s.h[0], C.l[0], a0);
-    a1 = mfma(s.h[1], C.l[1], a1);
-    a0 = mfma(s.h[0], C.m[0], a0);
-    a1 = mfma(s.h[1], C.m[1], a1);
-    a0 = mfma(s.h[0], C.h[0], a0);
-    a1 = mfma(s.h[1], C.h[1], a1);
-    return a0 + a1;
+    f32x16 acc = {};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        bf16x8 h, m, l;
+        split3_chunk(x, q, h, m, l);
+        acc = mfma(l, C.h[q], acc);
+        acc = mfma(m, C.m[q], acc);
+        acc = mfma(m, C.h[q], acc);
+        acc = mfma(h, C.l[q], acc);
+        acc = mfma(h, C.m[q], acc);
+        acc = mfma(h, C.h[q], acc);
+    }
+    return acc;
+}
+
+// Sum over the wavefront: DPP within rows of 16 lanes, then the four row sums via readlane.
+template <int CTRL>
+__device__ inline float dpp_add(float v) {
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                   0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ inline float wave_sum_f32(float v) {
+    v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0x141>(v);  // row_half_mirror
+    v = dpp_add<0x140>(v);  // row_mirror
+    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
 // One wavefront per (chain, worldline, block): the forward recursion of one block
 //   f~_0 = delta_a; h_j = W~_{start+j} . (C f~_{j-1} C); c_j = sum h_j; f~_j = h_j / c_j
 //   log Z = coef aux_start(a) + sum_j (log c_j + m_{start+j}) + log (C f~_{len-1} C)(e)
-// storing f~_j (j >= 1) as FP32 rows of N values, like the FFT path.
-__global__ __launch_bounds__(kThreads) void k_forward_mfma(
+// storing f~_j (j >= 1) as FP32 rows of N values, like the FFT path. LFIX = 32 compiles the
+// common full-tile case with constant offsets; LFIX = 0 handles any L <= 32 by zero padding.
+template <int LFIX>
+__global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
@@ -107,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma(
     const ChainInfo& c = chains[t.chain];
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
-    const int L = c.L, N = c.N, L_tau = c.L_tau;
+    const int L = LFIX ? LFIX : c.L, N = LFIX ? LFIX * LFIX : c.N, L_tau = c.L_tau;
     const int spin = t.p >= c.n_up ? 1 : 0;
     const float* Wsp = W + spin * aux_elems + c.aux_off;
     const double* shift = wshift + spin * total_slices + c.slice_off;
@@ -135,12 +143,13 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma(
         }
     }
     const int x = lane & 31;
-    const bool xin = x < L;
+    const bool xin = LFIX ? true : x < L;
     const int ax = a % L, ay = a / L;
     f32x16 F;
 #pragma unroll
     for (int v = 0; v < 16; ++v) F[v] = (x == ax && tile_row(lane, v) == ay) ? 1.0f : 0.0f;
     double la = coef * (double)aux[c.aux_off + (int64_t)start * N + a];
+    double prod = 1.0;
     float* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
     for (int j = 1; j < len; ++j) {
         const int l = (start + j) % L_tau;
@@ -149,7 +158,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma(
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int y = tile_row(lane, v);
-            const bool in = xin && y < L;
+            const bool in = LFIX ? true : (xin && y < L);
             const float wv = Wl[in ? y * L + x : 0];  // always an in-bounds address
             w[v] = in ? wv : 0.0f;
         }
@@ -161,17 +170,24 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma(
             F[v] = H[v] * w[v];
             s += F[v];
         }
-        const double tot = wave_sum((double)s);
-        if (!(tot > 0.0) || !isfinite(tot))
+        const float tot = wave_sum_f32(s);
+        if (!(tot > 0.0f) || !isfinite(tot))
             if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
-        const float inv = (float)(1.0 / tot);
-        la += log(tot) + shift[l];
+        // f~_j = h_j * inv, so the normaliser actually applied is exactly 1/inv: log Z takes
+        // -log(inv), accumulated as an FP64 product folded into the log occasionally
+        const float inv = __builtin_amdgcn_rcpf(tot);
+        prod *= (double)inv;
+        if (!(prod > 1e-200 && prod < 1e200)) {
+            la -= log(prod);
+            prod = 1.0;
+        }
+        la += shift[l];
         float* row = rows + (int64_t)(j - 1) * N;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             F[v] *= inv;
             const int y = tile_row(lane, v);
-            if (xin && y < L) row[y * L + x] = F[v];
+            if (LFIX || (xin && y < L)) row[y * L + x] = F[v];
         }
     }
     // end weight (C f~ C)(e)
@@ -185,6 +201,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma(
     for (int v = 0; v < 16; ++v)
         if (v == ve) hv = H[v];
     hv = __shfl(hv, le, 64);
+    la -= log(prod);
     if (lane == 0) blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log((double)hv);
 }
 
@@ -192,10 +209,18 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma(
 
 hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
     const unsigned blocks = (unsigned)((p->n_draw_tasks + kWaves - 1) / kWaves);
-    hipLaunchKernelGGL(k_forward_mfma, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                       p->d.draw_tasks, p->n_draw_tasks, p->d.cmat, (const float*)aux,
-                       (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices, paths,
-                       (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
+    bool all32 = true;
+    for (const ChainInfo& c : p->chains) all32 = all32 && c.L == 32;
+    if (all32)
+        hipLaunchKernelGGL(k_forward_mfma<32>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.draw_tasks, p->n_draw_tasks, p->d.cmat, (const float*)aux,
+                           (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
+                           paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
+    else
+        hipLaunchKernelGGL(k_forward_mfma<0>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.draw_tasks, p->n_draw_tasks, p->d.cmat, (const float*)aux,
+                           (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
+                           paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
     return hipGetLastError();
 }
 
