@@ -419,16 +419,46 @@ __global__ __launch_bounds__(kThreads) void k_backward(
     }
 }
 
+// Cross-lane helpers on DPP and readlane (no LDS crossbar).
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {  // value of the DPP source lane, 0 where none
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
+}
+__device__ inline double readlane_f64(double v, int lane) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+// Inclusive prefix sum over the 64 lanes (Hillis-Steele inside each row of 16 lanes with
+// row_shr, then the three preceding row totals); *total receives the sum of all lanes.
+__device__ inline double wave_incl_scan_f64(double v, int lane, double* total) {
+    v += dpp_f64<0x111>(v);  // row_shr:1
+    v += dpp_f64<0x112>(v);  // row_shr:2
+    v += dpp_f64<0x114>(v);  // row_shr:4
+    v += dpp_f64<0x118>(v);  // row_shr:8
+    const double r0 = readlane_f64(v, 15), r1 = readlane_f64(v, 31), r2 = readlane_f64(v, 47);
+    const double r3 = readlane_f64(v, 63);
+    const int row = lane >> 4;
+    const double base = row == 0 ? 0.0 : row == 1 ? r0 : row == 2 ? r0 + r1 : (r0 + r1) + r2;
+    *total = ((r0 + r1) + r2) + r3;
+    return v + base;
+}
+
 // Backward sampling for N <= 1024 (at most 16 sites per lane), same draw rule as k_backward:
-// the lane's weights stay in registers between the scan and the search, the next filter row is
-// loaded while the current one is searched, g lives in LDS, and lane k computes the Philox
-// uniform of draw s = 64 b + k once per 64 draws (broadcast with a shuffle when used).
-template <typename T>
+// the lane's weights stay in registers between the scan and the search, filter rows are
+// prefetched ahead (two rows in FP32, one in FP64; 16-byte loads when rows are aligned), g lives
+// in LDS, and lane k computes the Philox uniform of draw s = 64 b + k once per 64 draws.
+template <typename T, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_backward_fast(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
     const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
     constexpr int E = 16;
+    constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;  // rows in flight ahead of the current one
     __shared__ double gsh[kWaves][kMaxL];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int task = blockIdx.x * kWaves + wv;
@@ -455,9 +485,29 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
     const int cnt = max(0, min(per, N - i0));
     const int x0 = cnt > 0 ? i0 % L : 0, y0 = cnt > 0 ? i0 / L : 0;
     const T* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
-    T fv[E];
+    // row of draw j is rows + (j - 1) N; draws run j = len-1 .. 1
+    auto load_row = [&](int j, T (&dst)[E]) {
+        const T* r = rows + (int64_t)(j - 1) * N + i0;
+        if (VEC) {
+            typedef T vec4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-    for (int k = 0; k < E; ++k) fv[k] = k < cnt ? rows[(int64_t)(len - 2) * N + i0 + k] : T(0);
+            for (int q = 0; q < E / 4; ++q) {
+                vec4 v4 = {T(0), T(0), T(0), T(0)};
+                if (4 * q < cnt) v4 = *(const vec4*)(r + 4 * q);
+                dst[4 * q] = v4[0];
+                dst[4 * q + 1] = v4[1];
+                dst[4 * q + 2] = v4[2];
+                dst[4 * q + 3] = v4[3];
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < E; ++k) dst[k] = k < cnt ? r[k] : T(0);
+        }
+    };
+    T ring[DEPTH + 1][E];
+#pragma unroll
+    for (int d = 0; d <= DEPTH; ++d)
+        if (len - 1 - d >= 1) load_row(len - 1 - d, ring[d]);
     double ureg = 0.0;
     for (int s = 0; s < len - 1; ++s) {
         const int j = len - 1 - s;
@@ -470,15 +520,15 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
                 ureg = u01_from(r.x0);
             }
         }
-        const double u = __shfl(ureg, s & 63, 64);
+        const double u = readlane_f64(ureg, s & 63);
         T f[E];
 #pragma unroll
-        for (int k = 0; k < E; ++k) f[k] = fv[k];
-        if (j >= 2) {
-            const T* nxt = rows + (int64_t)(j - 2) * N + i0;
+        for (int k = 0; k < E; ++k) f[k] = ring[0][k];
 #pragma unroll
-            for (int k = 0; k < E; ++k) fv[k] = k < cnt ? nxt[k] : T(0);
-        }
+        for (int d = 0; d < DEPTH; ++d)
+#pragma unroll
+            for (int k = 0; k < E; ++k) ring[d][k] = ring[d + 1][k];
+        if (j - 1 - DEPTH >= 1) load_row(j - 1 - DEPTH, ring[DEPTH]);
         const int cx = cur % L, cy = cur / L;
         double w[E];
         double tot = 0.0;
@@ -507,15 +557,9 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
                 tot += wk;
             }
         }
-        double incl = tot;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const double up = __shfl_up(incl, o, 64);
-            if (lane >= o) incl += up;
-        }
-        double run = __shfl_up(incl, 1, 64);
-        if (lane == 0) run = 0.0;
-        const double total = __shfl(incl, 63, 64);
+        double total;
+        const double incl = wave_incl_scan_f64(tot, lane, &total);
+        double run = incl - tot;
         int chosen = cur;
         if (!(total > 0.0) || !isfinite(total)) {
             if (lane == 0)
@@ -530,14 +574,14 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
             }
             const uint64_t found = __ballot(first >= 0);
             if (found) {
-                chosen = __shfl(first, __ffsll((unsigned long long)found) - 1, 64);
+                chosen = __builtin_amdgcn_readlane(first, __ffsll((unsigned long long)found) - 1);
             } else {
                 int lastpos = -1;
 #pragma unroll
                 for (int k = 0; k < E; ++k)
                     if (k < cnt && w[k] > 0.0) lastpos = i0 + k;
                 const uint64_t has = __ballot(lastpos >= 0);
-                if (has) chosen = __shfl(lastpos, 63 - __clzll((long long)has), 64);
+                if (has) chosen = __builtin_amdgcn_readlane(lastpos, 63 - __clzll((long long)has));
             }
         }
         if (lane == 0) pc[(int64_t)((start + j) % L_tau) * c.np + t.p] = chosen;
@@ -727,6 +771,13 @@ unsigned grid_for(int64_t n) {
     return (unsigned)b;
 }
 
+template <typename T, bool VEC>
+void launch_bwd_fast(fh_plan p, int32_t* paths, unsigned blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_backward_fast<T, VEC>), dim3(blocks), dim3(kThreads), 0, s,
+                       p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
+                       (const T*)p->d.filt, paths, p->d.sweep, p->d.status);
+}
+
 }  // namespace
 
 size_t forward_lds_bytes(fh_plan p) {
@@ -799,14 +850,16 @@ hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s) {
 hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
     const unsigned blocks = (unsigned)((p->n_draw_tasks + kWaves - 1) / kWaves);
     if (p->max_N <= 1024) {
-        if (p->precision == FH_FP64)
-            hipLaunchKernelGGL(k_backward_fast<double>, dim3(blocks), dim3(kThreads), 0, s,
-                               p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
-                               (const double*)p->d.filt, paths, p->d.sweep, p->d.status);
-        else
-            hipLaunchKernelGGL(k_backward_fast<float>, dim3(blocks), dim3(kThreads), 0, s,
-                               p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
-                               (const float*)p->d.filt, paths, p->d.sweep, p->d.status);
+        // 16-byte row loads need every row start and every lane's first site 4-aligned
+        bool vec = true;
+        for (const ChainInfo& c : p->chains) vec = vec && c.N % 256 == 0;
+        if (p->precision == FH_FP64) {
+            if (vec) launch_bwd_fast<double, true>(p, paths, blocks, s);
+            else launch_bwd_fast<double, false>(p, paths, blocks, s);
+        } else {
+            if (vec) launch_bwd_fast<float, true>(p, paths, blocks, s);
+            else launch_bwd_fast<float, false>(p, paths, blocks, s);
+        }
         return hipGetLastError();
     }
     if (p->precision == FH_FP64)
