@@ -17,7 +17,6 @@ bounded sample (one chain, one sweep) and scales it to the same unit.
 import argparse
 import json
 import os
-import statistics
 import sys
 import time
 
@@ -26,7 +25,10 @@ sys.path.insert(0, ROOT)
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_mfma3": 2}
 HBM_PEAK_GBS = 8000.0
-PEAKS_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+KERNEL_SOURCES = {"forward": {"fp32_mfma3": "fh_mfma.hip", "fp32": "fh_kernels.hip",
+                              "fp64": "fh_kernels.hip"},
+                  "backward": {"fp32_mfma3": "fh_kernels.hip", "fp32": "fh_kernels.hip",
+                               "fp64": "fh_kernels.hip"}}
 
 
 def parse():
@@ -34,12 +36,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=sorted(PRECISIONS))
+    ap.add_argument("--precision", default="fp32_mfma3", choices=sorted(PRECISIONS))
     ap.add_argument("--chains", type=int, default=16)
     ap.add_argument("--U", type=float, default=4.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-error", action="store_true", help="skip the error-vs-oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -47,11 +51,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def fft_flops_per_particle_slice(N):
-    import math
-    # one complex 2D FFT pair per two worldlines = 5 N log2 N per worldline-slice, plus the
-    # pointwise ghat and W products, the sum and the rescale
-    return 5.0 * N * math.log2(N) + 6.0 * N
+def source_sha(name):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2510_13866_amd", "csrc", name)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source; None otherwise."""
+    src = KERNEL_SOURCES[kernel][precision]
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s_%s_32x32_Ltau160.md" % (kernel, precision))
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic_json:"):
+            rec = json.loads(line[len("traffic_json:"):])
+            if rec.get("source_sha256") != source_sha(src):
+                return None
+            return rec["fetch_bytes"] + rec["write_bytes"]
+    return None
 
 
 def time_sweeps(S, A, P, A0, P0, first, n, stream):
@@ -73,8 +92,8 @@ def time_sweeps(S, A, P, A0, P0, first, n, stream):
 
 
 def time_forward(S, A, P, n, stream):
-    """Average duration of fh_forward_filter (potentials + forward kernel) over n launches,
-    HIP events recorded on the stream the kernels are launched on."""
+    """Average duration of fh_forward_filter (site potentials + forward filter kernel) over n
+    launches, HIP events recorded on the stream the kernels are launched on."""
     import torch
     from paper_2510_13866_amd import fhmc
     e0 = torch.cuda.Event(enable_timing=True)
@@ -86,6 +105,38 @@ def time_forward(S, A, P, n, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / n
+
+
+def time_backward(S, A, P, n, stream):
+    """Average duration of fh_backward_sample over n launches after one forward filter (the
+    block endpoints do not change, so every launch redraws the same interiors)."""
+    import torch
+    from paper_2510_13866_amd import fhmc
+    fhmc.fh_forward_filter(S.plan, A, P, 2000, None, stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(n):
+        fhmc.fh_backward_sample(S.plan, P, 2000, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def copy_calibration(stream):
+    """A plain device copy of 1 GiB, five times: its FETCH_SIZE / WRITE_SIZE counters give the
+    factor that turns those counters into HBM bytes."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for _ in range(5):
+            b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def filter_error_sample(S, descs, aux, paths, sweep):
@@ -111,8 +162,8 @@ def filter_error_sample(S, descs, aux, paths, sweep):
     return float(np.max(errs)), float(np.median(errs))
 
 
-def cpu_baseline(desc, aux, paths):
-    """The oracle as it stands, one chain, one sweep, on the host cores."""
+def cpu_baseline(desc, aux, paths, n_sweeps=6):
+    """The oracle as it stands, one chain, n_sweeps sweeps, on the host cores."""
     import numpy as np
     from oracle import sweep as osweep
     try:
@@ -122,11 +173,13 @@ def cpu_baseline(desc, aux, paths):
         threads = os.cpu_count()
     tab = osweep.ChainTables(desc)
     t0 = time.perf_counter()
-    osweep.sweep(desc, aux, paths, 0, tab)
+    for s in range(n_sweeps):
+        aux, paths, _ = osweep.sweep(desc, aux, paths, s, tab)
     dt = time.perf_counter() - t0
-    return {"value": desc.N * desc.L_tau / dt, "unit": "site-slice updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "1 chain x 1 sweep of 32x32, L_tau=160, 512+512 worldlines (%.1f s)" % dt}
+    return {"value": n_sweeps * desc.N * desc.L_tau / dt, "unit": "site-slice updates/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "1 chain x %d sweeps of 32x32, L_tau=160, 512+512 worldlines (%.1f s)"
+                      % (n_sweeps, dt)}
 
 
 def main():
@@ -147,6 +200,8 @@ def main():
     paths = [synth.initial_paths(d) for d in descs]
     stream = torch.cuda.Stream()
     prec = PRECISIONS[args.precision]
+    if args.calibrate_copy:
+        copy_calibration(stream)
     sites = sum(d.N * d.L_tau for d in descs)
 
     log("bench: %s, %d chains 32x32 L_tau=160, warmup %d, steps %d" %
@@ -164,19 +219,32 @@ def main():
     value = sites * args.steps / (ms / 1e3)
     log("  %.3f ms/sweep, %.3e site-slice updates/s" % (ms_step, value))
 
-    # dominant kernel: the forward filter
+    # the two hot kernels, each timed alone on its stream; both move the spilled filters:
+    # the forward filter writes every filter row once, the backward sampler reads it once
     nf = max(3, min(10, args.steps))
     fwd_ms = time_forward(S, A, P, nf, stream)
-    particle_slices = sum(d.n_particles * (d.L_tau - 1) for d in descs)
+    bwd_ms = time_backward(S, A, P, nf, stream)
+    rsz = 8 if args.precision == "fp64" else 4
+    rows = sum(d.n_particles * (d.L_tau - 1) for d in descs)       # one block per worldline
     N = descs[0].N
-    flops = particle_slices * fft_flops_per_particle_slice(N)
-    tflops = flops / (fwd_ms / 1e3) / 1e12
-    peak = PEAKS_TFLOPS["fp64" if args.precision == "fp64" else "fp32"]
-    roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(tflops / peak, 4), "traffic": None,
-            "kernel": "forward filter (k_forward_fft)", "ms_per_launch": round(fwd_ms, 4),
-            "flops_per_launch": flops}
-    log("  forward filter %.3f ms/launch, %.2f TFLOP/s" % (fwd_ms, tflops))
+    w_bytes = sum(2 * d.L_tau * d.N * rsz for d in descs)         # site potentials, both spins
+    algo = {"forward": rows * N * rsz + w_bytes,
+            "backward": rows * (N * rsz + 4)}                      # + the drawn site (int32)
+    times = {"forward": fwd_ms, "backward": bwd_ms}
+    names = {"forward": "forward filter (%s)" % ("k_forward_mfma" if args.precision == "fp32_mfma3"
+                                                 else "k_forward_fft"),
+             "backward": "backward sampler (k_backward_fast)"}
+    roofs = {}
+    for k in ("forward", "backward"):
+        gbs = algo[k] / (times[k] / 1e3) / 1e9
+        roofs[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(k, args.precision),
+                    "kernel": names[k], "ms_per_launch": round(times[k], 4),
+                    "algorithmic_bytes_per_launch": algo[k]}
+        log("  %s %.3f ms/launch, %.0f GB/s algorithmic" % (names[k], times[k], gbs))
+    dominant = "forward" if fwd_ms >= bwd_ms else "backward"
+    roof = roofs[dominant]
 
     extra = {}
     if not args.no_error:
@@ -228,6 +296,7 @@ def main():
                    "graph": True},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "roofline_other_kernel": roofs["backward" if dominant == "forward" else "forward"],
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
