@@ -41,11 +41,3 @@ def potentials(aux: np.ndarray, hs_kind: int, U: float, dtau: float):
     """Site potentials (W_up, W_dn), each [L_tau, N]: W = exp(c_spin * aux)."""
     c_up, c_dn = log_weight_coeffs(hs_kind, U, dtau)
     return np.exp(c_up * aux), np.exp(c_dn * aux)
-
-
-def log_prior(aux: np.ndarray, hs_kind: int, U: float, dtau: float) -> float:
-    """log P_HS of the whole field up to a constant (the prior factor of eq. joint)."""
-    if hs_kind == HS_GAUSS:
-        a = gauss_coupling(U, dtau)
-        return float(np.sum(-0.5 * aux * aux - 0.5 * a * aux))
-    return 0.0
