@@ -452,7 +452,7 @@ __device__ inline double wave_incl_scan_f64(double v, int lane, double* total) {
 // the lane's weights stay in registers between the scan and the search, filter rows are
 // prefetched ahead (two rows in FP32, one in FP64; 16-byte loads when rows are aligned), g lives
 // in LDS, and lane k computes the Philox uniform of draw s = 64 b + k once per 64 draws.
-template <typename T, bool VEC>
+template <typename T, bool VEC, int LFIX>
 __global__ __launch_bounds__(kThreads) void k_backward_fast(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
@@ -476,13 +476,13 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
     int start, len;
     block_of(c, sweep, t.block, &start, &len);
     if (len < 2) return;
-    const int N = c.N, L = c.L, L_tau = c.L_tau;
+    const int L = LFIX ? LFIX : c.L, N = LFIX ? LFIX * LFIX : c.N, L_tau = c.L_tau;
     const double* g = gsh[wv];
     int32_t* pc = paths + c.path_off;
     int cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np + t.p], N, status, t.chain);
-    const int per = (N + 63) / 64;  // sites per lane (<= E)
+    const int per = LFIX ? (LFIX * LFIX) / 64 : (N + 63) / 64;  // sites per lane (<= E)
     const int i0 = lane * per;
-    const int cnt = max(0, min(per, N - i0));
+    const int cnt = LFIX ? per : max(0, min(per, N - i0));
     const int x0 = cnt > 0 ? i0 % L : 0, y0 = cnt > 0 ? i0 / L : 0;
     const T* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
     // row of draw j is rows + (j - 1) N; draws run j = len-1 .. 1
@@ -532,7 +532,17 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
         const int cx = cur % L, cy = cur / L;
         double w[E];
         double tot = 0.0;
-        {
+        if (LFIX == 32) {
+            // 16 sites per lane, all in row y0: no wraps, no guards
+            const double gy = g[(cy - y0) & 31];
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const double fk = (double)f[k];
+                const double wk = (fk > 0.0 ? fk : 0.0) * (gy * g[(cx - x0 - k) & 31]);
+                w[k] = wk;
+                tot += wk;
+            }
+        } else {
             int x = x0, y = y0;
             int dy = cy - y;
             dy += dy < 0 ? L : 0;
@@ -773,9 +783,16 @@ unsigned grid_for(int64_t n) {
 
 template <typename T, bool VEC>
 void launch_bwd_fast(fh_plan p, int32_t* paths, unsigned blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_backward_fast<T, VEC>), dim3(blocks), dim3(kThreads), 0, s,
-                       p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
-                       (const T*)p->d.filt, paths, p->d.sweep, p->d.status);
+    bool all32 = true;
+    for (const ChainInfo& c : p->chains) all32 = all32 && c.L == 32;
+    if (VEC && all32)
+        hipLaunchKernelGGL((k_backward_fast<T, VEC, 32>), dim3(blocks), dim3(kThreads), 0, s,
+                           p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
+                           (const T*)p->d.filt, paths, p->d.sweep, p->d.status);
+    else
+        hipLaunchKernelGGL((k_backward_fast<T, VEC, 0>), dim3(blocks), dim3(kThreads), 0, s,
+                           p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
+                           (const T*)p->d.filt, paths, p->d.sweep, p->d.status);
 }
 
 }  // namespace

@@ -42,19 +42,35 @@ struct Split3 {
     bf16x8 h[2], m[2], l[2];
 };
 
-// Registers 8q .. 8q+7 of x as x = h + m + l, each term rounded to bf16 (nearest even).
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+
+// (a, b) -> two bf16 (round to nearest even) packed as one dword, a in the low half.
+__device__ inline uint32_t pk_bf16(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+__device__ inline float lo_as_f32(uint32_t p) { return __builtin_bit_cast(float, p << 16); }
+__device__ inline float hi_as_f32(uint32_t p) { return __builtin_bit_cast(float, p & 0xFFFF0000u); }
+
+// Registers 8q .. 8q+7 of x as x = h + m + l, each term rounded to bf16 (nearest even). Works
+// on pairs: one packed convert per term, the f32 value of each half recovered by shift / mask.
 __device__ inline void split3_chunk(const f32x16& x, int q, bf16x8& h, bf16x8& m, bf16x8& l) {
+    u32x4 uh, um, ul;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const float v = x[8 * q + e];
-        const __bf16 bh = (__bf16)v;
-        const float r1 = v - (float)bh;
-        const __bf16 bm = (__bf16)r1;
-        const float r2 = r1 - (float)bm;
-        h[e] = bh;
-        m[e] = bm;
-        l[e] = (__bf16)r2;
+    for (int e = 0; e < 4; ++e) {
+        const float a = x[8 * q + 2 * e], b = x[8 * q + 2 * e + 1];
+        const uint32_t ph = pk_bf16(a, b);
+        const float ra = a - lo_as_f32(ph), rb = b - hi_as_f32(ph);
+        const uint32_t pm = pk_bf16(ra, rb);
+        const float sa = ra - lo_as_f32(pm), sb = rb - hi_as_f32(pm);
+        uh[e] = ph;
+        um[e] = pm;
+        ul[e] = pk_bf16(sa, sb);
     }
+    h = __builtin_bit_cast(bf16x8, uh);
+    m = __builtin_bit_cast(bf16x8, um);
+    l = __builtin_bit_cast(bf16x8, ul);
 }
 
 __device__ inline f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c) {
@@ -205,22 +221,168 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     if (lane == 0) blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log((double)hv);
 }
 
+// Two worldlines of the same (chain, spin, block) per wavefront: the W slice is shared and the
+// two GEMM chains are independent, so one worldline's bf16 splitting, normalisation and stores
+// overlap the other's matrix-core work. Same arithmetic as k_forward_mfma, step for step.
+template <int LFIX>
+__global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
+    const ChainInfo* __restrict__ chains, const PairTask* __restrict__ tasks, int n_tasks,
+    const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, float* __restrict__ filt, double* __restrict__ blk_logz,
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int task = blockIdx.x * kWaves + wv;
+    if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
+    const PairTask t = tasks[task];
+    const ChainInfo& c = chains[t.chain];
+    int start, len;
+    block_of(c, *sweep_ptr, t.block, &start, &len);
+    const int L = LFIX ? LFIX : c.L, N = LFIX ? LFIX * LFIX : c.N, L_tau = c.L_tau;
+    const bool has_b = t.p_b >= 0;
+    const int pp[2] = {t.p_a, has_b ? t.p_b : t.p_a};  // a lone worldline is shadowed, not stored
+    const int spin = t.p_a >= c.n_up ? 1 : 0;
+    const float* Wsp = W + spin * aux_elems + c.aux_off;
+    const double* shift = wshift + spin * total_slices + c.slice_off;
+    const double coef = spin ? c.coef_dn : c.coef_up;
+    const int32_t* pc = paths + c.path_off;
+    int a[2], e[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        a[k] = pc[(int64_t)start * c.np + pp[k]];
+        e[k] = pc[(int64_t)((start + len) % L_tau) * c.np + pp[k]];
+        if (a[k] < 0 || a[k] >= N || e[k] < 0 || e[k] >= N) {
+            if (lane == 0) set_status(status, FH_ERR_BAD_PATH, t.chain);
+            a[k] = (a[k] < 0 || a[k] >= N) ? 0 : a[k];
+            e[k] = (e[k] < 0 || e[k] >= N) ? 0 : e[k];
+        }
+    }
+    Split3 C;
+    {
+        const uint4* cm = (const uint4*)(cmat + (size_t)t.chain * 3 * 2 * 64 * 8);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            C.h[q] = __builtin_bit_cast(bf16x8, cm[(0 * 2 + q) * 64 + lane]);
+            C.m[q] = __builtin_bit_cast(bf16x8, cm[(1 * 2 + q) * 64 + lane]);
+            C.l[q] = __builtin_bit_cast(bf16x8, cm[(2 * 2 + q) * 64 + lane]);
+        }
+    }
+    const int x = lane & 31;
+    const bool xin = LFIX ? true : x < L;
+    f32x16 F0, F1;
+    {
+        const int ax0 = a[0] % L, ay0 = a[0] / L, ax1 = a[1] % L, ay1 = a[1] / L;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int y = tile_row(lane, v);
+            F0[v] = (x == ax0 && y == ay0) ? 1.0f : 0.0f;
+            F1[v] = (x == ax1 && y == ay1) ? 1.0f : 0.0f;
+        }
+    }
+    double la0 = coef * (double)aux[c.aux_off + (int64_t)start * N + a[0]];
+    double la1 = coef * (double)aux[c.aux_off + (int64_t)start * N + a[1]];
+    double prod0 = 1.0, prod1 = 1.0;
+    const int64_t rowoff = (int64_t)t.block * (c.B - 1);
+    float* rows0 = filt + c.filt_off + ((int64_t)pp[0] * L_tau + rowoff) * N;
+    float* rows1 = filt + c.filt_off + ((int64_t)pp[1] * L_tau + rowoff) * N;
+    for (int j = 1; j < len; ++j) {
+        const int l = (start + j) % L_tau;
+        const float* Wl = Wsp + (int64_t)l * N;
+        float w[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int y = tile_row(lane, v);
+            const bool in = LFIX ? true : (xin && y < L);
+            const float wv = Wl[in ? y * L + x : 0];  // always an in-bounds address
+            w[v] = in ? wv : 0.0f;
+        }
+        const f32x16 X0 = circ_step(F0, C);
+        const f32x16 X1 = circ_step(F1, C);
+        const f32x16 H0 = circ_step(X0, C);
+        const f32x16 H1 = circ_step(X1, C);
+        float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            F0[v] = H0[v] * w[v];
+            F1[v] = H1[v] * w[v];
+            s0 += F0[v];
+            s1 += F1[v];
+        }
+        const float tot0 = wave_sum_f32(s0), tot1 = wave_sum_f32(s1);
+        if (!(tot0 > 0.0f) || !isfinite(tot0) || !(tot1 > 0.0f) || !isfinite(tot1))
+            if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
+        // f~_j = h_j * inv: the normaliser applied is exactly 1/inv (see k_forward_mfma)
+        const float inv0 = __builtin_amdgcn_rcpf(tot0), inv1 = __builtin_amdgcn_rcpf(tot1);
+        prod0 *= (double)inv0;
+        prod1 *= (double)inv1;
+        if (!(prod0 > 1e-200 && prod0 < 1e200)) {
+            la0 -= log(prod0);
+            prod0 = 1.0;
+        }
+        if (!(prod1 > 1e-200 && prod1 < 1e200)) {
+            la1 -= log(prod1);
+            prod1 = 1.0;
+        }
+        const double m = shift[l];
+        la0 += m;
+        la1 += m;
+        float* row0 = rows0 + (int64_t)(j - 1) * N;
+        float* row1 = rows1 + (int64_t)(j - 1) * N;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            F0[v] *= inv0;
+            F1[v] *= inv1;
+            const int y = tile_row(lane, v);
+            if (LFIX || (xin && y < L)) {
+                __builtin_nontemporal_store(F0[v], &row0[y * L + x]);
+                if (has_b) __builtin_nontemporal_store(F1[v], &row1[y * L + x]);
+            }
+        }
+    }
+    // end weights (C f~ C)(e)
+    const f32x16 X0 = circ_step(F0, C);
+    const f32x16 X1 = circ_step(F1, C);
+    const f32x16 H0 = circ_step(X0, C);
+    const f32x16 H1 = circ_step(X1, C);
+    float hv0 = 0.0f, hv1 = 0.0f;
+    {
+        const int ex0 = e[0] % L, ey0 = e[0] / L, ex1 = e[1] % L, ey1 = e[1] / L;
+        const int ve0 = (ey0 >> 3) * 4 + (ey0 & 3), ve1 = (ey1 >> 3) * 4 + (ey1 & 3);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            if (v == ve0) hv0 = H0[v];
+            if (v == ve1) hv1 = H1[v];
+        }
+        hv0 = __shfl(hv0, ex0 + 32 * ((ey0 >> 2) & 1), 64);
+        hv1 = __shfl(hv1, ex1 + 32 * ((ey1 >> 2) & 1), 64);
+    }
+    la0 -= log(prod0);
+    la1 -= log(prod1);
+    if (lane == 0) {
+        blk_logz[c.blk_off + (int64_t)pp[0] * c.nb + t.block] = la0 + log((double)hv0);
+        if (has_b) blk_logz[c.blk_off + (int64_t)pp[1] * c.nb + t.block] = la1 + log((double)hv1);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
-    const unsigned blocks = (unsigned)((p->n_draw_tasks + kWaves - 1) / kWaves);
     bool all32 = true;
     for (const ChainInfo& c : p->chains) all32 = all32 && c.L == 32;
-    if (all32)
-        hipLaunchKernelGGL(k_forward_mfma<32>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           p->d.draw_tasks, p->n_draw_tasks, p->d.cmat, (const float*)aux,
+    if (all32) {
+        // pairs of worldlines per wavefront
+        const unsigned blocks = (unsigned)((p->n_fwd_tasks + kWaves - 1) / kWaves);
+        hipLaunchKernelGGL(k_forward_mfma2<32>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.fwd_tasks, p->n_fwd_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
-    else
+    } else {
+        const unsigned blocks = (unsigned)((p->n_draw_tasks + kWaves - 1) / kWaves);
         hipLaunchKernelGGL(k_forward_mfma<0>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.draw_tasks, p->n_draw_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
+    }
     return hipGetLastError();
 }
 
