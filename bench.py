@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--no-error", action="store_true", help="skip the error-vs-oracle sample")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--workload", default="32x32",
+                    choices=["32x32", "uneven", "hirsch16", "grad", "small"],
+                    help="32x32: the headline workload; the others time the remaining "
+                         "configurations (uneven batch, 16x16 Ising field, adjoint, 4x4 FP64)")
     return ap.parse_args()
 
 
@@ -182,12 +186,94 @@ def cpu_baseline(desc, aux, paths, n_sweeps=6):
                       % (n_sweeps, dt)}
 
 
+def other_workload(args):
+    """Secondary workloads: one JSON line each, same timing rules as the headline run."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2510_13866_amd import fhmc
+    from paper_2510_13866_amd.sampler import Sampler
+
+    prec_name = args.precision
+    if args.workload == "uneven":
+        descs = synth.config_uneven(256)
+        label = "FFBS sweep, 256 uneven chains (L in {8,12,16,24,32}, L_tau in {40,80,160}, " \
+                "dtau=0.05, U~U[2,6], half filling, Gaussian/Ising 50/50)"
+    elif args.workload == "hirsch16":
+        descs = synth.config_16x16_hirsch(64)
+        label = "FFBS sweep, 64 chains x 16x16 lattice, L_tau=64, dtau=0.0625, U=4, 128+128 " \
+                "worldlines, Ising field"
+    elif args.workload == "small":
+        descs = synth.config_small_fp64()
+        prec_name = "fp64"
+        label = "FFBS sweep, 1 chain x 4x4 lattice, L_tau=16, dtau=0.1, U=4, 8+8 worldlines, " \
+                "Gaussian field"
+    else:
+        descs = synth.config_gradient(8)
+        label = "log Z_path and its gradient (field and t), 8 chains x 32x32, L_tau=128, " \
+                "dtau=0.05, U=4, 512+512 worldlines, Gaussian field"
+    prec = PRECISIONS[prec_name]
+    aux = [synth.initial_aux(d) for d in descs]
+    paths = [synth.initial_paths(d) for d in descs]
+    stream = torch.cuda.Stream()
+    sites = sum(d.N * d.L_tau for d in descs)
+    log("bench: %s workload, %s, %d chains" % (args.workload, prec_name, len(descs)))
+    S = Sampler(descs, prec, fhmc.FH_FLAG_GRAPH)
+    A0, P0 = S.pack_aux(aux), S.pack_paths(paths)
+    A, P = A0.clone(), P0.clone()
+    torch.cuda.synchronize()
+    extra = {}
+    if args.workload == "grad":
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            logZ = torch.empty(len(descs), dtype=torch.float64, device="cuda")
+            gA = torch.empty_like(A)
+            gT = torch.empty(len(descs), dtype=torch.float64, device="cuda")
+            for _ in range(args.warmup):
+                fhmc.fh_logZ_grad(S.plan, A, P, 0, logZ, gA, gT, stream)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for i in range(args.steps):
+                fhmc.fh_logZ_grad(S.plan, A, P, i % descs[0].L_tau, logZ, gA, gT, stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        metric = "gradient evaluations/s (log Z_path, d/d field, d/d t) at 32x32 L_tau=128, 8 chains"
+        value = args.steps / (ms / 1e3)
+        unit = "evaluations/s"
+        extra["site_slices_per_s"] = sites * args.steps / (ms / 1e3)
+    else:
+        time_sweeps(S, A, P, A0, P0, 0, args.warmup, stream)
+        ms = time_sweeps(S, A, P, A0, P0, args.warmup, args.steps, stream)
+        metric = "site-slice updates/s (%s)" % args.workload
+        value = sites * args.steps / (ms / 1e3)
+        unit = "site-slice updates/s"
+    code, _ = S.status()
+    if code != 0:
+        raise RuntimeError("device status: " + fhmc.fh_strerror(code))
+    S.close()
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if prec_name == "fp64" else "f32", "data": "synthetic",
+           "config": {"workload": label, "chains": len(descs), "precision": prec_name,
+                      "site_slices_per_step": sites, "graph": True}}
+    out.update(extra)
+    log("  %.3f ms/step, %.4g %s" % (ms / args.steps, value, unit))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(chains are independent; see the sharding notes). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "32x32":
+        other_workload(args)
+        return
     import numpy as np
     import torch
 

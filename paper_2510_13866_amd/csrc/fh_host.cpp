@@ -132,7 +132,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.grad_tasks, d.draw_tasks, d.status, d.sweep};
+                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     d = fh::Device();
@@ -214,6 +214,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         ci.nb = (d.L_tau + ci.B - 1) / ci.B;
         default_radix_plan(d.L, &ci.plan);
         ci.gauss_a = sqrt(fabs(d.U) * d.dtau);
+        ci.dtau = d.dtau;
         ci.hirsch_lambda = d.hs_kind == FH_HS_HIRSCH ? acosh(exp(d.dtau * d.U / 2.0)) : 0.0;
         ci.coef_up = d.hs_kind == FH_HS_GAUSS ? ci.gauss_a : ci.hirsch_lambda;
         ci.coef_dn = d.hs_kind == FH_HS_GAUSS ? ci.gauss_a : -ci.hirsch_lambda;
@@ -259,6 +260,20 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     });
     std::vector<PairTask> fwd, grad;
     std::vector<DrawTask> draw;
+    std::vector<GroupTask> groups;
+    int64_t gpart = 0;
+    for (int c = 0; c < n_chains; ++c) {  // gradient groups in chain order (reduced per chain)
+        ChainInfo& ci = p->chains[c];
+        ci.g0 = (int32_t)groups.size();
+        for (int spin = 0; spin < 2; ++spin) {
+            int p0 = spin ? ci.n_up : 0, p1 = spin ? ci.np : ci.n_up;
+            for (int q = p0; q < p1; q += kGroup) {
+                groups.push_back({c, q, std::min(kGroup, p1 - q), spin, gpart});
+                gpart += (int64_t)ci.L_tau * ci.N;
+            }
+        }
+        ci.g1 = (int32_t)groups.size();
+    }
     for (int c : order) {
         const ChainInfo& ci = p->chains[c];
         for (int spin = 0; spin < 2; ++spin) {
@@ -275,6 +290,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->n_fwd_tasks = (int32_t)fwd.size();
     p->n_grad_tasks = (int32_t)grad.size();
     p->n_draw_tasks = (int32_t)draw.size();
+    p->n_groups = (int32_t)groups.size();
+    p->gpart_elems = precision == FH_FP32_MFMA3 ? gpart : 0;
 
     hipError_t e = hipSuccess;
     fh::Device& dv = p->d;
@@ -290,6 +307,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.fwd_tasks, sizeof(PairTask) * fwd.size());
     if (e == hipSuccess) e = dalloc(&dv.grad_tasks, sizeof(PairTask) * grad.size());
     if (e == hipSuccess) e = dalloc(&dv.draw_tasks, sizeof(DrawTask) * draw.size());
+    if (e == hipSuccess) e = dalloc(&dv.group_tasks, sizeof(GroupTask) * groups.size());
+    if (e == hipSuccess) e = dalloc(&dv.gpart, sizeof(float) * (size_t)p->gpart_elems);
     if (e == hipSuccess) e = dalloc(&dv.status, sizeof(int32_t) * 2);
     if (e == hipSuccess) e = dalloc(&dv.sweep, sizeof(uint64_t));
     if (e == hipSuccess) e = hipMemcpy(dv.chains, p->chains.data(), sizeof(ChainInfo) * n_chains, hipMemcpyHostToDevice);
@@ -298,6 +317,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = hipMemcpy(dv.fwd_tasks, fwd.data(), sizeof(PairTask) * fwd.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.grad_tasks, grad.data(), sizeof(PairTask) * grad.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.draw_tasks, draw.data(), sizeof(DrawTask) * draw.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dv.group_tasks, groups.data(), sizeof(GroupTask) * groups.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
         int32_t st[2] = {0, -1};
         e = hipMemcpy(dv.status, st, sizeof(st), hipMemcpyHostToDevice);
@@ -455,8 +475,12 @@ int fh_logZ_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t ancho
         if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     FH_TRY(launch_potentials(p, aux, s));
-    if (grad_aux) FH_TRY(launch_zero(grad_aux, (int64_t)p->real_size * p->aux_elems, s));
-    FH_TRY(launch_grad(p, aux, paths, anchor_slice, grad_aux, s));
+    if (p->precision == FH_FP32_MFMA3) {
+        FH_TRY(launch_grad_mfma(p, aux, paths, anchor_slice, grad_aux, s));
+    } else {
+        if (grad_aux) FH_TRY(launch_zero(grad_aux, (int64_t)p->real_size * p->aux_elems, s));
+        FH_TRY(launch_grad(p, aux, paths, anchor_slice, grad_aux, s));
+    }
     FH_TRY(launch_grad_reduce(p, logZ, grad_t, s));
     p->have_filters = true;
     p->filters_are_ring = true;

@@ -19,7 +19,7 @@ struct ChainInfo {
     int32_t L, N, L_tau, n_up, n_dn, np, hs_kind, B, nb;
     RadixPlan plan;           // FFT radix plan of one dimension (both dimensions are L)
     double coef_up, coef_dn;  // log W_spin = coef_spin * aux
-    double gauss_a, hirsch_lambda;
+    double gauss_a, hirsch_lambda, dtau;
     uint64_t seed;
     int64_t aux_off;   // packed aux / W offset (elements): aux[aux_off + l*N + r]
     int64_t path_off;  // packed paths offset: paths[path_off + l*np + p]
@@ -28,6 +28,7 @@ struct ChainInfo {
     int64_t filt_off;  // filter workspace: filt[filt_off + (p*L_tau + row)*N + r]
     int64_t blk_off;   // per-(particle, block) log Z: blk[blk_off + p*nb + block]
     int64_t slice_off; // index of this chain's slice 0 among all chains' slices
+    int32_t g0, g1;    // gradient worldline groups of this chain: [g0, g1)
 };
 
 // Offsets of the tables of one chain inside the double table buffer, relative to tab_off.
@@ -52,6 +53,13 @@ struct PairTask {
 struct DrawTask {
     int32_t chain, p, block, pad;
 };
+// Up to kGroup worldlines of one (chain, spin) processed by one workgroup in the MFMA adjoint;
+// part_off locates the group's partial field-gradient slab [L_tau][N].
+constexpr int kGroup = 4;
+struct GroupTask {
+    int32_t chain, p0, count, spin;
+    int64_t part_off;
+};
 
 struct Device {
     ChainInfo* chains = nullptr;
@@ -65,6 +73,8 @@ struct Device {
     PairTask* fwd_tasks = nullptr;
     PairTask* grad_tasks = nullptr;
     DrawTask* draw_tasks = nullptr;
+    GroupTask* group_tasks = nullptr;
+    float* gpart = nullptr;   // MFMA adjoint: per-group partial field gradients
     int32_t* status = nullptr;   // [0] first error code, [1] its chain
     uint64_t* sweep = nullptr;   // sweep index read by the kernels
 };
@@ -82,6 +92,8 @@ struct fh_plan_s {
     int64_t aux_elems = 0, path_elems = 0, particles = 0, blk_elems = 0, filt_elems = 0;
     int32_t n_fwd_tasks = 0, n_grad_tasks = 0, n_draw_tasks = 0;
     int64_t total_slices = 0;
+    int32_t n_groups = 0;
+    int64_t gpart_elems = 0;
     int32_t max_N = 0, max_L = 0, max_np = 0;
     size_t real_size = 8;
     fh::Device d;
@@ -112,6 +124,8 @@ hipError_t launch_gibbs(fh_plan p, const int32_t* paths, void* aux, hipStream_t 
 hipError_t launch_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
                        void* grad_aux, hipStream_t s);
 hipError_t launch_grad_reduce(fh_plan p, double* logZ, double* grad_t, hipStream_t s);
+hipError_t launch_grad_mfma(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
+                            void* grad_aux, hipStream_t s);
 hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t s);
 
 size_t forward_lds_bytes(fh_plan p);

@@ -364,6 +364,216 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     }
 }
 
+// Adjoint of the forward filter over the ring anchored at `anchor` (one block of length L_tau),
+// on the matrix cores. A workgroup takes up to kGroup worldlines of one (chain, spin), one per
+// wavefront, in lockstep over the slices:
+//   forward:  f~_j as in k_forward_mfma, every row j = 0..L_tau-1 stored (row 0 = delta_a)
+//   backward: u_{L_tau} = delta_a; beta_j = C u_{j+1} C; u_j = W~_j . beta_j / sum
+//   d log Z / d log W_j(r) = f~_j(r) beta_j(r) / <f~_j, beta_j>   (the smoothing marginal)
+//   d log Z / d t += dtau <A beta_j, f~_j> / <beta_j, f~_j>, A the nearest-neighbour hopping
+//                    matrix: G = exp(t dtau A), so dG/dt = dtau A G and <u, (dG/dt) f> =
+//                    dtau <A G u, f>; A beta is a four-neighbour stencil read from LDS.
+// The marginals of the group are summed in LDS and written (times the spin's coefficient) to
+// the group's partial slab; k_gpart_reduce adds the slabs of a chain in a fixed order, so the
+// field gradient is the same on every call.
+template <int LFIX>
+__global__ __launch_bounds__(kThreads) void k_grad_mfma(
+    const ChainInfo* __restrict__ chains, const GroupTask* __restrict__ groups,
+    const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, float* __restrict__ filt, float* __restrict__ gpart,
+    double* __restrict__ blk_logz, double* __restrict__ dt_out, int anchor, int32_t* status) {
+    __shared__ float bt[kWaves][1024];   // beta tile of each wavefront, y * 32 + x
+    __shared__ float mg[kWaves][1024];   // marginal tile of each wavefront
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const GroupTask g = groups[blockIdx.x];
+    const ChainInfo& c = chains[g.chain];
+    const int L = LFIX ? LFIX : c.L, N = LFIX ? LFIX * LFIX : c.N, L_tau = c.L_tau;
+    const bool real = wv < g.count;            // extra wavefronts shadow worldline p0
+    const int p = g.p0 + (real ? wv : 0);
+    const float* Wsp = W + g.spin * aux_elems + c.aux_off;
+    const double* shift = wshift + g.spin * total_slices + c.slice_off;
+    const double coef = g.spin ? c.coef_dn : c.coef_up;
+    const double dtau = c.dtau;
+    int a = paths[c.path_off + (int64_t)anchor * c.np + p];
+    if (a < 0 || a >= N) {
+        if (lane == 0 && real) set_status(status, FH_ERR_BAD_PATH, g.chain);
+        a = 0;
+    }
+    Split3 C;
+    {
+        const uint4* cm = (const uint4*)(cmat + (size_t)g.chain * 3 * 2 * 64 * 8);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            C.h[q] = __builtin_bit_cast(bf16x8, cm[(0 * 2 + q) * 64 + lane]);
+            C.m[q] = __builtin_bit_cast(bf16x8, cm[(1 * 2 + q) * 64 + lane]);
+            C.l[q] = __builtin_bit_cast(bf16x8, cm[(2 * 2 + q) * 64 + lane]);
+        }
+    }
+    const int x = lane & 31;
+    const bool xin = LFIX ? true : x < L;
+    const int ax = a % L, ay = a / L;
+    float* rows = filt + c.filt_off + (int64_t)p * L_tau * N;
+    // ---- forward pass over the ring, every row stored
+    f32x16 F;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int y = tile_row(lane, v);
+        F[v] = (x == ax && y == ay) ? 1.0f : 0.0f;
+        if (real && (LFIX || (xin && y < L))) rows[y * L + x] = F[v];
+    }
+    double la = coef * (double)aux[c.aux_off + (int64_t)anchor * N + a];
+    double prod = 1.0;
+    for (int j = 1; j < L_tau; ++j) {
+        const int l = (anchor + j) % L_tau;
+        const float* Wl = Wsp + (int64_t)l * N;
+        float w[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int y = tile_row(lane, v);
+            const bool in = LFIX ? true : (xin && y < L);
+            const float wv0 = Wl[in ? y * L + x : 0];
+            w[v] = in ? wv0 : 0.0f;
+        }
+        const f32x16 X = circ_step(F, C);
+        const f32x16 H = circ_step(X, C);
+        float s = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            F[v] = H[v] * w[v];
+            s += F[v];
+        }
+        const float tot = wave_sum_f32(s);
+        if ((!(tot > 0.0f) || !isfinite(tot)) && real && lane == 0)
+            set_status(status, FH_ERR_NONFINITE, g.chain);
+        const float inv = __builtin_amdgcn_rcpf(tot);
+        prod *= (double)inv;
+        if (!(prod > 1e-200 && prod < 1e200)) {
+            la -= log(prod);
+            prod = 1.0;
+        }
+        la += shift[l];
+        float* row = rows + (int64_t)j * N;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            F[v] *= inv;
+            const int y = tile_row(lane, v);
+            if (real && (LFIX || (xin && y < L))) row[y * L + x] = F[v];
+        }
+    }
+    {
+        const f32x16 X = circ_step(F, C);
+        const f32x16 H = circ_step(X, C);
+        float hv = 0.0f;
+        const int ve = (ay >> 3) * 4 + (ay & 3);
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+            if (v == ve) hv = H[v];
+        hv = __shfl(hv, ax + 32 * ((ay >> 2) & 1), 64);
+        la -= log(prod);
+        if (real && lane == 0) blk_logz[c.blk_off + (int64_t)p * c.nb] = la + log((double)hv);
+    }
+    __syncthreads();  // every row of the group is stored before any wavefront reads one back
+    // ---- backward messages
+    f32x16 U;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) U[v] = (x == ax && tile_row(lane, v) == ay) ? 1.0f : 0.0f;
+    double dt = 0.0;
+    float* slab = gpart + g.part_off;
+    for (int j = L_tau - 1; j >= 0; --j) {
+        const int l = (anchor + j) % L_tau;
+        const f32x16 X = circ_step(U, C);
+        const f32x16 B = circ_step(X, C);   // beta_j = C u_{j+1} C
+        const float* row = rows + (int64_t)j * N;
+        float fj[16];
+        float den = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int y = tile_row(lane, v);
+            const bool in = LFIX ? true : (xin && y < L);
+            const float fv = row[in ? y * L + x : 0];
+            fj[v] = in ? fv : 0.0f;
+            den += fj[v] * B[v];
+            bt[wv][y * 32 + x] = in ? B[v] : 0.0f;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float num = 0.0f;
+        const int xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int y = tile_row(lane, v);
+            const bool in = LFIX ? true : (xin && y < L);
+            const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+            const float nbr = in ? bt[wv][y * 32 + xp] + bt[wv][y * 32 + xm] + bt[wv][yp * 32 + x] +
+                                       bt[wv][ym * 32 + x]
+                                 : 0.0f;
+            num += fj[v] * nbr;
+        }
+        const double dden = (double)wave_sum_f32(den);
+        const double dnum = (double)wave_sum_f32(num);
+        dt += dtau * dnum / dden;
+        const float k = real ? (float)(coef / dden) : 0.0f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) mg[wv][tile_row(lane, v) * 32 + x] = k * fj[v] * B[v];
+        __syncthreads();
+        {
+            float* srow = slab + (int64_t)l * N;
+            for (int i = threadIdx.x; i < 1024; i += kThreads) {
+                const int yy = i >> 5, xx = i & 31;
+                if (LFIX || (xx < L && yy < L))
+                    srow[yy * L + xx] = (mg[0][i] + mg[1][i]) + (mg[2][i] + mg[3][i]);
+            }
+        }
+        __syncthreads();
+        if (j > 0) {
+            const float* Wl = Wsp + (int64_t)l * N;
+            float s = 0.0f;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int y = tile_row(lane, v);
+                const bool in = LFIX ? true : (xin && y < L);
+                const float wv0 = Wl[in ? y * L + x : 0];
+                U[v] = in ? wv0 * B[v] : 0.0f;
+                s += U[v];
+            }
+            const float tot = wave_sum_f32(s);
+            if ((!(tot > 0.0f) || !isfinite(tot)) && real && lane == 0)
+                set_status(status, FH_ERR_NONFINITE, g.chain);
+            const float inv = __builtin_amdgcn_rcpf(tot);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) U[v] *= inv;
+        }
+    }
+    if (real && lane == 0) dt_out[c.part_off + p] = dt;
+}
+
+// grad_aux[chain][l][r] = sum over the chain's groups, in group order, of the partial slabs.
+__global__ __launch_bounds__(kThreads) void k_gpart_reduce(const ChainInfo* __restrict__ chains,
+                                                           int n_chains,
+                                                           const GroupTask* __restrict__ groups,
+                                                           const float* __restrict__ gpart,
+                                                           float* __restrict__ grad,
+                                                           int64_t aux_elems) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < aux_elems;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n_chains - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (chains[mid].aux_off <= e)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const ChainInfo& c = chains[lo];
+        const int64_t off = e - c.aux_off;
+        float s = 0.0f;
+        for (int q = c.g0; q < c.g1; ++q) s += gpart[groups[q].part_off + off];
+        grad[e] = s;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
@@ -383,6 +593,29 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_mfma(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
+                            void* grad_aux, hipStream_t s) {
+    bool all32 = true;
+    for (const ChainInfo& c : p->chains) all32 = all32 && c.L == 32;
+    if (all32)
+        hipLaunchKernelGGL(k_grad_mfma<32>, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.group_tasks, p->d.cmat, (const float*)aux, (const float*)p->d.W,
+                           p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt,
+                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.status);
+    else
+        hipLaunchKernelGGL(k_grad_mfma<0>, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.group_tasks, p->d.cmat, (const float*)aux, (const float*)p->d.W,
+                           p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt,
+                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !grad_aux) return e;
+    int64_t b = (p->aux_elems + kThreads - 1) / kThreads;
+    if (b > 65536) b = 65536;
+    hipLaunchKernelGGL(k_gpart_reduce, dim3((unsigned)b), dim3(kThreads), 0, s, p->d.chains,
+                       p->n_chains, p->d.group_tasks, p->d.gpart, (float*)grad_aux, p->aux_elems);
     return hipGetLastError();
 }
 

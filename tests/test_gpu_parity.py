@@ -295,10 +295,10 @@ def test_full_size_sampled_parity(lib, prec):
     S.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mfma3"])
 def test_logz_grad_parity(lib, prec):
     fhmc, sampler = lib
-    precision = fhmc.FH_FP64 if prec == "fp64" else fhmc.FH_FP32
+    precision = PRECS[prec]
     descs = [synth.config_small_fp64()[0],
              synth.ChainDesc(L=6, L_tau=8, n_up=5, n_dn=4, hs_kind=synth.HS_HIRSCH, block_len=0,
                              t=1.0, U=4.0, dtau=0.1, seed=2),
@@ -388,3 +388,56 @@ def test_extreme_field_values_stay_finite(lib):
         assert np.all(np.isfinite(lz)), (prec, lz)
         assert np.allclose(lz, ref, rtol=tol), (prec, lz, ref)
         S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mfma3"])
+def test_uneven_batch_sampled_parity(lib, prec):
+    """Chains of the uneven batch (L in {8, 12, 16, 24, 32}, L_tau in {40, 80, 160}, mixed
+    fields) in one plan: log Z of every worldline of sampled chains and filters of sampled
+    worldlines against the oracle."""
+    fhmc, sampler = lib
+    descs = synth.config_uneven(256)
+    pick = []
+    for L in (8, 12, 16, 24, 32):
+        pick.append(next(i for i, d in enumerate(descs) if d.L == L))
+    descs = [descs[i] for i in pick] + descs[:11]
+    say("uneven batch parity", prec, [(d.L, d.L_tau, d.hs_kind) for d in descs[:5]])
+    S = sampler.Sampler(descs, PRECS[prec])
+    aux = [synth.initial_aux(d) for d in descs]
+    paths = [synth.random_walk_paths(d, 40 + i) for i, d in enumerate(descs)]
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    logZ = S.unpack_particles(S.forward_filter(A, P, 3))
+    assert S.status() == (0, -1)
+    for c in range(5):
+        d = descs[c]
+        sample = [0, d.n_up - 1, d.n_up, d.n_particles - 1]
+        ref_lz, ref_rows, tail = oracle_forward(d, aux[c], paths[c], 3, sample, with_tail=True)
+        err = np.abs(logZ[c][sample] - ref_lz)
+        assert np.all(err <= logz_tol(prec, ref_lz, tail)), (c, err)
+        for k, p in enumerate(sample):
+            assert rel_row_err(S.filters(c, p), ref_rows[k]) <= FILTER_TOL[prec], (c, p)
+    S.close()
+
+
+def test_logz_grad_mfma_full_lattice_repeatable(lib):
+    """32x32, L_tau=128 (the gradient workload's shape) on the MFMA adjoint: field and t
+    gradients against the oracle within 1e-4, and bit-identical on a second call (the field
+    gradient is reduced in a fixed order)."""
+    fhmc, sampler = lib
+    d = synth.ChainDesc(L=32, L_tau=128, n_up=7, n_dn=6, hs_kind=synth.HS_GAUSS, block_len=0,
+                        t=1.0, U=4.0, dtau=0.05, seed=8)
+    S = sampler.Sampler([d, dataclasses.replace(d, seed=9)], fhmc.FH_FP32_MFMA3)
+    aux = [synth.initial_aux(d), synth.initial_aux(d, rng_seed=77)]
+    paths = [synth.random_walk_paths(d, 5), synth.random_walk_paths(d, 6)]
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    lz1, g1, t1 = S.logz_grad(A, P, 17)
+    lz2, g2, t2 = S.logz_grad(A, P, 17)
+    assert S.status() == (0, -1)
+    assert torch.equal(g1, g2) and torch.equal(t1, t2) and torch.equal(lz1, lz2)
+    gA = S.unpack_aux(g1)
+    for c in range(2):
+        lz, g, gt, _ = ograd.logz_path_grad(d, aux[c], paths[c], 17)
+        assert lz1[c].item() == pytest.approx(lz, rel=2e-6)
+        assert np.linalg.norm(gA[c] - g) <= 1e-4 * np.linalg.norm(g)
+        assert t1[c].item() == pytest.approx(gt, rel=1e-4)
+    S.close()
