@@ -74,6 +74,8 @@ struct Device {
     PairTask* grad_tasks = nullptr;
     DrawTask* draw_tasks = nullptr;
     GroupTask* group_tasks = nullptr;
+    PairTask* fwd32_tasks = nullptr;    // MFMA forward: worldline pairs of L = 32 chains
+    DrawTask* fwdx_tasks = nullptr;     // MFMA forward: single worldlines of the other chains
     float* gpart = nullptr;   // MFMA adjoint: per-group partial field gradients
     int32_t* status = nullptr;   // [0] first error code, [1] its chain
     uint64_t* sweep = nullptr;   // sweep index read by the kernels
@@ -93,6 +95,7 @@ struct fh_plan_s {
     int32_t n_fwd_tasks = 0, n_grad_tasks = 0, n_draw_tasks = 0;
     int64_t total_slices = 0;
     int32_t n_groups = 0;
+    int32_t n_fwd32_tasks = 0, n_fwdx_tasks = 0;
     int64_t gpart_elems = 0;
     int32_t max_N = 0, max_L = 0, max_np = 0;
     size_t real_size = 8;

@@ -448,36 +448,20 @@ __device__ inline double wave_incl_scan_f64(double v, int lane, double* total) {
     return v + base;
 }
 
-// Backward sampling for N <= 1024 (at most 16 sites per lane), same draw rule as k_backward:
-// the lane's weights stay in registers between the scan and the search, filter rows are
-// prefetched ahead (two rows in FP32, one in FP64; 16-byte loads when rows are aligned), g lives
-// in LDS, and lane k computes the Philox uniform of draw s = 64 b + k once per 64 draws.
-template <typename T, bool VEC, int LFIX>
-__global__ __launch_bounds__(kThreads) void k_backward_fast(
-    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
-    const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
-    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
-    constexpr int E = 16;
+// Backward sampling for N <= 1024, same draw rule as k_backward: the lane's weights stay in
+// registers between the scan and the search, filter rows are prefetched ahead (two rows in FP32,
+// one in FP64; 16-byte loads for 32 x 32 lattices), g lives in LDS, and lane k computes the
+// Philox uniform of draw s = 64 b + k once per 64 draws. E = sites per lane this body handles;
+// LFIX = 32 is the branch-free full-tile case.
+template <typename T, bool VEC, int LFIX, int E>
+__device__ void backward_task(const DrawTask& t, const ChainInfo& c, const double* g,
+                              const T* __restrict__ filt, int32_t* __restrict__ paths,
+                              uint64_t sweep, int32_t* status, int lane) {
     constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;  // rows in flight ahead of the current one
-    __shared__ double gsh[kWaves][kMaxL];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int task = blockIdx.x * kWaves + wv;
-    const bool active = task < n_tasks;
-    DrawTask t = {0, 0, 0, 0};
-    if (active) {
-        t = tasks[task];
-        const ChainInfo& c0 = chains[t.chain];
-        for (int m = lane; m < c0.L; m += 64) gsh[wv][m] = tables[tab_g(c0) + m];
-    }
-    __syncthreads();  // the only barrier; every wave reaches it
-    if (!active) return;
-    const ChainInfo& c = chains[t.chain];
-    const uint64_t sweep = *sweep_ptr;
     int start, len;
     block_of(c, sweep, t.block, &start, &len);
     if (len < 2) return;
     const int L = LFIX ? LFIX : c.L, N = LFIX ? LFIX * LFIX : c.N, L_tau = c.L_tau;
-    const double* g = gsh[wv];
     int32_t* pc = paths + c.path_off;
     int cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np + t.p], N, status, t.chain);
     const int per = LFIX ? (LFIX * LFIX) / 64 : (N + 63) / 64;  // sites per lane (<= E)
@@ -492,8 +476,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
             typedef T vec4 __attribute__((ext_vector_type(4)));
 #pragma unroll
             for (int q = 0; q < E / 4; ++q) {
-                vec4 v4 = {T(0), T(0), T(0), T(0)};
-                if (4 * q < cnt) v4 = *(const vec4*)(r + 4 * q);
+                const vec4 v4 = *(const vec4*)(r + 4 * q);
                 dst[4 * q] = v4[0];
                 dst[4 * q + 1] = v4[1];
                 dst[4 * q + 2] = v4[2];
@@ -597,6 +580,35 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
         if (lane == 0) pc[(int64_t)((start + j) % L_tau) * c.np + t.p] = chosen;
         cur = chosen;
     }
+}
+
+// One wavefront per (chain, worldline, block), the body chosen per chain: full 32 x 32 tiles,
+// up to 4 sites per lane (N <= 256), or up to 16 (N <= 1024).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_backward_fast(
+    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
+    const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    __shared__ double gsh[kWaves][kMaxL];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int task = blockIdx.x * kWaves + wv;
+    const bool active = task < n_tasks;
+    DrawTask t = {0, 0, 0, 0};
+    if (active) {
+        t = tasks[task];
+        const ChainInfo& c0 = chains[t.chain];
+        for (int m = lane; m < c0.L; m += 64) gsh[wv][m] = tables[tab_g(c0) + m];
+    }
+    __syncthreads();  // the only barrier; every wave reaches it
+    if (!active) return;
+    const ChainInfo& c = chains[t.chain];
+    const uint64_t sweep = *sweep_ptr;
+    if (c.L == 32)
+        backward_task<T, true, 32, 16>(t, c, gsh[wv], filt, paths, sweep, status, lane);
+    else if (c.N <= 256)
+        backward_task<T, false, 0, 4>(t, c, gsh[wv], filt, paths, sweep, status, lane);
+    else
+        backward_task<T, false, 0, 16>(t, c, gsh[wv], filt, paths, sweep, status, lane);
 }
 
 // Occupation counts of one slice (LDS histogram) and the exact field draw of every site:
@@ -781,20 +793,6 @@ unsigned grid_for(int64_t n) {
     return (unsigned)b;
 }
 
-template <typename T, bool VEC>
-void launch_bwd_fast(fh_plan p, int32_t* paths, unsigned blocks, hipStream_t s) {
-    bool all32 = true;
-    for (const ChainInfo& c : p->chains) all32 = all32 && c.L == 32;
-    if (VEC && all32)
-        hipLaunchKernelGGL((k_backward_fast<T, VEC, 32>), dim3(blocks), dim3(kThreads), 0, s,
-                           p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
-                           (const T*)p->d.filt, paths, p->d.sweep, p->d.status);
-    else
-        hipLaunchKernelGGL((k_backward_fast<T, VEC, 0>), dim3(blocks), dim3(kThreads), 0, s,
-                           p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
-                           (const T*)p->d.filt, paths, p->d.sweep, p->d.status);
-}
-
 }  // namespace
 
 size_t forward_lds_bytes(fh_plan p) {
@@ -867,16 +865,14 @@ hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s) {
 hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
     const unsigned blocks = (unsigned)((p->n_draw_tasks + kWaves - 1) / kWaves);
     if (p->max_N <= 1024) {
-        // 16-byte row loads need every row start and every lane's first site 4-aligned
-        bool vec = true;
-        for (const ChainInfo& c : p->chains) vec = vec && c.N % 256 == 0;
-        if (p->precision == FH_FP64) {
-            if (vec) launch_bwd_fast<double, true>(p, paths, blocks, s);
-            else launch_bwd_fast<double, false>(p, paths, blocks, s);
-        } else {
-            if (vec) launch_bwd_fast<float, true>(p, paths, blocks, s);
-            else launch_bwd_fast<float, false>(p, paths, blocks, s);
-        }
+        if (p->precision == FH_FP64)
+            hipLaunchKernelGGL(k_backward_fast<double>, dim3(blocks), dim3(kThreads), 0, s,
+                               p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
+                               (const double*)p->d.filt, paths, p->d.sweep, p->d.status);
+        else
+            hipLaunchKernelGGL(k_backward_fast<float>, dim3(blocks), dim3(kThreads), 0, s,
+                               p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
+                               (const float*)p->d.filt, paths, p->d.sweep, p->d.status);
         return hipGetLastError();
     }
     if (p->precision == FH_FP64)

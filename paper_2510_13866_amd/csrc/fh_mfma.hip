@@ -577,19 +577,20 @@ __global__ __launch_bounds__(kThreads) void k_gpart_reduce(const ChainInfo* __re
 }  // namespace
 
 hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
-    bool all32 = true;
-    for (const ChainInfo& c : p->chains) all32 = all32 && c.L == 32;
-    if (all32) {
-        // pairs of worldlines per wavefront
-        const unsigned blocks = (unsigned)((p->n_fwd_tasks + kWaves - 1) / kWaves);
+    // L = 32 chains: worldline pairs per wavefront; other chains: one padded tile each
+    if (p->n_fwd32_tasks > 0) {
+        const unsigned blocks = (unsigned)((p->n_fwd32_tasks + kWaves - 1) / kWaves);
         hipLaunchKernelGGL(k_forward_mfma2<32>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           p->d.fwd_tasks, p->n_fwd_tasks, p->d.cmat, (const float*)aux,
+                           p->d.fwd32_tasks, p->n_fwd32_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
-    } else {
-        const unsigned blocks = (unsigned)((p->n_draw_tasks + kWaves - 1) / kWaves);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (p->n_fwdx_tasks > 0) {
+        const unsigned blocks = (unsigned)((p->n_fwdx_tasks + kWaves - 1) / kWaves);
         hipLaunchKernelGGL(k_forward_mfma<0>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           p->d.draw_tasks, p->n_draw_tasks, p->d.cmat, (const float*)aux,
+                           p->d.fwdx_tasks, p->n_fwdx_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
     }
