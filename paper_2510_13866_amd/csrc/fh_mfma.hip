@@ -124,8 +124,8 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, float* __restrict__ filt, double* __restrict__ blk_logz,
     const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int task = blockIdx.x * kWaves + wv;
+    const int lane = threadIdx.x & 63;
+    const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
     const DrawTask t = tasks[task];
     const ChainInfo& c = chains[t.chain];
@@ -150,16 +150,23 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
         const uint4* cm = (const uint4*)(cmat + (size_t)t.chain * 3 * 2 * 64 * 8);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            uint4 vh = cm[(0 * 2 + q) * 64 + lane];
-            uint4 vm = cm[(1 * 2 + q) * 64 + lane];
-            uint4 vl = cm[(2 * 2 + q) * 64 + lane];
-            C.h[q] = __builtin_bit_cast(bf16x8, vh);
-            C.m[q] = __builtin_bit_cast(bf16x8, vm);
-            C.l[q] = __builtin_bit_cast(bf16x8, vl);
+            C.h[q] = __builtin_bit_cast(bf16x8, cm[(0 * 2 + q) * 64 + lane]);
+            C.m[q] = __builtin_bit_cast(bf16x8, cm[(1 * 2 + q) * 64 + lane]);
+            C.l[q] = __builtin_bit_cast(bf16x8, cm[(2 * 2 + q) * 64 + lane]);
         }
     }
     const int x = lane & 31;
     const bool xin = LFIX ? true : x < L;
+    // element (tile_row(lane, v), x) sits at lane_off + vrow(v) * L of a row
+    const int lane_off = 4 * (lane >> 5) * L + x;
+    auto vrow = [](int v) { return 8 * (v >> 2) + (v & 3); };
+    auto inside = [&](int v) { return LFIX ? true : (xin && 4 * (lane >> 5) + vrow(v) < L); };
+    auto load_w = [&](int l, float (&dst)[16]) {
+        const float* Wl = Wsp + (int64_t)l * N;
+        // a padded position reads site 0 (in bounds) and multiplies an exact zero of C f C
+#pragma unroll
+        for (int v = 0; v < 16; ++v) dst[v] = Wl[inside(v) ? lane_off + vrow(v) * L : 0];
+    };
     const int ax = a % L, ay = a / L;
     f32x16 F;
 #pragma unroll
@@ -167,23 +174,19 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     double la = coef * (double)aux[c.aux_off + (int64_t)start * N + a];
     double prod = 1.0;
     float* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
-    for (int j = 1; j < len; ++j) {
+    // W of the next slice is loaded right after the stores of this one, so that its wait (one
+    // step of matrix work later) finds the stores, which may be skipped for padded lanes and so
+    // are not counted ahead of time, long retired
+    float wn[16];
+    load_w((start + 1) % L_tau, wn);
+    auto step = [&](int j) {
         const int l = (start + j) % L_tau;
-        const float* Wl = Wsp + (int64_t)l * N;
-        float w[16];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int y = tile_row(lane, v);
-            const bool in = LFIX ? true : (xin && y < L);
-            const float wv = Wl[in ? y * L + x : 0];  // always an in-bounds address
-            w[v] = in ? wv : 0.0f;
-        }
         const f32x16 X = circ_step(F, C);
         const f32x16 H = circ_step(X, C);
         float s = 0.0f;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            F[v] = H[v] * w[v];
+            F[v] = H[v] * wn[v];
             s += F[v];
         }
         const float tot = wave_sum_f32(s);
@@ -198,13 +201,19 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
             prod = 1.0;
         }
         la += shift[l];
-        float* row = rows + (int64_t)(j - 1) * N;
+        float* row = rows + (int64_t)(j - 1) * N + lane_off;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             F[v] *= inv;
-            const int y = tile_row(lane, v);
-            if (LFIX || (xin && y < L)) row[y * L + x] = F[v];
+            if (inside(v)) __builtin_nontemporal_store(F[v], row + vrow(v) * L);
         }
+        __builtin_amdgcn_sched_barrier(0);
+        load_w((l + 1) % L_tau, wn);  // the last step fetches a slice it does not use
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    if (len > 1) {
+        step(1);
+        for (int j = 2; j < len; ++j) step(j);
     }
     // end weight (C f~ C)(e)
     const f32x16 X = circ_step(F, C);
@@ -224,6 +233,12 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
 // Two worldlines of the same (chain, spin, block) per wavefront: the W slice is shared and the
 // two GEMM chains are independent, so one worldline's bf16 splitting, normalisation and stores
 // overlap the other's matrix-core work. Same arithmetic as k_forward_mfma, step for step.
+//
+// Memory order. Vector loads and stores retire in issue order, so a wait for a load also waits
+// for every store issued before it. The W slice of step j + 1 is therefore loaded before the
+// stores of step j (a compiler fence keeps that order) and is waited for one step later, when
+// those loads are long done and the stores may still be in flight. Task, chain, slice and row
+// bases are wavefront-uniform (scalar registers), so a store is one lane offset plus a constant.
 template <int LFIX>
 __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const ChainInfo* __restrict__ chains, const PairTask* __restrict__ tasks, int n_tasks,
@@ -231,8 +246,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, float* __restrict__ filt, double* __restrict__ blk_logz,
     const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int task = blockIdx.x * kWaves + wv;
+    const int lane = threadIdx.x & 63;
+    const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
     const PairTask t = tasks[task];
     const ChainInfo& c = chains[t.chain];
@@ -269,6 +284,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     }
     const int x = lane & 31;
     const bool xin = LFIX ? true : x < L;
+    // element (tile_row(lane, v), x) sits at lane_off + vrow(v) * L of a row
+    const int lane_off = 4 * (lane >> 5) * L + x;
+    auto vrow = [](int v) { return 8 * (v >> 2) + (v & 3); };
+    auto inside = [&](int v) { return LFIX ? true : (xin && 4 * (lane >> 5) + vrow(v) < L); };
+    auto load_w = [&](int l, float (&dst)[16]) {
+        const float* Wl = Wsp + (int64_t)l * N;
+        // a padded position reads site 0 (in bounds) and multiplies an exact zero of C f C
+#pragma unroll
+        for (int v = 0; v < 16; ++v) dst[v] = Wl[inside(v) ? lane_off + vrow(v) * L : 0];
+    };
     f32x16 F0, F1;
     {
         const int ax0 = a[0] % L, ay0 = a[0] / L, ax1 = a[1] % L, ay1 = a[1] / L;
@@ -285,17 +310,15 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const int64_t rowoff = (int64_t)t.block * (c.B - 1);
     float* rows0 = filt + c.filt_off + ((int64_t)pp[0] * L_tau + rowoff) * N;
     float* rows1 = filt + c.filt_off + ((int64_t)pp[1] * L_tau + rowoff) * N;
-    for (int j = 1; j < len; ++j) {
+    float wn[16];
+    load_w((start + 1) % L_tau, wn);
+    // One step: uses wn (this slice's W) and refills it with the next slice's W before the
+    // stores. The first step is peeled off the loop so that on entry to the loop, as on every
+    // later pass, the stores of the previous step sit between wn's loads and their use, and the
+    // wait before the W multiply leaves those stores in flight. A lone worldline's shadow stores
+    // the same values to the same row, which keeps the store count (and that wait) uniform.
+    auto step = [&](int j) {
         const int l = (start + j) % L_tau;
-        const float* Wl = Wsp + (int64_t)l * N;
-        float w[16];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int y = tile_row(lane, v);
-            const bool in = LFIX ? true : (xin && y < L);
-            const float wv = Wl[in ? y * L + x : 0];  // always an in-bounds address
-            w[v] = in ? wv : 0.0f;
-        }
         const f32x16 X0 = circ_step(F0, C);
         const f32x16 X1 = circ_step(F1, C);
         const f32x16 H0 = circ_step(X0, C);
@@ -303,11 +326,14 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
         float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            F0[v] = H0[v] * w[v];
-            F1[v] = H1[v] * w[v];
+            F0[v] = H0[v] * wn[v];
+            F1[v] = H1[v] * wn[v];
             s0 += F0[v];
             s1 += F1[v];
         }
+        // next slice's W (the last step fetches one slice it does not use; always in bounds)
+        load_w((l + 1) % L_tau, wn);
+        __builtin_amdgcn_sched_barrier(0);
         const float tot0 = wave_sum_f32(s0), tot1 = wave_sum_f32(s1);
         if (!(tot0 > 0.0f) || !isfinite(tot0) || !(tot1 > 0.0f) || !isfinite(tot1))
             if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
@@ -326,18 +352,21 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
         const double m = shift[l];
         la0 += m;
         la1 += m;
-        float* row0 = rows0 + (int64_t)(j - 1) * N;
-        float* row1 = rows1 + (int64_t)(j - 1) * N;
+        float* row0 = rows0 + (int64_t)(j - 1) * N + lane_off;
+        float* row1 = rows1 + (int64_t)(j - 1) * N + lane_off;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             F0[v] *= inv0;
             F1[v] *= inv1;
-            const int y = tile_row(lane, v);
-            if (LFIX || (xin && y < L)) {
-                __builtin_nontemporal_store(F0[v], &row0[y * L + x]);
-                if (has_b) __builtin_nontemporal_store(F1[v], &row1[y * L + x]);
+            if (inside(v)) {
+                __builtin_nontemporal_store(F0[v], row0 + vrow(v) * L);
+                __builtin_nontemporal_store(F1[v], row1 + vrow(v) * L);
             }
         }
+    };
+    if (len > 1) {
+        step(1);
+        for (int j = 2; j < len; ++j) step(j);
     }
     // end weights (C f~ C)(e)
     const f32x16 X0 = circ_step(F0, C);
