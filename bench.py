@@ -317,9 +317,9 @@ def main():
     algo = {"forward": rows * N * rsz + w_bytes,
             "backward": rows * (N * rsz + 4)}                      # + the drawn site (int32)
     times = {"forward": fwd_ms, "backward": bwd_ms}
-    names = {"forward": "forward filter (%s)" % ("k_forward_mfma" if args.precision == "fp32_mfma3"
+    names = {"forward": "forward filter (%s)" % ("k_forward_mfma2" if args.precision == "fp32_mfma3"
                                                  else "k_forward_fft"),
-             "backward": "backward sampler (k_backward_fast)"}
+             "backward": "backward sampler (k_backward_l32)"}
     roofs = {}
     for k in ("forward", "backward"):
         gbs = algo[k] / (times[k] / 1e3) / 1e9

@@ -132,7 +132,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks,
+                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.draw32_tasks,
                     d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -293,13 +293,20 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->n_grad_tasks = (int32_t)grad.size();
     p->n_draw_tasks = (int32_t)draw.size();
     std::vector<PairTask> fwd32;
-    std::vector<DrawTask> fwdx;
+    std::vector<DrawTask> fwdx, draw32;
     for (const PairTask& t : fwd)
         if (p->chains[t.chain].L == 32) fwd32.push_back(t);
-    for (const DrawTask& t : draw)
-        if (p->chains[t.chain].L != 32) fwdx.push_back(t);
+    for (const DrawTask& t : draw) {
+        if (p->chains[t.chain].L != 32) {
+            fwdx.push_back(t);
+            p->max_N_x = std::max(p->max_N_x, p->chains[t.chain].N);
+        } else {
+            draw32.push_back(t);
+        }
+    }
     p->n_fwd32_tasks = (int32_t)fwd32.size();
     p->n_fwdx_tasks = (int32_t)fwdx.size();
+    p->n_draw32_tasks = (int32_t)draw32.size();
     p->n_groups = (int32_t)groups.size();
     p->gpart_elems = precision == FH_FP32_MFMA3 ? gpart : 0;
 
@@ -320,6 +327,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.group_tasks, sizeof(GroupTask) * groups.size());
     if (e == hipSuccess) e = dalloc(&dv.fwd32_tasks, sizeof(PairTask) * fwd32.size());
     if (e == hipSuccess) e = dalloc(&dv.fwdx_tasks, sizeof(DrawTask) * fwdx.size());
+    if (e == hipSuccess) e = dalloc(&dv.draw32_tasks, sizeof(DrawTask) * draw32.size());
     if (e == hipSuccess) e = dalloc(&dv.gpart, sizeof(float) * (size_t)p->gpart_elems);
     if (e == hipSuccess) e = dalloc(&dv.status, sizeof(int32_t) * 2);
     if (e == hipSuccess) e = dalloc(&dv.sweep, sizeof(uint64_t));
@@ -332,6 +340,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = hipMemcpy(dv.group_tasks, groups.data(), sizeof(GroupTask) * groups.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !fwd32.empty()) e = hipMemcpy(dv.fwd32_tasks, fwd32.data(), sizeof(PairTask) * fwd32.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !fwdx.empty()) e = hipMemcpy(dv.fwdx_tasks, fwdx.data(), sizeof(DrawTask) * fwdx.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !draw32.empty()) e = hipMemcpy(dv.draw32_tasks, draw32.data(), sizeof(DrawTask) * draw32.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
         int32_t st[2] = {0, -1};
         e = hipMemcpy(dv.status, st, sizeof(st), hipMemcpyHostToDevice);

@@ -75,7 +75,8 @@ struct Device {
     DrawTask* draw_tasks = nullptr;
     GroupTask* group_tasks = nullptr;
     PairTask* fwd32_tasks = nullptr;    // MFMA forward: worldline pairs of L = 32 chains
-    DrawTask* fwdx_tasks = nullptr;     // MFMA forward: single worldlines of the other chains
+    DrawTask* fwdx_tasks = nullptr;     // single worldlines of the other chains (forward, backward)
+    DrawTask* draw32_tasks = nullptr;   // backward: worldline blocks of L = 32 chains
     float* gpart = nullptr;   // MFMA adjoint: per-group partial field gradients
     int32_t* status = nullptr;   // [0] first error code, [1] its chain
     uint64_t* sweep = nullptr;   // sweep index read by the kernels
@@ -95,7 +96,8 @@ struct fh_plan_s {
     int32_t n_fwd_tasks = 0, n_grad_tasks = 0, n_draw_tasks = 0;
     int64_t total_slices = 0;
     int32_t n_groups = 0;
-    int32_t n_fwd32_tasks = 0, n_fwdx_tasks = 0;
+    int32_t n_fwd32_tasks = 0, n_fwdx_tasks = 0, n_draw32_tasks = 0;
+    int32_t max_N_x = 0;  // largest N among the chains with L != 32
     int64_t gpart_elems = 0;
     int32_t max_N = 0, max_L = 0, max_np = 0;
     size_t real_size = 8;

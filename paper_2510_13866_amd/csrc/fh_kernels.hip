@@ -582,8 +582,140 @@ __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const doubl
     }
 }
 
-// One wavefront per (chain, worldline, block), the body chosen per chain: full 32 x 32 tiles,
-// up to 4 sites per lane (N <= 256), or up to 16 (N <= 1024).
+// Backward sampling for 32 x 32 lattices, one wavefront per (chain, worldline, block). Lane k
+// owns the sites 16k .. 16k+15, all in lattice row y0 = k / 2 from column x0 = 16 (k % 2), read
+// as four 16-byte loads per filter row. Given the next slice's site (cx, cy) the weight of site
+// (x0 + i, y0) is max(f_i, 0) g(cx - x0 - i) g(cy - y0) (periodic differences). The lane keeps
+// the FP64 prefix P_i = sum over i' <= i of max(f_i', 0) g(cx - x0 - i'); its total is
+// g(cy - y0) P_15, and the wavefront scan of the totals gives run, the sum before the lane. The
+// draw is the first site where run + g(cy - y0) P_i exceeds u times the grand total, tested as
+// P_i > (u total - run) / g(cy - y0): the same comparison up to FP64 rounding. The lowest lane
+// holding such a site supplies it. If rounding leaves none, the last site with a positive
+// weight increment is taken, as the draw rule prescribes for that case.
+//
+// Rows are prefetched DEPTH draws ahead into DEPTH + 1 buffers, and the draw loop is unrolled by
+// DEPTH + 1 so that no buffer moves between registers (a move would wait for the newest loads).
+// Every load and store is unconditional, which lets each wait leave younger memory operations in
+// flight: draws past the end of the block, padding the count to a multiple of DEPTH + 1, re-read
+// row 1 and rewrite the value the last real draw stored. All lanes store the (uniform) draw.
+template <typename T>
+__global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l32(
+    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
+    const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
+    constexpr int NB = DEPTH + 1;
+    __shared__ double g2sh[kWaves][64];  // g2[m] = g(m mod 32), so g(d) = g2[d + 32] for |d| < 32
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wv);
+    const bool active = task < n_tasks;
+    DrawTask t = {0, 0, 0, 0};
+    if (active) {
+        t = tasks[task];
+        g2sh[wv][lane] = tables[tab_g(chains[t.chain]) + (lane & 31)];
+    }
+    __syncthreads();  // the only barrier; every wave reaches it
+    if (!active) return;
+    const ChainInfo& c = chains[t.chain];
+    const uint64_t sweep = *sweep_ptr;
+    int start, len;
+    block_of(c, sweep, t.block, &start, &len);
+    const int nd = len - 1;  // draw s sets slice start + (nd - s), s = 0 .. nd - 1
+    if (nd < 1) return;
+    const int L_tau = c.L_tau;
+    int32_t* pc = paths + c.path_off;
+    int cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np + t.p], 1024, status, t.chain);
+    const int x0 = 16 * (lane & 1), y0 = lane >> 1;
+    const T* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * 1024 +
+                    16 * lane;
+    typedef T vec4 __attribute__((ext_vector_type(4)));
+    auto load_row = [&](int j, T (&dst)[16]) {  // row of draw slice start + j, j clamped to >= 1
+        const T* r = rows + (int64_t)((j < 1 ? 1 : j) - 1) * 1024;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const vec4 v4 = *(const vec4*)(r + 4 * q);
+            dst[4 * q] = v4[0];
+            dst[4 * q + 1] = v4[1];
+            dst[4 * q + 2] = v4[2];
+            dst[4 * q + 3] = v4[3];
+        }
+    };
+    T ring[NB][16];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {  // in draw order: the loop's first wait then spares the rest
+        load_row(nd - b, ring[b]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    const double* g2 = g2sh[wv];
+    double ureg = 0.0;
+    int err = 0;  // the first error of the block, reported once after the loop (no atomics inside)
+    const int nd_pad = (nd + NB - 1) / NB * NB;
+    for (int s0 = 0; s0 < nd_pad; s0 += NB) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int s = s0 + b;
+            const bool real = s < nd;
+            const int j = real ? nd - s : 1;
+            if ((s & 63) == 0) {  // lane k draws the uniform of draw s + k
+                const int jj = nd - s - lane;
+                ureg = 0.0;
+                if (jj >= 1) {
+                    const u64x4 r = philox4x64_10((uint64_t)t.p, (uint64_t)((start + jj) % L_tau),
+                                                  sweep, kTagPath, c.seed, 0);
+                    ureg = u01_from(r.x0);
+                }
+            }
+            const double u = readlane_f64(ureg, s & 63);
+            const int cx = cur & 31, cy = cur >> 5;
+            const double* gx = g2 + (cx - x0 + 17);  // g(cx - x0 - i) = gx[15 - i], index 1 .. 63
+            const double gy = g2[cy - y0 + 32];
+            double P[16];
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const double fi = (double)ring[b][i];
+                acc = fma(fi > 0.0 ? fi : 0.0, gx[15 - i], acc);
+                P[i] = acc;
+            }
+            load_row(nd - s - NB, ring[b]);  // this buffer now serves draw s + NB
+            const double tot = P[15] * gy;
+            double total;
+            const double incl = wave_incl_scan_f64(tot, lane, &total);
+            int chosen = cur;
+            if (!(total > 0.0) || !isfinite(total)) {
+                if (real && err == 0) err = isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE;
+            } else {
+                const double T_ = u * total;
+                const double Tl = fmax((T_ - (incl - tot)) / gy, 0.0);
+                int cnt = 0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) cnt += P[i] <= Tl ? 1 : 0;
+                const uint64_t found = __ballot(tot > 0.0 && cnt < 16);
+                if (found) {
+                    const int src = __ffsll((unsigned long long)found) - 1;
+                    chosen = 16 * src + __builtin_amdgcn_readlane(cnt, src);
+                } else {
+                    int lastpos = -1;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        if (gy > 0.0 && P[i] > (i ? P[i - 1] : 0.0)) lastpos = i;
+                    const uint64_t has = __ballot(lastpos >= 0);
+                    if (has) {
+                        const int src = 63 - __clzll((long long)has);
+                        chosen = 16 * src + __builtin_amdgcn_readlane(lastpos, src);
+                    }
+                }
+            }
+            chosen = real ? chosen : cur;
+            pc[(int64_t)((start + j) % L_tau) * c.np + t.p] = chosen;
+            cur = chosen;
+        }
+    }
+    if (err != 0 && lane == 0) set_status(status, err, t.chain);  // the block's first error
+}
+
+// One wavefront per (chain, worldline, block) of the chains with L != 32, the body chosen per
+// chain: up to 4 sites per lane (N <= 256), or up to 16 (N <= 1024).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_backward_fast(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
@@ -603,13 +735,12 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
     if (!active) return;
     const ChainInfo& c = chains[t.chain];
     const uint64_t sweep = *sweep_ptr;
-    if (c.L == 32)
-        backward_task<T, true, 32, 16>(t, c, gsh[wv], filt, paths, sweep, status, lane);
-    else if (c.N <= 256)
+    if (c.N <= 256)
         backward_task<T, false, 0, 4>(t, c, gsh[wv], filt, paths, sweep, status, lane);
     else
         backward_task<T, false, 0, 16>(t, c, gsh[wv], filt, paths, sweep, status, lane);
 }
+
 
 // Occupation counts of one slice (LDS histogram) and the exact field draw of every site:
 // Ising: s = +1 iff u < (1 + tanh(lambda (n_up - n_dn))) / 2; Gaussian: sigma = a (n - 1/2) + z.
@@ -863,26 +994,41 @@ hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s) {
 }
 
 hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
-    const unsigned blocks = (unsigned)((p->n_draw_tasks + kWaves - 1) / kWaves);
-    if (p->max_N <= 1024) {
+    // 32 x 32 chains on their own kernel, the rest (any L) on the generic ones
+    if (p->n_draw32_tasks > 0) {
+        const unsigned blocks = (unsigned)((p->n_draw32_tasks + kWaves - 1) / kWaves);
         if (p->precision == FH_FP64)
-            hipLaunchKernelGGL(k_backward_fast<double>, dim3(blocks), dim3(kThreads), 0, s,
-                               p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
+            hipLaunchKernelGGL(k_backward_l32<double>, dim3(blocks), dim3(kThreads), 0, s,
+                               p->d.chains, p->d.draw32_tasks, p->n_draw32_tasks, p->d.tables,
                                (const double*)p->d.filt, paths, p->d.sweep, p->d.status);
         else
-            hipLaunchKernelGGL(k_backward_fast<float>, dim3(blocks), dim3(kThreads), 0, s,
-                               p->d.chains, p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
+            hipLaunchKernelGGL(k_backward_l32<float>, dim3(blocks), dim3(kThreads), 0, s,
+                               p->d.chains, p->d.draw32_tasks, p->n_draw32_tasks, p->d.tables,
                                (const float*)p->d.filt, paths, p->d.sweep, p->d.status);
+    }
+    if (p->n_fwdx_tasks == 0) return hipGetLastError();
+    const unsigned blocks = (unsigned)((p->n_fwdx_tasks + kWaves - 1) / kWaves);
+    const DrawTask* tasks = p->d.fwdx_tasks;
+    const int n = p->n_fwdx_tasks;
+    if (p->max_N_x <= 1024) {
+        if (p->precision == FH_FP64)
+            hipLaunchKernelGGL(k_backward_fast<double>, dim3(blocks), dim3(kThreads), 0, s,
+                               p->d.chains, tasks, n, p->d.tables, (const double*)p->d.filt, paths,
+                               p->d.sweep, p->d.status);
+        else
+            hipLaunchKernelGGL(k_backward_fast<float>, dim3(blocks), dim3(kThreads), 0, s,
+                               p->d.chains, tasks, n, p->d.tables, (const float*)p->d.filt, paths,
+                               p->d.sweep, p->d.status);
         return hipGetLastError();
     }
     if (p->precision == FH_FP64)
         hipLaunchKernelGGL(k_backward<double>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
-                           (const double*)p->d.filt, paths, p->d.sweep, p->d.status);
+                           tasks, n, p->d.tables, (const double*)p->d.filt, paths, p->d.sweep,
+                           p->d.status);
     else
         hipLaunchKernelGGL(k_backward<float>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           p->d.draw_tasks, p->n_draw_tasks, p->d.tables,
-                           (const float*)p->d.filt, paths, p->d.sweep, p->d.status);
+                           tasks, n, p->d.tables, (const float*)p->d.filt, paths, p->d.sweep,
+                           p->d.status);
     return hipGetLastError();
 }
 
