@@ -50,20 +50,35 @@ typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
 __device__ inline uint32_t pk_bf16(float a, float b) {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
 }
-__device__ inline float lo_as_f32(uint32_t p) { return __builtin_bit_cast(float, p << 16); }
-__device__ inline float hi_as_f32(uint32_t p) { return __builtin_bit_cast(float, p & 0xFFFF0000u); }
+
+// The bf16 pairs (-1, 0) and (0, -1), for v_dot2c_f32_bf16: dot2((h_a, h_b), (-1, 0), a) is
+// a - h_a, exact (the rounding error of a bf16 rounding is an FP32 number, subnormals
+// included). They reach the kernels as arguments: written as a literal, the pair is folded into
+// a 32-bit inline constant whose halves do not match the pair.
+struct NegPairs {
+    uint32_t lo, hi;
+};
+constexpr NegPairs kNegPairs = {0x0000BF80u, 0xBF800000u};
+
+__device__ inline float resid_lo(uint32_t p, float a, const NegPairs& n) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, p), __builtin_bit_cast(bf16x2, n.lo), a, false);
+}
+__device__ inline float resid_hi(uint32_t p, float b, const NegPairs& n) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, p), __builtin_bit_cast(bf16x2, n.hi), b, false);
+}
 
 // Registers 8q .. 8q+7 of x as x = h + m + l, each term rounded to bf16 (nearest even). Works
-// on pairs: one packed convert per term, the f32 value of each half recovered by shift / mask.
-__device__ inline void split3_chunk(const f32x16& x, int q, bf16x8& h, bf16x8& m, bf16x8& l) {
+// on pairs: one packed convert per term and one exact residual per element.
+__device__ inline void split3_chunk(const f32x16& x, int q, bf16x8& h, bf16x8& m, bf16x8& l,
+                                    const NegPairs& n) {
     u32x4 uh, um, ul;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const float a = x[8 * q + 2 * e], b = x[8 * q + 2 * e + 1];
         const uint32_t ph = pk_bf16(a, b);
-        const float ra = a - lo_as_f32(ph), rb = b - hi_as_f32(ph);
+        const float ra = resid_lo(ph, a, n), rb = resid_hi(ph, b, n);
         const uint32_t pm = pk_bf16(ra, rb);
-        const float sa = ra - lo_as_f32(pm), sb = rb - hi_as_f32(pm);
+        const float sa = resid_lo(pm, ra, n), sb = resid_hi(pm, rb, n);
         uh[e] = ph;
         um[e] = pm;
         ul[e] = pk_bf16(sa, sb);
@@ -78,12 +93,12 @@ __device__ inline f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c)
 }
 
 // X (accumulator layout) -> X^T C: six split products per K chunk, smaller terms first.
-__device__ inline f32x16 circ_step(const f32x16& x, const Split3& C) {
+__device__ inline f32x16 circ_step(const f32x16& x, const Split3& C, const NegPairs& n) {
     f32x16 acc = {};
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         bf16x8 h, m, l;
-        split3_chunk(x, q, h, m, l);
+        split3_chunk(x, q, h, m, l, n);
         acc = mfma(l, C.h[q], acc);
         acc = mfma(m, C.m[q], acc);
         acc = mfma(m, C.h[q], acc);
@@ -123,7 +138,7 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, float* __restrict__ filt, double* __restrict__ blk_logz,
-    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const NegPairs neg) {
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
@@ -181,8 +196,8 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     load_w((start + 1) % L_tau, wn);
     auto step = [&](int j) {
         const int l = (start + j) % L_tau;
-        const f32x16 X = circ_step(F, C);
-        const f32x16 H = circ_step(X, C);
+        const f32x16 X = circ_step(F, C, neg);
+        const f32x16 H = circ_step(X, C, neg);
         float s = 0.0f;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -216,8 +231,8 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
         for (int j = 2; j < len; ++j) step(j);
     }
     // end weight (C f~ C)(e)
-    const f32x16 X = circ_step(F, C);
-    const f32x16 H = circ_step(X, C);
+    const f32x16 X = circ_step(F, C, neg);
+    const f32x16 H = circ_step(X, C, neg);
     const int ex = e % L, ey = e / L;
     const int ve = (ey >> 3) * 4 + (ey & 3);
     const int le = ex + 32 * ((ey >> 2) & 1);
@@ -245,7 +260,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, float* __restrict__ filt, double* __restrict__ blk_logz,
-    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const NegPairs neg) {
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
@@ -319,10 +334,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     // the same values to the same row, which keeps the store count (and that wait) uniform.
     auto step = [&](int j) {
         const int l = (start + j) % L_tau;
-        const f32x16 X0 = circ_step(F0, C);
-        const f32x16 X1 = circ_step(F1, C);
-        const f32x16 H0 = circ_step(X0, C);
-        const f32x16 H1 = circ_step(X1, C);
+        const f32x16 X0 = circ_step(F0, C, neg);
+        const f32x16 X1 = circ_step(F1, C, neg);
+        const f32x16 H0 = circ_step(X0, C, neg);
+        const f32x16 H1 = circ_step(X1, C, neg);
         float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -369,10 +384,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
         for (int j = 2; j < len; ++j) step(j);
     }
     // end weights (C f~ C)(e)
-    const f32x16 X0 = circ_step(F0, C);
-    const f32x16 X1 = circ_step(F1, C);
-    const f32x16 H0 = circ_step(X0, C);
-    const f32x16 H1 = circ_step(X1, C);
+    const f32x16 X0 = circ_step(F0, C, neg);
+    const f32x16 X1 = circ_step(F1, C, neg);
+    const f32x16 H0 = circ_step(X0, C, neg);
+    const f32x16 H1 = circ_step(X1, C, neg);
     float hv0 = 0.0f, hv1 = 0.0f;
     {
         const int ex0 = e[0] % L, ey0 = e[0] / L, ex1 = e[1] % L, ey1 = e[1] / L;
@@ -411,7 +426,8 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
     const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, float* __restrict__ filt, float* __restrict__ gpart,
-    double* __restrict__ blk_logz, double* __restrict__ dt_out, int anchor, int32_t* status) {
+    double* __restrict__ blk_logz, double* __restrict__ dt_out, int anchor, int32_t* status,
+    const NegPairs neg) {
     __shared__ float bt[kWaves][1024];   // beta tile of each wavefront, y * 32 + x
     __shared__ float mg[kWaves][1024];   // marginal tile of each wavefront
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -464,8 +480,8 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
             const float wv0 = Wl[in ? y * L + x : 0];
             w[v] = in ? wv0 : 0.0f;
         }
-        const f32x16 X = circ_step(F, C);
-        const f32x16 H = circ_step(X, C);
+        const f32x16 X = circ_step(F, C, neg);
+        const f32x16 H = circ_step(X, C, neg);
         float s = 0.0f;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
@@ -491,8 +507,8 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
         }
     }
     {
-        const f32x16 X = circ_step(F, C);
-        const f32x16 H = circ_step(X, C);
+        const f32x16 X = circ_step(F, C, neg);
+        const f32x16 H = circ_step(X, C, neg);
         float hv = 0.0f;
         const int ve = (ay >> 3) * 4 + (ay & 3);
 #pragma unroll
@@ -511,8 +527,8 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
     float* slab = gpart + g.part_off;
     for (int j = L_tau - 1; j >= 0; --j) {
         const int l = (anchor + j) % L_tau;
-        const f32x16 X = circ_step(U, C);
-        const f32x16 B = circ_step(X, C);   // beta_j = C u_{j+1} C
+        const f32x16 X = circ_step(U, C, neg);
+        const f32x16 B = circ_step(X, C, neg);   // beta_j = C u_{j+1} C
         const float* row = rows + (int64_t)j * N;
         float fj[16];
         float den = 0.0f;
@@ -612,7 +628,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
         hipLaunchKernelGGL(k_forward_mfma2<32>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwd32_tasks, p->n_fwd32_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
-                           paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
+                           paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status, kNegPairs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -621,7 +637,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
         hipLaunchKernelGGL(k_forward_mfma<0>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwdx_tasks, p->n_fwdx_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
-                           paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
+                           paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status, kNegPairs);
     }
     return hipGetLastError();
 }
@@ -634,12 +650,12 @@ hipError_t launch_grad_mfma(fh_plan p, const void* aux, const int32_t* paths, in
         hipLaunchKernelGGL(k_grad_mfma<32>, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
                            p->d.group_tasks, p->d.cmat, (const float*)aux, (const float*)p->d.W,
                            p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt,
-                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.status);
+                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.status, kNegPairs);
     else
         hipLaunchKernelGGL(k_grad_mfma<0>, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
                            p->d.group_tasks, p->d.cmat, (const float*)aux, (const float*)p->d.W,
                            p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt,
-                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.status);
+                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.status, kNegPairs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !grad_aux) return e;
     int64_t b = (p->aux_elems + kThreads - 1) / kThreads;
