@@ -174,6 +174,64 @@ def test_backward_sample_parity_fp64(lib):
     S.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mfma3"])
+def test_backward_draw_rule_on_device_filters(lib, prec):
+    """The FP32 backward samplers (32x32 chains, and N <= 256 / N <= 1024 chains) against the
+    oracle's draw rule applied to the device's own FP32 filters (read back exactly): with the
+    same filter values and uniforms the drawn sites must agree, except at a certified near-tie,
+    whatever the forward filter's own error. Ring and multi-block schedules."""
+    fhmc, sampler = lib
+    descs = [synth.ChainDesc(L=32, L_tau=40, n_up=6, n_dn=5, hs_kind=synth.HS_GAUSS, block_len=0,
+                             t=1.0, U=4.0, dtau=0.05, seed=31),
+             synth.ChainDesc(L=32, L_tau=30, n_up=4, n_dn=4, hs_kind=synth.HS_HIRSCH, block_len=8,
+                             t=1.0, U=3.0, dtau=0.05, seed=32),
+             synth.ChainDesc(L=24, L_tau=24, n_up=5, n_dn=3, hs_kind=synth.HS_HIRSCH, block_len=0,
+                             t=1.0, U=4.0, dtau=0.05, seed=33),
+             synth.ChainDesc(L=12, L_tau=20, n_up=3, n_dn=4, hs_kind=synth.HS_GAUSS, block_len=7,
+                             t=1.0, U=2.0, dtau=0.05, seed=34)]
+    say("backward draw rule on device filters", prec)
+    S = sampler.Sampler(descs, PRECS[prec])
+    aux, paths = mixed_state(descs, seed=51)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    n_cert = 0
+    for s in (2, 5):
+        before = S.unpack_paths(P)
+        S.forward_filter(A, P, s)
+        assert S.status() == (0, -1)
+        rows = [[S.filters(c, p) for p in range(d.n_particles)] for c, d in enumerate(descs)]
+        S.backward_sample(P, s)
+        assert S.status() == (0, -1)
+        got = S.unpack_paths(P)
+        for c, d in enumerate(descs):
+            Gm = lattice.transfer_matrix(d.L, d.t, d.dtau)
+            parts = np.arange(d.n_particles)
+            ref = before[c].astype(np.int64).copy()
+            marg = np.full(ref.shape, np.inf)
+            r0 = 0
+            for start, length in ffbs.block_schedule(d.L_tau, d.block_len, s):
+                filt = np.zeros((d.n_particles, length, d.N))
+                for p in parts:
+                    filt[p, 1:, :] = rows[c][p][r0:r0 + length - 1]
+                r0 += length - 1
+                u = np.zeros((d.n_particles, length))
+                for j in range(1, length):
+                    u[:, j] = philox_uniforms(d.seed, parts, (start + j) % d.L_tau, s)
+                anchors = before[c][start, :].astype(np.int64)
+                ends = before[c][(start + length) % d.L_tau, :].astype(np.int64)
+                pos, m = ffbs.backward_sample(Gm, filt, anchors, ends, u, True)
+                for j in range(1, length):
+                    ref[(start + j) % d.L_tau, :] = pos[:, j]
+                    marg[(start + j) % d.L_tau, :] = m[:, j]
+            n_cert += check_paths(d, got[c], ref, marg, "%s chain %d sweep %d" % (prec, c, s))
+    assert n_cert <= 1
+    S.close()
+
+
+def philox_uniforms(seed, particles, slc, sweep):
+    from oracle import philox
+    return philox.path_uniforms(seed, np.asarray(particles, dtype=np.uint64), slc, sweep)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_gibbs_parity(lib, prec):
     fhmc, sampler = lib
