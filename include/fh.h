@@ -71,7 +71,10 @@ enum fh_precision {
 
 enum fh_flags {
     FH_FLAG_NONE = 0,
-    FH_FLAG_GRAPH = 1 /* fh_sweep replays a captured hipGraph instead of eager launches */
+    FH_FLAG_GRAPH = 1,   /* fh_sweep replays a captured hipGraph instead of eager launches     */
+    FH_FLAG_AUTOTUNE = 2 /* fh_init times every radix-2/3/4 stage order of each distinct L on
+                            the device (FFT precisions) and keeps the fastest; without it the
+                            default order (4s, then a 2, then 3s) is used                    */
 };
 
 /* One chain. block_len: FFBS block length B (0 = L_tau, one block closing the ring);
@@ -95,12 +98,19 @@ typedef struct {
 } fh_chain_layout;
 
 /* Creates a plan for n_chains chains: validates every descriptor, builds the hopping tables
- * (exp(-dtau eps_k) of Sec. 3.3 and its real-space kernel), picks the FFT radix plan per L and
- * allocates the workspace (filters of every particle: L_tau*N values each in the plan's
+ * (exp(-dtau eps_k) of Sec. 3.3 and its real-space kernel), picks the FFT radix plan per L
+ * (timed on the device with FH_FLAG_AUTOTUNE) and allocates the workspace (filters of every particle: L_tau*N values each in the plan's
  * precision). Synchronous. *out is NULL on failure. */
 int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t precision,
             uint32_t flags);
 int fh_destroy(fh_plan plan);
+
+/* The FFT radix plan of chain `chain` (both dimensions): n_stages stages with radices
+ * radices[0..n_stages) in {2, 3, 4}, product L, applied in that order by every Stockham FFT of
+ * the chain (forward filter and adjoint of the FH_FP64 / FH_FP32 paths; unused on
+ * FH_FP32_MFMA3). radices: host array of at least 6 int32. Stage order is the only choice the
+ * autotuner makes; the transform is the same up to rounding for every order. */
+int fh_get_radix_plan(fh_plan plan, int32_t chain, int32_t* radices, int32_t* n_stages);
 
 /* Layout of chain `chain` in the packed arrays; totals over the batch via fh_sizes. */
 int fh_layout(fh_plan plan, int32_t chain, fh_chain_layout* out);

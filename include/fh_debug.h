@@ -20,6 +20,17 @@ extern "C" {
  * Returns FH_OK or FH_ERR_UNSUPPORTED (L not 2^a 3^b in [2, 64]). */
 int fh_debug_fft2d_host(double* data, int32_t L, int32_t inverse);
 
+/* Same as fh_debug_fft2d_host with an explicit stage order: n_stages radices from {2, 3, 4}
+ * whose product is L (any order the autotuner may pick). FH_ERR_INVALID_ARG otherwise. */
+int fh_debug_fft2d_host_plan(double* data, int32_t L, const int32_t* radices, int32_t n_stages,
+                             int32_t inverse);
+
+/* The autotuner's candidates for L: every ordered sequence of radices from {2, 3, 4} with
+ * product L and at most 6 stages, each once. out: host array of cap * 7 int32, entry k =
+ * (n_stages, radix_0, ..., radix_5) with unused radices 0. Returns the number of candidates
+ * (0 when L is not 2^a 3^b in [2, 64]); only the first cap are written. */
+int fh_debug_radix_orders(int32_t L, int32_t* out, int32_t cap);
+
 /* Real-space hopping kernel table g(d), d = 0..L-1, as built by fh_init (modified Bessel
  * series). out: host array of L doubles. */
 int fh_debug_kernel_table(int32_t L, double t, double dtau, double* out);

@@ -56,6 +56,52 @@ inline bool default_radix_plan(int L, RadixPlan* p) {
     return r == 1 && L >= 2 && L <= kMaxL;
 }
 
+// Every ordered sequence of radices from {2, 3, 4} with product L and at most kMaxRadices
+// stages, each exactly once (a depth-first walk over the radix of the next stage). These are the
+// candidates the autotuner times. Writes min(count, cap) plans to out; returns the count.
+inline int radix_orders(int L, RadixPlan* out, int cap) {
+    struct Walk {
+        RadixPlan* out;
+        int cap, count;
+        RadixPlan cur;
+        void go(int rest) {
+            if (rest == 1) {
+                if (cur.n > 0) {
+                    if (count < cap) out[count] = cur;
+                    ++count;
+                }
+                return;
+            }
+            if (cur.n == kMaxRadices) return;
+            const int radices[3] = {4, 2, 3};
+            for (int r : radices)
+                if (rest % r == 0) {
+                    cur.rad[cur.n++] = r;
+                    go(rest / r);
+                    --cur.n;
+                }
+        }
+    };
+    if (L < 2 || L > kMaxL) return 0;
+    Walk w{out, cap, 0, {}};
+    w.cur.n = 0;
+    for (int i = 0; i < kMaxRadices; ++i) w.cur.rad[i] = 0;
+    w.go(L);
+    return w.count;
+}
+
+// A plan is usable when its radices are in {2, 3, 4}, there are 1..kMaxRadices of them and
+// their product is L.
+inline bool valid_radix_plan(int L, const RadixPlan& p) {
+    if (p.n < 1 || p.n > kMaxRadices || L < 2 || L > kMaxL) return false;
+    int prod = 1;
+    for (int i = 0; i < p.n; ++i) {
+        if (p.rad[i] != 2 && p.rad[i] != 3 && p.rad[i] != 4) return false;
+        prod *= p.rad[i];
+    }
+    return prod == L;
+}
+
 // One small DFT of length P in {2, 3, 4}, in place on v.
 template <typename T, bool INV, int P>
 FH_HD inline void small_dft(cpx<T>* v) {

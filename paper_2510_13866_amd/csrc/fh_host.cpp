@@ -186,7 +186,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (!descs || n_chains < 1) return FH_ERR_INVALID_ARG;
     if (precision != FH_FP64 && precision != FH_FP32 && precision != FH_FP32_MFMA3)
         return FH_ERR_INVALID_ARG;
-    if (flags & ~(uint32_t)FH_FLAG_GRAPH) return FH_ERR_INVALID_ARG;
+    if (flags & ~(uint32_t)(FH_FLAG_GRAPH | FH_FLAG_AUTOTUNE)) return FH_ERR_INVALID_ARG;
     for (int c = 0; c < n_chains; ++c) {
         int v = validate(descs[c], precision);
         if (v != FH_OK) return v;
@@ -331,8 +331,25 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.gpart, sizeof(float) * (size_t)p->gpart_elems);
     if (e == hipSuccess) e = dalloc(&dv.status, sizeof(int32_t) * 2);
     if (e == hipSuccess) e = dalloc(&dv.sweep, sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMemcpy(dv.chains, p->chains.data(), sizeof(ChainInfo) * n_chains, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.tables, p->tables.data(), sizeof(double) * p->tables.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess && (flags & FH_FLAG_AUTOTUNE) && precision != FH_FP32_MFMA3) {
+        // one timing sweep per distinct L, on the twiddles of its first chain (the FFT paths
+        // only: the MFMA path has no radix plan)
+        std::vector<int> done;
+        for (int c = 0; c < n_chains && e == hipSuccess; ++c) {
+            const int L = p->chains[c].L;
+            if (std::find(done.begin(), done.end(), L) != done.end()) continue;
+            done.push_back(L);
+            RadixPlan best;
+            e = tune_radix_plan(p, L, dv.tables + tab_tw(p->chains[c]), p->capture_stream, &best,
+                                &p->tune_log);
+            if (e == hipSuccess)
+                for (ChainInfo& ci : p->chains)
+                    if (ci.L == L) ci.plan = best;
+        }
+    }
+    if (e == hipSuccess) e = hipMemcpy(dv.chains, p->chains.data(), sizeof(ChainInfo) * n_chains, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.cmat, p->cmat.data(), sizeof(uint16_t) * p->cmat.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.fwd_tasks, fwd.data(), sizeof(PairTask) * fwd.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.grad_tasks, grad.data(), sizeof(PairTask) * grad.size(), hipMemcpyHostToDevice);
@@ -349,7 +366,6 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         uint64_t z = 0;
         e = hipMemcpy(dv.sweep, &z, sizeof(z), hipMemcpyHostToDevice);
     }
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         free_device(dv);
         if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
@@ -368,6 +384,14 @@ int fh_destroy(fh_plan p) {
     free_device(p->d);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     delete p;
+    return FH_OK;
+}
+
+int fh_get_radix_plan(fh_plan p, int32_t chain, int32_t* radices, int32_t* n_stages) {
+    if (!p || !radices || !n_stages || chain < 0 || chain >= p->n_chains) return FH_ERR_INVALID_ARG;
+    const RadixPlan& rp = p->chains[chain].plan;
+    *n_stages = rp.n;
+    for (int i = 0; i < kMaxRadices; ++i) radices[i] = i < rp.n ? rp.rad[i] : 0;
     return FH_OK;
 }
 
@@ -561,9 +585,9 @@ int fh_get_filters(fh_plan p, int32_t chain, int32_t particle, void* dst, int64_
 
 // ---- host-only diagnostics ----------------------------------------------------------------
 
-int fh_debug_fft2d_host(double* data, int32_t L, int32_t inverse) {
-    RadixPlan rp;
-    if (!data || !default_radix_plan(L, &rp)) return FH_ERR_UNSUPPORTED;
+namespace {
+// The device kernels' 2D Stockham FFT, run on the host over every butterfly.
+void fft2d_host(double* data, int L, const RadixPlan& rp, bool inverse) {
     const int N = L * L;
     std::vector<cpx<double>> a(N), b(N), tw(L);
     for (int i = 0; i < N; ++i) a[i] = {data[2 * i], data[2 * i + 1]};
@@ -589,7 +613,36 @@ int fh_debug_fft2d_host(double* data, int32_t L, int32_t inverse) {
         data[2 * i] = src[i].re;
         data[2 * i + 1] = src[i].im;
     }
+}
+}  // namespace
+
+int fh_debug_fft2d_host(double* data, int32_t L, int32_t inverse) {
+    RadixPlan rp;
+    if (!data || !default_radix_plan(L, &rp)) return FH_ERR_UNSUPPORTED;
+    fft2d_host(data, L, rp, inverse != 0);
     return FH_OK;
+}
+
+int fh_debug_fft2d_host_plan(double* data, int32_t L, const int32_t* radices, int32_t n_stages,
+                             int32_t inverse) {
+    if (!data || !radices || n_stages < 1 || n_stages > kMaxRadices) return FH_ERR_INVALID_ARG;
+    RadixPlan rp;
+    rp.n = n_stages;
+    for (int i = 0; i < kMaxRadices; ++i) rp.rad[i] = i < n_stages ? radices[i] : 0;
+    if (!valid_radix_plan(L, rp)) return FH_ERR_INVALID_ARG;
+    fft2d_host(data, L, rp, inverse != 0);
+    return FH_OK;
+}
+
+int fh_debug_radix_orders(int32_t L, int32_t* out, int32_t cap) {
+    if (cap < 0 || (cap > 0 && !out)) return FH_ERR_INVALID_ARG;
+    std::vector<RadixPlan> v(cap > 0 ? cap : 1);
+    const int n = radix_orders(L, v.data(), cap);
+    for (int k = 0; k < std::min(n, (int)cap); ++k) {
+        out[7 * k] = v[k].n;
+        for (int i = 0; i < kMaxRadices; ++i) out[7 * k + 1 + i] = i < v[k].n ? v[k].rad[i] : 0;
+    }
+    return n;
 }
 
 int fh_debug_kernel_table(int32_t L, double t, double dtau, double* out) {

@@ -61,6 +61,13 @@ struct GroupTask {
     int64_t part_off;
 };
 
+// One autotuner timing: the radix order `plan` of lattice size L took `ms` per timing launch.
+struct TuneRecord {
+    int32_t L;
+    RadixPlan plan;
+    float ms;
+};
+
 struct Device {
     ChainInfo* chains = nullptr;
     double* tables = nullptr;
@@ -101,6 +108,7 @@ struct fh_plan_s {
     int64_t gpart_elems = 0;
     int32_t max_N = 0, max_L = 0, max_np = 0;
     size_t real_size = 8;
+    std::vector<fh::TuneRecord> tune_log;  // FH_FLAG_AUTOTUNE timings, in the order taken
     fh::Device d;
     // state
     bool have_filters = false;
@@ -125,6 +133,10 @@ hipError_t launch_forward(fh_plan p, const void* aux, const int32_t* paths, hipS
 hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s);
 hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s);
 hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s);
+// Times every radix order of L (k_fft_tune) on stream s and returns the fastest in *best (the
+// default order unless another is faster by more than 2%); timings are appended to *log.
+hipError_t tune_radix_plan(fh_plan p, int L, const double* tw_dev, hipStream_t s,
+                           RadixPlan* best, std::vector<TuneRecord>* log);
 hipError_t launch_gibbs(fh_plan p, const int32_t* paths, void* aux, hipStream_t s);
 hipError_t launch_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
                        void* grad_aux, hipStream_t s);

@@ -7,6 +7,9 @@
 // it maps f_a + i f_b to (G * f_a) + i (G * f_b) exactly. The tile and a ping-pong buffer live
 // in LDS; each radix-2/3/4 Stockham stage is one butterfly per thread between barriers.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
 #include <math.h>
 
 #include "fh_internal.h"
@@ -924,7 +927,100 @@ unsigned grid_for(int64_t n) {
     return (unsigned)b;
 }
 
+// Radix-order timing: every workgroup runs `reps` forward + inverse 2D FFTs of one L x L tile
+// with the candidate plan, the same stage code and launch shape (kThreads per tile, LDS
+// ping-pong) as the FFT kernels, rescaling by 1/N after each pair so nothing overflows.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fft_tune(const double* __restrict__ tw_tab,
+                                                       RadixPlan rp, int L, int reps,
+                                                       T* __restrict__ sink) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = L * L;
+    cpx<T>* A = (cpx<T>*)smem;
+    cpx<T>* S = A + N;
+    cpx<T>* tw = S + N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x)
+        A[i] = {T(1) / T(1 + (i + blockIdx.x) % 7), T(0)};
+    for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = {(T)tw_tab[2 * m], (T)tw_tab[2 * m + 1]};
+    __syncthreads();
+    const T scale = T(1) / T(N);
+    for (int r = 0; r < reps; ++r) {
+        fft2d<T, false>(A, S, L, rp, tw);
+        fft2d<T, true>(A, S, L, rp, tw);
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            A[i].re *= scale;
+            A[i].im *= scale;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sink[blockIdx.x] = A[0].re;
+}
+
+template <typename T>
+hipError_t time_fft_plan(const double* tw, const RadixPlan& rp, int L, hipStream_t s,
+                         hipEvent_t e0, hipEvent_t e1, T* sink, unsigned blocks, float* ms_out) {
+    constexpr int kReps = 8;
+    const size_t lds = sizeof(cpx<T>) * (2 * (size_t)L * L + L);
+    hipError_t e = allow_lds(k_fft_tune<T>, lds);
+    float best = 1e30f;
+    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {  // the first launch only warms up
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_fft_tune<T>, dim3(blocks), dim3(kThreads), lds, s, tw, rp, L,
+                               kReps, sink);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && rep > 0) best = std::min(best, ms);
+    }
+    *ms_out = best;
+    return e;
+}
+
 }  // namespace
+
+hipError_t tune_radix_plan(fh_plan p, int L, const double* tw_dev, hipStream_t s,
+                           RadixPlan* best, std::vector<TuneRecord>* log) {
+    constexpr int kCap = 64;
+    RadixPlan cand[kCap];
+    const int n = radix_orders(L, cand, kCap);
+    RadixPlan def;
+    if (!default_radix_plan(L, &def)) return hipErrorInvalidValue;
+    *best = def;
+    if (n <= 1 || n > kCap) return hipSuccess;  // nothing to choose
+    constexpr unsigned kBlocks = 1024;
+    void* sink = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&sink, kBlocks * sizeof(double));
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float best_ms = 1e30f, def_ms = 1e30f;
+    for (int k = 0; k < n && e == hipSuccess; ++k) {
+        float ms = 0.0f;
+        if (p->precision == FH_FP64)
+            e = time_fft_plan<double>(tw_dev, cand[k], L, s, e0, e1, (double*)sink, kBlocks, &ms);
+        else
+            e = time_fft_plan<float>(tw_dev, cand[k], L, s, e0, e1, (float*)sink, kBlocks, &ms);
+        if (e != hipSuccess) break;
+        if (log) log->push_back({L, cand[k], ms});
+        bool is_def = cand[k].n == def.n;
+        for (int i = 0; i < def.n && is_def; ++i) is_def = cand[k].rad[i] == def.rad[i];
+        if (is_def) def_ms = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            *best = cand[k];
+        }
+    }
+    // the default stays unless a candidate is faster by more than 2%
+    if (e != hipSuccess || !(best_ms < 0.98f * def_ms)) *best = def;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (sink) (void)hipFree(sink);
+    return e;
+}
 
 size_t forward_lds_bytes(fh_plan p) {
     return p->precision == FH_FP64 ? fft_lds<double>(p->max_N, p->max_L, false)

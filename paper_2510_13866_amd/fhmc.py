@@ -36,6 +36,7 @@ FH_FP32_MFMA3 = 2
 
 FH_FLAG_NONE = 0
 FH_FLAG_GRAPH = 1
+FH_FLAG_AUTOTUNE = 2
 
 
 class fh_chain_desc(ctypes.Structure):
@@ -71,8 +72,12 @@ _sig("fh_set_hopping", c_int32, c_void_p, POINTER(c_double))
 _sig("fh_get_status", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32))
 _sig("fh_get_filters", c_int32, c_void_p, c_int32, c_int32, c_void_p, c_int64, POINTER(c_int64),
      c_void_p)
+_sig("fh_get_radix_plan", c_int32, c_void_p, c_int32, POINTER(c_int32), POINTER(c_int32))
 _sig("fh_strerror", ctypes.c_char_p, c_int32)
 _sig("fh_debug_fft2d_host", c_int32, POINTER(c_double), c_int32, c_int32)
+_sig("fh_debug_fft2d_host_plan", c_int32, POINTER(c_double), c_int32, POINTER(c_int32), c_int32,
+     c_int32)
+_sig("fh_debug_radix_orders", c_int32, c_int32, POINTER(c_int32), c_int32)
 _sig("fh_debug_kernel_table", c_int32, c_int32, c_double, c_double, POINTER(c_double))
 _sig("fh_debug_philox", c_int32, c_uint64, c_uint64, c_uint64, c_uint64, c_uint64, c_uint64,
      POINTER(c_uint64))
@@ -181,6 +186,14 @@ def fh_get_filters(plan, chain, particle, dst=None, stream=None):
     _check(lib.fh_get_filters(plan, int(chain), int(particle), _ptr(dst), cap, byref(rows),
                               _stream(stream)), "fh_get_filters")
     return rows.value
+
+
+def fh_get_radix_plan(plan, chain):
+    """The radix stage order of chain `chain`'s FFTs, as a tuple of radices."""
+    rad = (c_int32 * 6)()
+    n = c_int32()
+    _check(lib.fh_get_radix_plan(plan, int(chain), rad, byref(n)), "fh_get_radix_plan")
+    return tuple(rad[i] for i in range(n.value))
 
 
 def fh_strerror(code):

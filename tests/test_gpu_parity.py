@@ -227,6 +227,57 @@ def test_backward_draw_rule_on_device_filters(lib, prec):
     S.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotuned_radix_plans(lib, prec):
+    """FH_FLAG_AUTOTUNE: every chain gets one of the candidate stage orders of its L, and the
+    forward filter (and, in FP64, every redrawn site) still matches the oracle."""
+    fhmc, sampler = lib
+    descs = MIXED + [
+        synth.ChainDesc(L=24, L_tau=10, n_up=3, n_dn=3, hs_kind=synth.HS_HIRSCH, block_len=0,
+                        t=1.0, U=4.0, dtau=0.05, seed=61),
+        synth.ChainDesc(L=32, L_tau=8, n_up=2, n_dn=2, hs_kind=synth.HS_GAUSS, block_len=0,
+                        t=1.0, U=4.0, dtau=0.05, seed=62)]
+    S = sampler.Sampler(descs, PRECS[prec], fhmc.FH_FLAG_AUTOTUNE)
+    plans = [fhmc.fh_get_radix_plan(S.plan, c) for c in range(len(descs))]
+    say("autotuned plans", prec, [(d.L, p) for d, p in zip(descs, plans)])
+    for d, rad in zip(descs, plans):
+        assert 1 <= len(rad) <= 6 and all(r in (2, 3, 4) for r in rad), rad
+        assert int(np.prod(rad)) == d.L, (d.L, rad)
+    for d, rad, c in zip(descs, plans, range(len(descs))):
+        same = [p for dd, p in zip(descs, plans) if dd.L == d.L]
+        assert all(p == rad for p in same), "chains of one L share a plan"
+    aux, paths = mixed_state(descs, seed=71)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    s = 1
+    before = S.unpack_paths(P)
+    logZ = S.unpack_particles(S.forward_filter(A, P, s))
+    assert S.status() == (0, -1)
+    for c, d in enumerate(descs):
+        ref_lz, ref_rows, tail = oracle_forward(d, aux[c], paths[c], s, with_tail=True)
+        assert np.all(np.abs(logZ[c] - ref_lz) <= logz_tol(prec, ref_lz, tail)), c
+        for p in range(d.n_particles):
+            assert rel_row_err(S.filters(c, p), ref_rows[p]) <= FILTER_TOL[prec], (c, p)
+    if prec == "fp64":
+        S.backward_sample(P, s)
+        assert S.status() == (0, -1)
+        got = S.unpack_paths(P)
+        n_cert = 0
+        for c, d in enumerate(descs):
+            Gm = lattice.transfer_matrix(d.L, d.t, d.dtau)
+            W_up, W_dn = hs.potentials(aux[c], d.hs_kind, d.U, d.dtau)
+            ref = before[c].astype(np.int64).copy()
+            marg = np.full(ref.shape, np.inf)
+            for W, parts in ((W_up, np.arange(d.n_up)), (W_dn, np.arange(d.n_up, d.n_particles))):
+                if len(parts) == 0:
+                    continue
+                out, _, m = ffbs.ffbs_spin(Gm, W, before[c], parts, d.seed, s, d.block_len, True)
+                ref[:, parts] = out
+                marg[:, parts] = m
+            n_cert += check_paths(d, got[c], ref, marg, "autotuned chain %d" % c)
+        assert n_cert <= 1
+    S.close()
+
+
 def philox_uniforms(seed, particles, slc, sweep):
     from oracle import philox
     return philox.path_uniforms(seed, np.asarray(particles, dtype=np.uint64), slc, sweep)

@@ -2,6 +2,7 @@
 descriptors before touching the device, and its host-side mirrors of the device arithmetic
 (FFT stages, kernel table, Philox) agree with numpy / the oracle. No GPU compute is called."""
 import ctypes
+import itertools
 import os
 import re
 
@@ -124,3 +125,76 @@ def test_null_plan_calls_are_rejected(fhmc):
     assert fhmc.lib.fh_sweep(None, None, None, 0, 1, None) == fhmc.FH_ERR_INVALID_ARG
     assert fhmc.lib.fh_get_status(None, None, None) == fhmc.FH_ERR_INVALID_ARG
     assert fhmc.fh_strerror(fhmc.FH_ERR_STATE) == "call order violated"
+
+
+def _radix_orders_brute(L):
+    """Every sequence over {2, 3, 4} of length <= 6 with product L (independent enumeration)."""
+    out = set()
+    for n in range(1, 7):
+        for seq in itertools.product((2, 3, 4), repeat=n):
+            if int(np.prod(seq)) == L:
+                out.add(seq)
+    return out
+
+
+def _smooth_lengths():
+    res = []
+    for L in range(2, 65):
+        r = L
+        for f in (2, 3):
+            while r % f == 0:
+                r //= f
+        if r == 1:
+            res.append(L)
+    return res
+
+
+@pytest.mark.parametrize("L", _smooth_lengths())
+def test_radix_order_candidates_are_every_valid_order(fhmc, L):
+    cap = 200
+    out = np.zeros(cap * 7, dtype=np.int32)
+    n = fhmc.lib.fh_debug_radix_orders(L, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cap)
+    got = [tuple(out[7 * k + 1:7 * k + 1 + out[7 * k]]) for k in range(n)]
+    assert len(got) == len(set(got)), "duplicate candidates"
+    assert set(got) == _radix_orders_brute(L)
+
+
+def test_radix_order_candidates_reject_unsupported(fhmc):
+    out = np.zeros(7, dtype=np.int32)
+    p = out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    for L in (1, 5, 7, 10, 81, 96):
+        assert fhmc.lib.fh_debug_radix_orders(L, p, 1) == 0
+
+
+@pytest.mark.parametrize("L", [6, 8, 12, 16, 24, 32, 48, 64])
+def test_every_radix_order_computes_the_dft(fhmc, L):
+    """Each stage order the autotuner may choose, run through the kernels' stage code on the
+    host, against numpy's FFT (forward and unscaled inverse)."""
+    cap = 200
+    out = np.zeros(cap * 7, dtype=np.int32)
+    n = fhmc.lib.fh_debug_radix_orders(L, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cap)
+    rng = np.random.default_rng(L)
+    x = rng.standard_normal((L, L)) + 1j * rng.standard_normal((L, L))
+    ref_f = np.fft.fft2(x)
+    ref_i = np.fft.ifft2(x) * L * L
+    for k in range(n):
+        ns = int(out[7 * k])
+        rad = np.ascontiguousarray(out[7 * k + 1:7 * k + 1 + ns], dtype=np.int32)
+        for inverse, ref in ((0, ref_f), (1, ref_i)):
+            buf = np.empty(2 * L * L)
+            buf[0::2], buf[1::2] = x.real.ravel(), x.imag.ravel()
+            rc = fhmc.lib.fh_debug_fft2d_host_plan(
+                buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), L,
+                rad.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ns, inverse)
+            assert rc == 0
+            y = (buf[0::2] + 1j * buf[1::2]).reshape(L, L)
+            assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref)), (L, tuple(rad), inverse)
+
+
+def test_fft_plan_rejects_invalid_orders(fhmc):
+    buf = np.zeros(2 * 64)
+    p = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for L, rad in ((8, [4, 4]), (8, [8]), (12, [4, 3, 1]), (8, [2, 2, 2, 1]), (6, [5, 1])):
+        r = np.array(rad, dtype=np.int32)
+        assert fhmc.lib.fh_debug_fft2d_host_plan(
+            p, L, r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(rad), 0) == fhmc.FH_ERR_INVALID_ARG
