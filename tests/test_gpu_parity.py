@@ -278,6 +278,58 @@ def test_autotuned_radix_plans(lib, prec):
     S.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mfma3"])
+def test_sampled_block_paths_chi2_against_enumeration(lib, prec):
+    """Statistical pin of the whole device sampler (forward filter + backward draws), each
+    precision: 3x3 lattice, two blocks of length 4 with fixed endpoints, 60 worldlines redrawn
+    in 400 sweeps (fresh Philox counters each); the histogram of each block's interior path
+    (729 classes) against the exact path law by brute-force enumeration, chi-square p > 1e-4."""
+    import itertools
+    import scipy.stats
+    fhmc, sampler = lib
+    d = synth.ChainDesc(L=3, L_tau=8, n_up=60, n_dn=0, hs_kind=synth.HS_GAUSS, block_len=4,
+                        t=1.0, U=4.0, dtau=0.2, seed=17)
+    S = sampler.Sampler([d], PRECS[prec])
+    aux = synth.initial_aux(d, rng_seed=5)
+    p0 = np.zeros((d.L_tau, d.n_particles), dtype=np.int32)
+    p0[4, :] = 5                     # block 0 runs site 0 -> 5, block 1 site 5 -> 0
+    A = S.pack_aux([aux])
+    P0 = S.pack_paths([p0])
+    sweeps = [4 * k for k in range(400)]  # block offset (s * 2) mod 8 = 0 for these
+    got = []
+    for s in sweeps:
+        P = P0.clone()
+        S.forward_filter(A, P, s)
+        S.backward_sample(P, s)
+        got.append(S.unpack_paths(P)[0])
+    assert S.status() == (0, -1)
+    got = np.stack(got)  # [sweeps, L_tau, particles]
+    Gm = lattice.transfer_matrix(d.L, d.t, d.dtau)
+    W, _ = hs.potentials(aux, d.hs_kind, d.U, d.dtau)
+    N = d.N
+    for start, a, e in ((0, 0, 5), (4, 5, 0)):
+        interior = np.array(list(itertools.product(range(N), repeat=3)), dtype=np.int64)
+        full = np.concatenate([np.full((len(interior), 1), a), interior,
+                               np.full((len(interior), 1), e)], axis=1)
+        w = np.ones(len(interior))
+        for j in range(4):
+            w *= W[start + j, full[:, j]] * Gm[full[:, j + 1], full[:, j]]
+        exact = w / w.sum()
+        drawn = got[:, start + 1:start + 4, :].transpose(0, 2, 1).reshape(-1, 3).astype(np.int64)
+        code = (drawn[:, 0] * N + drawn[:, 1]) * N + drawn[:, 2]
+        counts = np.bincount(code, minlength=N ** 3)
+        M = len(code)
+        ex = exact * M
+        keep = ex >= 5
+        obs = np.append(counts[keep], counts[~keep].sum())
+        exv = np.append(ex[keep], ex[~keep].sum())
+        chi2 = ((obs - exv) ** 2 / exv).sum()
+        pval = scipy.stats.chi2.sf(chi2, len(exv) - 1)
+        say("chi2 block at slice", start, prec, "classes", len(exv), "p =", pval)
+        assert pval > 1e-4, (prec, start, pval)
+    S.close()
+
+
 def philox_uniforms(seed, particles, slc, sweep):
     from oracle import philox
     return philox.path_uniforms(seed, np.asarray(particles, dtype=np.uint64), slc, sweep)
