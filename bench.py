@@ -45,9 +45,10 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--workload", default="32x32",
-                    choices=["32x32", "uneven", "hirsch16", "grad", "small"],
+                    choices=["32x32", "uneven", "hirsch16", "grad", "small", "paper64", "paper32"],
                     help="32x32: the headline workload; the others time the remaining "
-                         "configurations (uneven batch, 16x16 Ising field, adjoint, 4x4 FP64)")
+                         "configurations (uneven batch, 16x16 Ising field, adjoint, 4x4 FP64) "
+                         "and the paper's own shape (32x32, L_tau=1024, blocks of 64 or 32)")
     return ap.parse_args()
 
 
@@ -204,6 +205,11 @@ def other_workload(args):
         descs = synth.config_16x16_hirsch(64)
         label = "FFBS sweep, 64 chains x 16x16 lattice, L_tau=64, dtau=0.0625, U=4, 128+128 " \
                 "worldlines, Ising field"
+    elif args.workload in ("paper64", "paper32"):
+        B = 64 if args.workload == "paper64" else 32
+        descs = synth.config_paper_shape(32, B, 4)
+        label = "FFBS sweep, 4 chains x 32x32 lattice, L_tau=1024 (beta=32, dtau=1/32), " \
+                "FFBS blocks of %d slices, U=4, 512+512 worldlines, Gaussian field" % B
     elif args.workload == "small":
         descs = synth.config_small_fp64()
         prec_name = "fp64"

@@ -144,6 +144,13 @@ def config_uneven(n_chains: int = 256, gen_seed: int = 2510) -> List[ChainDesc]:
     return out
 
 
+def config_paper_shape(L: int = 32, block_len: int = 64, n_chains: int = 4) -> List[ChainDesc]:
+    """The paper's performance shape (Sec. 4): beta=32, dtau=1/32 (L_tau=1024), FFBS blocks of
+    32 or 64 slices, L x L at half filling; U=4, Gaussian field (the paper gives no U here)."""
+    return [half_filled(L, 1024, HS_GAUSS, 4.0, 1.0 / 32.0, seed=s, block_len=block_len)
+            for s in range(n_chains)]
+
+
 def config_gradient(n_chains: int = 8) -> List[ChainDesc]:
     """32x32, dtau=0.05, L_tau=128, U=4, Gaussian field, seeds 0.."""
     return [half_filled(32, 128, HS_GAUSS, 4.0, 0.05, seed=s) for s in range(n_chains)]
