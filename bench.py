@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--workload", default="32x32",
-                    choices=["32x32", "uneven", "hirsch16", "grad", "small", "paper64", "paper32"],
+                    choices=["32x32", "uneven", "hirsch16", "grad", "small", "paper64", "paper32",
+                             "local"],
                     help="32x32: the headline workload; the others time the remaining "
                          "configurations (uneven batch, 16x16 Ising field, adjoint, 4x4 FP64) "
                          "and the paper's own shape (32x32, L_tau=1024, blocks of 64 or 32)")
@@ -215,6 +216,10 @@ def other_workload(args):
         prec_name = "fp64"
         label = "FFBS sweep, 1 chain x 4x4 lattice, L_tau=16, dtau=0.1, U=4, 8+8 worldlines, " \
                 "Gaussian field"
+    elif args.workload == "local":
+        descs = synth.config_32x32(4.0, 16)
+        label = "local link updates (Sec. 3.5.1), 16 chains x 32x32 lattice, L_tau=160, " \
+                "512+512 worldlines, Gaussian field, 4 passes per step"
     else:
         descs = synth.config_gradient(8)
         label = "log Z_path and its gradient (field and t), 8 chains x 32x32, L_tau=128, " \
@@ -250,6 +255,24 @@ def other_workload(args):
         value = args.steps / (ms / 1e3)
         unit = "evaluations/s"
         extra["site_slices_per_s"] = sites * args.steps / (ms / 1e3)
+    elif args.workload == "local":
+        passes = 4
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            for i in range(args.warmup):
+                fhmc.fh_local_update(S.plan, A, P, i, passes, stream)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for i in range(args.steps):
+                fhmc.fh_local_update(S.plan, A, P, args.warmup + i, passes, stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        proposals = sum(d.n_particles * d.L_tau for d in descs) * passes
+        metric = "local link proposals/s (32x32, L_tau=160, 16 chains)"
+        value = proposals * args.steps / (ms / 1e3)
+        unit = "proposals/s"
     else:
         time_sweeps(S, A, P, A0, P0, 0, args.warmup, stream)
         ms = time_sweeps(S, A, P, A0, P0, args.warmup, args.steps, stream)

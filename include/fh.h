@@ -138,6 +138,18 @@ int fh_backward_sample(fh_plan plan, int32_t* paths, uint64_t sweep, fh_stream s
 int fh_gibbs_aux(fh_plan plan, const int32_t* paths, void* aux, uint64_t sweep,
                  fh_stream stream);
 
+/* Local link updates (Sec. 3.5.1, eq. Rlocal, site basis): n_passes Metropolis passes over the
+ * slices l = 0 .. L_tau-1 of every worldline in turn. Each proposes moving the worldline's site r
+ * on slice l to a nearest neighbour r' (+x, -x, +y or -y, equally likely, periodic) with its sites
+ * on slices l-1 (already updated in the pass) and l+1 fixed, and takes it iff u < R,
+ * R = W_l(r') G(r' - r_{l-1}) G(r_{l+1} - r') / [W_l(r) G(r - r_{l-1}) G(r_{l+1} - r)], in FP64.
+ * Random numbers: Philox counter (particle, slice, sweep, 2 + 256*pass); the top two bits of
+ * word 1 pick the direction, word 0 gives u. aux is read, paths updated in place. The filters of
+ * the last fh_forward_filter are invalidated (fh_backward_sample then returns FH_ERR_STATE).
+ * n_passes = 0 does nothing; negative is FH_ERR_INVALID_ARG. */
+int fh_local_update(fh_plan plan, const void* aux, int32_t* paths, uint64_t sweep,
+                    int32_t n_passes, fh_stream stream);
+
 /* n_sweeps full sweeps, sweep indices first_sweep .. first_sweep+n_sweeps-1: forward filter,
  * backward sample, Gibbs field draw, in place on aux and paths. With FH_FLAG_GRAPH the sweep
  * is captured once per (aux, paths) pair and replayed. */

@@ -458,6 +458,17 @@ int fh_gibbs_aux(fh_plan p, const int32_t* paths, void* aux, uint64_t sweep, fh_
     return FH_OK;
 }
 
+int fh_local_update(fh_plan p, const void* aux, int32_t* paths, uint64_t sweep, int32_t n_passes,
+                    fh_stream stream) {
+    if (!p || !aux || !paths || n_passes < 0) return FH_ERR_INVALID_ARG;
+    if (n_passes == 0) return FH_OK;
+    hipStream_t s = (hipStream_t)stream;
+    FH_TRY(launch_set_sweep(p, sweep, s));
+    FH_TRY(launch_local(p, aux, paths, n_passes, s));
+    p->have_filters = false;
+    return FH_OK;
+}
+
 // One sweep reading its index from the device word, as recorded into a graph.
 static hipError_t enqueue_sweep_body(fh_plan p, void* aux, int32_t* paths, hipStream_t s) {
     hipError_t e = enqueue_forward(p, aux, paths, s);

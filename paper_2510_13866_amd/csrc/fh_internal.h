@@ -138,6 +138,7 @@ hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s);
 hipError_t tune_radix_plan(fh_plan p, int L, const double* tw_dev, hipStream_t s,
                            RadixPlan* best, std::vector<TuneRecord>* log);
 hipError_t launch_gibbs(fh_plan p, const int32_t* paths, void* aux, hipStream_t s);
+hipError_t launch_local(fh_plan p, const void* aux, int32_t* paths, int n_passes, hipStream_t s);
 hipError_t launch_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
                        void* grad_aux, hipStream_t s);
 hipError_t launch_grad_reduce(fh_plan p, double* logZ, double* grad_t, hipStream_t s);

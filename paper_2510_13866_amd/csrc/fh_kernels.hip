@@ -745,6 +745,82 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
 }
 
 
+// Local link updates (Sec. 3.5.1, eq. Rlocal, site form). One thread per worldline runs
+// n_passes passes over its slices in order. The proposal moves the site r of slice l to a nearest
+// neighbour r' (top two bits of Philox word x1: +x, -x, +y, -y; periodic), the sites of slice
+// l - 1 (already updated in this pass) and slice l + 1 held fixed, and is taken iff u < R with
+//   R = exp(coef (aux_l(r') - aux_l(r))) G(r' - r_{l-1}) G(r_{l+1} - r') / [G(r - r_{l-1}) G(r_{l+1} - r)],
+// G(d) = g(d_x) g(d_y), everything in FP64 (W_l(r')/W_l(r) written through the field). Counter
+// (particle, slice, sweep, kTagLocal + 256 pass); u from word x0.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_local(const ChainInfo* __restrict__ chains,
+                                                    int n_chains, int64_t particles,
+                                                    const double* __restrict__ tables,
+                                                    const T* __restrict__ aux,
+                                                    int32_t* __restrict__ paths,
+                                                    const uint64_t* __restrict__ sweep_ptr,
+                                                    int n_passes, int32_t* status) {
+    const int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gp >= particles) return;
+    int lo = 0, hi = n_chains - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (chains[mid].part_off <= gp)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const ChainInfo& c = chains[lo];
+    const int p = (int)(gp - c.part_off);
+    const int L = c.L, N = c.N, L_tau = c.L_tau;
+    const int64_t np = c.np;
+    const double* g = tables + tab_g(c);
+    const double coef = p >= c.n_up ? c.coef_dn : c.coef_up;
+    const T* ax = aux + c.aux_off;
+    int32_t* pc = paths + c.path_off + p;  // slice l of this worldline at pc[l * np]
+    const uint64_t sweep = *sweep_ptr;
+    auto G = [&](int a, int b) {  // G(a - b) on the periodic lattice
+        int dx = a % L - b % L;
+        dx += dx < 0 ? L : 0;
+        int dy = a / L - b / L;
+        dy += dy < 0 ? L : 0;
+        return g[dx] * g[dy];
+    };
+    auto in_range = [&](int r) { return r >= 0 && r < N; };
+    for (int ps = 0; ps < n_passes; ++ps) {
+        int prev = pc[(int64_t)(L_tau - 1) * np];
+        int cur = pc[0];
+        int first = cur;
+        if (!in_range(prev) || !in_range(cur)) {
+            set_status(status, FH_ERR_BAD_PATH, lo);
+            return;
+        }
+        for (int l = 0; l < L_tau; ++l) {
+            const int next = l + 1 < L_tau ? pc[(int64_t)(l + 1) * np] : first;
+            if (!in_range(next)) {
+                set_status(status, FH_ERR_BAD_PATH, lo);
+                return;
+            }
+            const u64x4 w = philox4x64_10((uint64_t)p, (uint64_t)l, sweep,
+                                          kTagLocal + 256ull * (uint64_t)ps, c.seed, 0);
+            const int e = (int)(w.x1 >> 62);
+            const double u = u01_from(w.x0);
+            const int x = cur % L, y = cur / L;
+            const int nx = e == 0 ? (x + 1 == L ? 0 : x + 1) : e == 1 ? (x == 0 ? L - 1 : x - 1) : x;
+            const int ny = e == 2 ? (y + 1 == L ? 0 : y + 1) : e == 3 ? (y == 0 ? L - 1 : y - 1) : y;
+            const int cand = nx + L * ny;
+            const double dA = (double)ax[(int64_t)l * N + cand] - (double)ax[(int64_t)l * N + cur];
+            const double R =
+                exp(coef * dA) * ((G(cand, prev) * G(next, cand)) / (G(cur, prev) * G(next, cur)));
+            const int taken = u < R ? cand : cur;
+            if (taken != cur) pc[(int64_t)l * np] = taken;
+            if (l == 0) first = taken;
+            prev = taken;
+            cur = next;
+        }
+    }
+}
+
 // Occupation counts of one slice (LDS histogram) and the exact field draw of every site:
 // Ising: s = +1 iff u < (1 + tanh(lambda (n_up - n_dn))) / 2; Gaussian: sigma = a (n - 1/2) + z.
 template <typename T>
@@ -1125,6 +1201,19 @@ hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
         hipLaunchKernelGGL(k_backward<float>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            tasks, n, p->d.tables, (const float*)p->d.filt, paths, p->d.sweep,
                            p->d.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_local(fh_plan p, const void* aux, int32_t* paths, int n_passes, hipStream_t s) {
+    const unsigned blocks = (unsigned)((p->particles + kThreads - 1) / kThreads);
+    if (p->precision == FH_FP64)
+        hipLaunchKernelGGL(k_local<double>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->n_chains, p->particles, p->d.tables, (const double*)aux, paths,
+                           p->d.sweep, n_passes, p->d.status);
+    else
+        hipLaunchKernelGGL(k_local<float>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->n_chains, p->particles, p->d.tables, (const float*)aux, paths,
+                           p->d.sweep, n_passes, p->d.status);
     return hipGetLastError();
 }
 

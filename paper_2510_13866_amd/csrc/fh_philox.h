@@ -17,6 +17,7 @@ constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
 
 constexpr uint64_t kTagPath = 0;
 constexpr uint64_t kTagGibbs = 1;
+constexpr uint64_t kTagLocal = 2;  // local link updates; pass k uses kTagLocal + 256 k
 
 FH_HD inline uint64_t mulhi64(uint64_t a, uint64_t b) {
 #if defined(__HIP_DEVICE_COMPILE__)

@@ -83,6 +83,9 @@ class Sampler:
     def gibbs_aux(self, paths, aux, sweep, stream=None):
         fhmc.fh_gibbs_aux(self.plan, paths, aux, sweep, stream)
 
+    def local_update(self, aux, paths, sweep, n_passes=1, stream=None):
+        fhmc.fh_local_update(self.plan, aux, paths, sweep, n_passes, stream)
+
     def sweep(self, aux, paths, first_sweep, n_sweeps, stream=None):
         fhmc.fh_sweep(self.plan, aux, paths, first_sweep, n_sweeps, stream)
 

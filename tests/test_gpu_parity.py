@@ -330,6 +330,49 @@ def test_sampled_block_paths_chi2_against_enumeration(lib, prec):
     S.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_local_update_parity(lib, prec):
+    """fh_local_update (Sec. 3.5.1) against the oracle on a mixed batch (L from 2 to 32, both
+    field kinds, odd particle counts): every worldline after three passes equals the oracle's,
+    except where the oracle certifies a near-tie (|u - R| < 1e-9) among its proposals. The
+    oracle sees the field at the plan's precision."""
+    from oracle import local as olocal
+    fhmc, sampler = lib
+    descs = MIXED + [synth.ChainDesc(L=32, L_tau=12, n_up=40, n_dn=37, hs_kind=synth.HS_GAUSS,
+                                     block_len=0, t=1.0, U=4.0, dtau=0.05, seed=41)]
+    S = sampler.Sampler(descs, PRECS[prec])
+    aux, paths = mixed_state(descs, seed=81)
+    if prec != "fp64":
+        aux = [a.astype(np.float32).astype(np.float64) for a in aux]
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    n_cert = 0
+    for s, n_passes in ((3, 3), (4, 1)):
+        before = S.unpack_paths(P)
+        S.local_update(A, P, s, n_passes)
+        assert S.status() == (0, -1)
+        got = S.unpack_paths(P)
+        for c, d in enumerate(descs):
+            ref, marg = olocal.local_update(d, aux[c], before[c], s, n_passes, True)
+            bad = np.nonzero((got[c] != ref).any(axis=0))[0]
+            for p in bad:
+                m = marg[:, :, p].min()
+                assert m < 1e-9, "chain %d particle %d differs (oracle margin %g)" % (c, p, m)
+            n_cert += len(bad)
+            moved = (got[c] != before[c]).mean()
+            assert moved > 0.01, (c, moved)  # the move does move worldlines
+    assert n_cert <= 1
+    # the filters of an earlier forward filter no longer match the worldlines
+    S.forward_filter(A, P, 9)
+    S.local_update(A, P, 9, 1)
+    with pytest.raises(fhmc.FhError) as err:
+        S.backward_sample(P, 9)
+    assert err.value.code == fhmc.FH_ERR_STATE
+    with pytest.raises(fhmc.FhError) as err:
+        S.local_update(A, P, 9, -1)
+    assert err.value.code == fhmc.FH_ERR_INVALID_ARG
+    S.close()
+
+
 def philox_uniforms(seed, particles, slc, sweep):
     from oracle import philox
     return philox.path_uniforms(seed, np.asarray(particles, dtype=np.uint64), slc, sweep)
