@@ -46,7 +46,7 @@ def parse():
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--workload", default="32x32",
                     choices=["32x32", "uneven", "hirsch16", "grad", "small", "paper64", "paper32",
-                             "local"],
+                             "local", "measure"],
                     help="32x32: the headline workload; the others time the remaining "
                          "configurations (uneven batch, 16x16 Ising field, adjoint, 4x4 FP64) "
                          "and the paper's own shape (32x32, L_tau=1024, blocks of 64 or 32)")
@@ -216,6 +216,10 @@ def other_workload(args):
         prec_name = "fp64"
         label = "FFBS sweep, 1 chain x 4x4 lattice, L_tau=16, dtau=0.1, U=4, 8+8 worldlines, " \
                 "Gaussian field"
+    elif args.workload == "measure":
+        descs = synth.config_32x32(4.0, 16)
+        label = "equal-time observables S(k), C(r), D, local moment (Sec. 4), 16 chains x " \
+                "32x32 lattice, L_tau=160, 512+512 worldlines"
     elif args.workload == "local":
         descs = synth.config_32x32(4.0, 16)
         label = "local link updates (Sec. 3.5.1), 16 chains x 32x32 lattice, L_tau=160, " \
@@ -255,6 +259,27 @@ def other_workload(args):
         value = args.steps / (ms / 1e3)
         unit = "evaluations/s"
         extra["site_slices_per_s"] = sites * args.steps / (ms / 1e3)
+    elif args.workload == "measure":
+        total = sum(d.N for d in descs)
+        Sk = torch.empty(total, dtype=torch.float64, device="cuda")
+        Cr = torch.empty_like(Sk)
+        Dv = torch.empty(len(descs), dtype=torch.float64, device="cuda")
+        S2 = torch.empty_like(Dv)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            for _ in range(max(1, args.warmup)):
+                fhmc.fh_measure(S.plan, P, Sk, Cr, Dv, S2, stream)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(args.steps):
+                fhmc.fh_measure(S.plan, P, Sk, Cr, Dv, S2, stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        metric = "measured slices/s (S(k), C(r), D, local moment; 32x32, 16 chains)"
+        value = sum(d.L_tau for d in descs) * args.steps / (ms / 1e3)
+        unit = "slices/s"
     elif args.workload == "local":
         passes = 4
         e0 = torch.cuda.Event(enable_timing=True)

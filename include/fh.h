@@ -150,6 +150,18 @@ int fh_gibbs_aux(fh_plan plan, const int32_t* paths, void* aux, uint64_t sweep,
 int fh_local_update(fh_plan plan, const void* aux, int32_t* paths, uint64_t sweep,
                     int32_t n_passes, fh_stream stream);
 
+/* Equal-time observables of the worldlines `paths` (Sec. 4), per chain, averaged over the
+ * slices: with S^z_j = (n_{j,up} - n_{j,dn}) / 2 (worldline counts per site),
+ *   S(k) = (1/N) |sum_j e^{i k.r_j} S^z_j|^2,   k = 2 pi (k_x, k_y) / L indexed k_x + L k_y,
+ *   C(r) = (1/N) sum_j S^z_{j+r} S^z_j,         r indexed x + L y,
+ *   D = mean over sites of n_up n_dn,  S2 = (3/4) mean over sites of (n_up - n_dn)^2.
+ * S(k) and C(r) come from one FP64 2D FFT of S^z per slice and one inverse FFT of |F|^2. Outputs
+ * are device arrays, each nullable: Sk and Cr packed by chain (chain c's N_c values after those
+ * of chains 0..c-1), D and S2 [n_chains]. The first call allocates the plan's per-slice rows
+ * (2 * aux elements + 2 * slices doubles). */
+int fh_measure(fh_plan plan, const int32_t* paths, double* Sk, double* Cr, double* D,
+               double* S2, fh_stream stream);
+
 /* n_sweeps full sweeps, sweep indices first_sweep .. first_sweep+n_sweeps-1: forward filter,
  * backward sample, Gibbs field draw, in place on aux and paths. With FH_FLAG_GRAPH the sweep
  * is captured once per (aux, paths) pair and replayed. */

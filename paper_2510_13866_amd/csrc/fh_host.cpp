@@ -132,7 +132,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.draw32_tasks,
+                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.draw32_tasks, d.meas,
                     d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -227,6 +227,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         ci.filt_off = filt;
         ci.blk_off = blk;
         ci.slice_off = slices;
+        ci.site_off = p->total_sites;
+        p->total_sites += ci.N;
         slices += d.L_tau;
         aux += (int64_t)d.L_tau * ci.N;
         path += (int64_t)d.L_tau * ci.np;
@@ -466,6 +468,19 @@ int fh_local_update(fh_plan p, const void* aux, int32_t* paths, uint64_t sweep, 
     FH_TRY(launch_set_sweep(p, sweep, s));
     FH_TRY(launch_local(p, aux, paths, n_passes, s));
     p->have_filters = false;
+    return FH_OK;
+}
+
+int fh_measure(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* D, double* S2,
+               fh_stream stream) {
+    if (!p || !paths) return FH_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (!p->d.meas) {  // first call: the per-slice rows
+        const size_t n = 2 * (size_t)p->aux_elems + 2 * (size_t)p->total_slices;
+        FH_TRY(hipStreamSynchronize(s));
+        FH_TRY(hipMalloc((void**)&p->d.meas, sizeof(double) * n));
+    }
+    FH_TRY(launch_measure(p, paths, Sk, Cr, D, S2, s));
     return FH_OK;
 }
 

@@ -28,6 +28,7 @@ struct ChainInfo {
     int64_t filt_off;  // filter workspace: filt[filt_off + (p*L_tau + row)*N + r]
     int64_t blk_off;   // per-(particle, block) log Z: blk[blk_off + p*nb + block]
     int64_t slice_off; // index of this chain's slice 0 among all chains' slices
+    int64_t site_off;  // per-site outputs (S(k), C(r)) packed by chain: [site_off + r]
     int32_t g0, g1;    // gradient worldline groups of this chain: [g0, g1)
 };
 
@@ -85,6 +86,8 @@ struct Device {
     DrawTask* fwdx_tasks = nullptr;     // single worldlines of the other chains (forward, backward)
     DrawTask* draw32_tasks = nullptr;   // backward: worldline blocks of L = 32 chains
     float* gpart = nullptr;   // MFMA adjoint: per-group partial field gradients
+    double* meas = nullptr;   // fh_measure per-slice rows: S(k) [aux_elems], C(r) [aux_elems],
+                              // then the (n_up n_dn, (n_up - n_dn)^2) site sums [slices][2]
     int32_t* status = nullptr;   // [0] first error code, [1] its chain
     uint64_t* sweep = nullptr;   // sweep index read by the kernels
 };
@@ -106,6 +109,7 @@ struct fh_plan_s {
     int32_t n_fwd32_tasks = 0, n_fwdx_tasks = 0, n_draw32_tasks = 0;
     int32_t max_N_x = 0;  // largest N among the chains with L != 32
     int64_t gpart_elems = 0;
+    int64_t total_sites = 0;  // sum of N over the chains
     int32_t max_N = 0, max_L = 0, max_np = 0;
     size_t real_size = 8;
     std::vector<fh::TuneRecord> tune_log;  // FH_FLAG_AUTOTUNE timings, in the order taken
@@ -139,6 +143,8 @@ hipError_t tune_radix_plan(fh_plan p, int L, const double* tw_dev, hipStream_t s
                            RadixPlan* best, std::vector<TuneRecord>* log);
 hipError_t launch_gibbs(fh_plan p, const int32_t* paths, void* aux, hipStream_t s);
 hipError_t launch_local(fh_plan p, const void* aux, int32_t* paths, int n_passes, hipStream_t s);
+hipError_t launch_measure(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* D,
+                          double* S2, hipStream_t s);
 hipError_t launch_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
                        void* grad_aux, hipStream_t s);
 hipError_t launch_grad_reduce(fh_plan p, double* logZ, double* grad_t, hipStream_t s);

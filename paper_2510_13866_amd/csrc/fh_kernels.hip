@@ -862,6 +862,111 @@ __global__ __launch_bounds__(kThreads) void k_gibbs(const ChainInfo* __restrict_
     }
 }
 
+// Equal-time observables of one slice (Sec. 4), one workgroup per (chain, slice): occupation
+// counts by an LDS histogram, S^z = (n_up - n_dn) / 2, F = 2D FFT of S^z (the Stockham stages of
+// the forward filter, FP64), S(k) = |F(k)|^2 / N and, from the unscaled inverse FFT of |F|^2,
+// C(r) = (1/N) sum_j S^z_{j+r} S^z_j = IFFT(|F|^2)(r) / N^2. Rows go to the slice's place in
+// sk / cr (packed like aux); the site sums of n_up n_dn and (n_up - n_dn)^2 to sums[slice][2].
+__global__ __launch_bounds__(kThreads) void k_measure(const ChainInfo* __restrict__ chains,
+                                                      int n_chains, const double* __restrict__ tables,
+                                                      const int32_t* __restrict__ paths,
+                                                      double* __restrict__ sk, double* __restrict__ cr,
+                                                      double* __restrict__ sums, int32_t* status,
+                                                      int maxN, int maxL) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cpx<double>* A = (cpx<double>*)smem;  // [maxN]
+    cpx<double>* S = A + maxN;            // [maxN] FFT scratch; the histogram lives here first
+    cpx<double>* tw = S + maxN;           // [maxL]
+    double* red = (double*)(tw + maxL);   // [2][kWaves]
+    int32_t* cnt = (int32_t*)S;           // [2][maxN] ints fit in S (16 bytes per element)
+    const int64_t gs = blockIdx.x;
+    const int ci = find_chain(n_chains, gs, [&](int i) { return chains[i].slice_off; });
+    const ChainInfo& c = chains[ci];
+    const int l = (int)(gs - c.slice_off);
+    const int N = c.N, L = c.L;
+    for (int r = threadIdx.x; r < 2 * N; r += blockDim.x) cnt[r] = 0;
+    const double* twt = tables + tab_tw(c);
+    for (int m = threadIdx.x; m < L; m += blockDim.x) tw[m] = {twt[2 * m], twt[2 * m + 1]};
+    __syncthreads();
+    const int32_t* pl = paths + c.path_off + (int64_t)l * c.np;
+    for (int p = threadIdx.x; p < c.np; p += blockDim.x) {
+        const int r = pl[p];
+        if (r >= 0 && r < N)
+            atomicAdd(&cnt[(p >= c.n_up ? N : 0) + r], 1);
+        else
+            set_status(status, FH_ERR_BAD_PATH, ci);
+    }
+    __syncthreads();
+    double d = 0.0, m2 = 0.0;
+    for (int r = threadIdx.x; r < N; r += blockDim.x) {
+        const int nu = cnt[r], nd = cnt[N + r];
+        A[r] = {0.5 * (double)(nu - nd), 0.0};
+        d += (double)nu * (double)nd;
+        m2 += (double)(nu - nd) * (double)(nu - nd);
+    }
+    d = wave_sum(d);
+    m2 = wave_sum(m2);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        red[wv] = d;
+        red[kWaves + wv] = m2;
+    }
+    __syncthreads();  // also: the histogram in S is read before the FFT reuses S
+    if (threadIdx.x == 0) {
+        double sd = 0.0, sm = 0.0;
+        for (int w = 0; w < kWaves; ++w) {
+            sd += red[w];
+            sm += red[kWaves + w];
+        }
+        sums[2 * gs] = sd;
+        sums[2 * gs + 1] = sm;
+    }
+    fft2d<double, false>(A, S, L, c.plan, tw);
+    double* skr = sk + c.aux_off + (int64_t)l * N;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const double p2 = A[k].re * A[k].re + A[k].im * A[k].im;
+        skr[k] = p2 / (double)N;
+        A[k] = {p2, 0.0};
+    }
+    __syncthreads();
+    fft2d<double, true>(A, S, L, c.plan, tw);
+    double* crr = cr + c.aux_off + (int64_t)l * N;
+    const double inv = 1.0 / ((double)N * (double)N);
+    for (int r = threadIdx.x; r < N; r += blockDim.x) crr[r] = A[r].re * inv;
+}
+
+// Slice averages of k_measure's rows, summed in slice order: S(k), C(r) per site of every chain
+// (threads 0 .. total_sites-1), then D and the local moment per chain.
+__global__ __launch_bounds__(kThreads) void k_measure_reduce(
+    const ChainInfo* __restrict__ chains, int n_chains, int64_t total_sites,
+    const double* __restrict__ sk, const double* __restrict__ cr, const double* __restrict__ sums,
+    double* __restrict__ Sk, double* __restrict__ Cr, double* __restrict__ D,
+    double* __restrict__ S2) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t < total_sites) {
+        const int ci = find_chain(n_chains, t, [&](int i) { return chains[i].site_off; });
+        const ChainInfo& c = chains[ci];
+        const int k = (int)(t - c.site_off);
+        double a = 0.0, b = 0.0;
+        for (int l = 0; l < c.L_tau; ++l) {
+            a += sk[c.aux_off + (int64_t)l * c.N + k];
+            b += cr[c.aux_off + (int64_t)l * c.N + k];
+        }
+        if (Sk) Sk[t] = a / c.L_tau;
+        if (Cr) Cr[t] = b / c.L_tau;
+    } else if (t < total_sites + n_chains) {
+        const ChainInfo& c = chains[t - total_sites];
+        double a = 0.0, b = 0.0;
+        for (int l = 0; l < c.L_tau; ++l) {
+            a += sums[2 * (c.slice_off + l)];
+            b += sums[2 * (c.slice_off + l) + 1];
+        }
+        const double n = (double)c.L_tau * (double)c.N;
+        if (D) D[t - total_sites] = a / n;
+        if (S2) S2[t - total_sites] = 0.75 * b / n;
+    }
+}
+
 // Adjoint of the forward filter over the ring anchored at `anchor` (one block of length L_tau):
 // forward pass storing f~_j (j = 0..L_tau-1), then backward messages
 //   u_{L_tau} = delta_a;  beta_j = G * u_{j+1};  u_j = W_j . beta_j / sum   (FFT convolution)
@@ -1214,6 +1319,26 @@ hipError_t launch_local(fh_plan p, const void* aux, int32_t* paths, int n_passes
         hipLaunchKernelGGL(k_local<float>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->n_chains, p->particles, p->d.tables, (const float*)aux, paths,
                            p->d.sweep, n_passes, p->d.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* D,
+                          double* S2, hipStream_t s) {
+    const size_t lds = sizeof(cpx<double>) * (2 * (size_t)p->max_N + p->max_L) +
+                       sizeof(double) * 2 * kWaves;
+    hipError_t e = allow_lds(k_measure, lds);
+    if (e != hipSuccess) return e;
+    double* sk = p->d.meas;
+    double* cr = sk + p->aux_elems;
+    double* sums = cr + p->aux_elems;
+    hipLaunchKernelGGL(k_measure, dim3((unsigned)p->total_slices), dim3(kThreads), lds, s,
+                       p->d.chains, p->n_chains, p->d.tables, paths, sk, cr, sums, p->d.status,
+                       p->max_N, p->max_L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t n = p->total_sites + p->n_chains;
+    hipLaunchKernelGGL(k_measure_reduce, dim3((unsigned)((n + kThreads - 1) / kThreads)),
+                       dim3(kThreads), 0, s, p->d.chains, p->n_chains, p->total_sites, sk, cr,
+                       sums, Sk, Cr, D, S2);
     return hipGetLastError();
 }
 

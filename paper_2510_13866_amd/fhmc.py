@@ -67,6 +67,7 @@ _sig("fh_backward_sample", c_int32, c_void_p, c_void_p, c_uint64, c_void_p)
 _sig("fh_gibbs_aux", c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_void_p)
 _sig("fh_sweep", c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_int32, c_void_p)
 _sig("fh_local_update", c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_int32, c_void_p)
+_sig("fh_measure", c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
 _sig("fh_logZ_grad", c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
      c_void_p, c_void_p)
 _sig("fh_set_hopping", c_int32, c_void_p, POINTER(c_double))
@@ -192,6 +193,11 @@ def fh_get_filters(plan, chain, particle, dst=None, stream=None):
 def fh_local_update(plan, aux, paths, sweep, n_passes, stream=None):
     _check(lib.fh_local_update(plan, _ptr(aux), _ptr(paths), int(sweep), int(n_passes),
                                _stream(stream)), "fh_local_update")
+
+
+def fh_measure(plan, paths, Sk=None, Cr=None, D=None, S2=None, stream=None):
+    _check(lib.fh_measure(plan, _ptr(paths), _ptr(Sk), _ptr(Cr), _ptr(D), _ptr(S2),
+                          _stream(stream)), "fh_measure")
 
 
 def fh_get_radix_plan(plan, chain):

@@ -86,6 +86,22 @@ class Sampler:
     def local_update(self, aux, paths, sweep, n_passes=1, stream=None):
         fhmc.fh_local_update(self.plan, aux, paths, sweep, n_passes, stream)
 
+    def measure(self, paths, stream=None):
+        """Per-chain (S(k) [N], C(r) [N], D, local moment) of the worldlines, as numpy arrays."""
+        total = sum(lay["N"] for lay in self.layouts)
+        Sk = torch.empty(total, dtype=torch.float64, device=self.device)
+        Cr = torch.empty_like(Sk)
+        D = torch.empty(len(self.descs), dtype=torch.float64, device=self.device)
+        S2 = torch.empty_like(D)
+        fhmc.fh_measure(self.plan, paths, Sk, Cr, D, S2, stream)
+        Sk, Cr, D, S2 = (t.cpu().numpy() for t in (Sk, Cr, D, S2))
+        out, o = [], 0
+        for c, lay in enumerate(self.layouts):
+            n = lay["N"]
+            out.append((Sk[o:o + n], Cr[o:o + n], float(D[c]), float(S2[c])))
+            o += n
+        return out
+
     def sweep(self, aux, paths, first_sweep, n_sweeps, stream=None):
         fhmc.fh_sweep(self.plan, aux, paths, first_sweep, n_sweeps, stream)
 

@@ -373,6 +373,35 @@ def test_local_update_parity(lib, prec):
     S.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mfma3"])
+def test_measure_parity(lib, prec):
+    """fh_measure (Sec. 4 observables) against the oracle's direct sums on a mixed batch and a
+    32x32 chain: S(k), C(r) within 1e-12 of their largest value, D and the local moment to
+    1e-14 relative; the plan's precision does not enter (counts are exact, transforms FP64)."""
+    from oracle import measure as omeasure
+    fhmc, sampler = lib
+    descs = MIXED + [synth.ChainDesc(L=32, L_tau=6, n_up=300, n_dn=290, hs_kind=synth.HS_GAUSS,
+                                     block_len=0, t=1.0, U=4.0, dtau=0.05, seed=43)]
+    S = sampler.Sampler(descs, PRECS[prec])
+    rng = np.random.default_rng(91)
+    paths = []
+    for d in descs:
+        p = rng.integers(0, d.N, size=(d.L_tau, d.n_particles)).astype(np.int32)
+        p[:, : d.n_particles // 3] = p[:, :1]   # some stacked worldlines (counts above 1)
+        paths.append(p)
+    P = S.pack_paths(paths)
+    got = S.measure(P)
+    assert S.status() == (0, -1)
+    for c, d in enumerate(descs):
+        Sk, Cr, D, S2 = omeasure.observables(d.L, d.n_up, paths[c])
+        gSk, gCr, gD, gS2 = got[c]
+        assert np.max(np.abs(gSk - Sk)) <= 1e-12 * max(1.0, np.max(np.abs(Sk))), c
+        assert np.max(np.abs(gCr - Cr)) <= 1e-12 * max(1.0, np.max(np.abs(Cr))), c
+        assert gD == pytest.approx(D, rel=1e-14, abs=1e-300)
+        assert gS2 == pytest.approx(S2, rel=1e-14, abs=1e-300)
+    S.close()
+
+
 def philox_uniforms(seed, particles, slc, sweep):
     from oracle import philox
     return philox.path_uniforms(seed, np.asarray(particles, dtype=np.uint64), slc, sweep)
