@@ -21,6 +21,6 @@ Readings of the paper taken here (each is also listed with its reason in the des
 Modules: lattice (kernel tables), hs (potentials and field priors), philox (counter RNG),
 ffbs (forward filter / backward sampler), gibbs (field conditionals), sweep (composition),
 grad (log Z_path and its adjoint), local (local link updates, Sec. 3.5.1), measure
-(equal-time observables, Sec. 4).
+(equal-time observables, Sec. 4), mala (gradient-informed Gaussian-field proposals).
 """
-from . import lattice, hs, philox, ffbs, gibbs, sweep, grad, local, measure  # noqa: F401
+from . import lattice, hs, philox, ffbs, gibbs, sweep, grad, local, measure, mala  # noqa: F401
