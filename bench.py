@@ -46,7 +46,7 @@ def parse():
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--workload", default="32x32",
                     choices=["32x32", "uneven", "hirsch16", "grad", "small", "paper64", "paper32",
-                             "local", "measure"],
+                             "local", "measure", "mala"],
                     help="32x32: the headline workload; the others time the remaining "
                          "configurations (uneven batch, 16x16 Ising field, adjoint, 4x4 FP64) "
                          "and the paper's own shape (32x32, L_tau=1024, blocks of 64 or 32)")
@@ -216,6 +216,10 @@ def other_workload(args):
         prec_name = "fp64"
         label = "FFBS sweep, 1 chain x 4x4 lattice, L_tau=16, dtau=0.1, U=4, 8+8 worldlines, " \
                 "Gaussian field"
+    elif args.workload == "mala":
+        descs = synth.config_gradient(8)
+        label = "MALA move of the Gaussian field (two log Z_path gradients + proposal + " \
+                "accept), 8 chains x 32x32, L_tau=128, dtau=0.05, U=4, 512+512 worldlines"
     elif args.workload == "measure":
         descs = synth.config_32x32(4.0, 16)
         label = "equal-time observables S(k), C(r), D, local moment (Sec. 4), 16 chains x " \
@@ -259,6 +263,24 @@ def other_workload(args):
         value = args.steps / (ms / 1e3)
         unit = "evaluations/s"
         extra["site_slices_per_s"] = sites * args.steps / (ms / 1e3)
+    elif args.workload == "mala":
+        acc = torch.empty(len(descs), dtype=torch.int32, device="cuda")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            for i in range(max(1, args.warmup)):
+                fhmc.fh_mala_field(S.plan, A, P, 0, 0.02, i, acc, stream)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for i in range(args.steps):
+                fhmc.fh_mala_field(S.plan, A, P, i % descs[0].L_tau, 0.02, 100 + i, acc, stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        metric = "MALA field moves/s (all 8 chains per move; 32x32, L_tau=128)"
+        value = args.steps / (ms / 1e3)
+        unit = "moves/s"
+        extra["last_accepted"] = acc.cpu().tolist()
     elif args.workload == "measure":
         total = sum(d.N for d in descs)
         Sk = torch.empty(total, dtype=torch.float64, device="cuda")

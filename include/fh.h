@@ -179,6 +179,23 @@ int fh_sweep(fh_plan plan, void* aux, int32_t* paths, uint64_t first_sweep, int3
 int fh_logZ_grad(fh_plan plan, const void* aux, const int32_t* paths, int32_t anchor_slice,
                  double* logZ, void* grad_aux, double* grad_t, fh_stream stream);
 
+/* One gradient-informed move of the Gaussian field of every chain: a Metropolis-adjusted Langevin
+ * step (Roberts and Tweedie, 1996) on the field's law given the worldlines' sites at
+ * anchor_slice with their paths summed out,
+ *   pi(sigma) ∝ prod_{r,l} exp(-sigma^2/2 - a sigma/2) * Z_path(sigma)   (eq. gaussHS prior,
+ *   Z_path as in fh_logZ_grad):
+ *   sigma' = sigma + h g(sigma) + eps xi,  h = eps^2/2,  g = d log pi / d sigma,
+ * xi_rl ~ N(0,1) from the Philox counter (site, slice, sweep, 3) by Box-Muller; the chain's whole
+ * field moves to sigma' iff u < min(1, alpha), alpha the Metropolis-Hastings ratio with the
+ * Langevin proposal densities, u from counter (0, 0, sweep, 4). Two log Z_path-and-gradient
+ * evaluations per call. aux (plan precision, device) is updated in place; accepted (device
+ * int32 [n_chains], nullable) receives 1 or 0, and -1 for Ising-field chains, which stay
+ * unchanged. eps > 0 and finite. The first call allocates three field-sized work arrays. The
+ * step is an exact Metropolis-Hastings step on an FH_FP64 plan; on the FP32 plans log Z_path
+ * carries the FP32 filter error, which makes the acceptance approximate. */
+int fh_mala_field(fh_plan plan, void* aux, const int32_t* paths, int32_t anchor_slice,
+                  double eps, uint64_t sweep, int32_t* accepted, fh_stream stream);
+
 /* Replaces the hopping amplitude of every chain (t: host array [n_chains], each > 0) and
  * rebuilds the kernel tables. Synchronous; invalidates stored filters. */
 int fh_set_hopping(fh_plan plan, const double* t);

@@ -132,7 +132,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.draw32_tasks, d.meas,
+                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.draw32_tasks, d.meas, d.mala,
                     d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -541,22 +541,56 @@ int fh_sweep(fh_plan p, void* aux, int32_t* paths, uint64_t first_sweep, int32_t
     return FH_OK;
 }
 
+static hipError_t enqueue_logz_grad(fh_plan p, const void* aux, const int32_t* paths,
+                                    int32_t anchor_slice, double* logZ, void* grad_aux,
+                                    double* grad_t, hipStream_t s) {
+    hipError_t e = launch_potentials(p, aux, s);
+    if (e != hipSuccess) return e;
+    if (p->precision == FH_FP32_MFMA3) {
+        e = launch_grad_mfma(p, aux, paths, anchor_slice, grad_aux, s);
+    } else {
+        if (grad_aux) e = launch_zero(grad_aux, (int64_t)p->real_size * p->aux_elems, s);
+        if (e == hipSuccess) e = launch_grad(p, aux, paths, anchor_slice, grad_aux, s);
+    }
+    if (e == hipSuccess) e = launch_grad_reduce(p, logZ, grad_t, s);
+    return e;
+}
+
 int fh_logZ_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor_slice,
                  double* logZ, void* grad_aux, double* grad_t, fh_stream stream) {
     if (!p || !aux || !paths) return FH_ERR_INVALID_ARG;
     for (const ChainInfo& c : p->chains)
         if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
-    hipStream_t s = (hipStream_t)stream;
-    FH_TRY(launch_potentials(p, aux, s));
-    if (p->precision == FH_FP32_MFMA3) {
-        FH_TRY(launch_grad_mfma(p, aux, paths, anchor_slice, grad_aux, s));
-    } else {
-        if (grad_aux) FH_TRY(launch_zero(grad_aux, (int64_t)p->real_size * p->aux_elems, s));
-        FH_TRY(launch_grad(p, aux, paths, anchor_slice, grad_aux, s));
-    }
-    FH_TRY(launch_grad_reduce(p, logZ, grad_t, s));
+    FH_TRY(enqueue_logz_grad(p, aux, paths, anchor_slice, logZ, grad_aux, grad_t,
+                             (hipStream_t)stream));
     p->have_filters = true;
     p->filters_are_ring = true;
+    return FH_OK;
+}
+
+int fh_mala_field(fh_plan p, void* aux, const int32_t* paths, int32_t anchor_slice, double eps,
+                  uint64_t sweep, int32_t* accepted, fh_stream stream) {
+    if (!p || !aux || !paths || !(eps > 0.0) || !is_fin(eps)) return FH_ERR_INVALID_ARG;
+    for (const ChainInfo& c : p->chains)
+        if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t field = p->real_size * (size_t)p->aux_elems;
+    if (!p->d.mala) {  // first call: proposal, two gradients, two log Z_path vectors
+        FH_TRY(hipStreamSynchronize(s));
+        FH_TRY(hipMalloc(&p->d.mala, 3 * field + 2 * sizeof(double) * (size_t)p->n_chains));
+    }
+    char* base = (char*)p->d.mala;
+    void* prop = base;
+    void* g0 = base + field;
+    void* g1 = base + 2 * field;
+    double* lz0 = (double*)(base + 3 * field);
+    double* lz1 = lz0 + p->n_chains;
+    FH_TRY(launch_set_sweep(p, sweep, s));
+    FH_TRY(enqueue_logz_grad(p, aux, paths, anchor_slice, lz0, g0, nullptr, s));
+    FH_TRY(launch_mala_propose(p, aux, g0, prop, eps, s));
+    FH_TRY(enqueue_logz_grad(p, prop, paths, anchor_slice, lz1, g1, nullptr, s));
+    FH_TRY(launch_mala_accept(p, aux, prop, g0, g1, lz0, lz1, eps, accepted, s));
+    p->have_filters = false;
     return FH_OK;
 }
 

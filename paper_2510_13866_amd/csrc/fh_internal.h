@@ -86,6 +86,8 @@ struct Device {
     DrawTask* fwdx_tasks = nullptr;     // single worldlines of the other chains (forward, backward)
     DrawTask* draw32_tasks = nullptr;   // backward: worldline blocks of L = 32 chains
     float* gpart = nullptr;   // MFMA adjoint: per-group partial field gradients
+    void* mala = nullptr;     // fh_mala_field: proposal, two gradients [3][aux_elems] in plan
+                              // precision, then log Z_path at both fields [2][n_chains] f64
     double* meas = nullptr;   // fh_measure per-slice rows: S(k) [aux_elems], C(r) [aux_elems],
                               // then the (n_up n_dn, (n_up - n_dn)^2) site sums [slices][2]
     int32_t* status = nullptr;   // [0] first error code, [1] its chain
@@ -145,6 +147,11 @@ hipError_t launch_gibbs(fh_plan p, const int32_t* paths, void* aux, hipStream_t 
 hipError_t launch_local(fh_plan p, const void* aux, int32_t* paths, int n_passes, hipStream_t s);
 hipError_t launch_measure(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* D,
                           double* S2, hipStream_t s);
+hipError_t launch_mala_propose(fh_plan p, const void* aux, const void* dlogz, void* prop,
+                               double eps, hipStream_t s);
+hipError_t launch_mala_accept(fh_plan p, void* aux, const void* prop, const void* g0,
+                              const void* g1, const double* logz0, const double* logz1,
+                              double eps, int32_t* accepted, hipStream_t s);
 hipError_t launch_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
                        void* grad_aux, hipStream_t s);
 hipError_t launch_grad_reduce(fh_plan p, double* logZ, double* grad_t, hipStream_t s);

@@ -862,6 +862,86 @@ __global__ __launch_bounds__(kThreads) void k_gibbs(const ChainInfo* __restrict_
     }
 }
 
+// Langevin proposal for the Gaussian field (MALA), one thread per field value:
+//   sigma' = sigma + h (-sigma - a/2 + dlogZ(sigma)) + eps xi,  h = eps^2 / 2,
+// xi from the Philox counter (site, slice, sweep, kTagMala) by Box-Muller. Ising-field chains
+// copy their field (they are never accepted).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_mala_propose(
+    const ChainInfo* __restrict__ chains, int n_chains, int64_t aux_elems,
+    const T* __restrict__ aux, const T* __restrict__ dlogz, T* __restrict__ prop, double eps,
+    const uint64_t* __restrict__ sweep_ptr) {
+    const uint64_t sweep = *sweep_ptr;
+    const double h = 0.5 * eps * eps;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < aux_elems;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int ci = find_chain(n_chains, e, [&](int i) { return chains[i].aux_off; });
+        const ChainInfo& c = chains[ci];
+        const double s = (double)aux[e];
+        if (c.hs_kind != FH_HS_GAUSS) {
+            prop[e] = aux[e];
+            continue;
+        }
+        const int64_t off = e - c.aux_off;
+        const int l = (int)(off / c.N), r = (int)(off % c.N);
+        const u64x4 x = philox4x64_10((uint64_t)r, (uint64_t)l, sweep, kTagMala, c.seed, 0);
+        const double g = -s - 0.5 * c.gauss_a + (double)dlogz[e];
+        prop[e] = (T)(s + h * g + eps * normal_from(x.x0, x.x1));
+    }
+}
+
+// MALA acceptance, one workgroup per chain: the Metropolis-Hastings ratio of the Langevin move
+//   log alpha = [prior + log Z_path](sigma') - [prior + log Z_path](sigma)
+//               - |sigma - sigma' - h g(sigma')|^2 / (2 eps^2) + |sigma' - sigma - h g(sigma)|^2 / (2 eps^2),
+// prior = sum (-sigma^2/2 - a sigma/2), g = -sigma - a/2 + dlogZ, summed in FP64 in a fixed
+// order; u from Philox (0, 0, sweep, kTagMalaAccept); the chain's field becomes sigma' iff
+// u < exp(min(log alpha, 0)). accepted[c] = 1 / 0, -1 for Ising-field chains.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_mala_accept(
+    const ChainInfo* __restrict__ chains, T* __restrict__ aux, const T* __restrict__ prop,
+    const T* __restrict__ g0, const T* __restrict__ g1, const double* __restrict__ logz0,
+    const double* __restrict__ logz1, double eps, const uint64_t* __restrict__ sweep_ptr,
+    int32_t* __restrict__ accepted) {
+    __shared__ double red[3][kThreads];
+    __shared__ int take;
+    const ChainInfo& c = chains[blockIdx.x];
+    if (c.hs_kind != FH_HS_GAUSS) {
+        if (threadIdx.x == 0 && accepted) accepted[blockIdx.x] = -1;
+        return;  // whole workgroup; no barrier reached
+    }
+    const double h = 0.5 * eps * eps, a = c.gauss_a;
+    const int64_t n = (int64_t)c.L_tau * c.N;
+    double lp = 0.0, fwd = 0.0, rev = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int64_t e = c.aux_off + i;
+        const double s = (double)aux[e], sp = (double)prop[e];
+        const double gs = -s - 0.5 * a + (double)g0[e], gp = -sp - 0.5 * a + (double)g1[e];
+        lp += (-0.5 * sp * sp - 0.5 * a * sp) - (-0.5 * s * s - 0.5 * a * s);
+        const double df = sp - s - h * gs, dr = s - sp - h * gp;
+        fwd += df * df;
+        rev += dr * dr;
+    }
+    red[0][threadIdx.x] = lp;
+    red[1][threadIdx.x] = fwd;
+    red[2][threadIdx.x] = rev;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double la = red[0][0] + logz1[blockIdx.x] - logz0[blockIdx.x] -
+                          red[2][0] / (2.0 * eps * eps) + red[1][0] / (2.0 * eps * eps);
+        const u64x4 x = philox4x64_10(0, 0, *sweep_ptr, kTagMalaAccept, c.seed, 0);
+        take = u01_from(x.x0) < exp(la < 0.0 ? la : 0.0) ? 1 : 0;
+        if (accepted) accepted[blockIdx.x] = take;
+    }
+    __syncthreads();
+    if (take)
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) aux[c.aux_off + i] = prop[c.aux_off + i];
+}
+
 // Equal-time observables of one slice (Sec. 4), one workgroup per (chain, slice): occupation
 // counts by an LDS histogram, S^z = (n_up - n_dn) / 2, F = 2D FFT of S^z (the Stockham stages of
 // the forward filter, FP64), S(k) = |F(k)|^2 / N and, from the unscaled inverse FFT of |F|^2,
@@ -1339,6 +1419,34 @@ hipError_t launch_measure(fh_plan p, const int32_t* paths, double* Sk, double* C
     hipLaunchKernelGGL(k_measure_reduce, dim3((unsigned)((n + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, s, p->d.chains, p->n_chains, p->total_sites, sk, cr,
                        sums, Sk, Cr, D, S2);
+    return hipGetLastError();
+}
+
+hipError_t launch_mala_propose(fh_plan p, const void* aux, const void* dlogz, void* prop,
+                               double eps, hipStream_t s) {
+    const unsigned blocks = grid_for(p->aux_elems);
+    if (p->precision == FH_FP64)
+        hipLaunchKernelGGL(k_mala_propose<double>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->n_chains, p->aux_elems, (const double*)aux, (const double*)dlogz,
+                           (double*)prop, eps, p->d.sweep);
+    else
+        hipLaunchKernelGGL(k_mala_propose<float>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->n_chains, p->aux_elems, (const float*)aux, (const float*)dlogz,
+                           (float*)prop, eps, p->d.sweep);
+    return hipGetLastError();
+}
+
+hipError_t launch_mala_accept(fh_plan p, void* aux, const void* prop, const void* g0,
+                              const void* g1, const double* logz0, const double* logz1,
+                              double eps, int32_t* accepted, hipStream_t s) {
+    if (p->precision == FH_FP64)
+        hipLaunchKernelGGL(k_mala_accept<double>, dim3(p->n_chains), dim3(kThreads), 0, s,
+                           p->d.chains, (double*)aux, (const double*)prop, (const double*)g0,
+                           (const double*)g1, logz0, logz1, eps, p->d.sweep, accepted);
+    else
+        hipLaunchKernelGGL(k_mala_accept<float>, dim3(p->n_chains), dim3(kThreads), 0, s,
+                           p->d.chains, (float*)aux, (const float*)prop, (const float*)g0,
+                           (const float*)g1, logz0, logz1, eps, p->d.sweep, accepted);
     return hipGetLastError();
 }
 

@@ -68,6 +68,8 @@ _sig("fh_gibbs_aux", c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_void_p)
 _sig("fh_sweep", c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_int32, c_void_p)
 _sig("fh_local_update", c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_int32, c_void_p)
 _sig("fh_measure", c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
+_sig("fh_mala_field", c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_uint64, c_void_p,
+     c_void_p)
 _sig("fh_logZ_grad", c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
      c_void_p, c_void_p)
 _sig("fh_set_hopping", c_int32, c_void_p, POINTER(c_double))
@@ -198,6 +200,11 @@ def fh_local_update(plan, aux, paths, sweep, n_passes, stream=None):
 def fh_measure(plan, paths, Sk=None, Cr=None, D=None, S2=None, stream=None):
     _check(lib.fh_measure(plan, _ptr(paths), _ptr(Sk), _ptr(Cr), _ptr(D), _ptr(S2),
                           _stream(stream)), "fh_measure")
+
+
+def fh_mala_field(plan, aux, paths, anchor_slice, eps, sweep, accepted=None, stream=None):
+    _check(lib.fh_mala_field(plan, _ptr(aux), _ptr(paths), int(anchor_slice), float(eps),
+                             int(sweep), _ptr(accepted), _stream(stream)), "fh_mala_field")
 
 
 def fh_get_radix_plan(plan, chain):

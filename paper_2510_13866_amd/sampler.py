@@ -117,6 +117,21 @@ class Sampler:
         fhmc.fh_logZ_grad(self.plan, aux, paths, anchor_slice, logZ, grad_aux, grad_t, stream)
         return logZ, grad_aux, grad_t
 
+    def mala_field(self, aux, paths, anchor_slice, eps, sweep, stream=None) -> np.ndarray:
+        """One MALA move of every Gaussian field (fh_mala_field); per-chain 1 / 0 accepted,
+        -1 for Ising-field chains."""
+        acc = torch.empty(len(self.descs), dtype=torch.int32, device=self.device)
+        fhmc.fh_mala_field(self.plan, aux, paths, anchor_slice, eps, sweep, acc, stream)
+        return acc.cpu().numpy()
+
+    def kinetic_energy(self, aux, paths, anchor_slice, stream=None) -> np.ndarray:
+        """Rao-Blackwellised kinetic-energy estimate per chain, -(t / beta) d log Z_path / d t
+        (beta = L_tau dtau): the hopping term's expectation with the paths summed out given the
+        anchor sites, from the adjoint's d/dt."""
+        _, _, grad_t = self.logz_grad(aux, paths, anchor_slice, stream)
+        g = grad_t.cpu().numpy()
+        return np.array([-d.t / (d.L_tau * d.dtau) * g[c] for c, d in enumerate(self.descs)])
+
     def filters(self, chain, particle) -> np.ndarray:
         rows = fhmc.fh_get_filters(self.plan, chain, particle)
         N = self.layouts[chain]["N"]

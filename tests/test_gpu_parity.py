@@ -402,6 +402,66 @@ def test_measure_parity(lib, prec):
     S.close()
 
 
+def test_mala_field_parity(lib):
+    """fh_mala_field on an FP64 plan against the oracle's MALA step: the same accept decision per
+    Gaussian chain (unless the oracle's u sits within 1e-9 of min(1, alpha)), the same new field
+    (1e-10), untouched Ising chains reported as -1; several sweeps and step sizes."""
+    from oracle import mala as omala, philox as ophilox
+    fhmc, sampler = lib
+    descs = [synth.ChainDesc(L=4, L_tau=8, n_up=6, n_dn=5, hs_kind=synth.HS_GAUSS, block_len=0,
+                             t=1.0, U=4.0, dtau=0.1, seed=101),
+             synth.ChainDesc(L=3, L_tau=6, n_up=4, n_dn=4, hs_kind=synth.HS_HIRSCH, block_len=0,
+                             t=1.0, U=4.0, dtau=0.1, seed=102),
+             synth.ChainDesc(L=6, L_tau=5, n_up=10, n_dn=8, hs_kind=synth.HS_GAUSS, block_len=3,
+                             t=1.0, U=2.0, dtau=0.2, seed=103),
+             synth.ChainDesc(L=2, L_tau=4, n_up=1, n_dn=1, hs_kind=synth.HS_GAUSS, block_len=0,
+                             t=1.0, U=6.0, dtau=0.5, seed=104)]
+    S = sampler.Sampler(descs, fhmc.FH_FP64)
+    aux, paths = mixed_state(descs, seed=111)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    n_acc = n_rej = n_cert = 0
+    for sweep, eps, anchor in ((0, 0.15, 1), (1, 0.3, 2), (2, 0.08, 0), (3, 0.5, 3), (4, 1.5, 1)):
+        before = S.unpack_aux(A)
+        acc = S.mala_field(A, P, anchor, eps, sweep)
+        assert S.status() == (0, -1)
+        after = S.unpack_aux(A)
+        for c, d in enumerate(descs):
+            if d.hs_kind != synth.HS_GAUSS:
+                assert acc[c] == -1 and np.array_equal(after[c], before[c])
+                continue
+            ref, ok, la = omala.mala_step(d, before[c], paths[c], anchor, eps, sweep)
+            w0, _, _, _ = ophilox.draw_words(d.seed, np.uint64(0), np.uint64(0), sweep,
+                                             omala.TAG_MALA_ACCEPT)
+            u = float(ophilox.uniform(np.asarray(w0)))
+            if bool(acc[c]) != ok:
+                margin = abs(u - np.exp(min(la, 0.0)))
+                assert margin < 1e-9, (c, sweep, la, u)
+                n_cert += 1
+                continue
+            n_acc += ok
+            n_rej += not ok
+            assert np.max(np.abs(after[c] - ref)) <= 1e-10, (c, sweep)
+    assert n_cert <= 1 and n_acc >= 2 and n_rej >= 1, (n_acc, n_rej)
+    with pytest.raises(fhmc.FhError):
+        S.mala_field(A, P, 0, -0.1, 9)
+    S.close()
+
+
+def test_kinetic_energy_u0_closed_form(lib):
+    """-(t/beta) d log Z_path / d t at U = 0 (W = 1) equals, per worldline, -(t/beta) times
+    sum_k 2 beta c_k e^{2 beta t c_k} / sum_k e^{2 beta t c_k} (c_k = cos k_x + cos k_y):
+    5.898678748201 / 1.6 per worldline on the 4x4, L_tau = 16, dtau = 0.1 shape."""
+    fhmc, sampler = lib
+    d = synth.ChainDesc(L=4, L_tau=16, n_up=8, n_dn=8, hs_kind=synth.HS_GAUSS, block_len=0,
+                        t=1.0, U=0.0, dtau=0.1, seed=0)
+    S = sampler.Sampler([d], fhmc.FH_FP64)
+    A = S.pack_aux([synth.initial_aux(d)])
+    P = S.pack_paths([synth.random_paths(d, 7)])
+    ek = S.kinetic_energy(A, P, 5)
+    assert ek[0] == pytest.approx(-16 * 5.898678748201 / 1.6, rel=1e-10)
+    S.close()
+
+
 def philox_uniforms(seed, particles, slc, sweep):
     from oracle import philox
     return philox.path_uniforms(seed, np.asarray(particles, dtype=np.uint64), slc, sweep)
