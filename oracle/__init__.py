@@ -15,12 +15,14 @@ Readings of the paper taken here (each is also listed with its reason in the des
   * Trotter placement: under the periodic trace (Sec. 3.1) the symmetric split of eq. trotter
     is cyclically equal to prod_l (e^{-dtau K} W_l); a path weighs
     prod_l W_l(r_l) G(r_{l+1} - r_l).
-  * Permutations are fixed to the identity (each worldline closes on itself).
+  * Permutations are the identity (each worldline closes on itself) unless a reconnection
+    permutation is passed (FFBS, local updates and the pair swaps of `perm` accept one).
   * Convolutions are direct O(N^2) sums with a dense circulant matrix; no FFT anywhere.
 
 Modules: lattice (kernel tables), hs (potentials and field priors), philox (counter RNG),
 ffbs (forward filter / backward sampler), gibbs (field conditionals), sweep (composition),
 grad (log Z_path and its adjoint), local (local link updates, Sec. 3.5.1), measure
-(equal-time observables, Sec. 4), mala (gradient-informed Gaussian-field proposals).
+(equal-time observables, Sec. 4), mala (gradient-informed Gaussian-field proposals), perm
+(reconnections at tau = beta and their sign, Sec. 3.5.6).
 """
-from . import lattice, hs, philox, ffbs, gibbs, sweep, grad, local, measure, mala  # noqa: F401
+from . import lattice, hs, philox, ffbs, gibbs, sweep, grad, local, measure, mala, perm  # noqa: F401

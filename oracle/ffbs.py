@@ -113,21 +113,36 @@ def backward_sample(Gmat: np.ndarray, filt: np.ndarray, anchors: np.ndarray,
     return pos
 
 
-def ffbs_spin(Gmat, W, paths, particles, seed, sweep, block_len, return_margin=False):
+def ffbs_spin(Gmat, W, paths, particles, seed, sweep, block_len, return_margin=False,
+              perm=None):
     """FFBS of every block of the given particles (one spin) for one sweep.
 
     paths: [L_tau, n_particles] current worldlines (endpoints are read from it).
+    perm: optional [n_particles] permutation of the worldline connections at tau = beta (eq.
+    joint; Sec. 3.5.6): slice L_tau of worldline p is slice 0 of worldline perm[p]. A block that
+    runs past slice L_tau - 1 of its owner p continues on worldline perm[p]: its end site and
+    its interior slices from L_tau on are read from / written to perm[p]'s column. With a
+    permutation, `particles` must be all of the spin's worldlines (perm maps them onto
+    themselves); None is the identity.
     Returns (new positions for these particles [L_tau, P], logZ summed over blocks [P],
     and margins [L_tau, P] if asked; margins at fixed endpoints are +inf).
     """
     L_tau = W.shape[0]
+    particles = np.asarray(particles, dtype=np.int64)
     P = len(particles)
     out = paths[:, particles].astype(np.int64).copy()
+    col = np.arange(P)                       # column of each particle's own slices
+    if perm is None:
+        nxt = col                            # column holding each worldline's slices >= L_tau
+    else:
+        where = {int(q): k for k, q in enumerate(particles)}
+        nxt = np.array([where[int(perm[q])] for q in particles], dtype=np.int64)
     logZ = np.zeros(P)
     marg = np.full((L_tau, P), np.inf)
     for start, length in block_schedule(L_tau, block_len, sweep):
         anchors = paths[start, particles].astype(np.int64)
-        ends = paths[(start + length) % L_tau, particles].astype(np.int64)
+        end_col = nxt if start + length >= L_tau else col
+        ends = paths[(start + length) % L_tau, particles[end_col]].astype(np.int64)
         filt, lz, _ = forward_filter(Gmat, W, start, length, anchors, ends)
         logZ += lz
         u = np.zeros((P, length))
@@ -137,9 +152,10 @@ def ffbs_spin(Gmat, W, paths, particles, seed, sweep, block_len, return_margin=F
         res = backward_sample(Gmat, filt, anchors, ends, u, return_margin)
         pos, m = res if return_margin else (res, None)
         for j in range(1, length):
-            out[(start + j) % L_tau, :] = pos[:, j]
+            c = nxt if start + j >= L_tau else col
+            out[(start + j) % L_tau, c] = pos[:, j]
             if return_margin:
-                marg[(start + j) % L_tau, :] = m[:, j]
+                marg[(start + j) % L_tau, c] = m[:, j]
     if return_margin:
         return out, logZ, marg
     return out, logZ

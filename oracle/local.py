@@ -11,9 +11,12 @@ so moving r_l to r' is accepted with probability min(1, R),
 Readings where the paper is silent:
   * proposal: r' = r_l + e with e one of the four lattice vectors (+x, -x, +y, -y), equally
     likely, periodic. The proposal is symmetric, so min(1, R) is the Metropolis acceptance;
-  * order: one pass visits slices l = 0, 1, ..., L_tau-1 of a worldline in turn, the updated
-    position of slice l-1 being the neighbour of slice l (slice L_tau-1 neighbours slice 0).
-    Worldlines are independent given the field, so their order does not matter;
+  * order: one pass first visits the interior slices l = 1, ..., L_tau-2 of every worldline in
+    turn (the updated slice l-1 is the neighbour of slice l), then slice 0 of every worldline,
+    then slice L_tau-1 of every worldline. The two end slices neighbour other worldlines when the
+    worldlines reconnect at tau = beta (permutation perm: slice L_tau of p is slice 0 of
+    perm[p]); visiting them in phases of their own keeps each phase's moves independent.
+    Without a permutation each worldline closes on itself;
   * random numbers: Philox counter (particle, slice, sweep, TAG_LOCAL + 256 * pass), key
     (seed, 0); the top two bits of word x1 select e (0: +x, 1: -x, 2: +y, 3: -y), word x0 gives
     the uniform u, and the move is taken iff u < R.
@@ -37,12 +40,13 @@ def neighbour(r: np.ndarray, e: np.ndarray, L: int) -> np.ndarray:
 
 
 def local_update(desc, aux: np.ndarray, paths: np.ndarray, sweep: int, n_passes: int,
-                 return_margin: bool = False):
+                 return_margin: bool = False, perm: np.ndarray | None = None):
     """n_passes passes of local link updates over every worldline.
 
-    aux [L_tau, N] field, paths [L_tau, n_particles] (up particles first). Returns the new paths
-    and, if asked, the decision margins |u - R| of every proposal [n_passes, L_tau, particles]
-    (a proposal whose margin is at round-off level is a near-tie).
+    aux [L_tau, N] field, paths [L_tau, n_particles] (up particles first), perm [n_particles]
+    the reconnection at tau = beta (None: the identity). Returns the new paths and, if asked,
+    the decision margins |u - R| of every proposal [n_passes, L_tau, particles] (a proposal
+    whose margin is at round-off level is a near-tie).
     """
     L, L_tau, N = desc.L, desc.L_tau, desc.L * desc.L
     Gm = lattice.transfer_matrix(L, desc.t, desc.dtau)       # Gm[r', r] = G(r' - r)
@@ -51,23 +55,30 @@ def local_update(desc, aux: np.ndarray, paths: np.ndarray, sweep: int, n_passes:
     P = desc.n_up + desc.n_dn
     parts = np.arange(P)
     spin = (parts >= desc.n_up).astype(np.int64)
+    nxt = parts if perm is None else np.asarray(perm, dtype=np.int64)
+    prv = np.empty(P, dtype=np.int64)
+    prv[nxt] = parts                                          # slice -1 of p is slice L_tau-1 of prv[p]
     out = np.asarray(paths, dtype=np.int64).copy()
     margins = np.full((n_passes, L_tau, P), np.inf)
+
+    def visit(l, ps, r_prev, r_next):
+        x0, x1, _, _ = philox.draw_words(desc.seed, parts.astype(np.uint64), l, sweep,
+                                         TAG_LOCAL + 256 * ps)
+        e = (x1 >> np.uint64(62)).astype(np.int64)
+        u = philox.uniform(x0)
+        r = out[l].copy()
+        r_new = neighbour(r, e, L)
+        num = W[spin, l, r_new] * Gm[r_new, r_prev] * Gm[r_next, r_new]
+        den = W[spin, l, r] * Gm[r, r_prev] * Gm[r_next, r]
+        R = num / den
+        margins[ps, l] = np.abs(u - R)
+        out[l] = np.where(u < R, r_new, r)
+
     for ps in range(n_passes):
-        for l in range(L_tau):
-            x0, x1, _, _ = philox.draw_words(desc.seed, parts.astype(np.uint64), l, sweep,
-                                             TAG_LOCAL + 256 * ps)
-            e = (x1 >> np.uint64(62)).astype(np.int64)
-            u = philox.uniform(x0)
-            r = out[l]
-            r_prev = out[(l - 1) % L_tau]
-            r_next = out[(l + 1) % L_tau]
-            r_new = neighbour(r, e, L)
-            num = W[spin, l, r_new] * Gm[r_new, r_prev] * Gm[r_next, r_new]
-            den = W[spin, l, r] * Gm[r, r_prev] * Gm[r_next, r]
-            R = num / den
-            margins[ps, l] = np.abs(u - R)
-            out[l] = np.where(u < R, r_new, r)
+        for l in range(1, L_tau - 1):
+            visit(l, ps, out[l - 1], out[l + 1])
+        visit(0, ps, out[L_tau - 1, prv], out[1])
+        visit(L_tau - 1, ps, out[L_tau - 2], out[0, nxt])
     if return_margin:
         return out, margins
     return out
