@@ -46,7 +46,7 @@ def parse():
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--workload", default="32x32",
                     choices=["32x32", "uneven", "hirsch16", "grad", "small", "paper64", "paper32",
-                             "local", "measure", "mala"],
+                             "local", "measure", "mala", "perm"],
                     help="32x32: the headline workload; the others time the remaining "
                          "configurations (uneven batch, 16x16 Ising field, adjoint, 4x4 FP64) "
                          "and the paper's own shape (32x32, L_tau=1024, blocks of 64 or 32)")
@@ -228,6 +228,10 @@ def other_workload(args):
         descs = synth.config_32x32(4.0, 16)
         label = "local link updates (Sec. 3.5.1), 16 chains x 32x32 lattice, L_tau=160, " \
                 "512+512 worldlines, Gaussian field, 4 passes per step"
+    elif args.workload == "perm":
+        descs = synth.config_32x32(4.0, 16)
+        label = "FFBS sweep with random reconnections at tau=beta plus 2 passes of pair swaps " \
+                "(Sec. 3.5.6), 16 chains x 32x32 lattice, L_tau=160, 512+512 worldlines"
     else:
         descs = synth.config_gradient(8)
         label = "log Z_path and its gradient (field and t), 8 chains x 32x32, L_tau=128, " \
@@ -320,6 +324,32 @@ def other_workload(args):
         metric = "local link proposals/s (32x32, L_tau=160, 16 chains)"
         value = proposals * args.steps / (ms / 1e3)
         unit = "proposals/s"
+    elif args.workload == "perm":
+        rng = np.random.default_rng(2510)
+        S.set_permutation([np.concatenate([rng.permutation(d.n_up),
+                                           d.n_up + rng.permutation(d.n_dn)]) for d in descs])
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            for i in range(args.warmup):
+                S.sweep(A, P, i, 1, stream)
+                fhmc.fh_permutation_update(S.plan, P, i, 2, stream)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for i in range(args.steps):
+                A.copy_(A0, non_blocking=True)
+                P.copy_(P0, non_blocking=True)
+                S.sweep(A, P, args.warmup + i, 1, stream)
+                fhmc.fh_permutation_update(S.plan, P, args.warmup + i, 2, stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        metric = "site-slice updates/s with reconnections and pair swaps (32x32, L_tau=160, " \
+                 "16 chains)"
+        value = sites * args.steps / (ms / 1e3)
+        unit = "site-slice updates/s"
+        _, signs = S.permutation()
+        extra["sign_sum"] = int(np.sum(signs))
     else:
         time_sweeps(S, A, P, A0, P0, 0, args.warmup, stream)
         ms = time_sweeps(S, A, P, A0, P0, args.warmup, args.steps, stream)

@@ -138,10 +138,12 @@ int fh_backward_sample(fh_plan plan, int32_t* paths, uint64_t sweep, fh_stream s
 int fh_gibbs_aux(fh_plan plan, const int32_t* paths, void* aux, uint64_t sweep,
                  fh_stream stream);
 
-/* Local link updates (Sec. 3.5.1, eq. Rlocal, site basis): n_passes Metropolis passes over the
- * slices l = 0 .. L_tau-1 of every worldline in turn. Each proposes moving the worldline's site r
- * on slice l to a nearest neighbour r' (+x, -x, +y or -y, equally likely, periodic) with its sites
- * on slices l-1 (already updated in the pass) and l+1 fixed, and takes it iff u < R,
+/* Local link updates (Sec. 3.5.1, eq. Rlocal, site basis): n_passes Metropolis passes; a pass
+ * visits the interior slices l = 1 .. L_tau-2 of every worldline in turn, then slice 0 of every
+ * worldline, then slice L_tau-1 of every worldline (the end slices neighbour the worldlines the
+ * reconnection at tau = beta links to). Each visit proposes moving the worldline's site r on
+ * slice l to a nearest neighbour r' (+x, -x, +y or -y, equally likely, periodic) with its sites
+ * on slices l-1 and l+1 fixed (as updated so far), and takes it iff u < R,
  * R = W_l(r') G(r' - r_{l-1}) G(r_{l+1} - r') / [W_l(r) G(r - r_{l-1}) G(r_{l+1} - r)], in FP64.
  * Random numbers: Philox counter (particle, slice, sweep, 2 + 256*pass); the top two bits of
  * word 1 pick the direction, word 0 gives u. aux is read, paths updated in place. The filters of
@@ -149,6 +151,34 @@ int fh_gibbs_aux(fh_plan plan, const int32_t* paths, void* aux, uint64_t sweep,
  * n_passes = 0 does nothing; negative is FH_ERR_INVALID_ARG. */
 int fh_local_update(fh_plan plan, const void* aux, int32_t* paths, uint64_t sweep,
                     int32_t n_passes, fh_stream stream);
+
+/* Reconnections of the worldlines at tau = beta (eq. joint's sum over permutations; Sec. 3.5.6).
+ * The plan holds one permutation per spin of every chain: slice L_tau of worldline p is slice 0
+ * of worldline perm[p] (chain-local indices, up worldlines mapped onto up worldlines and down onto
+ * down), and a sign sgn(P_up) sgn(P_dn) per chain by which observables are reweighted (the
+ * sampled measure is |pi|). fh_init starts from the identity, sign +1. FFBS blocks that run past
+ * slice L_tau - 1 continue on the reconnected worldline (their end site is read from it and their
+ * interior slices from L_tau on are written to it); local updates link slice L_tau-1 of p to
+ * slice 0 of perm[p]. fh_logZ_grad and fh_mala_field are defined for worldlines that close on
+ * themselves and return FH_ERR_UNSUPPORTED once the permutation may differ from the identity. */
+
+/* Sets the permutation from a host array [particles] (packed like logZ: chain c's entries at its
+ * particle_offset) and recomputes the signs. FH_ERR_INVALID_ARG unless every chain's entries are
+ * a permutation of its worldlines that maps each spin onto itself. Synchronous. */
+int fh_set_permutation(fh_plan plan, const int32_t* perm);
+
+/* Copies the permutation (host array [particles], nullable) and the per-chain signs (host array
+ * [n_chains], nullable) out of the plan. Synchronous. */
+int fh_get_permutation(fh_plan plan, int32_t* perm, int32_t* sign);
+
+/* n_passes passes of pair swaps of the reconnections (Sec. 3.5.6): pass k pairs the worldlines of
+ * each spin as (p0 + o + 2i, p0 + o + 2i + 1), o = k mod 2 (p0 the spin's first worldline); a pair
+ * (p, q) trades perm[p] and perm[q] iff u < R, R the ratio of the two boundary hops after and
+ * before, G(r^{P(q)}_0 - r^p_{L-1}) G(r^{P(p)}_0 - r^q_{L-1}) / [G(r^{P(p)}_0 - r^p_{L-1})
+ * G(r^{P(q)}_0 - r^q_{L-1})] in FP64, u from the Philox counter (p, 0, sweep, 5 + 256 k). Every
+ * accepted swap flips the chain's sign. paths is read only. */
+int fh_permutation_update(fh_plan plan, const int32_t* paths, uint64_t sweep, int32_t n_passes,
+                          fh_stream stream);
 
 /* Equal-time observables of the worldlines `paths` (Sec. 4), per chain, averaged over the
  * slices: with S^z_j = (n_{j,up} - n_{j,dn}) / 2 (worldline counts per site),

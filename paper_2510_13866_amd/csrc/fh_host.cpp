@@ -132,7 +132,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.draw32_tasks, d.meas, d.mala,
+                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.draw32_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign,
                     d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -331,6 +331,9 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.fwdx_tasks, sizeof(DrawTask) * fwdx.size());
     if (e == hipSuccess) e = dalloc(&dv.draw32_tasks, sizeof(DrawTask) * draw32.size());
     if (e == hipSuccess) e = dalloc(&dv.gpart, sizeof(float) * (size_t)p->gpart_elems);
+    if (e == hipSuccess) e = dalloc(&dv.perm, sizeof(int32_t) * (size_t)part);
+    if (e == hipSuccess) e = dalloc(&dv.perm_inv, sizeof(int32_t) * (size_t)part);
+    if (e == hipSuccess) e = dalloc(&dv.sign, sizeof(int32_t) * (size_t)n_chains);
     if (e == hipSuccess) e = dalloc(&dv.status, sizeof(int32_t) * 2);
     if (e == hipSuccess) e = dalloc(&dv.sweep, sizeof(uint64_t));
     if (e == hipSuccess) e = hipMemcpy(dv.tables, p->tables.data(), sizeof(double) * p->tables.size(), hipMemcpyHostToDevice);
@@ -360,6 +363,16 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess && !fwd32.empty()) e = hipMemcpy(dv.fwd32_tasks, fwd32.data(), sizeof(PairTask) * fwd32.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !fwdx.empty()) e = hipMemcpy(dv.fwdx_tasks, fwdx.data(), sizeof(DrawTask) * fwdx.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !draw32.empty()) e = hipMemcpy(dv.draw32_tasks, draw32.data(), sizeof(DrawTask) * draw32.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {  // every worldline closes on itself; sign +1
+        std::vector<int32_t> id((size_t)part), one((size_t)n_chains, 1);
+        for (const ChainInfo& ci : p->chains)
+            for (int q = 0; q < ci.np; ++q) id[ci.part_off + q] = q;
+        e = hipMemcpy(dv.perm, id.data(), sizeof(int32_t) * id.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(dv.perm_inv, id.data(), sizeof(int32_t) * id.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(dv.sign, one.data(), sizeof(int32_t) * one.size(), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) {
         int32_t st[2] = {0, -1};
         e = hipMemcpy(dv.status, st, sizeof(st), hipMemcpyHostToDevice);
@@ -471,6 +484,62 @@ int fh_local_update(fh_plan p, const void* aux, int32_t* paths, uint64_t sweep, 
     return FH_OK;
 }
 
+int fh_set_permutation(fh_plan p, const int32_t* perm) {
+    if (!p || !perm) return FH_ERR_INVALID_ARG;
+    std::vector<int32_t> h((size_t)p->particles), inv((size_t)p->particles), sg(p->n_chains);
+    bool identity = true;
+    for (int c = 0; c < p->n_chains; ++c) {
+        const ChainInfo& ci = p->chains[c];
+        std::vector<char> seen(ci.np, 0);
+        int cycles = 0;
+        for (int q = 0; q < ci.np; ++q) {
+            const int32_t v = perm[ci.part_off + q];
+            const bool same_spin = (q < ci.n_up) == (v >= 0 && v < ci.n_up);
+            if (v < 0 || v >= ci.np || !same_spin || seen[v]) return FH_ERR_INVALID_ARG;
+            seen[v] = 1;
+            h[ci.part_off + q] = v;
+            inv[ci.part_off + v] = q;
+            identity = identity && v == q;
+        }
+        std::vector<char> done(ci.np, 0);
+        for (int q = 0; q < ci.np; ++q)
+            if (!done[q]) {
+                ++cycles;
+                for (int r = q; !done[r]; r = h[ci.part_off + r]) done[r] = 1;
+            }
+        sg[c] = ((ci.np - cycles) % 2 == 0) ? 1 : -1;
+    }
+    FH_TRY(hipDeviceSynchronize());
+    FH_TRY(hipMemcpy(p->d.perm, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice));
+    FH_TRY(hipMemcpy(p->d.perm_inv, inv.data(), sizeof(int32_t) * inv.size(), hipMemcpyHostToDevice));
+    FH_TRY(hipMemcpy(p->d.sign, sg.data(), sizeof(int32_t) * sg.size(), hipMemcpyHostToDevice));
+    p->perm_identity = identity;
+    p->have_filters = false;
+    return FH_OK;
+}
+
+int fh_get_permutation(fh_plan p, int32_t* perm, int32_t* sign) {
+    if (!p) return FH_ERR_INVALID_ARG;
+    FH_TRY(hipDeviceSynchronize());
+    if (perm)
+        FH_TRY(hipMemcpy(perm, p->d.perm, sizeof(int32_t) * (size_t)p->particles, hipMemcpyDeviceToHost));
+    if (sign)
+        FH_TRY(hipMemcpy(sign, p->d.sign, sizeof(int32_t) * (size_t)p->n_chains, hipMemcpyDeviceToHost));
+    return FH_OK;
+}
+
+int fh_permutation_update(fh_plan p, const int32_t* paths, uint64_t sweep, int32_t n_passes,
+                          fh_stream stream) {
+    if (!p || !paths || n_passes < 0) return FH_ERR_INVALID_ARG;
+    if (n_passes == 0) return FH_OK;
+    hipStream_t s = (hipStream_t)stream;
+    FH_TRY(launch_set_sweep(p, sweep, s));
+    FH_TRY(launch_perm_update(p, paths, n_passes, s));
+    p->perm_identity = false;
+    p->have_filters = false;
+    return FH_OK;
+}
+
 int fh_measure(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* D, double* S2,
                fh_stream stream) {
     if (!p || !paths) return FH_ERR_INVALID_ARG;
@@ -559,6 +628,7 @@ static hipError_t enqueue_logz_grad(fh_plan p, const void* aux, const int32_t* p
 int fh_logZ_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor_slice,
                  double* logZ, void* grad_aux, double* grad_t, fh_stream stream) {
     if (!p || !aux || !paths) return FH_ERR_INVALID_ARG;
+    if (!p->perm_identity) return FH_ERR_UNSUPPORTED;  // defined for self-closed worldlines
     for (const ChainInfo& c : p->chains)
         if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
     FH_TRY(enqueue_logz_grad(p, aux, paths, anchor_slice, logZ, grad_aux, grad_t,
@@ -571,6 +641,7 @@ int fh_logZ_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t ancho
 int fh_mala_field(fh_plan p, void* aux, const int32_t* paths, int32_t anchor_slice, double eps,
                   uint64_t sweep, int32_t* accepted, fh_stream stream) {
     if (!p || !aux || !paths || !(eps > 0.0) || !is_fin(eps)) return FH_ERR_INVALID_ARG;
+    if (!p->perm_identity) return FH_ERR_UNSUPPORTED;  // Z_path of self-closed worldlines
     for (const ChainInfo& c : p->chains)
         if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;

@@ -90,6 +90,11 @@ struct Device {
                               // precision, then log Z_path at both fields [2][n_chains] f64
     double* meas = nullptr;   // fh_measure per-slice rows: S(k) [aux_elems], C(r) [aux_elems],
                               // then the (n_up n_dn, (n_up - n_dn)^2) site sums [slices][2]
+    int32_t* perm = nullptr;     // [particles] reconnection at tau = beta: slice L_tau of
+                                 // worldline p is slice 0 of worldline perm[part_off + p]
+                                 // (chain-local indices); the identity unless changed
+    int32_t* perm_inv = nullptr; // [particles] its inverse
+    int32_t* sign = nullptr;     // [n_chains] sgn(P_up) sgn(P_dn), +1 or -1
     int32_t* status = nullptr;   // [0] first error code, [1] its chain
     uint64_t* sweep = nullptr;   // sweep index read by the kernels
 };
@@ -112,6 +117,7 @@ struct fh_plan_s {
     int32_t max_N_x = 0;  // largest N among the chains with L != 32
     int64_t gpart_elems = 0;
     int64_t total_sites = 0;  // sum of N over the chains
+    bool perm_identity = true;  // false once a permutation other than the identity may be set
     int32_t max_N = 0, max_L = 0, max_np = 0;
     size_t real_size = 8;
     std::vector<fh::TuneRecord> tune_log;  // FH_FLAG_AUTOTUNE timings, in the order taken
@@ -145,6 +151,7 @@ hipError_t tune_radix_plan(fh_plan p, int L, const double* tw_dev, hipStream_t s
                            RadixPlan* best, std::vector<TuneRecord>* log);
 hipError_t launch_gibbs(fh_plan p, const int32_t* paths, void* aux, hipStream_t s);
 hipError_t launch_local(fh_plan p, const void* aux, int32_t* paths, int n_passes, hipStream_t s);
+hipError_t launch_perm_update(fh_plan p, const int32_t* paths, int n_passes, hipStream_t s);
 hipError_t launch_measure(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* D,
                           double* S2, hipStream_t s);
 hipError_t launch_mala_propose(fh_plan p, const void* aux, const void* dlogz, void* prop,

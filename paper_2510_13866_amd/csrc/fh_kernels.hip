@@ -215,6 +215,10 @@ __device__ void forward_pass(const ChainInfo& c, const double* tables, const T* 
         }
     }
     block_sum<2>(z, l.red);
+    // an end site deeper in the filter's tail than the FFT resolves (~eps * max) can leave a
+    // non-positive end weight: report it instead of returning log of it
+    if ((!(z[0] > 0.0) || (has_b && !(z[1] > 0.0))) && threadIdx.x == 0)
+        set_status(status, FH_ERR_NONFINITE, chain);
     *logz_a = la + log(z[0]);
     *logz_b = has_b ? lb + log(z[1]) : 0.0;
 }
@@ -295,8 +299,9 @@ __global__ __launch_bounds__(kThreads) void k_forward_fft(
     const ChainInfo* __restrict__ chains, const PairTask* __restrict__ tasks,
     const double* __restrict__ tables, const T* __restrict__ aux, const T* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
-    const int32_t* __restrict__ paths, T* __restrict__ filt, double* __restrict__ blk_logz,
-    const uint64_t* __restrict__ sweep_ptr, int32_t* status, int maxN, int maxL) {
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, T* __restrict__ filt,
+    double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
+    int maxN, int maxL) {
     extern __shared__ __align__(16) unsigned char smem[];
     FftLds<T> l = carve<T>(smem, maxN, maxL, false);
     const PairTask t = tasks[blockIdx.x];
@@ -309,10 +314,14 @@ __global__ __launch_bounds__(kThreads) void k_forward_fft(
     const double* shift = wshift + spin * total_slices + c.slice_off;
     const int end = (start + len) % c.L_tau;
     const int32_t* pc = paths + c.path_off;
+    // a block that runs past slice L_tau - 1 ends on the worldline its owner reconnects to
+    const bool wraps = start + len >= c.L_tau;
+    const int qa = wraps ? perm[c.part_off + t.p_a] : t.p_a;
+    const int qb = has_b ? (wraps ? perm[c.part_off + t.p_b] : t.p_b) : 0;
     const int a_a = checked_site(pc[(int64_t)start * c.np + t.p_a], c.N, status, t.chain);
-    const int e_a = checked_site(pc[(int64_t)end * c.np + t.p_a], c.N, status, t.chain);
+    const int e_a = checked_site(pc[(int64_t)end * c.np + qa], c.N, status, t.chain);
     const int a_b = has_b ? checked_site(pc[(int64_t)start * c.np + t.p_b], c.N, status, t.chain) : 0;
-    const int e_b = has_b ? checked_site(pc[(int64_t)end * c.np + t.p_b], c.N, status, t.chain) : 0;
+    const int e_b = has_b ? checked_site(pc[(int64_t)end * c.np + qb], c.N, status, t.chain) : 0;
     load_chain_tables(c, tables, l);
     const int64_t rowbase = (int64_t)t.block * (c.B - 1);
     T* row_a = filt + c.filt_off + ((int64_t)t.p_a * c.L_tau + rowbase) * c.N;
@@ -349,7 +358,7 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_backward(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
-    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    const int32_t* __restrict__ perm, const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int task = blockIdx.x * kWaves + wv;
     if (task >= n_tasks) return;  // whole wavefront leaves; no block-level barrier below
@@ -362,7 +371,9 @@ __global__ __launch_bounds__(kThreads) void k_backward(
     const int N = c.N, L = c.L;
     const double* __restrict__ g = tables + tab_g(c);
     int32_t* pc = paths + c.path_off;
-    int cur = checked_site(pc[(int64_t)((start + len) % c.L_tau) * c.np + t.p], N, status, t.chain);
+    const int qn = perm[c.part_off + t.p];  // the worldline slices >= L_tau belong to
+    int cur = checked_site(pc[(int64_t)((start + len) % c.L_tau) * c.np +
+                              (start + len >= c.L_tau ? qn : t.p)], N, status, t.chain);
     const int E = (N + 63) / 64;
     const int i0 = lane * E;
     const int i1 = min(i0 + E, N);
@@ -417,7 +428,7 @@ __global__ __launch_bounds__(kThreads) void k_backward(
             chosen = first != 0x7fffffff ? first : lastpos;
             if (chosen < 0) chosen = cur;
         }
-        if (lane == 0) pc[(int64_t)l * c.np + t.p] = chosen;
+        if (lane == 0) pc[(int64_t)l * c.np + (start + j >= c.L_tau ? qn : t.p)] = chosen;
         cur = chosen;
     }
 }
@@ -459,14 +470,17 @@ __device__ inline double wave_incl_scan_f64(double v, int lane, double* total) {
 template <typename T, bool VEC, int LFIX, int E>
 __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const double* g,
                               const T* __restrict__ filt, int32_t* __restrict__ paths,
-                              uint64_t sweep, int32_t* status, int lane) {
+                              const int32_t* __restrict__ perm, uint64_t sweep, int32_t* status,
+                              int lane) {
     constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;  // rows in flight ahead of the current one
     int start, len;
     block_of(c, sweep, t.block, &start, &len);
     if (len < 2) return;
     const int L = LFIX ? LFIX : c.L, N = LFIX ? LFIX * LFIX : c.N, L_tau = c.L_tau;
     int32_t* pc = paths + c.path_off;
-    int cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np + t.p], N, status, t.chain);
+    const int qn = perm[c.part_off + t.p];  // the worldline slices >= L_tau belong to
+    int cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np +
+                              (start + len >= L_tau ? qn : t.p)], N, status, t.chain);
     const int per = LFIX ? (LFIX * LFIX) / 64 : (N + 63) / 64;  // sites per lane (<= E)
     const int i0 = lane * per;
     const int cnt = LFIX ? per : max(0, min(per, N - i0));
@@ -580,7 +594,8 @@ __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const doubl
                 if (has) chosen = __builtin_amdgcn_readlane(lastpos, 63 - __clzll((long long)has));
             }
         }
-        if (lane == 0) pc[(int64_t)((start + j) % L_tau) * c.np + t.p] = chosen;
+        if (lane == 0)
+            pc[(int64_t)((start + j) % L_tau) * c.np + (start + j >= L_tau ? qn : t.p)] = chosen;
         cur = chosen;
     }
 }
@@ -604,7 +619,7 @@ __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const doubl
 template <typename T>
 __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l32(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
-    const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
+    const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
     const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
     constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
     constexpr int NB = DEPTH + 1;
@@ -627,7 +642,9 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
     if (nd < 1) return;
     const int L_tau = c.L_tau;
     int32_t* pc = paths + c.path_off;
-    int cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np + t.p], 1024, status, t.chain);
+    const int qn = perm[c.part_off + t.p];  // the worldline slices >= L_tau belong to
+    int cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np +
+                              (start + len >= L_tau ? qn : t.p)], 1024, status, t.chain);
     const int x0 = 16 * (lane & 1), y0 = lane >> 1;
     const T* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * 1024 +
                     16 * lane;
@@ -710,7 +727,7 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
                 }
             }
             chosen = real ? chosen : cur;
-            pc[(int64_t)((start + j) % L_tau) * c.np + t.p] = chosen;
+            pc[(int64_t)((start + j) % L_tau) * c.np + (start + j >= L_tau ? qn : t.p)] = chosen;
             cur = chosen;
         }
     }
@@ -722,7 +739,7 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_backward_fast(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
-    const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
+    const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
     const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
     __shared__ double gsh[kWaves][kMaxL];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -739,46 +756,23 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
     const ChainInfo& c = chains[t.chain];
     const uint64_t sweep = *sweep_ptr;
     if (c.N <= 256)
-        backward_task<T, false, 0, 4>(t, c, gsh[wv], filt, paths, sweep, status, lane);
+        backward_task<T, false, 0, 4>(t, c, gsh[wv], filt, paths, perm, sweep, status, lane);
     else
-        backward_task<T, false, 0, 16>(t, c, gsh[wv], filt, paths, sweep, status, lane);
+        backward_task<T, false, 0, 16>(t, c, gsh[wv], filt, paths, perm, sweep, status, lane);
 }
 
 
-// Local link updates (Sec. 3.5.1, eq. Rlocal, site form). One thread per worldline runs
-// n_passes passes over its slices in order. The proposal moves the site r of slice l to a nearest
-// neighbour r' (top two bits of Philox word x1: +x, -x, +y, -y; periodic), the sites of slice
-// l - 1 (already updated in this pass) and slice l + 1 held fixed, and is taken iff u < R with
-//   R = exp(coef (aux_l(r') - aux_l(r))) G(r' - r_{l-1}) G(r_{l+1} - r') / [G(r - r_{l-1}) G(r_{l+1} - r)],
+// Local link updates (Sec. 3.5.1, eq. Rlocal, site form). A move proposes to take the site r of
+// slice l of a worldline to a nearest neighbour r' (top two bits of Philox word x1: +x, -x, +y,
+// -y; periodic) with the sites r_prev, r_next of the two adjacent slices fixed, and is taken iff
+// u < R with
+//   R = exp(coef (aux_l(r') - aux_l(r))) G(r' - r_prev) G(r_next - r') / [G(r - r_prev) G(r_next - r)],
 // G(d) = g(d_x) g(d_y), everything in FP64 (W_l(r')/W_l(r) written through the field). Counter
 // (particle, slice, sweep, kTagLocal + 256 pass); u from word x0.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_local(const ChainInfo* __restrict__ chains,
-                                                    int n_chains, int64_t particles,
-                                                    const double* __restrict__ tables,
-                                                    const T* __restrict__ aux,
-                                                    int32_t* __restrict__ paths,
-                                                    const uint64_t* __restrict__ sweep_ptr,
-                                                    int n_passes, int32_t* status) {
-    const int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (gp >= particles) return;
-    int lo = 0, hi = n_chains - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (chains[mid].part_off <= gp)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    const ChainInfo& c = chains[lo];
-    const int p = (int)(gp - c.part_off);
-    const int L = c.L, N = c.N, L_tau = c.L_tau;
-    const int64_t np = c.np;
-    const double* g = tables + tab_g(c);
-    const double coef = p >= c.n_up ? c.coef_dn : c.coef_up;
-    const T* ax = aux + c.aux_off;
-    int32_t* pc = paths + c.path_off + p;  // slice l of this worldline at pc[l * np]
-    const uint64_t sweep = *sweep_ptr;
+__device__ inline int local_move(const ChainInfo& c, const double* g, const T* ax, int l, int cur,
+                                 int prev, int next, double coef, int p, uint64_t sweep, int ps) {
+    const int L = c.L;
     auto G = [&](int a, int b) {  // G(a - b) on the periodic lattice
         int dx = a % L - b % L;
         dx += dx < 0 ? L : 0;
@@ -786,38 +780,135 @@ __global__ __launch_bounds__(kThreads) void k_local(const ChainInfo* __restrict_
         dy += dy < 0 ? L : 0;
         return g[dx] * g[dy];
     };
+    const u64x4 w = philox4x64_10((uint64_t)p, (uint64_t)l, sweep,
+                                  kTagLocal + 256ull * (uint64_t)ps, c.seed, 0);
+    const int e = (int)(w.x1 >> 62);
+    const double u = u01_from(w.x0);
+    const int x = cur % L, y = cur / L;
+    const int nx = e == 0 ? (x + 1 == L ? 0 : x + 1) : e == 1 ? (x == 0 ? L - 1 : x - 1) : x;
+    const int ny = e == 2 ? (y + 1 == L ? 0 : y + 1) : e == 3 ? (y == 0 ? L - 1 : y - 1) : y;
+    const int cand = nx + L * ny;
+    const double dA = (double)ax[(int64_t)l * c.N + cand] - (double)ax[(int64_t)l * c.N + cur];
+    const double R =
+        exp(coef * dA) * ((G(cand, prev) * G(next, cand)) / (G(cur, prev) * G(next, cur)));
+    return u < R ? cand : cur;
+}
+
+// One pass of local updates, in two launches (a pass visits the interior slices 1 .. L_tau-2 of
+// every worldline in turn, then slice 0 of every worldline, then slice L_tau-1 of every
+// worldline; the end slices neighbour the worldlines the reconnection at tau = beta links to).
+// PHASE 0: one thread per worldline runs its interior slices in order, then its slice 0, whose
+// previous slice is slice L_tau-1 of perm_inv[p] (not touched in this launch). PHASE 1: slice
+// L_tau-1 of every worldline, whose next slice is slice 0 of perm[p] (set by phase 0).
+template <typename T, int PHASE>
+__global__ __launch_bounds__(kThreads) void k_local(const ChainInfo* __restrict__ chains,
+                                                    int n_chains, int64_t particles,
+                                                    const double* __restrict__ tables,
+                                                    const T* __restrict__ aux,
+                                                    int32_t* __restrict__ paths,
+                                                    const int32_t* __restrict__ perm,
+                                                    const int32_t* __restrict__ perm_inv,
+                                                    const uint64_t* __restrict__ sweep_ptr,
+                                                    int ps, int32_t* status) {
+    const int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gp >= particles) return;
+    const int ci = find_chain(n_chains, gp, [&](int i) { return chains[i].part_off; });
+    const ChainInfo& c = chains[ci];
+    const int p = (int)(gp - c.part_off);
+    const int N = c.N, L_tau = c.L_tau;
+    const int64_t np = c.np;
+    const double* g = tables + tab_g(c);
+    const double coef = p >= c.n_up ? c.coef_dn : c.coef_up;
+    const T* ax = aux + c.aux_off;
+    int32_t* col = paths + c.path_off;  // slice l of worldline q at col[l * np + q]
+    const uint64_t sweep = *sweep_ptr;
     auto in_range = [&](int r) { return r >= 0 && r < N; };
-    for (int ps = 0; ps < n_passes; ++ps) {
-        int prev = pc[(int64_t)(L_tau - 1) * np];
-        int cur = pc[0];
-        int first = cur;
+    if (PHASE == 0) {
+        int prev = col[p];
+        int cur = col[np + p];
         if (!in_range(prev) || !in_range(cur)) {
-            set_status(status, FH_ERR_BAD_PATH, lo);
+            set_status(status, FH_ERR_BAD_PATH, ci);
             return;
         }
-        for (int l = 0; l < L_tau; ++l) {
-            const int next = l + 1 < L_tau ? pc[(int64_t)(l + 1) * np] : first;
+        for (int l = 1; l < L_tau - 1; ++l) {
+            const int next = col[(int64_t)(l + 1) * np + p];
             if (!in_range(next)) {
-                set_status(status, FH_ERR_BAD_PATH, lo);
+                set_status(status, FH_ERR_BAD_PATH, ci);
                 return;
             }
-            const u64x4 w = philox4x64_10((uint64_t)p, (uint64_t)l, sweep,
-                                          kTagLocal + 256ull * (uint64_t)ps, c.seed, 0);
-            const int e = (int)(w.x1 >> 62);
-            const double u = u01_from(w.x0);
-            const int x = cur % L, y = cur / L;
-            const int nx = e == 0 ? (x + 1 == L ? 0 : x + 1) : e == 1 ? (x == 0 ? L - 1 : x - 1) : x;
-            const int ny = e == 2 ? (y + 1 == L ? 0 : y + 1) : e == 3 ? (y == 0 ? L - 1 : y - 1) : y;
-            const int cand = nx + L * ny;
-            const double dA = (double)ax[(int64_t)l * N + cand] - (double)ax[(int64_t)l * N + cur];
-            const double R =
-                exp(coef * dA) * ((G(cand, prev) * G(next, cand)) / (G(cur, prev) * G(next, cur)));
-            const int taken = u < R ? cand : cur;
-            if (taken != cur) pc[(int64_t)l * np] = taken;
-            if (l == 0) first = taken;
+            const int taken = local_move(c, g, ax, l, cur, prev, next, coef, p, sweep, ps);
+            if (taken != cur) col[(int64_t)l * np + p] = taken;
             prev = taken;
             cur = next;
         }
+        const int prev0 = col[(int64_t)(L_tau - 1) * np + perm_inv[c.part_off + p]];
+        const int next0 = col[np + p];
+        const int cur0 = col[p];
+        if (!in_range(prev0)) {
+            set_status(status, FH_ERR_BAD_PATH, ci);
+            return;
+        }
+        const int taken = local_move(c, g, ax, 0, cur0, prev0, next0, coef, p, sweep, ps);
+        if (taken != cur0) col[p] = taken;
+    } else {
+        const int l = L_tau - 1;
+        const int prevL = col[(int64_t)(l - 1) * np + p];
+        const int nextL = col[perm[c.part_off + p]];
+        const int curL = col[(int64_t)l * np + p];
+        if (!in_range(prevL) || !in_range(nextL) || !in_range(curL)) {
+            set_status(status, FH_ERR_BAD_PATH, ci);
+            return;
+        }
+        const int taken = local_move(c, g, ax, l, curL, prevL, nextL, coef, p, sweep, ps);
+        if (taken != curL) col[(int64_t)l * np + p] = taken;
+    }
+}
+
+// Pair swaps of the reconnections at tau = beta (Sec. 3.5.6), one thread per worldline; the
+// first worldline p of each candidate pair of pass ps, (p0 + o + 2i, p0 + o + 2i + 1) within its
+// spin, o = ps mod 2, trades perm[p] and perm[q = p + 1] iff u < R,
+//   R = G(r^{P(q)}_0 - r^p_{L-1}) G(r^{P(p)}_0 - r^q_{L-1}) / [G(r^{P(p)}_0 - r^p_{L-1}) G(r^{P(q)}_0 - r^q_{L-1})]
+// (only the two boundary hops change), u from Philox (p, 0, sweep, kTagPerm + 256 ps). An accepted
+// swap flips the chain's sign (+1 <-> -1 by one atomic xor). The pairs of a pass are disjoint.
+__global__ __launch_bounds__(kThreads) void k_perm_update(
+    const ChainInfo* __restrict__ chains, int n_chains, int64_t particles,
+    const double* __restrict__ tables, const int32_t* __restrict__ paths, int32_t* perm,
+    int32_t* perm_inv, int32_t* sign, const uint64_t* __restrict__ sweep_ptr, int ps,
+    int32_t* status) {
+    const int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (gp >= particles) return;
+    const int ci = find_chain(n_chains, gp, [&](int i) { return chains[i].part_off; });
+    const ChainInfo& c = chains[ci];
+    const int p = (int)(gp - c.part_off);
+    const int p0 = p < c.n_up ? 0 : c.n_up, n = p < c.n_up ? c.n_up : c.n_dn;
+    const int k = p - p0 - (ps & 1);
+    if (k < 0 || (k & 1) || p + 1 >= p0 + n) return;
+    const int q = p + 1, L = c.L, N = c.N;
+    const double* g = tables + tab_g(c);
+    auto G = [&](int a, int b) {
+        int dx = a % L - b % L;
+        dx += dx < 0 ? L : 0;
+        int dy = a / L - b / L;
+        dy += dy < 0 ? L : 0;
+        return g[dx] * g[dy];
+    };
+    const int32_t* col = paths + c.path_off;
+    const int64_t last = (int64_t)(c.L_tau - 1) * c.np;
+    const int Pp = perm[c.part_off + p], Pq = perm[c.part_off + q];
+    const int lp = col[last + p], lq = col[last + q], fp = col[Pp], fq = col[Pq];
+    if (lp < 0 || lp >= N || lq < 0 || lq >= N || fp < 0 || fp >= N || fq < 0 || fq >= N) {
+        set_status(status, FH_ERR_BAD_PATH, ci);
+        return;
+    }
+    const double R = (G(fq, lp) * G(fp, lq)) / (G(fp, lp) * G(fq, lq));
+    const u64x4 w = philox4x64_10((uint64_t)p, 0, *sweep_ptr, kTagPerm + 256ull * (uint64_t)ps,
+                                  c.seed, 0);
+    if (u01_from(w.x0) < R) {
+        perm[c.part_off + p] = Pq;
+        perm[c.part_off + q] = Pp;
+        perm_inv[c.part_off + Pq] = p;
+        perm_inv[c.part_off + Pp] = q;
+        atomicXor(&sign[ci], (int32_t)0xFFFFFFFE);
     }
 }
 
@@ -1330,14 +1421,14 @@ hipError_t launch_forward(fh_plan p, const void* aux, const int32_t* paths, hipS
         hipLaunchKernelGGL(k_forward_fft<double>, dim3(p->n_fwd_tasks), dim3(kThreads), lds, s,
                            p->d.chains, p->d.fwd_tasks, p->d.tables, (const double*)aux,
                            (const double*)p->d.W,
-                           p->d.wshift, p->aux_elems, p->total_slices, paths, (double*)p->d.filt, p->d.blk_logz, p->d.sweep,
+                           p->d.wshift, p->aux_elems, p->total_slices, paths, p->d.perm, (double*)p->d.filt, p->d.blk_logz, p->d.sweep,
                            p->d.status, p->max_N, p->max_L);
     } else {
         if ((e = allow_lds(k_forward_fft<float>, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_forward_fft<float>, dim3(p->n_fwd_tasks), dim3(kThreads), lds, s,
                            p->d.chains, p->d.fwd_tasks, p->d.tables, (const float*)aux,
                            (const float*)p->d.W,
-                           p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep,
+                           p->d.wshift, p->aux_elems, p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep,
                            p->d.status, p->max_N, p->max_L);
     }
     return hipGetLastError();
@@ -1357,11 +1448,11 @@ hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
         if (p->precision == FH_FP64)
             hipLaunchKernelGGL(k_backward_l32<double>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draw32_tasks, p->n_draw32_tasks, p->d.tables,
-                               (const double*)p->d.filt, paths, p->d.sweep, p->d.status);
+                               (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status);
         else
             hipLaunchKernelGGL(k_backward_l32<float>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draw32_tasks, p->n_draw32_tasks, p->d.tables,
-                               (const float*)p->d.filt, paths, p->d.sweep, p->d.status);
+                               (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status);
     }
     if (p->n_fwdx_tasks == 0) return hipGetLastError();
     const unsigned blocks = (unsigned)((p->n_fwdx_tasks + kWaves - 1) / kWaves);
@@ -1371,35 +1462,55 @@ hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
         if (p->precision == FH_FP64)
             hipLaunchKernelGGL(k_backward_fast<double>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, tasks, n, p->d.tables, (const double*)p->d.filt, paths,
-                               p->d.sweep, p->d.status);
+                               p->d.perm, p->d.sweep, p->d.status);
         else
             hipLaunchKernelGGL(k_backward_fast<float>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, tasks, n, p->d.tables, (const float*)p->d.filt, paths,
-                               p->d.sweep, p->d.status);
+                               p->d.perm, p->d.sweep, p->d.status);
         return hipGetLastError();
     }
     if (p->precision == FH_FP64)
         hipLaunchKernelGGL(k_backward<double>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           tasks, n, p->d.tables, (const double*)p->d.filt, paths, p->d.sweep,
-                           p->d.status);
+                           tasks, n, p->d.tables, (const double*)p->d.filt, paths, p->d.perm,
+                           p->d.sweep, p->d.status);
     else
         hipLaunchKernelGGL(k_backward<float>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           tasks, n, p->d.tables, (const float*)p->d.filt, paths, p->d.sweep,
-                           p->d.status);
+                           tasks, n, p->d.tables, (const float*)p->d.filt, paths, p->d.perm,
+                           p->d.sweep, p->d.status);
     return hipGetLastError();
 }
 
-hipError_t launch_local(fh_plan p, const void* aux, int32_t* paths, int n_passes, hipStream_t s) {
+template <typename T>
+hipError_t launch_local_t(fh_plan p, const T* aux, int32_t* paths, int n_passes, hipStream_t s) {
     const unsigned blocks = (unsigned)((p->particles + kThreads - 1) / kThreads);
-    if (p->precision == FH_FP64)
-        hipLaunchKernelGGL(k_local<double>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           p->n_chains, p->particles, p->d.tables, (const double*)aux, paths,
-                           p->d.sweep, n_passes, p->d.status);
-    else
-        hipLaunchKernelGGL(k_local<float>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           p->n_chains, p->particles, p->d.tables, (const float*)aux, paths,
-                           p->d.sweep, n_passes, p->d.status);
-    return hipGetLastError();
+    for (int ps = 0; ps < n_passes; ++ps) {
+        hipLaunchKernelGGL((k_local<T, 0>), dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->n_chains, p->particles, p->d.tables, aux, paths, p->d.perm,
+                           p->d.perm_inv, p->d.sweep, ps, p->d.status);
+        hipLaunchKernelGGL((k_local<T, 1>), dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->n_chains, p->particles, p->d.tables, aux, paths, p->d.perm,
+                           p->d.perm_inv, p->d.sweep, ps, p->d.status);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_local(fh_plan p, const void* aux, int32_t* paths, int n_passes, hipStream_t s) {
+    if (p->precision == FH_FP64) return launch_local_t(p, (const double*)aux, paths, n_passes, s);
+    return launch_local_t(p, (const float*)aux, paths, n_passes, s);
+}
+
+hipError_t launch_perm_update(fh_plan p, const int32_t* paths, int n_passes, hipStream_t s) {
+    const unsigned blocks = (unsigned)((p->particles + kThreads - 1) / kThreads);
+    for (int ps = 0; ps < n_passes; ++ps) {
+        hipLaunchKernelGGL(k_perm_update, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->n_chains, p->particles, p->d.tables, paths, p->d.perm,
+                           p->d.perm_inv, p->d.sign, p->d.sweep, ps, p->d.status);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_measure(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* D,

@@ -137,8 +137,9 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
-    const int32_t* __restrict__ paths, float* __restrict__ filt, double* __restrict__ blk_logz,
-    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const NegPairs neg) {
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
+    double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
+    const NegPairs neg) {
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
@@ -153,7 +154,9 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     const double coef = spin ? c.coef_dn : c.coef_up;
     const int32_t* pc = paths + c.path_off;
     int a = pc[(int64_t)start * c.np + t.p];
-    int e = pc[(int64_t)((start + len) % L_tau) * c.np + t.p];
+    // a block that runs past slice L_tau - 1 ends on the worldline its owner reconnects to
+    const int qe = start + len >= L_tau ? perm[c.part_off + t.p] : t.p;
+    int e = pc[(int64_t)((start + len) % L_tau) * c.np + qe];
     if (a < 0 || a >= N || e < 0 || e >= N) {
         if (lane == 0) set_status(status, FH_ERR_BAD_PATH, t.chain);
         a = (a < 0 || a >= N) ? 0 : a;
@@ -242,7 +245,10 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
         if (v == ve) hv = H[v];
     hv = __shfl(hv, le, 64);
     la -= log(prod);
-    if (lane == 0) blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log((double)hv);
+    if (lane == 0) {
+        if (!(hv > 0.0f)) set_status(status, FH_ERR_NONFINITE, t.chain);  // end weight underflowed
+        blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log((double)hv);
+    }
 }
 
 // Two worldlines of the same (chain, spin, block) per wavefront: the W slice is shared and the
@@ -259,8 +265,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const ChainInfo* __restrict__ chains, const PairTask* __restrict__ tasks, int n_tasks,
     const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
-    const int32_t* __restrict__ paths, float* __restrict__ filt, double* __restrict__ blk_logz,
-    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const NegPairs neg) {
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
+    double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
+    const NegPairs neg) {
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
@@ -280,7 +287,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         a[k] = pc[(int64_t)start * c.np + pp[k]];
-        e[k] = pc[(int64_t)((start + len) % L_tau) * c.np + pp[k]];
+        const int qe = start + len >= L_tau ? perm[c.part_off + pp[k]] : pp[k];  // reconnection
+        e[k] = pc[(int64_t)((start + len) % L_tau) * c.np + qe];
         if (a[k] < 0 || a[k] >= N || e[k] < 0 || e[k] >= N) {
             if (lane == 0) set_status(status, FH_ERR_BAD_PATH, t.chain);
             a[k] = (a[k] < 0 || a[k] >= N) ? 0 : a[k];
@@ -403,6 +411,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     la0 -= log(prod0);
     la1 -= log(prod1);
     if (lane == 0) {
+        if (!(hv0 > 0.0f) || !(hv1 > 0.0f)) set_status(status, FH_ERR_NONFINITE, t.chain);
         blk_logz[c.blk_off + (int64_t)pp[0] * c.nb + t.block] = la0 + log((double)hv0);
         if (has_b) blk_logz[c.blk_off + (int64_t)pp[1] * c.nb + t.block] = la1 + log((double)hv1);
     }
@@ -516,7 +525,10 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
             if (v == ve) hv = H[v];
         hv = __shfl(hv, ax + 32 * ((ay >> 2) & 1), 64);
         la -= log(prod);
-        if (real && lane == 0) blk_logz[c.blk_off + (int64_t)p * c.nb] = la + log((double)hv);
+        if (real && lane == 0) {
+            if (!(hv > 0.0f)) set_status(status, FH_ERR_NONFINITE, g.chain);
+            blk_logz[c.blk_off + (int64_t)p * c.nb] = la + log((double)hv);
+        }
     }
     __syncthreads();  // every row of the group is stored before any wavefront reads one back
     // ---- backward messages
@@ -628,7 +640,8 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
         hipLaunchKernelGGL(k_forward_mfma2<32>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwd32_tasks, p->n_fwd32_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
-                           paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status, kNegPairs);
+                           paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
+                           kNegPairs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -637,7 +650,8 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
         hipLaunchKernelGGL(k_forward_mfma<0>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwdx_tasks, p->n_fwdx_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
-                           paths, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status, kNegPairs);
+                           paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
+                           kNegPairs);
     }
     return hipGetLastError();
 }

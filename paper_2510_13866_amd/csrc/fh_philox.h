@@ -20,6 +20,7 @@ constexpr uint64_t kTagGibbs = 1;
 constexpr uint64_t kTagLocal = 2;  // local link updates; pass k uses kTagLocal + 256 k
 constexpr uint64_t kTagMala = 3;        // MALA proposal noise per (site, slice)
 constexpr uint64_t kTagMalaAccept = 4;  // MALA acceptance uniform per chain
+constexpr uint64_t kTagPerm = 5;        // reconnection swaps; pass k uses kTagPerm + 256 k
 
 FH_HD inline uint64_t mulhi64(uint64_t a, uint64_t b) {
 #if defined(__HIP_DEVICE_COMPILE__)

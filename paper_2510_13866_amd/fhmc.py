@@ -67,6 +67,9 @@ _sig("fh_backward_sample", c_int32, c_void_p, c_void_p, c_uint64, c_void_p)
 _sig("fh_gibbs_aux", c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_void_p)
 _sig("fh_sweep", c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_int32, c_void_p)
 _sig("fh_local_update", c_int32, c_void_p, c_void_p, c_void_p, c_uint64, c_int32, c_void_p)
+_sig("fh_set_permutation", c_int32, c_void_p, POINTER(c_int32))
+_sig("fh_get_permutation", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32))
+_sig("fh_permutation_update", c_int32, c_void_p, c_void_p, c_uint64, c_int32, c_void_p)
 _sig("fh_measure", c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
 _sig("fh_mala_field", c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_uint64, c_void_p,
      c_void_p)
@@ -200,6 +203,25 @@ def fh_local_update(plan, aux, paths, sweep, n_passes, stream=None):
 def fh_measure(plan, paths, Sk=None, Cr=None, D=None, S2=None, stream=None):
     _check(lib.fh_measure(plan, _ptr(paths), _ptr(Sk), _ptr(Cr), _ptr(D), _ptr(S2),
                           _stream(stream)), "fh_measure")
+
+
+def fh_set_permutation(plan, perm):
+    """perm: host sequence [particles] (chain-local indices, packed like logZ)."""
+    arr = (c_int32 * len(perm))(*[int(v) for v in perm])
+    _check(lib.fh_set_permutation(plan, arr), "fh_set_permutation")
+
+
+def fh_get_permutation(plan, particles, n_chains):
+    """(perm list [particles], sign list [n_chains])."""
+    perm = (c_int32 * particles)()
+    sign = (c_int32 * n_chains)()
+    _check(lib.fh_get_permutation(plan, perm, sign), "fh_get_permutation")
+    return list(perm), list(sign)
+
+
+def fh_permutation_update(plan, paths, sweep, n_passes, stream=None):
+    _check(lib.fh_permutation_update(plan, _ptr(paths), int(sweep), int(n_passes),
+                                     _stream(stream)), "fh_permutation_update")
 
 
 def fh_mala_field(plan, aux, paths, anchor_slice, eps, sweep, accepted=None, stream=None):

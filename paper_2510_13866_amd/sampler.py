@@ -86,6 +86,21 @@ class Sampler:
     def local_update(self, aux, paths, sweep, n_passes=1, stream=None):
         fhmc.fh_local_update(self.plan, aux, paths, sweep, n_passes, stream)
 
+    def set_permutation(self, per_chain: Sequence[np.ndarray]):
+        """Reconnections at tau = beta, one chain-local permutation per chain."""
+        fhmc.fh_set_permutation(self.plan, np.concatenate([np.asarray(q).ravel()
+                                                           for q in per_chain]))
+
+    def permutation(self):
+        """(per-chain permutations, per-chain signs)."""
+        perm, sign = fhmc.fh_get_permutation(self.plan, self.n_particles, len(self.descs))
+        perm = np.asarray(perm)
+        return [perm[l["particle_offset"]:l["particle_offset"] + l["n_particles"]]
+                for l in self.layouts], np.asarray(sign)
+
+    def permutation_update(self, paths, sweep, n_passes=1, stream=None):
+        fhmc.fh_permutation_update(self.plan, paths, sweep, n_passes, stream)
+
     def measure(self, paths, stream=None):
         """Per-chain (S(k) [N], C(r) [N], D, local moment) of the worldlines, as numpy arrays."""
         total = sum(lay["N"] for lay in self.layouts)

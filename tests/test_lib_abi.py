@@ -35,6 +35,13 @@ def test_every_declared_symbol_is_exported(fhmc):
         assert hasattr(fhmc.lib, n), n
 
 
+def test_library_resolves_every_symbol_at_load(fhmc):
+    """Loading with immediate binding fails on any symbol the library uses but does not define
+    (a shared library links without them)."""
+    lib = ctypes.CDLL(fhmc._LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)
+    assert lib.fh_strerror is not None
+
+
 def test_struct_sizes_match_header(fhmc):
     assert ctypes.sizeof(fhmc.fh_chain_desc) == 56
     assert ctypes.sizeof(fhmc.fh_chain_layout) == 56
