@@ -332,6 +332,8 @@ def other_workload(args):
         e1 = torch.cuda.Event(enable_timing=True)
         with torch.cuda.stream(stream):
             for i in range(args.warmup):
+                A.copy_(A0, non_blocking=True)
+                P.copy_(P0, non_blocking=True)
                 S.sweep(A, P, i, 1, stream)
                 fhmc.fh_permutation_update(S.plan, P, i, 2, stream)
             torch.cuda.synchronize()

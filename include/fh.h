@@ -3,8 +3,9 @@
  *
  * The library samples the joint measure of fermion worldlines and Hubbard-Stratonovich (HS)
  * fields of the determinant-free auxiliary-variable MCMC of Kong, Feng, Xie and Wu
- * ("FFT-Accelerated Auxiliary Variable MCMC for Fermionic Lattice Models", eq. joint, with every
- * permutation fixed to the identity). One sweep redraws every worldline block by forward
+ * ("FFT-Accelerated Auxiliary Variable MCMC for Fermionic Lattice Models", eq. joint). The
+ * worldlines close on themselves unless a permutation is set (fh_set_permutation: reconnections at
+ * tau = beta with sign, Sec. 3.5.6). One sweep redraws every worldline block by forward
  * filtering / backward sampling (Sec. 3.5.2) and then every field value from its exact
  * conditional (Sec. 3.5.4 / 3.5.5).
  *
@@ -13,7 +14,8 @@
  *  - Worldlines are held in the site basis: paths[l][p] is the site of particle p on imaginary
  *    time slice l (0 <= l < L_tau); particles 0..n_up-1 are spin up, n_up..n_up+n_dn-1 spin down.
  *    A path weighs prod_l W_{l,spin}(r_l) G(r_{l+1} - r_l), G the real-space hopping kernel
- *    (inverse Fourier transform of exp(-dtau eps_k), eq. Tkk / Sec. 3.3), r_{L_tau} = r_0.
+ *    (inverse Fourier transform of exp(-dtau eps_k), eq. Tkk / Sec. 3.3), r_{L_tau} = r_0 of the
+ *    worldline it reconnects to (itself unless a permutation is set).
  *  - Fields: aux[l][i], Gaussian sigma (FH_HS_GAUSS, eq. gaussHS) or Ising s = +-1.0
  *    (FH_HS_HIRSCH, eq. hirsch). Site potentials: Gaussian W_up = W_dn = exp(a*sigma),
  *    a = sqrt(|U| dtau); Ising W_up = exp(lambda*s), W_dn = exp(-lambda*s),
