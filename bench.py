@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-error", action="store_true", help="skip the error-vs-oracle sample")
+    ap.add_argument("--no-evolved", action="store_true",
+                    help="skip the backward timings on the state after one unrestored sweep")
+    ap.add_argument("--full-row-draw", action="store_true",
+                    help="backward draws scan whole filter rows (FH_FLAG_FULL_ROW_DRAW)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--workload", default="32x32",
@@ -63,9 +67,9 @@ def source_sha(name):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel, precision):
+def measured_traffic(kernel, precision, kernel_name):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel source; None otherwise."""
+    the same kernel and on the current kernel source; None otherwise."""
     src = KERNEL_SOURCES[kernel][precision]
     path = os.path.join(ROOT, "profiles", "hbm_traffic_%s_%s_32x32_Ltau160.md" % (kernel, precision))
     if not os.path.exists(path):
@@ -74,6 +78,8 @@ def measured_traffic(kernel, precision):
         if line.startswith("traffic_json:"):
             rec = json.loads(line[len("traffic_json:"):])
             if rec.get("source_sha256") != source_sha(src):
+                return None
+            if not rec.get("kernel", "").startswith(kernel_name):
                 return None
             return rec["fetch_bytes"] + rec["write_bytes"]
     return None
@@ -113,18 +119,18 @@ def time_forward(S, A, P, n, stream):
     return e0.elapsed_time(e1) / n
 
 
-def time_backward(S, A, P, n, stream):
+def time_backward(S, A, P, n, stream, sweep=2000):
     """Average duration of fh_backward_sample over n launches after one forward filter (the
     block endpoints do not change, so every launch redraws the same interiors)."""
     import torch
     from paper_2510_13866_amd import fhmc
-    fhmc.fh_forward_filter(S.plan, A, P, 2000, None, stream)
+    fhmc.fh_forward_filter(S.plan, A, P, sweep, None, stream)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
     for i in range(n):
-        fhmc.fh_backward_sample(S.plan, P, 2000, stream)
+        fhmc.fh_backward_sample(S.plan, P, sweep, stream)
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / n
@@ -400,7 +406,8 @@ def main():
 
     log("bench: %s, %d chains 32x32 L_tau=160, warmup %d, steps %d" %
         (args.precision, args.chains, args.warmup, args.steps))
-    S = Sampler(descs, prec, fhmc.FH_FLAG_GRAPH)
+    draw_flag = fhmc.FH_FLAG_FULL_ROW_DRAW if args.full_row_draw else 0
+    S = Sampler(descs, prec, fhmc.FH_FLAG_GRAPH | draw_flag)
     A0, P0 = S.pack_aux(aux), S.pack_paths(paths)
     A, P = A0.clone(), P0.clone()
     torch.cuda.synchronize()
@@ -416,24 +423,31 @@ def main():
     # the two hot kernels, each timed alone on its stream; both move the spilled filters:
     # the forward filter writes every filter row once, the backward sampler reads it once
     nf = max(3, min(10, args.steps))
+    with torch.cuda.stream(stream):   # the state every timed sweep starts from
+        A.copy_(A0, non_blocking=True)
+        P.copy_(P0, non_blocking=True)
     fwd_ms = time_forward(S, A, P, nf, stream)
     bwd_ms = time_backward(S, A, P, nf, stream)
     rsz = 8 if args.precision == "fp64" else 4
     rows = sum(d.n_particles * (d.L_tau - 1) for d in descs)       # one block per worldline
     N = descs[0].N
     w_bytes = sum(2 * d.L_tau * d.N * rsz for d in descs)         # site potentials, both spins
+    # backward: the full-row kernel reads every filter row; the windowed one reads the 7 x 7
+    # window around the next slice's site (half-width 3 at dtau = 0.05), fallbacks aside
+    read_per_row = N * rsz if args.full_row_draw else 49 * rsz
     algo = {"forward": rows * N * rsz + w_bytes,
-            "backward": rows * (N * rsz + 4)}                      # + the drawn site (int32)
+            "backward": rows * (read_per_row + 4)}                 # + the drawn site (int32)
     times = {"forward": fwd_ms, "backward": bwd_ms}
     names = {"forward": "forward filter (%s)" % ("k_forward_mfma2" if args.precision == "fp32_mfma3"
                                                  else "k_forward_fft"),
-             "backward": "backward sampler (k_backward_l32)"}
+             "backward": "backward sampler (%s)" % ("k_backward_l32" if args.full_row_draw
+                                                    else "k_backward_win")}
     roofs = {}
     for k in ("forward", "backward"):
         gbs = algo[k] / (times[k] / 1e3) / 1e9
         roofs[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(k, args.precision),
+                    "traffic": measured_traffic(k, args.precision, names[k].split("(")[1][:-1]),
                     "kernel": names[k], "ms_per_launch": round(times[k], 4),
                     "algorithmic_bytes_per_launch": algo[k]}
         log("  %s %.3f ms/launch, %.0f GB/s algorithmic" % (names[k], times[k], gbs))
@@ -441,6 +455,26 @@ def main():
     roof = roofs[dominant]
 
     extra = {}
+    if not args.full_row_draw and not args.no_evolved:
+        # The windowed draws cost depends on the state: after one sweep left to run on (no
+        # restore), the fields have started to cluster and more draws need the wider window or
+        # the full row. Both backward kernels, timed on that same state.
+        with torch.cuda.stream(stream):
+            A.copy_(A0, non_blocking=True)
+            P.copy_(P0, non_blocking=True)
+            S.sweep(A, P, 5, 1, stream)
+        torch.cuda.synchronize()
+        S.status()   # FP32 filters may underflow on this state; only the timing is used
+        Sf = Sampler(descs, prec, fhmc.FH_FLAG_FULL_ROW_DRAW)
+        Ae, Pe = A.clone(), P.clone()
+        win_ms = time_backward(S, A.clone(), P.clone(), nf, stream, sweep=6)
+        full_ms = time_backward(Sf, Ae, Pe, nf, stream, sweep=6)
+        Sf.close()
+        S.status()
+        extra["backward_after_one_unrestored_sweep"] = {
+            "k_backward_win_ms": round(win_ms, 4), "k_backward_l32_ms": round(full_ms, 4)}
+        log("  after one unrestored sweep: k_backward_win %.3f ms, k_backward_l32 %.3f ms"
+            % (win_ms, full_ms))
     if not args.no_error:
         # fresh state so the sampled particles' oracle filters are cheap to rebuild
         A2, P2 = S.pack_aux(aux), S.pack_paths(paths)
@@ -487,7 +521,8 @@ def main():
         "config": {"workload": "FFBS sweep, %d chains x 32x32 lattice, L_tau=160, dtau=0.05, "
                                "U=%g, 512+512 worldlines, Gaussian field" % (args.chains, args.U),
                    "chains": args.chains, "L": 32, "L_tau": 160, "precision": args.precision,
-                   "graph": True},
+                   "graph": True,
+                   "backward_draw": "full row" if args.full_row_draw else "window"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "roofline_other_kernel": roofs["backward" if dominant == "forward" else "forward"],

@@ -74,9 +74,14 @@ enum fh_precision {
 enum fh_flags {
     FH_FLAG_NONE = 0,
     FH_FLAG_GRAPH = 1,   /* fh_sweep replays a captured hipGraph instead of eager launches     */
-    FH_FLAG_AUTOTUNE = 2 /* fh_init times every radix-2/3/4 stage order of each distinct L on
+    FH_FLAG_AUTOTUNE = 2, /* fh_init times every radix-2/3/4 stage order of each distinct L on
                             the device (FFT precisions) and keeps the fastest; without it the
                             default order (4s, then a 2, then 3s) is used                    */
+    FH_FLAG_FULL_ROW_DRAW = 4 /* backward draws scan every site of the filter row. Without it a
+                            chain whose hopping kernel decays fast enough draws from the window
+                            of sites within w <= 3 steps of the next slice's site and certifies
+                            that the draw equals the full-row one (else scans the row): the
+                            same draws, fewer bytes read                                      */
 };
 
 /* One chain. block_len: FFBS block length B (0 = L_tau, one block closing the ring);

@@ -10,6 +10,8 @@
 
 #include <stdint.h>
 
+#include "fh.h"
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -39,6 +41,31 @@ int fh_debug_kernel_table(int32_t L, double t, double dtau, double* out);
  * library's generator. out: host array of 4 uint64. */
 int fh_debug_philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1,
                     uint64_t* out);
+
+/* Window selection for backward draws from a kernel table g[0..L): writes the half-width w
+ * (1..3) and g_out, the bound on G(s - r) = g(dx) g(dy) over sites r outside the window of s.
+ * Returns 1 when w qualifies (window covers the lattice, or g_out <= 2^-20 max G), 0 when not
+ * (w = 3 with its true bound), FH_ERR_INVALID_ARG on bad input. */
+int fh_debug_window_select(const double* g, int32_t L, int32_t* w, double* g_out);
+
+/* One backward draw on the host with the windowed rule of the backward kernel: f is a filter row
+ * [L*L] (site x + L*y), s_site the next slice's site, u in [0, 1). Weights max(f, 0) g(dy) g(dx).
+ * *certified = 1 when the window's draw carried its certificate against the outside bound
+ * g_out, 2 when the wider second window (half-width 7, its bound computed from g) certified it,
+ * 0 when the draw was taken over the full row (first cumulative weight above u times the total,
+ * else the last positive weight). Returns FH_OK, FH_ERR_ZERO_WEIGHT, FH_ERR_NONFINITE or
+ * FH_ERR_INVALID_ARG. */
+int fh_debug_window_draw(int32_t L, int32_t w, const double* g, double g_out, const double* f,
+                         int32_t s_site, double u, int32_t* site, int32_t* certified);
+
+/* Device-plan test hooks (they synchronise the device):
+ *   fh_debug_inflate_window_bound multiplies every chain's outside bound by factor >= 1 (an
+ *   infinite factor sends every windowed draw through the full-row scan; a larger bound only
+ *   makes the certificate stricter, so draws stay exact);
+ *   fh_debug_backward_kernels reports how many backward tasks use the windowed kernel and how
+ *   many the full-row kernels. */
+int fh_debug_inflate_window_bound(fh_plan plan, double factor);
+int fh_debug_backward_kernels(fh_plan plan, int32_t* n_windowed, int32_t* n_full_row);
 
 #ifdef __cplusplus
 }

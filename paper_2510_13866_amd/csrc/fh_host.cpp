@@ -132,7 +132,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.draw32_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign,
+                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign,
                     d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -186,7 +186,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (!descs || n_chains < 1) return FH_ERR_INVALID_ARG;
     if (precision != FH_FP64 && precision != FH_FP32 && precision != FH_FP32_MFMA3)
         return FH_ERR_INVALID_ARG;
-    if (flags & ~(uint32_t)(FH_FLAG_GRAPH | FH_FLAG_AUTOTUNE)) return FH_ERR_INVALID_ARG;
+    if (flags & ~(uint32_t)(FH_FLAG_GRAPH | FH_FLAG_AUTOTUNE | FH_FLAG_FULL_ROW_DRAW))
+        return FH_ERR_INVALID_ARG;
     for (int c = 0; c < n_chains; ++c) {
         int v = validate(descs[c], precision);
         if (v != FH_OK) return v;
@@ -250,9 +251,14 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->total_slices = slices;
     p->tables.assign(tab, 0.0);
     p->cmat.assign((size_t)kCmatPerChain * n_chains, 0);
+    std::vector<char> windowed((size_t)n_chains, 0);
     for (int c = 0; c < n_chains; ++c) {
-        build_tables(descs[c], p->tables.data() + p->chains[c].tab_off);
-        build_cmat(descs[c].L, p->tables.data() + tab_g(p->chains[c]), p->cmat.data() + (size_t)kCmatPerChain * c);
+        ChainInfo& ci = p->chains[c];
+        build_tables(descs[c], p->tables.data() + ci.tab_off);
+        build_cmat(descs[c].L, p->tables.data() + tab_g(ci), p->cmat.data() + (size_t)kCmatPerChain * c);
+        windowed[c] = win_select(p->tables.data() + tab_g(ci), ci.L, &ci.win_w, &ci.win_gout) &&
+                      ci.L <= kWinMaxL && !(flags & FH_FLAG_FULL_ROW_DRAW);
+        ci.win_gout2 = win_bound_for(p->tables.data() + tab_g(ci), ci.L, kWin2W);
     }
 
     // Work lists, heaviest chains first so that the long tasks start early.
@@ -295,20 +301,25 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->n_grad_tasks = (int32_t)grad.size();
     p->n_draw_tasks = (int32_t)draw.size();
     std::vector<PairTask> fwd32;
-    std::vector<DrawTask> fwdx, draw32;
+    std::vector<DrawTask> fwdx, draw32, draww, drawx;
     for (const PairTask& t : fwd)
         if (p->chains[t.chain].L == 32) fwd32.push_back(t);
     for (const DrawTask& t : draw) {
-        if (p->chains[t.chain].L != 32) {
-            fwdx.push_back(t);
-            p->max_N_x = std::max(p->max_N_x, p->chains[t.chain].N);
-        } else {
+        if (p->chains[t.chain].L != 32) fwdx.push_back(t);
+        if (windowed[t.chain]) {
+            draww.push_back(t);
+        } else if (p->chains[t.chain].L == 32) {
             draw32.push_back(t);
+        } else {
+            drawx.push_back(t);
+            p->max_N_x = std::max(p->max_N_x, p->chains[t.chain].N);
         }
     }
     p->n_fwd32_tasks = (int32_t)fwd32.size();
     p->n_fwdx_tasks = (int32_t)fwdx.size();
     p->n_draw32_tasks = (int32_t)draw32.size();
+    p->n_draww_tasks = (int32_t)draww.size();
+    p->n_drawx_tasks = (int32_t)drawx.size();
     p->n_groups = (int32_t)groups.size();
     p->gpart_elems = precision == FH_FP32_MFMA3 ? gpart : 0;
 
@@ -330,6 +341,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.fwd32_tasks, sizeof(PairTask) * fwd32.size());
     if (e == hipSuccess) e = dalloc(&dv.fwdx_tasks, sizeof(DrawTask) * fwdx.size());
     if (e == hipSuccess) e = dalloc(&dv.draw32_tasks, sizeof(DrawTask) * draw32.size());
+    if (e == hipSuccess) e = dalloc(&dv.draww_tasks, sizeof(DrawTask) * draww.size());
+    if (e == hipSuccess) e = dalloc(&dv.drawx_tasks, sizeof(DrawTask) * drawx.size());
     if (e == hipSuccess) e = dalloc(&dv.gpart, sizeof(float) * (size_t)p->gpart_elems);
     if (e == hipSuccess) e = dalloc(&dv.perm, sizeof(int32_t) * (size_t)part);
     if (e == hipSuccess) e = dalloc(&dv.perm_inv, sizeof(int32_t) * (size_t)part);
@@ -363,6 +376,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess && !fwd32.empty()) e = hipMemcpy(dv.fwd32_tasks, fwd32.data(), sizeof(PairTask) * fwd32.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !fwdx.empty()) e = hipMemcpy(dv.fwdx_tasks, fwdx.data(), sizeof(DrawTask) * fwdx.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !draw32.empty()) e = hipMemcpy(dv.draw32_tasks, draw32.data(), sizeof(DrawTask) * draw32.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !draww.empty()) e = hipMemcpy(dv.draww_tasks, draww.data(), sizeof(DrawTask) * draww.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !drawx.empty()) e = hipMemcpy(dv.drawx_tasks, drawx.data(), sizeof(DrawTask) * drawx.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) {  // every worldline closes on itself; sign +1
         std::vector<int32_t> id((size_t)part), one((size_t)n_chains, 1);
         for (const ChainInfo& ci : p->chains)
@@ -671,11 +686,19 @@ int fh_set_hopping(fh_plan p, const double* t) {
         if (!is_fin(t[c]) || !(t[c] > 0)) return FH_ERR_INVALID_ARG;
     FH_TRY(hipDeviceSynchronize());
     for (int c = 0; c < p->n_chains; ++c) {
+        ChainInfo& ci = p->chains[c];
         p->descs[c].t = t[c];
-        build_tables(p->descs[c], p->tables.data() + p->chains[c].tab_off);
-        build_cmat(p->descs[c].L, p->tables.data() + tab_g(p->chains[c]),
+        build_tables(p->descs[c], p->tables.data() + ci.tab_off);
+        build_cmat(p->descs[c].L, p->tables.data() + tab_g(ci),
                    p->cmat.data() + (size_t)kCmatPerChain * c);
+        // the window keeps its width; its outside bound follows the new kernel
+        ci.win_gout = win_bound_for(p->tables.data() + tab_g(ci), ci.L, ci.win_w) *
+                      p->win_bound_scale;
+        ci.win_gout2 = win_bound_for(p->tables.data() + tab_g(ci), ci.L, kWin2W) *
+                       p->win_bound_scale;
     }
+    FH_TRY(hipMemcpy(p->d.chains, p->chains.data(), sizeof(ChainInfo) * p->n_chains,
+                     hipMemcpyHostToDevice));
     FH_TRY(hipMemcpy(p->d.tables, p->tables.data(), sizeof(double) * p->tables.size(),
                      hipMemcpyHostToDevice));
     FH_TRY(hipMemcpy(p->d.cmat, p->cmat.data(), sizeof(uint16_t) * p->cmat.size(),
@@ -790,6 +813,107 @@ int fh_debug_philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t
     out[1] = r.x1;
     out[2] = r.x2;
     out[3] = r.x3;
+    return FH_OK;
+}
+
+int fh_debug_window_select(const double* g, int32_t L, int32_t* w, double* g_out) {
+    if (!g || !w || !g_out || L < 2 || L > kMaxL) return FH_ERR_INVALID_ARG;
+    int ww = 0;
+    double go = 0.0;
+    const bool ok = win_select(g, L, &ww, &go);
+    *w = ww;
+    *g_out = go;
+    return ok ? 1 : 0;
+}
+
+int fh_debug_window_draw(int32_t L, int32_t w, const double* g, double g_out, const double* f,
+                         int32_t s_site, double u, int32_t* site, int32_t* certified) {
+    if (!g || !f || !site || !certified || L < 2 || L > kMaxL || w < 1 || w > kWinMaxW ||
+        s_site < 0 || s_site >= L * L || !(u >= 0.0 && u < 1.0) || !(g_out >= 0.0))
+        return FH_ERR_INVALID_ARG;
+    const int N = L * L;
+    const int cx = s_site % L, cy = s_site / L;
+    auto wt = [&](int x, int y) {
+        int dx = cx - x, dy = cy - y;
+        dx += dx < 0 ? L : 0;
+        dy += dy < 0 ? L : 0;
+        const double fi = f[x + L * y];
+        return (fi > 0.0 ? fi : 0.0) * (g[dy] * g[dx]);
+    };
+    // a window of half-width ww: its cumulative weights in rank (= site) order, then the
+    // certificate against the outside bound go
+    auto try_window = [&](int ww, double go) {
+        const int WW = win_width(ww, L), nwin = WW * WW;
+        std::vector<double> P(nwin);
+        std::vector<int> xs(nwin), ys(nwin);
+        double acc = 0.0;
+        for (int q = 0; q < nwin; ++q) {
+            xs[q] = win_coord(q % WW, cx, ww, L, WW);
+            ys[q] = win_coord(q / WW, cy, ww, L, WW);
+            acc += wt(xs[q], ys[q]);
+            P[q] = acc;
+        }
+        const double T_in = acc, tau = u * T_in;
+        if (!(T_in > 0.0) || !std::isfinite(T_in)) return -1;
+        int q = 0;
+        while (q < nwin && !(P[q] > tau)) ++q;
+        if (q < nwin && win_certified(q ? P[q - 1] : 0.0, P[q], tau,
+                                      go * kWinMassBound + kWinSlack * T_in))
+            return xs[q] + L * ys[q];
+        return -1;
+    };
+    int r = try_window(w, g_out);
+    if (r >= 0) {
+        *certified = 1;
+        *site = r;
+        return FH_OK;
+    }
+    r = try_window(kWin2W, win_bound_for(g, L, kWin2W));
+    if (r >= 0) {
+        *certified = 2;
+        *site = r;
+        return FH_OK;
+    }
+    *certified = 0;
+    // the full row in site order: first cumulative weight above u * total, else the last
+    // positive weight
+    double total = 0.0;
+    for (int i = 0; i < N; ++i) total += wt(i % L, i / L);
+    if (!std::isfinite(total)) return FH_ERR_NONFINITE;
+    if (!(total > 0.0)) return FH_ERR_ZERO_WEIGHT;
+    const double T = u * total;
+    double run = 0.0;
+    int last = -1;
+    for (int i = 0; i < N; ++i) {
+        const double wi = wt(i % L, i / L);
+        run += wi;
+        if (run > T) {
+            *site = i;
+            return FH_OK;
+        }
+        if (wi > 0.0) last = i;
+    }
+    *site = last;
+    return FH_OK;
+}
+
+int fh_debug_inflate_window_bound(fh_plan p, double factor) {
+    if (!p || !(factor >= 1.0)) return FH_ERR_INVALID_ARG;
+    FH_TRY(hipDeviceSynchronize());
+    p->win_bound_scale = factor;
+    for (ChainInfo& ci : p->chains) {
+        ci.win_gout = win_bound_for(p->tables.data() + tab_g(ci), ci.L, ci.win_w) * factor;
+        ci.win_gout2 = win_bound_for(p->tables.data() + tab_g(ci), ci.L, kWin2W) * factor;
+    }
+    FH_TRY(hipMemcpy(p->d.chains, p->chains.data(), sizeof(ChainInfo) * p->n_chains,
+                     hipMemcpyHostToDevice));
+    return FH_OK;
+}
+
+int fh_debug_backward_kernels(fh_plan p, int32_t* n_windowed, int32_t* n_full_row) {
+    if (!p || !n_windowed || !n_full_row) return FH_ERR_INVALID_ARG;
+    *n_windowed = p->n_draww_tasks;
+    *n_full_row = p->n_draw32_tasks + p->n_drawx_tasks;
     return FH_OK;
 }
 

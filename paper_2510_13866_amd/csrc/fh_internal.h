@@ -11,6 +11,7 @@
 
 #include "../../include/fh.h"
 #include "fh_fft.h"
+#include "fh_window.h"
 
 namespace fh {
 
@@ -30,6 +31,10 @@ struct ChainInfo {
     int64_t slice_off; // index of this chain's slice 0 among all chains' slices
     int64_t site_off;  // per-site outputs (S(k), C(r)) packed by chain: [site_off + r]
     int32_t g0, g1;    // gradient worldline groups of this chain: [g0, g1)
+    int32_t win_w;     // windowed backward draws: half-width w of the window around s
+    int32_t win_pad;
+    double win_gout;   // bound on G(s - r) over the sites r outside that window
+    double win_gout2;  // the same for the second window (half-width kWin2W)
 };
 
 // Offsets of the tables of one chain inside the double table buffer, relative to tab_off.
@@ -85,6 +90,8 @@ struct Device {
     PairTask* fwd32_tasks = nullptr;    // MFMA forward: worldline pairs of L = 32 chains
     DrawTask* fwdx_tasks = nullptr;     // single worldlines of the other chains (forward, backward)
     DrawTask* draw32_tasks = nullptr;   // backward: worldline blocks of L = 32 chains
+    DrawTask* draww_tasks = nullptr;    // backward, windowed draws (k_backward_win)
+    DrawTask* drawx_tasks = nullptr;    // backward: the remaining chains (any L)
     float* gpart = nullptr;   // MFMA adjoint: per-group partial field gradients
     void* mala = nullptr;     // fh_mala_field: proposal, two gradients [3][aux_elems] in plan
                               // precision, then log Z_path at both fields [2][n_chains] f64
@@ -114,7 +121,9 @@ struct fh_plan_s {
     int64_t total_slices = 0;
     int32_t n_groups = 0;
     int32_t n_fwd32_tasks = 0, n_fwdx_tasks = 0, n_draw32_tasks = 0;
-    int32_t max_N_x = 0;  // largest N among the chains with L != 32
+    int32_t max_N_x = 0;  // largest N among the chains of drawx_tasks
+    int32_t n_draww_tasks = 0, n_drawx_tasks = 0;
+    double win_bound_scale = 1.0;  // test hook: >= 1 inflates every window bound
     int64_t gpart_elems = 0;
     int64_t total_sites = 0;  // sum of N over the chains
     bool perm_identity = true;  // false once a permutation other than the identity may be set

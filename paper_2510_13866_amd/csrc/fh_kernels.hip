@@ -734,6 +734,412 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
     if (err != 0 && lane == 0) set_status(status, err, t.chain);  // the block's first error
 }
 
+// Full-row draw of one 16-lane group (the draw rule of k_backward: the first site in site order
+// whose cumulative weight exceeds u times the total, else the last site with a positive weight).
+// Lane li owns the M contiguous sites from li M. Weights max(f, 0) g(dy) g(dx) about (cx, cy).
+// On a zero or non-finite total the current site is kept and *err records the first error.
+__device__ inline double group_scan_incl(double v) {  // inclusive scan within a DPP row of 16
+    v += dpp_f64<0x111>(v);
+    v += dpp_f64<0x112>(v);
+    v += dpp_f64<0x114>(v);
+    v += dpp_f64<0x118>(v);
+    return v;
+}
+
+// Rows of up to 1024 sites (M <= 64): up to eight chunks of 8 sites per lane, the loads of a
+// chunk issued together; the chunk sums stay in registers so that the crossing is re-scanned in
+// one chunk only.
+template <typename T>
+__device__ int row_draw_chunked(const T* __restrict__ row, int N, int L, int M, int li, int gbase,
+                                int cx, int cy, const double* g, double u, int cur, int* err) {
+    constexpr int C = 8;
+    const int i0 = li * M;
+    const int cnt = max(0, min(M, N - i0));
+    const int nch = (cnt + C - 1) / C;
+    int x = i0 % L, y = i0 / L;
+    int dy = cy - y;
+    dy += dy < 0 ? L : 0;
+    double gy = g[dy];
+    double cs[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int lastpos = -1;
+#pragma unroll 1
+    for (int ch = 0; ch < nch; ++ch) {
+        T v[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) v[k] = row[min(i0 + ch * C + k, N - 1)];
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int m = ch * C + k;
+            if (m < cnt) {
+                int dx = cx - x;
+                dx += dx < 0 ? L : 0;
+                const double fm = (double)v[k];
+                const double wm = (fm > 0.0 ? fm : 0.0) * (gy * g[dx]);
+                sum += wm;
+                if (wm > 0.0) lastpos = i0 + m;
+                if (++x == L) {
+                    x = 0;
+                    ++y;
+                    dy = cy - y;
+                    dy += dy < 0 ? L : 0;
+                    gy = g[dy < L ? dy : 0];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cs[q] = ch == q ? sum : cs[q];  // static register indices
+    }
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) tot += cs[q];
+    const double incl = group_scan_incl(tot);
+    const double excl = dpp_f64<0x111>(incl);
+    const double total = __shfl(incl, gbase + 15, 64);
+    if (!(total > 0.0) || !isfinite(total)) {
+        if (*err == 0) *err = isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE;
+        return cur;
+    }
+    const double Tq = u * total;
+    const uint32_t fm = (uint32_t)(__ballot(incl > Tq && tot > 0.0) >> gbase) & 0xFFFFu;
+    int pick = -1;
+    if (fm && li == __ffs((int)fm) - 1) {
+        // the chunk holding the crossing (the last one if rounding between the two summation
+        // orders leaves none), then the first site in it above Tq
+        double run = excl, before = excl;
+        int c_hit = -1;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (c_hit < 0) {
+                if (run + cs[q] > Tq) {
+                    c_hit = q;
+                    before = run;
+                } else {
+                    run += cs[q];
+                }
+            }
+        }
+        if (c_hit < 0) {
+            c_hit = max(nch - 1, 0);
+            before = excl;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) before += q < c_hit ? cs[q] : 0.0;
+        }
+        const int m0 = C * c_hit;
+        int xx = (i0 + m0) % L, yy = (i0 + m0) / L;
+        int last_in = -1;
+        T v[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) v[k] = row[min(i0 + m0 + k, N - 1)];
+        run = before;
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            const int m = m0 + k;
+            if (m < cnt && pick < 0) {
+                int dx = cx - xx, dyy = cy - yy;
+                dx += dx < 0 ? L : 0;
+                dyy += dyy < 0 ? L : 0;
+                const double fv = (double)v[k];
+                const double wm = (fv > 0.0 ? fv : 0.0) * (g[dyy] * g[dx]);
+                run += wm;
+                if (wm > 0.0) last_in = i0 + m;
+                if (run > Tq) pick = i0 + m;
+                if (++xx == L) {
+                    xx = 0;
+                    ++yy;
+                }
+            }
+        }
+        if (pick < 0) pick = last_in >= 0 ? last_in : lastpos;  // rounding between sum orders
+    }
+    if (fm) return __shfl(pick, gbase + __ffs((int)fm) - 1, 64);
+    const uint32_t lm = (uint32_t)(__ballot(lastpos >= 0) >> gbase) & 0xFFFFu;
+    return lm ? __shfl(lastpos, gbase + 31 - __clz((int)lm), 64) : cur;
+}
+
+// Any row length: two plain passes over the lane's sites.
+template <typename T>
+__device__ int row_draw_plain(const T* __restrict__ row, int N, int L, int M, int li, int gbase,
+                              int cx, int cy, const double* g, double u, int cur, int* err) {
+    const int i0 = li * M, i1 = min(i0 + M, N);
+    auto weight = [&](int i) {
+        const int x = i % L, y = i / L;
+        int dx = cx - x, dy = cy - y;
+        dx += dx < 0 ? L : 0;
+        dy += dy < 0 ? L : 0;
+        const double fi = (double)row[i];
+        return (fi > 0.0 ? fi : 0.0) * (g[dy] * g[dx]);
+    };
+    double tot = 0.0;
+    for (int i = i0; i < i1; ++i) tot += weight(i);
+    const double incl = group_scan_incl(tot);
+    const double excl = dpp_f64<0x111>(incl);
+    const double total = __shfl(incl, gbase + 15, 64);
+    if (!(total > 0.0) || !isfinite(total)) {
+        if (*err == 0) *err = isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE;
+        return cur;
+    }
+    const double Tq = u * total;
+    double run = excl;
+    int found = -1, lastpos = -1;
+    for (int i = i0; i < i1; ++i) {
+        const double wi = weight(i);
+        run += wi;
+        if (found < 0 && run > Tq) found = i;
+        if (wi > 0.0) lastpos = i;
+    }
+    const uint32_t fm = (uint32_t)(__ballot(found >= 0) >> gbase) & 0xFFFFu;
+    const uint32_t lm = (uint32_t)(__ballot(lastpos >= 0) >> gbase) & 0xFFFFu;
+    if (fm) return __shfl(found, gbase + __ffs((int)fm) - 1, 64);
+    return lm ? __shfl(lastpos, gbase + 31 - __clz((int)lm), 64) : cur;
+}
+
+// Draw on the second window (half-width kWin2W) of one 16-lane group: lane li sums the weights
+// of its kWin2PerLane ranks in three sub-chunks of five (five loads in flight at a time, within
+// the register budget), the lane sums are scanned, and the lane holding the crossing re-reads the
+// one sub-chunk that holds it (from cache) to find the rank and its certificate. Returns
+// (1 << 16 | y << 8 | x) for a certified draw, 0 otherwise (uniform within the group).
+template <typename T>
+__device__ int window2_draw(const T* __restrict__ row, int L, int li, int gbase, int cx, int cy,
+                            const double* g, double u, double gout2) {
+    constexpr int K2 = kWin2PerLane, SUB = 5;
+    static_assert(K2 == 3 * SUB, "three sub-chunks per lane");
+    const int WW = win_width(kWin2W, L), nwin = WW * WW;
+    const float rw = 1.0f / (float)WW;  // (q + 1/2) / WW in FP32 floors exactly for q < 2^12
+    auto site_of = [&](int k, int* x, int* y) {
+        const int q = li * K2 + k;
+        const int qq = q < nwin ? q : 0;
+        const int qy = (int)(((float)qq + 0.5f) * rw);
+        *x = win_coord(qq - qy * WW, cx, kWin2W, L, WW);
+        *y = win_coord(qy, cy, kWin2W, L, WW);
+    };
+    auto wt = [&](int k, T fv, int x, int y) {
+        int dx = cx - x, dy = cy - y;
+        dx += dx < 0 ? L : 0;
+        dy += dy < 0 ? L : 0;
+        const double f = li * K2 + k < nwin ? (double)fv : 0.0;
+        return (f > 0.0 ? f : 0.0) * (g[dy] * g[dx]);
+    };
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+#pragma unroll 1
+    for (int k0 = 0; k0 < K2; k0 += SUB) {  // five loads in flight at a time (register budget)
+        double cs = 0.0;
+#pragma unroll
+        for (int k = k0; k < k0 + SUB; ++k) {
+            int x, y;
+            site_of(k, &x, &y);
+            cs += wt(k, row[y * L + x], x, y);
+        }
+        c0 = k0 == 0 ? cs : c0;
+        c1 = k0 == SUB ? cs : c1;
+        c2 = k0 == 2 * SUB ? cs : c2;
+    }
+    const double tot = (c0 + c1) + c2;
+    const double incl = group_scan_incl(tot);
+    const double excl = dpp_f64<0x111>(incl);
+    const double T_in = __shfl(incl, gbase + 15, 64);
+    const double tau = u * T_in;
+    const bool fin = T_in > 0.0 && isfinite(T_in);
+    const uint32_t gm = (uint32_t)(__ballot(fin && incl > tau && tot > 0.0) >> gbase) & 0xFFFFu;
+    const int src = gm ? __ffs((int)gm) - 1 : 0;
+    int res = 0;
+    if (gm && li == src) {
+        const double r1 = excl + c0, r2 = r1 + c1;
+        const int sc = r1 > tau ? 0 : r2 > tau ? 1 : 2;
+        double c_lo = sc == 0 ? excl : sc == 1 ? r1 : r2, c_hi = 0.0;
+        T v[SUB];  // one lane re-reads the sub-chunk from cache, all five loads at once
+        int xs[SUB], ys[SUB];
+#pragma unroll
+        for (int k = 0; k < SUB; ++k) {
+            site_of(SUB * sc + k, &xs[k], &ys[k]);
+            v[k] = row[ys[k] * L + xs[k]];
+        }
+        int pick = -1, pxy = 0;
+#pragma unroll
+        for (int k = 0; k < SUB; ++k) {
+            if (pick < 0) {
+                const double ck = c_lo + wt(SUB * sc + k, v[k], xs[k], ys[k]);
+                if (ck > tau) {
+                    pick = k;
+                    pxy = xs[k] | (ys[k] << 8);
+                    c_hi = ck;
+                } else {
+                    c_lo = ck;
+                }
+            }
+        }
+        if (pick >= 0 && win_certified(c_lo, c_hi, tau, gout2 * kWinMassBound + kWinSlack * T_in))
+            res = (1 << 16) | pxy;
+    }
+    return __shfl(res, gbase + src, 64);
+}
+
+// Backward sampling with windowed draws (the certificate is in fh_window.h): 16 lanes per
+// (chain, worldline, block), four per wavefront, so that every wavefront keeps four independent
+// chains of dependent loads in flight. Lane li holds the window ranks 4 li .. 4 li + 3 (site
+// order). Per draw it loads those filter values, forms max(f, 0) g(dy) g(dx), and the 16 lanes
+// scan their sums with DPP inside their row of the wavefront. The lane holding the first rank
+// above tau certifies the draw. An uncertified draw scans the whole row in site order instead
+// (ceil(N / 16) contiguous sites per lane), with k_backward's rule. Lane li of a group computes
+// the Philox uniform of draw s0 + li once per 16 draws. Every load address is in bounds for any
+// lane (inactive groups read chain 0's first row), so loads are unconditional and values masked.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_backward_win(
+    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
+    const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
+    const int32_t* __restrict__ perm, const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    constexpr int G = kThreads / kWinLanes;
+    constexpr int K = kWinPerLane;
+    __shared__ double gsh[G][kWinMaxL];
+    const int grp = threadIdx.x / kWinLanes, li = threadIdx.x % kWinLanes;
+    const int gbase = (threadIdx.x & 63) - li;  // the group's first lane in the wavefront
+    const int task = blockIdx.x * G + grp;
+    const bool active = task < n_tasks;
+    const DrawTask t = active ? tasks[task] : DrawTask{0, 0, 0, 0};
+    const ChainInfo& c = chains[t.chain];
+    const int L = c.L, N = c.N, L_tau = c.L_tau, w = c.win_w;
+    double* g = gsh[grp];
+    for (int d = li; d < L; d += kWinLanes) g[d] = tables[tab_g(c) + d];
+    __syncthreads();  // the only barrier; every wave reaches it
+    const uint64_t sweep = *sweep_ptr;
+    int start = 0, len = 1;
+    if (active) block_of(c, sweep, t.block, &start, &len);
+    const int nd = len - 1;  // draw s sets slice start + (nd - s), s = 0 .. nd - 1
+    int nd_max = nd;
+    nd_max = max(nd_max, __shfl_xor(nd_max, 16, 64));
+    nd_max = max(nd_max, __shfl_xor(nd_max, 32, 64));
+    int32_t* pc = paths + c.path_off;
+    const int qn = perm[c.part_off + t.p];  // the worldline slices >= L_tau belong to
+    int cur = 0;
+    if (nd >= 1)
+        cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np +
+                              (start + len >= L_tau ? qn : t.p)], N, status, t.chain);
+    int cx = cur % L, cy = cur / L;
+    const int WW = win_width(w, L), nwin = WW * WW;
+    int qx[K], qy[K];
+    bool qv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int q = li * K + k;
+        qv[k] = q < nwin;
+        qy[k] = qv[k] ? q / WW : 0;
+        qx[k] = qv[k] ? q - qy[k] * WW : 0;
+    }
+    const T* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+    const double gout = c.win_gout * kWinMassBound;
+    const int M = (N + kWinLanes - 1) / kWinLanes;  // full-row scan: sites per lane
+    double ureg = 0.0;
+    int err = 0;  // the first error of the block, reported once after the loop
+    // Drawn sites are stored sixteen draws at a time: lane li keeps the site of draw sb + li of
+    // the current batch sb. A store retires in order with the loads after it, so a store after
+    // every draw would make each draw's window loads wait for the previous draw's store; the
+    // batch store is issued after the next draw's loads.
+    int pend = 0;
+    auto flush = [&](int sb) {
+        const int sd = sb + li;
+        if (sd < nd) {
+            const int jd = nd - sd;
+            pc[(int64_t)((start + jd) % L_tau) * c.np + (start + jd >= L_tau ? qn : t.p)] = pend;
+        }
+    };
+    for (int s = 0; s < nd_max; ++s) {
+        const bool real = s < nd;
+        const int j = real ? nd - s : 1;
+        if ((s & 15) == 0) {  // lane li draws the uniform of draw s + li
+            const int jj = nd - s - li;
+            ureg = 0.0;
+            if (jj >= 1) {
+                const u64x4 r = philox4x64_10((uint64_t)t.p, (uint64_t)((start + jj) % L_tau),
+                                              sweep, kTagPath, c.seed, 0);
+                ureg = u01_from(r.x0);
+            }
+        }
+        const double u = __shfl(ureg, gbase + (s & 15), 64);
+        const T* row = rows + (int64_t)(j - 1) * N;
+        int xs[K], ys[K];
+        T fv[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            xs[k] = win_coord(qx[k], cx, w, L, WW);
+            ys[k] = win_coord(qy[k], cy, w, L, WW);
+            fv[k] = row[ys[k] * L + xs[k]];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if ((s & 15) == 0 && s > 0) flush(s - 16);  // the previous batch, after these loads
+        __builtin_amdgcn_sched_barrier(0);
+        double P[K];
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            int dx = cx - xs[k], dy = cy - ys[k];
+            dx += dx < 0 ? L : 0;
+            dy += dy < 0 ? L : 0;
+            const double fk = (real && qv[k]) ? (double)fv[k] : 0.0;
+            acc += (fk > 0.0 ? fk : 0.0) * (g[dy] * g[dx]);
+            P[k] = acc;
+        }
+        double incl = acc;  // inclusive scan over the group's 16 lanes (one DPP row)
+        incl += dpp_f64<0x111>(incl);
+        incl += dpp_f64<0x112>(incl);
+        incl += dpp_f64<0x114>(incl);
+        incl += dpp_f64<0x118>(incl);
+        const double excl = dpp_f64<0x111>(incl);  // the previous lane's inclusive sum (0 first)
+        const double T_in = __shfl(incl, gbase + 15, 64);
+        const double tau = u * T_in;
+        const bool fin = T_in > 0.0 && isfinite(T_in);
+        const uint32_t gm =
+            (uint32_t)(__ballot(real && fin && incl > tau && acc > 0.0) >> gbase) & 0xFFFFu;
+        const int src = gm ? __ffs((int)gm) - 1 : 0;
+        int pick = -1;
+        double c_lo = excl, c_hi = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double ck = excl + P[k];
+            if (pick < 0) {
+                if (ck > tau) {
+                    pick = k;
+                    c_hi = ck;
+                } else {
+                    c_lo = ck;
+                }
+            }
+        }
+        int px = xs[0], py = ys[0];
+#pragma unroll
+        for (int k = 1; k < K; ++k)
+            if (k == pick) {
+                px = xs[k];
+                py = ys[k];
+            }
+        const bool cert_l = li == src && pick >= 0 &&
+                            win_certified(c_lo, c_hi, tau, gout + kWinSlack * T_in);
+        const int packed = __shfl((cert_l ? 1 << 16 : 0) | (py << 8) | px, gbase + src, 64);
+        const bool cert = gm != 0 && (packed >> 16) != 0;
+        int nx = packed & 255, ny = (packed >> 8) & 255;
+        if (real && !cert) {  // uniform within the group: the wider window, then the full row
+            const int p2 = window2_draw(row, L, li, gbase, cx, cy, g, u, c.win_gout2);
+            if (p2 >> 16) {
+                nx = p2 & 255;
+                ny = (p2 >> 8) & 255;
+            } else {
+                const int chosen =
+                    M <= 64 ? row_draw_chunked(row, N, L, M, li, gbase, cx, cy, g, u, cur, &err)
+                            : row_draw_plain(row, N, L, M, li, gbase, cx, cy, g, u, cur, &err);
+                nx = chosen % L;
+                ny = chosen / L;
+            }
+        }
+        if (real) {
+            cx = nx;
+            cy = ny;
+            cur = cx + L * cy;
+        }
+        if (li == (s & 15)) pend = cur;
+    }
+    if (nd_max > 0) flush((nd_max - 1) & ~15);
+    if (err != 0 && li == 0) set_status(status, err, t.chain);  // the block's first error
+}
+
 // One wavefront per (chain, worldline, block) of the chains with L != 32, the body chosen per
 // chain: up to 4 sites per lane (N <= 256), or up to 16 (N <= 1024).
 template <typename T>
@@ -1442,7 +1848,20 @@ hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s) {
 }
 
 hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
-    // 32 x 32 chains on their own kernel, the rest (any L) on the generic ones
+    // windowed draws where the hopping kernel allows them; otherwise 32 x 32 chains on their own
+    // full-row kernel, the rest (any L) on the generic ones
+    if (p->n_draww_tasks > 0) {
+        const unsigned blocks = (unsigned)((p->n_draww_tasks + kThreads / kWinLanes - 1) /
+                                           (kThreads / kWinLanes));
+        if (p->precision == FH_FP64)
+            hipLaunchKernelGGL(k_backward_win<double>, dim3(blocks), dim3(kThreads), 0, s,
+                               p->d.chains, p->d.draww_tasks, p->n_draww_tasks, p->d.tables,
+                               (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status);
+        else
+            hipLaunchKernelGGL(k_backward_win<float>, dim3(blocks), dim3(kThreads), 0, s,
+                               p->d.chains, p->d.draww_tasks, p->n_draww_tasks, p->d.tables,
+                               (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status);
+    }
     if (p->n_draw32_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_draw32_tasks + kWaves - 1) / kWaves);
         if (p->precision == FH_FP64)
@@ -1454,10 +1873,10 @@ hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
                                p->d.chains, p->d.draw32_tasks, p->n_draw32_tasks, p->d.tables,
                                (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status);
     }
-    if (p->n_fwdx_tasks == 0) return hipGetLastError();
-    const unsigned blocks = (unsigned)((p->n_fwdx_tasks + kWaves - 1) / kWaves);
-    const DrawTask* tasks = p->d.fwdx_tasks;
-    const int n = p->n_fwdx_tasks;
+    if (p->n_drawx_tasks == 0) return hipGetLastError();
+    const unsigned blocks = (unsigned)((p->n_drawx_tasks + kWaves - 1) / kWaves);
+    const DrawTask* tasks = p->d.drawx_tasks;
+    const int n = p->n_drawx_tasks;
     if (p->max_N_x <= 1024) {
         if (p->precision == FH_FP64)
             hipLaunchKernelGGL(k_backward_fast<double>, dim3(blocks), dim3(kThreads), 0, s,

@@ -37,6 +37,7 @@ FH_FP32_MFMA3 = 2
 FH_FLAG_NONE = 0
 FH_FLAG_GRAPH = 1
 FH_FLAG_AUTOTUNE = 2
+FH_FLAG_FULL_ROW_DRAW = 4
 
 
 class fh_chain_desc(ctypes.Structure):
@@ -88,6 +89,12 @@ _sig("fh_debug_radix_orders", c_int32, c_int32, POINTER(c_int32), c_int32)
 _sig("fh_debug_kernel_table", c_int32, c_int32, c_double, c_double, POINTER(c_double))
 _sig("fh_debug_philox", c_int32, c_uint64, c_uint64, c_uint64, c_uint64, c_uint64, c_uint64,
      POINTER(c_uint64))
+_sig("fh_debug_window_select", c_int32, POINTER(c_double), c_int32, POINTER(c_int32),
+     POINTER(c_double))
+_sig("fh_debug_window_draw", c_int32, c_int32, c_int32, POINTER(c_double), c_double,
+     POINTER(c_double), c_int32, c_double, POINTER(c_int32), POINTER(c_int32))
+_sig("fh_debug_inflate_window_bound", c_int32, c_void_p, c_double)
+_sig("fh_debug_backward_kernels", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32))
 
 
 class FhError(RuntimeError):

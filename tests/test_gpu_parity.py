@@ -7,6 +7,7 @@ Tolerances (written here, derived in the design notes):
   FP32 paths: filters <= 1e-5 normwise (MFMA split-bf16) / measured and bounded (FFT),
   log Z <= 1e-6 relative, gradients <= 1e-4 normwise.
 """
+import ctypes
 import dataclasses
 import sys
 
@@ -1027,3 +1028,52 @@ def test_logz_grad_mfma_full_lattice_repeatable(lib):
         assert np.linalg.norm(gA[c] - g) <= 1e-4 * np.linalg.norm(g)
         assert t1[c].item() == pytest.approx(gt, rel=1e-4)
     S.close()
+
+
+WINDOW_BATCH = MIXED + [
+    synth.ChainDesc(L=32, L_tau=40, n_up=6, n_dn=5, hs_kind=synth.HS_GAUSS, block_len=0,
+                    t=1.0, U=4.0, dtau=0.05, seed=61),
+    synth.ChainDesc(L=24, L_tau=24, n_up=5, n_dn=3, hs_kind=synth.HS_HIRSCH, block_len=9,
+                    t=1.0, U=4.0, dtau=0.05, seed=62),
+    synth.ChainDesc(L=16, L_tau=12, n_up=4, n_dn=4, hs_kind=synth.HS_GAUSS, block_len=0,
+                    t=1.0, U=4.0, dtau=0.4, seed=63),      # kernel too wide for a window
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mfma3"])
+def test_windowed_draws_equal_full_row_draws(lib, prec):
+    """The windowed backward kernel, its full-row fallback forced on every draw (bound inflated
+    to infinity), and the full-row kernels (FH_FLAG_FULL_ROW_DRAW) draw identical paths from the
+    same filters and uniforms; the FP64 FFT path adds a 48 x 48 chain (N > 1024)."""
+    fhmc, sampler = lib
+    descs = list(WINDOW_BATCH)
+    if prec != "mfma3":
+        descs.append(synth.ChainDesc(L=48, L_tau=12, n_up=3, n_dn=2, hs_kind=synth.HS_GAUSS,
+                                     block_len=5, t=1.0, U=4.0, dtau=0.05, seed=64))
+    say("windowed vs full-row draws", prec)
+    aux, paths = mixed_state(descs, seed=171)
+    plans = {"window": sampler.Sampler(descs, PRECS[prec]),
+             "fallback": sampler.Sampler(descs, PRECS[prec]),
+             "full": sampler.Sampler(descs, PRECS[prec], fhmc.FH_FLAG_FULL_ROW_DRAW)}
+    assert fhmc.lib.fh_debug_inflate_window_bound(plans["fallback"].plan, float("inf")) == 0
+    nw, nf = ctypes.c_int32(), ctypes.c_int32()
+    assert fhmc.lib.fh_debug_backward_kernels(plans["window"].plan, ctypes.byref(nw),
+                                              ctypes.byref(nf)) == 0
+    wide = sum(d.n_particles * max(1, -(-d.L_tau // (d.block_len or d.L_tau)))
+               for d in descs if d.dtau > 0.3)
+    assert nw.value > 0 and nf.value == wide
+    assert fhmc.lib.fh_debug_backward_kernels(plans["full"].plan, ctypes.byref(nw),
+                                              ctypes.byref(nf)) == 0
+    assert nw.value == 0
+    out = {}
+    for name, S in plans.items():
+        A, P = S.pack_aux(aux), S.pack_paths(paths)
+        for s in (0, 1, 2):
+            S.forward_filter(A, P, s)
+            S.backward_sample(P, s)
+        assert S.status() == (0, -1), name
+        out[name] = S.unpack_paths(P)
+        S.close()
+    for c in range(len(descs)):
+        assert np.array_equal(out["window"][c], out["full"][c]), ("window", c)
+        assert np.array_equal(out["fallback"][c], out["full"][c]), ("fallback", c)
