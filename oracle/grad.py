@@ -7,15 +7,22 @@ on the same site. It is log p(anchor sites | field) up to a field-independent co
 prior is not included. The paper does not define this gradient; it is the adjoint of the
 forward recursion:
 
-  backward messages  beta_{L_tau-1}(r) = G(a (-) r),
+  backward messages  beta_{L_tau-1}(r) = G(e (-) r),  e the site the block closes on (a),
                      beta_j = G * (W_{j+1} . beta_{j+1})            (G is symmetric)
   so that Z = sum_r f_j(r) beta_j(r) for every j, and
   d log Z / d log W_j(r) = f_j(r) beta_j(r) / Z      (the smoothing marginal of r_j)
   d log Z / d t = sum_j <u_{j+1}, (dG/dt) * f_j> / <u_{j+1}, G * f_j>,
-                  u_{j+1} = W_{j+1} . beta_{j+1}  (u_{L_tau} = delta_a).
+                  u_{j+1} = W_{j+1} . beta_{j+1}  (u_{L_tau} = delta_e).
 With log W_spin = c_spin * aux (c = a for the Gaussian field, +-lambda for the Ising one),
 d log Z_path / d aux(l, r) = sum_p c_spin(p) P(r_l^(p) = r).
 All messages are kept normalised; every ratio above is scale-free.
+
+With reconnections at tau = beta (eq. joint's sum over permutations, slice L_tau of worldline p
+being slice 0 of worldline perm[p]) the block of p anchored at (l0, a_p) runs through tau = beta
+onto perm[p] and closes on the anchor site of perm[p]: Z_p is the weight of all paths from a_p
+to a_{perm[p]} over L_tau slices (the same recursion with end site a_{perm[p]} in place of a_p),
+and log Z_path is still the log-probability of the anchor sites given the field, up to a
+field-independent constant.
 """
 from __future__ import annotations
 
@@ -35,19 +42,28 @@ def _spins(desc, aux):
     return out
 
 
-def logz_path(desc, aux: np.ndarray, paths: np.ndarray, anchor_slice: int, t: float | None = None):
-    """(total log Z_path, per-particle log Z_p [Np])."""
+def _ends(desc, paths, anchor_slice, parts, perm):
+    """Anchor sites of the worldlines each block closes on (itself, or its reconnection)."""
+    nxt = parts if perm is None else np.asarray(perm, dtype=np.int64)[parts]
+    return paths[anchor_slice, nxt].astype(np.int64)
+
+
+def logz_path(desc, aux: np.ndarray, paths: np.ndarray, anchor_slice: int, t: float | None = None,
+              perm: np.ndarray | None = None):
+    """(total log Z_path, per-particle log Z_p [Np]); perm: reconnection (None = identity)."""
     t = desc.t if t is None else t
     Gmat = lattice.transfer_matrix(desc.L, t, desc.dtau)
     per = np.zeros(desc.n_particles)
     for W, _, parts in _spins(desc, aux):
         a = paths[anchor_slice, parts].astype(np.int64)
-        _, lz, _ = ffbs.forward_filter(Gmat, W, anchor_slice, desc.L_tau, a, a)
+        e = _ends(desc, paths, anchor_slice, parts, perm)
+        _, lz, _ = ffbs.forward_filter(Gmat, W, anchor_slice, desc.L_tau, a, e)
         per[parts] = lz
     return float(per.sum()), per
 
 
-def logz_path_grad(desc, aux: np.ndarray, paths: np.ndarray, anchor_slice: int):
+def logz_path_grad(desc, aux: np.ndarray, paths: np.ndarray, anchor_slice: int,
+                   perm: np.ndarray | None = None):
     """Returns (log Z_path, grad_aux [L_tau, N], d log Z_path / d t, per-particle dt [Np])."""
     L_tau, N = desc.L_tau, desc.N
     Gmat = lattice.transfer_matrix(desc.L, desc.t, desc.dtau)
@@ -59,10 +75,11 @@ def logz_path_grad(desc, aux: np.ndarray, paths: np.ndarray, anchor_slice: int):
         P = len(parts)
         rows = np.arange(P)
         a = paths[anchor_slice, parts].astype(np.int64)
-        filt, lz, _ = ffbs.forward_filter(Gmat, W, anchor_slice, L_tau, a, a)
+        e = _ends(desc, paths, anchor_slice, parts, perm)
+        filt, lz, _ = ffbs.forward_filter(Gmat, W, anchor_slice, L_tau, a, e)
         total += float(lz.sum())
         u_next = np.zeros((P, N))
-        u_next[rows, a] = 1.0                       # u_{L_tau} = delta_a
+        u_next[rows, e] = 1.0                       # u_{L_tau} = delta_e
         dt = np.zeros(P)
         for j in range(L_tau - 1, -1, -1):
             f = filt[:, j, :]

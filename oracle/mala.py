@@ -30,26 +30,29 @@ def log_prior(desc, sigma: np.ndarray) -> float:
     return float(np.sum(-0.5 * sigma * sigma - 0.5 * a * sigma))
 
 
-def log_target(desc, sigma, paths, anchor):
-    """(log pi up to a constant, d log pi / d sigma)."""
+def log_target(desc, sigma, paths, anchor, perm=None):
+    """(log pi up to a constant, d log pi / d sigma); perm: reconnection (None = identity)."""
     a = hs.gauss_coupling(desc.U, desc.dtau)
-    lz, g, _, _ = grad.logz_path_grad(desc, sigma, paths, anchor)
+    lz, g, _, _ = grad.logz_path_grad(desc, sigma, paths, anchor, perm=perm)
     return log_prior(desc, sigma) + lz, -sigma - 0.5 * a + g
 
 
-def mala_step(desc, sigma: np.ndarray, paths: np.ndarray, anchor: int, eps: float, sweep: int):
-    """One MALA step of the chain's field. Returns (new field, accepted, log alpha)."""
+def mala_step(desc, sigma: np.ndarray, paths: np.ndarray, anchor: int, eps: float, sweep: int,
+              perm=None):
+    """One MALA step of the chain's field. Returns (new field, accepted, log alpha). With a
+    reconnection perm, Z_path is the weight of the paths joining each anchor site to that of the
+    reconnected worldline (see `grad`)."""
     if desc.hs_kind != hs.HS_GAUSS:
         raise ValueError("MALA moves the Gaussian field only")
     L_tau, N = sigma.shape
     h = 0.5 * eps * eps
-    lp0, g0 = log_target(desc, sigma, paths, anchor)
+    lp0, g0 = log_target(desc, sigma, paths, anchor, perm)
     sites = np.arange(N, dtype=np.uint64)[None, :]
     slices = np.arange(L_tau, dtype=np.uint64)[:, None]
     x0, x1, _, _ = philox.draw_words(desc.seed, sites, slices, sweep, TAG_MALA)
     xi = philox.gaussian(x0, x1)
     prop = sigma + h * g0 + eps * xi
-    lp1, g1 = log_target(desc, prop, paths, anchor)
+    lp1, g1 = log_target(desc, prop, paths, anchor, perm)
     fwd = np.sum((prop - sigma - h * g0) ** 2) / (2.0 * eps * eps)
     rev = np.sum((sigma - prop - h * g1) ** 2) / (2.0 * eps * eps)
     log_alpha = lp1 - lp0 - rev + fwd

@@ -73,3 +73,63 @@ def test_u0_t_gradient_closed_form(L, L_tau, dtau):
     assert np.allclose(per, ref, rtol=1e-12)
     if (L, L_tau) == (4, 16):
         assert ref == pytest.approx(5.898678748201, abs=1e-10)
+
+
+def enumerate_logz(desc, aux, paths, anchor, perm):
+    """log Z_p by summing every path of the block: from p's anchor site over L_tau slices to the
+    anchor site of perm[p], weight prod W_l(r_l) G(r_{l+1} - r_l) (brute force, tiny systems)."""
+    import itertools
+    from oracle import lattice
+    Gm = lattice.transfer_matrix(desc.L, desc.t, desc.dtau)
+    W_up, W_dn = hs.potentials(aux, desc.hs_kind, desc.U, desc.dtau)
+    out = np.zeros(desc.n_particles)
+    for p in range(desc.n_particles):
+        W = W_up if p < desc.n_up else W_dn
+        a, e = paths[anchor, p], paths[anchor, perm[p]]
+        z = 0.0
+        for mid in itertools.product(range(desc.N), repeat=desc.L_tau - 1):
+            r = (a,) + mid + (e,)
+            wgt = 1.0
+            for j in range(desc.L_tau):
+                wgt *= W[(anchor + j) % desc.L_tau, r[j]] * Gm[r[j + 1], r[j]]
+            z += wgt
+        out[p] = np.log(z)
+    return out
+
+
+def test_reconnected_logz_matches_enumeration():
+    d = synth.ChainDesc(L=2, L_tau=4, n_up=3, n_dn=2, hs_kind=synth.HS_GAUSS, block_len=0, t=1.0,
+                        U=4.0, dtau=0.3, seed=5)
+    aux = synth.initial_aux(d)
+    paths = synth.random_paths(d, 7)
+    perm = np.array([2, 0, 1, 4, 3])
+    for anchor in (0, 2):
+        _, per = grad.logz_path(d, aux, paths, anchor, perm=perm)
+        assert np.allclose(per, enumerate_logz(d, aux, paths, anchor, perm), rtol=1e-12)
+    # the identity permutation is the plain closed ring
+    assert np.allclose(grad.logz_path(d, aux, paths, 1, perm=np.arange(5))[1],
+                       grad.logz_path(d, aux, paths, 1)[1], rtol=0, atol=0)
+
+
+def test_reconnected_gradients_match_central_differences():
+    d = small_chain(L=3, L_tau=8, n=(3, 2))
+    aux = synth.initial_aux(d)
+    paths = synth.random_paths(d, 6)
+    perm = np.array([1, 2, 0, 4, 3])
+    _, g, gt, _ = grad.logz_path_grad(d, aux, paths, 3, perm=perm)
+    rng = np.random.default_rng(4)
+    h = 1e-4
+    for _ in range(12):
+        l, r = rng.integers(0, d.L_tau), rng.integers(0, d.N)
+        ap, am = aux.copy(), aux.copy()
+        ap[l, r] += h
+        am[l, r] -= h
+        fd = (grad.logz_path(d, ap, paths, 3, perm=perm)[0]
+              - grad.logz_path(d, am, paths, 3, perm=perm)[0]) / (2 * h)
+        assert g[l, r] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+    fd = (grad.logz_path(d, aux, paths, 3, t=d.t + h, perm=perm)[0]
+          - grad.logz_path(d, aux, paths, 3, t=d.t - h, perm=perm)[0]) / (2 * h)
+    assert gt == pytest.approx(fd, rel=1e-7)
+    # the smoothing marginals still sum to one per worldline and slice
+    a = hs.gauss_coupling(d.U, d.dtau)
+    assert np.allclose(g.sum(axis=1), a * d.n_particles, rtol=1e-13)
