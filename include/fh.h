@@ -166,8 +166,8 @@ int fh_local_update(fh_plan plan, const void* aux, int32_t* paths, uint64_t swee
  * sampled measure is |pi|). fh_init starts from the identity, sign +1. FFBS blocks that run past
  * slice L_tau - 1 continue on the reconnected worldline (their end site is read from it and their
  * interior slices from L_tau on are written to it); local updates link slice L_tau-1 of p to
- * slice 0 of perm[p]. fh_logZ_grad and fh_mala_field are defined for worldlines that close on
- * themselves and return FH_ERR_UNSUPPORTED once the permutation may differ from the identity. */
+ * slice 0 of perm[p]. fh_logZ_grad and fh_mala_field close the ring of worldline p on the anchor
+ * site of perm[p]: Z_p sums the paths from p's anchor site to that of perm[p] over L_tau slices. */
 
 /* Sets the permutation from a host array [particles] (packed like logZ: chain c's entries at its
  * particle_offset) and recomputes the signs. FH_ERR_INVALID_ARG unless every chain's entries are

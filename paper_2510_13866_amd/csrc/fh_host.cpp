@@ -502,7 +502,6 @@ int fh_local_update(fh_plan p, const void* aux, int32_t* paths, uint64_t sweep, 
 int fh_set_permutation(fh_plan p, const int32_t* perm) {
     if (!p || !perm) return FH_ERR_INVALID_ARG;
     std::vector<int32_t> h((size_t)p->particles), inv((size_t)p->particles), sg(p->n_chains);
-    bool identity = true;
     for (int c = 0; c < p->n_chains; ++c) {
         const ChainInfo& ci = p->chains[c];
         std::vector<char> seen(ci.np, 0);
@@ -514,7 +513,6 @@ int fh_set_permutation(fh_plan p, const int32_t* perm) {
             seen[v] = 1;
             h[ci.part_off + q] = v;
             inv[ci.part_off + v] = q;
-            identity = identity && v == q;
         }
         std::vector<char> done(ci.np, 0);
         for (int q = 0; q < ci.np; ++q)
@@ -528,7 +526,6 @@ int fh_set_permutation(fh_plan p, const int32_t* perm) {
     FH_TRY(hipMemcpy(p->d.perm, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice));
     FH_TRY(hipMemcpy(p->d.perm_inv, inv.data(), sizeof(int32_t) * inv.size(), hipMemcpyHostToDevice));
     FH_TRY(hipMemcpy(p->d.sign, sg.data(), sizeof(int32_t) * sg.size(), hipMemcpyHostToDevice));
-    p->perm_identity = identity;
     p->have_filters = false;
     return FH_OK;
 }
@@ -550,7 +547,6 @@ int fh_permutation_update(fh_plan p, const int32_t* paths, uint64_t sweep, int32
     hipStream_t s = (hipStream_t)stream;
     FH_TRY(launch_set_sweep(p, sweep, s));
     FH_TRY(launch_perm_update(p, paths, n_passes, s));
-    p->perm_identity = false;
     p->have_filters = false;
     return FH_OK;
 }
@@ -643,7 +639,6 @@ static hipError_t enqueue_logz_grad(fh_plan p, const void* aux, const int32_t* p
 int fh_logZ_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor_slice,
                  double* logZ, void* grad_aux, double* grad_t, fh_stream stream) {
     if (!p || !aux || !paths) return FH_ERR_INVALID_ARG;
-    if (!p->perm_identity) return FH_ERR_UNSUPPORTED;  // defined for self-closed worldlines
     for (const ChainInfo& c : p->chains)
         if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
     FH_TRY(enqueue_logz_grad(p, aux, paths, anchor_slice, logZ, grad_aux, grad_t,
@@ -656,7 +651,6 @@ int fh_logZ_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t ancho
 int fh_mala_field(fh_plan p, void* aux, const int32_t* paths, int32_t anchor_slice, double eps,
                   uint64_t sweep, int32_t* accepted, fh_stream stream) {
     if (!p || !aux || !paths || !(eps > 0.0) || !is_fin(eps)) return FH_ERR_INVALID_ARG;
-    if (!p->perm_identity) return FH_ERR_UNSUPPORTED;  // Z_path of self-closed worldlines
     for (const ChainInfo& c : p->chains)
         if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;

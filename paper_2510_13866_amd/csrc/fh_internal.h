@@ -126,7 +126,6 @@ struct fh_plan_s {
     double win_bound_scale = 1.0;  // test hook: >= 1 inflates every window bound
     int64_t gpart_elems = 0;
     int64_t total_sites = 0;  // sum of N over the chains
-    bool perm_identity = true;  // false once a permutation other than the identity may be set
     int32_t max_N = 0, max_L = 0, max_np = 0;
     size_t real_size = 8;
     std::vector<fh::TuneRecord> tune_log;  // FH_FLAG_AUTOTUNE timings, in the order taken

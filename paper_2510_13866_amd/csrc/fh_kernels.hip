@@ -1544,9 +1544,10 @@ __global__ __launch_bounds__(kThreads) void k_measure_reduce(
     }
 }
 
-// Adjoint of the forward filter over the ring anchored at `anchor` (one block of length L_tau):
+// Adjoint of the forward filter over the ring anchored at `anchor` (one block of length L_tau,
+// closing on the anchor site e of the reconnected worldline, e = a without reconnection):
 // forward pass storing f~_j (j = 0..L_tau-1), then backward messages
-//   u_{L_tau} = delta_a;  beta_j = G * u_{j+1};  u_j = W_j . beta_j / sum   (FFT convolution)
+//   u_{L_tau} = delta_e;  beta_j = G * u_{j+1};  u_j = W_j . beta_j / sum   (FFT convolution)
 // with d log Z / d log W_j(r) = f~_j(r) beta_j(r) / <f~_j, beta_j> accumulated into grad_aux
 // (times the spin's coefficient) and d log Z / dt += <dG/dt * u_{j+1}, f~_j> / <beta_j, f~_j>.
 template <typename T>
@@ -1555,7 +1556,8 @@ __global__ __launch_bounds__(kThreads) void k_grad(
     const double* __restrict__ tables, const T* __restrict__ aux, const T* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, T* __restrict__ filt, double* __restrict__ blk_logz,
-    double* __restrict__ dt_out, T* grad_aux, int anchor, int32_t* status, int maxN, int maxL) {
+    double* __restrict__ dt_out, T* grad_aux, int anchor, const int32_t* __restrict__ perm,
+    int32_t* status, int maxN, int maxL) {
     extern __shared__ __align__(16) unsigned char smem[];
     FftLds<T> l = carve<T>(smem, maxN, maxL, true);
     const PairTask t = tasks[blockIdx.x];
@@ -1569,16 +1571,22 @@ __global__ __launch_bounds__(kThreads) void k_grad(
     const int32_t* pc = paths + c.path_off;
     const int a_a = checked_site(pc[(int64_t)anchor * c.np + t.p_a], N, status, t.chain);
     const int a_b = has_b ? checked_site(pc[(int64_t)anchor * c.np + t.p_b], N, status, t.chain) : 0;
+    // the ring closes on the anchor site of the reconnected worldline (itself for the identity)
+    const int e_a = checked_site(pc[(int64_t)anchor * c.np + perm[c.part_off + t.p_a]], N, status,
+                                 t.chain);
+    const int e_b = has_b ? checked_site(pc[(int64_t)anchor * c.np + perm[c.part_off + t.p_b]], N,
+                                         status, t.chain)
+                          : 0;
     load_chain_tables(c, tables, l);
     T* row_a = filt + c.filt_off + (int64_t)t.p_a * L_tau * N;
     T* row_b = has_b ? filt + c.filt_off + (int64_t)t.p_b * L_tau * N : nullptr;
     double lza, lzb;
-    forward_pass<T>(c, tables, Wsp, shift, aux + c.aux_off, coef, anchor, L_tau, a_a, a_a, a_b,
-                    a_b, has_b, row_a, row_b, 0, l, &lza, &lzb, status, t.chain);
+    forward_pass<T>(c, tables, Wsp, shift, aux + c.aux_off, coef, anchor, L_tau, a_a, e_a, a_b,
+                    e_b, has_b, row_a, row_b, 0, l, &lza, &lzb, status, t.chain);
     const double* gh = tables + tab_ghat(c);
     const double* dgh = tables + tab_dghat(c);
     for (int r = threadIdx.x; r < N; r += blockDim.x)
-        l.U[r] = {r == a_a ? T(1) : T(0), (has_b && r == a_b) ? T(1) : T(0)};
+        l.U[r] = {r == e_a ? T(1) : T(0), (has_b && r == e_b) ? T(1) : T(0)};
     double dta = 0.0, dtb = 0.0;
     T* gl = grad_aux ? grad_aux + c.aux_off : nullptr;
     for (int j = L_tau - 1; j >= 0; --j) {
@@ -2003,14 +2011,14 @@ hipError_t launch_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t
                            p->d.chains, p->d.grad_tasks, p->d.tables, (const double*)aux,
                            (const double*)p->d.W,
                            p->d.wshift, p->aux_elems, p->total_slices, paths, (double*)p->d.filt, p->d.blk_logz, p->d.dt,
-                           (double*)grad_aux, anchor, p->d.status, p->max_N, p->max_L);
+                           (double*)grad_aux, anchor, p->d.perm, p->d.status, p->max_N, p->max_L);
     } else {
         if ((e = allow_lds(k_grad<float>, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_grad<float>, dim3(p->n_grad_tasks), dim3(kThreads), lds, s,
                            p->d.chains, p->d.grad_tasks, p->d.tables, (const float*)aux,
                            (const float*)p->d.W,
                            p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt, p->d.blk_logz, p->d.dt,
-                           (float*)grad_aux, anchor, p->d.status, p->max_N, p->max_L);
+                           (float*)grad_aux, anchor, p->d.perm, p->d.status, p->max_N, p->max_L);
     }
     return hipGetLastError();
 }

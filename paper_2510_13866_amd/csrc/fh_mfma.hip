@@ -417,11 +417,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     }
 }
 
-// Adjoint of the forward filter over the ring anchored at `anchor` (one block of length L_tau),
-// on the matrix cores. A workgroup takes up to kGroup worldlines of one (chain, spin), one per
+// Adjoint of the forward filter over the ring anchored at `anchor` (one block of length L_tau,
+// closing on the anchor site e of the reconnected worldline, e = a without reconnection), on
+// the matrix cores. A workgroup takes up to kGroup worldlines of one (chain, spin), one per
 // wavefront, in lockstep over the slices:
 //   forward:  f~_j as in k_forward_mfma, every row j = 0..L_tau-1 stored (row 0 = delta_a)
-//   backward: u_{L_tau} = delta_a; beta_j = C u_{j+1} C; u_j = W~_j . beta_j / sum
+//   backward: u_{L_tau} = delta_e; beta_j = C u_{j+1} C; u_j = W~_j . beta_j / sum
 //   d log Z / d log W_j(r) = f~_j(r) beta_j(r) / <f~_j, beta_j>   (the smoothing marginal)
 //   d log Z / d t += dtau <A beta_j, f~_j> / <beta_j, f~_j>, A the nearest-neighbour hopping
 //                    matrix: G = exp(t dtau A), so dG/dt = dtau A G and <u, (dG/dt) f> =
@@ -435,8 +436,8 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
     const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, float* __restrict__ filt, float* __restrict__ gpart,
-    double* __restrict__ blk_logz, double* __restrict__ dt_out, int anchor, int32_t* status,
-    const NegPairs neg) {
+    double* __restrict__ blk_logz, double* __restrict__ dt_out, int anchor,
+    const int32_t* __restrict__ perm, int32_t* status, const NegPairs neg) {
     __shared__ float bt[kWaves][1024];   // beta tile of each wavefront, y * 32 + x
     __shared__ float mg[kWaves][1024];   // marginal tile of each wavefront
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -450,9 +451,12 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
     const double coef = g.spin ? c.coef_dn : c.coef_up;
     const double dtau = c.dtau;
     int a = paths[c.path_off + (int64_t)anchor * c.np + p];
-    if (a < 0 || a >= N) {
+    // the ring closes on the anchor site of the reconnected worldline (itself for the identity)
+    int e = paths[c.path_off + (int64_t)anchor * c.np + perm[c.part_off + p]];
+    if (a < 0 || a >= N || e < 0 || e >= N) {
         if (lane == 0 && real) set_status(status, FH_ERR_BAD_PATH, g.chain);
-        a = 0;
+        a = a < 0 || a >= N ? 0 : a;
+        e = e < 0 || e >= N ? 0 : e;
     }
     Split3 C;
     {
@@ -466,7 +470,7 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
     }
     const int x = lane & 31;
     const bool xin = LFIX ? true : x < L;
-    const int ax = a % L, ay = a / L;
+    const int ax = a % L, ay = a / L, ex = e % L, ey = e / L;
     float* rows = filt + c.filt_off + (int64_t)p * L_tau * N;
     // ---- forward pass over the ring, every row stored
     f32x16 F;
@@ -519,11 +523,11 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
         const f32x16 X = circ_step(F, C, neg);
         const f32x16 H = circ_step(X, C, neg);
         float hv = 0.0f;
-        const int ve = (ay >> 3) * 4 + (ay & 3);
+        const int ve = (ey >> 3) * 4 + (ey & 3);
 #pragma unroll
         for (int v = 0; v < 16; ++v)
             if (v == ve) hv = H[v];
-        hv = __shfl(hv, ax + 32 * ((ay >> 2) & 1), 64);
+        hv = __shfl(hv, ex + 32 * ((ey >> 2) & 1), 64);
         la -= log(prod);
         if (real && lane == 0) {
             if (!(hv > 0.0f)) set_status(status, FH_ERR_NONFINITE, g.chain);
@@ -534,7 +538,7 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
     // ---- backward messages
     f32x16 U;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) U[v] = (x == ax && tile_row(lane, v) == ay) ? 1.0f : 0.0f;
+    for (int v = 0; v < 16; ++v) U[v] = (x == ex && tile_row(lane, v) == ey) ? 1.0f : 0.0f;
     double dt = 0.0;
     float* slab = gpart + g.part_off;
     for (int j = L_tau - 1; j >= 0; --j) {
@@ -664,12 +668,12 @@ hipError_t launch_grad_mfma(fh_plan p, const void* aux, const int32_t* paths, in
         hipLaunchKernelGGL(k_grad_mfma<32>, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
                            p->d.group_tasks, p->d.cmat, (const float*)aux, (const float*)p->d.W,
                            p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt,
-                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.status, kNegPairs);
+                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm, p->d.status, kNegPairs);
     else
         hipLaunchKernelGGL(k_grad_mfma<0>, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
                            p->d.group_tasks, p->d.cmat, (const float*)aux, (const float*)p->d.W,
                            p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt,
-                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.status, kNegPairs);
+                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm, p->d.status, kNegPairs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !grad_aux) return e;
     int64_t b = (p->aux_elems + kThreads - 1) / kThreads;

@@ -596,9 +596,6 @@ def test_ffbs_with_reconnections_parity_fp64(lib):
                                                        tail[err > tol], np.nonzero(err > tol)[0])))
             n_cert += check_paths(d, got[c], ref, marg, "reconnected chain %d sweep %d" % (c, s))
     assert n_cert <= 1
-    with pytest.raises(fhmc.FhError) as err:
-        S.logz_grad(A, P, 0)
-    assert err.value.code == fhmc.FH_ERR_UNSUPPORTED
     bad = [q.copy() for q in perms]
     bad[0][0] = bad[0][1]
     with pytest.raises(fhmc.FhError):
@@ -1077,3 +1074,141 @@ def test_windowed_draws_equal_full_row_draws(lib, prec):
     for c in range(len(descs)):
         assert np.array_equal(out["window"][c], out["full"][c]), ("window", c)
         assert np.array_equal(out["fallback"][c], out["full"][c]), ("fallback", c)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mfma3"])
+def test_windowed_draws_on_a_clustering_state(lib, prec):
+    """Sweeps run on from the static start let the field cluster, so that many draws need the
+    wider window or the full row; the windowed kernel must still draw exactly what the full-row
+    kernel draws, sweep after sweep (32 x 32 at L_tau = 160 and 16 x 16 at L_tau = 64). The host
+    mirror of the
+    draw rule, run on the device's filters and draws of one more backward pass, shows that the
+    wider window and the full row were both reached."""
+    fhmc, sampler = lib
+    descs = synth.config_32x32(4.0, 1) + synth.config_16x16_hirsch(1) + [
+        synth.ChainDesc(L=16, L_tau=64, n_up=128, n_dn=128, hs_kind=synth.HS_GAUSS, block_len=0,
+                        t=1.0, U=4.0, dtau=0.0625, seed=70 + i) for i in range(2)]
+    say("windowed draws on a clustering state", prec)
+    Sw = sampler.Sampler(descs, PRECS[prec])
+    Sf = sampler.Sampler(descs, PRECS[prec], fhmc.FH_FLAG_FULL_ROW_DRAW)
+    aux = [synth.initial_aux(d) for d in descs]
+    paths = [synth.initial_paths(d) for d in descs]
+    Aw, Pw = Sw.pack_aux(aux), Sw.pack_paths(paths)
+    Af, Pf = Sf.pack_aux(aux), Sf.pack_paths(paths)
+    for s in range(4):
+        Sw.sweep(Aw, Pw, s, 1)
+        Sf.sweep(Af, Pf, s, 1)
+        gw, gf = Sw.unpack_paths(Pw), Sf.unpack_paths(Pf)
+        for c in range(len(descs)):
+            assert np.array_equal(gw[c], gf[c]), (s, c)
+        assert np.array_equal(Aw.cpu().numpy(), Af.cpu().numpy()), s
+    # which tier decided the draws of one more forward + backward on the clustered state
+    s = 4
+    c = 0
+    d = descs[c]
+    before = Sw.unpack_paths(Pw)
+    Sw.forward_filter(Aw, Pw, s)
+    rows = [Sw.filters(c, p) for p in range(0, d.n_up, 8)]
+    Sw.backward_sample(Pw, s)
+    after = Sw.unpack_paths(Pw)[c]
+    g = np.zeros(d.L)
+    P_D = ctypes.POINTER(ctypes.c_double)
+    fhmc.lib.fh_debug_kernel_table(d.L, d.t, d.dtau, g.ctypes.data_as(P_D))
+    w, go = ctypes.c_int32(), ctypes.c_double()
+    fhmc.lib.fh_debug_window_select(g.ctypes.data_as(P_D), d.L, ctypes.byref(w), ctypes.byref(go))
+    tiers = np.zeros(3, dtype=int)
+    for k, p in enumerate(range(0, d.n_up, 8)):
+        for j in range(1, d.L_tau):   # ring block from slice 0 (sweep 4, B = L_tau)
+            nxt = after[(j + 1) % d.L_tau, p]
+            u = philox_uniforms(d.seed, np.array([p]), j, s)[0]
+            f = np.ascontiguousarray(rows[k][j - 1], dtype=np.float64)
+            site, cert = ctypes.c_int32(), ctypes.c_int32()
+            rc = fhmc.lib.fh_debug_window_draw(d.L, w.value, g.ctypes.data_as(P_D), go.value,
+                                               f.ctypes.data_as(P_D), int(nxt), float(u),
+                                               ctypes.byref(site), ctypes.byref(cert))
+            if rc != 0:   # an FP32 row that underflowed on this state: the draw kept its site
+                assert rc in (fhmc.FH_ERR_ZERO_WEIGHT, fhmc.FH_ERR_NONFINITE)
+                continue
+            assert site.value == after[j, p], (p, j)
+            tiers[cert.value] += 1
+    say("  draws decided by the full row / first window / wider window:", tiers)
+    assert tiers[0] > 0 and tiers[2] > 0 and tiers[1] > 0
+    del before
+    Sw.status()
+    Sf.status()
+    Sw.close()
+    Sf.close()
+
+
+GRAD_BATCH = [synth.config_small_fp64()[0],
+              synth.ChainDesc(L=6, L_tau=8, n_up=5, n_dn=4, hs_kind=synth.HS_HIRSCH, block_len=0,
+                              t=1.0, U=4.0, dtau=0.1, seed=2),
+              synth.ChainDesc(L=32, L_tau=128, n_up=9, n_dn=8, hs_kind=synth.HS_GAUSS,
+                              block_len=0, t=1.0, U=4.0, dtau=0.05, seed=3)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mfma3"])
+def test_logz_grad_with_reconnections_parity(lib, prec):
+    """log Z_path, d/d field and d/d t with random reconnections (each ring closes on the anchor
+    site of the reconnected worldline) against the oracle, on closed-loop worldlines."""
+    fhmc, sampler = lib
+    descs = GRAD_BATCH
+    say("logZ grad with reconnections", prec)
+    S = sampler.Sampler(descs, PRECS[prec])
+    aux, _ = mixed_state(descs, seed=181)
+    perms = random_perms(descs, np.random.default_rng(18))
+    rng = np.random.default_rng(19)
+    paths = [loop_walk_paths(d, q, rng) for d, q in zip(descs, perms)]
+    S.set_permutation(perms)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    for anchor in (0, 5):
+        logZ, gA, gT = S.logz_grad(A, P, anchor)
+        assert S.status() == (0, -1)
+        logZ, gT, gA = logZ.cpu().numpy(), gT.cpu().numpy(), S.unpack_aux(gA)
+        for c, d in enumerate(descs):
+            lz, g, gt, _ = ograd.logz_path_grad(d, aux[c], paths[c], anchor, perm=perms[c])
+            lz_id = ograd.logz_path(d, aux[c], paths[c], anchor)[0]
+            assert abs(lz - lz_id) > 1e-6   # the reconnection changes the answer
+            tol = 1e-10 if prec == "fp64" else 1e-4
+            assert logZ[c] == pytest.approx(lz, rel=1e-12 if prec == "fp64" else 2e-6), c
+            assert np.linalg.norm(gA[c] - g) <= tol * np.linalg.norm(g), c
+            assert gT[c] == pytest.approx(gt, rel=tol), c
+    S.close()
+
+
+def test_mala_field_with_reconnections_parity(lib):
+    """fh_mala_field with reconnections against the oracle's MALA step on the reconnected
+    Z_path (FP64): same decisions up to certified near-ties, same new fields."""
+    from oracle import mala as omala, philox as ophilox
+    fhmc, sampler = lib
+    descs = [synth.ChainDesc(L=4, L_tau=8, n_up=6, n_dn=5, hs_kind=synth.HS_GAUSS, block_len=0,
+                             t=1.0, U=4.0, dtau=0.1, seed=201),
+             synth.ChainDesc(L=6, L_tau=5, n_up=10, n_dn=8, hs_kind=synth.HS_GAUSS, block_len=3,
+                             t=1.0, U=2.0, dtau=0.2, seed=203)]
+    S = sampler.Sampler(descs, fhmc.FH_FP64)
+    aux, _ = mixed_state(descs, seed=211)
+    perms = random_perms(descs, np.random.default_rng(21))
+    rng = np.random.default_rng(22)
+    paths = [loop_walk_paths(d, q, rng) for d, q in zip(descs, perms)]
+    S.set_permutation(perms)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    n_acc = n_rej = n_cert = 0
+    for sweep, eps, anchor in ((0, 0.15, 1), (1, 0.3, 2), (2, 0.08, 0), (3, 1.5, 3)):
+        before = S.unpack_aux(A)
+        acc = S.mala_field(A, P, anchor, eps, sweep)
+        assert S.status() == (0, -1)
+        after = S.unpack_aux(A)
+        for c, d in enumerate(descs):
+            ref, ok, la = omala.mala_step(d, before[c], paths[c], anchor, eps, sweep, perm=perms[c])
+            w0, _, _, _ = ophilox.draw_words(d.seed, np.uint64(0), np.uint64(0), sweep,
+                                             omala.TAG_MALA_ACCEPT)
+            u = float(ophilox.uniform(np.asarray(w0)))
+            if bool(acc[c]) != ok:
+                assert abs(u - np.exp(min(la, 0.0))) < 1e-9, (c, sweep, la, u)
+                n_cert += 1
+                continue
+            n_acc += ok
+            n_rej += not ok
+            assert np.max(np.abs(after[c] - ref)) <= 1e-10, (c, sweep)
+    assert n_cert <= 1 and n_acc >= 1 and n_rej >= 1, (n_acc, n_rej)
+    S.close()
