@@ -906,12 +906,15 @@ __device__ int window2_draw(const T* __restrict__ row, int L, int li, int gbase,
     static_assert(K2 == 3 * SUB, "three sub-chunks per lane");
     const int WW = win_width(kWin2W, L), nwin = WW * WW;
     const float rw = 1.0f / (float)WW;  // (q + 1/2) / WW in FP32 floors exactly for q < 2^12
+    int tx, bx, ty, by;
+    win_axis(cx, kWin2W, L, WW, &tx, &bx);
+    win_axis(cy, kWin2W, L, WW, &ty, &by);
     auto site_of = [&](int k, int* x, int* y) {
         const int q = li * K2 + k;
         const int qq = q < nwin ? q : 0;
         const int qy = (int)(((float)qq + 0.5f) * rw);
-        *x = win_coord(qq - qy * WW, cx, kWin2W, L, WW);
-        *y = win_coord(qy, cy, kWin2W, L, WW);
+        *x = win_at(qq - qy * WW, tx, bx);
+        *y = win_at(qy, ty, by);
     };
     auto wt = [&](int k, T fv, int x, int y) {
         int dx = cx - x, dy = cy - y;
@@ -1058,10 +1061,13 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         const T* row = rows + (int64_t)(j - 1) * N;
         int xs[K], ys[K];
         T fv[K];
+        int tx, bx, ty, by;
+        win_axis(cx, w, L, WW, &tx, &bx);
+        win_axis(cy, w, L, WW, &ty, &by);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            xs[k] = win_coord(qx[k], cx, w, L, WW);
-            ys[k] = win_coord(qy[k], cy, w, L, WW);
+            xs[k] = win_at(qx[k], tx, bx);
+            ys[k] = win_at(qy[k], ty, by);
             fv[k] = row[ys[k] * L + xs[k]];
         }
         __builtin_amdgcn_sched_barrier(0);

@@ -40,15 +40,26 @@ constexpr int kWin2PerLane = 15;          // its ranks per lane: 16 * 15 >= 225
 // Window width along one dimension: 2w + 1, or the whole dimension when that covers it.
 FH_HD inline int win_width(int w, int L) { return 2 * w + 1 < L ? 2 * w + 1 : L; }
 
-// Coordinate of the window's rank q (0 <= q < WW) along one dimension, for a window centred on
-// c: the window's coordinates {c - w, ..., c + w} mod L sorted ascending, so that ranks follow
-// site order. When the window wraps past 0 or L - 1, the wrapped part comes first (or last).
-FH_HD inline int win_coord(int q, int c, int w, int L, int WW) {
-    if (WW == L) return q;
+// Coordinates of the window along one dimension, for a window centred on c: the coordinates
+// {c - w, ..., c + w} mod L sorted ascending, so that ranks follow site order. When the window
+// wraps past 0 or L - 1, the wrapped part comes first (or last). Rank q (0 <= q < WW) sits at
+// q when q <= thr and at q + base otherwise (branch-free in the kernel):
+//   no wrap:          thr = -1,         base = c - w;
+//   wraps below 0:    thr = c + w,      base = L - WW;
+//   wraps past L - 1: thr = c + w - L,  base = L - WW;
+//   window = whole dimension (WW = L): thr = L.
+FH_HD inline void win_axis(int c, int w, int L, int WW, int* thr, int* base) {
     const int lo = c - w, hi = c + w;
-    if (lo < 0) return q <= hi ? q : q + L - WW;
-    if (hi >= L) return q <= hi - L ? q : q + L - WW;
-    return lo + q;
+    const bool wl = lo < 0, wh = hi >= L;
+    *thr = WW == L ? L : wl ? hi : wh ? hi - L : -1;
+    *base = (wl || wh) ? L - WW : lo;
+}
+FH_HD inline int win_at(int q, int thr, int base) { return q + (q <= thr ? 0 : base); }
+
+FH_HD inline int win_coord(int q, int c, int w, int L, int WW) {
+    int thr, base;
+    win_axis(c, w, L, WW, &thr, &base);
+    return win_at(q, thr, base);
 }
 
 // The two margin conditions above, with bound = g_out * kWinMassBound + kWinSlack * window mass.
