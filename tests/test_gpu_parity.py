@@ -1212,3 +1212,38 @@ def test_mala_field_with_reconnections_parity(lib):
             assert np.max(np.abs(after[c] - ref)) <= 1e-10, (c, sweep)
     assert n_cert <= 1 and n_acc >= 1 and n_rej >= 1, (n_acc, n_rej)
     S.close()
+
+
+@pytest.mark.parametrize("prec,L", [("fp64", 2), ("fp64", 3), ("mfma3", 3)])
+def test_u0_fermion_energy_from_device_gradients(lib, prec, L):
+    """The free-fermion canonical energy from the device's reconnected adjoint: one chain per
+    (anchor sites, permutation) of two up worldlines at U = 0, and the sign-weighted average of
+    -(t/beta) d log Z_path / dt over them, weighted by Z_path, against the closed form."""
+    import itertools
+    fhmc, sampler = lib
+    L_tau, dtau, t = 4, 0.25, 1.0
+    N = L * L
+    cases = [(a, pm, sg) for a in itertools.product(range(N), repeat=2)
+             for pm, sg in (((0, 1), 1), ((1, 0), -1))]
+    descs = [synth.ChainDesc(L=L, L_tau=L_tau, n_up=2, n_dn=0, hs_kind=synth.HS_GAUSS,
+                             block_len=0, t=t, U=0.0, dtau=dtau, seed=c)
+             for c in range(len(cases))]
+    say("u0 fermion energy from device gradients", prec, L, len(cases), "chains")
+    S = sampler.Sampler(descs, PRECS[prec])
+    S.set_permutation([np.array(pm) for _, pm, _ in cases])
+    aux = [np.zeros((L_tau, N)) for _ in cases]
+    paths = [np.tile(np.array(a, dtype=np.int32), (L_tau, 1)) for a, _, _ in cases]
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    logZ, _, gT = S.logz_grad(A, P, 0)
+    assert S.status() == (0, -1)
+    logZ, gT = logZ.cpu().numpy(), gT.cpu().numpy()
+    beta = L_tau * dtau
+    w = np.array([sg for _, _, sg in cases]) * np.exp(logZ - logZ.max())
+    energy = float((w * (-t / beta) * gT).sum() / w.sum())
+    ks = 2 * np.pi * np.arange(L) / L
+    eps = (-2 * t * (np.cos(ks)[:, None] + np.cos(ks)[None, :])).ravel()
+    pairs = [(i, j) for i in range(N) for j in range(i + 1, N)]
+    lam = np.array([np.exp(-beta * (eps[i] + eps[j])) for i, j in pairs])
+    ref = float(sum((eps[i] + eps[j]) * l for (i, j), l in zip(pairs, lam)) / lam.sum())
+    assert energy == pytest.approx(ref, rel=1e-10 if prec == "fp64" else 1e-4), (energy, ref)
+    S.close()

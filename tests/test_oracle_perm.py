@@ -140,3 +140,47 @@ def test_local_updates_with_reconnections_preserve_the_joint_law():
     st, pm = to_states(out, perm, M)
     counts = np.bincount(code(st, pm, 4), minlength=len(prob))
     assert chi2_p(counts, prob) > 1e-4
+
+
+def free_fermion_energy(L, t, beta, n):
+    """Canonical energy of n free fermions (one spin) on the periodic L x L lattice: levels
+    eps_k = -2t(cos kx + cos ky), weights of the n-fermion states prod lambda_k over k-subsets."""
+    ks = 2 * np.pi * np.arange(L) / L
+    eps = (-2 * t * (np.cos(ks)[:, None] + np.cos(ks)[None, :])).ravel()
+    num = den = 0.0
+    for sub in itertools.combinations(range(len(eps)), n):
+        e = eps[list(sub)].sum()
+        w = np.exp(-beta * e)
+        num += e * w
+        den += w
+    return num / den
+
+
+@pytest.mark.parametrize("L_tau,dtau", [(3, 0.3), (4, 0.25)])
+def test_u0_fermion_energy_from_reconnected_gradients(L_tau, dtau):
+    """At U = 0 the sign-weighted average, over every (anchor sites, permutation) of two up
+    worldlines weighted by prod_p Z_p, of the Rao-Blackwellised kinetic energy
+    -(t/beta) sum_p d log Z_p / dt (Z_p closing on the anchor of perm[p]) is the canonical energy
+    of two free fermions: the permutation sum antisymmetrises the propagator."""
+    from oracle import grad as ograd
+    d = synth.ChainDesc(L=2, L_tau=L_tau, n_up=2, n_dn=0, hs_kind=synth.HS_GAUSS, block_len=0,
+                        t=1.0, U=0.0, dtau=dtau, seed=1)
+    aux = np.zeros((L_tau, d.N))
+    beta = L_tau * dtau
+    num = den = 0.0
+    for a in itertools.product(range(d.N), repeat=2):
+        paths = np.tile(np.array(a), (L_tau, 1))
+        for pm, sg in (((0, 1), 1), ((1, 0), -1)):
+            lz, _, dt, _ = ograd.logz_path_grad(d, aux, paths, 0, perm=np.array(pm))
+            w = sg * np.exp(lz)
+            num += w * (-d.t / beta) * dt
+            den += w
+    assert num / den == pytest.approx(free_fermion_energy(2, d.t, beta, 2), rel=1e-11)
+    # without the permutation sum the same average gives distinguishable particles' energy
+    num_b = den_b = 0.0
+    for a in itertools.product(range(d.N), repeat=2):
+        paths = np.tile(np.array(a), (L_tau, 1))
+        lz, _, dt, _ = ograd.logz_path_grad(d, aux, paths, 0)
+        num_b += np.exp(lz) * (-d.t / beta) * dt
+        den_b += np.exp(lz)
+    assert abs(num_b / den_b - free_fermion_energy(2, d.t, beta, 2)) > 1e-3
