@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_mfma3": 2}
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = {"forward": {"fp32_mfma3": "fh_mfma.hip", "fp32": "fh_kernels.hip",
-                              "fp64": "fh_kernels.hip"},
+                              "fp64": "fh_mfma.hip"},
                   "backward": {"fp32_mfma3": "fh_kernels.hip", "fp32": "fh_kernels.hip",
                                "fp64": "fh_kernels.hip"}}
 
@@ -438,8 +438,9 @@ def main():
     algo = {"forward": rows * N * rsz + w_bytes,
             "backward": rows * (read_per_row + 4)}                 # + the drawn site (int32)
     times = {"forward": fwd_ms, "backward": bwd_ms}
-    names = {"forward": "forward filter (%s)" % ("k_forward_mfma2" if args.precision == "fp32_mfma3"
-                                                 else "k_forward_fft"),
+    fwd_kernel = {"fp32_mfma3": "k_forward_mfma2", "fp64": "k_forward_dmfma"}.get(args.precision,
+                                                                                 "k_forward_fft")
+    names = {"forward": "forward filter (%s)" % fwd_kernel,
              "backward": "backward sampler (%s)" % ("k_backward_l32" if args.full_row_draw
                                                     else "k_backward_win")}
     roofs = {}
@@ -495,10 +496,22 @@ def main():
         k = max(2, args.steps // 4)
         ms64 = time_sweeps(S64, A6, P6, A06, P06, 1, k, stream) / k
         extra["fp64_plain"] = {"ms_per_step": round(ms64, 4),
-                               "value": sites / (ms64 / 1e3)}
+                               "value": sites / (ms64 / 1e3),
+                               "convolution": "FP64 circulant on the matrix cores"}
         extra["speedup_vs_fp64_plain"] = round(ms64 / ms_step, 3)
         S64.close()
         log("  fp64 plain %.3f ms/sweep" % ms64)
+        # the same FP64 sweep with FFT convolutions
+        S64 = Sampler(descs, fhmc.FH_FP64, fhmc.FH_FLAG_GRAPH | fhmc.FH_FLAG_FFT_CONV)
+        A06, P06 = S64.pack_aux(aux), S64.pack_paths(paths)
+        A6, P6 = A06.clone(), P06.clone()
+        torch.cuda.synchronize()
+        time_sweeps(S64, A6, P6, A06, P06, 0, 1, stream)
+        k = 2
+        ms64f = time_sweeps(S64, A6, P6, A06, P06, 1, k, stream) / k
+        extra["fp64_fft_plain"] = {"ms_per_step": round(ms64f, 4), "value": sites / (ms64f / 1e3)}
+        S64.close()
+        log("  fp64 FFT plain %.3f ms/sweep" % ms64f)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -77,6 +77,10 @@ enum fh_flags {
     FH_FLAG_AUTOTUNE = 2, /* fh_init times every radix-2/3/4 stage order of each distinct L on
                             the device (FFT precisions) and keeps the fastest; without it the
                             default order (4s, then a 2, then 3s) is used                    */
+    FH_FLAG_FFT_CONV = 8, /* FH_FP64 plans convolve every chain with the FP64 FFT. Without it
+                            chains with L <= 32 use the circulant C f C on the FP64 matrix cores
+                            (every product positive, so filter tails keep their relative
+                            accuracy); larger L always use the FFT                             */
     FH_FLAG_FULL_ROW_DRAW = 4 /* backward draws scan every site of the filter row. Without it a
                             chain whose hopping kernel decays fast enough draws from the window
                             of sites within w <= 3 steps of the next slice's site and certifies

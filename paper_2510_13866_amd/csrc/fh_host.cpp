@@ -84,6 +84,19 @@ double bf16_val(uint16_t b) {
 // Split-bf16 operand of the circulant C[i][j] = g(i - j mod L) (zero outside L x L, 32 x 32
 // tile) in the lane order the MFMA forward filter consumes: term t (x = h + m + l), K chunk q,
 // lane, element e holds term_t(C[R][lane % 32]) with R = 16q + 8(e/4) + 4(lane/32) + e%4.
+// B operands of the FP64 circulant for v_mfma_f64_16x16x4_f64: slot (4 K + r) * 2 + J, lane l
+// holds C[16 K + 4 r + l / 16][16 J + l % 16], C[k][j] = g((k - j) mod L) inside L x L, else 0.
+void build_cmat64(int L, const double* g, double* out) {
+    for (int K = 0; K < 2; ++K)
+        for (int r = 0; r < 4; ++r)
+            for (int J = 0; J < 2; ++J)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int k = 16 * K + 4 * r + lane / 16, j = 16 * J + lane % 16;
+                    out[((4 * K + r) * 2 + J) * 64 + lane] =
+                        (L <= 32 && k < L && j < L) ? g[((k - j) % L + L) % L] : 0.0;
+                }
+}
+
 void build_cmat(int L, const double* g, uint16_t* out) {
     if (L > 32) {
         memset(out, 0, sizeof(uint16_t) * kCmatPerChain);
@@ -131,7 +144,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 }
 
 void free_device(fh::Device& d) {
-    void* ptrs[] = {d.chains, d.tables, d.cmat, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
+    void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
                     d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign,
                     d.status, d.sweep};
     for (void* p : ptrs)
@@ -186,7 +199,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (!descs || n_chains < 1) return FH_ERR_INVALID_ARG;
     if (precision != FH_FP64 && precision != FH_FP32 && precision != FH_FP32_MFMA3)
         return FH_ERR_INVALID_ARG;
-    if (flags & ~(uint32_t)(FH_FLAG_GRAPH | FH_FLAG_AUTOTUNE | FH_FLAG_FULL_ROW_DRAW))
+    if (flags & ~(uint32_t)(FH_FLAG_GRAPH | FH_FLAG_AUTOTUNE | FH_FLAG_FULL_ROW_DRAW |
+                            FH_FLAG_FFT_CONV))
         return FH_ERR_INVALID_ARG;
     for (int c = 0; c < n_chains; ++c) {
         int v = validate(descs[c], precision);
@@ -251,11 +265,14 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->total_slices = slices;
     p->tables.assign(tab, 0.0);
     p->cmat.assign((size_t)kCmatPerChain * n_chains, 0);
+    p->cmat64.assign((size_t)kCmat64PerChain * n_chains, 0.0);
     std::vector<char> windowed((size_t)n_chains, 0);
     for (int c = 0; c < n_chains; ++c) {
         ChainInfo& ci = p->chains[c];
         build_tables(descs[c], p->tables.data() + ci.tab_off);
         build_cmat(descs[c].L, p->tables.data() + tab_g(ci), p->cmat.data() + (size_t)kCmatPerChain * c);
+        build_cmat64(descs[c].L, p->tables.data() + tab_g(ci),
+                     p->cmat64.data() + (size_t)kCmat64PerChain * c);
         windowed[c] = win_select(p->tables.data() + tab_g(ci), ci.L, &ci.win_w, &ci.win_gout) &&
                       ci.L <= kWinMaxL && !(flags & FH_FLAG_FULL_ROW_DRAW);
         ci.win_gout2 = win_bound_for(p->tables.data() + tab_g(ci), ci.L, kWin2W);
@@ -297,7 +314,18 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         for (int q = 0; q < ci.np; ++q)
             for (int b = 0; b < ci.nb; ++b) draw.push_back({c, q, b, 0});
     }
-    p->n_fwd_tasks = (int32_t)fwd.size();
+    // FP64 plans: chains with L <= 32 on the FP64 circulant, the others on the FFT
+    auto dmfma = [&](int c) {
+        return precision == FH_FP64 && !(flags & FH_FLAG_FFT_CONV) && p->chains[c].L <= 32;
+    };
+    std::vector<PairTask> fwdf;
+    std::vector<DrawTask> fwdd;
+    for (const PairTask& t : fwd)
+        if (!dmfma(t.chain)) fwdf.push_back(t);
+    for (const DrawTask& t : draw)
+        if (dmfma(t.chain)) fwdd.push_back(t);
+    p->n_fwd_tasks = (int32_t)fwdf.size();
+    p->n_fwdd_tasks = (int32_t)fwdd.size();
     p->n_grad_tasks = (int32_t)grad.size();
     p->n_draw_tasks = (int32_t)draw.size();
     std::vector<PairTask> fwd32;
@@ -334,7 +362,9 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.filt, rs * (size_t)filt);
     if (e == hipSuccess) e = dalloc(&dv.blk_logz, sizeof(double) * (size_t)blk);
     if (e == hipSuccess) e = dalloc(&dv.dt, sizeof(double) * (size_t)part);
-    if (e == hipSuccess) e = dalloc(&dv.fwd_tasks, sizeof(PairTask) * fwd.size());
+    if (e == hipSuccess) e = dalloc(&dv.fwd_tasks, sizeof(PairTask) * fwdf.size());
+    if (e == hipSuccess) e = dalloc(&dv.fwdd_tasks, sizeof(DrawTask) * fwdd.size());
+    if (e == hipSuccess) e = dalloc(&dv.cmat64, sizeof(double) * p->cmat64.size());
     if (e == hipSuccess) e = dalloc(&dv.grad_tasks, sizeof(PairTask) * grad.size());
     if (e == hipSuccess) e = dalloc(&dv.draw_tasks, sizeof(DrawTask) * draw.size());
     if (e == hipSuccess) e = dalloc(&dv.group_tasks, sizeof(GroupTask) * groups.size());
@@ -369,7 +399,9 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     }
     if (e == hipSuccess) e = hipMemcpy(dv.chains, p->chains.data(), sizeof(ChainInfo) * n_chains, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.cmat, p->cmat.data(), sizeof(uint16_t) * p->cmat.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dv.fwd_tasks, fwd.data(), sizeof(PairTask) * fwd.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !fwdf.empty()) e = hipMemcpy(dv.fwd_tasks, fwdf.data(), sizeof(PairTask) * fwdf.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !fwdd.empty()) e = hipMemcpy(dv.fwdd_tasks, fwdd.data(), sizeof(DrawTask) * fwdd.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dv.cmat64, p->cmat64.data(), sizeof(double) * p->cmat64.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.grad_tasks, grad.data(), sizeof(PairTask) * grad.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.draw_tasks, draw.data(), sizeof(DrawTask) * draw.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.group_tasks, groups.data(), sizeof(GroupTask) * groups.size(), hipMemcpyHostToDevice);
@@ -452,7 +484,9 @@ static hipError_t enqueue_forward(fh_plan p, const void* aux, const int32_t* pat
     hipError_t e = launch_potentials(p, aux, s);
     if (e != hipSuccess) return e;
     if (p->precision == FH_FP32_MFMA3) return launch_forward_mfma(p, aux, paths, s);
-    return launch_forward(p, aux, paths, s);
+    e = launch_forward_dmfma(p, aux, paths, s);  // FP64 plans, chains with L <= 32
+    if (e != hipSuccess) return e;
+    return p->n_fwd_tasks > 0 ? launch_forward(p, aux, paths, s) : hipSuccess;
 }
 
 int fh_forward_filter(fh_plan p, const void* aux, const int32_t* paths, uint64_t sweep,
@@ -685,6 +719,8 @@ int fh_set_hopping(fh_plan p, const double* t) {
         build_tables(p->descs[c], p->tables.data() + ci.tab_off);
         build_cmat(p->descs[c].L, p->tables.data() + tab_g(ci),
                    p->cmat.data() + (size_t)kCmatPerChain * c);
+        build_cmat64(p->descs[c].L, p->tables.data() + tab_g(ci),
+                     p->cmat64.data() + (size_t)kCmat64PerChain * c);
         // the window keeps its width; its outside bound follows the new kernel
         ci.win_gout = win_bound_for(p->tables.data() + tab_g(ci), ci.L, ci.win_w) *
                       p->win_bound_scale;
@@ -696,6 +732,8 @@ int fh_set_hopping(fh_plan p, const double* t) {
     FH_TRY(hipMemcpy(p->d.tables, p->tables.data(), sizeof(double) * p->tables.size(),
                      hipMemcpyHostToDevice));
     FH_TRY(hipMemcpy(p->d.cmat, p->cmat.data(), sizeof(uint16_t) * p->cmat.size(),
+                     hipMemcpyHostToDevice));
+    FH_TRY(hipMemcpy(p->d.cmat64, p->cmat64.data(), sizeof(double) * p->cmat64.size(),
                      hipMemcpyHostToDevice));
     p->have_filters = false;
     return FH_OK;

@@ -44,6 +44,7 @@ FH_HD inline int64_t tab_g(const ChainInfo& c) { return c.tab_off + 2 * c.N; }
 FH_HD inline int64_t tab_tw(const ChainInfo& c) { return c.tab_off + 2 * c.N + c.L; }
 inline int64_t tab_size(int L) { return 2 * (int64_t)L * L + L + 2 * L; }
 constexpr int kCmatPerChain = 3 * 2 * 64 * 8;
+constexpr int kCmat64PerChain = 16 * 64;
 
 // Block of a sweep: start slice and length (the schedule of fh.h).
 FH_HD inline void block_of(const ChainInfo& c, uint64_t sweep, int b, int* start, int* len) {
@@ -78,6 +79,8 @@ struct Device {
     ChainInfo* chains = nullptr;
     double* tables = nullptr;
     uint16_t* cmat = nullptr;  // per chain: split-bf16 circulant operand [3][2][64][8]
+    double* cmat64 = nullptr;  // per chain: FP64 circulant B operands [16][64]
+    DrawTask* fwdd_tasks = nullptr;  // FP64 circulant forward: worldline blocks of L <= 32 chains
     void* W = nullptr;        // [2][sum L_tau*N] in plan precision (up, then down)
     double* wshift = nullptr; // [2][total slices]: log W = log W~ + wshift per (spin, slice)
     void* filt = nullptr;     // filter workspace, plan precision
@@ -116,6 +119,7 @@ struct fh_plan_s {
     std::vector<fh::ChainInfo> chains;
     std::vector<double> tables;
     std::vector<uint16_t> cmat;
+    std::vector<double> cmat64;
     int64_t aux_elems = 0, path_elems = 0, particles = 0, blk_elems = 0, filt_elems = 0;
     int32_t n_fwd_tasks = 0, n_grad_tasks = 0, n_draw_tasks = 0;
     int64_t total_slices = 0;
@@ -123,6 +127,7 @@ struct fh_plan_s {
     int32_t n_fwd32_tasks = 0, n_fwdx_tasks = 0, n_draw32_tasks = 0;
     int32_t max_N_x = 0;  // largest N among the chains of drawx_tasks
     int32_t n_draww_tasks = 0, n_drawx_tasks = 0;
+    int32_t n_fwdd_tasks = 0;  // FP64 circulant forward tasks (the FFT takes n_fwd_tasks pairs)
     double win_bound_scale = 1.0;  // test hook: >= 1 inflates every window bound
     int64_t gpart_elems = 0;
     int64_t total_sites = 0;  // sum of N over the chains
@@ -150,6 +155,7 @@ hipError_t launch_set_sweep(fh_plan p, uint64_t sweep, hipStream_t s);
 hipError_t launch_bump_sweep(fh_plan p, hipStream_t s);
 hipError_t launch_potentials(fh_plan p, const void* aux, hipStream_t s);
 hipError_t launch_forward(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s);
+hipError_t launch_forward_dmfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s);
 hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s);
 hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s);
 hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s);

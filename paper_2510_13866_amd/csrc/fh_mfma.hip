@@ -251,6 +251,145 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     }
 }
 
+// ---- FP64 circulant on the FP64 matrix cores -------------------------------------------------
+//
+// v_mfma_f64_16x16x4_f64 reads A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k, and
+// leaves D[i][j] in lane j + 16 (i mod 4), register i / 4 (checked on the device). A 32 x 32
+// matrix in that accumulator layout is four 16 x 16 tiles (I, J), tile index 2 I + J; element
+// (16 I + 4 r + lane / 16, 16 J + lane % 16) sits in register r of tile (I, J). Register r of
+// tile (K, I) is then directly the A operand of X^T with K-index 16 K + 4 r + lane / 16, so
+//   (X^T C)(I, J) = sum over K, r of mfma(X(K, I)[r], Cb[(4 K + r) * 2 + J])
+// with Cb the matching B operands of the circulant C[k][j] = g((k - j) mod L) (zero outside
+// L x L): 32 products per multiplication, no operand splitting, every product and sum in FP64.
+// Two multiplications give (F^T C)^T C = C F C, C being symmetric.
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
+struct Tile64 {
+    f64x4 t[4];
+};
+
+__device__ inline Tile64 circ64(const Tile64& X, const double (&Cb)[16]) {
+    Tile64 Y;
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J) {
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int K = 0; K < 2; ++K)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X.t[2 * K + I][r],
+                                                               Cb[(4 * K + r) * 2 + J], acc, 0, 0, 0);
+            Y.t[2 * I + J] = acc;
+        }
+    return Y;
+}
+
+__device__ inline double wave_sum_f64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wavefront per (chain, worldline, block) of an FP64 plan with L <= 32: the forward
+// recursion of one block with the FP64 circulant,
+//   f~_0 = delta_a; h_j = W~_{start+j} . (C f~_{j-1} C); c_j = sum h_j; f~_j = h_j / c_j
+//   log Z = coef aux_start(a) + sum_j (log c_j + m_{start+j}) + log (C f~_{len-1} C)(e),
+// rows f~_j (j >= 1) stored as FP64 rows of N values, exactly where the FFT path stores them.
+// Padded positions (x or y >= L) stay exact zeros: C is zero outside the lattice.
+__global__ __launch_bounds__(kThreads) void k_forward_dmfma(
+    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
+    const double* __restrict__ cmat64, const double* __restrict__ aux, const double* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, double* __restrict__ filt,
+    double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    const int lane = threadIdx.x & 63;
+    const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
+    if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
+    const DrawTask t = tasks[task];
+    const ChainInfo& c = chains[t.chain];
+    int start, len;
+    block_of(c, *sweep_ptr, t.block, &start, &len);
+    const int L = c.L, N = c.N, L_tau = c.L_tau;
+    const int spin = t.p >= c.n_up ? 1 : 0;
+    const double* Wsp = W + spin * aux_elems + c.aux_off;
+    const double* shift = wshift + spin * total_slices + c.slice_off;
+    const double coef = spin ? c.coef_dn : c.coef_up;
+    const int32_t* pc = paths + c.path_off;
+    int a = pc[(int64_t)start * c.np + t.p];
+    // a block that runs past slice L_tau - 1 ends on the worldline its owner reconnects to
+    const int qe = start + len >= L_tau ? perm[c.part_off + t.p] : t.p;
+    int e = pc[(int64_t)((start + len) % L_tau) * c.np + qe];
+    if (a < 0 || a >= N || e < 0 || e >= N) {
+        if (lane == 0) set_status(status, FH_ERR_BAD_PATH, t.chain);
+        a = (a < 0 || a >= N) ? 0 : a;
+        e = (e < 0 || e >= N) ? 0 : e;
+    }
+    double Cb[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Cb[q] = cmat64[((int64_t)t.chain * 16 + q) * 64 + lane];
+    const int xl = lane & 15, yl = lane >> 4;
+    // element (tile q, register r): x = 16 (q & 1) + xl, y = 16 (q >> 1) + 4 r + yl
+    auto xo = [&](int q) { return 16 * (q & 1) + xl; };
+    auto yo = [&](int q, int r) { return 16 * (q >> 1) + 4 * r + yl; };
+    auto inside = [&](int q, int r) { return xo(q) < L && yo(q, r) < L; };
+    const int ax = a % L, ay = a / L;
+    Tile64 F;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) F.t[q][r] = (xo(q) == ax && yo(q, r) == ay) ? 1.0 : 0.0;
+    double la = coef * aux[c.aux_off + (int64_t)start * N + a];
+    double* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+    for (int j = 1; j < len; ++j) {
+        const int l = (start + j) % L_tau;
+        const double* Wl = Wsp + (int64_t)l * N;
+        double w[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)  // a padded position reads site 0 (in bounds), times 0
+                w[4 * q + r] = Wl[inside(q, r) ? yo(q, r) * L + xo(q) : 0];
+        const Tile64 H = circ64(circ64(F, Cb), Cb);
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                F.t[q][r] = H.t[q][r] * w[4 * q + r];
+                sum += F.t[q][r];
+            }
+        const double tot = wave_sum_f64(sum);
+        if (!(tot > 0.0) || !isfinite(tot))
+            if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
+        const double inv = 1.0 / tot;
+        la += log(tot) + shift[l];
+        double* row = rows + (int64_t)(j - 1) * N;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                F.t[q][r] *= inv;
+                if (inside(q, r)) row[yo(q, r) * L + xo(q)] = F.t[q][r];
+            }
+    }
+    // end weight (C f~ C)(e)
+    const Tile64 H = circ64(circ64(F, Cb), Cb);
+    const int ex = e % L, ey = e / L;
+    const int qe2 = 2 * (ey >> 4) + (ex >> 4), re = (ey & 15) >> 2;
+    double hv = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (q == qe2 && r == re) hv = H.t[q][r];
+    hv = __shfl(hv, (ex & 15) + 16 * (ey & 3), 64);
+    if (lane == 0) {
+        if (!(hv > 0.0)) set_status(status, FH_ERR_NONFINITE, t.chain);
+        blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log(hv);
+    }
+}
+
 // Two worldlines of the same (chain, spin, block) per wavefront: the W slice is shared and the
 // two GEMM chains are independent, so one worldline's bf16 splitting, normalisation and stores
 // overlap the other's matrix-core work. Same arithmetic as k_forward_mfma, step for step.
@@ -636,6 +775,16 @@ __global__ __launch_bounds__(kThreads) void k_gpart_reduce(const ChainInfo* __re
 }
 
 }  // namespace
+
+hipError_t launch_forward_dmfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
+    if (p->n_fwdd_tasks == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((p->n_fwdd_tasks + kWaves - 1) / kWaves);
+    hipLaunchKernelGGL(k_forward_dmfma, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                       p->d.fwdd_tasks, p->n_fwdd_tasks, p->d.cmat64, (const double*)aux,
+                       (const double*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices, paths,
+                       p->d.perm, (double*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
+    return hipGetLastError();
+}
 
 hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
     // L = 32 chains: worldline pairs per wavefront; other chains: one padded tile each

@@ -38,6 +38,7 @@ FH_FLAG_NONE = 0
 FH_FLAG_GRAPH = 1
 FH_FLAG_AUTOTUNE = 2
 FH_FLAG_FULL_ROW_DRAW = 4
+FH_FLAG_FFT_CONV = 8
 
 
 class fh_chain_desc(ctypes.Structure):

@@ -33,11 +33,16 @@ def lib(gpu):
     return fhmc, sampler
 
 
-PRECS = {"fp64": 0, "fp32": 1, "mfma3": 2}
+PRECS = {"fp64": 0, "fp32": 1, "mfma3": 2, "fp64fft": 0}
+
+
+def plan_flags(fhmc, prec, flags=0):
+    """fp64 plans convolve on the FP64 matrix cores (L <= 32); fp64fft forces the FP64 FFT."""
+    return flags | (fhmc.FH_FLAG_FFT_CONV if prec == "fp64fft" else 0)
 # normwise filter tolerance per precision: FP64 plain, FP32 FFT (its round-off drifts
 # coherently over many slices, measured ~5e-5 at 160 slices), FP32 split-bf16 MFMA circulant
-FILTER_TOL = {"fp64": 1e-11, "fp32": 2e-5, "mfma3": 1e-5}
-FILTER_TOL_FULL = {"fp64": 1e-11, "fp32": 2e-4, "mfma3": 1e-5}
+FILTER_TOL = {"fp64": 1e-11, "fp64fft": 1e-11, "fp32": 2e-5, "mfma3": 1e-5}
+FILTER_TOL_FULL = {"fp64": 1e-11, "fp64fft": 1e-11, "fp32": 2e-4, "mfma3": 1e-5}
 
 
 MIXED = [
@@ -120,9 +125,9 @@ def logz_tol(prec, ref_lz, tail, n_slices):
     filter's precision per slice, so it grows with the number of slices summed into log Z),
     plus the FFT's resolution limit along the block (fft_depth). The MFMA circulant works with
     positive products only, so it has no such limit."""
-    eps = {"fp64": 1e-15, "fp32": 6e-8, "mfma3": 0.0}[prec]
-    unit = 1.2e-16 if prec == "fp64" else 6e-8
-    floor = 1e-12 if prec == "fp64" else 2e-6
+    eps = {"fp64": 1e-15, "fp64fft": 1e-15, "fp32": 6e-8, "mfma3": 0.0}[prec]
+    unit = 1.2e-16 if prec.startswith("fp64") else 6e-8
+    floor = 1e-12 if prec.startswith("fp64") else 2e-6
     return floor * (1 + np.abs(ref_lz)) + 4 * unit * n_slices + 10 * eps * tail
 
 
@@ -142,13 +147,13 @@ def check_paths(desc, got, ref, margins, what):
     return len(bad)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "mfma3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp64fft", "fp32", "mfma3"])
 def test_forward_filter_parity_mixed_batch(lib, prec):
     fhmc, sampler = lib
     precision = PRECS[prec]
     descs = MIXED
     say("forward parity", prec, [(d.L, d.L_tau, d.n_up, d.n_dn, d.block_len) for d in descs])
-    S = sampler.Sampler(descs, precision)
+    S = sampler.Sampler(descs, precision, plan_flags(fhmc, prec))
     aux, paths = mixed_state(descs)
     A, P = S.pack_aux(aux), S.pack_paths(paths)
     for s in (0, 1, 3):
@@ -165,11 +170,12 @@ def test_forward_filter_parity_mixed_batch(lib, prec):
     S.close()
 
 
-def test_backward_sample_parity_fp64(lib):
+@pytest.mark.parametrize("prec", ["fp64", "fp64fft"])
+def test_backward_sample_parity_fp64(lib, prec):
     fhmc, sampler = lib
     descs = MIXED
-    say("backward parity fp64")
-    S = sampler.Sampler(descs, fhmc.FH_FP64)
+    say("backward parity", prec)
+    S = sampler.Sampler(descs, fhmc.FH_FP64, plan_flags(fhmc, prec))
     aux, paths = mixed_state(descs, seed=3)
     A, P = S.pack_aux(aux), S.pack_paths(paths)
     n_cert = 0
@@ -839,7 +845,7 @@ def test_batch_invariance(lib):
         Sa.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "mfma3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp64fft", "fp32", "mfma3"])
 def test_full_size_sampled_parity(lib, prec):
     """32x32, L_tau=160, 512+512 worldlines, 2 chains (the benchmark's shape and launch):
     log Z of every particle against the oracle on a sample of particles, their filters and,
@@ -848,7 +854,7 @@ def test_full_size_sampled_parity(lib, prec):
     precision = PRECS[prec]
     descs = synth.config_32x32(4.0, n_chains=2)
     say("full size sampled parity", prec)
-    S = sampler.Sampler(descs, precision)
+    S = sampler.Sampler(descs, precision, plan_flags(fhmc, prec))
     aux = [synth.initial_aux(d) for d in descs]
     paths = [synth.initial_paths(d) for d in descs]
     A, P = S.pack_aux(aux), S.pack_paths(paths)
@@ -859,14 +865,14 @@ def test_full_size_sampled_parity(lib, prec):
     worst = 0.0
     for c, d in enumerate(descs):
         ref_lz, ref_rows = oracle_forward(d, aux[c], paths[c], s, sample)
-        tol_lz = 1e-12 if prec == "fp64" else 2e-6
+        tol_lz = 1e-12 if prec.startswith("fp64") else 2e-6
         assert np.allclose(logZ[c][sample], ref_lz, rtol=tol_lz), c
         for k, p in enumerate(sample):
             err = rel_row_err(S.filters(c, p), ref_rows[k])
             worst = max(worst, err)
             assert err <= FILTER_TOL_FULL[prec], (c, p, err)
     say("  worst filter error", prec, worst)
-    if prec == "fp64":
+    if prec.startswith("fp64"):
         before = S.unpack_paths(P)
         S.backward_sample(P, s)
         got = S.unpack_paths(P)
