@@ -734,11 +734,8 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
     if (err != 0 && lane == 0) set_status(status, err, t.chain);  // the block's first error
 }
 
-// Full-row draw of one 16-lane group (the draw rule of k_backward: the first site in site order
-// whose cumulative weight exceeds u times the total, else the last site with a positive weight).
-// Lane li owns the M contiguous sites from li M. Weights max(f, 0) g(dy) g(dx) about (cx, cy).
-// On a zero or non-finite total the current site is kept and *err records the first error.
-__device__ inline double group_scan_incl(double v) {  // inclusive scan within a DPP row of 16
+// Inclusive scan within a DPP row of 16 lanes.
+__device__ inline double group_scan_incl(double v) {
     v += dpp_f64<0x111>(v);
     v += dpp_f64<0x112>(v);
     v += dpp_f64<0x114>(v);
@@ -746,152 +743,86 @@ __device__ inline double group_scan_incl(double v) {  // inclusive scan within a
     return v;
 }
 
-// Rows of up to 1024 sites (M <= 64): up to eight chunks of 8 sites per lane, the loads of a
-// chunk issued together; the chunk sums stay in registers so that the crossing is re-scanned in
-// one chunk only.
+// Full-row draw by the whole wavefront for one group's worldline (the draw rule of k_backward:
+// the first site in site order whose cumulative weight exceeds u times the total, else the last
+// site with a positive weight). Lane k owns the per = ceil(N / 64) contiguous sites from k per;
+// the weights max(f, 0) g(dy) g(dx) are taken about (cx, cy). Every argument is wavefront
+// uniform. On a zero or non-finite total the current site is kept and *bad gets the error.
 template <typename T>
-__device__ int row_draw_chunked(const T* __restrict__ row, int N, int L, int M, int li, int gbase,
-                                int cx, int cy, const double* g, double u, int cur, int* err) {
-    constexpr int C = 8;
-    const int i0 = li * M;
-    const int cnt = max(0, min(M, N - i0));
-    const int nch = (cnt + C - 1) / C;
-    int x = i0 % L, y = i0 / L;
-    int dy = cy - y;
-    dy += dy < 0 ? L : 0;
-    double gy = g[dy];
-    double cs[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int lastpos = -1;
-#pragma unroll 1
-    for (int ch = 0; ch < nch; ++ch) {
-        T v[C];
-#pragma unroll
-        for (int k = 0; k < C; ++k) v[k] = row[min(i0 + ch * C + k, N - 1)];
-        double sum = 0.0;
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const int m = ch * C + k;
-            if (m < cnt) {
-                int dx = cx - x;
-                dx += dx < 0 ? L : 0;
-                const double fm = (double)v[k];
-                const double wm = (fm > 0.0 ? fm : 0.0) * (gy * g[dx]);
-                sum += wm;
-                if (wm > 0.0) lastpos = i0 + m;
-                if (++x == L) {
-                    x = 0;
-                    ++y;
-                    dy = cy - y;
-                    dy += dy < 0 ? L : 0;
-                    gy = g[dy < L ? dy : 0];
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) cs[q] = ch == q ? sum : cs[q];  // static register indices
-    }
-    double tot = 0.0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) tot += cs[q];
-    const double incl = group_scan_incl(tot);
-    const double excl = dpp_f64<0x111>(incl);
-    const double total = __shfl(incl, gbase + 15, 64);
-    if (!(total > 0.0) || !isfinite(total)) {
-        if (*err == 0) *err = isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE;
-        return cur;
-    }
-    const double Tq = u * total;
-    const uint32_t fm = (uint32_t)(__ballot(incl > Tq && tot > 0.0) >> gbase) & 0xFFFFu;
-    int pick = -1;
-    if (fm && li == __ffs((int)fm) - 1) {
-        // the chunk holding the crossing (the last one if rounding between the two summation
-        // orders leaves none), then the first site in it above Tq
-        double run = excl, before = excl;
-        int c_hit = -1;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            if (c_hit < 0) {
-                if (run + cs[q] > Tq) {
-                    c_hit = q;
-                    before = run;
-                } else {
-                    run += cs[q];
-                }
-            }
-        }
-        if (c_hit < 0) {
-            c_hit = max(nch - 1, 0);
-            before = excl;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) before += q < c_hit ? cs[q] : 0.0;
-        }
-        const int m0 = C * c_hit;
-        int xx = (i0 + m0) % L, yy = (i0 + m0) / L;
-        int last_in = -1;
-        T v[C];
-#pragma unroll
-        for (int k = 0; k < C; ++k) v[k] = row[min(i0 + m0 + k, N - 1)];
-        run = before;
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            const int m = m0 + k;
-            if (m < cnt && pick < 0) {
-                int dx = cx - xx, dyy = cy - yy;
-                dx += dx < 0 ? L : 0;
-                dyy += dyy < 0 ? L : 0;
-                const double fv = (double)v[k];
-                const double wm = (fv > 0.0 ? fv : 0.0) * (g[dyy] * g[dx]);
-                run += wm;
-                if (wm > 0.0) last_in = i0 + m;
-                if (run > Tq) pick = i0 + m;
-                if (++xx == L) {
-                    xx = 0;
-                    ++yy;
-                }
-            }
-        }
-        if (pick < 0) pick = last_in >= 0 ? last_in : lastpos;  // rounding between sum orders
-    }
-    if (fm) return __shfl(pick, gbase + __ffs((int)fm) - 1, 64);
-    const uint32_t lm = (uint32_t)(__ballot(lastpos >= 0) >> gbase) & 0xFFFFu;
-    return lm ? __shfl(lastpos, gbase + 31 - __clz((int)lm), 64) : cur;
-}
-
-// Any row length: two plain passes over the lane's sites.
-template <typename T>
-__device__ int row_draw_plain(const T* __restrict__ row, int N, int L, int M, int li, int gbase,
-                              int cx, int cy, const double* g, double u, int cur, int* err) {
-    const int i0 = li * M, i1 = min(i0 + M, N);
-    auto weight = [&](int i) {
-        const int x = i % L, y = i / L;
+__device__ int wave_row_draw(const T* __restrict__ row, int N, int L, int cx, int cy,
+                             const double* g, double u, int cur, int lane, int* bad) {
+    constexpr int C = 8;  // loads in flight per lane (register budget of the caller)
+    const int per = (N + 63) >> 6;
+    const int i0 = lane * per;
+    const int cnt = max(0, min(per, N - i0));
+    auto weight = [&](T fv, int x, int y) {
         int dx = cx - x, dy = cy - y;
         dx += dx < 0 ? L : 0;
         dy += dy < 0 ? L : 0;
-        const double fi = (double)row[i];
-        return (fi > 0.0 ? fi : 0.0) * (g[dy] * g[dx]);
+        const double f = (double)fv;
+        return (f > 0.0 ? f : 0.0) * (g[dy] * g[dx]);
     };
+    const int x0 = cnt > 0 ? i0 % L : 0, y0 = cnt > 0 ? i0 / L : 0;
     double tot = 0.0;
-    for (int i = i0; i < i1; ++i) tot += weight(i);
-    const double incl = group_scan_incl(tot);
-    const double excl = dpp_f64<0x111>(incl);
-    const double total = __shfl(incl, gbase + 15, 64);
+    int lastpos = -1;
+    {
+        int x = x0, y = y0;
+#pragma unroll 1
+        for (int m0 = 0; m0 < cnt; m0 += C) {
+            T v[C];
+#pragma unroll
+            for (int k = 0; k < C; ++k) v[k] = row[min(i0 + m0 + k, N - 1)];
+#pragma unroll
+            for (int k = 0; k < C; ++k)
+                if (m0 + k < cnt) {
+                    const double w = weight(v[k], x, y);
+                    tot += w;
+                    if (w > 0.0) lastpos = i0 + m0 + k;
+                    if (++x == L) {
+                        x = 0;
+                        ++y;
+                    }
+                }
+        }
+    }
+    double total;
+    const double incl = wave_incl_scan_f64(tot, lane, &total);
     if (!(total > 0.0) || !isfinite(total)) {
-        if (*err == 0) *err = isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE;
+        *bad = isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE;
         return cur;
     }
     const double Tq = u * total;
-    double run = excl;
-    int found = -1, lastpos = -1;
-    for (int i = i0; i < i1; ++i) {
-        const double wi = weight(i);
-        run += wi;
-        if (found < 0 && run > Tq) found = i;
-        if (wi > 0.0) lastpos = i;
+    const uint64_t fm = __ballot(incl > Tq && tot > 0.0);
+    if (fm) {
+        const int src = __ffsll((unsigned long long)fm) - 1;
+        int pick = -1;
+        if (lane == src) {  // the lane holding the crossing walks its sites again
+            double run = incl - tot;
+            int x = x0, y = y0, last_in = -1;
+#pragma unroll 1
+            for (int m0 = 0; m0 < cnt && pick < 0; m0 += C) {
+                T v[C];
+#pragma unroll
+                for (int k = 0; k < C; ++k) v[k] = row[min(i0 + m0 + k, N - 1)];
+#pragma unroll
+                for (int k = 0; k < C; ++k)
+                    if (m0 + k < cnt && pick < 0) {
+                        const double w = weight(v[k], x, y);
+                        run += w;
+                        if (w > 0.0) last_in = i0 + m0 + k;
+                        if (run > Tq) pick = i0 + m0 + k;
+                        if (++x == L) {
+                            x = 0;
+                            ++y;
+                        }
+                    }
+            }
+            if (pick < 0) pick = last_in >= 0 ? last_in : lastpos;  // rounding between orders
+        }
+        return __builtin_amdgcn_readlane(pick, src);
     }
-    const uint32_t fm = (uint32_t)(__ballot(found >= 0) >> gbase) & 0xFFFFu;
-    const uint32_t lm = (uint32_t)(__ballot(lastpos >= 0) >> gbase) & 0xFFFFu;
-    if (fm) return __shfl(found, gbase + __ffs((int)fm) - 1, 64);
-    return lm ? __shfl(lastpos, gbase + 31 - __clz((int)lm), 64) : cur;
+    const uint64_t lm = __ballot(lastpos >= 0);
+    return lm ? __builtin_amdgcn_readlane(lastpos, 63 - __clzll((long long)lm)) : cur;
 }
 
 // Draw on the second window (half-width kWin2W) of one 16-lane group: lane li sums the weights
@@ -982,8 +913,9 @@ __device__ int window2_draw(const T* __restrict__ row, int L, int li, int gbase,
 // chains of dependent loads in flight. Lane li holds the window ranks 4 li .. 4 li + 3 (site
 // order). Per draw it loads those filter values, forms max(f, 0) g(dy) g(dx), and the 16 lanes
 // scan their sums with DPP inside their row of the wavefront. The lane holding the first rank
-// above tau certifies the draw. An uncertified draw scans the whole row in site order instead
-// (ceil(N / 16) contiguous sites per lane), with k_backward's rule. Lane li of a group computes
+// above tau certifies the draw. An uncertified draw is retried on the wider window, and failing
+// that the whole wavefront scans the row in site order with k_backward's rule, one such group
+// at a time (ceil(N / 64) contiguous sites per lane). Lane li of a group computes
 // the Philox uniform of draw s0 + li once per 16 draws. Every load address is in bounds for any
 // lane (inactive groups read chain 0's first row), so loads are unconditional and values masked.
 template <typename T>
@@ -995,7 +927,8 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     constexpr int K = kWinPerLane;
     __shared__ double gsh[G][kWinMaxL];
     const int grp = threadIdx.x / kWinLanes, li = threadIdx.x % kWinLanes;
-    const int gbase = (threadIdx.x & 63) - li;  // the group's first lane in the wavefront
+    const int lane64 = threadIdx.x & 63;
+    const int gbase = lane64 - li;  // the group's first lane in the wavefront
     const int task = blockIdx.x * G + grp;
     const bool active = task < n_tasks;
     const DrawTask t = active ? tasks[task] : DrawTask{0, 0, 0, 0};
@@ -1030,7 +963,6 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     }
     const T* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
     const double gout = c.win_gout * kWinMassBound;
-    const int M = (N + kWinLanes - 1) / kWinLanes;  // full-row scan: sites per lane
     double ureg = 0.0;
     int err = 0;  // the first error of the block, reported once after the loop
     // Drawn sites are stored sixteen draws at a time: lane li keeps the site of draw sb + li of
@@ -1122,17 +1054,35 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         const int packed = __shfl((cert_l ? 1 << 16 : 0) | (py << 8) | px, gbase + src, 64);
         const bool cert = gm != 0 && (packed >> 16) != 0;
         int nx = packed & 255, ny = (packed >> 8) & 255;
-        if (real && !cert) {  // uniform within the group: the wider window, then the full row
+        bool need_row = false;
+        if (real && !cert) {  // uniform within the group: the wider window
             const int p2 = window2_draw(row, L, li, gbase, cx, cy, g, u, c.win_gout2);
             if (p2 >> 16) {
                 nx = p2 & 255;
                 ny = (p2 >> 8) & 255;
             } else {
-                const int chosen =
-                    M <= 64 ? row_draw_chunked(row, N, L, M, li, gbase, cx, cy, g, u, cur, &err)
-                            : row_draw_plain(row, N, L, M, li, gbase, cx, cy, g, u, cur, &err);
-                nx = chosen % L;
-                ny = chosen / L;
+                need_row = true;
+            }
+        }
+        // then the full row, one group at a time, by the whole wavefront
+        uint64_t rows_left = __ballot(li == 0 && need_row);
+        while (rows_left) {
+            const int g0 = __ffsll((unsigned long long)rows_left) - 1;  // the group's lane 0
+            rows_left &= rows_left - 1;
+            const uint64_t rp = (uint64_t)(uintptr_t)row;
+            const T* rowg = (const T*)(uintptr_t)(
+                (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)rp, g0) |
+                ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(rp >> 32), g0) << 32));
+            int bad = 0;
+            const int Lg = __builtin_amdgcn_readlane(L, g0);
+            const int chosen = wave_row_draw(
+                rowg, __builtin_amdgcn_readlane(N, g0), Lg, __builtin_amdgcn_readlane(cx, g0),
+                __builtin_amdgcn_readlane(cy, g0), gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)],
+                readlane_f64(u, g0), __builtin_amdgcn_readlane(cur, g0), lane64, &bad);
+            if ((lane64 >> 4) == (g0 >> 4)) {
+                nx = chosen % Lg;
+                ny = chosen / Lg;
+                if (bad != 0 && err == 0) err = bad;
             }
         }
         if (real) {
