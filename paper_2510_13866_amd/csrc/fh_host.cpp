@@ -349,7 +349,9 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->n_draww_tasks = (int32_t)draww.size();
     p->n_drawx_tasks = (int32_t)drawx.size();
     p->n_groups = (int32_t)groups.size();
-    p->gpart_elems = precision == FH_FP32_MFMA3 ? gpart : 0;
+    p->grad_dmfma = precision == FH_FP64 && !(flags & FH_FLAG_FFT_CONV);
+    for (const ChainInfo& ci : p->chains) p->grad_dmfma = p->grad_dmfma && ci.L <= 32;
+    p->gpart_elems = (precision == FH_FP32_MFMA3 || p->grad_dmfma) ? gpart : 0;
 
     hipError_t e = hipSuccess;
     fh::Device& dv = p->d;
@@ -373,7 +375,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.draw32_tasks, sizeof(DrawTask) * draw32.size());
     if (e == hipSuccess) e = dalloc(&dv.draww_tasks, sizeof(DrawTask) * draww.size());
     if (e == hipSuccess) e = dalloc(&dv.drawx_tasks, sizeof(DrawTask) * drawx.size());
-    if (e == hipSuccess) e = dalloc(&dv.gpart, sizeof(float) * (size_t)p->gpart_elems);
+    if (e == hipSuccess) e = dalloc(&dv.gpart, p->real_size * (size_t)p->gpart_elems);
     if (e == hipSuccess) e = dalloc(&dv.perm, sizeof(int32_t) * (size_t)part);
     if (e == hipSuccess) e = dalloc(&dv.perm_inv, sizeof(int32_t) * (size_t)part);
     if (e == hipSuccess) e = dalloc(&dv.sign, sizeof(int32_t) * (size_t)n_chains);
@@ -662,6 +664,8 @@ static hipError_t enqueue_logz_grad(fh_plan p, const void* aux, const int32_t* p
     if (e != hipSuccess) return e;
     if (p->precision == FH_FP32_MFMA3) {
         e = launch_grad_mfma(p, aux, paths, anchor_slice, grad_aux, s);
+    } else if (p->grad_dmfma) {
+        e = launch_grad_dmfma(p, aux, paths, anchor_slice, grad_aux, s);
     } else {
         if (grad_aux) e = launch_zero(grad_aux, (int64_t)p->real_size * p->aux_elems, s);
         if (e == hipSuccess) e = launch_grad(p, aux, paths, anchor_slice, grad_aux, s);

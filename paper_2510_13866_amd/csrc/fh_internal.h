@@ -95,7 +95,8 @@ struct Device {
     DrawTask* draw32_tasks = nullptr;   // backward: worldline blocks of L = 32 chains
     DrawTask* draww_tasks = nullptr;    // backward, windowed draws (k_backward_win)
     DrawTask* drawx_tasks = nullptr;    // backward: the remaining chains (any L)
-    float* gpart = nullptr;   // MFMA adjoint: per-group partial field gradients
+    void* gpart = nullptr;    // matrix-core adjoints: per-group partial field gradients (plan
+                              // precision: FP32 for FH_FP32_MFMA3, FP64 for the FP64 circulant)
     void* mala = nullptr;     // fh_mala_field: proposal, two gradients [3][aux_elems] in plan
                               // precision, then log Z_path at both fields [2][n_chains] f64
     double* meas = nullptr;   // fh_measure per-slice rows: S(k) [aux_elems], C(r) [aux_elems],
@@ -128,6 +129,7 @@ struct fh_plan_s {
     int32_t max_N_x = 0;  // largest N among the chains of drawx_tasks
     int32_t n_draww_tasks = 0, n_drawx_tasks = 0;
     int32_t n_fwdd_tasks = 0;  // FP64 circulant forward tasks (the FFT takes n_fwd_tasks pairs)
+    bool grad_dmfma = false;   // FP64 plan whose chains all have L <= 32: adjoint on the matrix cores
     double win_bound_scale = 1.0;  // test hook: >= 1 inflates every window bound
     int64_t gpart_elems = 0;
     int64_t total_sites = 0;  // sum of N over the chains
@@ -156,6 +158,8 @@ hipError_t launch_bump_sweep(fh_plan p, hipStream_t s);
 hipError_t launch_potentials(fh_plan p, const void* aux, hipStream_t s);
 hipError_t launch_forward(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s);
 hipError_t launch_forward_dmfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s);
+hipError_t launch_grad_dmfma(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
+                             void* grad_aux, hipStream_t s);
 hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s);
 hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s);
 hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s);

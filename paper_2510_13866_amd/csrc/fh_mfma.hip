@@ -749,12 +749,191 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
     if (real && lane == 0) dt_out[c.part_off + p] = dt;
 }
 
+// The adjoint of k_grad_mfma on the FP64 matrix cores (FP64 plans, every chain L <= 32): the
+// same ring, recursion, marginals and d/dt stencil, every product and sum in FP64 with the
+// circulant of k_forward_dmfma; ring rows stored as FP64 rows, group partial slabs in FP64.
+__global__ __launch_bounds__(kThreads) void k_grad_dmfma(
+    const ChainInfo* __restrict__ chains, const GroupTask* __restrict__ groups,
+    const double* __restrict__ cmat64, const double* __restrict__ aux,
+    const double* __restrict__ W, const double* __restrict__ wshift, int64_t aux_elems,
+    int64_t total_slices, const int32_t* __restrict__ paths, double* __restrict__ filt,
+    double* __restrict__ gpart, double* __restrict__ blk_logz, double* __restrict__ dt_out,
+    int anchor, const int32_t* __restrict__ perm, int32_t* status) {
+    __shared__ double bt[kWaves][1024];  // beta tile of each wavefront, y * 32 + x
+    __shared__ double mg[kWaves][1024];  // marginal tile of each wavefront
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const GroupTask g = groups[blockIdx.x];
+    const ChainInfo& c = chains[g.chain];
+    const int L = c.L, N = c.N, L_tau = c.L_tau;
+    const bool real = wv < g.count;  // extra wavefronts shadow worldline p0
+    const int p = g.p0 + (real ? wv : 0);
+    const double* Wsp = W + g.spin * aux_elems + c.aux_off;
+    const double* shift = wshift + g.spin * total_slices + c.slice_off;
+    const double coef = g.spin ? c.coef_dn : c.coef_up;
+    const double dtau = c.dtau;
+    int a = paths[c.path_off + (int64_t)anchor * c.np + p];
+    // the ring closes on the anchor site of the reconnected worldline (itself for the identity)
+    int e = paths[c.path_off + (int64_t)anchor * c.np + perm[c.part_off + p]];
+    if (a < 0 || a >= N || e < 0 || e >= N) {
+        if (lane == 0 && real) set_status(status, FH_ERR_BAD_PATH, g.chain);
+        a = a < 0 || a >= N ? 0 : a;
+        e = e < 0 || e >= N ? 0 : e;
+    }
+    double Cb[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Cb[q] = cmat64[((int64_t)g.chain * 16 + q) * 64 + lane];
+    const int xl = lane & 15, yl = lane >> 4;
+    auto xo = [&](int q) { return 16 * (q & 1) + xl; };
+    auto yo = [&](int q, int r) { return 16 * (q >> 1) + 4 * r + yl; };
+    auto inside = [&](int q, int r) { return xo(q) < L && yo(q, r) < L; };
+    const int ax = a % L, ay = a / L, ex = e % L, ey = e / L;
+    double* rows = filt + c.filt_off + (int64_t)p * L_tau * N;
+    // ---- forward pass over the ring, every row stored
+    Tile64 F;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            F.t[q][r] = (xo(q) == ax && yo(q, r) == ay) ? 1.0 : 0.0;
+            if (real && inside(q, r)) rows[yo(q, r) * L + xo(q)] = F.t[q][r];
+        }
+    double la = coef * aux[c.aux_off + (int64_t)anchor * N + a];
+    for (int j = 1; j < L_tau; ++j) {
+        const int l = (anchor + j) % L_tau;
+        const double* Wl = Wsp + (int64_t)l * N;
+        double w[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w[4 * q + r] = Wl[inside(q, r) ? yo(q, r) * L + xo(q) : 0];
+        const Tile64 H = circ64(circ64(F, Cb), Cb);
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                F.t[q][r] = H.t[q][r] * w[4 * q + r];
+                sum += F.t[q][r];
+            }
+        const double tot = wave_sum_f64(sum);
+        if ((!(tot > 0.0) || !isfinite(tot)) && real && lane == 0)
+            set_status(status, FH_ERR_NONFINITE, g.chain);
+        const double inv = 1.0 / tot;
+        la += log(tot) + shift[l];
+        double* row = rows + (int64_t)j * N;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                F.t[q][r] *= inv;
+                if (real && inside(q, r)) row[yo(q, r) * L + xo(q)] = F.t[q][r];
+            }
+    }
+    {
+        const Tile64 H = circ64(circ64(F, Cb), Cb);
+        const int qe = 2 * (ey >> 4) + (ex >> 4), re = (ey & 15) >> 2;
+        double hv = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (q == qe && r == re) hv = H.t[q][r];
+        hv = __shfl(hv, (ex & 15) + 16 * (ey & 3), 64);
+        if (real && lane == 0) {
+            if (!(hv > 0.0)) set_status(status, FH_ERR_NONFINITE, g.chain);
+            blk_logz[c.blk_off + (int64_t)p * c.nb] = la + log(hv);
+        }
+    }
+    __syncthreads();  // every row of the group is stored before any wavefront reads one back
+    // ---- backward messages
+    Tile64 U;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) U.t[q][r] = (xo(q) == ex && yo(q, r) == ey) ? 1.0 : 0.0;
+    double dt = 0.0;
+    double* slab = gpart + g.part_off;
+    for (int j = L_tau - 1; j >= 0; --j) {
+        const int l = (anchor + j) % L_tau;
+        const Tile64 B = circ64(circ64(U, Cb), Cb);  // beta_j = C u_{j+1} C
+        const double* row = rows + (int64_t)j * N;
+        double fj[16];
+        double den = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const bool in = inside(q, r);
+                const double fv = row[in ? yo(q, r) * L + xo(q) : 0];
+                fj[4 * q + r] = in ? fv : 0.0;
+                den += fj[4 * q + r] * B.t[q][r];
+                bt[wv][yo(q, r) * 32 + xo(q)] = in ? B.t[q][r] : 0.0;
+            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double num = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int x = xo(q), y = yo(q, r);
+                const int xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
+                const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
+                const double nbr = inside(q, r) ? bt[wv][y * 32 + xp] + bt[wv][y * 32 + xm] +
+                                                      bt[wv][yp * 32 + x] + bt[wv][ym * 32 + x]
+                                                : 0.0;
+                num += fj[4 * q + r] * nbr;
+            }
+        const double dden = wave_sum_f64(den);
+        const double dnum = wave_sum_f64(num);
+        dt += dtau * dnum / dden;
+        const double k = real ? coef / dden : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) mg[wv][yo(q, r) * 32 + xo(q)] = k * fj[4 * q + r] * B.t[q][r];
+        __syncthreads();
+        {
+            double* srow = slab + (int64_t)l * N;
+            for (int i = threadIdx.x; i < 1024; i += kThreads) {
+                const int yy = i >> 5, xx = i & 31;
+                if (xx < L && yy < L) srow[yy * L + xx] = (mg[0][i] + mg[1][i]) + (mg[2][i] + mg[3][i]);
+            }
+        }
+        __syncthreads();
+        if (j > 0) {
+            const double* Wl = Wsp + (int64_t)l * N;
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const bool in = inside(q, r);
+                    const double wv0 = Wl[in ? yo(q, r) * L + xo(q) : 0];
+                    U.t[q][r] = in ? wv0 * B.t[q][r] : 0.0;
+                    sum += U.t[q][r];
+                }
+            const double tot = wave_sum_f64(sum);
+            if ((!(tot > 0.0) || !isfinite(tot)) && real && lane == 0)
+                set_status(status, FH_ERR_NONFINITE, g.chain);
+            const double inv = 1.0 / tot;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) U.t[q][r] *= inv;
+        }
+    }
+    if (real && lane == 0) dt_out[c.part_off + p] = dt;
+}
+
 // grad_aux[chain][l][r] = sum over the chain's groups, in group order, of the partial slabs.
+template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gpart_reduce(const ChainInfo* __restrict__ chains,
                                                            int n_chains,
                                                            const GroupTask* __restrict__ groups,
-                                                           const float* __restrict__ gpart,
-                                                           float* __restrict__ grad,
+                                                           const T* __restrict__ gpart,
+                                                           T* __restrict__ grad,
                                                            int64_t aux_elems) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < aux_elems;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -768,7 +947,7 @@ __global__ __launch_bounds__(kThreads) void k_gpart_reduce(const ChainInfo* __re
         }
         const ChainInfo& c = chains[lo];
         const int64_t off = e - c.aux_off;
-        float s = 0.0f;
+        T s = T(0);
         for (int q = c.g0; q < c.g1; ++q) s += gpart[groups[q].part_off + off];
         grad[e] = s;
     }
@@ -817,18 +996,36 @@ hipError_t launch_grad_mfma(fh_plan p, const void* aux, const int32_t* paths, in
         hipLaunchKernelGGL(k_grad_mfma<32>, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
                            p->d.group_tasks, p->d.cmat, (const float*)aux, (const float*)p->d.W,
                            p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt,
-                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm, p->d.status, kNegPairs);
+                           (float*)p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm, p->d.status, kNegPairs);
     else
         hipLaunchKernelGGL(k_grad_mfma<0>, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
                            p->d.group_tasks, p->d.cmat, (const float*)aux, (const float*)p->d.W,
                            p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt,
-                           p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm, p->d.status, kNegPairs);
+                           (float*)p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm, p->d.status, kNegPairs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !grad_aux) return e;
     int64_t b = (p->aux_elems + kThreads - 1) / kThreads;
     if (b > 65536) b = 65536;
-    hipLaunchKernelGGL(k_gpart_reduce, dim3((unsigned)b), dim3(kThreads), 0, s, p->d.chains,
-                       p->n_chains, p->d.group_tasks, p->d.gpart, (float*)grad_aux, p->aux_elems);
+    hipLaunchKernelGGL(k_gpart_reduce<float>, dim3((unsigned)b), dim3(kThreads), 0, s,
+                       p->d.chains, p->n_chains, p->d.group_tasks, (const float*)p->d.gpart,
+                       (float*)grad_aux, p->aux_elems);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_dmfma(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
+                             void* grad_aux, hipStream_t s) {
+    hipLaunchKernelGGL(k_grad_dmfma, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
+                       p->d.group_tasks, p->d.cmat64, (const double*)aux, (const double*)p->d.W,
+                       p->d.wshift, p->aux_elems, p->total_slices, paths, (double*)p->d.filt,
+                       (double*)p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm,
+                       p->d.status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !grad_aux) return e;
+    int64_t b = (p->aux_elems + kThreads - 1) / kThreads;
+    if (b > 65536) b = 65536;
+    hipLaunchKernelGGL(k_gpart_reduce<double>, dim3((unsigned)b), dim3(kThreads), 0, s,
+                       p->d.chains, p->n_chains, p->d.group_tasks, (const double*)p->d.gpart,
+                       (double*)grad_aux, p->aux_elems);
     return hipGetLastError();
 }
 

@@ -885,7 +885,7 @@ def test_full_size_sampled_parity(lib, prec):
     S.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "mfma3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp64fft", "fp32", "mfma3"])
 def test_logz_grad_parity(lib, prec):
     fhmc, sampler = lib
     precision = PRECS[prec]
@@ -895,7 +895,7 @@ def test_logz_grad_parity(lib, prec):
              synth.ChainDesc(L=32, L_tau=128, n_up=9, n_dn=8, hs_kind=synth.HS_GAUSS,
                              block_len=0, t=1.0, U=4.0, dtau=0.05, seed=3)]
     say("logZ grad parity", prec)
-    S = sampler.Sampler(descs, precision)
+    S = sampler.Sampler(descs, precision, plan_flags(fhmc, prec))
     aux, paths = mixed_state(descs, seed=21)
     A, P = S.pack_aux(aux), S.pack_paths(paths)
     for anchor in (0, 5):
@@ -906,8 +906,8 @@ def test_logz_grad_parity(lib, prec):
         gA = S.unpack_aux(gA)
         for c, d in enumerate(descs):
             lz, g, gt, _ = ograd.logz_path_grad(d, aux[c], paths[c], anchor)
-            tol = 1e-10 if prec == "fp64" else 1e-4
-            assert logZ[c] == pytest.approx(lz, rel=1e-12 if prec == "fp64" else 2e-6), c
+            tol = 1e-10 if prec.startswith("fp64") else 1e-4
+            assert logZ[c] == pytest.approx(lz, rel=1e-12 if prec.startswith("fp64") else 2e-6), c
             assert np.linalg.norm(gA[c] - g) <= tol * np.linalg.norm(g), c
             assert gT[c] == pytest.approx(gt, rel=tol), c
     S.close()
@@ -1153,14 +1153,14 @@ GRAD_BATCH = [synth.config_small_fp64()[0],
                               block_len=0, t=1.0, U=4.0, dtau=0.05, seed=3)]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "mfma3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp64fft", "fp32", "mfma3"])
 def test_logz_grad_with_reconnections_parity(lib, prec):
     """log Z_path, d/d field and d/d t with random reconnections (each ring closes on the anchor
     site of the reconnected worldline) against the oracle, on closed-loop worldlines."""
     fhmc, sampler = lib
     descs = GRAD_BATCH
     say("logZ grad with reconnections", prec)
-    S = sampler.Sampler(descs, PRECS[prec])
+    S = sampler.Sampler(descs, PRECS[prec], plan_flags(fhmc, prec))
     aux, _ = mixed_state(descs, seed=181)
     perms = random_perms(descs, np.random.default_rng(18))
     rng = np.random.default_rng(19)
@@ -1175,8 +1175,8 @@ def test_logz_grad_with_reconnections_parity(lib, prec):
             lz, g, gt, _ = ograd.logz_path_grad(d, aux[c], paths[c], anchor, perm=perms[c])
             lz_id = ograd.logz_path(d, aux[c], paths[c], anchor)[0]
             assert abs(lz - lz_id) > 1e-6   # the reconnection changes the answer
-            tol = 1e-10 if prec == "fp64" else 1e-4
-            assert logZ[c] == pytest.approx(lz, rel=1e-12 if prec == "fp64" else 2e-6), c
+            tol = 1e-10 if prec.startswith("fp64") else 1e-4
+            assert logZ[c] == pytest.approx(lz, rel=1e-12 if prec.startswith("fp64") else 2e-6), c
             assert np.linalg.norm(gA[c] - g) <= tol * np.linalg.norm(g), c
             assert gT[c] == pytest.approx(gt, rel=tol), c
     S.close()
