@@ -1253,3 +1253,73 @@ def test_u0_fermion_energy_from_device_gradients(lib, prec, L):
     ref = float(sum((eps[i] + eps[j]) * l for (i, j), l in zip(pairs, lam)) / lam.sum())
     assert energy == pytest.approx(ref, rel=1e-10 if prec == "fp64" else 1e-4), (energy, ref)
     S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_largest_lattice_parity(lib, prec):
+    """L = 64 (N = 4096, the largest lattice): FFT forward against the oracle (log Z, filters)
+    and the windowed backward draws against the full-row kernel for N > 1024 and, in FP64,
+    against the oracle's draw rule."""
+    fhmc, sampler = lib
+    descs = [synth.ChainDesc(L=64, L_tau=6, n_up=3, n_dn=2, hs_kind=synth.HS_GAUSS, block_len=0,
+                             t=1.0, U=4.0, dtau=0.05, seed=301),
+             synth.ChainDesc(L=48, L_tau=5, n_up=2, n_dn=2, hs_kind=synth.HS_HIRSCH, block_len=3,
+                             t=1.0, U=4.0, dtau=0.05, seed=302)]
+    say("largest lattice parity", prec)
+    aux, paths = mixed_state(descs, seed=311)
+    Sw = sampler.Sampler(descs, PRECS[prec])
+    Sf = sampler.Sampler(descs, PRECS[prec], fhmc.FH_FLAG_FULL_ROW_DRAW)
+    Aw, Pw = Sw.pack_aux(aux), Sw.pack_paths(paths)
+    Af, Pf = Sf.pack_aux(aux), Sf.pack_paths(paths)
+    s = 1
+    logZ = Sw.unpack_particles(Sw.forward_filter(Aw, Pw, s))
+    assert Sw.status() == (0, -1)
+    for c, d in enumerate(descs):
+        ref_lz, ref_rows, tail = oracle_forward(d, aux[c], paths[c], s, with_tail=True)
+        err = np.abs(logZ[c] - ref_lz)
+        assert np.all(err <= logz_tol(prec, ref_lz, tail, d.L_tau)), (c, err, tail)
+        for p in range(d.n_particles):
+            assert rel_row_err(Sw.filters(c, p), ref_rows[p]) <= FILTER_TOL[prec], (c, p)
+    Sw.backward_sample(Pw, s)
+    Sf.forward_filter(Af, Pf, s)
+    Sf.backward_sample(Pf, s)
+    assert Sw.status() == (0, -1) and Sf.status() == (0, -1)
+    gw, gf = Sw.unpack_paths(Pw), Sf.unpack_paths(Pf)
+    for c, d in enumerate(descs):
+        assert np.array_equal(gw[c], gf[c]), c
+        if prec == "fp64":
+            Gm = lattice.transfer_matrix(d.L, d.t, d.dtau)
+            W_up, W_dn = hs.potentials(aux[c], d.hs_kind, d.U, d.dtau)
+            ref = paths[c].astype(np.int64).copy()
+            marg = np.full(ref.shape, np.inf)
+            for W, parts in ((W_up, np.arange(d.n_up)), (W_dn, np.arange(d.n_up, d.n_particles))):
+                out, _, m = ffbs.ffbs_spin(Gm, W, paths[c], parts, d.seed, s, d.block_len, True)
+                ref[:, parts] = out
+                marg[:, parts] = m
+            assert check_paths(d, gw[c], ref, marg, "largest lattice chain %d" % c) <= 1
+    Sw.close()
+    Sf.close()
+
+
+def test_fp64_circulant_resolves_deep_filter_tails(lib):
+    """Block ends placed anywhere on the lattice sit deep in the filter's tail, where an FFT
+    convolution (accurate to ~eps * max per site) cannot resolve them. The FP64 circulant keeps
+    every product positive, so its log Z matches the oracle with no tail allowance at all."""
+    fhmc, sampler = lib
+    descs = [d for d in MIXED if d.L >= 6]
+    say("fp64 circulant deep tails")
+    S = sampler.Sampler(descs, fhmc.FH_FP64)
+    aux = [synth.initial_aux(d, rng_seed=400 + i) for i, d in enumerate(descs)]
+    paths = [synth.random_paths(d, 410 + i) for i, d in enumerate(descs)]
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    deepest = 0.0
+    for s in (0, 1):
+        logZ = S.unpack_particles(S.forward_filter(A, P, s))
+        assert S.status() == (0, -1)
+        for c, d in enumerate(descs):
+            ref_lz, _, tail = oracle_forward(d, aux[c], paths[c], s, with_tail=True)
+            deepest = max(deepest, float(tail.max()))
+            err = np.abs(logZ[c] - ref_lz)
+            assert np.all(err <= 1e-12 * (1 + np.abs(ref_lz)) + 4 * 1.2e-16 * d.L_tau), (c, err.max())
+    assert deepest > 1e6   # the ends really are deep in the tails
+    S.close()
