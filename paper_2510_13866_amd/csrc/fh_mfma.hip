@@ -946,9 +946,21 @@ __global__ __launch_bounds__(kThreads) void k_gpart_reduce(const ChainInfo* __re
                 hi = mid - 1;
         }
         const ChainInfo& c = chains[lo];
-        const int64_t off = e - c.aux_off;
+        // a chain's group slabs are consecutive, [L_tau][N] apart: eight loads in flight, the
+        // sum still taken in group order
+        const int64_t stride = (int64_t)c.L_tau * c.N;
+        const T* src = gpart + groups[c.g0].part_off + (e - c.aux_off);
+        const int n = c.g1 - c.g0;
         T s = T(0);
-        for (int q = c.g0; q < c.g1; ++q) s += gpart[groups[q].part_off + off];
+        int q = 0;
+        for (; q + 8 <= n; q += 8) {
+            T v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = src[(int64_t)(q + k) * stride];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += v[k];
+        }
+        for (; q < n; ++q) s += src[(int64_t)q * stride];
         grad[e] = s;
     }
 }
