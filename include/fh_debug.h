@@ -67,6 +67,12 @@ int fh_debug_window_draw(int32_t L, int32_t w, const double* g, double g_out, co
 int fh_debug_inflate_window_bound(fh_plan plan, double factor);
 int fh_debug_backward_kernels(fh_plan plan, int32_t* n_windowed, int32_t* n_full_row);
 
+/* Forward work items of an FH_FP32_MFMA3 plan, by kernel: counts[0] worldline pairs of L = 32
+ * chains, counts[1] single padded worldlines (16 < L < 32), counts[2] packed tasks of 2 x 2
+ * worldlines per tile (8 < L <= 16), counts[3] packed tasks of 4 x 4 (L <= 8). counts holds 4
+ * int32 written by the call (caller-owned host memory). */
+int fh_debug_forward_kernels(fh_plan plan, int32_t* counts);
+
 #ifdef __cplusplus
 }
 #endif

@@ -97,8 +97,11 @@ void build_cmat64(int L, const double* g, double* out) {
                 }
 }
 
-void build_cmat(int L, const double* g, uint16_t* out) {
-    if (L > 32) {
+// With bs < 32 the operand is block-diagonal: diagonal blocks of side bs, each holding the
+// L x L circulant in its leading corner (the packed small-lattice forward); bs = 32 is the
+// single padded circulant.
+void build_cmat(int L, const double* g, uint16_t* out, int bs = 32) {
+    if (L > bs) {
         memset(out, 0, sizeof(uint16_t) * kCmatPerChain);
         return;
     }
@@ -107,7 +110,8 @@ void build_cmat(int L, const double* g, uint16_t* out) {
             for (int e = 0; e < 8; ++e) {
                 const int R = 16 * q + 8 * (e / 4) + 4 * (lane / 32) + e % 4;
                 const int n = lane % 32;
-                const double v = (R < L && n < L) ? g[((R - n) % L + L) % L] : 0.0;
+                const int r = R % bs, k = n % bs;
+                const double v = (R / bs == n / bs && r < L && k < L) ? g[((r - k) % L + L) % L] : 0.0;
                 const uint16_t h = bf16_rne((float)v);
                 const double r1 = v - bf16_val(h);
                 const uint16_t m = bf16_rne((float)r1);
@@ -145,7 +149,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign,
+                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign,
                     d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -265,12 +269,16 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->total_slices = slices;
     p->tables.assign(tab, 0.0);
     p->cmat.assign((size_t)kCmatPerChain * n_chains, 0);
+    p->cmatp.assign((size_t)kCmatPerChain * n_chains, 0);
     p->cmat64.assign((size_t)kCmat64PerChain * n_chains, 0.0);
     std::vector<char> windowed((size_t)n_chains, 0);
     for (int c = 0; c < n_chains; ++c) {
         ChainInfo& ci = p->chains[c];
         build_tables(descs[c], p->tables.data() + ci.tab_off);
         build_cmat(descs[c].L, p->tables.data() + tab_g(ci), p->cmat.data() + (size_t)kCmatPerChain * c);
+        if (ci.L <= kPackMaxL)
+            build_cmat(ci.L, p->tables.data() + tab_g(ci), p->cmatp.data() + (size_t)kCmatPerChain * c,
+                       32 / pack_blocks(ci.L));
         build_cmat64(descs[c].L, p->tables.data() + tab_g(ci),
                      p->cmat64.data() + (size_t)kCmat64PerChain * c);
         windowed[c] = win_select(p->tables.data() + tab_g(ci), ci.L, &ci.win_w, &ci.win_gout) &&
@@ -330,10 +338,27 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->n_draw_tasks = (int32_t)draw.size();
     std::vector<PairTask> fwd32;
     std::vector<DrawTask> fwdx, draw32, draww, drawx;
+    std::vector<PackTask> fwdp2, fwdp4;
+    // small lattices whose filter region fits the packed kernel's 32-bit row offsets
+    auto packed = [&](int c) {
+        const ChainInfo& ci = p->chains[c];
+        return ci.L <= kPackMaxL && (int64_t)ci.np * ci.L_tau * ci.N < ((int64_t)1 << 31);
+    };
+    for (int c : order) {
+        if (!packed(c)) continue;
+        const ChainInfo& ci = p->chains[c];
+        const int P = pack_blocks(ci.L), per = 2 * P * P;
+        for (int spin = 0; spin < 2; ++spin) {
+            const int p0 = spin ? ci.n_up : 0, p1 = spin ? ci.np : ci.n_up;
+            for (int q = p0; q < p1; q += per)
+                for (int b = 0; b < ci.nb; ++b)
+                    (P == 2 ? fwdp2 : fwdp4).push_back({c, q, std::min(per, p1 - q), b});
+        }
+    }
     for (const PairTask& t : fwd)
         if (p->chains[t.chain].L == 32) fwd32.push_back(t);
     for (const DrawTask& t : draw) {
-        if (p->chains[t.chain].L != 32) fwdx.push_back(t);
+        if (p->chains[t.chain].L != 32 && !packed(t.chain)) fwdx.push_back(t);
         if (windowed[t.chain]) {
             draww.push_back(t);
         } else if (p->chains[t.chain].L == 32) {
@@ -345,6 +370,10 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     }
     p->n_fwd32_tasks = (int32_t)fwd32.size();
     p->n_fwdx_tasks = (int32_t)fwdx.size();
+    p->n_fwdp2_tasks = (int32_t)fwdp2.size();
+    p->n_fwdp4_tasks = (int32_t)fwdp4.size();
+    std::vector<PackTask> fwdp(fwdp2);
+    fwdp.insert(fwdp.end(), fwdp4.begin(), fwdp4.end());
     p->n_draw32_tasks = (int32_t)draw32.size();
     p->n_draww_tasks = (int32_t)draww.size();
     p->n_drawx_tasks = (int32_t)drawx.size();
@@ -372,6 +401,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.group_tasks, sizeof(GroupTask) * groups.size());
     if (e == hipSuccess) e = dalloc(&dv.fwd32_tasks, sizeof(PairTask) * fwd32.size());
     if (e == hipSuccess) e = dalloc(&dv.fwdx_tasks, sizeof(DrawTask) * fwdx.size());
+    if (e == hipSuccess) e = dalloc(&dv.fwdp_tasks, sizeof(PackTask) * fwdp.size());
+    if (e == hipSuccess) e = dalloc(&dv.cmatp, sizeof(uint16_t) * p->cmatp.size());
     if (e == hipSuccess) e = dalloc(&dv.draw32_tasks, sizeof(DrawTask) * draw32.size());
     if (e == hipSuccess) e = dalloc(&dv.draww_tasks, sizeof(DrawTask) * draww.size());
     if (e == hipSuccess) e = dalloc(&dv.drawx_tasks, sizeof(DrawTask) * drawx.size());
@@ -409,6 +440,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = hipMemcpy(dv.group_tasks, groups.data(), sizeof(GroupTask) * groups.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !fwd32.empty()) e = hipMemcpy(dv.fwd32_tasks, fwd32.data(), sizeof(PairTask) * fwd32.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !fwdx.empty()) e = hipMemcpy(dv.fwdx_tasks, fwdx.data(), sizeof(DrawTask) * fwdx.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !fwdp.empty()) e = hipMemcpy(dv.fwdp_tasks, fwdp.data(), sizeof(PackTask) * fwdp.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dv.cmatp, p->cmatp.data(), sizeof(uint16_t) * p->cmatp.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !draw32.empty()) e = hipMemcpy(dv.draw32_tasks, draw32.data(), sizeof(DrawTask) * draw32.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !draww.empty()) e = hipMemcpy(dv.draww_tasks, draww.data(), sizeof(DrawTask) * draww.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !drawx.empty()) e = hipMemcpy(dv.drawx_tasks, drawx.data(), sizeof(DrawTask) * drawx.size(), hipMemcpyHostToDevice);
@@ -723,6 +756,9 @@ int fh_set_hopping(fh_plan p, const double* t) {
         build_tables(p->descs[c], p->tables.data() + ci.tab_off);
         build_cmat(p->descs[c].L, p->tables.data() + tab_g(ci),
                    p->cmat.data() + (size_t)kCmatPerChain * c);
+        if (ci.L <= kPackMaxL)
+            build_cmat(ci.L, p->tables.data() + tab_g(ci), p->cmatp.data() + (size_t)kCmatPerChain * c,
+                       32 / pack_blocks(ci.L));
         build_cmat64(p->descs[c].L, p->tables.data() + tab_g(ci),
                      p->cmat64.data() + (size_t)kCmat64PerChain * c);
         // the window keeps its width; its outside bound follows the new kernel
@@ -736,6 +772,8 @@ int fh_set_hopping(fh_plan p, const double* t) {
     FH_TRY(hipMemcpy(p->d.tables, p->tables.data(), sizeof(double) * p->tables.size(),
                      hipMemcpyHostToDevice));
     FH_TRY(hipMemcpy(p->d.cmat, p->cmat.data(), sizeof(uint16_t) * p->cmat.size(),
+                     hipMemcpyHostToDevice));
+    FH_TRY(hipMemcpy(p->d.cmatp, p->cmatp.data(), sizeof(uint16_t) * p->cmatp.size(),
                      hipMemcpyHostToDevice));
     FH_TRY(hipMemcpy(p->d.cmat64, p->cmat64.data(), sizeof(double) * p->cmat64.size(),
                      hipMemcpyHostToDevice));
@@ -950,6 +988,15 @@ int fh_debug_backward_kernels(fh_plan p, int32_t* n_windowed, int32_t* n_full_ro
     if (!p || !n_windowed || !n_full_row) return FH_ERR_INVALID_ARG;
     *n_windowed = p->n_draww_tasks;
     *n_full_row = p->n_draw32_tasks + p->n_drawx_tasks;
+    return FH_OK;
+}
+
+int fh_debug_forward_kernels(fh_plan p, int32_t* counts) {
+    if (!p || !counts) return FH_ERR_INVALID_ARG;
+    counts[0] = p->n_fwd32_tasks;
+    counts[1] = p->n_fwdx_tasks;
+    counts[2] = p->n_fwdp2_tasks;
+    counts[3] = p->n_fwdp4_tasks;
     return FH_OK;
 }
 

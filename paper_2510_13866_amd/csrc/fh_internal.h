@@ -60,6 +60,15 @@ struct PairTask {
 struct DrawTask {
     int32_t chain, p, block, pad;
 };
+// Worldlines p0 .. p0 + n - 1 of one (chain, spin), one block: the packed small-lattice forward
+// (two tiles of P x P worldlines, n <= 2 P^2).
+struct PackTask {
+    int32_t chain, p0, n, block;
+};
+// Lattices up to this size run the packed forward: P = 4 blocks per tile side for L <= 8,
+// P = 2 for L <= 16.
+constexpr int kPackMaxL = 16;
+FH_HD inline int pack_blocks(int L) { return L <= 8 ? 4 : 2; }
 // Up to kGroup worldlines of one (chain, spin) processed by one workgroup in the MFMA adjoint;
 // part_off locates the group's partial field-gradient slab [L_tau][N].
 constexpr int kGroup = 4;
@@ -79,6 +88,7 @@ struct Device {
     ChainInfo* chains = nullptr;
     double* tables = nullptr;
     uint16_t* cmat = nullptr;  // per chain: split-bf16 circulant operand [3][2][64][8]
+    uint16_t* cmatp = nullptr; // per chain with L <= kPackMaxL: the block-diagonal operand, same layout
     double* cmat64 = nullptr;  // per chain: FP64 circulant B operands [16][64]
     DrawTask* fwdd_tasks = nullptr;  // FP64 circulant forward: worldline blocks of L <= 32 chains
     void* W = nullptr;        // [2][sum L_tau*N] in plan precision (up, then down)
@@ -91,7 +101,8 @@ struct Device {
     DrawTask* draw_tasks = nullptr;
     GroupTask* group_tasks = nullptr;
     PairTask* fwd32_tasks = nullptr;    // MFMA forward: worldline pairs of L = 32 chains
-    DrawTask* fwdx_tasks = nullptr;     // single worldlines of the other chains (forward, backward)
+    DrawTask* fwdx_tasks = nullptr;     // MFMA forward: single worldlines of 16 < L < 32 chains
+    PackTask* fwdp_tasks = nullptr;     // MFMA forward, packed: P = 2 tasks, then P = 4 tasks
     DrawTask* draw32_tasks = nullptr;   // backward: worldline blocks of L = 32 chains
     DrawTask* draww_tasks = nullptr;    // backward, windowed draws (k_backward_win)
     DrawTask* drawx_tasks = nullptr;    // backward: the remaining chains (any L)
@@ -120,12 +131,14 @@ struct fh_plan_s {
     std::vector<fh::ChainInfo> chains;
     std::vector<double> tables;
     std::vector<uint16_t> cmat;
+    std::vector<uint16_t> cmatp;
     std::vector<double> cmat64;
     int64_t aux_elems = 0, path_elems = 0, particles = 0, blk_elems = 0, filt_elems = 0;
     int32_t n_fwd_tasks = 0, n_grad_tasks = 0, n_draw_tasks = 0;
     int64_t total_slices = 0;
     int32_t n_groups = 0;
     int32_t n_fwd32_tasks = 0, n_fwdx_tasks = 0, n_draw32_tasks = 0;
+    int32_t n_fwdp2_tasks = 0, n_fwdp4_tasks = 0;
     int32_t max_N_x = 0;  // largest N among the chains of drawx_tasks
     int32_t n_draww_tasks = 0, n_drawx_tasks = 0;
     int32_t n_fwdd_tasks = 0;  // FP64 circulant forward tasks (the FFT takes n_fwd_tasks pairs)

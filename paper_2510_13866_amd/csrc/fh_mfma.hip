@@ -556,6 +556,209 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     }
 }
 
+// Segmented sum over the lanes that share a column block of BS lanes (BS = 16: the DPP rows
+// J and J + 2; BS = 8: the half rows J and J + 4): every lane gets its block's sum.
+template <int BS>
+__device__ inline float block_sum(float v) {
+    v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_add<0x141>(v);  // row_half_mirror: sums over 8 lanes
+    if (BS == 16) v = dpp_add<0x140>(v);  // row_mirror: sums over 16 lanes
+    return v + __shfl_xor(v, 32, 64);
+}
+
+// Small lattices packed block-diagonally (L <= BS = 32 / P). P x P worldlines of one (chain,
+// spin, block) share a 32 x 32 tile: worldline (I, J) of the tile occupies rows BS I .. BS I + L - 1
+// and columns BS J .. BS J + L - 1, and the circulant operand is block-diagonal with one L x L
+// circulant g((i - j) mod L) per diagonal block. Every term coupling two blocks is an exact zero,
+// so C F C is C_L F_IJ C_L block by block, with the same six split products as the padded tile
+// of k_forward_mfma: same arithmetic, P^2 worldlines for the matrix work of one. Two tiles per
+// wavefront, as in k_forward_mfma2.
+//
+// Slots. Slot s = T P^2 + I P + J (tile T, block (I, J)) of a task holds worldline
+// p0 + min(s, n - 1); slots past n repeat the last worldline and are neither stored nor
+// counted. Each block's normaliser comes from a segmented wavefront sum; the slot's log Z is
+// kept by its owner lane BS J + T P + I (first half of the wavefront) as an FP64 mantissa and a
+// binary exponent, renormalised every step, so no log is taken inside the loop.
+template <int P>
+__global__ __launch_bounds__(kThreads, 2) void k_forward_pack(
+    const ChainInfo* __restrict__ chains, const PackTask* __restrict__ tasks, int n_tasks,
+    const uint16_t* __restrict__ cmatp, const float* __restrict__ aux, const float* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
+    double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
+    const NegPairs neg) {
+    constexpr int BS = 32 / P;   // block side
+    constexpr int PP = P * P;    // worldlines per tile
+    constexpr int RPB = 16 / P;  // registers of one block row band per lane
+    const int lane = threadIdx.x & 63;
+    const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
+    if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
+    const PackTask t = tasks[task];
+    const ChainInfo& c = chains[t.chain];
+    int start, len;
+    block_of(c, *sweep_ptr, t.block, &start, &len);
+    const int L = c.L, N = c.N, L_tau = c.L_tau;
+    const int spin = t.p0 >= c.n_up ? 1 : 0;
+    const float* Wsp = W + spin * aux_elems + c.aux_off;
+    const double* shift = wshift + spin * total_slices + c.slice_off;
+    const double coef = spin ? c.coef_dn : c.coef_up;
+    const int32_t* pc = paths + c.path_off;
+    // a full task (every slot its own worldline, L filling the blocks) stores unmasked
+    const bool full = t.n == 2 * PP && L == BS;
+
+    Split3 C;
+    {
+        const uint4* cm = (const uint4*)(cmatp + (size_t)t.chain * 3 * 2 * 64 * 8);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            C.h[q] = __builtin_bit_cast(bf16x8, cm[(0 * 2 + q) * 64 + lane]);
+            C.m[q] = __builtin_bit_cast(bf16x8, cm[(1 * 2 + q) * 64 + lane]);
+            C.l[q] = __builtin_bit_cast(bf16x8, cm[(2 * 2 + q) * 64 + lane]);
+        }
+    }
+    const int x = lane & 31, hl = lane >> 5;
+    const int J = x / BS, lx = x % BS;
+    // register v holds tile row 8 (v / 4) + 4 hl + v % 4: block row I(v) = v / RPB, local row
+    // 4 hl + cv(v)
+    auto cv = [](int v) { return 8 * (v >> 2) + (v & 3) - BS * (v / RPB); };
+    const int64_t rowoff = (int64_t)t.block * (c.B - 1);
+    // per (tile, block row): this lane's slot, its start site and its row offset in the chain's
+    // filter region (element (4 hl + cv(v), lx) of the block at off + cv(v) L)
+    int ax[2][P], ay[2][P];
+    uint32_t off[2][P];
+    bool ok[2][P];
+#pragma unroll
+    for (int T = 0; T < 2; ++T)
+#pragma unroll
+        for (int I = 0; I < P; ++I) {
+            const int s = T * PP + I * P + J;
+            const int pw = t.p0 + (s < t.n ? s : t.n - 1);
+            int a = pc[(int64_t)start * c.np + pw];
+            a = (a < 0 || a >= N) ? 0 : a;  // reported by the owner lane below
+            ax[T][I] = a % L;
+            ay[T][I] = a / L;
+            off[T][I] = (uint32_t)(((int64_t)pw * L_tau + rowoff) * N + 4 * hl * L + lx);
+            ok[T][I] = s < t.n && lx < L;
+        }
+    // owner lane: slot (T, I, J) with T P + I = lx, first half
+    const int oti = lx;
+    const int oT = oti / P, oI = oti % P;
+    const int os = oT * PP + oI * P + J;
+    const bool owner = hl == 0 && oti < 2 * P && os < t.n;
+    int oe = 0;
+    double la = 0.0, mant = 1.0;
+    int ex2 = 0;
+    if (owner) {
+        const int pw = t.p0 + os;
+        const int a = pc[(int64_t)start * c.np + pw];
+        const int qe = start + len >= L_tau ? perm[c.part_off + pw] : pw;  // reconnection
+        oe = pc[(int64_t)((start + len) % L_tau) * c.np + qe];
+        if (a < 0 || a >= N || oe < 0 || oe >= N) {
+            set_status(status, FH_ERR_BAD_PATH, t.chain);
+            oe = (oe < 0 || oe >= N) ? 0 : oe;
+        } else {
+            la = coef * (double)aux[c.aux_off + (int64_t)start * N + a];
+        }
+    }
+    auto inside = [&](int v) { return lx < L && 4 * hl + cv(v) < L; };
+    auto load_w = [&](int l, float (&dst)[16]) {
+        const float* Wl = Wsp + (int64_t)l * N + 4 * hl * L + lx;
+        // a padded position reads the slice's first site and multiplies an exact zero of C f C
+#pragma unroll
+        for (int v = 0; v < 16; ++v) dst[v] = inside(v) ? Wl[cv(v) * L] : Wsp[(int64_t)l * N];
+    };
+    f32x16 F0, F1;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int I = v / RPB, ly = 4 * hl + cv(v);
+        F0[v] = (lx == ax[0][I] && ly == ay[0][I]) ? 1.0f : 0.0f;
+        F1[v] = (lx == ax[1][I] && ly == ay[1][I]) ? 1.0f : 0.0f;
+    }
+    bool bad = false;
+    float wn[16];
+    load_w((start + 1) % L_tau, wn);
+    auto step = [&](int j) {
+        const int l = (start + j) % L_tau;
+        const f32x16 X0 = circ_step(F0, C, neg);
+        const f32x16 X1 = circ_step(F1, C, neg);
+        const f32x16 H0 = circ_step(X0, C, neg);
+        const f32x16 H1 = circ_step(X1, C, neg);
+        float s0[P], s1[P];
+#pragma unroll
+        for (int I = 0; I < P; ++I) s0[I] = s1[I] = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            F0[v] = H0[v] * wn[v];
+            F1[v] = H1[v] * wn[v];
+            s0[v / RPB] += F0[v];
+            s1[v / RPB] += F1[v];
+        }
+        load_w((l + 1) % L_tau, wn);  // the last step fetches a slice it does not use
+        __builtin_amdgcn_sched_barrier(0);
+        float inv0[P], inv1[P], mine = 1.0f;
+#pragma unroll
+        for (int I = 0; I < P; ++I) {
+            const float t0 = block_sum<BS>(s0[I]), t1 = block_sum<BS>(s1[I]);
+            bad = bad || !(t0 > 0.0f && t0 <= 3.402823466e38f) || !(t1 > 0.0f && t1 <= 3.402823466e38f);
+            // f~_j = h_j * inv: the normaliser applied is exactly 1/inv
+            inv0[I] = __builtin_amdgcn_rcpf(t0);
+            inv1[I] = __builtin_amdgcn_rcpf(t1);
+            mine = oti == I ? inv0[I] : mine;
+            mine = oti == P + I ? inv1[I] : mine;
+        }
+        // log Z -= log(inv): FP64 mantissa times 2^ex2, renormalised every step
+        mant *= (double)mine;
+        int e;
+        mant = frexp(mant, &e);
+        ex2 += e;
+        la += shift[l];
+        float* rowj = filt + c.filt_off + (int64_t)(j - 1) * N;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            F0[v] *= inv0[v / RPB];
+            F1[v] *= inv1[v / RPB];
+        }
+        if (full) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                __builtin_nontemporal_store(F0[v], rowj + cv(v) * L + off[0][v / RPB]);
+                __builtin_nontemporal_store(F1[v], rowj + cv(v) * L + off[1][v / RPB]);
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const bool in = 4 * hl + cv(v) < L;
+                if (in && ok[0][v / RPB]) __builtin_nontemporal_store(F0[v], rowj + cv(v) * L + off[0][v / RPB]);
+                if (in && ok[1][v / RPB]) __builtin_nontemporal_store(F1[v], rowj + cv(v) * L + off[1][v / RPB]);
+            }
+        }
+    };
+    if (len > 1) {
+        step(1);
+        for (int j = 2; j < len; ++j) step(j);
+    }
+    // end weights (C f~ C)(e) of every slot: the owner reads its block's element at e
+    const f32x16 X0 = circ_step(F0, C, neg);
+    const f32x16 X1 = circ_step(F1, C, neg);
+    const f32x16 H0 = circ_step(X0, C, neg);
+    const f32x16 H1 = circ_step(X1, C, neg);
+    const int row = BS * oI + oe / L, col = BS * J + oe % L;
+    const int src = col + 32 * ((row >> 2) & 1), ve = 4 * (row >> 3) + (row & 3);
+    float hv = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const float h0 = __shfl(H0[v], src, 64), h1 = __shfl(H1[v], src, 64);
+        if (v == ve) hv = oT ? h1 : h0;
+    }
+    if (bad) set_status(status, FH_ERR_NONFINITE, t.chain);
+    if (owner) {
+        if (!(hv > 0.0f)) set_status(status, FH_ERR_NONFINITE, t.chain);  // end weight underflowed
+        const double lz = la - (log(mant) + (double)ex2 * 0.69314718055994530942) + log((double)hv);
+        blk_logz[c.blk_off + (int64_t)(t.p0 + os) * c.nb + t.block] = lz;
+    }
+}
+
 // Adjoint of the forward filter over the ring anchored at `anchor` (one block of length L_tau,
 // closing on the anchor site e of the reconnected worldline, e = a without reconnection), on
 // the matrix cores. A workgroup takes up to kGroup worldlines of one (chain, spin), one per
@@ -996,6 +1199,27 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
                            kNegPairs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // small lattices, packed block-diagonally: L <= 16 two-by-two, L <= 8 four-by-four
+    if (p->n_fwdp2_tasks > 0) {
+        const unsigned blocks = (unsigned)((p->n_fwdp2_tasks + kWaves - 1) / kWaves);
+        hipLaunchKernelGGL(k_forward_pack<2>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.fwdp_tasks, p->n_fwdp2_tasks, p->d.cmatp, (const float*)aux,
+                           (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
+                           paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
+                           kNegPairs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (p->n_fwdp4_tasks > 0) {
+        const unsigned blocks = (unsigned)((p->n_fwdp4_tasks + kWaves - 1) / kWaves);
+        hipLaunchKernelGGL(k_forward_pack<4>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.fwdp_tasks + p->n_fwdp2_tasks, p->n_fwdp4_tasks, p->d.cmatp,
+                           (const float*)aux, (const float*)p->d.W, p->d.wshift, p->aux_elems,
+                           p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
+                           p->d.sweep, p->d.status, kNegPairs);
     }
     return hipGetLastError();
 }

@@ -96,6 +96,7 @@ _sig("fh_debug_window_draw", c_int32, c_int32, c_int32, POINTER(c_double), c_dou
      POINTER(c_double), c_int32, c_double, POINTER(c_int32), POINTER(c_int32))
 _sig("fh_debug_inflate_window_bound", c_int32, c_void_p, c_double)
 _sig("fh_debug_backward_kernels", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32))
+_sig("fh_debug_forward_kernels", c_int32, c_void_p, POINTER(c_int32))
 
 
 class FhError(RuntimeError):

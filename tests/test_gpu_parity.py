@@ -170,6 +170,77 @@ def test_forward_filter_parity_mixed_batch(lib, prec):
     S.close()
 
 
+# Small lattices on the packed MFMA forward: full tasks (every slot its own worldline, L filling
+# its block), ragged tasks (shadow slots), lattices smaller than their block (masked stores),
+# next to the padded-tile (16 < L < 32) and pair (L = 32) kernels.
+PACKED = [
+    synth.ChainDesc(L=16, L_tau=6, n_up=16, n_dn=16, hs_kind=synth.HS_HIRSCH, block_len=0,
+                    t=1.0, U=4.0, dtau=0.0625, seed=81),                             # 2 x 2, full
+    synth.ChainDesc(L=16, L_tau=5, n_up=11, n_dn=3, hs_kind=synth.HS_GAUSS, block_len=3,
+                    t=1.0, U=4.0, dtau=0.05, seed=82),                               # ragged
+    synth.ChainDesc(L=9, L_tau=6, n_up=9, n_dn=8, hs_kind=synth.HS_GAUSS, block_len=4,
+                    t=1.0, U=3.0, dtau=0.1, seed=83),                                # L < 16
+    synth.ChainDesc(L=8, L_tau=5, n_up=32, n_dn=32, hs_kind=synth.HS_HIRSCH, block_len=0,
+                    t=1.0, U=4.0, dtau=0.05, seed=84),                               # 4 x 4, full
+    synth.ChainDesc(L=8, L_tau=7, n_up=37, n_dn=5, hs_kind=synth.HS_GAUSS, block_len=3,
+                    t=1.0, U=6.0, dtau=0.05, seed=85),                               # ragged
+    synth.ChainDesc(L=6, L_tau=4, n_up=7, n_dn=6, hs_kind=synth.HS_GAUSS, block_len=0,
+                    t=1.0, U=4.0, dtau=0.1, seed=86),                                # L < 8
+    synth.ChainDesc(L=12, L_tau=5, n_up=20, n_dn=20, hs_kind=synth.HS_HIRSCH, block_len=0,
+                    t=1.0, U=4.0, dtau=0.05, seed=87),
+    synth.ChainDesc(L=24, L_tau=4, n_up=3, n_dn=2, hs_kind=synth.HS_GAUSS, block_len=0,
+                    t=1.0, U=4.0, dtau=0.05, seed=88),                               # padded tile
+    synth.ChainDesc(L=32, L_tau=3, n_up=2, n_dn=1, hs_kind=synth.HS_GAUSS, block_len=0,
+                    t=1.0, U=4.0, dtau=0.05, seed=89),                               # pairs
+]
+
+
+def test_packed_small_lattice_forward_parity(lib):
+    """Filters and log Z of the packed small-lattice forward (P x P worldlines per 32 x 32 tile,
+    block-diagonal circulant) against the oracle, with and without reconnections at tau = beta;
+    the plan must route every L <= 16 chain through it."""
+    fhmc, sampler = lib
+    descs = PACKED
+    say("packed forward parity", [(d.L, d.L_tau, d.n_up, d.n_dn, d.block_len) for d in descs])
+    S = sampler.Sampler(descs, PRECS["mfma3"])
+    counts = (ctypes.c_int32 * 4)()
+    assert fhmc.lib.fh_debug_forward_kernels(S.plan, counts) == 0
+
+    def n_tasks(sel, per):
+        return sum((-(-d.n_up // per) + -(-d.n_dn // per)) * -(-d.L_tau // (d.block_len or d.L_tau))
+                   for d in descs if sel(d.L))
+    assert counts[2] == n_tasks(lambda L: 8 < L <= 16, 8)
+    assert counts[3] == n_tasks(lambda L: L <= 8, 32)
+    assert counts[1] == sum(d.n_particles * -(-d.L_tau // (d.block_len or d.L_tau))
+                            for d in descs if 16 < d.L < 32)
+    aux, paths = mixed_state(descs, seed=191)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+
+    def check(s, perms=None):
+        logZ = S.unpack_particles(S.forward_filter(A, P, s))
+        assert S.status() == (0, -1)
+        for c, d in enumerate(descs):
+            ref_lz, ref_rows = oracle_forward(d, aux[c], paths[c], s)
+            if perms is not None:
+                ref_lz, _ = oracle_logz_perm(d, aux[c], paths[c], s, perms[c])
+            err = np.abs(logZ[c] - ref_lz)
+            assert np.all(err <= logz_tol("mfma3", ref_lz, 0.0, d.L_tau)), (c, s, err.max())
+            for p in range(d.n_particles):
+                err = rel_row_err(S.filters(c, p), ref_rows[p])
+                assert err <= FILTER_TOL["mfma3"], (c, p, s, err)
+
+    for s in (0, 1, 2):
+        check(s)
+    perms = random_perms(descs, np.random.default_rng(19))
+    rng = np.random.default_rng(91)
+    paths = [loop_walk_paths(d, q, rng) for d, q in zip(descs, perms)]
+    S.set_permutation(perms)
+    P = S.pack_paths(paths)
+    for s in (1, 2):
+        check(s, perms)
+    S.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp64fft"])
 def test_backward_sample_parity_fp64(lib, prec):
     fhmc, sampler = lib
