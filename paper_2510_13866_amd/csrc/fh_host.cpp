@@ -339,15 +339,15 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     std::vector<PairTask> fwd32;
     std::vector<DrawTask> fwdx, draw32, draww, drawx;
     std::vector<PackTask> fwdp2, fwdp4;
-    // small lattices whose filter region fits the packed kernel's 32-bit row offsets
+    // small lattices whose filter region (FP32) fits the packed kernel's 31-bit byte offsets
     auto packed = [&](int c) {
         const ChainInfo& ci = p->chains[c];
-        return ci.L <= kPackMaxL && (int64_t)ci.np * ci.L_tau * ci.N < ((int64_t)1 << 31);
+        return ci.L <= kPackMaxL && (int64_t)ci.np * ci.L_tau * ci.N * 4 < ((int64_t)1 << 31);
     };
     for (int c : order) {
         if (!packed(c)) continue;
         const ChainInfo& ci = p->chains[c];
-        const int P = pack_blocks(ci.L), per = 2 * P * P;
+        const int P = pack_blocks(ci.L), per = kPackTiles * P * P;
         for (int spin = 0; spin < 2; ++spin) {
             const int p0 = spin ? ci.n_up : 0, p1 = spin ? ci.np : ci.n_up;
             for (int q = p0; q < p1; q += per)

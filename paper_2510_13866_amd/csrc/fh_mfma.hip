@@ -556,15 +556,31 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     }
 }
 
+// Raw buffer resources: word 3 of the descriptor on gfx9-family chips (32-bit data format,
+// no swizzle), and the cache-policy bit of a streaming (nontemporal) store.
+constexpr int kBufferWord3 = 0x00020000;
+constexpr int kNontemporal = 2;
+
+// Bits of a float for the b32 buffer store. The value is taken as a function argument: applied
+// directly to an element of an ext_vector_type, __builtin_bit_cast reads element 0 whatever the
+// index (seen with this compiler), so it never gets a vector element.
+__device__ inline uint32_t fbits(float f) { return __builtin_bit_cast(uint32_t, f); }
+
 // Segmented sum over the lanes that share a column block of BS lanes (BS = 16: the DPP rows
-// J and J + 2; BS = 8: the half rows J and J + 4): every lane gets its block's sum.
+// J and J + 2; BS = 8: the half rows J and J + 4): every lane gets its block's sum. The two
+// halves of the wavefront meet through v_permlane32_swap, which exchanges one half of its
+// destination with the other half of its source: the two results hold the low half's values
+// in one and the high half's in the other, so their sum is the same in every lane.
 template <int BS>
 __device__ inline float block_sum(float v) {
     v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
     v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
     v = dpp_add<0x141>(v);  // row_half_mirror: sums over 8 lanes
     if (BS == 16) v = dpp_add<0x140>(v);  // row_mirror: sums over 16 lanes
-    return v + __shfl_xor(v, 32, 64);
+    // both halves of the wavefront, in the same operand order in every lane
+    const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(uint32_t, v),
+                                                    __builtin_bit_cast(uint32_t, v), false, false);
+    return __builtin_bit_cast(float, (uint32_t)r[0]) + __builtin_bit_cast(float, (uint32_t)r[1]);
 }
 
 // Small lattices packed block-diagonally (L <= BS = 32 / P). P x P worldlines of one (chain,
@@ -572,16 +588,17 @@ __device__ inline float block_sum(float v) {
 // and columns BS J .. BS J + L - 1, and the circulant operand is block-diagonal with one L x L
 // circulant g((i - j) mod L) per diagonal block. Every term coupling two blocks is an exact zero,
 // so C F C is C_L F_IJ C_L block by block, with the same six split products as the padded tile
-// of k_forward_mfma: same arithmetic, P^2 worldlines for the matrix work of one. Two tiles per
-// wavefront, as in k_forward_mfma2.
+// of k_forward_mfma: same arithmetic, P^2 worldlines for the matrix work of one. NT tiles per
+// wavefront (two tiles overlap one tile's splitting with the other's matrix work, as in
+// k_forward_mfma2; one tile doubles the wavefronts of a small batch).
 //
 // Slots. Slot s = T P^2 + I P + J (tile T, block (I, J)) of a task holds worldline
 // p0 + min(s, n - 1); slots past n repeat the last worldline and are neither stored nor
 // counted. Each block's normaliser comes from a segmented wavefront sum; the slot's log Z is
 // kept by its owner lane BS J + T P + I (first half of the wavefront) as an FP64 mantissa and a
 // binary exponent, renormalised every step, so no log is taken inside the loop.
-template <int P>
-__global__ __launch_bounds__(kThreads, 2) void k_forward_pack(
+template <int P, int NT>
+__global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
     const ChainInfo* __restrict__ chains, const PackTask* __restrict__ tasks, int n_tasks,
     const uint16_t* __restrict__ cmatp, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
@@ -605,7 +622,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_pack(
     const double coef = spin ? c.coef_dn : c.coef_up;
     const int32_t* pc = paths + c.path_off;
     // a full task (every slot its own worldline, L filling the blocks) stores unmasked
-    const bool full = t.n == 2 * PP && L == BS;
+    const bool full = t.n == NT * PP && L == BS;
 
     Split3 C;
     {
@@ -623,29 +640,35 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_pack(
     // 4 hl + cv(v)
     auto cv = [](int v) { return 8 * (v >> 2) + (v & 3) - BS * (v / RPB); };
     const int64_t rowoff = (int64_t)t.block * (c.B - 1);
-    // per (tile, block row): this lane's slot, its start site and its row offset in the chain's
-    // filter region (element (4 hl + cv(v), lx) of the block at off + cv(v) L)
-    int ax[2][P], ay[2][P];
-    uint32_t off[2][P];
-    bool ok[2][P];
+    // per (tile, block row): this lane's slot, its byte offset in the chain's filter region
+    // (element (4 hl + cv(v), lx) of the block at off + 4 cv(v) L) and whether it is stored.
+    // The region is addressed through a buffer resource (32-bit offsets; the plan packs only
+    // chains whose filter region is under 2 GiB).
+    const __amdgpu_buffer_rsrc_t frs = __builtin_amdgcn_make_buffer_rsrc(
+        filt + c.filt_off, (short)0, 0x7fffffff, kBufferWord3);
+    uint32_t off[NT][P];
+    bool ok[NT][P];
+    f32x16 F[NT];
 #pragma unroll
-    for (int T = 0; T < 2; ++T)
+    for (int T = 0; T < NT; ++T)
 #pragma unroll
         for (int I = 0; I < P; ++I) {
             const int s = T * PP + I * P + J;
             const int pw = t.p0 + (s < t.n ? s : t.n - 1);
             int a = pc[(int64_t)start * c.np + pw];
             a = (a < 0 || a >= N) ? 0 : a;  // reported by the owner lane below
-            ax[T][I] = a % L;
-            ay[T][I] = a / L;
-            off[T][I] = (uint32_t)(((int64_t)pw * L_tau + rowoff) * N + 4 * hl * L + lx);
+            const int ax = a % L, ay = a / L;
+#pragma unroll
+            for (int v = I * RPB; v < (I + 1) * RPB; ++v)
+                F[T][v] = (lx == ax && 4 * hl + cv(v) == ay) ? 1.0f : 0.0f;
+            off[T][I] = (uint32_t)((((int64_t)pw * L_tau + rowoff) * N + 4 * hl * L + lx) * 4);
             ok[T][I] = s < t.n && lx < L;
         }
     // owner lane: slot (T, I, J) with T P + I = lx, first half
     const int oti = lx;
     const int oT = oti / P, oI = oti % P;
     const int os = oT * PP + oI * P + J;
-    const bool owner = hl == 0 && oti < 2 * P && os < t.n;
+    const bool owner = hl == 0 && oti < NT * P && os < t.n;
     int oe = 0;
     double la = 0.0, mant = 1.0;
     int ex2 = 0;
@@ -668,69 +691,69 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_pack(
 #pragma unroll
         for (int v = 0; v < 16; ++v) dst[v] = inside(v) ? Wl[cv(v) * L] : Wsp[(int64_t)l * N];
     };
-    f32x16 F0, F1;
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int I = v / RPB, ly = 4 * hl + cv(v);
-        F0[v] = (lx == ax[0][I] && ly == ay[0][I]) ? 1.0f : 0.0f;
-        F1[v] = (lx == ax[1][I] && ly == ay[1][I]) ? 1.0f : 0.0f;
-    }
     bool bad = false;
     float wn[16];
     load_w((start + 1) % L_tau, wn);
     auto step = [&](int j) {
         const int l = (start + j) % L_tau;
-        const f32x16 X0 = circ_step(F0, C, neg);
-        const f32x16 X1 = circ_step(F1, C, neg);
-        const f32x16 H0 = circ_step(X0, C, neg);
-        const f32x16 H1 = circ_step(X1, C, neg);
-        float s0[P], s1[P];
+        f32x16 H[NT];
 #pragma unroll
-        for (int I = 0; I < P; ++I) s0[I] = s1[I] = 0.0f;
+        for (int T = 0; T < NT; ++T) H[T] = circ_step(F[T], C, neg);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            F0[v] = H0[v] * wn[v];
-            F1[v] = H1[v] * wn[v];
-            s0[v / RPB] += F0[v];
-            s1[v / RPB] += F1[v];
-        }
+        for (int T = 0; T < NT; ++T) H[T] = circ_step(H[T], C, neg);
+        float sm[NT][P];
+#pragma unroll
+        for (int T = 0; T < NT; ++T)
+#pragma unroll
+            for (int I = 0; I < P; ++I) sm[T][I] = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+#pragma unroll
+            for (int T = 0; T < NT; ++T) {
+                F[T][v] = H[T][v] * wn[v];
+                sm[T][v / RPB] += F[T][v];
+            }
         load_w((l + 1) % L_tau, wn);  // the last step fetches a slice it does not use
         __builtin_amdgcn_sched_barrier(0);
-        float inv0[P], inv1[P], mine = 1.0f;
+        float inv[NT][P], mine = 1.0f;
 #pragma unroll
-        for (int I = 0; I < P; ++I) {
-            const float t0 = block_sum<BS>(s0[I]), t1 = block_sum<BS>(s1[I]);
-            bad = bad || !(t0 > 0.0f && t0 <= 3.402823466e38f) || !(t1 > 0.0f && t1 <= 3.402823466e38f);
-            // f~_j = h_j * inv: the normaliser applied is exactly 1/inv
-            inv0[I] = __builtin_amdgcn_rcpf(t0);
-            inv1[I] = __builtin_amdgcn_rcpf(t1);
-            mine = oti == I ? inv0[I] : mine;
-            mine = oti == P + I ? inv1[I] : mine;
-        }
+        for (int T = 0; T < NT; ++T)
+#pragma unroll
+            for (int I = 0; I < P; ++I) {
+                const float tot = block_sum<BS>(sm[T][I]);
+                bad = bad || !(tot > 0.0f && tot <= 3.402823466e38f);
+                // f~_j = h_j * inv: the normaliser applied is exactly 1/inv
+                inv[T][I] = __builtin_amdgcn_rcpf(tot);
+                mine = oti == T * P + I ? inv[T][I] : mine;
+            }
         // log Z -= log(inv): FP64 mantissa times 2^ex2, renormalised every step
         mant *= (double)mine;
         int e;
         mant = frexp(mant, &e);
         ex2 += e;
         la += shift[l];
-        float* rowj = filt + c.filt_off + (int64_t)(j - 1) * N;
+        // byte offsets: lane part in a VGPR, row and register part in an SGPR
+        const int rowj = (j - 1) * N;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            F0[v] *= inv0[v / RPB];
-            F1[v] *= inv1[v / RPB];
-        }
+        for (int v = 0; v < 16; ++v)
+#pragma unroll
+            for (int T = 0; T < NT; ++T) F[T][v] *= inv[T][v / RPB];
         if (full) {
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                __builtin_nontemporal_store(F0[v], rowj + cv(v) * L + off[0][v / RPB]);
-                __builtin_nontemporal_store(F1[v], rowj + cv(v) * L + off[1][v / RPB]);
-            }
+            for (int v = 0; v < 16; ++v)
+#pragma unroll
+                for (int T = 0; T < NT; ++T)
+                    __builtin_amdgcn_raw_buffer_store_b32(fbits(F[T][v]), frs, off[T][v / RPB],
+                                                          (rowj + cv(v) * L) * 4, kNontemporal);
         } else {
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const bool in = 4 * hl + cv(v) < L;
-                if (in && ok[0][v / RPB]) __builtin_nontemporal_store(F0[v], rowj + cv(v) * L + off[0][v / RPB]);
-                if (in && ok[1][v / RPB]) __builtin_nontemporal_store(F1[v], rowj + cv(v) * L + off[1][v / RPB]);
+#pragma unroll
+                for (int T = 0; T < NT; ++T)
+                    if (in && ok[T][v / RPB])
+                        __builtin_amdgcn_raw_buffer_store_b32(fbits(F[T][v]), frs, off[T][v / RPB],
+                                                              (rowj + cv(v) * L) * 4, kNontemporal);
             }
         }
     };
@@ -739,18 +762,19 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_pack(
         for (int j = 2; j < len; ++j) step(j);
     }
     // end weights (C f~ C)(e) of every slot: the owner reads its block's element at e
-    const f32x16 X0 = circ_step(F0, C, neg);
-    const f32x16 X1 = circ_step(F1, C, neg);
-    const f32x16 H0 = circ_step(X0, C, neg);
-    const f32x16 H1 = circ_step(X1, C, neg);
+    f32x16 H[NT];
+#pragma unroll
+    for (int T = 0; T < NT; ++T) H[T] = circ_step(circ_step(F[T], C, neg), C, neg);
     const int row = BS * oI + oe / L, col = BS * J + oe % L;
     const int src = col + 32 * ((row >> 2) & 1), ve = 4 * (row >> 3) + (row & 3);
     float hv = 0.0f;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const float h0 = __shfl(H0[v], src, 64), h1 = __shfl(H1[v], src, 64);
-        if (v == ve) hv = oT ? h1 : h0;
-    }
+    for (int v = 0; v < 16; ++v)
+#pragma unroll
+        for (int T = 0; T < NT; ++T) {
+            const float h = __shfl(H[T][v], src, 64);
+            if (v == ve && T == oT) hv = h;
+        }
     if (bad) set_status(status, FH_ERR_NONFINITE, t.chain);
     if (owner) {
         if (!(hv > 0.0f)) set_status(status, FH_ERR_NONFINITE, t.chain);  // end weight underflowed
@@ -1205,7 +1229,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
     // small lattices, packed block-diagonally: L <= 16 two-by-two, L <= 8 four-by-four
     if (p->n_fwdp2_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_fwdp2_tasks + kWaves - 1) / kWaves);
-        hipLaunchKernelGGL(k_forward_pack<2>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+        hipLaunchKernelGGL((k_forward_pack<2, kPackTiles>), dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwdp_tasks, p->n_fwdp2_tasks, p->d.cmatp, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
@@ -1215,7 +1239,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
     }
     if (p->n_fwdp4_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_fwdp4_tasks + kWaves - 1) / kWaves);
-        hipLaunchKernelGGL(k_forward_pack<4>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+        hipLaunchKernelGGL((k_forward_pack<4, kPackTiles>), dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwdp_tasks + p->n_fwdp2_tasks, p->n_fwdp4_tasks, p->d.cmatp,
                            (const float*)aux, (const float*)p->d.W, p->d.wshift, p->aux_elems,
                            p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,

@@ -209,8 +209,8 @@ def test_packed_small_lattice_forward_parity(lib):
     def n_tasks(sel, per):
         return sum((-(-d.n_up // per) + -(-d.n_dn // per)) * -(-d.L_tau // (d.block_len or d.L_tau))
                    for d in descs if sel(d.L))
-    assert counts[2] == n_tasks(lambda L: 8 < L <= 16, 8)
-    assert counts[3] == n_tasks(lambda L: L <= 8, 32)
+    assert counts[2] == n_tasks(lambda L: 8 < L <= 16, 4)     # one tile of 2 x 2 per task
+    assert counts[3] == n_tasks(lambda L: L <= 8, 16)         # one tile of 4 x 4
     assert counts[1] == sum(d.n_particles * -(-d.L_tau // (d.block_len or d.L_tau))
                             for d in descs if 16 < d.L < 32)
     aux, paths = mixed_state(descs, seed=191)
