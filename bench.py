@@ -468,14 +468,21 @@ def main():
         S.status()   # FP32 filters may underflow on this state; only the timing is used
         Sf = Sampler(descs, prec, fhmc.FH_FLAG_FULL_ROW_DRAW)
         Ae, Pe = A.clone(), P.clone()
+        # the plan as built (per-chain switch between the windowed and full-row kernels), the
+        # windowed kernel alone, and the full-row kernel alone; each the average over nf
+        # backward passes of the same state
+        adapt_ms = time_backward(S, A.clone(), P.clone(), nf, stream, sweep=6)
+        assert fhmc.lib.fh_debug_backward_adapt(S.plan, 0, None) == 0
         win_ms = time_backward(S, A.clone(), P.clone(), nf, stream, sweep=6)
+        assert fhmc.lib.fh_debug_backward_adapt(S.plan, 1, None) == 0
         full_ms = time_backward(Sf, Ae, Pe, nf, stream, sweep=6)
         Sf.close()
         S.status()
         extra["backward_after_one_unrestored_sweep"] = {
-            "k_backward_win_ms": round(win_ms, 4), "k_backward_l32_ms": round(full_ms, 4)}
-        log("  after one unrestored sweep: k_backward_win %.3f ms, k_backward_l32 %.3f ms"
-            % (win_ms, full_ms))
+            "adaptive_ms": round(adapt_ms, 4), "k_backward_win_only_ms": round(win_ms, 4),
+            "k_backward_l32_only_ms": round(full_ms, 4), "passes_averaged": nf}
+        log("  after one unrestored sweep: adaptive %.3f ms, k_backward_win only %.3f ms, "
+            "k_backward_l32 only %.3f ms" % (adapt_ms, win_ms, full_ms))
     if not args.no_error:
         # fresh state so the sampled particles' oracle filters are cheap to rebuild
         A2, P2 = S.pack_aux(aux), S.pack_paths(paths)

@@ -62,10 +62,20 @@ int fh_debug_window_draw(int32_t L, int32_t w, const double* g, double g_out, co
  *   fh_debug_inflate_window_bound multiplies every chain's outside bound by factor >= 1 (an
  *   infinite factor sends every windowed draw through the full-row scan; a larger bound only
  *   makes the certificate stricter, so draws stay exact);
- *   fh_debug_backward_kernels reports how many backward tasks use the windowed kernel and how
- *   many the full-row kernels. */
+ *   fh_debug_backward_kernels reports how many backward tasks belong to chains that may use the
+ *   windowed kernel (n_windowed) and how many to chains that always use the full-row kernels
+ *   (n_full_row);
+ *   fh_debug_backward_adapt switches the plan's choice between the windowed and the full-row
+ *   kernels on (enable = 1, the default of a new plan) or off (0: windowed chains always use the
+ *   window). After a backward pass whose first windows left more than 3/20 of the windowed
+ *   chains' draws uncertified, the next backward passes (16, doubling to 64 while retries fail)
+ *   use the full-row kernels; the draws are the same either way. full_row_passes_left (nullable,
+ *   caller-owned, one int32) receives how many coming backward passes use the full-row kernels
+ *   (0: the window), read before the switch; changing the setting puts the plan back on the
+ *   window. */
 int fh_debug_inflate_window_bound(fh_plan plan, double factor);
 int fh_debug_backward_kernels(fh_plan plan, int32_t* n_windowed, int32_t* n_full_row);
+int fh_debug_backward_adapt(fh_plan plan, int32_t enable, int32_t* full_row_passes_left);
 
 /* Forward work items of an FH_FP32_MFMA3 plan, by kernel: counts[0] worldline pairs of L = 32
  * chains, counts[1] single padded worldlines (16 < L < 32), counts[2] packed tasks of 2 x 2

@@ -149,7 +149,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign,
+                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
                     d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -283,6 +283,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
                      p->cmat64.data() + (size_t)kCmat64PerChain * c);
         windowed[c] = win_select(p->tables.data() + tab_g(ci), ci.L, &ci.win_w, &ci.win_gout) &&
                       ci.L <= kWinMaxL && !(flags & FH_FLAG_FULL_ROW_DRAW);
+        ci.win_on = windowed[c] ? 1 : 0;
         ci.win_gout2 = win_bound_for(p->tables.data() + tab_g(ci), ci.L, kWin2W);
     }
 
@@ -357,11 +358,13 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     }
     for (const PairTask& t : fwd)
         if (p->chains[t.chain].L == 32) fwd32.push_back(t);
+    // Backward: a windowed chain's tasks sit both in the windowed list and in a full-row list;
+    // per sweep, bw_state decides which of the two kernels draws them (the other skips them).
     for (const DrawTask& t : draw) {
         if (p->chains[t.chain].L != 32 && !packed(t.chain)) fwdx.push_back(t);
-        if (windowed[t.chain]) {
-            draww.push_back(t);
-        } else if (p->chains[t.chain].L == 32) {
+        if (windowed[t.chain]) draww.push_back(t);
+        else ++p->n_full_only_tasks;
+        if (p->chains[t.chain].L == 32) {
             draw32.push_back(t);
         } else {
             drawx.push_back(t);
@@ -411,6 +414,11 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.perm_inv, sizeof(int32_t) * (size_t)part);
     if (e == hipSuccess) e = dalloc(&dv.sign, sizeof(int32_t) * (size_t)n_chains);
     if (e == hipSuccess) e = dalloc(&dv.status, sizeof(int32_t) * 2);
+    if (e == hipSuccess) e = dalloc(&dv.bw_state, sizeof(int32_t) * (kBwCounts + (size_t)n_chains));
+    if (e == hipSuccess) {
+        std::vector<int32_t> zero(kBwCounts + (size_t)n_chains, 0);
+        e = hipMemcpy(dv.bw_state, zero.data(), sizeof(int32_t) * zero.size(), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = dalloc(&dv.sweep, sizeof(uint64_t));
     if (e == hipSuccess) e = hipMemcpy(dv.tables, p->tables.data(), sizeof(double) * p->tables.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
@@ -987,7 +995,22 @@ int fh_debug_inflate_window_bound(fh_plan p, double factor) {
 int fh_debug_backward_kernels(fh_plan p, int32_t* n_windowed, int32_t* n_full_row) {
     if (!p || !n_windowed || !n_full_row) return FH_ERR_INVALID_ARG;
     *n_windowed = p->n_draww_tasks;
-    *n_full_row = p->n_draw32_tasks + p->n_drawx_tasks;
+    *n_full_row = p->n_full_only_tasks;
+    return FH_OK;
+}
+
+int fh_debug_backward_adapt(fh_plan p, int32_t enable, int32_t* full_row_passes_left) {
+    if (!p || (enable != 0 && enable != 1)) return FH_ERR_INVALID_ARG;
+    FH_TRY(hipDeviceSynchronize());
+    std::vector<int32_t> st(kBwCounts + (size_t)p->n_chains);
+    FH_TRY(hipMemcpy(st.data(), p->d.bw_state, sizeof(int32_t) * st.size(), hipMemcpyDeviceToHost));
+    if (full_row_passes_left) *full_row_passes_left = st[0];
+    if ((enable != 0) != p->bw_adapt) {
+        p->bw_adapt = enable != 0;
+        drop_graph(p);  // the captured sweep launches the adaptation kernel or not
+        std::fill(st.begin(), st.end(), 0);  // back on the window
+        FH_TRY(hipMemcpy(p->d.bw_state, st.data(), sizeof(int32_t) * st.size(), hipMemcpyHostToDevice));
+    }
     return FH_OK;
 }
 

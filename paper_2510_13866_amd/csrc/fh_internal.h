@@ -32,7 +32,7 @@ struct ChainInfo {
     int64_t site_off;  // per-site outputs (S(k), C(r)) packed by chain: [site_off + r]
     int32_t g0, g1;    // gradient worldline groups of this chain: [g0, g1)
     int32_t win_w;     // windowed backward draws: half-width w of the window around s
-    int32_t win_pad;
+    int32_t win_on;    // 1: the chain's draws may use the windowed kernel (see bw_state)
     double win_gout;   // bound on G(s - r) over the sites r outside that window
     double win_gout2;  // the same for the second window (half-width kWin2W)
 };
@@ -43,6 +43,7 @@ FH_HD inline int64_t tab_dghat(const ChainInfo& c) { return c.tab_off + c.N; }
 FH_HD inline int64_t tab_g(const ChainInfo& c) { return c.tab_off + 2 * c.N; }
 FH_HD inline int64_t tab_tw(const ChainInfo& c) { return c.tab_off + 2 * c.N + c.L; }
 inline int64_t tab_size(int L) { return 2 * (int64_t)L * L + L + 2 * L; }
+constexpr int kBwCounts = 4;  // offset of the per-chain counts in Device::bw_state
 constexpr int kCmatPerChain = 3 * 2 * 64 * 8;
 constexpr int kCmat64PerChain = 16 * 64;
 
@@ -121,6 +122,10 @@ struct Device {
                                  // (chain-local indices); the identity unless changed
     int32_t* perm_inv = nullptr; // [particles] its inverse
     int32_t* sign = nullptr;     // [n_chains] sgn(P_up) sgn(P_dn), +1 or -1
+    int32_t* bw_state = nullptr; // backward kernel choice for the windowed chains:
+                                 // [0] full-row passes left (0: windowed), [1] current hold
+                                 // length, then per chain the uncertified first-window draws
+                                 // of the last windowed pass ([kBwCounts + chain])
     int32_t* status = nullptr;   // [0] first error code, [1] its chain
     uint64_t* sweep = nullptr;   // sweep index read by the kernels
 };
@@ -148,6 +153,8 @@ struct fh_plan_s {
     int32_t n_fwdd_tasks = 0;  // FP64 circulant forward tasks (the FFT takes n_fwd_tasks pairs)
     bool grad_dmfma = false;   // FP64 plan whose chains all have L <= 32: adjoint on the matrix cores
     double win_bound_scale = 1.0;  // test hook: >= 1 inflates every window bound
+    bool bw_adapt = true;          // switch clustered chains to the full-row kernels
+    int32_t n_full_only_tasks = 0; // backward tasks of chains that never use the window
     int64_t gpart_elems = 0;
     int64_t total_sites = 0;  // sum of N over the chains
     int32_t max_N = 0, max_L = 0, max_np = 0;

@@ -350,6 +350,13 @@ __global__ void k_logz_reduce(const ChainInfo* __restrict__ chains, int n_chains
     logZ[gp] = s;
 }
 
+// A windowed chain's backward tasks sit in the windowed kernel's list and in a full-row
+// kernel's list; the windowed kernel draws them unless k_bw_adapt has moved the plan to the
+// full-row kernels for this pass (bw_state[0] > 0).
+__device__ inline bool on_window(const ChainInfo* chains, int chain, const int32_t* bw_state) {
+    return chains[chain].win_on && bw_state[0] == 0;
+}
+
 // Backward sampling, one wavefront per (chain, particle, block). For j = len-1 .. 1:
 // w(r) = max(f~_j(r), 0) g(x_{j+1} - x) g(y_{j+1} - y) in FP64; lane l owns the contiguous sites
 // [l E, (l+1) E); C_r = (exclusive scan of lane totals) + (running sum within the lane);
@@ -358,10 +365,12 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_backward(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
-    const int32_t* __restrict__ perm, const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    const int32_t* __restrict__ perm, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
+    const int32_t* __restrict__ bw_state) {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int task = blockIdx.x * kWaves + wv;
     if (task >= n_tasks) return;  // whole wavefront leaves; no block-level barrier below
+    if (on_window(chains, tasks[task].chain, bw_state)) return;  // k_backward_win draws it
     const DrawTask t = tasks[task];
     const ChainInfo& c = chains[t.chain];
     const uint64_t sweep = *sweep_ptr;
@@ -620,13 +629,13 @@ template <typename T>
 __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l32(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
-    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const int32_t* __restrict__ bw_state) {
     constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
     constexpr int NB = DEPTH + 1;
     __shared__ double g2sh[kWaves][64];  // g2[m] = g(m mod 32), so g(d) = g2[d + 32] for |d| < 32
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wv);
-    const bool active = task < n_tasks;
+    const bool active = task < n_tasks && !on_window(chains, tasks[task].chain, bw_state);
     DrawTask t = {0, 0, 0, 0};
     if (active) {
         t = tasks[task];
@@ -922,7 +931,8 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_backward_win(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
-    const int32_t* __restrict__ perm, const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    const int32_t* __restrict__ perm, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
+    int32_t* __restrict__ bw_state) {
     constexpr int G = kThreads / kWinLanes;
     constexpr int K = kWinPerLane;
     __shared__ double gsh[G][kWinMaxL];
@@ -930,7 +940,8 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     const int lane64 = threadIdx.x & 63;
     const int gbase = lane64 - li;  // the group's first lane in the wavefront
     const int task = blockIdx.x * G + grp;
-    const bool active = task < n_tasks;
+    // while the plan is on the full-row kernels, they draw these tasks
+    const bool active = task < n_tasks && bw_state[0] == 0;
     const DrawTask t = active ? tasks[task] : DrawTask{0, 0, 0, 0};
     const ChainInfo& c = chains[t.chain];
     const int L = c.L, N = c.N, L_tau = c.L_tau, w = c.win_w;
@@ -965,6 +976,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     const double gout = c.win_gout * kWinMassBound;
     double ureg = 0.0;
     int err = 0;  // the first error of the block, reported once after the loop
+    int n_unc = 0;  // draws the first window did not certify (kept by lane 0 of the group)
     // Drawn sites are stored sixteen draws at a time: lane li keeps the site of draw sb + li of
     // the current batch sb. A store retires in order with the loads after it, so a store after
     // every draw would make each draw's window loads wait for the previous draw's store; the
@@ -1055,6 +1067,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         const bool cert = gm != 0 && (packed >> 16) != 0;
         int nx = packed & 255, ny = (packed >> 8) & 255;
         bool need_row = false;
+        n_unc += (real && !cert) ? 1 : 0;
         if (real && !cert) {  // uniform within the group: the wider window
             const int p2 = window2_draw(row, L, li, gbase, cx, cy, g, u, c.win_gout2);
             if (p2 >> 16) {
@@ -1094,6 +1107,44 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     }
     if (nd_max > 0) flush((nd_max - 1) & ~15);
     if (err != 0 && li == 0) set_status(status, err, t.chain);  // the block's first error
+    if (active && li == 0 && n_unc > 0) atomicAdd(&bw_state[kBwCounts + t.chain], n_unc);
+}
+
+// After the backward pass of a sweep: moves the plan's windowed chains between the windowed
+// kernel and the full-row kernels (the draws are the same either way). When the first window
+// left more than 3/20 of the windowed chains' draws uncertified, the windowed kernel runs slower
+// than the full-row one (its four worldlines per wavefront wait for every fallback), and the
+// next `hold` backward passes use the full-row kernels; then the window is tried again. hold
+// starts at 16 and doubles, up to 64, while the retries keep failing. The switch is plan-wide:
+// both kernels are latency-bound, so splitting the chains between them would cost the sum of
+// their times. One workgroup; the per-chain counts are summed in chain order.
+__global__ void k_bw_adapt(const ChainInfo* __restrict__ chains, int n_chains,
+                           int32_t* __restrict__ bw_state) {
+    __shared__ int64_t part[2][kThreads];
+    int64_t unc = 0, draws = 0;
+    for (int ci = threadIdx.x; ci < n_chains; ci += blockDim.x) {
+        const ChainInfo& c = chains[ci];
+        if (!c.win_on) continue;
+        unc += bw_state[kBwCounts + ci];
+        draws += (int64_t)c.np * (c.L_tau - c.nb);
+        bw_state[kBwCounts + ci] = 0;
+    }
+    part[0][threadIdx.x] = unc;
+    part[1][threadIdx.x] = draws;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int k = 1; k < (int)blockDim.x; ++k) {
+        unc += part[0][k];
+        draws += part[1][k];
+    }
+    if (bw_state[0] > 0) {  // a full-row pass just ran
+        bw_state[0] -= 1;
+    } else if (unc * 20 > draws * 3) {
+        bw_state[1] = bw_state[1] == 0 ? 16 : min(2 * bw_state[1], 64);
+        bw_state[0] = bw_state[1];
+    } else {
+        bw_state[1] = 0;
+    }
 }
 
 // One wavefront per (chain, worldline, block) of the chains with L != 32, the body chosen per
@@ -1102,11 +1153,11 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_backward_fast(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
-    const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const int32_t* __restrict__ bw_state) {
     __shared__ double gsh[kWaves][kMaxL];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int task = blockIdx.x * kWaves + wv;
-    const bool active = task < n_tasks;
+    const bool active = task < n_tasks && !on_window(chains, tasks[task].chain, bw_state);
     DrawTask t = {0, 0, 0, 0};
     if (active) {
         t = tasks[task];
@@ -1811,31 +1862,30 @@ hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
-    // windowed draws where the hopping kernel allows them; otherwise 32 x 32 chains on their own
-    // full-row kernel, the rest (any L) on the generic ones
+namespace {
+hipError_t launch_backward_kernels(fh_plan p, int32_t* paths, hipStream_t s) {
     if (p->n_draww_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_draww_tasks + kThreads / kWinLanes - 1) /
                                            (kThreads / kWinLanes));
         if (p->precision == FH_FP64)
             hipLaunchKernelGGL(k_backward_win<double>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draww_tasks, p->n_draww_tasks, p->d.tables,
-                               (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status);
+                               (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
         else
             hipLaunchKernelGGL(k_backward_win<float>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draww_tasks, p->n_draww_tasks, p->d.tables,
-                               (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status);
+                               (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
     }
     if (p->n_draw32_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_draw32_tasks + kWaves - 1) / kWaves);
         if (p->precision == FH_FP64)
             hipLaunchKernelGGL(k_backward_l32<double>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draw32_tasks, p->n_draw32_tasks, p->d.tables,
-                               (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status);
+                               (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
         else
             hipLaunchKernelGGL(k_backward_l32<float>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draw32_tasks, p->n_draw32_tasks, p->d.tables,
-                               (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status);
+                               (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
     }
     if (p->n_drawx_tasks == 0) return hipGetLastError();
     const unsigned blocks = (unsigned)((p->n_drawx_tasks + kWaves - 1) / kWaves);
@@ -1845,21 +1895,33 @@ hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
         if (p->precision == FH_FP64)
             hipLaunchKernelGGL(k_backward_fast<double>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, tasks, n, p->d.tables, (const double*)p->d.filt, paths,
-                               p->d.perm, p->d.sweep, p->d.status);
+                               p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
         else
             hipLaunchKernelGGL(k_backward_fast<float>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, tasks, n, p->d.tables, (const float*)p->d.filt, paths,
-                               p->d.perm, p->d.sweep, p->d.status);
+                               p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
         return hipGetLastError();
     }
     if (p->precision == FH_FP64)
         hipLaunchKernelGGL(k_backward<double>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            tasks, n, p->d.tables, (const double*)p->d.filt, paths, p->d.perm,
-                           p->d.sweep, p->d.status);
+                           p->d.sweep, p->d.status, p->d.bw_state);
     else
         hipLaunchKernelGGL(k_backward<float>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            tasks, n, p->d.tables, (const float*)p->d.filt, paths, p->d.perm,
-                           p->d.sweep, p->d.status);
+                           p->d.sweep, p->d.status, p->d.bw_state);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
+    // windowed draws where the hopping kernel allows them; 32 x 32 chains without the window (or
+    // moved off it for this sweep by k_bw_adapt) on their own full-row kernel, the rest on the
+    // generic ones
+    hipError_t e = launch_backward_kernels(p, paths, s);
+    if (e != hipSuccess || !p->bw_adapt || p->n_draww_tasks == 0) return e;
+    hipLaunchKernelGGL(k_bw_adapt, dim3(1), dim3(kThreads), 0, s, p->d.chains, p->n_chains,
+                       p->d.bw_state);
     return hipGetLastError();
 }
 

@@ -97,6 +97,7 @@ _sig("fh_debug_window_draw", c_int32, c_int32, c_int32, POINTER(c_double), c_dou
 _sig("fh_debug_inflate_window_bound", c_int32, c_void_p, c_double)
 _sig("fh_debug_backward_kernels", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32))
 _sig("fh_debug_forward_kernels", c_int32, c_void_p, POINTER(c_int32))
+_sig("fh_debug_backward_adapt", c_int32, c_void_p, c_int32, POINTER(c_int32))
 
 
 class FhError(RuntimeError):

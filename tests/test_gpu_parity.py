@@ -1157,10 +1157,10 @@ def test_windowed_draws_equal_full_row_draws(lib, prec):
 def test_windowed_draws_on_a_clustering_state(lib, prec):
     """Sweeps run on from the static start let the field cluster, so that many draws need the
     wider window or the full row; the windowed kernel must still draw exactly what the full-row
-    kernel draws, sweep after sweep (32 x 32 at L_tau = 160 and 16 x 16 at L_tau = 64). The host
-    mirror of the
-    draw rule, run on the device's filters and draws of one more backward pass, shows that the
-    wider window and the full row were both reached."""
+    kernel draws, sweep after sweep (32 x 32 at L_tau = 160 and 16 x 16 at L_tau = 64), with the
+    switch to the full-row kernels on (which the clustered state must trigger) and off. The host
+    mirror of the draw rule, run on the device's filters and draws of one more backward pass,
+    shows that the wider window and the full row were both reached."""
     fhmc, sampler = lib
     descs = synth.config_32x32(4.0, 1) + synth.config_16x16_hirsch(1) + [
         synth.ChainDesc(L=16, L_tau=64, n_up=128, n_dn=128, hs_kind=synth.HS_GAUSS, block_len=0,
@@ -1168,17 +1168,32 @@ def test_windowed_draws_on_a_clustering_state(lib, prec):
     say("windowed draws on a clustering state", prec)
     Sw = sampler.Sampler(descs, PRECS[prec])
     Sf = sampler.Sampler(descs, PRECS[prec], fhmc.FH_FLAG_FULL_ROW_DRAW)
+    So = sampler.Sampler(descs, PRECS[prec])          # windowed kernel only, no adaptation
+    assert fhmc.lib.fh_debug_backward_adapt(So.plan, 0, None) == 0
     aux = [synth.initial_aux(d) for d in descs]
     paths = [synth.initial_paths(d) for d in descs]
     Aw, Pw = Sw.pack_aux(aux), Sw.pack_paths(paths)
     Af, Pf = Sf.pack_aux(aux), Sf.pack_paths(paths)
+    Ao, Po = So.pack_aux(aux), So.pack_paths(paths)
+    held = ctypes.c_int32()
+    n_held = 0
     for s in range(4):
         Sw.sweep(Aw, Pw, s, 1)
         Sf.sweep(Af, Pf, s, 1)
-        gw, gf = Sw.unpack_paths(Pw), Sf.unpack_paths(Pf)
+        So.sweep(Ao, Po, s, 1)
+        gw, gf, go = Sw.unpack_paths(Pw), Sf.unpack_paths(Pf), So.unpack_paths(Po)
         for c in range(len(descs)):
             assert np.array_equal(gw[c], gf[c]), (s, c)
+            assert np.array_equal(go[c], gf[c]), (s, c)
         assert np.array_equal(Aw.cpu().numpy(), Af.cpu().numpy()), s
+        assert np.array_equal(Ao.cpu().numpy(), Af.cpu().numpy()), s
+        assert fhmc.lib.fh_debug_backward_adapt(Sw.plan, 1, ctypes.byref(held)) == 0
+        n_held += held.value > 0
+        assert fhmc.lib.fh_debug_backward_adapt(So.plan, 0, ctypes.byref(held)) == 0
+        assert held.value == 0
+    say("  sweeps after which the plan was on the full-row kernels:", n_held)
+    assert n_held > 0          # the clustered state moved the plan off the window
+    So.close()
     # which tier decided the draws of one more forward + backward on the clustered state
     s = 4
     c = 0
