@@ -834,74 +834,59 @@ __device__ int wave_row_draw(const T* __restrict__ row, int N, int L, int cx, in
     return lm ? __builtin_amdgcn_readlane(lastpos, 63 - __clzll((long long)lm)) : cur;
 }
 
-// Draw on the second window (half-width kWin2W) of one 16-lane group: lane li sums the weights
-// of its kWin2PerLane ranks in three sub-chunks of five (five loads in flight at a time, within
-// the register budget), the lane sums are scanned, and the lane holding the crossing re-reads the
-// one sub-chunk that holds it (from cache) to find the rank and its certificate. Returns
-// (1 << 16 | y << 8 | x) for a certified draw, 0 otherwise (uniform within the group).
+// Draw on the second window (half-width kWin2W) of one group's worldline, taken by the whole
+// wavefront: lane k holds the window ranks 4k .. 4k + 3 (site order), so the draw costs one
+// round trip of four loads per lane. The lane sums are scanned across the wavefront and the lane
+// holding the first rank above tau certifies the draw. Every argument is wavefront uniform.
+// Returns (1 << 16 | y << 8 | x) for a certified draw, 0 otherwise (uniform).
 template <typename T>
-__device__ int window2_draw(const T* __restrict__ row, int L, int li, int gbase, int cx, int cy,
-                            const double* g, double u, double gout2) {
-    constexpr int K2 = kWin2PerLane, SUB = 5;
-    static_assert(K2 == 3 * SUB, "three sub-chunks per lane");
+__device__ int wave_window2_draw(const T* __restrict__ row, int L, int cx, int cy,
+                                 const double* g, double u, double gout2, int lane) {
+    constexpr int K = 4;
+    static_assert(64 * K >= (2 * kWin2W + 1) * (2 * kWin2W + 1), "the window fits the wavefront");
     const int WW = win_width(kWin2W, L), nwin = WW * WW;
     const float rw = 1.0f / (float)WW;  // (q + 1/2) / WW in FP32 floors exactly for q < 2^12
     int tx, bx, ty, by;
     win_axis(cx, kWin2W, L, WW, &tx, &bx);
     win_axis(cy, kWin2W, L, WW, &ty, &by);
-    auto site_of = [&](int k, int* x, int* y) {
-        const int q = li * K2 + k;
+    int xs[K], ys[K];
+    T fv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int q = lane * K + k;
         const int qq = q < nwin ? q : 0;
         const int qy = (int)(((float)qq + 0.5f) * rw);
-        *x = win_at(qq - qy * WW, tx, bx);
-        *y = win_at(qy, ty, by);
-    };
-    auto wt = [&](int k, T fv, int x, int y) {
-        int dx = cx - x, dy = cy - y;
+        xs[k] = win_at(qq - qy * WW, tx, bx);
+        ys[k] = win_at(qy, ty, by);
+        fv[k] = row[ys[k] * L + xs[k]];
+    }
+    double P[K];
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        int dx = cx - xs[k], dy = cy - ys[k];
         dx += dx < 0 ? L : 0;
         dy += dy < 0 ? L : 0;
-        const double f = li * K2 + k < nwin ? (double)fv : 0.0;
-        return (f > 0.0 ? f : 0.0) * (g[dy] * g[dx]);
-    };
-    double c0 = 0.0, c1 = 0.0, c2 = 0.0;
-#pragma unroll 1
-    for (int k0 = 0; k0 < K2; k0 += SUB) {  // five loads in flight at a time (register budget)
-        double cs = 0.0;
-#pragma unroll
-        for (int k = k0; k < k0 + SUB; ++k) {
-            int x, y;
-            site_of(k, &x, &y);
-            cs += wt(k, row[y * L + x], x, y);
-        }
-        c0 = k0 == 0 ? cs : c0;
-        c1 = k0 == SUB ? cs : c1;
-        c2 = k0 == 2 * SUB ? cs : c2;
+        const double f = lane * K + k < nwin ? (double)fv[k] : 0.0;
+        acc += (f > 0.0 ? f : 0.0) * (g[dy] * g[dx]);
+        P[k] = acc;
     }
-    const double tot = (c0 + c1) + c2;
-    const double incl = group_scan_incl(tot);
-    const double excl = dpp_f64<0x111>(incl);
-    const double T_in = __shfl(incl, gbase + 15, 64);
+    double T_in;
+    const double incl = wave_incl_scan_f64(acc, lane, &T_in);
+    const double excl = incl - acc;
     const double tau = u * T_in;
     const bool fin = T_in > 0.0 && isfinite(T_in);
-    const uint32_t gm = (uint32_t)(__ballot(fin && incl > tau && tot > 0.0) >> gbase) & 0xFFFFu;
-    const int src = gm ? __ffs((int)gm) - 1 : 0;
+    const uint64_t fm = __ballot(fin && incl > tau && acc > 0.0);
+    if (!fm) return 0;
+    const int src = __ffsll((unsigned long long)fm) - 1;
     int res = 0;
-    if (gm && li == src) {
-        const double r1 = excl + c0, r2 = r1 + c1;
-        const int sc = r1 > tau ? 0 : r2 > tau ? 1 : 2;
-        double c_lo = sc == 0 ? excl : sc == 1 ? r1 : r2, c_hi = 0.0;
-        T v[SUB];  // one lane re-reads the sub-chunk from cache, all five loads at once
-        int xs[SUB], ys[SUB];
-#pragma unroll
-        for (int k = 0; k < SUB; ++k) {
-            site_of(SUB * sc + k, &xs[k], &ys[k]);
-            v[k] = row[ys[k] * L + xs[k]];
-        }
+    if (lane == src) {
+        double c_lo = excl, c_hi = 0.0;
         int pick = -1, pxy = 0;
 #pragma unroll
-        for (int k = 0; k < SUB; ++k) {
+        for (int k = 0; k < K; ++k) {
+            const double ck = excl + P[k];
             if (pick < 0) {
-                const double ck = c_lo + wt(SUB * sc + k, v[k], xs[k], ys[k]);
                 if (ck > tau) {
                     pick = k;
                     pxy = xs[k] | (ys[k] << 8);
@@ -914,7 +899,7 @@ __device__ int window2_draw(const T* __restrict__ row, int L, int li, int gbase,
         if (pick >= 0 && win_certified(c_lo, c_hi, tau, gout2 * kWinMassBound + kWinSlack * T_in))
             res = (1 << 16) | pxy;
     }
-    return __shfl(res, gbase + src, 64);
+    return __builtin_amdgcn_readlane(res, src);
 }
 
 // Backward sampling with windowed draws (the certificate is in fh_window.h): 16 lanes per
@@ -932,7 +917,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
     const int32_t* __restrict__ perm, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    int32_t* __restrict__ bw_state) {
+    int32_t* __restrict__ bw_state, int count_uncertified) {
     constexpr int G = kThreads / kWinLanes;
     constexpr int K = kWinPerLane;
     __shared__ double gsh[G][kWinMaxL];
@@ -1068,13 +1053,27 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         int nx = packed & 255, ny = (packed >> 8) & 255;
         bool need_row = false;
         n_unc += (real && !cert) ? 1 : 0;
-        if (real && !cert) {  // uniform within the group: the wider window
-            const int p2 = window2_draw(row, L, li, gbase, cx, cy, g, u, c.win_gout2);
-            if (p2 >> 16) {
-                nx = p2 & 255;
-                ny = (p2 >> 8) & 255;
-            } else {
-                need_row = true;
+        // an uncertified draw tries the wider window, one such group at a time, taken by the
+        // whole wavefront
+        uint64_t wide_left = __ballot(li == 0 && real && !cert);
+        while (wide_left) {
+            const int g0 = __ffsll((unsigned long long)wide_left) - 1;  // the group's lane 0
+            wide_left &= wide_left - 1;
+            const uint64_t rp = (uint64_t)(uintptr_t)row;
+            const T* rowg = (const T*)(uintptr_t)(
+                (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)rp, g0) |
+                ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(rp >> 32), g0) << 32));
+            const int p2 = wave_window2_draw(
+                rowg, __builtin_amdgcn_readlane(L, g0), __builtin_amdgcn_readlane(cx, g0),
+                __builtin_amdgcn_readlane(cy, g0), gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)],
+                readlane_f64(u, g0), readlane_f64(c.win_gout2, g0), lane64);
+            if ((lane64 >> 4) == (g0 >> 4)) {
+                if (p2 >> 16) {
+                    nx = p2 & 255;
+                    ny = (p2 >> 8) & 255;
+                } else {
+                    need_row = true;
+                }
             }
         }
         // then the full row, one group at a time, by the whole wavefront
@@ -1107,7 +1106,8 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     }
     if (nd_max > 0) flush((nd_max - 1) & ~15);
     if (err != 0 && li == 0) set_status(status, err, t.chain);  // the block's first error
-    if (active && li == 0 && n_unc > 0) atomicAdd(&bw_state[kBwCounts + t.chain], n_unc);
+    if (count_uncertified && active && li == 0 && n_unc > 0)
+        atomicAdd(&bw_state[kBwCounts + t.chain], n_unc);
 }
 
 // After the backward pass of a sweep: moves the plan's windowed chains between the windowed
@@ -1870,11 +1870,13 @@ hipError_t launch_backward_kernels(fh_plan p, int32_t* paths, hipStream_t s) {
         if (p->precision == FH_FP64)
             hipLaunchKernelGGL(k_backward_win<double>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draww_tasks, p->n_draww_tasks, p->d.tables,
-                               (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
+                               (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state,
+                               p->bw_adapt ? 1 : 0);
         else
             hipLaunchKernelGGL(k_backward_win<float>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draww_tasks, p->n_draww_tasks, p->d.tables,
-                               (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
+                               (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state,
+                               p->bw_adapt ? 1 : 0);
     }
     if (p->n_draw32_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_draw32_tasks + kWaves - 1) / kWaves);
