@@ -908,8 +908,9 @@ __device__ int wave_window2_draw(const T* __restrict__ row, int L, int cx, int c
 // order). Per draw it loads those filter values, forms max(f, 0) g(dy) g(dx), and the 16 lanes
 // scan their sums with DPP inside their row of the wavefront. The lane holding the first rank
 // above tau certifies the draw. An uncertified draw is retried on the wider window, and failing
-// that the whole wavefront scans the row in site order with k_backward's rule, one such group
-// at a time (ceil(N / 64) contiguous sites per lane). Lane li of a group computes
+// that on the row in site order with k_backward's rule; the whole wavefront takes each of these,
+// one such group at a time (four window ranks, or ceil(N / 64) contiguous sites, per lane).
+// Lane li of a group computes
 // the Philox uniform of draw s0 + li once per 16 draws. Every load address is in bounds for any
 // lane (inactive groups read chain 0's first row), so loads are unconditional and values masked.
 template <typename T>

@@ -35,7 +35,6 @@ constexpr double kWinMassBound = 1.0625;  // >= sum_r max(f_j(r), 0) of a normal
 constexpr double kWinSlack = 1e-13;       // FP64 rounding allowance, relative to the window mass
 constexpr int kWinSelectLog2 = 20;        // w is the smallest with g_out <= 2^-20 max G
 constexpr int kWin2W = 7;                 // second window, tried before the full row: 15 x 15
-constexpr int kWin2PerLane = 15;          // its ranks per lane: 16 * 15 >= 225
 
 // Window width along one dimension: 2w + 1, or the whole dimension when that covers it.
 FH_HD inline int win_width(int w, int L) { return 2 * w + 1 < L ? 2 * w + 1 : L; }
