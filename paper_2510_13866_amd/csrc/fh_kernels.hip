@@ -1665,19 +1665,29 @@ __global__ __launch_bounds__(kThreads) void k_grad(
 }
 
 // Per chain, in particle order: logZ = sum of ring log Z_p, grad_t = sum of d log Z_p / dt.
+// Per chain: log Z_path = sum of the ring log Z of its worldlines, d/dt = sum of theirs. One
+// wavefront per chain; lane k sums worldlines k, k + 64, ... in order, then a fixed butterfly adds
+// the lanes, so the result is the same on every call.
 __global__ void k_grad_reduce(const ChainInfo* __restrict__ chains, int n_chains,
                               const double* __restrict__ blk_logz, const double* __restrict__ dt,
                               double* logZ, double* grad_t) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
     if (c >= n_chains) return;
     const ChainInfo& ci = chains[c];
     double a = 0.0, b = 0.0;
-    for (int p = 0; p < ci.np; ++p) {
+    for (int p = lane; p < ci.np; p += 64) {
         a += blk_logz[ci.blk_off + (int64_t)p * ci.nb];
         b += dt[ci.part_off + p];
     }
-    if (logZ) logZ[c] = a;
-    if (grad_t) grad_t[c] = b;
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if (lane == 0) {
+        if (logZ) logZ[c] = a;
+        if (grad_t) grad_t[c] = b;
+    }
 }
 
 template <typename T>
@@ -2046,7 +2056,7 @@ hipError_t launch_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t
 
 hipError_t launch_grad_reduce(fh_plan p, double* logZ, double* grad_t, hipStream_t s) {
     if (!logZ && !grad_t) return hipSuccess;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((p->n_chains + 63) / 64)), dim3(64), 0, s,
+    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)p->n_chains), dim3(64), 0, s,
                        p->d.chains, p->n_chains, p->d.blk_logz, p->d.dt, logZ, grad_t);
     return hipGetLastError();
 }

@@ -804,8 +804,11 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
     const int32_t* __restrict__ paths, float* __restrict__ filt, float* __restrict__ gpart,
     double* __restrict__ blk_logz, double* __restrict__ dt_out, int anchor,
     const int32_t* __restrict__ perm, int32_t* status, const NegPairs neg) {
-    __shared__ float bt[kWaves][1024];   // beta tile of each wavefront, y * 32 + x
-    __shared__ float mg[kWaves][1024];   // marginal tile of each wavefront
+    // beta tile of each wavefront with a halo row on each side: row y at (y + 1) * 32, row -1
+    // repeats row L - 1 and row L repeats row 0, so the four-neighbour stencil reads at fixed
+    // offsets from three per-lane bases
+    __shared__ float bt[kWaves][34 * 32];
+    __shared__ float mg[2][kWaves][1024];  // marginal tiles, double-buffered over the slices
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const GroupTask g = groups[blockIdx.x];
     const ChainInfo& c = chains[g.chain];
@@ -859,6 +862,7 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
             const float wv0 = Wl[in ? y * L + x : 0];
             w[v] = in ? wv0 : 0.0f;
         }
+        __builtin_amdgcn_sched_barrier(0);  // W in flight during the matrix work
         const f32x16 X = circ_step(F, C, neg);
         const f32x16 H = circ_step(X, C, neg);
         float s = 0.0f;
@@ -907,62 +911,77 @@ __global__ __launch_bounds__(kThreads) void k_grad_mfma(
     for (int v = 0; v < 16; ++v) U[v] = (x == ex && tile_row(lane, v) == ey) ? 1.0f : 0.0f;
     double dt = 0.0;
     float* slab = gpart + g.part_off;
+    const int xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
+    float* btw = bt[wv] + 4 * (lane >> 5) * 32;  // row 4 (lane / 32) - 1 of the halo layout
     for (int j = L_tau - 1; j >= 0; --j) {
         const int l = (anchor + j) % L_tau;
+        // this slice's filter row and W: issued before the matrix work, waited for after it
+        const float* row = rows + (int64_t)j * N;
+        const float* Wl = Wsp + (int64_t)l * N;
+        float fj[16], wl[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int y = tile_row(lane, v);
+            const bool in = LFIX ? true : (xin && y < L);
+            fj[v] = row[in ? y * L + x : 0];
+            wl[v] = Wl[in ? y * L + x : 0];
+        }
+        __builtin_amdgcn_sched_barrier(0);
         const f32x16 X = circ_step(U, C, neg);
         const f32x16 B = circ_step(X, C, neg);   // beta_j = C u_{j+1} C
-        const float* row = rows + (int64_t)j * N;
-        float fj[16];
         float den = 0.0f;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int y = tile_row(lane, v);
             const bool in = LFIX ? true : (xin && y < L);
-            const float fv = row[in ? y * L + x : 0];
-            fj[v] = in ? fv : 0.0f;
+            fj[v] = in ? fj[v] : 0.0f;
             den += fj[v] * B[v];
-            bt[wv][y * 32 + x] = in ? B[v] : 0.0f;
+            const float bv = in ? B[v] : 0.0f;
+            const int r = 8 * (v >> 2) + (v & 3);  // y = 4 (lane / 32) + r
+            // rows past L - 1 are not written: row L's slot holds the halo copy of row 0
+            if (LFIX || y < L) btw[(r + 1) * 32 + x] = bv;
+            if (y == L - 1) bt[wv][x] = bv;                 // halo row -1
+            if (y == 0) bt[wv][(L + 1) * 32 + x] = bv;      // halo row L
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float num = 0.0f;
-        const int xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int y = tile_row(lane, v);
             const bool in = LFIX ? true : (xin && y < L);
-            const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
-            const float nbr = in ? bt[wv][y * 32 + xp] + bt[wv][y * 32 + xm] + bt[wv][yp * 32 + x] +
-                                       bt[wv][ym * 32 + x]
-                                 : 0.0f;
-            num += fj[v] * nbr;
+            const int r = 8 * (v >> 2) + (v & 3);
+            const float nbr = btw[(r + 1) * 32 + xp] + btw[(r + 1) * 32 + xm] +
+                              btw[(r + 2) * 32 + x] + btw[r * 32 + x];
+            num += in ? fj[v] * nbr : 0.0f;
         }
         const double dden = (double)wave_sum_f32(den);
         const double dnum = (double)wave_sum_f32(num);
         dt += dtau * dnum / dden;
         const float k = real ? (float)(coef / dden) : 0.0f;
+        float* mgb = mg[j & 1][wv];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) mg[wv][tile_row(lane, v) * 32 + x] = k * fj[v] * B[v];
-        __syncthreads();
+        for (int v = 0; v < 16; ++v) mgb[tile_row(lane, v) * 32 + x] = k * fj[v] * B[v];
+        __syncthreads();  // one barrier per slice: the tiles of slice j + 2 reuse these buffers
         {
+            const float* m0 = mg[j & 1][0];
+            const float* m1 = mg[j & 1][1];
+            const float* m2 = mg[j & 1][2];
+            const float* m3 = mg[j & 1][3];
             float* srow = slab + (int64_t)l * N;
             for (int i = threadIdx.x; i < 1024; i += kThreads) {
                 const int yy = i >> 5, xx = i & 31;
-                if (LFIX || (xx < L && yy < L))
-                    srow[yy * L + xx] = (mg[0][i] + mg[1][i]) + (mg[2][i] + mg[3][i]);
+                if (LFIX || (xx < L && yy < L)) srow[yy * L + xx] = (m0[i] + m1[i]) + (m2[i] + m3[i]);
             }
         }
-        __syncthreads();
         if (j > 0) {
-            const float* Wl = Wsp + (int64_t)l * N;
             float s = 0.0f;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int y = tile_row(lane, v);
                 const bool in = LFIX ? true : (xin && y < L);
-                const float wv0 = Wl[in ? y * L + x : 0];
-                U[v] = in ? wv0 * B[v] : 0.0f;
+                U[v] = in ? wl[v] * B[v] : 0.0f;
                 s += U[v];
             }
             const float tot = wave_sum_f32(s);
