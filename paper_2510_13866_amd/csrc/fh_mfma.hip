@@ -1005,8 +1005,10 @@ __global__ __launch_bounds__(kThreads) void k_grad_dmfma(
     int64_t total_slices, const int32_t* __restrict__ paths, double* __restrict__ filt,
     double* __restrict__ gpart, double* __restrict__ blk_logz, double* __restrict__ dt_out,
     int anchor, const int32_t* __restrict__ perm, int32_t* status) {
-    __shared__ double bt[kWaves][1024];  // beta tile of each wavefront, y * 32 + x
-    __shared__ double mg[kWaves][1024];  // marginal tile of each wavefront
+    // beta tile of each wavefront with halo rows (row y at (y + 1) * 32; row -1 repeats row L - 1,
+    // row L repeats row 0), and double-buffered marginal tiles, as in k_grad_mfma
+    __shared__ double bt[kWaves][34 * 32];
+    __shared__ double mg[2][kWaves][1024];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const GroupTask g = groups[blockIdx.x];
     const ChainInfo& c = chains[g.chain];
@@ -1052,6 +1054,7 @@ __global__ __launch_bounds__(kThreads) void k_grad_dmfma(
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) w[4 * q + r] = Wl[inside(q, r) ? yo(q, r) * L + xo(q) : 0];
+        __builtin_amdgcn_sched_barrier(0);  // W in flight during the matrix work
         const Tile64 H = circ64(circ64(F, Cb), Cb);
         double sum = 0.0;
 #pragma unroll
@@ -1101,63 +1104,83 @@ __global__ __launch_bounds__(kThreads) void k_grad_dmfma(
     double* slab = gpart + g.part_off;
     for (int j = L_tau - 1; j >= 0; --j) {
         const int l = (anchor + j) % L_tau;
-        const Tile64 B = circ64(circ64(U, Cb), Cb);  // beta_j = C u_{j+1} C
+        // this slice's filter row and W: issued before the matrix work, waited for after it
         const double* row = rows + (int64_t)j * N;
-        double fj[16];
+        const double* Wl = Wsp + (int64_t)l * N;
+        double fj[16], wl[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = inside(q, r) ? yo(q, r) * L + xo(q) : 0;
+                fj[4 * q + r] = row[o];
+                wl[4 * q + r] = Wl[o];
+            }
+        __builtin_amdgcn_sched_barrier(0);
+        const Tile64 B = circ64(circ64(U, Cb), Cb);  // beta_j = C u_{j+1} C
         double den = 0.0;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const bool in = inside(q, r);
-                const double fv = row[in ? yo(q, r) * L + xo(q) : 0];
-                fj[4 * q + r] = in ? fv : 0.0;
+                const int x = xo(q), y = yo(q, r);
+                fj[4 * q + r] = in ? fj[4 * q + r] : 0.0;
                 den += fj[4 * q + r] * B.t[q][r];
-                bt[wv][yo(q, r) * 32 + xo(q)] = in ? B.t[q][r] : 0.0;
+                const double bv = in ? B.t[q][r] : 0.0;
+                // rows past L - 1 are not written: row L's slot holds the halo copy of row 0
+                if (y < L) bt[wv][(y + 1) * 32 + x] = bv;
+                if (y == L - 1) bt[wv][x] = bv;                 // halo row -1
+                if (y == 0) bt[wv][(L + 1) * 32 + x] = bv;      // halo row L
             }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         double num = 0.0;
+        {
+            const double* btw = bt[wv] + yl * 32;  // row lane / 16 - 1 of the halo layout
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int x = xo(q), y = yo(q, r);
+            for (int q = 0; q < 4; ++q) {
+                const int x = xo(q);
                 const int xp = x + 1 == L ? 0 : x + 1, xm = x == 0 ? L - 1 : x - 1;
-                const int yp = y + 1 == L ? 0 : y + 1, ym = y == 0 ? L - 1 : y - 1;
-                const double nbr = inside(q, r) ? bt[wv][y * 32 + xp] + bt[wv][y * 32 + xm] +
-                                                      bt[wv][yp * 32 + x] + bt[wv][ym * 32 + x]
-                                                : 0.0;
-                num += fj[4 * q + r] * nbr;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = 16 * (q >> 1) + 4 * r;  // y = lane / 16 + rr
+                    const double nbr = btw[(rr + 1) * 32 + xp] + btw[(rr + 1) * 32 + xm] +
+                                       btw[(rr + 2) * 32 + x] + btw[rr * 32 + x];
+                    num += inside(q, r) ? fj[4 * q + r] * nbr : 0.0;
+                }
             }
+        }
         const double dden = wave_sum_f64(den);
         const double dnum = wave_sum_f64(num);
         dt += dtau * dnum / dden;
         const double k = real ? coef / dden : 0.0;
+        double* mgb = mg[j & 1][wv];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) mg[wv][yo(q, r) * 32 + xo(q)] = k * fj[4 * q + r] * B.t[q][r];
-        __syncthreads();
+            for (int r = 0; r < 4; ++r) mgb[yo(q, r) * 32 + xo(q)] = k * fj[4 * q + r] * B.t[q][r];
+        __syncthreads();  // one barrier per slice: the tiles of slice j + 2 reuse these buffers
         {
+            const double* m0 = mg[j & 1][0];
+            const double* m1 = mg[j & 1][1];
+            const double* m2 = mg[j & 1][2];
+            const double* m3 = mg[j & 1][3];
             double* srow = slab + (int64_t)l * N;
             for (int i = threadIdx.x; i < 1024; i += kThreads) {
                 const int yy = i >> 5, xx = i & 31;
-                if (xx < L && yy < L) srow[yy * L + xx] = (mg[0][i] + mg[1][i]) + (mg[2][i] + mg[3][i]);
+                if (xx < L && yy < L) srow[yy * L + xx] = (m0[i] + m1[i]) + (m2[i] + m3[i]);
             }
         }
-        __syncthreads();
         if (j > 0) {
-            const double* Wl = Wsp + (int64_t)l * N;
             double sum = 0.0;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const bool in = inside(q, r);
-                    const double wv0 = Wl[in ? yo(q, r) * L + xo(q) : 0];
-                    U.t[q][r] = in ? wv0 * B.t[q][r] : 0.0;
+                    U.t[q][r] = in ? wl[4 * q + r] * B.t[q][r] : 0.0;
                     sum += U.t[q][r];
                 }
             const double tot = wave_sum_f64(sum);
