@@ -797,7 +797,7 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
 // the group's partial slab; k_gpart_reduce adds the slabs of a chain in a fixed order, so the
 // field gradient is the same on every call.
 template <int LFIX>
-__global__ __launch_bounds__(kThreads) void k_grad_mfma(
+__global__ __launch_bounds__(kThreads, 3) void k_grad_mfma(
     const ChainInfo* __restrict__ chains, const GroupTask* __restrict__ groups,
     const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
