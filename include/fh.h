@@ -150,11 +150,13 @@ int fh_gibbs_aux(fh_plan plan, const int32_t* paths, void* aux, uint64_t sweep,
                  fh_stream stream);
 
 /* Local link updates (Sec. 3.5.1, eq. Rlocal, site basis): n_passes Metropolis passes; a pass
- * visits the interior slices l = 1 .. L_tau-2 of every worldline in turn, then slice 0 of every
+ * is a checkerboard in tau: it visits the odd interior slices l = 1, 3, ... <= L_tau-2 of every
+ * worldline, then the even interior slices 2, 4, ... <= L_tau-2, then slice 0 of every
  * worldline, then slice L_tau-1 of every worldline (the end slices neighbour the worldlines the
- * reconnection at tau = beta links to). Each visit proposes moving the worldline's site r on
- * slice l to a nearest neighbour r' (+x, -x, +y or -y, equally likely, periodic) with its sites
- * on slices l-1 and l+1 fixed (as updated so far), and takes it iff u < R,
+ * reconnection at tau = beta links to). The visits of one phase are independent of each other.
+ * Each visit proposes moving the worldline's site r on slice l to a nearest neighbour r' (+x,
+ * -x, +y or -y, equally likely, periodic) with its sites on slices l-1 and l+1 fixed (as left by
+ * the earlier phases), and takes it iff u < R,
  * R = W_l(r') G(r' - r_{l-1}) G(r_{l+1} - r') / [W_l(r) G(r - r_{l-1}) G(r_{l+1} - r)], in FP64.
  * Random numbers: Philox counter (particle, slice, sweep, 2 + 256*pass); the top two bits of
  * word 1 pick the direction, word 0 gives u. aux is read, paths updated in place. The filters of

@@ -11,12 +11,14 @@ so moving r_l to r' is accepted with probability min(1, R),
 Readings where the paper is silent:
   * proposal: r' = r_l + e with e one of the four lattice vectors (+x, -x, +y, -y), equally
     likely, periodic. The proposal is symmetric, so min(1, R) is the Metropolis acceptance;
-  * order: one pass first visits the interior slices l = 1, ..., L_tau-2 of every worldline in
-    turn (the updated slice l-1 is the neighbour of slice l), then slice 0 of every worldline,
-    then slice L_tau-1 of every worldline. The two end slices neighbour other worldlines when the
-    worldlines reconnect at tau = beta (permutation perm: slice L_tau of p is slice 0 of
-    perm[p]); visiting them in phases of their own keeps each phase's moves independent.
-    Without a permutation each worldline closes on itself;
+  * order: a checkerboard in tau. One pass visits, for every worldline, first the odd interior
+    slices l = 1, 3, ... <= L_tau-2, then the even interior slices l = 2, 4, ... <= L_tau-2, then
+    slice 0, then slice L_tau-1. A move on slice l sees only slices l-1 and l+1, which belong to
+    other phases, so the moves of one phase are independent of each other and the order inside
+    a phase does not matter. The two end slices neighbour other worldlines when the worldlines
+    reconnect at tau = beta (permutation perm: slice L_tau of p is slice 0 of perm[p]); they
+    have phases of their own for the same reason. Without a permutation each worldline closes
+    on itself;
   * random numbers: Philox counter (particle, slice, sweep, TAG_LOCAL + 256 * pass), key
     (seed, 0); the top two bits of word x1 select e (0: +x, 1: -x, 2: +y, 3: -y), word x0 gives
     the uniform u, and the move is taken iff u < R.
@@ -75,8 +77,9 @@ def local_update(desc, aux: np.ndarray, paths: np.ndarray, sweep: int, n_passes:
         out[l] = np.where(u < R, r_new, r)
 
     for ps in range(n_passes):
-        for l in range(1, L_tau - 1):
-            visit(l, ps, out[l - 1], out[l + 1])
+        for first in (1, 2):                       # odd, then even interior slices
+            for l in range(first, L_tau - 1, 2):
+                visit(l, ps, out[l - 1], out[l + 1])
         visit(0, ps, out[L_tau - 1, prv], out[1])
         visit(L_tau - 1, ps, out[L_tau - 2], out[0, nxt])
     if return_margin:

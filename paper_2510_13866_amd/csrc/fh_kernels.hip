@@ -1208,12 +1208,13 @@ __device__ inline int local_move(const ChainInfo& c, const double* g, const T* a
     return u < R ? cand : cur;
 }
 
-// One pass of local updates, in two launches (a pass visits the interior slices 1 .. L_tau-2 of
-// every worldline in turn, then slice 0 of every worldline, then slice L_tau-1 of every
-// worldline; the end slices neighbour the worldlines the reconnection at tau = beta links to).
-// PHASE 0: one thread per worldline runs its interior slices in order, then its slice 0, whose
-// previous slice is slice L_tau-1 of perm_inv[p] (not touched in this launch). PHASE 1: slice
-// L_tau-1 of every worldline, whose next slice is slice 0 of perm[p] (set by phase 0).
+// One pass of local updates: a checkerboard in tau, four launches. PHASE 0 moves the odd
+// interior slices 1, 3, ... <= L_tau-2 of every worldline, PHASE 1 the even interior slices
+// 2, 4, ... <= L_tau-2, PHASE 2 slice 0 (whose previous slice is slice L_tau-1 of perm_inv[p]),
+// PHASE 3 slice L_tau-1 (whose next slice is slice 0 of perm[p]). A move sees only the two
+// adjacent slices, which belong to other phases, so the moves of a launch are independent: one
+// thread per (worldline, slice). Interior phases take k0 plus the grid's y index as the slice
+// pair k (slice 2k + 1 or 2k + 2); threads past a chain's last slice of the phase leave.
 template <typename T, int PHASE>
 __global__ __launch_bounds__(kThreads) void k_local(const ChainInfo* __restrict__ chains,
                                                     int n_chains, int64_t particles,
@@ -1223,7 +1224,7 @@ __global__ __launch_bounds__(kThreads) void k_local(const ChainInfo* __restrict_
                                                     const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ perm_inv,
                                                     const uint64_t* __restrict__ sweep_ptr,
-                                                    int ps, int32_t* status) {
+                                                    int ps, int k0, int32_t* status) {
     const int64_t gp = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (gp >= particles) return;
     const int ci = find_chain(n_chains, gp, [&](int i) { return chains[i].part_off; });
@@ -1231,51 +1232,32 @@ __global__ __launch_bounds__(kThreads) void k_local(const ChainInfo* __restrict_
     const int p = (int)(gp - c.part_off);
     const int N = c.N, L_tau = c.L_tau;
     const int64_t np = c.np;
+    int l, qprev = p, qnext = p;  // slice, and the worldlines holding its neighbours
+    if (PHASE < 2) {
+        l = 2 * (k0 + (int)blockIdx.y) + 1 + PHASE;
+        if (l > L_tau - 2) return;
+    } else if (PHASE == 2) {
+        l = 0;
+        qprev = perm_inv[c.part_off + p];
+    } else {
+        l = L_tau - 1;
+        qnext = perm[c.part_off + p];
+    }
     const double* g = tables + tab_g(c);
     const double coef = p >= c.n_up ? c.coef_dn : c.coef_up;
     const T* ax = aux + c.aux_off;
     int32_t* col = paths + c.path_off;  // slice l of worldline q at col[l * np + q]
     const uint64_t sweep = *sweep_ptr;
-    auto in_range = [&](int r) { return r >= 0 && r < N; };
-    if (PHASE == 0) {
-        int prev = col[p];
-        int cur = col[np + p];
-        if (!in_range(prev) || !in_range(cur)) {
-            set_status(status, FH_ERR_BAD_PATH, ci);
-            return;
-        }
-        for (int l = 1; l < L_tau - 1; ++l) {
-            const int next = col[(int64_t)(l + 1) * np + p];
-            if (!in_range(next)) {
-                set_status(status, FH_ERR_BAD_PATH, ci);
-                return;
-            }
-            const int taken = local_move(c, g, ax, l, cur, prev, next, coef, p, sweep, ps);
-            if (taken != cur) col[(int64_t)l * np + p] = taken;
-            prev = taken;
-            cur = next;
-        }
-        const int prev0 = col[(int64_t)(L_tau - 1) * np + perm_inv[c.part_off + p]];
-        const int next0 = col[np + p];
-        const int cur0 = col[p];
-        if (!in_range(prev0)) {
-            set_status(status, FH_ERR_BAD_PATH, ci);
-            return;
-        }
-        const int taken = local_move(c, g, ax, 0, cur0, prev0, next0, coef, p, sweep, ps);
-        if (taken != cur0) col[p] = taken;
-    } else {
-        const int l = L_tau - 1;
-        const int prevL = col[(int64_t)(l - 1) * np + p];
-        const int nextL = col[perm[c.part_off + p]];
-        const int curL = col[(int64_t)l * np + p];
-        if (!in_range(prevL) || !in_range(nextL) || !in_range(curL)) {
-            set_status(status, FH_ERR_BAD_PATH, ci);
-            return;
-        }
-        const int taken = local_move(c, g, ax, l, curL, prevL, nextL, coef, p, sweep, ps);
-        if (taken != curL) col[(int64_t)l * np + p] = taken;
+    const int lp = l == 0 ? L_tau - 1 : l - 1, ln = l == L_tau - 1 ? 0 : l + 1;
+    const int prev = col[(int64_t)lp * np + qprev];
+    const int next = col[(int64_t)ln * np + qnext];
+    const int cur = col[(int64_t)l * np + p];
+    if (prev < 0 || prev >= N || next < 0 || next >= N || cur < 0 || cur >= N) {
+        set_status(status, FH_ERR_BAD_PATH, ci);
+        return;
     }
+    const int taken = local_move(c, g, ax, l, cur, prev, next, coef, p, sweep, ps);
+    if (taken != cur) col[(int64_t)l * np + p] = taken;
 }
 
 // Pair swaps of the reconnections at tau = beta (Sec. 3.5.6), one thread per worldline; the
@@ -1941,13 +1923,29 @@ hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
 template <typename T>
 hipError_t launch_local_t(fh_plan p, const T* aux, int32_t* paths, int n_passes, hipStream_t s) {
     const unsigned blocks = (unsigned)((p->particles + kThreads - 1) / kThreads);
+    int max_tau = 2;
+    for (const ChainInfo& c : p->chains) max_tau = std::max(max_tau, c.L_tau);
+    const int pairs = std::max(1, (max_tau - 1) / 2);  // slice pairs of the interior phases
+    constexpr int kMaxGridY = 65535;
     for (int ps = 0; ps < n_passes; ++ps) {
-        hipLaunchKernelGGL((k_local<T, 0>), dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+        for (int ph = 0; ph < 2; ++ph)
+            for (int k0 = 0; k0 < pairs; k0 += kMaxGridY) {
+                const dim3 grid(blocks, (unsigned)std::min(kMaxGridY, pairs - k0));
+                if (ph == 0)
+                    hipLaunchKernelGGL((k_local<T, 0>), grid, dim3(kThreads), 0, s, p->d.chains,
+                                       p->n_chains, p->particles, p->d.tables, aux, paths,
+                                       p->d.perm, p->d.perm_inv, p->d.sweep, ps, k0, p->d.status);
+                else
+                    hipLaunchKernelGGL((k_local<T, 1>), grid, dim3(kThreads), 0, s, p->d.chains,
+                                       p->n_chains, p->particles, p->d.tables, aux, paths,
+                                       p->d.perm, p->d.perm_inv, p->d.sweep, ps, k0, p->d.status);
+            }
+        hipLaunchKernelGGL((k_local<T, 2>), dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->n_chains, p->particles, p->d.tables, aux, paths, p->d.perm,
-                           p->d.perm_inv, p->d.sweep, ps, p->d.status);
-        hipLaunchKernelGGL((k_local<T, 1>), dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.perm_inv, p->d.sweep, ps, 0, p->d.status);
+        hipLaunchKernelGGL((k_local<T, 3>), dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->n_chains, p->particles, p->d.tables, aux, paths, p->d.perm,
-                           p->d.perm_inv, p->d.sweep, ps, p->d.status);
+                           p->d.perm_inv, p->d.sweep, ps, 0, p->d.status);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
