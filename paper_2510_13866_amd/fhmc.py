@@ -11,6 +11,12 @@ import ctypes
 import os
 from ctypes import POINTER, byref, c_double, c_int32, c_int64, c_uint32, c_uint64, c_void_p
 
+# PyTorch ships its own HIP and HSA runtimes under the same sonames as the system ROCm ones.
+# Loading torch first makes libfhmc.so bind to those already-loaded runtimes, so the process has
+# one HIP runtime and torch's device pointers and streams are valid in the library. Loaded the
+# other way round, the process would hold two runtimes and torch would find no GPU.
+import torch  # noqa: E402,F401  (load order only)
+
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfhmc.so")
 if not os.path.exists(_LIB_PATH):
     raise ImportError("libfhmc.so is not built (%s); run paper_2510_13866_amd.build.build() "
