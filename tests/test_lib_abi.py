@@ -35,6 +35,24 @@ def test_every_declared_symbol_is_exported(fhmc):
         assert hasattr(fhmc.lib, n), n
 
 
+def test_binding_leaves_one_hip_runtime_in_the_process():
+    """PyTorch ships HIP and HSA runtimes under the system ROCm sonames. Importing the binding
+    first (before torch) must still leave one runtime of each in the process, so that torch's
+    device pointers and streams are valid in the library (checked in a fresh interpreter)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2510_13866_amd import fhmc\n"
+            "import torch\n"
+            "libs = set(l.split()[-1] for l in open('/proc/self/maps') if '/' in l)\n"
+            "print(sum('libamdhip64' in l for l in libs), sum('libhsa-runtime64' in l for l in libs))\n"
+            % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    n_hip, n_hsa = (int(v) for v in out.stdout.split()[-2:])
+    assert n_hip == 1 and n_hsa == 1, out.stdout
+
+
 def test_library_resolves_every_symbol_at_load(fhmc):
     """Loading with immediate binding fails on any symbol the library uses but does not define
     (a shared library links without them)."""
