@@ -85,7 +85,10 @@ enum fh_flags {
                             chain whose hopping kernel decays fast enough draws from the window
                             of sites within w <= 3 steps of the next slice's site and certifies
                             that the draw equals the full-row one (else scans the row): the
-                            same draws, fewer bytes read                                      */
+                            same draws, fewer bytes read. While the window leaves more than
+                            3/20 of a backward pass's draws uncertified (clustered states), the
+                            plan draws the following passes with the full-row kernels and
+                            retries the window after 16 to 64 passes; the draws are the same */
 };
 
 /* One chain. block_len: FFBS block length B (0 = L_tau, one block closing the ring);
