@@ -47,6 +47,9 @@ def parse():
                     help="skip the backward timings on the state after one unrestored sweep")
     ap.add_argument("--full-row-draw", action="store_true",
                     help="backward draws scan whole filter rows (FH_FLAG_FULL_ROW_DRAW)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="FFT plans (--precision fp32 or fp64 with L > 32): time every radix-2/3/4 "
+                         "stage order per lattice size at plan creation (FH_FLAG_AUTOTUNE)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--workload", default="32x32",
@@ -248,11 +251,18 @@ def other_workload(args):
     stream = torch.cuda.Stream()
     sites = sum(d.N * d.L_tau for d in descs)
     log("bench: %s workload, %s, %d chains" % (args.workload, prec_name, len(descs)))
-    S = Sampler(descs, prec, fhmc.FH_FLAG_GRAPH)
+    flags = fhmc.FH_FLAG_GRAPH | (fhmc.FH_FLAG_AUTOTUNE if args.autotune else 0)
+    S = Sampler(descs, prec, flags)
     A0, P0 = S.pack_aux(aux), S.pack_paths(paths)
     A, P = A0.clone(), P0.clone()
     torch.cuda.synchronize()
     extra = {}
+    if args.autotune:  # the stage order chosen per lattice size
+        chosen = {}
+        for c, d in enumerate(descs):
+            if d.L not in chosen:
+                chosen[d.L] = list(fhmc.fh_get_radix_plan(S.plan, c))
+        extra["radix_plans"] = {str(L): v for L, v in sorted(chosen.items())}
     if args.workload == "grad":
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -373,7 +383,7 @@ def other_workload(args):
            "scaling": "weak", "vs_baseline": None,
            "dtype": "f64" if prec_name == "fp64" else "f32", "data": "synthetic",
            "config": {"workload": label, "chains": len(descs), "precision": prec_name,
-                      "site_slices_per_step": sites, "graph": True}}
+                      "site_slices_per_step": sites, "graph": True, "autotune": args.autotune}}
     out.update(extra)
     log("  %.3f ms/step, %.4g %s" % (ms / args.steps, value, unit))
     print(json.dumps(out), flush=True)
