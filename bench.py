@@ -54,7 +54,7 @@ def parse():
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--workload", default="32x32",
                     choices=["32x32", "uneven", "hirsch16", "grad", "small", "paper64", "paper32",
-                             "local", "measure", "mala", "perm"],
+                             "local", "measure", "mala", "perm", "64x64"],
                     help="32x32: the headline workload; the others time the remaining "
                          "configurations (uneven batch, 16x16 Ising field, adjoint, 4x4 FP64) "
                          "and the paper's own shape (32x32, L_tau=1024, blocks of 64 or 32)")
@@ -220,6 +220,10 @@ def other_workload(args):
         descs = synth.config_paper_shape(32, B, 4)
         label = "FFBS sweep, 4 chains x 32x32 lattice, L_tau=1024 (beta=32, dtau=1/32), " \
                 "FFBS blocks of %d slices, U=4, 512+512 worldlines, Gaussian field" % B
+    elif args.workload == "64x64":
+        descs = [synth.half_filled(64, 160, synth.HS_GAUSS, 4.0, 0.05, seed=s) for s in range(4)]
+        label = "FFBS sweep, 4 chains x 64x64 lattice, L_tau=160, dtau=0.05, U=4, 2048+2048 " \
+                "worldlines, Gaussian field"
     elif args.workload == "small":
         descs = synth.config_small_fp64()
         prec_name = "fp64"

@@ -68,7 +68,8 @@ enum fh_precision {
     FH_FP64 = 0,      /* plain path: FP64 FFT convolution, FP64 filters                       */
     FH_FP32 = 1,      /* FP32 FFT convolution and filters; FP64 normaliser and CDF            */
     FH_FP32_MFMA3 = 2 /* FP32 filters, convolution as the separable real circulant on MFMA
-                         with three-term split-bf16 products; FP64 normaliser and CDF; L<=32  */
+                         with three-term split-bf16 products; FP64 normaliser and CDF;
+                         L <= 32 or L = 64 (fh_logZ_grad and fh_mala_field: L <= 32)          */
 };
 
 enum fh_flags {
@@ -94,7 +95,7 @@ enum fh_flags {
 /* One chain. block_len: FFBS block length B (0 = L_tau, one block closing the ring);
  * blocks of a sweep s start at o_s + j*B (mod L_tau), o_s = (s*floor(B/2)) mod L_tau,
  * the last one shorter when B does not divide L_tau; endpoints stay fixed within a sweep.
- * Requirements: L in {2..64} with L = 2^a 3^b (L <= 32 for FH_FP32_MFMA3), L_tau >= 2,
+ * Requirements: L in {2..64} with L = 2^a 3^b (L <= 32 or L = 64 for FH_FP32_MFMA3), L_tau >= 2,
  * n_up, n_dn >= 0 with n_up + n_dn >= 1, block_len = 0 or 2 <= block_len <= L_tau,
  * t > 0, dtau > 0, U finite (U >= 0 for FH_HS_HIRSCH), all finite. */
 typedef struct {

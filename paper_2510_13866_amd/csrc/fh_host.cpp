@@ -122,6 +122,25 @@ void build_cmat(int L, const double* g, uint16_t* out, int bs = 32) {
             }
 }
 
+// The two distinct 32 x 32 blocks of the L = 64 circulant g((i - j) mod 64), in the operand
+// layout of build_cmat: blk 0 is C_00 = C_11, blk 1 is C_01 = C_10 (columns shifted by 32).
+void build_cmat_block64(const double* g, int blk, uint16_t* out) {
+    for (int q = 0; q < 2; ++q)
+        for (int lane = 0; lane < 64; ++lane)
+            for (int e = 0; e < 8; ++e) {
+                const int R = 16 * q + 8 * (e / 4) + 4 * (lane / 32) + e % 4;
+                const int n = lane % 32 + 32 * blk;
+                const double v = g[((R - n) % 64 + 64) % 64];
+                const uint16_t h = bf16_rne((float)v);
+                const double r1 = v - bf16_val(h);
+                const uint16_t m = bf16_rne((float)r1);
+                const double r2 = r1 - bf16_val(m);
+                const uint16_t l = bf16_rne((float)r2);
+                const uint16_t terms[3] = {h, m, l};
+                for (int t = 0; t < 3; ++t) out[((t * 2 + q) * 64 + lane) * 8 + e] = terms[t];
+            }
+}
+
 bool is_fin(double v) { return std::isfinite(v); }
 
 int validate(const fh_chain_desc& d, int precision) {
@@ -137,7 +156,7 @@ int validate(const fh_chain_desc& d, int precision) {
         return FH_ERR_INVALID_ARG;
     if (d.hs_kind == FH_HS_HIRSCH && d.U < 0) return FH_ERR_INVALID_ARG;
     if (!default_radix_plan(d.L, &rp)) return FH_ERR_UNSUPPORTED;
-    if (precision == FH_FP32_MFMA3 && d.L > 32) return FH_ERR_UNSUPPORTED;
+    if (precision == FH_FP32_MFMA3 && d.L > 32 && d.L != 64) return FH_ERR_UNSUPPORTED;
     return FH_OK;
 }
 
@@ -149,7 +168,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
+                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
                     d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -270,6 +289,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->tables.assign(tab, 0.0);
     p->cmat.assign((size_t)kCmatPerChain * n_chains, 0);
     p->cmatp.assign((size_t)kCmatPerChain * n_chains, 0);
+    p->cmatb.assign((size_t)2 * kCmatPerChain * n_chains, 0);
     p->cmat64.assign((size_t)kCmat64PerChain * n_chains, 0.0);
     std::vector<char> windowed((size_t)n_chains, 0);
     for (int c = 0; c < n_chains; ++c) {
@@ -279,6 +299,10 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         if (ci.L <= kPackMaxL)
             build_cmat(ci.L, p->tables.data() + tab_g(ci), p->cmatp.data() + (size_t)kCmatPerChain * c,
                        32 / pack_blocks(ci.L));
+        if (ci.L == 64)
+            for (int b = 0; b < 2; ++b)
+                build_cmat_block64(p->tables.data() + tab_g(ci),
+                                   b, p->cmatb.data() + (size_t)kCmatPerChain * (2 * c + b));
         build_cmat64(descs[c].L, p->tables.data() + tab_g(ci),
                      p->cmat64.data() + (size_t)kCmat64PerChain * c);
         windowed[c] = win_select(p->tables.data() + tab_g(ci), ci.L, &ci.win_w, &ci.win_gout) &&
@@ -340,6 +364,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     std::vector<PairTask> fwd32;
     std::vector<DrawTask> fwdx, draw32, draww, drawx;
     std::vector<PackTask> fwdp2, fwdp4;
+    std::vector<DrawTask> fwd64;
     // small lattices whose filter region (FP32) fits the packed kernel's 31-bit byte offsets
     auto packed = [&](int c) {
         const ChainInfo& ci = p->chains[c];
@@ -361,7 +386,9 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     // Backward: a windowed chain's tasks sit both in the windowed list and in a full-row list;
     // per sweep, bw_state decides which of the two kernels draws them (the other skips them).
     for (const DrawTask& t : draw) {
-        if (p->chains[t.chain].L != 32 && !packed(t.chain)) fwdx.push_back(t);
+        if (p->chains[t.chain].L == 64) fwd64.push_back(t);
+        else if (p->chains[t.chain].L != 32 && !packed(t.chain) && p->chains[t.chain].L <= 32)
+            fwdx.push_back(t);
         if (windowed[t.chain]) draww.push_back(t);
         else ++p->n_full_only_tasks;
         if (p->chains[t.chain].L == 32) {
@@ -374,6 +401,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->n_fwd32_tasks = (int32_t)fwd32.size();
     p->n_fwdx_tasks = (int32_t)fwdx.size();
     p->n_fwdp2_tasks = (int32_t)fwdp2.size();
+    p->n_fwd64_tasks = (int32_t)fwd64.size();
     p->n_fwdp4_tasks = (int32_t)fwdp4.size();
     std::vector<PackTask> fwdp(fwdp2);
     fwdp.insert(fwdp.end(), fwdp4.begin(), fwdp4.end());
@@ -406,6 +434,9 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.fwdx_tasks, sizeof(DrawTask) * fwdx.size());
     if (e == hipSuccess) e = dalloc(&dv.fwdp_tasks, sizeof(PackTask) * fwdp.size());
     if (e == hipSuccess) e = dalloc(&dv.cmatp, sizeof(uint16_t) * p->cmatp.size());
+    if (e == hipSuccess) e = dalloc(&dv.cmatb, sizeof(uint16_t) * p->cmatb.size());
+    if (e == hipSuccess) e = dalloc(&dv.fwd64_tasks, sizeof(DrawTask) * fwd64.size());
+    if (e == hipSuccess && !fwd64.empty()) e = hipMemcpy(dv.fwd64_tasks, fwd64.data(), sizeof(DrawTask) * fwd64.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = dalloc(&dv.draw32_tasks, sizeof(DrawTask) * draw32.size());
     if (e == hipSuccess) e = dalloc(&dv.draww_tasks, sizeof(DrawTask) * draww.size());
     if (e == hipSuccess) e = dalloc(&dv.drawx_tasks, sizeof(DrawTask) * drawx.size());
@@ -450,6 +481,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess && !fwdx.empty()) e = hipMemcpy(dv.fwdx_tasks, fwdx.data(), sizeof(DrawTask) * fwdx.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !fwdp.empty()) e = hipMemcpy(dv.fwdp_tasks, fwdp.data(), sizeof(PackTask) * fwdp.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.cmatp, p->cmatp.data(), sizeof(uint16_t) * p->cmatp.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dv.cmatb, p->cmatb.data(), sizeof(uint16_t) * p->cmatb.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !draw32.empty()) e = hipMemcpy(dv.draw32_tasks, draw32.data(), sizeof(DrawTask) * draw32.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !draww.empty()) e = hipMemcpy(dv.draww_tasks, draww.data(), sizeof(DrawTask) * draww.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !drawx.empty()) e = hipMemcpy(dv.drawx_tasks, drawx.data(), sizeof(DrawTask) * drawx.size(), hipMemcpyHostToDevice);
@@ -718,6 +750,7 @@ static hipError_t enqueue_logz_grad(fh_plan p, const void* aux, const int32_t* p
 int fh_logZ_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor_slice,
                  double* logZ, void* grad_aux, double* grad_t, fh_stream stream) {
     if (!p || !aux || !paths) return FH_ERR_INVALID_ARG;
+    if (p->precision == FH_FP32_MFMA3 && p->max_L > 32) return FH_ERR_UNSUPPORTED;
     for (const ChainInfo& c : p->chains)
         if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
     FH_TRY(enqueue_logz_grad(p, aux, paths, anchor_slice, logZ, grad_aux, grad_t,
@@ -730,6 +763,7 @@ int fh_logZ_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t ancho
 int fh_mala_field(fh_plan p, void* aux, const int32_t* paths, int32_t anchor_slice, double eps,
                   uint64_t sweep, int32_t* accepted, fh_stream stream) {
     if (!p || !aux || !paths || !(eps > 0.0) || !is_fin(eps)) return FH_ERR_INVALID_ARG;
+    if (p->precision == FH_FP32_MFMA3 && p->max_L > 32) return FH_ERR_UNSUPPORTED;
     for (const ChainInfo& c : p->chains)
         if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
@@ -767,6 +801,10 @@ int fh_set_hopping(fh_plan p, const double* t) {
         if (ci.L <= kPackMaxL)
             build_cmat(ci.L, p->tables.data() + tab_g(ci), p->cmatp.data() + (size_t)kCmatPerChain * c,
                        32 / pack_blocks(ci.L));
+        if (ci.L == 64)
+            for (int b = 0; b < 2; ++b)
+                build_cmat_block64(p->tables.data() + tab_g(ci),
+                                   b, p->cmatb.data() + (size_t)kCmatPerChain * (2 * c + b));
         build_cmat64(p->descs[c].L, p->tables.data() + tab_g(ci),
                      p->cmat64.data() + (size_t)kCmat64PerChain * c);
         // the window keeps its width; its outside bound follows the new kernel
@@ -782,6 +820,8 @@ int fh_set_hopping(fh_plan p, const double* t) {
     FH_TRY(hipMemcpy(p->d.cmat, p->cmat.data(), sizeof(uint16_t) * p->cmat.size(),
                      hipMemcpyHostToDevice));
     FH_TRY(hipMemcpy(p->d.cmatp, p->cmatp.data(), sizeof(uint16_t) * p->cmatp.size(),
+                     hipMemcpyHostToDevice));
+    FH_TRY(hipMemcpy(p->d.cmatb, p->cmatb.data(), sizeof(uint16_t) * p->cmatb.size(),
                      hipMemcpyHostToDevice));
     FH_TRY(hipMemcpy(p->d.cmat64, p->cmat64.data(), sizeof(double) * p->cmat64.size(),
                      hipMemcpyHostToDevice));

@@ -94,6 +94,7 @@ struct Device {
     double* tables = nullptr;
     uint16_t* cmat = nullptr;  // per chain: split-bf16 circulant operand [3][2][64][8]
     uint16_t* cmatp = nullptr; // per chain with L <= kPackMaxL: the block-diagonal operand, same layout
+    uint16_t* cmatb = nullptr; // per chain with L = 64: the blocks T0 = C_00 and T1 = C_01, same layout
     double* cmat64 = nullptr;  // per chain: FP64 circulant B operands [16][64]
     DrawTask* fwdd_tasks = nullptr;  // FP64 circulant forward: worldline blocks of L <= 32 chains
     void* W = nullptr;        // [2][sum L_tau*N] in plan precision (up, then down)
@@ -107,7 +108,8 @@ struct Device {
     GroupTask* group_tasks = nullptr;
     PairTask* fwd32_tasks = nullptr;    // MFMA forward: worldline pairs of L = 32 chains
     DrawTask* fwdx_tasks = nullptr;     // MFMA forward: single worldlines of 16 < L < 32 chains
-    PackTask* fwdp_tasks = nullptr;     // MFMA forward, packed: P = 2 tasks, then P = 4 tasks
+    PackTask* fwdp_tasks = nullptr;
+    DrawTask* fwd64_tasks = nullptr;    // MFMA forward: single worldlines of L = 64 chains     // MFMA forward, packed: P = 2 tasks, then P = 4 tasks
     DrawTask* draw32_tasks = nullptr;   // backward: worldline blocks of L = 32 chains
     DrawTask* draww_tasks = nullptr;    // backward, windowed draws (k_backward_win)
     DrawTask* drawx_tasks = nullptr;    // backward: the remaining chains (any L)
@@ -141,6 +143,7 @@ struct fh_plan_s {
     std::vector<double> tables;
     std::vector<uint16_t> cmat;
     std::vector<uint16_t> cmatp;
+    std::vector<uint16_t> cmatb;
     std::vector<double> cmat64;
     int64_t aux_elems = 0, path_elems = 0, particles = 0, blk_elems = 0, filt_elems = 0;
     int32_t n_fwd_tasks = 0, n_grad_tasks = 0, n_draw_tasks = 0;
@@ -148,6 +151,7 @@ struct fh_plan_s {
     int32_t n_groups = 0;
     int32_t n_fwd32_tasks = 0, n_fwdx_tasks = 0, n_draw32_tasks = 0;
     int32_t n_fwdp2_tasks = 0, n_fwdp4_tasks = 0;
+    int32_t n_fwd64_tasks = 0;
     int32_t max_N_x = 0;  // largest N among the chains of drawx_tasks
     int32_t n_draww_tasks = 0, n_drawx_tasks = 0;
     int32_t n_fwdd_tasks = 0;  // FP64 circulant forward tasks (the FFT takes n_fwd_tasks pairs)

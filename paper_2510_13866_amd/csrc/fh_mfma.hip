@@ -556,6 +556,178 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     }
 }
 
+// L = 64 on the same matrix cores: the 64 x 64 filter in four 32 x 32 sub-tiles X_RS (rows
+// 32 R .., columns 32 S ..), each in the accumulator layout. X^T C is assembled from the
+// sub-tile products of circ_step: (X^T C)_IJ = sum_K X_KI^T C_KJ, K in order, each term the six
+// split products of the two K chunks. For L = 64 the circulant g((i - j) mod 64) has two
+// distinct 32 x 32 blocks: C_00 = C_11 (T0) and C_01 = C_10 (T1, since -32 = 32 mod 64), so the
+// operand holds two split blocks. Same arithmetic per product as the 32 x 32 tile: every
+// product positive, FP32 accumulation, filters within the same bound.
+__device__ inline void circ64_step(const f32x16 (&X)[2][2], f32x16 (&Y)[2][2],
+                                   const Split3 (&T)[2], const NegPairs& n) {
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J) Y[I][J] = f32x16{};
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int K = 0; K < 2; ++K)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                bf16x8 h, m, l;
+                split3_chunk(X[K][I], q, h, m, l, n);
+#pragma unroll
+                for (int J = 0; J < 2; ++J) {
+                    const Split3& C = T[K == J ? 0 : 1];
+                    f32x16 acc = Y[I][J];
+                    acc = mfma(l, C.h[q], acc);
+                    acc = mfma(m, C.m[q], acc);
+                    acc = mfma(m, C.h[q], acc);
+                    acc = mfma(h, C.l[q], acc);
+                    acc = mfma(h, C.m[q], acc);
+                    acc = mfma(h, C.h[q], acc);
+                    Y[I][J] = acc;
+                }
+            }
+}
+
+// The forward recursion of k_forward_mfma for L = 64 chains, one wavefront per (chain,
+// worldline, block); rows stored as 4096 FP32 values, log Z as in k_forward_mfma.
+__global__ __launch_bounds__(kThreads) void k_forward_mfma64(
+    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
+    const uint16_t* __restrict__ cmatb, const float* __restrict__ aux, const float* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
+    double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
+    const NegPairs neg) {
+    constexpr int L = 64, N = 4096;
+    const int lane = threadIdx.x & 63;
+    const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
+    if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
+    const DrawTask t = tasks[task];
+    const ChainInfo& c = chains[t.chain];
+    int start, len;
+    block_of(c, *sweep_ptr, t.block, &start, &len);
+    const int L_tau = c.L_tau;
+    const int spin = t.p >= c.n_up ? 1 : 0;
+    const float* Wsp = W + spin * aux_elems + c.aux_off;
+    const double* shift = wshift + spin * total_slices + c.slice_off;
+    const double coef = spin ? c.coef_dn : c.coef_up;
+    const int32_t* pc = paths + c.path_off;
+    int a = pc[(int64_t)start * c.np + t.p];
+    const int qe = start + len >= L_tau ? perm[c.part_off + t.p] : t.p;  // reconnection
+    int e = pc[(int64_t)((start + len) % L_tau) * c.np + qe];
+    if (a < 0 || a >= N || e < 0 || e >= N) {
+        if (lane == 0) set_status(status, FH_ERR_BAD_PATH, t.chain);
+        a = (a < 0 || a >= N) ? 0 : a;
+        e = (e < 0 || e >= N) ? 0 : e;
+    }
+    Split3 T[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const uint4* cm = (const uint4*)(cmatb + ((size_t)t.chain * 2 + b) * 3 * 2 * 64 * 8);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            T[b].h[q] = __builtin_bit_cast(bf16x8, cm[(0 * 2 + q) * 64 + lane]);
+            T[b].m[q] = __builtin_bit_cast(bf16x8, cm[(1 * 2 + q) * 64 + lane]);
+            T[b].l[q] = __builtin_bit_cast(bf16x8, cm[(2 * 2 + q) * 64 + lane]);
+        }
+    }
+    const int x = lane & 31;
+    // element (32 R + tile_row(lane, v), 32 S + x) of sub-tile (R, S) sits at
+    // lane_off + 32 (R L + S) + vrow(v) L of a row
+    const int lane_off = 4 * (lane >> 5) * L + x;
+    auto vrow = [](int v) { return 8 * (v >> 2) + (v & 3); };
+    auto load_w = [&](int l, float (&dst)[2][2][16]) {
+        const float* Wl = Wsp + (int64_t)l * N + lane_off;
+#pragma unroll
+        for (int R = 0; R < 2; ++R)
+#pragma unroll
+            for (int S = 0; S < 2; ++S)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) dst[R][S][v] = Wl[32 * (R * L + S) + vrow(v) * L];
+    };
+    f32x16 F[2][2];
+    {
+        const int ax = a % L, ay = a / L;
+#pragma unroll
+        for (int R = 0; R < 2; ++R)
+#pragma unroll
+            for (int S = 0; S < 2; ++S)
+#pragma unroll
+                for (int v = 0; v < 16; ++v)
+                    F[R][S][v] = (32 * S + x == ax && 32 * R + tile_row(lane, v) == ay) ? 1.0f : 0.0f;
+    }
+    double la = coef * (double)aux[c.aux_off + (int64_t)start * N + a];
+    double prod = 1.0;
+    float* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+    // W of the next slice is loaded before this slice's stores (loads and stores retire in
+    // order), so its wait one step later does not wait for them
+    float wn[2][2][16];
+    load_w((start + 1) % L_tau, wn);
+    for (int j = 1; j < len; ++j) {
+        const int l = (start + j) % L_tau;
+        f32x16 X[2][2], H[2][2];
+        circ64_step(F, X, T, neg);
+        circ64_step(X, H, T, neg);
+        float s = 0.0f;
+#pragma unroll
+        for (int R = 0; R < 2; ++R)
+#pragma unroll
+            for (int S = 0; S < 2; ++S)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    F[R][S][v] = H[R][S][v] * wn[R][S][v];
+                    s += F[R][S][v];
+                }
+        load_w((l + 1) % L_tau, wn);  // the last step fetches a slice it does not use
+        __builtin_amdgcn_sched_barrier(0);
+        const float tot = wave_sum_f32(s);
+        if (!(tot > 0.0f) || !isfinite(tot))
+            if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
+        // f~_j = h_j * inv: the normaliser applied is exactly 1/inv (see k_forward_mfma)
+        const float inv = __builtin_amdgcn_rcpf(tot);
+        prod *= (double)inv;
+        if (!(prod > 1e-200 && prod < 1e200)) {
+            la -= log(prod);
+            prod = 1.0;
+        }
+        la += shift[l];
+        float* row = rows + (int64_t)(j - 1) * N + lane_off;
+#pragma unroll
+        for (int R = 0; R < 2; ++R)
+#pragma unroll
+            for (int S = 0; S < 2; ++S)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    F[R][S][v] *= inv;
+                    __builtin_nontemporal_store(F[R][S][v], row + 32 * (R * L + S) + vrow(v) * L);
+                }
+    }
+    // end weight (C f~ C)(e)
+    f32x16 X[2][2], H[2][2];
+    circ64_step(F, X, T, neg);
+    circ64_step(X, H, T, neg);
+    const int ex = e % L, ey = e / L;
+    const int Re = ey >> 5, Se = ex >> 5, ty = ey & 31, tx = ex & 31;
+    const int ve = (ty >> 3) * 4 + (ty & 3);
+    float hv = 0.0f;
+#pragma unroll
+    for (int R = 0; R < 2; ++R)
+#pragma unroll
+        for (int S = 0; S < 2; ++S)
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                if (R == Re && S == Se && v == ve) hv = H[R][S][v];
+    hv = __shfl(hv, tx + 32 * ((ty >> 2) & 1), 64);
+    la -= log(prod);
+    if (lane == 0) {
+        if (!(hv > 0.0f)) set_status(status, FH_ERR_NONFINITE, t.chain);  // end weight underflowed
+        blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log((double)hv);
+    }
+}
+
 // Raw buffer resources: word 3 of the descriptor on gfx9-family chips (32-bit data format,
 // no swizzle), and the cache-policy bit of a streaming (nontemporal) store.
 constexpr int kBufferWord3 = 0x00020000;
@@ -1262,6 +1434,16 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
         const unsigned blocks = (unsigned)((p->n_fwdx_tasks + kWaves - 1) / kWaves);
         hipLaunchKernelGGL(k_forward_mfma<0>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwdx_tasks, p->n_fwdx_tasks, p->d.cmat, (const float*)aux,
+                           (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
+                           paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
+                           kNegPairs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (p->n_fwd64_tasks > 0) {  // L = 64: four sub-tiles per worldline
+        const unsigned blocks = (unsigned)((p->n_fwd64_tasks + kWaves - 1) / kWaves);
+        hipLaunchKernelGGL(k_forward_mfma64, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.fwd64_tasks, p->n_fwd64_tasks, p->d.cmatb, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
                            kNegPairs);

@@ -1387,6 +1387,51 @@ def test_largest_lattice_parity(lib, prec):
     Sf.close()
 
 
+def test_mfma_circulant_at_l64_parity(lib):
+    """L = 64 on the FP32 matrix-core path (four 32 x 32 sub-tiles, two circulant blocks) next to
+    32 x 32 and small chains: filters and log Z against the oracle, windowed draws equal to the
+    full-row kernel's, and the adjoint refused (it covers L <= 32 only)."""
+    fhmc, sampler = lib
+    descs = [synth.ChainDesc(L=64, L_tau=6, n_up=3, n_dn=2, hs_kind=synth.HS_GAUSS, block_len=0,
+                             t=1.0, U=4.0, dtau=0.05, seed=401),
+             synth.ChainDesc(L=64, L_tau=7, n_up=2, n_dn=2, hs_kind=synth.HS_HIRSCH, block_len=4,
+                             t=1.0, U=4.0, dtau=0.0625, seed=402),
+             synth.ChainDesc(L=32, L_tau=5, n_up=3, n_dn=1, hs_kind=synth.HS_GAUSS, block_len=0,
+                             t=1.0, U=4.0, dtau=0.05, seed=403),
+             synth.ChainDesc(L=8, L_tau=4, n_up=5, n_dn=4, hs_kind=synth.HS_GAUSS, block_len=0,
+                             t=1.0, U=4.0, dtau=0.05, seed=404)]
+    say("mfma circulant at L = 64")
+    aux, paths = mixed_state(descs, seed=411)
+    Sw = sampler.Sampler(descs, PRECS["mfma3"])
+    Sf = sampler.Sampler(descs, PRECS["mfma3"], fhmc.FH_FLAG_FULL_ROW_DRAW)
+    counts = (ctypes.c_int32 * 4)()
+    assert fhmc.lib.fh_debug_forward_kernels(Sw.plan, counts) == 0
+    assert counts[1] == 0          # no L = 64 task on the padded 32 x 32 kernel
+    Aw, Pw = Sw.pack_aux(aux), Sw.pack_paths(paths)
+    Af, Pf = Sf.pack_aux(aux), Sf.pack_paths(paths)
+    for s in (0, 1):
+        logZ = Sw.unpack_particles(Sw.forward_filter(Aw, Pw, s))
+        assert Sw.status() == (0, -1)
+        for c, d in enumerate(descs):
+            ref_lz, ref_rows = oracle_forward(d, aux[c], paths[c], s)
+            err = np.abs(logZ[c] - ref_lz)
+            assert np.all(err <= logz_tol("mfma3", ref_lz, 0.0, d.L_tau)), (c, s, err)
+            for p in range(d.n_particles):
+                assert rel_row_err(Sw.filters(c, p), ref_rows[p]) <= FILTER_TOL["mfma3"], (c, p, s)
+    s = 1
+    Sw.backward_sample(Pw, s)
+    Sf.forward_filter(Af, Pf, s)
+    Sf.backward_sample(Pf, s)
+    assert Sw.status() == (0, -1) and Sf.status() == (0, -1)
+    gw, gf = Sw.unpack_paths(Pw), Sf.unpack_paths(Pf)
+    for c in range(len(descs)):
+        assert np.array_equal(gw[c], gf[c]), c
+    with pytest.raises(fhmc.FhError):
+        Sw.logz_grad(Aw, Pw, 0)
+    Sw.close()
+    Sf.close()
+
+
 def test_fp64_circulant_resolves_deep_filter_tails(lib):
     """Block ends placed anywhere on the lattice sit deep in the filter's tail, where an FFT
     convolution (accurate to ~eps * max per site) cannot resolve them. The FP64 circulant keeps
