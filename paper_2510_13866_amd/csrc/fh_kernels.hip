@@ -446,8 +446,9 @@ __global__ __launch_bounds__(kThreads) void k_backward(
 template <int CTRL>
 __device__ inline double dpp_f64(double v) {  // value of the DPP source lane, 0 where none
     const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    // bound_ctrl: a lane without a source lane reads 0, so no zeroed destination is needed
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
     return __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
 }
 __device__ inline double readlane_f64(double v, int lane) {
@@ -921,7 +922,8 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     int32_t* __restrict__ bw_state, int count_uncertified) {
     constexpr int G = kThreads / kWinLanes;
     constexpr int K = kWinPerLane;
-    __shared__ double gsh[G][kWinMaxL];
+    // g(d) for d in (-L, L): gsh[grp][kWinMaxL + d], so a signed offset indexes it directly
+    __shared__ double gsh[G][2 * kWinMaxL];
     const int grp = threadIdx.x / kWinLanes, li = threadIdx.x % kWinLanes;
     const int lane64 = threadIdx.x & 63;
     const int gbase = lane64 - li;  // the group's first lane in the wavefront
@@ -930,9 +932,14 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     const bool active = task < n_tasks && bw_state[0] == 0;
     const DrawTask t = active ? tasks[task] : DrawTask{0, 0, 0, 0};
     const ChainInfo& c = chains[t.chain];
-    const int L = c.L, N = c.N, L_tau = c.L_tau, w = c.win_w;
-    double* g = gsh[grp];
-    for (int d = li; d < L; d += kWinLanes) g[d] = tables[tab_g(c) + d];
+    // an inactive group runs on a one-site lattice (chain 0 may be wider than the LDS table)
+    const int L = active ? c.L : 1, N = active ? c.N : 1, L_tau = c.L_tau, w = c.win_w;
+    double* g = gsh[grp] + kWinMaxL;  // g[d] = g(d mod L) for -L < d < L
+    for (int d = li; d < L; d += kWinLanes) {
+        const double gd = tables[tab_g(c) + d];
+        g[d] = gd;
+        g[d - L] = gd;
+    }
     __syncthreads();  // the only barrier; every wave reaches it
     const uint64_t sweep = *sweep_ptr;
     int start = 0, len = 1;
@@ -1007,9 +1014,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            int dx = cx - xs[k], dy = cy - ys[k];
-            dx += dx < 0 ? L : 0;
-            dy += dy < 0 ? L : 0;
+            const int dx = cx - xs[k], dy = cy - ys[k];  // in (-L, L)
             const double fk = (real && qv[k]) ? (double)fv[k] : 0.0;
             acc += (fk > 0.0 ? fk : 0.0) * (g[dy] * g[dx]);
             P[k] = acc;
@@ -1066,7 +1071,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
                 ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(rp >> 32), g0) << 32));
             const int p2 = wave_window2_draw(
                 rowg, __builtin_amdgcn_readlane(L, g0), __builtin_amdgcn_readlane(cx, g0),
-                __builtin_amdgcn_readlane(cy, g0), gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)],
+                __builtin_amdgcn_readlane(cy, g0), gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)] + kWinMaxL,
                 readlane_f64(u, g0), readlane_f64(c.win_gout2, g0), lane64);
             if ((lane64 >> 4) == (g0 >> 4)) {
                 if (p2 >> 16) {
@@ -1090,7 +1095,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
             const int Lg = __builtin_amdgcn_readlane(L, g0);
             const int chosen = wave_row_draw(
                 rowg, __builtin_amdgcn_readlane(N, g0), Lg, __builtin_amdgcn_readlane(cx, g0),
-                __builtin_amdgcn_readlane(cy, g0), gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)],
+                __builtin_amdgcn_readlane(cy, g0), gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)] + kWinMaxL,
                 readlane_f64(u, g0), __builtin_amdgcn_readlane(cur, g0), lane64, &bad);
             if ((lane64 >> 4) == (g0 >> 4)) {
                 nx = chosen % Lg;
