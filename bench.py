@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_mfma3": 2}
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFS = 2500.0   # dense bf16 matrix-core peak
 KERNEL_SOURCES = {"forward": {"fp32_mfma3": "fh_mfma.hip", "fp32": "fh_kernels.hip",
                               "fp64": "fh_mfma.hip"},
                   "backward": {"fp32_mfma3": "fh_kernels.hip", "fp32": "fh_kernels.hip",
@@ -466,6 +467,15 @@ def main():
                     "kernel": names[k], "ms_per_launch": round(times[k], 4),
                     "algorithmic_bytes_per_launch": algo[k]}
         log("  %s %.3f ms/launch, %.0f GB/s algorithmic" % (names[k], times[k], gbs))
+    if args.precision == "fp32_mfma3":
+        # the same forward launch against the matrix cores: 24 bf16 MFMA 32x32x16 per
+        # worldline-step (two circulant products, three-term splits, six products each); a
+        # block of L_tau slices takes L_tau - 1 steps and one more product for its end weight
+        flops = sum(d.n_particles * d.L_tau for d in descs) * 24 * 32 * 32 * 16 * 2
+        tf = flops / (times["forward"] / 1e3) / 1e12
+        roofs["forward"]["matrix_cores"] = {
+            "achieved": round(tf, 1), "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": round(tf / BF16_PEAK_TFS, 4), "flops_per_launch": flops, "dtype": "bf16"}
     dominant = "forward" if fwd_ms >= bwd_ms else "backward"
     roof = roofs[dominant]
 
