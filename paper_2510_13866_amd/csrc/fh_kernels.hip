@@ -932,7 +932,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     const bool active = task < n_tasks && bw_state[0] == 0;
     const DrawTask t = active ? tasks[task] : DrawTask{0, 0, 0, 0};
     const ChainInfo& c = chains[t.chain];
-    // an inactive group runs on a one-site lattice (chain 0 may be wider than the LDS table)
+    // an inactive group draws nothing; on a one-site lattice its table fill and loads stay minimal
     const int L = active ? c.L : 1, N = active ? c.N : 1, L_tau = c.L_tau, w = c.win_w;
     double* g = gsh[grp] + kWinMaxL;  // g[d] = g(d mod L) for -L < d < L
     for (int d = li; d < L; d += kWinLanes) {
