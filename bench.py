@@ -397,8 +397,9 @@ def other_workload(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(chains are independent; see the sharding notes). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (chains are "
+              "independent, so each GPU would run its own share of them). Use --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
     if args.workload != "32x32":
         other_workload(args)
