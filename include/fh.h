@@ -53,7 +53,7 @@ typedef void* fh_stream; /* hipStream_t */
 enum fh_status {
     FH_OK = 0,
     FH_ERR_INVALID_ARG = -1, /* bad descriptor, null pointer, size or index           */
-    FH_ERR_UNSUPPORTED = -2, /* valid request this build does not implement (e.g. L)   */
+    FH_ERR_UNSUPPORTED = -2, /* valid request the library does not implement (e.g. L) */
     FH_ERR_OOM = -3,         /* device allocation failed                               */
     FH_ERR_HIP = -4,         /* a HIP runtime call failed                              */
     FH_ERR_NONFINITE = -5,   /* device: a normaliser or weight total was NaN or Inf    */
