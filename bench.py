@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_mfma3": 2}
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFS = 2500.0   # dense bf16 matrix-core peak
+FP64_PEAK_TFS = 78.6     # FP64 matrix-core peak
+FP32_VECTOR_PEAK_TFS = 157.3
 KERNEL_SOURCES = {"forward": {"fp32_mfma3": "fh_mfma.hip", "fp32": "fh_kernels.hip",
                               "fp64": "fh_mfma.hip"},
                   "backward": {"fp32_mfma3": "fh_kernels.hip", "fp32": "fh_kernels.hip",
@@ -477,6 +479,23 @@ def main():
         roofs["forward"]["matrix_cores"] = {
             "achieved": round(tf, 1), "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
             "frac": round(tf / BF16_PEAK_TFS, 4), "flops_per_launch": flops, "dtype": "bf16"}
+    elif args.precision == "fp64":
+        # FP64 circulant: 64 v_mfma_f64_16x16x4_f64 per worldline-step
+        flops = sum(d.n_particles * d.L_tau for d in descs) * 64 * 16 * 16 * 4 * 2
+        tf = flops / (times["forward"] / 1e3) / 1e12
+        roofs["forward"]["matrix_cores"] = {
+            "achieved": round(tf, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": round(tf / FP64_PEAK_TFS, 4), "flops_per_launch": flops, "dtype": "f64"}
+    else:
+        # FFT convolution in FP32 on the vector ALUs: two worldlines share one complex signal,
+        # so each worldline-step costs half of a forward and an inverse complex 2D FFT
+        # (5 N log2 N flops each) plus ~6N for the spectral product, W and the normaliser
+        import math
+        flops = int(sum(d.n_particles * d.L_tau for d in descs) * (5 * N * math.log2(N) + 6 * N))
+        tf = flops / (times["forward"] / 1e3) / 1e12
+        roofs["forward"]["alu"] = {
+            "achieved": round(tf, 2), "peak": FP32_VECTOR_PEAK_TFS, "unit": "TFLOP/s",
+            "frac": round(tf / FP32_VECTOR_PEAK_TFS, 4), "flops_per_launch": flops, "dtype": "f32"}
     dominant = "forward" if fwd_ms >= bwd_ms else "backward"
     roof = roofs[dominant]
 
