@@ -71,6 +71,16 @@ enum fh_precision {
                          with three-term split-bf16 products; FP64 normaliser and CDF;
                          L <= 32 or L = 64 (fh_logZ_grad and fh_mala_field: L <= 32)          */
 };
+/* Range of the FP32 plans. A filter row is normalised to sum 1; FP32 holds its values to full
+ * relative precision only down to ~2^-110 (bf16 splitting) or ~2^-126. Strong, clustered fields
+ * push the part of a row that a block's draws need below that (block end weights of 2^-160 and
+ * less occur on the way to clustered states). Both FP32 plans therefore queue every block whose
+ * forward step total, end weight or backward draw total falls below 2^-100 of its row's mass,
+ * and redo it in FP64: the forward recursion on the FP64 circulant with W computed in FP64 from
+ * the field (its log Z replaces the FP32 one, its rows rounded to FP32 replace the stored rows),
+ * and, in fh_backward_sample and fh_sweep, the block's draws from the FP64 rows with the same
+ * rule and uniforms as an FH_FP64 plan. Only chains with L <= 32 have this FP64 re-filter; a
+ * queued block of a larger lattice latches FH_ERR_NONFINITE and keeps its sites. */
 
 enum fh_flags {
     FH_FLAG_NONE = 0,
@@ -144,7 +154,9 @@ int fh_forward_filter(fh_plan plan, const void* aux, const int32_t* paths, uint6
  * of every block interior, from the filters of the last fh_forward_filter, which must have been
  * called with the same `sweep` and the same `paths` contents (FH_ERR_STATE otherwise).
  * Inverse CDF in site order with an FP64 running sum; the draw is the smallest site whose
- * running sum exceeds u * total. `paths` is updated in place (block endpoints are kept). */
+ * running sum exceeds u * total. `paths` is updated in place (block endpoints are kept).
+ * FP32 plans re-filter out-of-range blocks (see the range note above) from the `aux` passed to
+ * that fh_forward_filter, which must therefore still hold the same field. */
 int fh_backward_sample(fh_plan plan, int32_t* paths, uint64_t sweep, fh_stream stream);
 
 /* Exact Gibbs draw of the whole field given the worldlines (Sec. 3.5.4: Ising,

@@ -77,6 +77,17 @@ int fh_debug_inflate_window_bound(fh_plan plan, double factor);
 int fh_debug_backward_kernels(fh_plan plan, int32_t* n_windowed, int32_t* n_full_row);
 int fh_debug_backward_adapt(fh_plan plan, int32_t enable, int32_t* full_row_passes_left);
 
+/* FP32 plans queue the blocks whose filters leave FP32's range (see the range note of fh.h),
+ * and every block of a chain that had such a block in this or one of the two preceding forward
+ * passes, for an FP64 re-filter and redraw. fh_debug_rescue synchronises the device and reports
+ * the queue of the last forward pass (with what its backward pass added): last_count
+ * (nullable) receives its length, whole_chains (nullable) the chains queued whole, total
+ * (nullable) the blocks redrawn by every backward pass since the previous call (then reset to
+ * 0), and list (caller-owned host memory, cap triples, may be null when cap = 0) the first
+ * min(cap, last_count) queued blocks as (chain, particle, block). FP64 plans report 0. */
+int fh_debug_rescue(fh_plan plan, int32_t* last_count, int32_t* whole_chains, int64_t* total,
+                    int32_t* list, int32_t cap);
+
 /* Forward work items of an FH_FP32_MFMA3 plan, by kernel: counts[0] worldline pairs of L = 32
  * chains, counts[1] single padded worldlines (16 < L < 32), counts[2] packed tasks of 2 x 2
  * worldlines per tile (8 < L <= 16), counts[3] packed tasks of 4 x 4 (L <= 8). counts holds 4

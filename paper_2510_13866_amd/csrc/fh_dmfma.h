@@ -1,0 +1,119 @@
+// FP64 circulant on the FP64 matrix cores, shared by the FP64 forward filter, the FP64 adjoint
+// and the FP64 re-filter of blocks that leave FP32's range (fh_kernels.hip, fh_mfma.hip).
+//
+// v_mfma_f64_16x16x4_f64 reads A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k, and
+// leaves D[i][j] in lane j + 16 (i mod 4), register i / 4 (checked on the device). A 32 x 32
+// matrix in that accumulator layout is four 16 x 16 tiles (I, J), tile index 2 I + J; element
+// (16 I + 4 r + lane / 16, 16 J + lane % 16) sits in register r of tile (I, J). Register r of
+// tile (K, I) is then directly the A operand of X^T with K-index 16 K + 4 r + lane / 16, so
+//   (X^T C)(I, J) = sum over K, r of mfma(X(K, I)[r], Cb[(4 K + r) * 2 + J])
+// with Cb the matching B operands of the circulant C[k][j] = g((k - j) mod L) (zero outside
+// L x L): 32 products per multiplication, no operand splitting, every product and sum in FP64.
+// Two multiplications give (F^T C)^T C = C F C, C being symmetric.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace fh {
+
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
+struct Tile64 {
+    f64x4 t[4];
+};
+
+__device__ inline Tile64 circ64(const Tile64& X, const double (&Cb)[16]) {
+    Tile64 Y;
+#pragma unroll
+    for (int I = 0; I < 2; ++I)
+#pragma unroll
+        for (int J = 0; J < 2; ++J) {
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int K = 0; K < 2; ++K)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X.t[2 * K + I][r],
+                                                               Cb[(4 * K + r) * 2 + J], acc, 0, 0, 0);
+            Y.t[2 * I + J] = acc;
+        }
+    return Y;
+}
+
+__device__ inline double wave_sum_f64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Tile coordinates of element (tile q, register r) of a lane: x = 16 (q & 1) + lane % 16,
+// y = 16 (q >> 1) + 4 r + lane / 16.
+__device__ inline int t64_x(int q, int lane) { return 16 * (q & 1) + (lane & 15); }
+__device__ inline int t64_y(int q, int r, int lane) { return 16 * (q >> 1) + 4 * r + (lane >> 4); }
+
+// The forward recursion of one block on the FP64 circulant, one wavefront (Sec. 3.5.2, site
+// basis, with the per-step sum normaliser and the log-shifted potentials W~ = W exp(-m_l)):
+//   f~_0 = delta_a; h_j = W~_{start+j} . (C f~_{j-1} C); c_j = sum h_j; f~_j = h_j / c_j
+//   log Z = la + sum_j (log c_j + m_{start+j}) + log (C f~_{len-1} C)(e),
+// where la is log W_start(a), supplied by the caller. wtab(l, w) fills w[4 q + r] with W~ of
+// slice l at the lane's element (q, r) (any finite value at padded positions, where C f C is an
+// exact zero); put(j, q, r, v) receives element (q, r) of row f~_j, j = 1 .. len - 1, at the
+// lane's positions inside the L x L lattice only. Returns log Z; *ok becomes false when a
+// normaliser or the end weight is not a positive finite number.
+template <typename WTab, typename Put>
+__device__ inline double dmfma_block_forward(const double (&Cb)[16], int L, int L_tau, int start,
+                                             int len, int a, int e, double la,
+                                             const double* __restrict__ shift, WTab wtab, Put put,
+                                             bool* ok) {
+    const int lane = threadIdx.x & 63;
+    auto inside = [&](int q, int r) { return t64_x(q, lane) < L && t64_y(q, r, lane) < L; };
+    const int ax = a % L, ay = a / L;
+    Tile64 F;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            F.t[q][r] = (t64_x(q, lane) == ax && t64_y(q, r, lane) == ay) ? 1.0 : 0.0;
+    bool good = true;
+    for (int j = 1; j < len; ++j) {
+        const int l = (start + j) % L_tau;
+        double w[16];
+        wtab(l, w);
+        const Tile64 H = circ64(circ64(F, Cb), Cb);
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                F.t[q][r] = H.t[q][r] * w[4 * q + r];
+                sum += F.t[q][r];
+            }
+        const double tot = wave_sum_f64(sum);
+        good = good && tot > 0.0 && isfinite(tot);
+        const double inv = 1.0 / tot;
+        la += log(tot) + shift[l];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                F.t[q][r] *= inv;
+                if (inside(q, r)) put(j, q, r, F.t[q][r]);
+            }
+    }
+    // end weight (C f~ C)(e)
+    const Tile64 H = circ64(circ64(F, Cb), Cb);
+    const int ex = e % L, ey = e / L;
+    const int qe = 2 * (ey >> 4) + (ex >> 4), re = (ey & 15) >> 2;
+    double hv = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (q == qe && r == re) hv = H.t[q][r];
+    hv = __shfl(hv, (ex & 15) + 16 * (ey & 3), 64);
+    good = good && hv > 0.0;
+    *ok = good;
+    return la + log(hv);
+}
+
+}  // namespace fh

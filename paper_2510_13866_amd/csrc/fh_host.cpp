@@ -160,6 +160,23 @@ int validate(const fh_chain_desc& d, int precision) {
     return FH_OK;
 }
 
+// FP32 range parameters of a chain (see kRangeFloor): rows scaled by 2^row_exp, lowered from
+// kRowExp when the kernel's mass sum G = exp(4 t dtau) exceeds 2^6, so that W~ 2^60 times a
+// row of mass 2^row_exp stays below 2^126; the step floor is 2^-160 of a step's unweighted mass.
+void set_range(ChainInfo& ci, double t, double dtau, bool fp32) {
+    if (!fp32) {
+        ci.row_exp = 0;
+        ci.row_mass = 1.0;
+        ci.step_floor = 0.0f;
+        return;
+    }
+    const double lsum = 4.0 * t * dtau / log(2.0);  // log2 of sum_d G(d)
+    ci.row_exp = kRowExp - std::max(0, (int)ceil(lsum) - 6);
+    if (ci.row_exp < 0) ci.row_exp = 0;
+    ci.row_mass = ldexp(1.0, ci.row_exp);
+    ci.step_floor = (float)ldexp(exp(4.0 * t * dtau), ci.row_exp + kWScaleLog2 - 160);
+}
+
 template <typename T>
 hipError_t dalloc(T** p, size_t bytes) {
     if (bytes == 0) bytes = 16;
@@ -169,7 +186,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
                     d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
-                    d.status, d.sweep};
+                    d.rescue, d.rescue_list, d.rescue_ws, d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     d = fh::Device();
@@ -309,6 +326,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
                       ci.L <= kWinMaxL && !(flags & FH_FLAG_FULL_ROW_DRAW);
         ci.win_on = windowed[c] ? 1 : 0;
         ci.win_gout2 = win_bound_for(p->tables.data() + tab_g(ci), ci.L, kWin2W);
+        set_range(ci, descs[c].t, descs[c].dtau, precision != FH_FP64);
     }
 
     // Work lists, heaviest chains first so that the long tasks start early.
@@ -413,6 +431,20 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     for (const ChainInfo& ci : p->chains) p->grad_dmfma = p->grad_dmfma && ci.L <= 32;
     p->gpart_elems = (precision == FH_FP32_MFMA3 || p->grad_dmfma) ? gpart : 0;
 
+    // FP32 plans: the FP64 re-filter of blocks that leave FP32's range, one slot of FP64 rows
+    // per wavefront, sized for the longest block of the chains with L <= 32
+    if (precision != FH_FP64) {
+        int64_t rescuable = 0;
+        for (const ChainInfo& ci : p->chains)
+            if (ci.L <= 32) {
+                p->rescue_slot_elems = std::max(p->rescue_slot_elems, (int64_t)(ci.B - 1) * ci.N);
+                rescuable += (int64_t)ci.np * ci.nb;
+            }
+        const int64_t waves = std::min<int64_t>(kRescueMaxSlots, std::max<int64_t>(rescuable, 1));
+        p->n_rescue_slots = (int32_t)((waves + 3) / 4 * 4);
+        p->rescue_slot_elems = std::max<int64_t>(p->rescue_slot_elems, 1);
+    }
+
     hipError_t e = hipSuccess;
     fh::Device& dv = p->d;
     const size_t rs = p->real_size;
@@ -444,6 +476,14 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.perm, sizeof(int32_t) * (size_t)part);
     if (e == hipSuccess) e = dalloc(&dv.perm_inv, sizeof(int32_t) * (size_t)part);
     if (e == hipSuccess) e = dalloc(&dv.sign, sizeof(int32_t) * (size_t)n_chains);
+    if (e == hipSuccess && p->n_rescue_slots > 0) {
+        const size_t words = kRescueChain + 2 * (size_t)n_chains + (size_t)blk;
+        e = dalloc(&dv.rescue, sizeof(int32_t) * words);
+        if (e == hipSuccess) e = hipMemset(dv.rescue, 0, sizeof(int32_t) * words);
+        if (e == hipSuccess) e = dalloc(&dv.rescue_list, sizeof(DrawTask) * draw.size());
+        if (e == hipSuccess)
+            e = dalloc(&dv.rescue_ws, sizeof(double) * (size_t)p->n_rescue_slots * p->rescue_slot_elems);
+    }
     if (e == hipSuccess) e = dalloc(&dv.status, sizeof(int32_t) * 2);
     if (e == hipSuccess) e = dalloc(&dv.bw_state, sizeof(int32_t) * (kBwCounts + (size_t)n_chains));
     if (e == hipSuccess) {
@@ -557,11 +597,16 @@ int fh_sizes(fh_plan p, int64_t* aux_elems, int64_t* path_elems, int64_t* partic
 
 static hipError_t enqueue_forward(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
     hipError_t e = launch_potentials(p, aux, s);
+    if (e == hipSuccess) e = launch_rescue_reset(p, s);  // FP32 plans: empty re-filter queue
     if (e != hipSuccess) return e;
-    if (p->precision == FH_FP32_MFMA3) return launch_forward_mfma(p, aux, paths, s);
-    e = launch_forward_dmfma(p, aux, paths, s);  // FP64 plans, chains with L <= 32
-    if (e != hipSuccess) return e;
-    return p->n_fwd_tasks > 0 ? launch_forward(p, aux, paths, s) : hipSuccess;
+    if (p->precision == FH_FP32_MFMA3) {
+        e = launch_forward_mfma(p, aux, paths, s);
+    } else {
+        e = launch_forward_dmfma(p, aux, paths, s);  // FP64 plans, chains with L <= 32
+        if (e == hipSuccess && p->n_fwd_tasks > 0) e = launch_forward(p, aux, paths, s);
+    }
+    if (e == hipSuccess) e = launch_rescue_expand(p, s);  // FP32: chains re-filtered whole
+    return e;
 }
 
 int fh_forward_filter(fh_plan p, const void* aux, const int32_t* paths, uint64_t sweep,
@@ -570,11 +615,13 @@ int fh_forward_filter(fh_plan p, const void* aux, const int32_t* paths, uint64_t
     hipStream_t s = (hipStream_t)stream;
     FH_TRY(launch_set_sweep(p, sweep, s));
     FH_TRY(enqueue_forward(p, aux, paths, s));
+    FH_TRY(launch_rescue(p, aux, const_cast<int32_t*>(paths), false, s));  // FP64 log Z, rows
     if (logZ) FH_TRY(launch_logz_reduce(p, logZ, s));
     p->have_filters = true;
     p->filters_are_ring = false;
     p->last_sweep = sweep;
     p->last_paths = paths;
+    p->last_aux = aux;
     return FH_OK;
 }
 
@@ -585,6 +632,7 @@ int fh_backward_sample(fh_plan p, int32_t* paths, uint64_t sweep, fh_stream stre
     hipStream_t s = (hipStream_t)stream;
     FH_TRY(launch_set_sweep(p, sweep, s));
     FH_TRY(launch_backward(p, paths, s));
+    FH_TRY(launch_rescue(p, p->last_aux, paths, true, s));  // blocks out of FP32's range
     return FH_OK;
 }
 
@@ -677,6 +725,7 @@ int fh_measure(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* 
 static hipError_t enqueue_sweep_body(fh_plan p, void* aux, int32_t* paths, hipStream_t s) {
     hipError_t e = enqueue_forward(p, aux, paths, s);
     if (e == hipSuccess) e = launch_backward(p, paths, s);
+    if (e == hipSuccess) e = launch_rescue(p, aux, paths, true, s);
     if (e == hipSuccess) e = launch_gibbs(p, paths, aux, s);
     return e;
 }
@@ -812,6 +861,7 @@ int fh_set_hopping(fh_plan p, const double* t) {
                       p->win_bound_scale;
         ci.win_gout2 = win_bound_for(p->tables.data() + tab_g(ci), ci.L, kWin2W) *
                        p->win_bound_scale;
+        set_range(ci, t[c], p->descs[c].dtau, p->precision != FH_FP64);
     }
     FH_TRY(hipMemcpy(p->d.chains, p->chains.data(), sizeof(ChainInfo) * p->n_chains,
                      hipMemcpyHostToDevice));
@@ -854,7 +904,12 @@ int fh_get_filters(fh_plan p, int32_t chain, int32_t particle, void* dst, int64_
     const char* src = (const char*)p->d.filt +
                       p->real_size * (size_t)(c.filt_off + (int64_t)particle * c.L_tau * c.N);
     hipStream_t s = (hipStream_t)stream;
-    FH_TRY(hipMemcpyAsync(dst, src, p->real_size * (size_t)(rows * c.N), hipMemcpyDeviceToDevice, s));
+    if (!p->filters_are_ring && c.row_exp != 0)  // FP32 sweep rows hold f~ 2^row_exp
+        FH_TRY(launch_scale_copy((float*)dst, (const float*)src, rows * c.N,
+                                 (float)ldexp(1.0, -c.row_exp), s));
+    else
+        FH_TRY(hipMemcpyAsync(dst, src, p->real_size * (size_t)(rows * c.N),
+                              hipMemcpyDeviceToDevice, s));
     FH_TRY(hipStreamSynchronize(s));
     return FH_OK;
 }
@@ -1050,6 +1105,34 @@ int fh_debug_backward_adapt(fh_plan p, int32_t enable, int32_t* full_row_passes_
         drop_graph(p);  // the captured sweep launches the adaptation kernel or not
         std::fill(st.begin(), st.end(), 0);  // back on the window
         FH_TRY(hipMemcpy(p->d.bw_state, st.data(), sizeof(int32_t) * st.size(), hipMemcpyHostToDevice));
+    }
+    return FH_OK;
+}
+
+int fh_debug_rescue(fh_plan p, int32_t* last_count, int32_t* whole_chains, int64_t* total,
+                    int32_t* list, int32_t cap) {
+    if (!p || cap < 0 || (cap > 0 && !list)) return FH_ERR_INVALID_ARG;
+    if (last_count) *last_count = 0;
+    if (whole_chains) *whole_chains = 0;
+    if (total) *total = 0;
+    if (!p->d.rescue) return FH_OK;
+    FH_TRY(hipDeviceSynchronize());
+    int32_t w[3];
+    FH_TRY(hipMemcpy(w, p->d.rescue, sizeof(w), hipMemcpyDeviceToHost));
+    const int32_t zero = 0;
+    FH_TRY(hipMemcpy(p->d.rescue + 1, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    if (last_count) *last_count = w[0];
+    if (whole_chains) *whole_chains = w[2];
+    if (total) *total = w[1];
+    const int n = std::min(cap, w[0]);
+    if (n > 0) {
+        std::vector<DrawTask> t((size_t)n);
+        FH_TRY(hipMemcpy(t.data(), p->d.rescue_list, sizeof(DrawTask) * n, hipMemcpyDeviceToHost));
+        for (int i = 0; i < n; ++i) {
+            list[3 * i] = t[i].chain;
+            list[3 * i + 1] = t[i].p;
+            list[3 * i + 2] = t[i].block;
+        }
     }
     return FH_OK;
 }

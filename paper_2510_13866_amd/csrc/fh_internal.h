@@ -35,6 +35,12 @@ struct ChainInfo {
     int32_t win_on;    // 1: the chain's draws may use the windowed kernel (see bw_state)
     double win_gout;   // bound on G(s - r) over the sites r outside that window
     double win_gout2;  // the same for the second window (half-width kWin2W)
+    // FP32 plans: the forward rows of the sweep hold f~ 2^row_exp (row mass 2^row_exp instead
+    // of 1) and a block is queued for the FP64 re-filter when a step's W-weighted mass falls
+    // below step_floor (see kRangeFloor). FP64 plans: row_exp = 0, row_mass = 1.
+    int32_t row_exp;
+    float step_floor;
+    double row_mass;
 };
 
 // Offsets of the tables of one chain inside the double table buffer, relative to tab_off.
@@ -82,6 +88,61 @@ struct GroupTask {
     int64_t part_off;
 };
 
+// FP32 range. FP32 holds a value to full relative precision only down to ~2^-126, and the
+// three-term bf16 split of the matrix-core forward only down to ~2^-110, while the filter rows
+// of strongly clustered fields span far more than that. The FP32 plans therefore place both
+// operands of the weight multiply high in FP32's range: W tables hold W~ 2^kWScaleLog2
+// (W~ = W / max_r W of the slice, so the table's largest entry is 2^60 and W~ down to 2^-186 is
+// representable), and forward rows hold f~ 2^row_exp (row mass 2^60, values down to 2^-170 of
+// the mass split exactly). A block is queued for the FP64 re-filter and redraw (k_rescue) when
+// what its draws need approaches the floor: a forward step whose W-weighted mass is below
+// 2^-160 of its unweighted mass (step_floor), an end weight or a backward draw total below
+// kRangeFloor = 2^-90 (2^-150 of the row mass). A chain with a queued block has every block
+// re-filtered in FP64 in that pass and for the next kRescueHold forward passes: on the way to a
+// clustered state some FP32 blocks drift without meeting a floor, while the settled states
+// meet none.
+constexpr int kWScaleLog2 = 60;
+constexpr int kRowExp = 60;
+constexpr float kRangeFloor = 0x1p-90f;
+constexpr double kRangeFloorD = 0x1p-90;
+constexpr int kRescueHold = 2;
+// Rescue state words: [0] blocks queued in this pass, [1] blocks redrawn since the last read by
+// fh_debug_rescue, [2] chains re-filtered whole in this pass, then per chain: blocks queued by
+// the kernels in this pass (kRescueChain + c) and forward passes left on FP64
+// (kRescueChain + n_chains + c), then one flag per (chain, particle, block) at
+// kRescueChain + 2 n_chains + blk_off + p nb + b (the `flags` pointer passed to the kernels).
+constexpr int kRescueChain = 4;
+// Wavefronts of the FP64 re-filter; each owns one slot of (B - 1) N doubles.
+constexpr int kRescueMaxSlots = 1024;
+
+// Rescue state as the kernels see it: the words above, and the per-block flags.
+struct Rescue {
+    int32_t* words;   // null for FP64 plans
+    int32_t* flags;   // words + kRescueChain + 2 n_chains
+    DrawTask* list;
+    int32_t n_chains;
+};
+// Queues block (chain, p, block) for the FP64 re-filter once; called by one lane.
+__device__ inline bool rescue_enqueue(const Rescue& r, const ChainInfo& c, int chain, int p,
+                                      int block) {
+    if (atomicExch(&r.flags[c.blk_off + (int64_t)p * c.nb + block], 1) != 0) return false;
+    const int i = atomicAdd(&r.words[0], 1);
+    r.list[i] = DrawTask{chain, p, block, 0};
+    return true;
+}
+// A kernel found block (chain, p, block) out of FP32's range: queue it, count it for its chain
+// and keep the chain on the FP64 re-filter for the next kRescueHold forward passes.
+__device__ inline void rescue_push(const Rescue& r, const ChainInfo& c, int chain, int p,
+                                   int block) {
+    if (rescue_enqueue(r, c, chain, p, block)) {
+        atomicAdd(&r.words[kRescueChain + chain], 1);
+        atomicMax(&r.words[kRescueChain + r.n_chains + chain], kRescueHold);
+    }
+}
+__device__ inline bool rescue_queued(const Rescue& r, const ChainInfo& c, int p, int block) {
+    return r.words && r.flags[c.blk_off + (int64_t)p * c.nb + block] != 0;
+}
+
 // One autotuner timing: the radix order `plan` of lattice size L took `ms` per timing launch.
 struct TuneRecord {
     int32_t L;
@@ -128,6 +189,9 @@ struct Device {
                                  // [0] full-row passes left (0: windowed), [1] current hold
                                  // length, then per chain the uncertified first-window draws
                                  // of the last windowed pass ([kBwCounts + chain])
+    int32_t* rescue = nullptr;   // FP32 plans: rescue state words (kRescueFlags), else null
+    DrawTask* rescue_list = nullptr;  // blocks queued for the FP64 re-filter, [n_draw_tasks]
+    double* rescue_ws = nullptr;      // [n_rescue_slots][rescue_slot_elems] FP64 filter rows
     int32_t* status = nullptr;   // [0] first error code, [1] its chain
     uint64_t* sweep = nullptr;   // sweep index read by the kernels
 };
@@ -160,6 +224,8 @@ struct fh_plan_s {
     bool bw_adapt = true;          // switch clustered chains to the full-row kernels
     int32_t n_full_only_tasks = 0; // backward tasks of chains that never use the window
     int64_t gpart_elems = 0;
+    int32_t n_rescue_slots = 0;     // FP32 plans: wavefronts of k_rescue
+    int64_t rescue_slot_elems = 0;  // doubles per slot: (B - 1) N of the largest L <= 32 chain
     int64_t total_sites = 0;  // sum of N over the chains
     int32_t max_N = 0, max_L = 0, max_np = 0;
     size_t real_size = 8;
@@ -170,6 +236,7 @@ struct fh_plan_s {
     bool filters_are_ring = false;
     uint64_t last_sweep = 0;
     const int32_t* last_paths = nullptr;
+    const void* last_aux = nullptr;  // the field of the last fh_forward_filter (FP64 re-filter)
     // graph cache for fh_sweep
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -179,6 +246,16 @@ struct fh_plan_s {
 };
 
 namespace fh {
+
+// The rescue state of a plan as passed to the kernels (all null for FP64 plans).
+inline Rescue rescue_args(fh_plan p) {
+    Rescue r;
+    r.words = p->d.rescue;
+    r.flags = p->d.rescue ? p->d.rescue + kRescueChain + 2 * p->n_chains : nullptr;
+    r.list = p->d.rescue_list;
+    r.n_chains = p->n_chains;
+    return r;
+}
 
 // Kernel launchers (fh_kernels.hip / fh_mfma.hip). All enqueue on `s` and return hipError_t.
 hipError_t launch_set_sweep(fh_plan p, uint64_t sweep, hipStream_t s);
@@ -191,6 +268,11 @@ hipError_t launch_grad_dmfma(fh_plan p, const void* aux, const int32_t* paths, i
 hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s);
 hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s);
 hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s);
+// FP32 plans: clears the rescue queue (before a forward pass), queues whole chains (after it),
+// and re-filters (and, with draw, redraws) the queued blocks in FP64. No-ops for FP64 plans.
+hipError_t launch_rescue_reset(fh_plan p, hipStream_t s);
+hipError_t launch_rescue_expand(fh_plan p, hipStream_t s);  // after the FP32 forward pass
+hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, hipStream_t s);
 // Times every radix order of L (k_fft_tune) on stream s and returns the fastest in *best (the
 // default order unless another is faster by more than 2%); timings are appended to *log.
 hipError_t tune_radix_plan(fh_plan p, int L, const double* tw_dev, hipStream_t s,
@@ -211,6 +293,7 @@ hipError_t launch_grad_reduce(fh_plan p, double* logZ, double* grad_t, hipStream
 hipError_t launch_grad_mfma(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
                             void* grad_aux, hipStream_t s);
 hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t s);
+hipError_t launch_scale_copy(float* dst, const float* src, int64_t n, float factor, hipStream_t s);
 
 size_t forward_lds_bytes(fh_plan p);
 size_t grad_lds_bytes(fh_plan p);

@@ -12,6 +12,7 @@
 #include <vector>
 #include <math.h>
 
+#include "fh_dmfma.h"
 #include "fh_internal.h"
 #include "fh_philox.h"
 
@@ -142,15 +143,25 @@ __device__ inline int checked_site(int r, int N, int32_t* status, int chain) {
 // with W~ = W exp(-m) the shifted potentials, shift[l] = m_spin(l) and log W = coef * aux.
 // Rows f~_j are stored at row + (j - jshift)*N for j >= 1 (and j = 0 when jshift == 0).
 // The last step's end weight is a direct FP64 sum with the real-space kernel g(dx) g(dy).
+// With `low` given (the FP32 sweep), a worldline whose step total or end weight falls below
+// kRangeFloor is reported there (low[0], low[1]) for the FP64 re-filter instead of the status.
 template <typename T>
 __device__ void forward_pass(const ChainInfo& c, const double* tables, const T* Wsp,
                              const double* shift, const T* auxc, double coef, int start, int len,
                              int a_a, int e_a, int a_b,
                              int e_b, bool has_b, T* row_a, T* row_b, int jshift, FftLds<T>& l,
-                             double* logz_a, double* logz_b, int32_t* status, int chain) {
+                             double* logz_a, double* logz_b, int32_t* status, int chain,
+                             bool* low = nullptr) {
+    // the sweep's FP32 rows hold f~ 2^row_exp; the adjoint's ring (jshift = 0) is unscaled
+    const int rexp = jshift == 0 ? 0 : c.row_exp;
+    const T sc = (T)ldexp(1.0, rexp);
+    const double lsc = rexp * 0.69314718055994530942;
+    const double floor = low ? (double)c.step_floor : 0.0;
+    const double efloor = low ? kRangeFloorD : 0.0;
+    bool low_a = false, low_b = false;
     const int N = c.N, L = c.L, L_tau = c.L_tau;
     for (int r = threadIdx.x; r < N; r += blockDim.x) {
-        cpx<T> v = {r == a_a ? T(1) : T(0), (has_b && r == a_b) ? T(1) : T(0)};
+        cpx<T> v = {r == a_a ? sc : T(0), (has_b && r == a_b) ? sc : T(0)};
         l.A[r] = v;
         if (jshift == 0) {
             row_a[r] = v.re;
@@ -158,8 +169,8 @@ __device__ void forward_pass(const ChainInfo& c, const double* tables, const T* 
         }
     }
     // log W_start(a) straight from the field: exact, and immune to underflow of W~(a)
-    double la = coef * (double)auxc[(int64_t)start * N + a_a];
-    double lb = has_b ? coef * (double)auxc[(int64_t)start * N + a_b] : 0.0;
+    double la = coef * (double)auxc[(int64_t)start * N + a_a] - lsc;
+    double lb = has_b ? coef * (double)auxc[(int64_t)start * N + a_b] - lsc : 0.0;
     const double* gh = tables + tab_ghat(c);
     __syncthreads();
     for (int j = 1; j < len; ++j) {
@@ -181,11 +192,14 @@ __device__ void forward_pass(const ChainInfo& c, const double* tables, const T* 
             s[1] += (double)h.im;
         }
         block_sum<2>(s, l.red);
-        if (!(s[0] > 0.0) || !isfinite(s[0]) || (has_b && (!(s[1] > 0.0) || !isfinite(s[1]))))
-            if (threadIdx.x == 0) set_status(status, FH_ERR_NONFINITE, chain);
-        const T ia = (T)(1.0 / s[0]);
-        const T ib = has_b ? (T)(1.0 / s[1]) : T(0);
-        const double m = shift[(start + j) % L_tau];
+        const bool ba = !(s[0] > floor) || !isfinite(s[0]);
+        const bool bb = has_b && (!(s[1] > floor) || !isfinite(s[1]));
+        low_a = low_a || ba;
+        low_b = low_b || bb;
+        if (!low && (ba || bb) && threadIdx.x == 0) set_status(status, FH_ERR_NONFINITE, chain);
+        const T ia = (T)((double)sc / s[0]);
+        const T ib = has_b ? (T)((double)sc / s[1]) : T(0);
+        const double m = shift[(start + j) % L_tau] - lsc;
         la += log(s[0]) + m;
         if (has_b) lb += log(s[1]) + m;
         T* ra = row_a + (int64_t)(j - jshift) * N;
@@ -217,8 +231,14 @@ __device__ void forward_pass(const ChainInfo& c, const double* tables, const T* 
     block_sum<2>(z, l.red);
     // an end site deeper in the filter's tail than the FFT resolves (~eps * max) can leave a
     // non-positive end weight: report it instead of returning log of it
-    if ((!(z[0] > 0.0) || (has_b && !(z[1] > 0.0))) && threadIdx.x == 0)
+    low_a = low_a || !(z[0] > efloor);
+    low_b = low_b || (has_b && !(z[1] > efloor));
+    if (low) {
+        low[0] = low_a;
+        low[1] = low_b;
+    } else if ((low_a || low_b) && threadIdx.x == 0) {
         set_status(status, FH_ERR_NONFINITE, chain);
+    }
     *logz_a = la + log(z[0]);
     *logz_b = has_b ? lb + log(z[1]) : 0.0;
 }
@@ -241,8 +261,9 @@ __global__ void k_zero(uint32_t* p, int64_t words) {
 
 // Site potentials of one (chain, slice) in log-domain-shifted form (eq. hirsch / eq. gaussHS):
 // log W_spin(l, r) = coef_spin * aux(l, r); the tables hold W~ = exp(log W - m_spin(l)) with
-// m_spin(l) = max_r log W_spin(l, r), so W~ <= 1 whatever the field, and m is kept in FP64 and
-// added back to log Z. Filters are normalised per step, so the shift changes nothing else.
+// m_spin(l) = max_r log W_spin(l, r), so W~ <= 1 whatever the field (FP32 tables: m lowered by
+// kWScaleLog2 ln 2, so W~ <= 2^60), and m is kept in FP64 and added back to log Z. Filters are
+// normalised per step, so the shift changes nothing else.
 // W[0 .. aux_elems) holds spin up, W[aux_elems .. 2 aux_elems) spin down.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_potentials(const ChainInfo* __restrict__ chains,
@@ -283,6 +304,10 @@ __global__ __launch_bounds__(kThreads) void k_potentials(const ChainInfo* __rest
     }
     if (!isfinite(mu)) mu = 0.0;
     if (!isfinite(md)) md = 0.0;
+    if (sizeof(T) == 4) {  // FP32 tables: W~ 2^kWScaleLog2, so W~ down to 2^-186 stays normal
+        mu -= kWScaleLog2 * 0.69314718055994530942;
+        md -= kWScaleLog2 * 0.69314718055994530942;
+    }
     for (int r = threadIdx.x; r < c.N; r += blockDim.x) {
         const double v = (double)aux[base + r];
         W[base + r] = (T)exp(c.coef_up * v - mu);
@@ -301,7 +326,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_fft(
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, T* __restrict__ filt,
     double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    int maxN, int maxL) {
+    int maxN, int maxL, const Rescue rsc) {
     extern __shared__ __align__(16) unsigned char smem[];
     FftLds<T> l = carve<T>(smem, maxN, maxL, false);
     const PairTask t = tasks[blockIdx.x];
@@ -327,12 +352,15 @@ __global__ __launch_bounds__(kThreads) void k_forward_fft(
     T* row_a = filt + c.filt_off + ((int64_t)t.p_a * c.L_tau + rowbase) * c.N;
     T* row_b = has_b ? filt + c.filt_off + ((int64_t)t.p_b * c.L_tau + rowbase) * c.N : nullptr;
     double lza, lzb;
+    bool low[2] = {false, false};  // FP32: the worldlines that left FP32's range
     forward_pass<T>(c, tables, Wsp, shift, aux + c.aux_off, spin ? c.coef_dn : c.coef_up, start,
                     len, a_a, e_a, a_b, e_b, has_b, row_a, row_b, 1, l, &lza, &lzb, status,
-                    t.chain);
+                    t.chain, rsc.words ? low : nullptr);
     if (threadIdx.x == 0) {
         blk_logz[c.blk_off + (int64_t)t.p_a * c.nb + t.block] = lza;
         if (has_b) blk_logz[c.blk_off + (int64_t)t.p_b * c.nb + t.block] = lzb;
+        if (low[0]) rescue_push(rsc, c, t.chain, t.p_a, t.block);
+        if (has_b && low[1]) rescue_push(rsc, c, t.chain, t.p_b, t.block);
     }
 }
 
@@ -366,13 +394,14 @@ __global__ __launch_bounds__(kThreads) void k_backward(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
     const int32_t* __restrict__ perm, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    const int32_t* __restrict__ bw_state) {
+    const int32_t* __restrict__ bw_state, const Rescue rsc) {
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int task = blockIdx.x * kWaves + wv;
     if (task >= n_tasks) return;  // whole wavefront leaves; no block-level barrier below
     if (on_window(chains, tasks[task].chain, bw_state)) return;  // k_backward_win draws it
     const DrawTask t = tasks[task];
     const ChainInfo& c = chains[t.chain];
+    if (rescue_queued(rsc, c, t.p, t.block)) return;  // k_rescue redraws it in FP64
     const uint64_t sweep = *sweep_ptr;
     int start, len;
     block_of(c, sweep, t.block, &start, &len);
@@ -410,6 +439,11 @@ __global__ __launch_bounds__(kThreads) void k_backward(
         if (lane == 0) excl = 0.0;
         const double total = __shfl(incl, 63, 64);
         int chosen = cur;
+        if (rsc.words && (!(total >= kRangeFloorD) || !isfinite(total))) {
+            // an FP32 row this far below its mass: the block is redrawn from FP64 filters
+            if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
+            return;
+        }
         if (!(total > 0.0) || !isfinite(total)) {
             if (lane == 0)
                 set_status(status, isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE, t.chain);
@@ -481,11 +515,12 @@ template <typename T, bool VEC, int LFIX, int E>
 __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const double* g,
                               const T* __restrict__ filt, int32_t* __restrict__ paths,
                               const int32_t* __restrict__ perm, uint64_t sweep, int32_t* status,
-                              int lane) {
+                              int lane, const Rescue rsc) {
     constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;  // rows in flight ahead of the current one
     int start, len;
     block_of(c, sweep, t.block, &start, &len);
     if (len < 2) return;
+    if (rescue_queued(rsc, c, t.p, t.block)) return;  // k_rescue redraws it in FP64
     const int L = LFIX ? LFIX : c.L, N = LFIX ? LFIX * LFIX : c.N, L_tau = c.L_tau;
     int32_t* pc = paths + c.path_off;
     const int qn = perm[c.part_off + t.p];  // the worldline slices >= L_tau belong to
@@ -581,6 +616,11 @@ __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const doubl
         const double incl = wave_incl_scan_f64(tot, lane, &total);
         double run = incl - tot;
         int chosen = cur;
+        if (rsc.words && (!(total >= kRangeFloorD) || !isfinite(total))) {
+            // an FP32 row this far below its mass: the block is redrawn from FP64 filters
+            if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
+            return;
+        }
         if (!(total > 0.0) || !isfinite(total)) {
             if (lane == 0)
                 set_status(status, isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE, t.chain);
@@ -630,17 +670,19 @@ template <typename T>
 __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l32(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
-    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const int32_t* __restrict__ bw_state) {
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const int32_t* __restrict__ bw_state,
+    const Rescue rsc) {
     constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;
     constexpr int NB = DEPTH + 1;
     __shared__ double g2sh[kWaves][64];  // g2[m] = g(m mod 32), so g(d) = g2[d + 32] for |d| < 32
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + wv);
-    const bool active = task < n_tasks && !on_window(chains, tasks[task].chain, bw_state);
+    bool active = task < n_tasks && !on_window(chains, tasks[task].chain, bw_state);
     DrawTask t = {0, 0, 0, 0};
     if (active) {
         t = tasks[task];
         g2sh[wv][lane] = tables[tab_g(chains[t.chain]) + (lane & 31)];
+        active = !rescue_queued(rsc, chains[t.chain], t.p, t.block);  // k_rescue draws it
     }
     __syncthreads();  // the only barrier; every wave reaches it
     if (!active) return;
@@ -680,11 +722,12 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
     double ureg = 0.0;
     int err = 0;  // the first error of the block, reported once after the loop (no atomics inside)
     const int nd_pad = (nd + NB - 1) / NB * NB;
-    for (int s0 = 0; s0 < nd_pad; s0 += NB) {
+    bool halted = false;  // the block left FP32's range: k_rescue redraws it
+    for (int s0 = 0; s0 < nd_pad && !halted; s0 += NB) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int s = s0 + b;
-            const bool real = s < nd;
+            const bool real = s < nd && !halted;
             const int j = real ? nd - s : 1;
             if ((s & 63) == 0) {  // lane k draws the uniform of draw s + k
                 const int jj = nd - s - lane;
@@ -712,7 +755,10 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
             double total;
             const double incl = wave_incl_scan_f64(tot, lane, &total);
             int chosen = cur;
-            if (!(total > 0.0) || !isfinite(total)) {
+            if (rsc.words && real && (!(total >= kRangeFloorD) || !isfinite(total))) {
+                halted = true;  // an FP32 row this far below its mass: redrawn from FP64 filters
+                if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
+            } else if (!(total > 0.0) || !isfinite(total)) {
                 if (real && err == 0) err = isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE;
             } else {
                 const double T_ = u * total;
@@ -757,10 +803,13 @@ __device__ inline double group_scan_incl(double v) {
 // the first site in site order whose cumulative weight exceeds u times the total, else the last
 // site with a positive weight). Lane k owns the per = ceil(N / 64) contiguous sites from k per;
 // the weights max(f, 0) g(dy) g(dx) are taken about (cx, cy). Every argument is wavefront
-// uniform. On a zero or non-finite total the current site is kept and *bad gets the error.
+// uniform. On a zero or non-finite total the current site is kept and *bad gets the error;
+// with `range` (FP32 plans) a total below kRangeFloorD sets *bad = kBadRange instead.
+constexpr int kBadRange = 1;
 template <typename T>
 __device__ int wave_row_draw(const T* __restrict__ row, int N, int L, int cx, int cy,
-                             const double* g, double u, int cur, int lane, int* bad) {
+                             const double* g, double u, int cur, int lane, int* bad,
+                             bool range = false) {
     constexpr int C = 8;  // loads in flight per lane (register budget of the caller)
     const int per = (N + 63) >> 6;
     const int i0 = lane * per;
@@ -797,6 +846,10 @@ __device__ int wave_row_draw(const T* __restrict__ row, int N, int L, int cx, in
     }
     double total;
     const double incl = wave_incl_scan_f64(tot, lane, &total);
+    if (range && (!(total >= kRangeFloorD) || !isfinite(total))) {
+        *bad = kBadRange;
+        return cur;
+    }
     if (!(total > 0.0) || !isfinite(total)) {
         *bad = isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE;
         return cur;
@@ -839,10 +892,12 @@ __device__ int wave_row_draw(const T* __restrict__ row, int N, int L, int cx, in
 // wavefront: lane k holds the window ranks 4k .. 4k + 3 (site order), so the draw costs one
 // round trip of four loads per lane. The lane sums are scanned across the wavefront and the lane
 // holding the first rank above tau certifies the draw. Every argument is wavefront uniform.
-// Returns (1 << 16 | y << 8 | x) for a certified draw, 0 otherwise (uniform).
+// Returns (1 << 16 | y << 8 | x) for a certified draw, 0 otherwise (uniform). A window whose
+// mass is not above `floor` is never certified.
 template <typename T>
 __device__ int wave_window2_draw(const T* __restrict__ row, int L, int cx, int cy,
-                                 const double* g, double u, double gout2, int lane) {
+                                 const double* g, double u, double gout2, int lane,
+                                 double floor) {
     constexpr int K = 4;
     static_assert(64 * K >= (2 * kWin2W + 1) * (2 * kWin2W + 1), "the window fits the wavefront");
     const int WW = win_width(kWin2W, L), nwin = WW * WW;
@@ -876,7 +931,7 @@ __device__ int wave_window2_draw(const T* __restrict__ row, int L, int cx, int c
     const double incl = wave_incl_scan_f64(acc, lane, &T_in);
     const double excl = incl - acc;
     const double tau = u * T_in;
-    const bool fin = T_in > 0.0 && isfinite(T_in);
+    const bool fin = T_in > floor && isfinite(T_in);
     const uint64_t fm = __ballot(fin && incl > tau && acc > 0.0);
     if (!fm) return 0;
     const int src = __ffsll((unsigned long long)fm) - 1;
@@ -919,7 +974,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
     const int32_t* __restrict__ perm, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    int32_t* __restrict__ bw_state, int count_uncertified) {
+    int32_t* __restrict__ bw_state, int count_uncertified, const Rescue rsc) {
     constexpr int G = kThreads / kWinLanes;
     constexpr int K = kWinPerLane;
     // g(d) for d in (-L, L): gsh[grp][kWinMaxL + d], so a signed offset indexes it directly
@@ -929,9 +984,13 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     const int gbase = lane64 - li;  // the group's first lane in the wavefront
     const int task = blockIdx.x * G + grp;
     // while the plan is on the full-row kernels, they draw these tasks
-    const bool active = task < n_tasks && bw_state[0] == 0;
-    const DrawTask t = active ? tasks[task] : DrawTask{0, 0, 0, 0};
+    const bool listed = task < n_tasks && bw_state[0] == 0;
+    const DrawTask t = listed ? tasks[task] : DrawTask{0, 0, 0, 0};
     const ChainInfo& c = chains[t.chain];
+    // a block queued for the FP64 re-filter is drawn by k_rescue
+    const bool active = listed && !rescue_queued(rsc, c, t.p, t.block);
+    // FP32 plans: a window or row whose mass is below kRangeFloorD is not drawn in FP32
+    const double wfloor = rsc.words ? kRangeFloorD : 0.0;
     // an inactive group draws nothing; on a one-site lattice its table fill and loads stay minimal
     const int L = active ? c.L : 1, N = active ? c.N : 1, L_tau = c.L_tau, w = c.win_w;
     double* g = gsh[grp] + kWinMaxL;  // g[d] = g(d mod L) for -L < d < L
@@ -966,7 +1025,8 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         qx[k] = qv[k] ? q - qy[k] * WW : 0;
     }
     const T* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
-    const double gout = c.win_gout * kWinMassBound;
+    // the outside bound scales with the row mass (2^row_exp on FP32 plans)
+    const double gout = c.win_gout * c.row_mass * kWinMassBound;
     double ureg = 0.0;
     int err = 0;  // the first error of the block, reported once after the loop
     int n_unc = 0;  // draws the first window did not certify (kept by lane 0 of the group)
@@ -975,6 +1035,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     // every draw would make each draw's window loads wait for the previous draw's store; the
     // batch store is issued after the next draw's loads.
     int pend = 0;
+    bool halt = false;  // the block left FP32's range: k_rescue redraws it
     auto flush = [&](int sb) {
         const int sd = sb + li;
         if (sd < nd) {
@@ -983,8 +1044,8 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         }
     };
     for (int s = 0; s < nd_max; ++s) {
-        const bool real = s < nd;
-        const int j = real ? nd - s : 1;
+        const bool real = s < nd && !halt;
+        const int j = s < nd ? nd - s : 1;
         if ((s & 15) == 0) {  // lane li draws the uniform of draw s + li
             const int jj = nd - s - li;
             ureg = 0.0;
@@ -1027,7 +1088,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         const double excl = dpp_f64<0x111>(incl);  // the previous lane's inclusive sum (0 first)
         const double T_in = __shfl(incl, gbase + 15, 64);
         const double tau = u * T_in;
-        const bool fin = T_in > 0.0 && isfinite(T_in);
+        const bool fin = T_in > wfloor && isfinite(T_in);
         const uint32_t gm =
             (uint32_t)(__ballot(real && fin && incl > tau && acc > 0.0) >> gbase) & 0xFFFFu;
         const int src = gm ? __ffs((int)gm) - 1 : 0;
@@ -1072,7 +1133,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
             const int p2 = wave_window2_draw(
                 rowg, __builtin_amdgcn_readlane(L, g0), __builtin_amdgcn_readlane(cx, g0),
                 __builtin_amdgcn_readlane(cy, g0), gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)] + kWinMaxL,
-                readlane_f64(u, g0), readlane_f64(c.win_gout2, g0), lane64);
+                readlane_f64(u, g0), readlane_f64(c.win_gout2 * c.row_mass, g0), lane64, wfloor);
             if ((lane64 >> 4) == (g0 >> 4)) {
                 if (p2 >> 16) {
                     nx = p2 & 255;
@@ -1096,11 +1157,15 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
             const int chosen = wave_row_draw(
                 rowg, __builtin_amdgcn_readlane(N, g0), Lg, __builtin_amdgcn_readlane(cx, g0),
                 __builtin_amdgcn_readlane(cy, g0), gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)] + kWinMaxL,
-                readlane_f64(u, g0), __builtin_amdgcn_readlane(cur, g0), lane64, &bad);
+                readlane_f64(u, g0), __builtin_amdgcn_readlane(cur, g0), lane64, &bad,
+                rsc.words != nullptr);
             if ((lane64 >> 4) == (g0 >> 4)) {
                 nx = chosen % Lg;
                 ny = chosen / Lg;
-                if (bad != 0 && err == 0) err = bad;
+                if (bad == kBadRange)
+                    halt = true;
+                else if (bad != 0 && err == 0)
+                    err = bad;
             }
         }
         if (real) {
@@ -1111,9 +1176,139 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         if (li == (s & 15)) pend = cur;
     }
     if (nd_max > 0) flush((nd_max - 1) & ~15);
+    if (halt && li == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
     if (err != 0 && li == 0) set_status(status, err, t.chain);  // the block's first error
     if (count_uncertified && active && li == 0 && n_unc > 0)
         atomicAdd(&bw_state[kBwCounts + t.chain], n_unc);
+}
+
+// FP64 re-filter and redraw of the blocks an FP32 pass queued because their filters left
+// FP32's range (kRangeFloor). The FP32 pass's rows for such a block hold values at FP32's floor
+// that decide its draws and log Z; FP64 holds them to ~2^-1022. One wavefront takes queued
+// blocks i = wid, wid + n_slots, ... in turn, with its own slot of FP64 rows:
+//   forward: the block recursion of k_forward_dmfma on the FP64 circulant, with
+//            W~ = exp(coef aux - m_l) computed in FP64 from the field (the FP32 tables may hold
+//            zeros there); rows to the slot and, rounded, to the plan's FP32 rows (what
+//            fh_get_filters returns); log Z to blk_logz;
+//   DRAW:    the block's sites from the slot's rows with k_backward's full-row rule and the same
+//            Philox uniforms, so the draws are those of an FP64 plan.
+// Only chains with L <= 32 have the FP64 circulant; a queued block of a larger lattice latches
+// FH_ERR_NONFINITE and keeps its sites. Every wavefront reads the queue length once and leaves
+// when its share is done.
+template <bool DRAW>
+__global__ __launch_bounds__(kThreads) void k_rescue(
+    const ChainInfo* __restrict__ chains, const double* __restrict__ tables,
+    const double* __restrict__ cmat64, const float* __restrict__ aux,
+    const double* __restrict__ wshift, int64_t total_slices, int32_t* __restrict__ paths,
+    const int32_t* __restrict__ perm, float* __restrict__ filt, double* __restrict__ blk_logz,
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const Rescue rsc,
+    double* __restrict__ ws, int64_t slot_elems, int n_slots) {
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
+    const int count = __builtin_amdgcn_readfirstlane(rsc.words[0]);
+    if (DRAW && wid == 0 && lane == 0 && count > 0) atomicAdd(&rsc.words[1], count);
+    double* slot = ws + (int64_t)wid * slot_elems;
+    const uint64_t sweep = *sweep_ptr;
+    for (int i = wid; i < count; i += n_slots) {
+        const DrawTask t = rsc.list[i];
+        const ChainInfo& c = chains[t.chain];
+        if (c.L > 32) {
+            if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
+            continue;
+        }
+        int start, len;
+        block_of(c, sweep, t.block, &start, &len);
+        const int L = c.L, N = c.N, L_tau = c.L_tau;
+        const int spin = t.p >= c.n_up ? 1 : 0;
+        const double coef = spin ? c.coef_dn : c.coef_up;
+        const double* shift = wshift + spin * total_slices + c.slice_off;
+        const float* ax = aux + c.aux_off;
+        int32_t* pc = paths + c.path_off;
+        const int qn = perm[c.part_off + t.p];  // the worldline slices >= L_tau belong to
+        const int a = checked_site(pc[(int64_t)start * c.np + t.p], N, status, t.chain);
+        const int e = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np +
+                                      (start + len >= L_tau ? qn : t.p)], N, status, t.chain);
+        double Cb[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) Cb[q] = cmat64[((int64_t)t.chain * 16 + q) * 64 + lane];
+        float* frows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+        auto wtab = [&](int l, double (&w)[16]) {
+            const float* al = ax + (int64_t)l * N;
+            const double m = shift[l];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int x = t64_x(q, lane), y = t64_y(q, r, lane);
+                    w[4 * q + r] = (x < L && y < L) ? exp(coef * (double)al[y * L + x] - m) : 0.0;
+                }
+        };
+        auto put = [&](int j, int q, int r, double v) {
+            const int64_t o = (int64_t)(j - 1) * N + t64_y(q, r, lane) * L + t64_x(q, lane);
+            slot[o] = v;
+            frows[o] = (float)(v * c.row_mass);  // the FP32 rows' scaling
+        };
+        bool ok = true;
+        const double lz = dmfma_block_forward(Cb, L, L_tau, start, len, a, e,
+                                              coef * (double)ax[(int64_t)start * N + a], shift,
+                                              wtab, put, &ok);
+        if (lane == 0) {
+            if (!ok) set_status(status, FH_ERR_NONFINITE, t.chain);
+            blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = lz;
+        }
+        if (!DRAW || !ok) continue;
+        // the slot's rows were stored by this wavefront's lanes: make them visible to its loads
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        const double* g = tables + tab_g(c);
+        int cur = e;
+        int err = 0;
+        for (int j = len - 1; j >= 1; --j) {
+            const int l = (start + j) % L_tau;
+            const u64x4 rnd = philox4x64_10((uint64_t)t.p, (uint64_t)l, sweep, kTagPath, c.seed, 0);
+            int bad = 0;
+            const int chosen = wave_row_draw(slot + (int64_t)(j - 1) * N, N, L, cur % L, cur / L,
+                                             g, u01_from(rnd.x0), cur, lane, &bad);
+            if (bad != 0 && err == 0) err = bad;
+            if (lane == 0) pc[(int64_t)l * c.np + (start + j >= L_tau ? qn : t.p)] = chosen;
+            cur = chosen;
+        }
+        if (err != 0 && lane == 0) set_status(status, err, t.chain);
+        // the next block reuses the slot: its stores must follow these loads
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    }
+}
+
+// Before a forward pass: an empty queue, no block flagged, no chain counted (the per-chain
+// holds and the redrawn total stay).
+__global__ void k_rescue_reset(const Rescue rsc, int64_t n_flags) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (i == 0) {
+        rsc.words[0] = 0;
+        rsc.words[2] = 0;
+    }
+    for (int64_t k = i; k < rsc.n_chains; k += stride) rsc.words[kRescueChain + k] = 0;
+    for (int64_t k = i; k < n_flags; k += stride) rsc.flags[k] = 0;
+}
+
+// After the FP32 forward pass, one workgroup per chain: a chain with a block queued in this pass,
+// or still held from an earlier one, has all its blocks queued for the FP64 re-filter; its hold
+// then counts down (kRescueHold passes after the last pass with a queued block).
+__global__ __launch_bounds__(kThreads) void k_rescue_expand(const ChainInfo* __restrict__ chains,
+                                                            const Rescue rsc) {
+    const int ci = blockIdx.x;
+    const ChainInfo& c = chains[ci];
+    const int cnt = rsc.words[kRescueChain + ci];
+    const int hold = rsc.words[kRescueChain + rsc.n_chains + ci];
+    const bool whole = cnt > 0 || hold > 0;
+    if (whole)
+        for (int i = threadIdx.x; i < c.np * c.nb; i += blockDim.x)
+            rescue_enqueue(rsc, c, ci, i / c.nb, i % c.nb);
+    __syncthreads();  // every thread read the hold before it changes
+    if (threadIdx.x == 0) {
+        rsc.words[kRescueChain + rsc.n_chains + ci] = cnt > 0 ? kRescueHold : max(hold - 1, 0);
+        if (whole) atomicAdd(&rsc.words[2], 1);
+    }
 }
 
 // After the backward pass of a sweep: moves the plan's windowed chains between the windowed
@@ -1159,7 +1354,8 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_backward_fast(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
-    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const int32_t* __restrict__ bw_state) {
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const int32_t* __restrict__ bw_state,
+    const Rescue rsc) {
     __shared__ double gsh[kWaves][kMaxL];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int task = blockIdx.x * kWaves + wv;
@@ -1175,9 +1371,11 @@ __global__ __launch_bounds__(kThreads) void k_backward_fast(
     const ChainInfo& c = chains[t.chain];
     const uint64_t sweep = *sweep_ptr;
     if (c.N <= 256)
-        backward_task<T, false, 0, 4>(t, c, gsh[wv], filt, paths, perm, sweep, status, lane);
+        backward_task<T, false, 0, 4>(t, c, gsh[wv], filt, paths, perm, sweep, status, lane,
+                                      rsc);
     else
-        backward_task<T, false, 0, 16>(t, c, gsh[wv], filt, paths, perm, sweep, status, lane);
+        backward_task<T, false, 0, 16>(t, c, gsh[wv], filt, paths, perm, sweep, status, lane,
+                                       rsc);
 }
 
 
@@ -1841,14 +2039,14 @@ hipError_t launch_forward(fh_plan p, const void* aux, const int32_t* paths, hipS
                            p->d.chains, p->d.fwd_tasks, p->d.tables, (const double*)aux,
                            (const double*)p->d.W,
                            p->d.wshift, p->aux_elems, p->total_slices, paths, p->d.perm, (double*)p->d.filt, p->d.blk_logz, p->d.sweep,
-                           p->d.status, p->max_N, p->max_L);
+                           p->d.status, p->max_N, p->max_L, rescue_args(p));
     } else {
         if ((e = allow_lds(k_forward_fft<float>, lds)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_forward_fft<float>, dim3(p->n_fwd_tasks), dim3(kThreads), lds, s,
                            p->d.chains, p->d.fwd_tasks, p->d.tables, (const float*)aux,
                            (const float*)p->d.W,
                            p->d.wshift, p->aux_elems, p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep,
-                           p->d.status, p->max_N, p->max_L);
+                           p->d.status, p->max_N, p->max_L, rescue_args(p));
     }
     return hipGetLastError();
 }
@@ -1869,23 +2067,25 @@ hipError_t launch_backward_kernels(fh_plan p, int32_t* paths, hipStream_t s) {
             hipLaunchKernelGGL(k_backward_win<double>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draww_tasks, p->n_draww_tasks, p->d.tables,
                                (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state,
-                               p->bw_adapt ? 1 : 0);
+                               p->bw_adapt ? 1 : 0, rescue_args(p));
         else
             hipLaunchKernelGGL(k_backward_win<float>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draww_tasks, p->n_draww_tasks, p->d.tables,
                                (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state,
-                               p->bw_adapt ? 1 : 0);
+                               p->bw_adapt ? 1 : 0, rescue_args(p));
     }
     if (p->n_draw32_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_draw32_tasks + kWaves - 1) / kWaves);
         if (p->precision == FH_FP64)
             hipLaunchKernelGGL(k_backward_l32<double>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draw32_tasks, p->n_draw32_tasks, p->d.tables,
-                               (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
+                               (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state,
+                               rescue_args(p));
         else
             hipLaunchKernelGGL(k_backward_l32<float>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draw32_tasks, p->n_draw32_tasks, p->d.tables,
-                               (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
+                               (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state,
+                               rescue_args(p));
     }
     if (p->n_drawx_tasks == 0) return hipGetLastError();
     const unsigned blocks = (unsigned)((p->n_drawx_tasks + kWaves - 1) / kWaves);
@@ -1895,24 +2095,72 @@ hipError_t launch_backward_kernels(fh_plan p, int32_t* paths, hipStream_t s) {
         if (p->precision == FH_FP64)
             hipLaunchKernelGGL(k_backward_fast<double>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, tasks, n, p->d.tables, (const double*)p->d.filt, paths,
-                               p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
+                               p->d.perm, p->d.sweep, p->d.status, p->d.bw_state,
+                               rescue_args(p));
         else
             hipLaunchKernelGGL(k_backward_fast<float>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, tasks, n, p->d.tables, (const float*)p->d.filt, paths,
-                               p->d.perm, p->d.sweep, p->d.status, p->d.bw_state);
+                               p->d.perm, p->d.sweep, p->d.status, p->d.bw_state,
+                               rescue_args(p));
         return hipGetLastError();
     }
     if (p->precision == FH_FP64)
         hipLaunchKernelGGL(k_backward<double>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            tasks, n, p->d.tables, (const double*)p->d.filt, paths, p->d.perm,
-                           p->d.sweep, p->d.status, p->d.bw_state);
+                           p->d.sweep, p->d.status, p->d.bw_state,
+                               rescue_args(p));
     else
         hipLaunchKernelGGL(k_backward<float>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            tasks, n, p->d.tables, (const float*)p->d.filt, paths, p->d.perm,
-                           p->d.sweep, p->d.status, p->d.bw_state);
+                           p->d.sweep, p->d.status, p->d.bw_state,
+                               rescue_args(p));
     return hipGetLastError();
 }
 }  // namespace
+
+__global__ void k_scale_f32(float* __restrict__ dst, const float* __restrict__ src, int64_t n,
+                            float factor) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i] * factor;
+}
+
+hipError_t launch_scale_copy(float* dst, const float* src, int64_t n, float factor, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_f32, dim3(grid_for(n)), dim3(kThreads), 0, s, dst, src, n, factor);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescue_reset(fh_plan p, hipStream_t s) {
+    if (!p->d.rescue) return hipSuccess;
+    hipLaunchKernelGGL(k_rescue_reset, dim3(grid_for(std::max<int64_t>(p->blk_elems, p->n_chains))),
+                       dim3(kThreads), 0, s, rescue_args(p), p->blk_elems);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescue_expand(fh_plan p, hipStream_t s) {
+    if (!p->d.rescue) return hipSuccess;
+    hipLaunchKernelGGL(k_rescue_expand, dim3(p->n_chains), dim3(kThreads), 0, s, p->d.chains,
+                       rescue_args(p));
+    return hipGetLastError();
+}
+
+hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, hipStream_t s) {
+    if (!p->d.rescue) return hipSuccess;
+    const unsigned blocks = (unsigned)(p->n_rescue_slots / kWaves);
+    if (draw)
+        hipLaunchKernelGGL(k_rescue<true>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.tables, p->d.cmat64, (const float*)aux, p->d.wshift,
+                           p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
+                           p->d.sweep, p->d.status, rescue_args(p), p->d.rescue_ws,
+                           p->rescue_slot_elems, p->n_rescue_slots);
+    else
+        hipLaunchKernelGGL(k_rescue<false>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.tables, p->d.cmat64, (const float*)aux, p->d.wshift,
+                           p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
+                           p->d.sweep, p->d.status, rescue_args(p), p->d.rescue_ws,
+                           p->rescue_slot_elems, p->n_rescue_slots);
+    return hipGetLastError();
+}
 
 hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s) {
     // windowed draws where the hopping kernel allows them; 32 x 32 chains without the window (or

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "fh_dmfma.h"
 #include "fh_internal.h"
 
 namespace fh {
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
     double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    const NegPairs neg) {
+    const Rescue rsc, const NegPairs neg) {
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
@@ -186,10 +187,13 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
         for (int v = 0; v < 16; ++v) dst[v] = Wl[inside(v) ? lane_off + vrow(v) * L : 0];
     };
     const int ax = a % L, ay = a / L;
+    // rows hold f~ 2^row_exp (the FP32 range scaling), from f_0 = 2^row_exp delta_a on
+    const float sc = ldexpf(1.0f, c.row_exp);
+    const double lsc = c.row_exp * 0.69314718055994530942;
     f32x16 F;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) F[v] = (x == ax && tile_row(lane, v) == ay) ? 1.0f : 0.0f;
-    double la = coef * (double)aux[c.aux_off + (int64_t)start * N + a];
+    for (int v = 0; v < 16; ++v) F[v] = (x == ax && tile_row(lane, v) == ay) ? sc : 0.0f;
+    double la = coef * (double)aux[c.aux_off + (int64_t)start * N + a] - lsc;
     double prod = 1.0;
     float* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
     // W of the next slice is loaded right after the stores of this one, so that its wait (one
@@ -197,6 +201,7 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     // are not counted ahead of time, long retired
     float wn[16];
     load_w((start + 1) % L_tau, wn);
+    bool low = false;  // the block left FP32's range: queued for the FP64 re-filter
     auto step = [&](int j) {
         const int l = (start + j) % L_tau;
         const f32x16 X = circ_step(F, C, neg);
@@ -208,21 +213,22 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
             s += F[v];
         }
         const float tot = wave_sum_f32(s);
-        if (!(tot > 0.0f) || !isfinite(tot))
-            if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
+        low = low || !(tot >= c.step_floor) || !isfinite(tot);
         // f~_j = h_j * inv, so the normaliser actually applied is exactly 1/inv: log Z takes
-        // -log(inv), accumulated as an FP64 product folded into the log occasionally
+        // -log(inv), accumulated as an FP64 product folded into the log occasionally; the
+        // rows carry the power of two sc on top
         const float inv = __builtin_amdgcn_rcpf(tot);
         prod *= (double)inv;
         if (!(prod > 1e-200 && prod < 1e200)) {
             la -= log(prod);
             prod = 1.0;
         }
-        la += shift[l];
+        la += shift[l] - lsc;
+        const float k = inv * sc;
         float* row = rows + (int64_t)(j - 1) * N + lane_off;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            F[v] *= inv;
+            F[v] *= k;
             if (inside(v)) __builtin_nontemporal_store(F[v], row + vrow(v) * L);
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -246,50 +252,12 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     hv = __shfl(hv, le, 64);
     la -= log(prod);
     if (lane == 0) {
-        if (!(hv > 0.0f)) set_status(status, FH_ERR_NONFINITE, t.chain);  // end weight underflowed
+        if (low || !(hv >= kRangeFloor)) rescue_push(rsc, c, t.chain, t.p, t.block);
         blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log((double)hv);
     }
 }
 
-// ---- FP64 circulant on the FP64 matrix cores -------------------------------------------------
-//
-// v_mfma_f64_16x16x4_f64 reads A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k, and
-// leaves D[i][j] in lane j + 16 (i mod 4), register i / 4 (checked on the device). A 32 x 32
-// matrix in that accumulator layout is four 16 x 16 tiles (I, J), tile index 2 I + J; element
-// (16 I + 4 r + lane / 16, 16 J + lane % 16) sits in register r of tile (I, J). Register r of
-// tile (K, I) is then directly the A operand of X^T with K-index 16 K + 4 r + lane / 16, so
-//   (X^T C)(I, J) = sum over K, r of mfma(X(K, I)[r], Cb[(4 K + r) * 2 + J])
-// with Cb the matching B operands of the circulant C[k][j] = g((k - j) mod L) (zero outside
-// L x L): 32 products per multiplication, no operand splitting, every product and sum in FP64.
-// Two multiplications give (F^T C)^T C = C F C, C being symmetric.
-typedef __attribute__((ext_vector_type(4))) double f64x4;
-
-struct Tile64 {
-    f64x4 t[4];
-};
-
-__device__ inline Tile64 circ64(const Tile64& X, const double (&Cb)[16]) {
-    Tile64 Y;
-#pragma unroll
-    for (int I = 0; I < 2; ++I)
-#pragma unroll
-        for (int J = 0; J < 2; ++J) {
-            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int K = 0; K < 2; ++K)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X.t[2 * K + I][r],
-                                                               Cb[(4 * K + r) * 2 + J], acc, 0, 0, 0);
-            Y.t[2 * I + J] = acc;
-        }
-    return Y;
-}
-
-__device__ inline double wave_sum_f64(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+// ---- FP64 circulant on the FP64 matrix cores (fh_dmfma.h) ----------------------------------
 
 // One wavefront per (chain, worldline, block) of an FP64 plan with L <= 32: the forward
 // recursion of one block with the FP64 circulant,
@@ -328,65 +296,26 @@ __global__ __launch_bounds__(kThreads) void k_forward_dmfma(
     double Cb[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) Cb[q] = cmat64[((int64_t)t.chain * 16 + q) * 64 + lane];
-    const int xl = lane & 15, yl = lane >> 4;
-    // element (tile q, register r): x = 16 (q & 1) + xl, y = 16 (q >> 1) + 4 r + yl
-    auto xo = [&](int q) { return 16 * (q & 1) + xl; };
-    auto yo = [&](int q, int r) { return 16 * (q >> 1) + 4 * r + yl; };
-    auto inside = [&](int q, int r) { return xo(q) < L && yo(q, r) < L; };
-    const int ax = a % L, ay = a / L;
-    Tile64 F;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) F.t[q][r] = (xo(q) == ax && yo(q, r) == ay) ? 1.0 : 0.0;
-    double la = coef * aux[c.aux_off + (int64_t)start * N + a];
+    const double la = coef * aux[c.aux_off + (int64_t)start * N + a];
     double* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
-    for (int j = 1; j < len; ++j) {
-        const int l = (start + j) % L_tau;
+    auto wtab = [&](int l, double (&w)[16]) {
         const double* Wl = Wsp + (int64_t)l * N;
-        double w[16];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)  // a padded position reads site 0 (in bounds), times 0
-                w[4 * q + r] = Wl[inside(q, r) ? yo(q, r) * L + xo(q) : 0];
-        const Tile64 H = circ64(circ64(F, Cb), Cb);
-        double sum = 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                F.t[q][r] = H.t[q][r] * w[4 * q + r];
-                sum += F.t[q][r];
+            for (int r = 0; r < 4; ++r) {  // a padded position reads site 0 (in bounds), times 0
+                const int x = t64_x(q, lane), y = t64_y(q, r, lane);
+                w[4 * q + r] = Wl[(x < L && y < L) ? y * L + x : 0];
             }
-        const double tot = wave_sum_f64(sum);
-        if (!(tot > 0.0) || !isfinite(tot))
-            if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
-        const double inv = 1.0 / tot;
-        la += log(tot) + shift[l];
-        double* row = rows + (int64_t)(j - 1) * N;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                F.t[q][r] *= inv;
-                if (inside(q, r)) row[yo(q, r) * L + xo(q)] = F.t[q][r];
-            }
-    }
-    // end weight (C f~ C)(e)
-    const Tile64 H = circ64(circ64(F, Cb), Cb);
-    const int ex = e % L, ey = e / L;
-    const int qe2 = 2 * (ey >> 4) + (ex >> 4), re = (ey & 15) >> 2;
-    double hv = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (q == qe2 && r == re) hv = H.t[q][r];
-    hv = __shfl(hv, (ex & 15) + 16 * (ey & 3), 64);
+    };
+    auto put = [&](int j, int q, int r, double v) {
+        rows[(int64_t)(j - 1) * N + t64_y(q, r, lane) * L + t64_x(q, lane)] = v;
+    };
+    bool ok = true;
+    const double lz = dmfma_block_forward(Cb, L, L_tau, start, len, a, e, la, shift, wtab, put, &ok);
     if (lane == 0) {
-        if (!(hv > 0.0)) set_status(status, FH_ERR_NONFINITE, t.chain);
-        blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log(hv);
+        if (!ok) set_status(status, FH_ERR_NONFINITE, t.chain);
+        blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = lz;
     }
 }
 
@@ -406,7 +335,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
     double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    const NegPairs neg) {
+    const Rescue rsc, const NegPairs neg) {
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
@@ -456,24 +385,28 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
 #pragma unroll
         for (int v = 0; v < 16; ++v) dst[v] = Wl[inside(v) ? lane_off + vrow(v) * L : 0];
     };
+    // rows hold f~ 2^row_exp (the FP32 range scaling), from f_0 = 2^row_exp delta_a on
+    const float sc = ldexpf(1.0f, c.row_exp);
+    const double lsc = c.row_exp * 0.69314718055994530942;
     f32x16 F0, F1;
     {
         const int ax0 = a[0] % L, ay0 = a[0] / L, ax1 = a[1] % L, ay1 = a[1] / L;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int y = tile_row(lane, v);
-            F0[v] = (x == ax0 && y == ay0) ? 1.0f : 0.0f;
-            F1[v] = (x == ax1 && y == ay1) ? 1.0f : 0.0f;
+            F0[v] = (x == ax0 && y == ay0) ? sc : 0.0f;
+            F1[v] = (x == ax1 && y == ay1) ? sc : 0.0f;
         }
     }
-    double la0 = coef * (double)aux[c.aux_off + (int64_t)start * N + a[0]];
-    double la1 = coef * (double)aux[c.aux_off + (int64_t)start * N + a[1]];
+    double la0 = coef * (double)aux[c.aux_off + (int64_t)start * N + a[0]] - lsc;
+    double la1 = coef * (double)aux[c.aux_off + (int64_t)start * N + a[1]] - lsc;
     double prod0 = 1.0, prod1 = 1.0;
     const int64_t rowoff = (int64_t)t.block * (c.B - 1);
     float* rows0 = filt + c.filt_off + ((int64_t)pp[0] * L_tau + rowoff) * N;
     float* rows1 = filt + c.filt_off + ((int64_t)pp[1] * L_tau + rowoff) * N;
     float wn[16];
     load_w((start + 1) % L_tau, wn);
+    bool low0 = false, low1 = false;  // a worldline left FP32's range: FP64 re-filter
     // One step: uses wn (this slice's W) and refills it with the next slice's W before the
     // stores. The first step is peeled off the loop so that on entry to the loop, as on every
     // later pass, the stores of the previous step sit between wn's loads and their use, and the
@@ -497,8 +430,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
         load_w((l + 1) % L_tau, wn);
         __builtin_amdgcn_sched_barrier(0);
         const float tot0 = wave_sum_f32(s0), tot1 = wave_sum_f32(s1);
-        if (!(tot0 > 0.0f) || !isfinite(tot0) || !(tot1 > 0.0f) || !isfinite(tot1))
-            if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
+        low0 = low0 || !(tot0 >= c.step_floor) || !isfinite(tot0);
+        low1 = low1 || !(tot1 >= c.step_floor) || !isfinite(tot1);
         // f~_j = h_j * inv: the normaliser applied is exactly 1/inv (see k_forward_mfma)
         const float inv0 = __builtin_amdgcn_rcpf(tot0), inv1 = __builtin_amdgcn_rcpf(tot1);
         prod0 *= (double)inv0;
@@ -511,15 +444,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
             la1 -= log(prod1);
             prod1 = 1.0;
         }
-        const double m = shift[l];
+        const double m = shift[l] - lsc;
         la0 += m;
         la1 += m;
+        const float k0 = inv0 * sc, k1 = inv1 * sc;
         float* row0 = rows0 + (int64_t)(j - 1) * N + lane_off;
         float* row1 = rows1 + (int64_t)(j - 1) * N + lane_off;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            F0[v] *= inv0;
-            F1[v] *= inv1;
+            F0[v] *= k0;
+            F1[v] *= k1;
             if (inside(v)) {
                 __builtin_nontemporal_store(F0[v], row0 + vrow(v) * L);
                 __builtin_nontemporal_store(F1[v], row1 + vrow(v) * L);
@@ -550,7 +484,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     la0 -= log(prod0);
     la1 -= log(prod1);
     if (lane == 0) {
-        if (!(hv0 > 0.0f) || !(hv1 > 0.0f)) set_status(status, FH_ERR_NONFINITE, t.chain);
+        if (low0 || !(hv0 >= kRangeFloor)) rescue_push(rsc, c, t.chain, pp[0], t.block);
+        if (has_b && (low1 || !(hv1 >= kRangeFloor)))
+            rescue_push(rsc, c, t.chain, pp[1], t.block);
         blk_logz[c.blk_off + (int64_t)pp[0] * c.nb + t.block] = la0 + log((double)hv0);
         if (has_b) blk_logz[c.blk_off + (int64_t)pp[1] * c.nb + t.block] = la1 + log((double)hv1);
     }
@@ -600,7 +536,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
     double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    const NegPairs neg) {
+    const Rescue rsc, const NegPairs neg) {
     constexpr int L = 64, N = 4096;
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
@@ -648,6 +584,9 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
 #pragma unroll
                 for (int v = 0; v < 16; ++v) dst[R][S][v] = Wl[32 * (R * L + S) + vrow(v) * L];
     };
+    // rows hold f~ 2^row_exp (the FP32 range scaling), from f_0 = 2^row_exp delta_a on
+    const float sc = ldexpf(1.0f, c.row_exp);
+    const double lsc = c.row_exp * 0.69314718055994530942;
     f32x16 F[2][2];
     {
         const int ax = a % L, ay = a / L;
@@ -657,15 +596,16 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
             for (int S = 0; S < 2; ++S)
 #pragma unroll
                 for (int v = 0; v < 16; ++v)
-                    F[R][S][v] = (32 * S + x == ax && 32 * R + tile_row(lane, v) == ay) ? 1.0f : 0.0f;
+                    F[R][S][v] = (32 * S + x == ax && 32 * R + tile_row(lane, v) == ay) ? sc : 0.0f;
     }
-    double la = coef * (double)aux[c.aux_off + (int64_t)start * N + a];
+    double la = coef * (double)aux[c.aux_off + (int64_t)start * N + a] - lsc;
     double prod = 1.0;
     float* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
     // W of the next slice is loaded before this slice's stores (loads and stores retire in
     // order), so its wait one step later does not wait for them
     float wn[2][2][16];
     load_w((start + 1) % L_tau, wn);
+    bool low = false;  // the block left FP32's range (the FP64 re-filter takes L <= 32 only)
     for (int j = 1; j < len; ++j) {
         const int l = (start + j) % L_tau;
         f32x16 X[2][2], H[2][2];
@@ -684,8 +624,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
         load_w((l + 1) % L_tau, wn);  // the last step fetches a slice it does not use
         __builtin_amdgcn_sched_barrier(0);
         const float tot = wave_sum_f32(s);
-        if (!(tot > 0.0f) || !isfinite(tot))
-            if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
+        low = low || !(tot >= c.step_floor) || !isfinite(tot);
         // f~_j = h_j * inv: the normaliser applied is exactly 1/inv (see k_forward_mfma)
         const float inv = __builtin_amdgcn_rcpf(tot);
         prod *= (double)inv;
@@ -693,7 +632,8 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
             la -= log(prod);
             prod = 1.0;
         }
-        la += shift[l];
+        la += shift[l] - lsc;
+        const float k = inv * sc;
         float* row = rows + (int64_t)(j - 1) * N + lane_off;
 #pragma unroll
         for (int R = 0; R < 2; ++R)
@@ -701,7 +641,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
             for (int S = 0; S < 2; ++S)
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
-                    F[R][S][v] *= inv;
+                    F[R][S][v] *= k;
                     __builtin_nontemporal_store(F[R][S][v], row + 32 * (R * L + S) + vrow(v) * L);
                 }
     }
@@ -723,7 +663,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
     hv = __shfl(hv, tx + 32 * ((ty >> 2) & 1), 64);
     la -= log(prod);
     if (lane == 0) {
-        if (!(hv > 0.0f)) set_status(status, FH_ERR_NONFINITE, t.chain);  // end weight underflowed
+        if (low || !(hv >= kRangeFloor)) rescue_push(rsc, c, t.chain, t.p, t.block);
         blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log((double)hv);
     }
 }
@@ -776,7 +716,7 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
     double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    const NegPairs neg) {
+    const Rescue rsc, const NegPairs neg) {
     constexpr int BS = 32 / P;   // block side
     constexpr int PP = P * P;    // worldlines per tile
     constexpr int RPB = 16 / P;  // registers of one block row band per lane
@@ -820,6 +760,9 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
         filt + c.filt_off, (short)0, 0x7fffffff, kBufferWord3);
     uint32_t off[NT][P];
     bool ok[NT][P];
+    // rows hold f~ 2^row_exp (the FP32 range scaling), from f_0 = 2^row_exp delta_a on
+    const float sc = ldexpf(1.0f, c.row_exp);
+    const double lsc = c.row_exp * 0.69314718055994530942;
     f32x16 F[NT];
 #pragma unroll
     for (int T = 0; T < NT; ++T)
@@ -832,7 +775,7 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
             const int ax = a % L, ay = a / L;
 #pragma unroll
             for (int v = I * RPB; v < (I + 1) * RPB; ++v)
-                F[T][v] = (lx == ax && 4 * hl + cv(v) == ay) ? 1.0f : 0.0f;
+                F[T][v] = (lx == ax && 4 * hl + cv(v) == ay) ? sc : 0.0f;
             off[T][I] = (uint32_t)((((int64_t)pw * L_tau + rowoff) * N + 4 * hl * L + lx) * 4);
             ok[T][I] = s < t.n && lx < L;
         }
@@ -853,7 +796,7 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
             set_status(status, FH_ERR_BAD_PATH, t.chain);
             oe = (oe < 0 || oe >= N) ? 0 : oe;
         } else {
-            la = coef * (double)aux[c.aux_off + (int64_t)start * N + a];
+            la = coef * (double)aux[c.aux_off + (int64_t)start * N + a] - lsc;
         }
     }
     auto inside = [&](int v) { return lx < L && 4 * hl + cv(v) < L; };
@@ -863,7 +806,7 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
 #pragma unroll
         for (int v = 0; v < 16; ++v) dst[v] = inside(v) ? Wl[cv(v) * L] : Wsp[(int64_t)l * N];
     };
-    bool bad = false;
+    bool low = false;  // the owner's worldline left FP32's range: FP64 re-filter
     float wn[16];
     load_w((start + 1) % L_tau, wn);
     auto step = [&](int j) {
@@ -887,29 +830,30 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
             }
         load_w((l + 1) % L_tau, wn);  // the last step fetches a slice it does not use
         __builtin_amdgcn_sched_barrier(0);
-        float inv[NT][P], mine = 1.0f;
+        float inv[NT][P], mine = 1.0f, mtot = 1.0f;
 #pragma unroll
         for (int T = 0; T < NT; ++T)
 #pragma unroll
             for (int I = 0; I < P; ++I) {
                 const float tot = block_sum<BS>(sm[T][I]);
-                bad = bad || !(tot > 0.0f && tot <= 3.402823466e38f);
                 // f~_j = h_j * inv: the normaliser applied is exactly 1/inv
                 inv[T][I] = __builtin_amdgcn_rcpf(tot);
                 mine = oti == T * P + I ? inv[T][I] : mine;
+                mtot = oti == T * P + I ? tot : mtot;
             }
+        low = low || !(mtot >= c.step_floor && mtot <= 3.402823466e38f);
         // log Z -= log(inv): FP64 mantissa times 2^ex2, renormalised every step
         mant *= (double)mine;
         int e;
         mant = frexp(mant, &e);
         ex2 += e;
-        la += shift[l];
+        la += shift[l] - lsc;
         // byte offsets: lane part in a VGPR, row and register part in an SGPR
         const int rowj = (j - 1) * N;
 #pragma unroll
         for (int v = 0; v < 16; ++v)
 #pragma unroll
-            for (int T = 0; T < NT; ++T) F[T][v] *= inv[T][v / RPB];
+            for (int T = 0; T < NT; ++T) F[T][v] *= inv[T][v / RPB] * sc;
         if (full) {
 #pragma unroll
             for (int v = 0; v < 16; ++v)
@@ -947,9 +891,8 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
             const float h = __shfl(H[T][v], src, 64);
             if (v == ve && T == oT) hv = h;
         }
-    if (bad) set_status(status, FH_ERR_NONFINITE, t.chain);
     if (owner) {
-        if (!(hv > 0.0f)) set_status(status, FH_ERR_NONFINITE, t.chain);  // end weight underflowed
+        if (low || !(hv >= kRangeFloor)) rescue_push(rsc, c, t.chain, t.p0 + os, t.block);
         const double lz = la - (log(mant) + (double)ex2 * 0.69314718055994530942) + log((double)hv);
         blk_logz[c.blk_off + (int64_t)(t.p0 + os) * c.nb + t.block] = lz;
     }
@@ -1426,7 +1369,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
                            p->d.fwd32_tasks, p->n_fwd32_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
-                           kNegPairs);
+                           rescue_args(p), kNegPairs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1436,7 +1379,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
                            p->d.fwdx_tasks, p->n_fwdx_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
-                           kNegPairs);
+                           rescue_args(p), kNegPairs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1446,7 +1389,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
                            p->d.fwd64_tasks, p->n_fwd64_tasks, p->d.cmatb, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
-                           kNegPairs);
+                           rescue_args(p), kNegPairs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1457,7 +1400,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
                            p->d.fwdp_tasks, p->n_fwdp2_tasks, p->d.cmatp, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
-                           kNegPairs);
+                           rescue_args(p), kNegPairs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1467,7 +1410,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
                            p->d.fwdp_tasks + p->n_fwdp2_tasks, p->n_fwdp4_tasks, p->d.cmatp,
                            (const float*)aux, (const float*)p->d.W, p->d.wshift, p->aux_elems,
                            p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
-                           p->d.sweep, p->d.status, kNegPairs);
+                           p->d.sweep, p->d.status, rescue_args(p), kNegPairs);
     }
     return hipGetLastError();
 }

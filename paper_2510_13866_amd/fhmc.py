@@ -104,6 +104,8 @@ _sig("fh_debug_inflate_window_bound", c_int32, c_void_p, c_double)
 _sig("fh_debug_backward_kernels", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32))
 _sig("fh_debug_forward_kernels", c_int32, c_void_p, POINTER(c_int32))
 _sig("fh_debug_backward_adapt", c_int32, c_void_p, c_int32, POINTER(c_int32))
+_sig("fh_debug_rescue", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int64),
+     POINTER(c_int32), c_int32)
 
 
 class FhError(RuntimeError):
@@ -255,3 +257,16 @@ def fh_get_radix_plan(plan, chain):
 
 def fh_strerror(code):
     return lib.fh_strerror(int(code)).decode()
+
+
+def fh_debug_rescue(plan, cap=0):
+    """(queued blocks of the last forward pass incl. its backward, blocks redrawn in FP64 since
+    the previous call, [(chain, particle, block)] of the first `cap` queued blocks, chains
+    queued whole)."""
+    import numpy as np
+    last, whole, total = c_int32(), c_int32(), c_int64()
+    buf = np.zeros((max(cap, 1), 3), dtype=np.int32)
+    _check(lib.fh_debug_rescue(plan, byref(last), byref(whole), byref(total),
+                               buf.ctypes.data_as(POINTER(c_int32)), cap), "fh_debug_rescue")
+    n = min(cap, last.value)
+    return last.value, total.value, [tuple(int(v) for v in buf[i]) for i in range(n)], whole.value
