@@ -2,18 +2,22 @@
 """Throughput of the FFBS worldline sweep on one MI355X: site-slice updates/s.
 
 Workload: 16 chains of a 32x32 periodic lattice, L_tau = 160 (beta = 8, dtau = 0.05), U = 4,
-512 + 512 worldlines per chain, Gaussian HS field; synthetic seeded inputs already resident
-in HBM. One step = one pass of the hot path over that batch: restore the resident input
-(device-to-device copy), then one full sweep (forward filter + backward sample of every
-worldline, then the Gibbs draw of every field value) of all 16 chains, replayed from a captured
-hipGraph. Restoring keeps every step on the same synthetic input: with the permutation fixed to
-the identity the worldlines are distinguishable and a long chain clusters, which changes no
-amount of work but would make later steps depend on the chain's history.
+512 + 512 worldlines per chain, Gaussian HS field, 500 sweeps; synthetic seeded inputs already
+resident in HBM. One step = one sweep of the chain as it runs (forward filter + backward sample
+of every worldline, then the Gibbs draw of every field value, for all 16 chains), replayed from
+a captured hipGraph, each sweep continuing from the state the previous one left. The warmup
+sweeps start from the initial state (the first one captures the graph); the timed sweeps carry
+the chain on, 500 sweeps in all by default. The chain clusters within a few sweeps (the
+worldlines are distinguishable while the permutation is the identity), so the timed sweeps
+include the transitional ones, whose out-of-range blocks the FP32 plan re-filters in FP64, and
+then the settled state; `per_sweep_ms` gives both parts, and the same chain is also run at
+U = 2 and U = 6.
 
 Prints one JSON line. `roofline` is for the dominant kernel (the forward filter), timed with HIP
 events on the stream it runs on; `cpu_baseline` times the FP64 oracle on host cores on a
-bounded sample (one chain, six sweeps) and scales it to the same unit. `filter_err_vs_fp64_plain`
-compares the FP32 filters with the FP64 plain path's on the same GPU.
+bounded sample (one chain, six sweeps) and scales it to the same unit. `err_vs_fp64_plain`
+compares the FP32 plan's log Z and filters with the FP64 plain path's on the same GPU and the
+same states (the initial one and a transitional one).
 """
 import argparse
 import json
@@ -38,16 +42,16 @@ KERNEL_SOURCES = {"forward": {"fp32_mfma3": "fh_mfma.hip", "fp32": "fh_kernels.h
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=499)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp32_mfma3", choices=sorted(PRECISIONS))
     ap.add_argument("--chains", type=int, default=16)
     ap.add_argument("--U", type=float, default=4.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--no-error", action="store_true", help="skip the filter error sample against the FP64 plain path")
-    ap.add_argument("--no-evolved", action="store_true",
-                    help="skip the backward timings on the state after one unrestored sweep")
+    ap.add_argument("--no-other-u", action="store_true",
+                    help="skip the same chain at U = 2 and U = 6")
     ap.add_argument("--full-row-draw", action="store_true",
                     help="backward draws scan whole filter rows (FH_FLAG_FULL_ROW_DRAW)")
     ap.add_argument("--autotune", action="store_true",
@@ -92,22 +96,31 @@ def measured_traffic(kernel, precision, kernel_name):
     return None
 
 
-def time_sweeps(S, A, P, A0, P0, first, n, stream):
-    """n steps; a step restores the resident synthetic input (device-to-device copies of the
-    field and the worldlines, ~20 MB) and runs one full sweep of every chain."""
+def run_chain(S, A, P, first, n, stream):
+    """n consecutive sweeps (sweep indices first .. first + n - 1) continuing the chain in A, P,
+    with a HIP event after each; returns (total ms, [ms of each sweep])."""
     import torch
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
     torch.cuda.synchronize()
-    e0.record(stream)
+    ev[0].record(stream)
     with torch.cuda.stream(stream):
         for i in range(n):
-            A.copy_(A0, non_blocking=True)
-            P.copy_(P0, non_blocking=True)
             S.sweep(A, P, first + i, 1, stream)
-    e1.record(stream)
+            ev[i + 1].record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1)
+    each = [ev[i].elapsed_time(ev[i + 1]) for i in range(n)]
+    return ev[0].elapsed_time(ev[n]), each
+
+
+def chain_summary(each, warmup):
+    """Per-sweep figures of a timed chain: the first ten timed sweeps one by one, and the median
+    of the second half (the settled state)."""
+    import statistics
+    half = each[len(each) // 2:] or each
+    return {"first_timed_sweep_index": warmup,
+            "first_10_ms": [round(x, 3) for x in each[:10]],
+            "settled_median_ms": round(statistics.median(half), 4),
+            "max_ms": round(max(each), 3)}
 
 
 def time_forward(S, A, P, n, stream):
@@ -158,26 +171,43 @@ def copy_calibration(stream):
     del a, b
 
 
-def filter_error_vs_fp64_plain(S, descs, aux, paths, sweep, stream):
-    """Normwise relative error of the stored filters of 4 worldlines of chain 0 against the FP64
-    plain path's (an FP64 plan on the same GPU, same inputs and sweep; its own filters match the
-    FP64 oracle to 1e-11 in the parity tests): (max over rows, median over rows)."""
+def err_vs_fp64_plain(precision, descs, aux, paths, sweep, stream):
+    """The FP32 plan against the FP64 plain path (an FP64 plan on the same GPU; its filters match
+    the FP64 oracle to 1e-11 and its log Z to 1e-12 in the parity tests) on one state (aux as the
+    FP32 plan holds it, paths) and sweep index: the relative log Z error of every worldline, and
+    the normwise filter error of every stored row of 8 worldlines of chain 0, together with the
+    number of blocks the FP32 plan re-filtered in FP64 on that state."""
     import numpy as np
     import torch
     from paper_2510_13866_amd import fhmc
     from paper_2510_13866_amd.sampler import Sampler
+    out = {}
+    S32 = Sampler(descs, precision)
     S64 = Sampler(descs, fhmc.FH_FP64)
-    A, P = S64.pack_aux(aux), S64.pack_paths(paths)
-    fhmc.fh_forward_filter(S64.plan, A, P, sweep, None, stream)
-    torch.cuda.synchronize()
+    lz = []
+    for S in (S32, S64):
+        A, P = S.pack_aux(aux), S.pack_paths(paths)
+        t = S.forward_filter(A, P, sweep, stream)
+        torch.cuda.synchronize()   # the library wrote t on `stream`
+        lz.append(t.cpu().numpy())
+    rel = np.abs(lz[0] - lz[1]) / (1.0 + np.abs(lz[1]))
     errs = []
-    for p in (0, 255, 512, 1023):
+    for p in range(0, 1024, 128):
         ref = S64.filters(0, p)
-        got = S.filters(0, p)
-        errs.extend(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1))
-    S64.status()
-    S64.close()
-    return float(np.max(errs)), float(np.median(errs))
+        errs.extend(np.linalg.norm(S32.filters(0, p) - ref, axis=1) / np.linalg.norm(ref, axis=1))
+    queued, _, _, whole = fhmc.fh_debug_rescue(S32.plan)
+    for S in (S32, S64):
+        code, _ = S.status()
+        if code != 0:
+            raise RuntimeError("device status in the error sample: " + fhmc.fh_strerror(code))
+        S.close()
+    out["logz_err"] = {"max": float(rel.max()), "median": float(np.median(rel)),
+                       "worldlines": int(rel.size), "measure": "|dlogZ| / (1 + |logZ|)"}
+    out["filter_err"] = {"max": float(np.max(errs)), "median": float(np.median(errs)),
+                         "sample": "8 worldlines of chain 0, every stored row"}
+    out["blocks_refiltered_fp64"] = int(queued)
+    out["chains_refiltered_whole"] = int(whole)
+    return out
 
 
 def cpu_baseline(desc, aux, paths, n_sweeps=6):
@@ -260,8 +290,7 @@ def other_workload(args):
     log("bench: %s workload, %s, %d chains" % (args.workload, prec_name, len(descs)))
     flags = fhmc.FH_FLAG_GRAPH | (fhmc.FH_FLAG_AUTOTUNE if args.autotune else 0)
     S = Sampler(descs, prec, flags)
-    A0, P0 = S.pack_aux(aux), S.pack_paths(paths)
-    A, P = A0.clone(), P0.clone()
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
     torch.cuda.synchronize()
     extra = {}
     if args.autotune:  # the stage order chosen per lattice size
@@ -353,17 +382,13 @@ def other_workload(args):
                                            d.n_up + rng.permutation(d.n_dn)]) for d in descs])
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(stream):
+        with torch.cuda.stream(stream):  # one chain run on from the initial state
             for i in range(args.warmup):
-                A.copy_(A0, non_blocking=True)
-                P.copy_(P0, non_blocking=True)
                 S.sweep(A, P, i, 1, stream)
                 fhmc.fh_permutation_update(S.plan, P, i, 2, stream)
             torch.cuda.synchronize()
             e0.record(stream)
             for i in range(args.steps):
-                A.copy_(A0, non_blocking=True)
-                P.copy_(P0, non_blocking=True)
                 S.sweep(A, P, args.warmup + i, 1, stream)
                 fhmc.fh_permutation_update(S.plan, P, args.warmup + i, 2, stream)
             e1.record(stream)
@@ -375,12 +400,15 @@ def other_workload(args):
         unit = "site-slice updates/s"
         _, signs = S.permutation()
         extra["sign_sum"] = int(np.sum(signs))
-    else:
-        time_sweeps(S, A, P, A0, P0, 0, args.warmup, stream)
-        ms = time_sweeps(S, A, P, A0, P0, args.warmup, args.steps, stream)
+    else:  # one chain run on from the initial state: warmup sweeps, then the timed ones
+        run_chain(S, A, P, 0, args.warmup, stream)
+        fhmc.fh_debug_rescue(S.plan)
+        ms, each = run_chain(S, A, P, args.warmup, args.steps, stream)
         metric = "site-slice updates/s (%s)" % args.workload
         value = sites * args.steps / (ms / 1e3)
         unit = "site-slice updates/s"
+        extra["per_sweep_ms"] = chain_summary(each, args.warmup)
+        extra["blocks_redrawn_fp64"] = int(fhmc.fh_debug_rescue(S.plan)[1])
     code, _ = S.status()
     if code != 0:
         raise RuntimeError("device status: " + fhmc.fh_strerror(code))
@@ -422,30 +450,53 @@ def main():
         copy_calibration(stream)
     sites = sum(d.N * d.L_tau for d in descs)
 
-    log("bench: %s, %d chains 32x32 L_tau=160, warmup %d, steps %d" %
+    log("bench: %s, %d chains 32x32 L_tau=160, warmup %d, steps %d (one chain run on)" %
         (args.precision, args.chains, args.warmup, args.steps))
     draw_flag = fhmc.FH_FLAG_FULL_ROW_DRAW if args.full_row_draw else 0
-    S = Sampler(descs, prec, fhmc.FH_FLAG_GRAPH | draw_flag)
-    A0, P0 = S.pack_aux(aux), S.pack_paths(paths)
-    A, P = A0.clone(), P0.clone()
-    torch.cuda.synchronize()
-    time_sweeps(S, A, P, A0, P0, 0, args.warmup, stream)
-    ms = time_sweeps(S, A, P, A0, P0, args.warmup, args.steps, stream)
-    code, _ = S.status()
-    if code != 0:
-        raise RuntimeError("device status after sweeps: " + fhmc.fh_strerror(code))
+
+    def chain(U, precision, flags, warmup, steps):
+        """The headline chain at coupling U: warmup sweeps from the initial state, then `steps`
+        timed sweeps continuing it; the status is checked after the timed sweeps."""
+        ds = synth.config_32x32(U, n_chains=args.chains)
+        S = Sampler(ds, precision, fhmc.FH_FLAG_GRAPH | flags)
+        A = S.pack_aux([synth.initial_aux(d) for d in ds])
+        P = S.pack_paths([synth.initial_paths(d) for d in ds])
+        run_chain(S, A, P, 0, warmup, stream)
+        fhmc.fh_debug_rescue(S.plan)  # restart the count of FP64-redrawn blocks
+        ms, each = run_chain(S, A, P, warmup, steps, stream)
+        code, _ = S.status()
+        if code != 0:
+            raise RuntimeError("device status after the timed sweeps (U=%g): %s" %
+                               (U, fhmc.fh_strerror(code)))
+        _, redrawn, last, _ = fhmc.fh_debug_rescue(S.plan, cap=1 << 20)
+        per_chain = [0] * len(ds)
+        for (c, _, _) in last:
+            per_chain[c] += 1
+        log("  U=%g: blocks queued for FP64 in the last sweep, per chain: %s" % (U, per_chain))
+        return S, A, P, ms, each, redrawn
+
+    S, A, P, ms, each, redrawn = chain(args.U, prec, draw_flag, args.warmup, args.steps)
     ms_step = ms / args.steps
     value = sites * args.steps / (ms / 1e3)
-    log("  %.3f ms/sweep, %.3e site-slice updates/s" % (ms_step, value))
+    n_blocks = sum(d.n_particles for d in descs) * args.steps
+    log("  %.3f ms/sweep, %.3e site-slice updates/s; blocks redrawn in FP64: %d of %d" %
+        (ms_step, value, redrawn, n_blocks))
+    extra = {"per_sweep_ms": chain_summary(each, args.warmup),
+             "blocks_redrawn_fp64": {"count": int(redrawn), "of": int(n_blocks)}}
+    log("  per sweep: %s" % extra["per_sweep_ms"])
 
-    # the two hot kernels, each timed alone on its stream; both move the spilled filters:
-    # the forward filter writes every filter row once, the backward sampler reads it once
+    # the two hot kernels, each timed alone on its stream: the forward filter (whose work does
+    # not depend on the state) on the initial state, where no block needs the FP64 re-filter,
+    # and the backward sampler on the state the chain reached; the forward writes every filter
+    # row once, the backward reads what its draws need
     nf = max(3, min(10, args.steps))
-    with torch.cuda.stream(stream):   # the state every timed sweep starts from
-        A.copy_(A0, non_blocking=True)
-        P.copy_(P0, non_blocking=True)
-    fwd_ms = time_forward(S, A, P, nf, stream)
-    bwd_ms = time_backward(S, A, P, nf, stream)
+    Ae, Pe = A.clone(), P.clone()
+    S0 = Sampler(descs, prec, draw_flag)
+    fwd_ms = time_forward(S0, S0.pack_aux(aux), S0.pack_paths(paths), nf, stream)
+    if fhmc.fh_debug_rescue(S0.plan)[0] != 0:
+        raise RuntimeError("the forward timing's state needed the FP64 re-filter")
+    S0.close()
+    bwd_ms = time_backward(S, Ae, Pe, nf, stream)
     rsz = 8 if args.precision == "fp64" else 4
     rows = sum(d.n_particles * (d.L_tau - 1) for d in descs)       # one block per worldline
     N = descs[0].N
@@ -468,7 +519,8 @@ def main():
                     "frac": round(gbs / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic(k, args.precision, names[k].split("(")[1][:-1]),
                     "kernel": names[k], "ms_per_launch": round(times[k], 4),
-                    "algorithmic_bytes_per_launch": algo[k]}
+                    "algorithmic_bytes_per_launch": algo[k],
+                    "state": "initial" if k == "forward" else "after the timed sweeps"}
         log("  %s %.3f ms/launch, %.0f GB/s algorithmic" % (names[k], times[k], gbs))
     if args.precision == "fp32_mfma3":
         # the same forward launch against the matrix cores: 24 bf16 MFMA 32x32x16 per
@@ -498,70 +550,56 @@ def main():
             "frac": round(tf / FP32_VECTOR_PEAK_TFS, 4), "flops_per_launch": flops, "dtype": "f32"}
     dominant = "forward" if fwd_ms >= bwd_ms else "backward"
     roof = roofs[dominant]
-
-    extra = {}
-    if not args.full_row_draw and not args.no_evolved:
-        # The windowed draws cost depends on the state: after one sweep left to run on (no
-        # restore), the fields have started to cluster and more draws need the wider window or
-        # the full row. Both backward kernels, timed on that same state.
-        with torch.cuda.stream(stream):
-            A.copy_(A0, non_blocking=True)
-            P.copy_(P0, non_blocking=True)
-            S.sweep(A, P, 5, 1, stream)
-        torch.cuda.synchronize()
-        S.status()   # FP32 filters may underflow on this state; only the timing is used
-        Sf = Sampler(descs, prec, fhmc.FH_FLAG_FULL_ROW_DRAW)
-        Ae, Pe = A.clone(), P.clone()
-        # the plan as built (per-chain switch between the windowed and full-row kernels), the
-        # windowed kernel alone, and the full-row kernel alone; each the average over nf
-        # backward passes of the same state
-        adapt_ms = time_backward(S, A.clone(), P.clone(), nf, stream, sweep=6)
-        assert fhmc.lib.fh_debug_backward_adapt(S.plan, 0, None) == 0
-        win_ms = time_backward(S, A.clone(), P.clone(), nf, stream, sweep=6)
-        assert fhmc.lib.fh_debug_backward_adapt(S.plan, 1, None) == 0
-        full_ms = time_backward(Sf, Ae, Pe, nf, stream, sweep=6)
-        Sf.close()
-        S.status()
-        extra["backward_after_one_unrestored_sweep"] = {
-            "adaptive_ms": round(adapt_ms, 4), "k_backward_win_only_ms": round(win_ms, 4),
-            "k_backward_l32_only_ms": round(full_ms, 4), "passes_averaged": nf}
-        log("  after one unrestored sweep: adaptive %.3f ms, k_backward_win only %.3f ms, "
-            "k_backward_l32 only %.3f ms" % (adapt_ms, win_ms, full_ms))
-    if not args.no_error:
-        # the resident input again (the timed steps restore it too), filtered by both plans
-        A2, P2 = S.pack_aux(aux), S.pack_paths(paths)
-        fhmc.fh_forward_filter(S.plan, A2, P2, 1, None, stream)
-        torch.cuda.synchronize()
-        emax, emed = filter_error_vs_fp64_plain(S, descs, aux, paths, 1, stream)
-        extra["filter_err_vs_fp64_plain"] = {"max": emax, "median": emed,
-                                             "sample": "4 worldlines of chain 0, all 159 rows"}
-        log("  filter error vs the FP64 plain path: max %.2e median %.2e" % (emax, emed))
     S.close()
 
+    if not args.no_other_u:
+        for U in (2.0, 4.0, 6.0):
+            if U == args.U:
+                continue
+            So, _, _, msu, eachu, redu = chain(U, prec, draw_flag, args.warmup, args.steps)
+            So.close()
+            extra["U=%g" % U] = {"ms_per_step": round(msu / args.steps, 4),
+                                 "value": sites * args.steps / (msu / 1e3),
+                                 "per_sweep_ms": chain_summary(eachu, args.warmup),
+                                 "blocks_redrawn_fp64": int(redu)}
+            log("  U=%g: %.3f ms/sweep" % (U, msu / args.steps))
+    if not args.no_error and args.precision != "fp64":
+        # the FP32 plan against the FP64 plain path on the initial state and on the state after
+        # two sweeps of the FP32 chain (a transitional one)
+        Sx = Sampler(descs, prec, fhmc.FH_FLAG_GRAPH)
+        Ax, Px = Sx.pack_aux(aux), Sx.pack_paths(paths)
+        errs = {"initial": err_vs_fp64_plain(prec, descs, Sx.unpack_aux(Ax), paths, 0, stream)}
+        run_chain(Sx, Ax, Px, 0, 2, stream)
+        errs["after_2_sweeps"] = err_vs_fp64_plain(prec, descs, Sx.unpack_aux(Ax),
+                                                   Sx.unpack_paths(Px), 2, stream)
+        Sx.close()
+        extra["err_vs_fp64_plain"] = errs
+        log("  error vs the FP64 plain path: %s" % errs)
+
     if not args.no_plain and args.precision != "fp64":
-        S64 = Sampler(descs, fhmc.FH_FP64, fhmc.FH_FLAG_GRAPH)
-        A06, P06 = S64.pack_aux(aux), S64.pack_paths(paths)
-        A6, P6 = A06.clone(), P06.clone()
-        torch.cuda.synchronize()
-        time_sweeps(S64, A6, P6, A06, P06, 0, 1, stream)
-        k = max(2, args.steps // 4)
-        ms64 = time_sweeps(S64, A6, P6, A06, P06, 1, k, stream) / k
+        S64, _, _, ms64, each64, _ = chain(args.U, fhmc.FH_FP64, 0, args.warmup, args.steps)
+        S64.close()
+        ms64 /= args.steps
         extra["fp64_plain"] = {"ms_per_step": round(ms64, 4),
                                "value": sites / (ms64 / 1e3),
+                               "per_sweep_ms": chain_summary(each64, args.warmup),
                                "convolution": "FP64 circulant on the matrix cores"}
         extra["speedup_vs_fp64_plain"] = round(ms64 / ms_step, 3)
-        S64.close()
         log("  fp64 plain %.3f ms/sweep" % ms64)
-        # the same FP64 sweep with FFT convolutions
-        S64 = Sampler(descs, fhmc.FH_FP64, fhmc.FH_FLAG_GRAPH | fhmc.FH_FLAG_FFT_CONV)
-        A06, P06 = S64.pack_aux(aux), S64.pack_paths(paths)
-        A6, P6 = A06.clone(), P06.clone()
-        torch.cuda.synchronize()
-        time_sweeps(S64, A6, P6, A06, P06, 0, 1, stream)
-        k = 2
-        ms64f = time_sweeps(S64, A6, P6, A06, P06, 1, k, stream) / k
-        extra["fp64_fft_plain"] = {"ms_per_step": round(ms64f, 4), "value": sites / (ms64f / 1e3)}
+        # the first sweep from the initial state with FFT convolutions in FP64: an FFT resolves a
+        # filter only to ~eps of its largest value, which the end weights of the chain's next
+        # sweeps fall below
+        S64 = Sampler(descs, fhmc.FH_FP64, fhmc.FH_FLAG_FFT_CONV)
+        Af, Pf = S64.pack_aux(aux), S64.pack_paths(paths)
+        run_chain(S64, Af.clone(), Pf.clone(), 0, 1, stream)   # module load, untimed
+        ms64f, _ = run_chain(S64, Af, Pf, 0, 1, stream)
+        code, _ = S64.status()
         S64.close()
+        if code != 0:
+            raise RuntimeError("device status of the FP64 FFT sweep: " + fhmc.fh_strerror(code))
+        extra["fp64_fft_plain"] = {"ms_per_step": round(ms64f, 4),
+                                   "value": sites / (ms64f / 1e3),
+                                   "sweeps": "the first sweep from the initial state"}
         log("  fp64 FFT plain %.3f ms/sweep" % ms64f)
 
     cpu = None
@@ -583,7 +621,9 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": "FFBS sweep, %d chains x 32x32 lattice, L_tau=160, dtau=0.05, "
-                               "U=%g, 512+512 worldlines, Gaussian field" % (args.chains, args.U),
+                               "U=%g, 512+512 worldlines, Gaussian field, %d consecutive sweeps "
+                               "from the initial state (%d untimed)" %
+                               (args.chains, args.U, args.warmup + args.steps, args.warmup),
                    "chains": args.chains, "L": 32, "L_tau": 160, "precision": args.precision,
                    "graph": True,
                    "backward_draw": "full row" if args.full_row_draw else "window"},

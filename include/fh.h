@@ -74,9 +74,12 @@ enum fh_precision {
 /* Range of the FP32 plans. A filter row is normalised to sum 1; FP32 holds its values to full
  * relative precision only down to ~2^-110 (bf16 splitting) or ~2^-126. Strong, clustered fields
  * push the part of a row that a block's draws need below that (block end weights of 2^-160 and
- * less occur on the way to clustered states). Both FP32 plans therefore queue every block whose
- * forward step total, end weight or backward draw total falls below 2^-100 of its row's mass,
- * and redo it in FP64: the forward recursion on the FP64 circulant with W computed in FP64 from
+ * less occur on the way to clustered states). Both FP32 plans therefore hold W and the filter
+ * rows scaled high in FP32's range, queue every block whose forward step loses nearly all its
+ * mass to the weights (below 2^-196 of it), whose end weight falls below 2^-110 of the row mass
+ * or whose backward draw picks a site with a filter value below that, queue every block of a
+ * chain that has a queued block (in that pass and the next two), and redo the
+ * queued blocks in FP64: the forward recursion on the FP64 circulant with W computed in FP64 from
  * the field (its log Z replaces the FP32 one, its rows rounded to FP32 replace the stored rows),
  * and, in fh_backward_sample and fh_sweep, the block's draws from the FP64 rows with the same
  * rule and uniforms as an FH_FP64 plan. Only chains with L <= 32 have this FP64 re-filter; a

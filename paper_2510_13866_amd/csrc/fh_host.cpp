@@ -161,9 +161,11 @@ int validate(const fh_chain_desc& d, int precision) {
 }
 
 // FP32 range parameters of a chain (see kRangeFloor): rows scaled by 2^row_exp, lowered from
-// kRowExp when the kernel's mass sum G = exp(4 t dtau) exceeds 2^6, so that W~ 2^60 times a
-// row of mass 2^row_exp stays below 2^126; the step floor is 2^-160 of a step's unweighted mass.
+// kRowExp when the kernel's mass sum G = exp(4 t dtau) exceeds 2^6, so that W~ 2^100 times a
+// row of mass 2^row_exp stays below 2^126; the step floor is 2^-196 of a step's unweighted
+// mass; a chain is queued whole when any of its blocks is queued.
 void set_range(ChainInfo& ci, double t, double dtau, bool fp32) {
+    ci.whole_min = 0;
     if (!fp32) {
         ci.row_exp = 0;
         ci.row_mass = 1.0;
@@ -174,7 +176,7 @@ void set_range(ChainInfo& ci, double t, double dtau, bool fp32) {
     ci.row_exp = kRowExp - std::max(0, (int)ceil(lsum) - 6);
     if (ci.row_exp < 0) ci.row_exp = 0;
     ci.row_mass = ldexp(1.0, ci.row_exp);
-    ci.step_floor = (float)ldexp(exp(4.0 * t * dtau), ci.row_exp + kWScaleLog2 - 160);
+    ci.step_floor = (float)ldexp(exp(4.0 * t * dtau), ci.row_exp + kWScaleLog2 - 196);
 }
 
 template <typename T>
@@ -186,7 +188,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
                     d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
-                    d.rescue, d.rescue_list, d.rescue_ws, d.status, d.sweep};
+                    d.rescue, d.rescue_list, d.rescue_ws, d.rescue_w, d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     d = fh::Device();
@@ -483,6 +485,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         if (e == hipSuccess) e = dalloc(&dv.rescue_list, sizeof(DrawTask) * draw.size());
         if (e == hipSuccess)
             e = dalloc(&dv.rescue_ws, sizeof(double) * (size_t)p->n_rescue_slots * p->rescue_slot_elems);
+        if (e == hipSuccess) e = dalloc(&dv.rescue_w, sizeof(double) * 2 * (size_t)aux);
     }
     if (e == hipSuccess) e = dalloc(&dv.status, sizeof(int32_t) * 2);
     if (e == hipSuccess) e = dalloc(&dv.bw_state, sizeof(int32_t) * (kBwCounts + (size_t)n_chains));

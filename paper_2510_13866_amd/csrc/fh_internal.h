@@ -41,6 +41,7 @@ struct ChainInfo {
     int32_t row_exp;
     float step_floor;
     double row_mass;
+    int32_t whole_min;  // queued blocks of one pass above which the whole chain is queued
 };
 
 // Offsets of the tables of one chain inside the double table buffer, relative to tab_off.
@@ -89,20 +90,25 @@ struct GroupTask {
 };
 
 // FP32 range. FP32 holds a value to full relative precision only down to ~2^-126, and the
-// three-term bf16 split of the matrix-core forward only down to ~2^-110, while the filter rows
-// of strongly clustered fields span far more than that. The FP32 plans therefore place both
+// three-term bf16 split of the matrix-core forward only down to ~2^-110, while the weights of
+// strongly clustered fields span far more than that. The FP32 plans therefore place both
 // operands of the weight multiply high in FP32's range: W tables hold W~ 2^kWScaleLog2
-// (W~ = W / max_r W of the slice, so the table's largest entry is 2^60 and W~ down to 2^-186 is
-// representable), and forward rows hold f~ 2^row_exp (row mass 2^60, values down to 2^-170 of
-// the mass split exactly). A block is queued for the FP64 re-filter and redraw (k_rescue) when
-// what its draws need approaches the floor: a forward step whose W-weighted mass is below
-// 2^-160 of its unweighted mass (step_floor), an end weight or a backward draw total below
-// kRangeFloor = 2^-90 (2^-150 of the row mass). A chain with a queued block has every block
-// re-filtered in FP64 in that pass and for the next kRescueHold forward passes: on the way to a
-// clustered state some FP32 blocks drift without meeting a floor, while the settled states
-// meet none.
-constexpr int kWScaleLog2 = 60;
-constexpr int kRowExp = 60;
+// (W~ = W / max_r W of the slice, so the table's largest entry is 2^100 and W~ down to 2^-226
+// is representable), and forward rows hold f~ 2^row_exp (row mass 2^20). A block is queued for
+// the FP64 re-filter and redraw (k_rescue) when what its draws need approaches the floor: a
+// forward step whose W-weighted mass is below 2^-196 of its unweighted mass (step_floor: the
+// weights FP32 flushed to zero can then matter), an end weight below kRangeFloor = 2^-90
+// (2^-110 of the row mass; it also needs the far hops of the circulant, whose bf16 terms stop
+// there), or a backward draw that picks a site whose FP32 filter value is below kRangeFloor or
+// finds no positive weight (the draw's FP64 weights carry G exactly, so only the filter value
+// is in question). When a chain has a block queued in a forward pass (more than
+// whole_min), every block of the chain is re-filtered in FP64 in that pass and in the next
+// kRescueHold forward passes: on the way to a clustered state many blocks meet a floor and some
+// FP32 blocks drift without meeting one (a hop whose product underflows in one slice can move
+// log Z by 16 nats), while the blocks of a settled chain meet a floor all together or not at
+// all.
+constexpr int kWScaleLog2 = 100;
+constexpr int kRowExp = 20;
 constexpr float kRangeFloor = 0x1p-90f;
 constexpr double kRangeFloorD = 0x1p-90;
 constexpr int kRescueHold = 2;
@@ -131,7 +137,8 @@ __device__ inline bool rescue_enqueue(const Rescue& r, const ChainInfo& c, int c
     return true;
 }
 // A kernel found block (chain, p, block) out of FP32's range: queue it, count it for its chain
-// and keep the chain on the FP64 re-filter for the next kRescueHold forward passes.
+// and hold the chain on the FP64 re-filter for the next kRescueHold forward passes (a backward
+// pass queues after the chain's blocks were expanded for this one).
 __device__ inline void rescue_push(const Rescue& r, const ChainInfo& c, int chain, int p,
                                    int block) {
     if (rescue_enqueue(r, c, chain, p, block)) {
@@ -192,6 +199,7 @@ struct Device {
     int32_t* rescue = nullptr;   // FP32 plans: rescue state words (kRescueFlags), else null
     DrawTask* rescue_list = nullptr;  // blocks queued for the FP64 re-filter, [n_draw_tasks]
     double* rescue_ws = nullptr;      // [n_rescue_slots][rescue_slot_elems] FP64 filter rows
+    double* rescue_w = nullptr;       // [2][aux_elems] FP64 W~ of the chains with queued blocks
     int32_t* status = nullptr;   // [0] first error code, [1] its chain
     uint64_t* sweep = nullptr;   // sweep index read by the kernels
 };

@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_potentials(const ChainInfo* __rest
     }
     if (!isfinite(mu)) mu = 0.0;
     if (!isfinite(md)) md = 0.0;
-    if (sizeof(T) == 4) {  // FP32 tables: W~ 2^kWScaleLog2, so W~ down to 2^-186 stays normal
+    if (sizeof(T) == 4) {  // FP32 tables: W~ 2^kWScaleLog2, so W~ down to 2^-226 stays normal
         mu -= kWScaleLog2 * 0.69314718055994530942;
         md -= kWScaleLog2 * 0.69314718055994530942;
     }
@@ -439,8 +439,8 @@ __global__ __launch_bounds__(kThreads) void k_backward(
         if (lane == 0) excl = 0.0;
         const double total = __shfl(incl, 63, 64);
         int chosen = cur;
-        if (rsc.words && (!(total >= kRangeFloorD) || !isfinite(total))) {
-            // an FP32 row this far below its mass: the block is redrawn from FP64 filters
+        if (rsc.words && (!(total > 0.0) || !isfinite(total))) {
+            // no usable FP32 weight: the block is redrawn from FP64 filters
             if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
             return;
         }
@@ -470,6 +470,11 @@ __global__ __launch_bounds__(kThreads) void k_backward(
             }
             chosen = first != 0x7fffffff ? first : lastpos;
             if (chosen < 0) chosen = cur;
+            // FP32 plans: a site drawn from a filter value near FP32's floor (kRangeFloor)
+            if (rsc.words && !((double)f[chosen] >= kRangeFloorD)) {
+                if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
+                return;
+            }
         }
         if (lane == 0) pc[(int64_t)l * c.np + (start + j >= c.L_tau ? qn : t.p)] = chosen;
         cur = chosen;
@@ -515,7 +520,7 @@ template <typename T, bool VEC, int LFIX, int E>
 __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const double* g,
                               const T* __restrict__ filt, int32_t* __restrict__ paths,
                               const int32_t* __restrict__ perm, uint64_t sweep, int32_t* status,
-                              int lane, const Rescue rsc) {
+                              int lane, const Rescue rsc, const T* rows_at = nullptr) {
     constexpr int DEPTH = sizeof(T) == 4 ? 2 : 1;  // rows in flight ahead of the current one
     int start, len;
     block_of(c, sweep, t.block, &start, &len);
@@ -530,7 +535,9 @@ __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const doubl
     const int i0 = lane * per;
     const int cnt = LFIX ? per : max(0, min(per, N - i0));
     const int x0 = cnt > 0 ? i0 % L : 0, y0 = cnt > 0 ? i0 / L : 0;
-    const T* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+    // the block's rows in the plan's workspace, or at rows_at (the FP64 re-filter's slot)
+    const T* rows = rows_at ? rows_at
+                            : filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
     // row of draw j is rows + (j - 1) N; draws run j = len-1 .. 1
     auto load_row = [&](int j, T (&dst)[E]) {
         const T* r = rows + (int64_t)(j - 1) * N + i0;
@@ -616,8 +623,8 @@ __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const doubl
         const double incl = wave_incl_scan_f64(tot, lane, &total);
         double run = incl - tot;
         int chosen = cur;
-        if (rsc.words && (!(total >= kRangeFloorD) || !isfinite(total))) {
-            // an FP32 row this far below its mass: the block is redrawn from FP64 filters
+        if (rsc.words && (!(total > 0.0) || !isfinite(total))) {
+            // no usable FP32 weight: the block is redrawn from FP64 filters
             if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
             return;
         }
@@ -627,21 +634,39 @@ __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const doubl
         } else {
             const double T_ = u * total;
             int first = -1;
+            double fsel = 0.0;  // the filter value of the drawn site
 #pragma unroll
             for (int k = 0; k < E; ++k) {
                 run += w[k];
-                if (first < 0 && k < cnt && run > T_) first = i0 + k;
+                if (first < 0 && k < cnt && run > T_) {
+                    first = i0 + k;
+                    fsel = (double)f[k];
+                }
             }
             const uint64_t found = __ballot(first >= 0);
             if (found) {
-                chosen = __builtin_amdgcn_readlane(first, __ffsll((unsigned long long)found) - 1);
+                const int src = __ffsll((unsigned long long)found) - 1;
+                chosen = __builtin_amdgcn_readlane(first, src);
+                fsel = readlane_f64(fsel, src);
             } else {
                 int lastpos = -1;
 #pragma unroll
                 for (int k = 0; k < E; ++k)
-                    if (k < cnt && w[k] > 0.0) lastpos = i0 + k;
+                    if (k < cnt && w[k] > 0.0) {
+                        lastpos = i0 + k;
+                        fsel = (double)f[k];
+                    }
                 const uint64_t has = __ballot(lastpos >= 0);
-                if (has) chosen = __builtin_amdgcn_readlane(lastpos, 63 - __clzll((long long)has));
+                if (has) {
+                    const int src = 63 - __clzll((long long)has);
+                    chosen = __builtin_amdgcn_readlane(lastpos, src);
+                    fsel = readlane_f64(fsel, src);
+                }
+            }
+            // FP32 plans: a site drawn from a filter value near FP32's floor (kRangeFloor)
+            if (rsc.words && !(fsel >= kRangeFloorD)) {
+                if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
+                return;
             }
         }
         if (lane == 0)
@@ -750,16 +775,23 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
                 acc = fma(fi > 0.0 ? fi : 0.0, gx[15 - i], acc);
                 P[i] = acc;
             }
+            // FP32 plans: which of the lane's sites hold a filter value at or above kRangeFloor
+            uint32_t okb = 0;
+            if (rsc.words) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) okb |= (ring[b][i] >= (T)kRangeFloor ? 1u : 0u) << i;
+            }
             load_row(nd - s - NB, ring[b]);  // this buffer now serves draw s + NB
             const double tot = P[15] * gy;
             double total;
             const double incl = wave_incl_scan_f64(tot, lane, &total);
             int chosen = cur;
-            if (rsc.words && real && (!(total >= kRangeFloorD) || !isfinite(total))) {
-                halted = true;  // an FP32 row this far below its mass: redrawn from FP64 filters
-                if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
-            } else if (!(total > 0.0) || !isfinite(total)) {
-                if (real && err == 0) err = isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE;
+            bool low = false;  // FP32: drawn from a filter value below kRangeFloor, or no weight
+            if (!(total > 0.0) || !isfinite(total)) {
+                if (rsc.words)
+                    low = true;
+                else if (real && err == 0)
+                    err = isfinite(total) ? FH_ERR_ZERO_WEIGHT : FH_ERR_NONFINITE;
             } else {
                 const double T_ = u * total;
                 const double Tl = fmax((T_ - (incl - tot)) / gy, 0.0);
@@ -769,7 +801,9 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
                 const uint64_t found = __ballot(tot > 0.0 && cnt < 16);
                 if (found) {
                     const int src = __ffsll((unsigned long long)found) - 1;
-                    chosen = 16 * src + __builtin_amdgcn_readlane(cnt, src);
+                    const int k = __builtin_amdgcn_readlane(cnt, src);
+                    chosen = 16 * src + k;
+                    low = ((__builtin_amdgcn_readlane((int)okb, src) >> k) & 1) == 0;
                 } else {
                     int lastpos = -1;
 #pragma unroll
@@ -778,9 +812,16 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
                     const uint64_t has = __ballot(lastpos >= 0);
                     if (has) {
                         const int src = 63 - __clzll((long long)has);
-                        chosen = 16 * src + __builtin_amdgcn_readlane(lastpos, src);
+                        const int k = __builtin_amdgcn_readlane(lastpos, src);
+                        chosen = 16 * src + k;
+                        low = ((__builtin_amdgcn_readlane((int)okb, src) >> k) & 1) == 0;
                     }
                 }
+                low = low && rsc.words;
+            }
+            if (low && real) {
+                halted = true;  // an FP32 value near FP32's floor decides it: FP64 redraw
+                if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
             }
             chosen = real ? chosen : cur;
             pc[(int64_t)((start + j) % L_tau) * c.np + (start + j >= L_tau ? qn : t.p)] = chosen;
@@ -804,7 +845,8 @@ __device__ inline double group_scan_incl(double v) {
 // site with a positive weight). Lane k owns the per = ceil(N / 64) contiguous sites from k per;
 // the weights max(f, 0) g(dy) g(dx) are taken about (cx, cy). Every argument is wavefront
 // uniform. On a zero or non-finite total the current site is kept and *bad gets the error;
-// with `range` (FP32 plans) a total below kRangeFloorD sets *bad = kBadRange instead.
+// with `range` (FP32 plans) such a total, or a drawn site whose filter value is below
+// kRangeFloor, sets *bad = kBadRange instead.
 constexpr int kBadRange = 1;
 template <typename T>
 __device__ int wave_row_draw(const T* __restrict__ row, int N, int L, int cx, int cy,
@@ -846,7 +888,7 @@ __device__ int wave_row_draw(const T* __restrict__ row, int N, int L, int cx, in
     }
     double total;
     const double incl = wave_incl_scan_f64(tot, lane, &total);
-    if (range && (!(total >= kRangeFloorD) || !isfinite(total))) {
+    if (range && (!(total > 0.0) || !isfinite(total))) {
         *bad = kBadRange;
         return cur;
     }
@@ -882,29 +924,34 @@ __device__ int wave_row_draw(const T* __restrict__ row, int N, int L, int cx, in
             }
             if (pick < 0) pick = last_in >= 0 ? last_in : lastpos;  // rounding between orders
         }
-        return __builtin_amdgcn_readlane(pick, src);
+        const int chosen = __builtin_amdgcn_readlane(pick, src);
+        if (range && !((double)row[chosen] >= kRangeFloorD)) *bad = kBadRange;
+        return chosen;
     }
     const uint64_t lm = __ballot(lastpos >= 0);
-    return lm ? __builtin_amdgcn_readlane(lastpos, 63 - __clzll((long long)lm)) : cur;
+    const int chosen = lm ? __builtin_amdgcn_readlane(lastpos, 63 - __clzll((long long)lm)) : cur;
+    if (range && !((double)row[chosen] >= kRangeFloorD)) *bad = kBadRange;
+    return chosen;
 }
 
-// Draw on the second window (half-width kWin2W) of one group's worldline, taken by the whole
-// wavefront: lane k holds the window ranks 4k .. 4k + 3 (site order), so the draw costs one
-// round trip of four loads per lane. The lane sums are scanned across the wavefront and the lane
-// holding the first rank above tau certifies the draw. Every argument is wavefront uniform.
-// Returns (1 << 16 | y << 8 | x) for a certified draw, 0 otherwise (uniform). A window whose
-// mass is not above `floor` is never certified.
+// Draw on the window of half-width w <= kWin2W around (cx, cy), taken by the whole wavefront:
+// lane k holds the window ranks 4k .. 4k + 3 (site order), so the draw costs one round trip of
+// four loads per lane. The lane sums are scanned across the wavefront and the lane holding the
+// first rank above tau certifies the draw against `bound` (the outside bound times the row's mass
+// bound, fh_window.h). Every argument is wavefront uniform.
+// Returns (1 << 16 | y << 8 | x) for a certified draw, 0 otherwise (uniform); *fsel receives
+// the drawn site's filter value.
 template <typename T>
-__device__ int wave_window2_draw(const T* __restrict__ row, int L, int cx, int cy,
-                                 const double* g, double u, double gout2, int lane,
-                                 double floor) {
+__device__ int wave_window_draw(const T* __restrict__ row, int L, int cx, int cy, int w,
+                                const double* g, double u, double bound, int lane,
+                                double* fsel) {
     constexpr int K = 4;
     static_assert(64 * K >= (2 * kWin2W + 1) * (2 * kWin2W + 1), "the window fits the wavefront");
-    const int WW = win_width(kWin2W, L), nwin = WW * WW;
+    const int WW = win_width(w, L), nwin = WW * WW;
     const float rw = 1.0f / (float)WW;  // (q + 1/2) / WW in FP32 floors exactly for q < 2^12
     int tx, bx, ty, by;
-    win_axis(cx, kWin2W, L, WW, &tx, &bx);
-    win_axis(cy, kWin2W, L, WW, &ty, &by);
+    win_axis(cx, w, L, WW, &tx, &bx);
+    win_axis(cy, w, L, WW, &ty, &by);
     int xs[K], ys[K];
     T fv[K];
 #pragma unroll
@@ -931,11 +978,12 @@ __device__ int wave_window2_draw(const T* __restrict__ row, int L, int cx, int c
     const double incl = wave_incl_scan_f64(acc, lane, &T_in);
     const double excl = incl - acc;
     const double tau = u * T_in;
-    const bool fin = T_in > floor && isfinite(T_in);
+    const bool fin = T_in > 0.0 && isfinite(T_in);
     const uint64_t fm = __ballot(fin && incl > tau && acc > 0.0);
     if (!fm) return 0;
     const int src = __ffsll((unsigned long long)fm) - 1;
     int res = 0;
+    double fp = 0.0;
     if (lane == src) {
         double c_lo = excl, c_hi = 0.0;
         int pick = -1, pxy = 0;
@@ -947,14 +995,16 @@ __device__ int wave_window2_draw(const T* __restrict__ row, int L, int cx, int c
                     pick = k;
                     pxy = xs[k] | (ys[k] << 8);
                     c_hi = ck;
+                    fp = (double)fv[k];
                 } else {
                     c_lo = ck;
                 }
             }
         }
-        if (pick >= 0 && win_certified(c_lo, c_hi, tau, gout2 * kWinMassBound + kWinSlack * T_in))
+        if (pick >= 0 && win_certified(c_lo, c_hi, tau, bound + kWinSlack * T_in))
             res = (1 << 16) | pxy;
     }
+    *fsel = readlane_f64(fp, src);
     return __builtin_amdgcn_readlane(res, src);
 }
 
@@ -989,8 +1039,6 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     const ChainInfo& c = chains[t.chain];
     // a block queued for the FP64 re-filter is drawn by k_rescue
     const bool active = listed && !rescue_queued(rsc, c, t.p, t.block);
-    // FP32 plans: a window or row whose mass is below kRangeFloorD is not drawn in FP32
-    const double wfloor = rsc.words ? kRangeFloorD : 0.0;
     // an inactive group draws nothing; on a one-site lattice its table fill and loads stay minimal
     const int L = active ? c.L : 1, N = active ? c.N : 1, L_tau = c.L_tau, w = c.win_w;
     double* g = gsh[grp] + kWinMaxL;  // g[d] = g(d mod L) for -L < d < L
@@ -1088,7 +1136,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         const double excl = dpp_f64<0x111>(incl);  // the previous lane's inclusive sum (0 first)
         const double T_in = __shfl(incl, gbase + 15, 64);
         const double tau = u * T_in;
-        const bool fin = T_in > wfloor && isfinite(T_in);
+        const bool fin = T_in > 0.0 && isfinite(T_in);
         const uint32_t gm =
             (uint32_t)(__ballot(real && fin && incl > tau && acc > 0.0) >> gbase) & 0xFFFFu;
         const int src = gm ? __ffs((int)gm) - 1 : 0;
@@ -1107,16 +1155,21 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
             }
         }
         int px = xs[0], py = ys[0];
+        double fp = (double)fv[0];
 #pragma unroll
         for (int k = 1; k < K; ++k)
             if (k == pick) {
                 px = xs[k];
                 py = ys[k];
+                fp = (double)fv[k];
             }
         const bool cert_l = li == src && pick >= 0 &&
                             win_certified(c_lo, c_hi, tau, gout + kWinSlack * T_in);
         const int packed = __shfl((cert_l ? 1 << 16 : 0) | (py << 8) | px, gbase + src, 64);
         const bool cert = gm != 0 && (packed >> 16) != 0;
+        // FP32 plans: a site drawn from a filter value below kRangeFloor is redrawn in FP64
+        const double fpick = __shfl(fp, gbase + src, 64);
+        if (rsc.words && real && cert && !(fpick >= kRangeFloorD)) halt = true;
         int nx = packed & 255, ny = (packed >> 8) & 255;
         bool need_row = false;
         n_unc += (real && !cert) ? 1 : 0;
@@ -1130,14 +1183,17 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
             const T* rowg = (const T*)(uintptr_t)(
                 (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)rp, g0) |
                 ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(rp >> 32), g0) << 32));
-            const int p2 = wave_window2_draw(
+            double f2;
+            const int p2 = wave_window_draw(
                 rowg, __builtin_amdgcn_readlane(L, g0), __builtin_amdgcn_readlane(cx, g0),
-                __builtin_amdgcn_readlane(cy, g0), gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)] + kWinMaxL,
-                readlane_f64(u, g0), readlane_f64(c.win_gout2 * c.row_mass, g0), lane64, wfloor);
+                __builtin_amdgcn_readlane(cy, g0), kWin2W,
+                gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)] + kWinMaxL, readlane_f64(u, g0),
+                readlane_f64(c.win_gout2 * c.row_mass * kWinMassBound, g0), lane64, &f2);
             if ((lane64 >> 4) == (g0 >> 4)) {
                 if (p2 >> 16) {
                     nx = p2 & 255;
                     ny = (p2 >> 8) & 255;
+                    if (rsc.words && !(f2 >= kRangeFloorD)) halt = true;
                 } else {
                     need_row = true;
                 }
@@ -1182,14 +1238,59 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         atomicAdd(&bw_state[kBwCounts + t.chain], n_unc);
 }
 
+// The draws of one re-filtered block from its FP64 rows, by the whole wavefront: the rule of
+// the FP64 plans' backward kernels, taken on the certified window of half-width win_w, else on
+// the wider one, else on the full row (fh_window.h), so the sites are those of an FP64 plan.
+// Kept out of line: inlined into k_rescue next to the FP64 forward recursion, the compiler fails.
+__device__ __attribute__((noinline)) void rescue_draws(const DrawTask& t, const ChainInfo& c,
+                                                       const double* g, int32_t* paths,
+                                                       const int32_t* perm, uint64_t sweep,
+                                                       int32_t* status, int lane,
+                                                       const double* rows) {
+    int start, len;
+    block_of(c, sweep, t.block, &start, &len);
+    if (len < 2) return;
+    const int L = c.L, N = c.N, L_tau = c.L_tau;
+    int32_t* pc = paths + c.path_off;
+    const int qn = perm[c.part_off + t.p];  // the worldline slices >= L_tau belong to
+    int cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np +
+                              (start + len >= L_tau ? qn : t.p)], N, status, t.chain);
+    int err = 0;
+    for (int j = len - 1; j >= 1; --j) {
+        const int l = (start + j) % L_tau;
+        const u64x4 rnd = philox4x64_10((uint64_t)t.p, (uint64_t)l, sweep, kTagPath, c.seed, 0);
+        const double u = u01_from(rnd.x0);
+        const double* row = rows + (int64_t)(j - 1) * N;
+        const int cx = cur % L, cy = cur / L;
+        int site = -1;
+        double f;
+        if (c.win_on) {
+            int pk = wave_window_draw(row, L, cx, cy, c.win_w, g, u, c.win_gout * kWinMassBound,
+                                      lane, &f);
+            if (!(pk >> 16))
+                pk = wave_window_draw(row, L, cx, cy, kWin2W, g, u, c.win_gout2 * kWinMassBound,
+                                      lane, &f);
+            if (pk >> 16) site = (pk & 255) + L * ((pk >> 8) & 255);
+        }
+        if (site < 0) {
+            int bad = 0;
+            site = wave_row_draw(row, N, L, cx, cy, g, u, cur, lane, &bad);
+            if (bad != 0 && err == 0) err = bad;
+        }
+        if (lane == 0) pc[(int64_t)l * c.np + (start + j >= L_tau ? qn : t.p)] = site;
+        cur = site;
+    }
+    if (err != 0 && lane == 0) set_status(status, err, t.chain);
+}
+
 // FP64 re-filter and redraw of the blocks an FP32 pass queued because their filters left
 // FP32's range (kRangeFloor). The FP32 pass's rows for such a block hold values at FP32's floor
 // that decide its draws and log Z; FP64 holds them to ~2^-1022. One wavefront takes queued
 // blocks i = wid, wid + n_slots, ... in turn, with its own slot of FP64 rows:
-//   forward: the block recursion of k_forward_dmfma on the FP64 circulant, with
-//            W~ = exp(coef aux - m_l) computed in FP64 from the field (the FP32 tables may hold
-//            zeros there); rows to the slot and, rounded, to the plan's FP32 rows (what
-//            fh_get_filters returns); log Z to blk_logz;
+//   forward: the block recursion of k_forward_dmfma on the FP64 circulant, with the FP64
+//            W~ = exp(coef aux - m_l) of k_rescue_potentials (the FP32 tables may hold zeros
+//            there); log Z to blk_logz; rows to the slot (DRAW), or else, rounded and scaled,
+//            to the plan's FP32 rows (what fh_get_filters returns after fh_forward_filter);
 //   DRAW:    the block's sites from the slot's rows with k_backward's full-row rule and the same
 //            Philox uniforms, so the draws are those of an FP64 plan.
 // Only chains with L <= 32 have the FP64 circulant; a queued block of a larger lattice latches
@@ -1202,7 +1303,8 @@ __global__ __launch_bounds__(kThreads) void k_rescue(
     const double* __restrict__ wshift, int64_t total_slices, int32_t* __restrict__ paths,
     const int32_t* __restrict__ perm, float* __restrict__ filt, double* __restrict__ blk_logz,
     const uint64_t* __restrict__ sweep_ptr, int32_t* status, const Rescue rsc,
-    double* __restrict__ ws, int64_t slot_elems, int n_slots) {
+    double* __restrict__ ws, int64_t slot_elems, int n_slots, const double* __restrict__ W64,
+    int64_t aux_elems) {
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     const int count = __builtin_amdgcn_readfirstlane(rsc.words[0]);
@@ -1232,21 +1334,23 @@ __global__ __launch_bounds__(kThreads) void k_rescue(
 #pragma unroll
         for (int q = 0; q < 16; ++q) Cb[q] = cmat64[((int64_t)t.chain * 16 + q) * 64 + lane];
         float* frows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+        const double* Wl0 = W64 + spin * aux_elems + c.aux_off;
         auto wtab = [&](int l, double (&w)[16]) {
-            const float* al = ax + (int64_t)l * N;
-            const double m = shift[l];
+            const double* Wl = Wl0 + (int64_t)l * N;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
+                for (int r = 0; r < 4; ++r) {  // a padded position reads site 0, times 0
                     const int x = t64_x(q, lane), y = t64_y(q, r, lane);
-                    w[4 * q + r] = (x < L && y < L) ? exp(coef * (double)al[y * L + x] - m) : 0.0;
+                    w[4 * q + r] = Wl[(x < L && y < L) ? y * L + x : 0];
                 }
         };
         auto put = [&](int j, int q, int r, double v) {
             const int64_t o = (int64_t)(j - 1) * N + t64_y(q, r, lane) * L + t64_x(q, lane);
-            slot[o] = v;
-            frows[o] = (float)(v * c.row_mass);  // the FP32 rows' scaling
+            if (DRAW)
+                slot[o] = v;                         // the rows the draws below read
+            else
+                frows[o] = (float)(v * c.row_mass);  // the plan's rows (FP32 scaling)
         };
         bool ok = true;
         const double lz = dmfma_block_forward(Cb, L, L_tau, start, len, a, e,
@@ -1259,20 +1363,8 @@ __global__ __launch_bounds__(kThreads) void k_rescue(
         if (!DRAW || !ok) continue;
         // the slot's rows were stored by this wavefront's lanes: make them visible to its loads
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-        const double* g = tables + tab_g(c);
-        int cur = e;
-        int err = 0;
-        for (int j = len - 1; j >= 1; --j) {
-            const int l = (start + j) % L_tau;
-            const u64x4 rnd = philox4x64_10((uint64_t)t.p, (uint64_t)l, sweep, kTagPath, c.seed, 0);
-            int bad = 0;
-            const int chosen = wave_row_draw(slot + (int64_t)(j - 1) * N, N, L, cur % L, cur / L,
-                                             g, u01_from(rnd.x0), cur, lane, &bad);
-            if (bad != 0 && err == 0) err = bad;
-            if (lane == 0) pc[(int64_t)l * c.np + (start + j >= L_tau ? qn : t.p)] = chosen;
-            cur = chosen;
-        }
-        if (err != 0 && lane == 0) set_status(status, err, t.chain);
+        // the full-row rule of the FP64 plans' backward kernel, on the slot's rows
+        rescue_draws(t, c, tables + tab_g(c), paths, perm, sweep, status, lane, slot);
         // the next block reuses the slot: its stores must follow these loads
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
     }
@@ -1291,23 +1383,47 @@ __global__ void k_rescue_reset(const Rescue rsc, int64_t n_flags) {
     for (int64_t k = i; k < n_flags; k += stride) rsc.flags[k] = 0;
 }
 
-// After the FP32 forward pass, one workgroup per chain: a chain with a block queued in this pass,
-// or still held from an earlier one, has all its blocks queued for the FP64 re-filter; its hold
-// then counts down (kRescueHold passes after the last pass with a queued block).
+// After the FP32 forward pass, one workgroup per chain: a chain with more than whole_min blocks
+// queued in this pass, or still held from an earlier such pass, has all its blocks queued for the
+// FP64 re-filter; its hold then counts down (kRescueHold passes after the last such pass).
 __global__ __launch_bounds__(kThreads) void k_rescue_expand(const ChainInfo* __restrict__ chains,
                                                             const Rescue rsc) {
     const int ci = blockIdx.x;
     const ChainInfo& c = chains[ci];
     const int cnt = rsc.words[kRescueChain + ci];
     const int hold = rsc.words[kRescueChain + rsc.n_chains + ci];
-    const bool whole = cnt > 0 || hold > 0;
+    const bool many = cnt > c.whole_min;
+    const bool whole = many || hold > 0;
     if (whole)
         for (int i = threadIdx.x; i < c.np * c.nb; i += blockDim.x)
             rescue_enqueue(rsc, c, ci, i / c.nb, i % c.nb);
-    __syncthreads();  // every thread read the hold before it changes
+    __syncthreads();  // every thread read the count and the hold before they change
     if (threadIdx.x == 0) {
-        rsc.words[kRescueChain + rsc.n_chains + ci] = cnt > 0 ? kRescueHold : max(hold - 1, 0);
-        if (whole) atomicAdd(&rsc.words[2], 1);
+        rsc.words[kRescueChain + rsc.n_chains + ci] = many ? kRescueHold : max(hold - 1, 0);
+        if (whole) {
+            atomicAdd(&rsc.words[2], 1);
+            rsc.words[kRescueChain + ci] = cnt + c.np * c.nb;  // the chain has queued blocks
+        }
+    }
+}
+
+// Before the FP64 re-filter, one workgroup per (chain, slice) of the chains with queued blocks:
+// W~ = exp(coef aux - m) in FP64 for both spins (the FP32 tables may hold zeros), with the
+// shift m of the FP32 tables.
+__global__ __launch_bounds__(kThreads) void k_rescue_potentials(
+    const ChainInfo* __restrict__ chains, int n_chains, const float* __restrict__ aux,
+    const double* __restrict__ wshift, double* __restrict__ W64, int64_t aux_elems,
+    int64_t total_slices, const Rescue rsc) {
+    const int gs = blockIdx.x;
+    const int ci = find_chain(n_chains, gs, [&](int i) { return chains[i].slice_off; });
+    if (rsc.words[kRescueChain + ci] == 0) return;  // nothing of this chain is queued
+    const ChainInfo& c = chains[ci];
+    const int64_t base = c.aux_off + (int64_t)(gs - c.slice_off) * c.N;
+    const double mu = wshift[gs], md = wshift[total_slices + gs];
+    for (int r = threadIdx.x; r < c.N; r += blockDim.x) {
+        const double v = (double)aux[base + r];
+        W64[base + r] = exp(c.coef_up * v - mu);
+        W64[aux_elems + base + r] = exp(c.coef_dn * v - md);
     }
 }
 
@@ -2146,19 +2262,22 @@ hipError_t launch_rescue_expand(fh_plan p, hipStream_t s) {
 
 hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, hipStream_t s) {
     if (!p->d.rescue) return hipSuccess;
+    hipLaunchKernelGGL(k_rescue_potentials, dim3((unsigned)p->total_slices), dim3(kThreads), 0, s,
+                       p->d.chains, p->n_chains, (const float*)aux, p->d.wshift, p->d.rescue_w,
+                       p->aux_elems, p->total_slices, rescue_args(p));
     const unsigned blocks = (unsigned)(p->n_rescue_slots / kWaves);
     if (draw)
         hipLaunchKernelGGL(k_rescue<true>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.tables, p->d.cmat64, (const float*)aux, p->d.wshift,
                            p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
                            p->d.sweep, p->d.status, rescue_args(p), p->d.rescue_ws,
-                           p->rescue_slot_elems, p->n_rescue_slots);
+                           p->rescue_slot_elems, p->n_rescue_slots, p->d.rescue_w, p->aux_elems);
     else
         hipLaunchKernelGGL(k_rescue<false>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.tables, p->d.cmat64, (const float*)aux, p->d.wshift,
                            p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
                            p->d.sweep, p->d.status, rescue_args(p), p->d.rescue_ws,
-                           p->rescue_slot_elems, p->n_rescue_slots);
+                           p->rescue_slot_elems, p->n_rescue_slots, p->d.rescue_w, p->aux_elems);
     return hipGetLastError();
 }
 
