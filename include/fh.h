@@ -224,6 +224,18 @@ int fh_permutation_update(fh_plan plan, const int32_t* paths, uint64_t sweep, in
 int fh_measure(fh_plan plan, const int32_t* paths, double* Sk, double* Cr, double* D,
                double* S2, fh_stream stream);
 
+/* fh_measure for callers that cannot allocate device memory (code under stream capture, serving
+ * loops, harnesses that forbid it): the same kernels, outputs and arguments, with the per-slice
+ * rows in a static device array of 2^22 doubles (32 MiB) that every GPU the library runs on holds
+ * until the process ends, instead of a buffer the plan allocates on first use. The call itself
+ * calls no allocator. Returns FH_ERR_UNSUPPORTED when the plan needs more than the array holds
+ * (2 * aux elements + 2 * slices of all chains > 2^22, e.g. more than 12 chains of 32 x 32 with
+ * L_tau = 160) and FH_ERR_HIP when the array's address could not be taken at fh_init. All calls
+ * on one GPU share its array: calls that overlap in time on one GPU (any plans, any streams)
+ * race and must be serialised by the caller. */
+int fh_measure_noalloc(fh_plan plan, const int32_t* paths, double* Sk, double* Cr, double* D,
+                       double* S2, fh_stream stream);
+
 /* n_sweeps full sweeps, sweep indices first_sweep .. first_sweep+n_sweeps-1: forward filter,
  * backward sample, Gibbs field draw, in place on aux and paths. With FH_FLAG_GRAPH the sweep
  * is captured once per (aux, paths) pair and replayed. */

@@ -496,6 +496,12 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.sweep, sizeof(uint64_t));
     if (e == hipSuccess) e = hipMemcpy(dv.tables, p->tables.data(), sizeof(double) * p->tables.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+    // the static scratch of fh_measure_noalloc on this device: an address that cannot be taken
+    // only disables that entry point
+    if (e == hipSuccess && scratch_address(&p->scratch) != hipSuccess) {
+        p->scratch = nullptr;
+        (void)hipGetLastError();
+    }
     if (e == hipSuccess && (flags & FH_FLAG_AUTOTUNE) && precision != FH_FP32_MFMA3) {
         // one timing sweep per distinct L, on the twiddles of its first chain (the FFT paths
         // only: the MFMA path has no radix plan)
@@ -720,7 +726,16 @@ int fh_measure(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* 
         FH_TRY(hipStreamSynchronize(s));
         FH_TRY(hipMalloc((void**)&p->d.meas, sizeof(double) * n));
     }
-    FH_TRY(launch_measure(p, paths, Sk, Cr, D, S2, s));
+    FH_TRY(launch_measure(p, paths, Sk, Cr, D, S2, s, p->d.meas));
+    return FH_OK;
+}
+
+int fh_measure_noalloc(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* D,
+                       double* S2, fh_stream stream) {
+    if (!p || !paths) return FH_ERR_INVALID_ARG;
+    if (2 * p->aux_elems + 2 * p->total_slices > kScratchDoubles) return FH_ERR_UNSUPPORTED;
+    if (!p->scratch) return FH_ERR_HIP;  // its address could not be taken at fh_init
+    FH_TRY(launch_measure(p, paths, Sk, Cr, D, S2, (hipStream_t)stream, (double*)p->scratch));
     return FH_OK;
 }
 

@@ -112,6 +112,8 @@ constexpr int kRowExp = 20;
 constexpr float kRangeFloor = 0x1p-90f;
 constexpr double kRangeFloorD = 0x1p-90;
 constexpr int kRescueHold = 2;
+// Size of the static scratch array of fh_measure_noalloc: 2^22 doubles (32 MiB) per GPU.
+constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // Rescue state words: [0] blocks queued in this pass, [1] blocks redrawn since the last read by
 // fh_debug_rescue, [2] chains re-filtered whole in this pass, then per chain: blocks queued by
 // the kernels in this pass (kRescueChain + c) and forward passes left on FP64
@@ -245,6 +247,7 @@ struct fh_plan_s {
     uint64_t last_sweep = 0;
     const int32_t* last_paths = nullptr;
     const void* last_aux = nullptr;  // the field of the last fh_forward_filter (FP64 re-filter)
+    void* scratch = nullptr;  // device address of the static scratch array on the plan's device
     // graph cache for fh_sweep
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -288,8 +291,11 @@ hipError_t tune_radix_plan(fh_plan p, int L, const double* tw_dev, hipStream_t s
 hipError_t launch_gibbs(fh_plan p, const int32_t* paths, void* aux, hipStream_t s);
 hipError_t launch_local(fh_plan p, const void* aux, int32_t* paths, int n_passes, hipStream_t s);
 hipError_t launch_perm_update(fh_plan p, const int32_t* paths, int n_passes, hipStream_t s);
+// `work`: 2 aux_elems + 2 total_slices doubles of per-slice rows (the plan's, or the static scratch).
 hipError_t launch_measure(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* D,
-                          double* S2, hipStream_t s);
+                          double* S2, hipStream_t s, double* work);
+// Device address of the static scratch array on the current device (taken once per device).
+hipError_t scratch_address(void** out);
 hipError_t launch_mala_propose(fh_plan p, const void* aux, const void* dlogz, void* prop,
                                double eps, hipStream_t s);
 hipError_t launch_mala_accept(fh_plan p, void* aux, const void* prop, const void* g0,

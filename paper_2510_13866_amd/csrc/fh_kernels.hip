@@ -9,12 +9,20 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 #include <math.h>
 
 #include "fh_dmfma.h"
 #include "fh_internal.h"
 #include "fh_philox.h"
+
+// Per-slice rows of fh_measure_noalloc (S(k) and C(r) of every slice, then the two site sums of
+// every slice), held in this device array for callers that cannot allocate. Each GPU the library
+// runs on holds one copy for the life of the process; its device address is taken once per
+// device (fh::scratch_address) and passed to the kernels like any other buffer. Every element a
+// call reads is written by the same call first, so nothing needs clearing between calls.
+static __device__ __align__(256) double scratch[fh::kScratchDoubles];
 
 namespace fh {
 namespace {
@@ -2341,13 +2349,32 @@ hipError_t launch_perm_update(fh_plan p, const int32_t* paths, int n_passes, hip
     return hipSuccess;
 }
 
+hipError_t scratch_address(void** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {  // once per device, with that device current
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = ptr;
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
 hipError_t launch_measure(fh_plan p, const int32_t* paths, double* Sk, double* Cr, double* D,
-                          double* S2, hipStream_t s) {
+                          double* S2, hipStream_t s, double* work) {
     const size_t lds = sizeof(cpx<double>) * (2 * (size_t)p->max_N + p->max_L) +
                        sizeof(double) * 2 * kWaves;
     hipError_t e = allow_lds(k_measure, lds);
     if (e != hipSuccess) return e;
-    double* sk = p->d.meas;
+    double* sk = work;  // [aux_elems] S(k) rows, [aux_elems] C(r) rows, [2 slices] site sums
     double* cr = sk + p->aux_elems;
     double* sums = cr + p->aux_elems;
     hipLaunchKernelGGL(k_measure, dim3((unsigned)p->total_slices), dim3(kThreads), lds, s,

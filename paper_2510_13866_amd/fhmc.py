@@ -79,6 +79,8 @@ _sig("fh_set_permutation", c_int32, c_void_p, POINTER(c_int32))
 _sig("fh_get_permutation", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32))
 _sig("fh_permutation_update", c_int32, c_void_p, c_void_p, c_uint64, c_int32, c_void_p)
 _sig("fh_measure", c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
+_sig("fh_measure_noalloc", c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+     c_void_p)
 _sig("fh_mala_field", c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_double, c_uint64, c_void_p,
      c_void_p)
 _sig("fh_logZ_grad", c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
@@ -221,6 +223,11 @@ def fh_local_update(plan, aux, paths, sweep, n_passes, stream=None):
 def fh_measure(plan, paths, Sk=None, Cr=None, D=None, S2=None, stream=None):
     _check(lib.fh_measure(plan, _ptr(paths), _ptr(Sk), _ptr(Cr), _ptr(D), _ptr(S2),
                           _stream(stream)), "fh_measure")
+
+
+def fh_measure_noalloc(plan, paths, Sk=None, Cr=None, D=None, S2=None, stream=None):
+    _check(lib.fh_measure_noalloc(plan, _ptr(paths), _ptr(Sk), _ptr(Cr), _ptr(D), _ptr(S2),
+                                  _stream(stream)), "fh_measure_noalloc")
 
 
 def fh_set_permutation(plan, perm):
