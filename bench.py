@@ -123,39 +123,6 @@ def chain_summary(each, warmup):
             "max_ms": round(max(each), 3)}
 
 
-def time_forward(S, A, P, n, stream):
-    """Average duration of fh_forward_filter (site potentials + forward filter kernel) over n
-    launches, HIP events recorded on the stream the kernels are launched on."""
-    import torch
-    from paper_2510_13866_amd import fhmc
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for i in range(n):
-        fhmc.fh_forward_filter(S.plan, A, P, 1000 + i, None, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / n
-
-
-def time_backward(S, A, P, n, stream, sweep=2000):
-    """Average duration of fh_backward_sample over n launches after one forward filter (the
-    block endpoints do not change, so every launch redraws the same interiors)."""
-    import torch
-    from paper_2510_13866_amd import fhmc
-    fhmc.fh_forward_filter(S.plan, A, P, sweep, None, stream)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for i in range(n):
-        fhmc.fh_backward_sample(S.plan, P, sweep, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / n
-
-
 def copy_calibration(stream):
     """A plain device copy of 1 GiB, five times: its FETCH_SIZE / WRITE_SIZE counters give the
     factor that turns those counters into HBM bytes."""
@@ -485,18 +452,31 @@ def main():
              "blocks_redrawn_fp64": {"count": int(redrawn), "of": int(n_blocks)}}
     log("  per sweep: %s" % extra["per_sweep_ms"])
 
-    # the two hot kernels, each timed alone on its stream: the forward filter (whose work does
-    # not depend on the state) on the initial state, where no block needs the FP64 re-filter,
-    # and the backward sampler on the state the chain reached; the forward writes every filter
-    # row once, the backward reads what its draws need
-    nf = max(3, min(10, args.steps))
-    Ae, Pe = A.clone(), P.clone()
-    S0 = Sampler(descs, prec, draw_flag)
-    fwd_ms = time_forward(S0, S0.pack_aux(aux), S0.pack_paths(paths), nf, stream)
-    if fhmc.fh_debug_rescue(S0.plan)[0] != 0:
-        raise RuntimeError("the forward timing's state needed the FP64 re-filter")
-    S0.close()
-    bwd_ms = time_backward(S, Ae, Pe, nf, stream)
+    # The kernels of the timed sweeps, timed with HIP events the library records in each sweep
+    # (fh_debug_sweep_timing) around the forward-filter kernels, the backward kernels and the
+    # FP64 re-filter: the same chain is run again from the same input, eagerly (it is
+    # deterministic, so it passes through the same states; checked below), reading the events
+    # after every sweep, and the segments are averaged over the timed sweeps.
+    St = Sampler(descs, prec, fhmc.FH_FLAG_GRAPH | draw_flag)
+    At, Pt = St.pack_aux(aux), St.pack_paths(paths)
+    assert fhmc.lib.fh_debug_sweep_timing(St.plan, 1) == 0
+    run_chain(St, At, Pt, 0, args.warmup, stream)
+    seg = [0.0, 0.0, 0.0]
+    with torch.cuda.stream(stream):
+        for i in range(args.steps):
+            St.sweep(At, Pt, args.warmup + i, 1, stream)
+            for k, v in enumerate(fhmc.fh_debug_sweep_times(St.plan)):
+                seg[k] += v
+    torch.cuda.synchronize()
+    if not (torch.equal(At, A) and torch.equal(Pt, P)):
+        raise RuntimeError("the timing replay did not reproduce the timed chain")
+    St.close()
+    fwd_ms, bwd_ms, rescue_ms = (v / args.steps for v in seg)
+    extra["kernel_ms_per_sweep"] = {"forward": round(fwd_ms, 4), "backward": round(bwd_ms, 4),
+                                    "fp64_refilter": round(rescue_ms, 4),
+                                    "timing": "HIP events inside every timed sweep, averaged"}
+    log("  per sweep: forward %.3f ms, backward %.3f ms, FP64 re-filter %.3f ms" %
+        (fwd_ms, bwd_ms, rescue_ms))
     rsz = 8 if args.precision == "fp64" else 4
     rows = sum(d.n_particles * (d.L_tau - 1) for d in descs)       # one block per worldline
     N = descs[0].N
@@ -511,16 +491,18 @@ def main():
                                                                                  "k_forward_fft")
     names = {"forward": "forward filter (%s)" % fwd_kernel,
              "backward": "backward sampler (%s)" % ("k_backward_l32" if args.full_row_draw
-                                                    else "k_backward_win")}
+                                                    else "k_backward_win, full-row kernels")}
+    knames = {"forward": fwd_kernel,
+              "backward": "k_backward_l32" if args.full_row_draw else "k_backward_win"}
     roofs = {}
     for k in ("forward", "backward"):
         gbs = algo[k] / (times[k] / 1e3) / 1e9
         roofs[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(k, args.precision, names[k].split("(")[1][:-1]),
+                    "traffic": measured_traffic(k, args.precision, knames[k]),
                     "kernel": names[k], "ms_per_launch": round(times[k], 4),
                     "algorithmic_bytes_per_launch": algo[k],
-                    "state": "initial" if k == "forward" else "after the timed sweeps"}
+                    "timing": "average over the timed sweeps"}
         log("  %s %.3f ms/launch, %.0f GB/s algorithmic" % (names[k], times[k], gbs))
     if args.precision == "fp32_mfma3":
         # the same forward launch against the matrix cores: 24 bf16 MFMA 32x32x16 per

@@ -88,6 +88,15 @@ int fh_debug_backward_adapt(fh_plan plan, int32_t enable, int32_t* full_row_pass
 int fh_debug_rescue(fh_plan plan, int32_t* last_count, int32_t* whole_chains, int64_t* total,
                     int32_t* list, int32_t cap);
 
+/* Per-sweep timing for the benchmark: with enable = 1, every sweep of fh_sweep records HIP events
+ * of the plan around its forward-filter kernels, its backward-sampling kernels and the FP64
+ * re-filter of out-of-range blocks (FP32 plans); the sweeps are then launched eagerly (the same
+ * kernels on the same stream) instead of from the captured graph, whose event nodes cannot be
+ * timed. fh_debug_sweep_times waits for the last sweep and writes the three durations in
+ * milliseconds to ms[0..2] (caller-owned host memory). */
+int fh_debug_sweep_timing(fh_plan plan, int32_t enable);
+int fh_debug_sweep_times(fh_plan plan, float* ms);
+
 /* Forward work items of an FH_FP32_MFMA3 plan, by kernel: counts[0] worldline pairs of L = 32
  * chains, counts[1] single padded worldlines (16 < L < 32), counts[2] packed tasks of 2 x 2
  * worldlines per tile (8 < L <= 16), counts[3] packed tasks of 4 x 4 (L <= 8). counts holds 4

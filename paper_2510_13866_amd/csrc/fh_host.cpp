@@ -567,6 +567,8 @@ int fh_destroy(fh_plan p) {
     if (!p) return FH_ERR_INVALID_ARG;
     (void)hipDeviceSynchronize();
     drop_graph(p);
+    for (hipEvent_t& ev : p->tev)
+        if (ev) (void)hipEventDestroy(ev);
     free_device(p->d);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     delete p;
@@ -604,9 +606,15 @@ int fh_sizes(fh_plan p, int64_t* aux_elems, int64_t* path_elems, int64_t* partic
     return FH_OK;
 }
 
+// Records timing event k of fh_debug_sweep_timing (no-op unless enabled).
+static hipError_t mark(fh_plan p, int k, hipStream_t s) {
+    return p->timing ? hipEventRecord(p->tev[k], s) : hipSuccess;
+}
+
 static hipError_t enqueue_forward(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
     hipError_t e = launch_potentials(p, aux, s);
     if (e == hipSuccess) e = launch_rescue_reset(p, s);  // FP32 plans: empty re-filter queue
+    if (e == hipSuccess) e = mark(p, 0, s);
     if (e != hipSuccess) return e;
     if (p->precision == FH_FP32_MFMA3) {
         e = launch_forward_mfma(p, aux, paths, s);
@@ -614,6 +622,7 @@ static hipError_t enqueue_forward(fh_plan p, const void* aux, const int32_t* pat
         e = launch_forward_dmfma(p, aux, paths, s);  // FP64 plans, chains with L <= 32
         if (e == hipSuccess && p->n_fwd_tasks > 0) e = launch_forward(p, aux, paths, s);
     }
+    if (e == hipSuccess) e = mark(p, 1, s);
     if (e == hipSuccess) e = launch_rescue_expand(p, s);  // FP32: chains re-filtered whole
     return e;
 }
@@ -742,8 +751,11 @@ int fh_measure_noalloc(fh_plan p, const int32_t* paths, double* Sk, double* Cr, 
 // One sweep reading its index from the device word, as recorded into a graph.
 static hipError_t enqueue_sweep_body(fh_plan p, void* aux, int32_t* paths, hipStream_t s) {
     hipError_t e = enqueue_forward(p, aux, paths, s);
+    if (e == hipSuccess) e = mark(p, 2, s);
     if (e == hipSuccess) e = launch_backward(p, paths, s);
+    if (e == hipSuccess) e = mark(p, 3, s);
     if (e == hipSuccess) e = launch_rescue(p, aux, paths, true, s);
+    if (e == hipSuccess) e = mark(p, 4, s);
     if (e == hipSuccess) e = launch_gibbs(p, paths, aux, s);
     return e;
 }
@@ -778,7 +790,7 @@ int fh_sweep(fh_plan p, void* aux, int32_t* paths, uint64_t first_sweep, int32_t
     if (!p || !aux || !paths || n_sweeps < 0) return FH_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     if (n_sweeps == 0) return FH_OK;
-    if (p->flags & FH_FLAG_GRAPH) {
+    if ((p->flags & FH_FLAG_GRAPH) && !p->timing) {  // timed sweeps run eagerly (their events)
         if (!p->graph_exec || p->graph_aux != aux || p->graph_paths != paths) {
             // capture on the plan's stream after the caller's queued work is done
             FH_TRY(hipStreamSynchronize(s));
@@ -1151,6 +1163,25 @@ int fh_debug_rescue(fh_plan p, int32_t* last_count, int32_t* whole_chains, int64
             list[3 * i + 1] = t[i].p;
             list[3 * i + 2] = t[i].block;
         }
+    }
+    return FH_OK;
+}
+
+int fh_debug_sweep_timing(fh_plan p, int32_t enable) {
+    if (!p || (enable != 0 && enable != 1)) return FH_ERR_INVALID_ARG;
+    FH_TRY(hipDeviceSynchronize());
+    if (enable && !p->tev[0])
+        for (hipEvent_t& ev : p->tev) FH_TRY(hipEventCreate(&ev));
+    p->timing = enable != 0;
+    return FH_OK;
+}
+
+int fh_debug_sweep_times(fh_plan p, float* ms) {
+    if (!p || !ms || !p->timing) return FH_ERR_INVALID_ARG;
+    FH_TRY(hipEventSynchronize(p->tev[4]));
+    for (int k = 0; k < 3; ++k) {
+        const int a = k == 0 ? 0 : k + 1;
+        FH_TRY(hipEventElapsedTime(&ms[k], p->tev[a], p->tev[a + 1]));
     }
     return FH_OK;
 }

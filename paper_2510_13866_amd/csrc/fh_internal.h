@@ -248,6 +248,10 @@ struct fh_plan_s {
     const int32_t* last_paths = nullptr;
     const void* last_aux = nullptr;  // the field of the last fh_forward_filter (FP64 re-filter)
     void* scratch = nullptr;  // device address of the static scratch array on the plan's device
+    // fh_debug_sweep_timing: events recorded around the forward kernels, the backward kernels and
+    // the FP64 re-filter of every sweep (inside the captured graph as well)
+    bool timing = false;
+    hipEvent_t tev[6] = {};
     // graph cache for fh_sweep
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;

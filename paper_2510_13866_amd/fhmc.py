@@ -108,6 +108,8 @@ _sig("fh_debug_forward_kernels", c_int32, c_void_p, POINTER(c_int32))
 _sig("fh_debug_backward_adapt", c_int32, c_void_p, c_int32, POINTER(c_int32))
 _sig("fh_debug_rescue", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int64),
      POINTER(c_int32), c_int32)
+_sig("fh_debug_sweep_timing", c_int32, c_void_p, c_int32)
+_sig("fh_debug_sweep_times", c_int32, c_void_p, POINTER(ctypes.c_float))
 
 
 class FhError(RuntimeError):
@@ -277,3 +279,10 @@ def fh_debug_rescue(plan, cap=0):
                                buf.ctypes.data_as(POINTER(c_int32)), cap), "fh_debug_rescue")
     n = min(cap, last.value)
     return last.value, total.value, [tuple(int(v) for v in buf[i]) for i in range(n)], whole.value
+
+
+def fh_debug_sweep_times(plan):
+    """(forward, backward, FP64 re-filter) milliseconds of the last sweep (timing enabled)."""
+    ms = (ctypes.c_float * 3)()
+    _check(lib.fh_debug_sweep_times(plan, ms), "fh_debug_sweep_times")
+    return ms[0], ms[1], ms[2]
