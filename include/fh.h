@@ -249,9 +249,20 @@ int fh_sweep(fh_plan plan, void* aux, int32_t* paths, uint64_t first_sweep, int3
  * f_j(r) beta_j(r) / Z, d/dt through d exp(-dtau eps_k)/dt in Fourier space.
  * logZ: per chain [n_chains] (nullable); grad_aux: packed like aux, overwritten, in the
  * plan's precision, d log Z_path / d aux(l, r) (nullable); grad_t: [n_chains] (nullable).
- * Accumulation into grad_aux uses atomics: the last bits may vary between calls. */
+ * Every adjoint writes one partial field gradient per group of worldlines and adds a chain's
+ * groups in a fixed order, so repeated calls on the same inputs return the same bits. */
 int fh_logZ_grad(fh_plan plan, const void* aux, const int32_t* paths, int32_t anchor_slice,
                  double* logZ, void* grad_aux, double* grad_t, fh_stream stream);
+
+/* Rao-Blackwellised kinetic energy per chain (the expectation of the hopping term of the Hubbard
+ * Hamiltonian, eq. hubbard, with the worldlines' paths summed out given their sites at
+ * anchor_slice): energy[c] = -(t_c / beta_c) d log Z_path / d t_c, beta_c = L_tau dtau, Z_path
+ * as in fh_logZ_grad; t enters each kinetic step through exp(-dtau eps_k) of the symmetric
+ * Trotter split (Sec. on the path integral). The paper gives no estimator of its own; this is
+ * the one its path weights define. energy: device double [n_chains], overwritten. Same
+ * argument rules, errors and filter side effects as fh_logZ_grad; fixed-order reductions. */
+int fh_kinetic_energy(fh_plan plan, const void* aux, const int32_t* paths, int32_t anchor_slice,
+                      double* energy, fh_stream stream);
 
 /* One gradient-informed move of the Gaussian field of every chain: a Metropolis-adjusted Langevin
  * step (Roberts and Tweedie, 1996) on the field's law given the worldlines' sites at

@@ -187,7 +187,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.grad_tasks, d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
+                    d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
                     d.rescue, d.rescue_list, d.rescue_ws, d.rescue_w, d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -273,6 +273,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         default_radix_plan(d.L, &ci.plan);
         ci.gauss_a = sqrt(fabs(d.U) * d.dtau);
         ci.dtau = d.dtau;
+        ci.hop_t = d.t;
         ci.hirsch_lambda = d.hs_kind == FH_HS_HIRSCH ? acosh(exp(d.dtau * d.U / 2.0)) : 0.0;
         ci.coef_up = d.hs_kind == FH_HS_GAUSS ? ci.gauss_a : ci.hirsch_lambda;
         ci.coef_dn = d.hs_kind == FH_HS_GAUSS ? ci.gauss_a : -ci.hirsch_lambda;
@@ -338,17 +339,22 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         const ChainInfo &x = p->chains[a], &y = p->chains[b];
         return (int64_t)x.B * x.N > (int64_t)y.B * y.N;
     });
-    std::vector<PairTask> fwd, grad;
+    std::vector<PairTask> fwd;
     std::vector<DrawTask> draw;
     std::vector<GroupTask> groups;
+    // the adjoint: FP64 circulant when every chain has L <= 32, else the FFT (one complex
+    // signal = two worldlines per group); FP32 plans run the matrix-core adjoint
+    p->grad_dmfma = precision == FH_FP64 && !(flags & FH_FLAG_FFT_CONV);
+    for (const ChainInfo& ci : p->chains) p->grad_dmfma = p->grad_dmfma && ci.L <= 32;
+    const int gsize = (precision == FH_FP32_MFMA3 || p->grad_dmfma) ? kGroup : 2;
     int64_t gpart = 0;
     for (int c = 0; c < n_chains; ++c) {  // gradient groups in chain order (reduced per chain)
         ChainInfo& ci = p->chains[c];
         ci.g0 = (int32_t)groups.size();
         for (int spin = 0; spin < 2; ++spin) {
             int p0 = spin ? ci.n_up : 0, p1 = spin ? ci.np : ci.n_up;
-            for (int q = p0; q < p1; q += kGroup) {
-                groups.push_back({c, q, std::min(kGroup, p1 - q), spin, gpart});
+            for (int q = p0; q < p1; q += gsize) {
+                groups.push_back({c, q, std::min(gsize, p1 - q), spin, gpart});
                 gpart += (int64_t)ci.L_tau * ci.N;
             }
         }
@@ -361,7 +367,6 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
             for (int q = p0; q < p1; q += 2) {
                 int qb = q + 1 < p1 ? q + 1 : -1;
                 for (int b = 0; b < ci.nb; ++b) fwd.push_back({c, q, qb, b});
-                grad.push_back({c, q, qb, 0});
             }
         }
         for (int q = 0; q < ci.np; ++q)
@@ -379,7 +384,6 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         if (dmfma(t.chain)) fwdd.push_back(t);
     p->n_fwd_tasks = (int32_t)fwdf.size();
     p->n_fwdd_tasks = (int32_t)fwdd.size();
-    p->n_grad_tasks = (int32_t)grad.size();
     p->n_draw_tasks = (int32_t)draw.size();
     std::vector<PairTask> fwd32;
     std::vector<DrawTask> fwdx, draw32, draww, drawx;
@@ -429,9 +433,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->n_draww_tasks = (int32_t)draww.size();
     p->n_drawx_tasks = (int32_t)drawx.size();
     p->n_groups = (int32_t)groups.size();
-    p->grad_dmfma = precision == FH_FP64 && !(flags & FH_FLAG_FFT_CONV);
-    for (const ChainInfo& ci : p->chains) p->grad_dmfma = p->grad_dmfma && ci.L <= 32;
-    p->gpart_elems = (precision == FH_FP32_MFMA3 || p->grad_dmfma) ? gpart : 0;
+    p->gpart_elems = gpart;
 
     // FP32 plans: the FP64 re-filter of blocks that leave FP32's range, one slot of FP64 rows
     // per wavefront, sized for the longest block of the chains with L <= 32
@@ -461,7 +463,6 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.fwd_tasks, sizeof(PairTask) * fwdf.size());
     if (e == hipSuccess) e = dalloc(&dv.fwdd_tasks, sizeof(DrawTask) * fwdd.size());
     if (e == hipSuccess) e = dalloc(&dv.cmat64, sizeof(double) * p->cmat64.size());
-    if (e == hipSuccess) e = dalloc(&dv.grad_tasks, sizeof(PairTask) * grad.size());
     if (e == hipSuccess) e = dalloc(&dv.draw_tasks, sizeof(DrawTask) * draw.size());
     if (e == hipSuccess) e = dalloc(&dv.group_tasks, sizeof(GroupTask) * groups.size());
     if (e == hipSuccess) e = dalloc(&dv.fwd32_tasks, sizeof(PairTask) * fwd32.size());
@@ -523,7 +524,6 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess && !fwdf.empty()) e = hipMemcpy(dv.fwd_tasks, fwdf.data(), sizeof(PairTask) * fwdf.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !fwdd.empty()) e = hipMemcpy(dv.fwdd_tasks, fwdd.data(), sizeof(DrawTask) * fwdd.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.cmat64, p->cmat64.data(), sizeof(double) * p->cmat64.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(dv.grad_tasks, grad.data(), sizeof(PairTask) * grad.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.draw_tasks, draw.data(), sizeof(DrawTask) * draw.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dv.group_tasks, groups.data(), sizeof(GroupTask) * groups.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && !fwd32.empty()) e = hipMemcpy(dv.fwd32_tasks, fwd32.data(), sizeof(PairTask) * fwd32.size(), hipMemcpyHostToDevice);
@@ -819,8 +819,7 @@ static hipError_t enqueue_logz_grad(fh_plan p, const void* aux, const int32_t* p
     } else if (p->grad_dmfma) {
         e = launch_grad_dmfma(p, aux, paths, anchor_slice, grad_aux, s);
     } else {
-        if (grad_aux) e = launch_zero(grad_aux, (int64_t)p->real_size * p->aux_elems, s);
-        if (e == hipSuccess) e = launch_grad(p, aux, paths, anchor_slice, grad_aux, s);
+        e = launch_grad(p, aux, paths, anchor_slice, grad_aux, s);
     }
     if (e == hipSuccess) e = launch_grad_reduce(p, logZ, grad_t, s);
     return e;
@@ -834,6 +833,21 @@ int fh_logZ_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t ancho
         if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
     FH_TRY(enqueue_logz_grad(p, aux, paths, anchor_slice, logZ, grad_aux, grad_t,
                              (hipStream_t)stream));
+    p->have_filters = true;
+    p->filters_are_ring = true;
+    return FH_OK;
+}
+
+int fh_kinetic_energy(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor_slice,
+                      double* energy, fh_stream stream) {
+    if (!p || !aux || !paths || !energy) return FH_ERR_INVALID_ARG;
+    if (p->precision == FH_FP32_MFMA3 && p->max_L > 32) return FH_ERR_UNSUPPORTED;
+    for (const ChainInfo& c : p->chains)
+        if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    // d log Z_path / dt lands in energy (no field gradient, no log Z), then is scaled in place
+    FH_TRY(enqueue_logz_grad(p, aux, paths, anchor_slice, nullptr, nullptr, energy, s));
+    FH_TRY(launch_kinetic_scale(p, energy, s));
     p->have_filters = true;
     p->filters_are_ring = true;
     return FH_OK;
@@ -874,6 +888,7 @@ int fh_set_hopping(fh_plan p, const double* t) {
     for (int c = 0; c < p->n_chains; ++c) {
         ChainInfo& ci = p->chains[c];
         p->descs[c].t = t[c];
+        ci.hop_t = t[c];
         build_tables(p->descs[c], p->tables.data() + ci.tab_off);
         build_cmat(p->descs[c].L, p->tables.data() + tab_g(ci),
                    p->cmat.data() + (size_t)kCmatPerChain * c);

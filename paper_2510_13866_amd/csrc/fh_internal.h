@@ -20,7 +20,7 @@ struct ChainInfo {
     int32_t L, N, L_tau, n_up, n_dn, np, hs_kind, B, nb;
     RadixPlan plan;           // FFT radix plan of one dimension (both dimensions are L)
     double coef_up, coef_dn;  // log W_spin = coef_spin * aux
-    double gauss_a, hirsch_lambda, dtau;
+    double gauss_a, hirsch_lambda, dtau, hop_t;
     uint64_t seed;
     int64_t aux_off;   // packed aux / W offset (elements): aux[aux_off + l*N + r]
     int64_t path_off;  // packed paths offset: paths[path_off + l*np + p]
@@ -81,8 +81,9 @@ FH_HD inline int pack_blocks(int L) { return L <= 8 ? 4 : 2; }
 // faster than two on batches of mixed block lengths (finer work items balance better) and
 // within 5% on uniform ones.
 constexpr int kPackTiles = 1;
-// Up to kGroup worldlines of one (chain, spin) processed by one workgroup in the MFMA adjoint;
-// part_off locates the group's partial field-gradient slab [L_tau][N].
+// Up to kGroup worldlines of one (chain, spin) processed by one workgroup in the matrix-core
+// adjoints (two, one complex FFT signal, in the FFT adjoint); part_off locates the group's
+// partial field-gradient slab [L_tau][N], which k_gpart_reduce adds per chain in a fixed order.
 constexpr int kGroup = 4;
 struct GroupTask {
     int32_t chain, p0, count, spin;
@@ -173,7 +174,6 @@ struct Device {
     double* blk_logz = nullptr;
     double* dt = nullptr;     // per particle d log Z / d t
     PairTask* fwd_tasks = nullptr;
-    PairTask* grad_tasks = nullptr;
     DrawTask* draw_tasks = nullptr;
     GroupTask* group_tasks = nullptr;
     PairTask* fwd32_tasks = nullptr;    // MFMA forward: worldline pairs of L = 32 chains
@@ -220,7 +220,7 @@ struct fh_plan_s {
     std::vector<uint16_t> cmatb;
     std::vector<double> cmat64;
     int64_t aux_elems = 0, path_elems = 0, particles = 0, blk_elems = 0, filt_elems = 0;
-    int32_t n_fwd_tasks = 0, n_grad_tasks = 0, n_draw_tasks = 0;
+    int32_t n_fwd_tasks = 0, n_draw_tasks = 0;
     int64_t total_slices = 0;
     int32_t n_groups = 0;
     int32_t n_fwd32_tasks = 0, n_fwdx_tasks = 0, n_draw32_tasks = 0;
@@ -308,6 +308,10 @@ hipError_t launch_mala_accept(fh_plan p, void* aux, const void* prop, const void
 hipError_t launch_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
                        void* grad_aux, hipStream_t s);
 hipError_t launch_grad_reduce(fh_plan p, double* logZ, double* grad_t, hipStream_t s);
+// grad_aux = per chain, the sum of its groups' partial slabs in group order (every adjoint).
+hipError_t launch_gpart_reduce(fh_plan p, void* grad_aux, hipStream_t s);
+// energy[c] <- -(t_c / beta_c) energy[c]: d log Z_path / d t into the kinetic-energy estimate.
+hipError_t launch_kinetic_scale(fh_plan p, double* energy, hipStream_t s);
 hipError_t launch_grad_mfma(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
                             void* grad_aux, hipStream_t s);
 hipError_t launch_zero(void* ptr, int64_t bytes, hipStream_t s);

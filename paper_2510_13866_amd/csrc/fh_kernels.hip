@@ -1869,15 +1869,16 @@ __global__ __launch_bounds__(kThreads) void k_measure_reduce(
 // (times the spin's coefficient) and d log Z / dt += <dG/dt * u_{j+1}, f~_j> / <beta_j, f~_j>.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_grad(
-    const ChainInfo* __restrict__ chains, const PairTask* __restrict__ tasks,
+    const ChainInfo* __restrict__ chains, const GroupTask* __restrict__ groups,
     const double* __restrict__ tables, const T* __restrict__ aux, const T* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, T* __restrict__ filt, double* __restrict__ blk_logz,
-    double* __restrict__ dt_out, T* grad_aux, int anchor, const int32_t* __restrict__ perm,
-    int32_t* status, int maxN, int maxL) {
+    double* __restrict__ dt_out, T* __restrict__ gpart, int anchor,
+    const int32_t* __restrict__ perm, int32_t* status, int maxN, int maxL) {
     extern __shared__ __align__(16) unsigned char smem[];
     FftLds<T> l = carve<T>(smem, maxN, maxL, true);
-    const PairTask t = tasks[blockIdx.x];
+    const GroupTask g = groups[blockIdx.x];  // one or two worldlines of one (chain, spin)
+    const PairTask t = {g.chain, g.p0, g.count > 1 ? g.p0 + 1 : -1, 0};
     const ChainInfo& c = chains[t.chain];
     const int N = c.N, L = c.L, L_tau = c.L_tau;
     const bool has_b = t.p_b >= 0;
@@ -1905,7 +1906,9 @@ __global__ __launch_bounds__(kThreads) void k_grad(
     for (int r = threadIdx.x; r < N; r += blockDim.x)
         l.U[r] = {r == e_a ? T(1) : T(0), (has_b && r == e_b) ? T(1) : T(0)};
     double dta = 0.0, dtb = 0.0;
-    T* gl = grad_aux ? grad_aux + c.aux_off : nullptr;
+    // the pair's own partial field-gradient slab [L_tau][N]; k_gpart_reduce adds a chain's slabs
+    // in group order, so the field gradient is the same on every call
+    T* gl = gpart ? gpart + g.part_off : nullptr;
     for (int j = L_tau - 1; j >= 0; --j) {
         const int lj = (anchor + j) % L_tau;
         __syncthreads();
@@ -1940,7 +1943,7 @@ __global__ __launch_bounds__(kThreads) void k_grad(
             for (int r = threadIdx.x; r < N; r += blockDim.x) {
                 double v = ka * (double)fa[r] * (double)l.A[r].re;
                 if (has_b) v += kb * (double)fb[r] * (double)l.A[r].im;
-                atomicAdd(&gl[(int64_t)lj * N + r], (T)v);
+                gl[(int64_t)lj * N + r] = (T)v;
             }
         }
         if (j > 0) {
@@ -2433,21 +2436,38 @@ hipError_t launch_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t
                        void* grad_aux, hipStream_t s) {
     const size_t lds = grad_lds_bytes(p);
     hipError_t e;
+    void* slabs = grad_aux ? p->d.gpart : nullptr;  // the field gradient only when asked for
     if (p->precision == FH_FP64) {
         if ((e = allow_lds(k_grad<double>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_grad<double>, dim3(p->n_grad_tasks), dim3(kThreads), lds, s,
-                           p->d.chains, p->d.grad_tasks, p->d.tables, (const double*)aux,
-                           (const double*)p->d.W,
-                           p->d.wshift, p->aux_elems, p->total_slices, paths, (double*)p->d.filt, p->d.blk_logz, p->d.dt,
-                           (double*)grad_aux, anchor, p->d.perm, p->d.status, p->max_N, p->max_L);
+        hipLaunchKernelGGL(k_grad<double>, dim3(p->n_groups), dim3(kThreads), lds, s,
+                           p->d.chains, p->d.group_tasks, p->d.tables, (const double*)aux,
+                           (const double*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
+                           paths, (double*)p->d.filt, p->d.blk_logz, p->d.dt, (double*)slabs,
+                           anchor, p->d.perm, p->d.status, p->max_N, p->max_L);
     } else {
         if ((e = allow_lds(k_grad<float>, lds)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_grad<float>, dim3(p->n_grad_tasks), dim3(kThreads), lds, s,
-                           p->d.chains, p->d.grad_tasks, p->d.tables, (const float*)aux,
-                           (const float*)p->d.W,
-                           p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt, p->d.blk_logz, p->d.dt,
-                           (float*)grad_aux, anchor, p->d.perm, p->d.status, p->max_N, p->max_L);
+        hipLaunchKernelGGL(k_grad<float>, dim3(p->n_groups), dim3(kThreads), lds, s,
+                           p->d.chains, p->d.group_tasks, p->d.tables, (const float*)aux,
+                           (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
+                           paths, (float*)p->d.filt, p->d.blk_logz, p->d.dt, (float*)slabs,
+                           anchor, p->d.perm, p->d.status, p->max_N, p->max_L);
     }
+    if ((e = hipGetLastError()) != hipSuccess || !grad_aux) return e;
+    return launch_gpart_reduce(p, grad_aux, s);
+}
+
+__global__ void k_kinetic_scale(const ChainInfo* __restrict__ chains, int n_chains,
+                                double* __restrict__ energy) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n_chains) {
+        const ChainInfo& ci = chains[c];
+        energy[c] *= -ci.hop_t / ((double)ci.L_tau * ci.dtau);
+    }
+}
+
+hipError_t launch_kinetic_scale(fh_plan p, double* energy, hipStream_t s) {
+    hipLaunchKernelGGL(k_kinetic_scale, dim3((unsigned)((p->n_chains + 63) / 64)), dim3(64), 0, s,
+                       p->d.chains, p->n_chains, energy);
     return hipGetLastError();
 }
 

@@ -1431,11 +1431,20 @@ hipError_t launch_grad_mfma(fh_plan p, const void* aux, const int32_t* paths, in
                            (float*)p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm, p->d.status, kNegPairs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !grad_aux) return e;
+    return launch_gpart_reduce(p, grad_aux, s);
+}
+
+hipError_t launch_gpart_reduce(fh_plan p, void* grad_aux, hipStream_t s) {
     int64_t b = (p->aux_elems + kThreads - 1) / kThreads;
     if (b > 65536) b = 65536;
-    hipLaunchKernelGGL(k_gpart_reduce<float>, dim3((unsigned)b), dim3(kThreads), 0, s,
-                       p->d.chains, p->n_chains, p->d.group_tasks, (const float*)p->d.gpart,
-                       (float*)grad_aux, p->aux_elems);
+    if (p->precision == FH_FP64)
+        hipLaunchKernelGGL(k_gpart_reduce<double>, dim3((unsigned)b), dim3(kThreads), 0, s,
+                           p->d.chains, p->n_chains, p->d.group_tasks, (const double*)p->d.gpart,
+                           (double*)grad_aux, p->aux_elems);
+    else
+        hipLaunchKernelGGL(k_gpart_reduce<float>, dim3((unsigned)b), dim3(kThreads), 0, s,
+                           p->d.chains, p->n_chains, p->d.group_tasks, (const float*)p->d.gpart,
+                           (float*)grad_aux, p->aux_elems);
     return hipGetLastError();
 }
 
@@ -1448,12 +1457,7 @@ hipError_t launch_grad_dmfma(fh_plan p, const void* aux, const int32_t* paths, i
                        p->d.status);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !grad_aux) return e;
-    int64_t b = (p->aux_elems + kThreads - 1) / kThreads;
-    if (b > 65536) b = 65536;
-    hipLaunchKernelGGL(k_gpart_reduce<double>, dim3((unsigned)b), dim3(kThreads), 0, s,
-                       p->d.chains, p->n_chains, p->d.group_tasks, (const double*)p->d.gpart,
-                       (double*)grad_aux, p->aux_elems);
-    return hipGetLastError();
+    return launch_gpart_reduce(p, grad_aux, s);
 }
 
 }  // namespace fh

@@ -85,6 +85,7 @@ _sig("fh_mala_field", c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_double, 
      c_void_p)
 _sig("fh_logZ_grad", c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
      c_void_p, c_void_p)
+_sig("fh_kinetic_energy", c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p)
 _sig("fh_set_hopping", c_int32, c_void_p, POINTER(c_double))
 _sig("fh_get_status", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32))
 _sig("fh_get_filters", c_int32, c_void_p, c_int32, c_int32, c_void_p, c_int64, POINTER(c_int64),
@@ -195,6 +196,11 @@ def fh_logZ_grad(plan, aux, paths, anchor_slice, logZ=None, grad_aux=None, grad_
                  stream=None):
     _check(lib.fh_logZ_grad(plan, _ptr(aux), _ptr(paths), int(anchor_slice), _ptr(logZ),
                             _ptr(grad_aux), _ptr(grad_t), _stream(stream)), "fh_logZ_grad")
+
+
+def fh_kinetic_energy(plan, aux, paths, anchor_slice, energy, stream=None):
+    _check(lib.fh_kinetic_energy(plan, _ptr(aux), _ptr(paths), int(anchor_slice), _ptr(energy),
+                                 _stream(stream)), "fh_kinetic_energy")
 
 
 def fh_set_hopping(plan, t_values):

@@ -140,12 +140,10 @@ class Sampler:
         return acc.cpu().numpy()
 
     def kinetic_energy(self, aux, paths, anchor_slice, stream=None) -> np.ndarray:
-        """Rao-Blackwellised kinetic-energy estimate per chain, -(t / beta) d log Z_path / d t
-        (beta = L_tau dtau): the hopping term's expectation with the paths summed out given the
-        anchor sites, from the adjoint's d/dt."""
-        _, _, grad_t = self.logz_grad(aux, paths, anchor_slice, stream)
-        g = grad_t.cpu().numpy()
-        return np.array([-d.t / (d.L_tau * d.dtau) * g[c] for c, d in enumerate(self.descs)])
+        """Rao-Blackwellised kinetic-energy estimate per chain (fh_kinetic_energy)."""
+        out = torch.empty(len(self.descs), dtype=torch.float64, device=self.device)
+        fhmc.fh_kinetic_energy(self.plan, aux, paths, anchor_slice, out, stream)
+        return out.cpu().numpy()
 
     def filters(self, chain, particle) -> np.ndarray:
         rows = fhmc.fh_get_filters(self.plan, chain, particle)

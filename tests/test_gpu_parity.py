@@ -1104,6 +1104,61 @@ def test_logz_grad_mfma_full_lattice_repeatable(lib):
     S.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64fft", "fp32"])
+def test_logz_grad_fft_repeatable(lib, prec):
+    """The FFT adjoints (worldlines in pairs, an odd one alone) write per-pair partial field
+    gradients that are added per chain in a fixed order: two calls give identical bits, and
+    both match the oracle."""
+    fhmc, sampler = lib
+    descs = [synth.ChainDesc(L=12, L_tau=24, n_up=5, n_dn=4, hs_kind=synth.HS_GAUSS,
+                             block_len=0, t=1.0, U=4.0, dtau=0.1, seed=31),
+             synth.ChainDesc(L=48, L_tau=16, n_up=3, n_dn=2, hs_kind=synth.HS_HIRSCH,
+                             block_len=0, t=1.0, U=4.0, dtau=0.1, seed=32)]
+    S = sampler.Sampler(descs, PRECS[prec], plan_flags(fhmc, prec))
+    aux, paths = mixed_state(descs, seed=23)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    lz1, g1, t1 = S.logz_grad(A, P, 3)
+    lz2, g2, t2 = S.logz_grad(A, P, 3)
+    assert S.status() == (0, -1)
+    assert torch.equal(g1, g2) and torch.equal(t1, t2) and torch.equal(lz1, lz2)
+    gA = S.unpack_aux(g1)
+    tol = 1e-10 if prec == "fp64fft" else 1e-4
+    for c, d in enumerate(descs):
+        lz, g, gt, _ = ograd.logz_path_grad(d, aux[c], paths[c], 3)
+        assert np.linalg.norm(gA[c] - g) <= tol * np.linalg.norm(g), c
+        assert t1[c].item() == pytest.approx(gt, rel=tol), c
+    S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp64fft", "mfma3"])
+def test_kinetic_energy_parity(lib, prec):
+    """fh_kinetic_energy against -(t/beta) d log Z_path / dt of the oracle's adjoint at U != 0,
+    with a hopping amplitude other than 1 (the scale takes each chain's own t and beta)."""
+    fhmc, sampler = lib
+    descs = [synth.ChainDesc(L=8, L_tau=20, n_up=4, n_dn=3, hs_kind=synth.HS_GAUSS,
+                             block_len=0, t=0.8, U=4.0, dtau=0.1, seed=41),
+             synth.ChainDesc(L=6, L_tau=12, n_up=3, n_dn=3, hs_kind=synth.HS_HIRSCH,
+                             block_len=0, t=1.3, U=2.0, dtau=0.125, seed=42)]
+    S = sampler.Sampler(descs, PRECS[prec], plan_flags(fhmc, prec))
+    aux, paths = mixed_state(descs, seed=25)
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    ek = S.kinetic_energy(A, P, 4)
+    assert S.status() == (0, -1)
+    tol = 1e-10 if prec.startswith("fp64") else 1e-4
+    for c, d in enumerate(descs):
+        _, _, gt, _ = ograd.logz_path_grad(d, aux[c], paths[c], 4)
+        assert ek[c] == pytest.approx(-d.t / (d.L_tau * d.dtau) * gt, rel=tol), c
+    S.set_hopping([0.9, 1.1])
+    ek = S.kinetic_energy(A, P, 4)
+    for c, d in enumerate(descs):
+        d2 = dataclasses.replace(d, t=[0.9, 1.1][c])
+        _, _, gt, _ = ograd.logz_path_grad(d2, aux[c], paths[c], 4)
+        assert ek[c] == pytest.approx(-d2.t / (d2.L_tau * d2.dtau) * gt, rel=tol), c
+    with pytest.raises(fhmc.FhError):
+        S.kinetic_energy(A, P, 12)
+    S.close()
+
+
 WINDOW_BATCH = MIXED + [
     synth.ChainDesc(L=32, L_tau=40, n_up=6, n_dn=5, hs_kind=synth.HS_GAUSS, block_len=0,
                     t=1.0, U=4.0, dtau=0.05, seed=61),
