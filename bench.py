@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="FFT plans (--precision fp32 or fp64 with L > 32): time every radix-2/3/4 "
                          "stage order per lattice size at plan creation (FH_FLAG_AUTOTUNE)")
+    ap.add_argument("--grad-checkpoint", action="store_true",
+                    help="grad / mala workloads: the adjoint keeps every ceil(sqrt(L_tau))-th "
+                         "ring row and recomputes the rest (FH_FLAG_GRAD_CHECKPOINT)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--workload", default="32x32",
@@ -256,10 +259,16 @@ def other_workload(args):
     sites = sum(d.N * d.L_tau for d in descs)
     log("bench: %s workload, %s, %d chains" % (args.workload, prec_name, len(descs)))
     flags = fhmc.FH_FLAG_GRAPH | (fhmc.FH_FLAG_AUTOTUNE if args.autotune else 0)
+    if args.grad_checkpoint:
+        flags |= fhmc.FH_FLAG_GRAD_CHECKPOINT
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
     S = Sampler(descs, prec, flags)
     A, P = S.pack_aux(aux), S.pack_paths(paths)
     torch.cuda.synchronize()
     extra = {}
+    if args.grad_checkpoint:
+        extra["grad_checkpoint"] = True
     if args.autotune:  # the stage order chosen per lattice size
         chosen = {}
         for c, d in enumerate(descs):
@@ -276,6 +285,9 @@ def other_workload(args):
             for _ in range(args.warmup):
                 fhmc.fh_logZ_grad(S.plan, A, P, 0, logZ, gA, gT, stream)
             torch.cuda.synchronize()
+            # device memory taken by the plan and the call's buffers (the library allocates
+            # with hipMalloc; free memory before the plan and after the warm-up calls)
+            extra["device_bytes_plan_and_buffers"] = free0 - torch.cuda.mem_get_info()[0]
             e0.record(stream)
             for i in range(args.steps):
                 fhmc.fh_logZ_grad(S.plan, A, P, i % descs[0].L_tau, logZ, gA, gT, stream)
@@ -294,6 +306,7 @@ def other_workload(args):
             for i in range(max(1, args.warmup)):
                 fhmc.fh_mala_field(S.plan, A, P, 0, 0.02, i, acc, stream)
             torch.cuda.synchronize()
+            extra["device_bytes_plan_and_buffers"] = free0 - torch.cuda.mem_get_info()[0]
             e0.record(stream)
             for i in range(args.steps):
                 fhmc.fh_mala_field(S.plan, A, P, i % descs[0].L_tau, 0.02, 100 + i, acc, stream)
@@ -456,17 +469,26 @@ def main():
     # (fh_debug_sweep_timing) around the forward-filter kernels, the backward kernels and the
     # FP64 re-filter: the same chain is run again from the same input, eagerly (it is
     # deterministic, so it passes through the same states; checked below), reading the events
-    # after every sweep, and the segments are averaged over the timed sweeps.
+    # after every sweep, and the segments are averaged over the timed sweeps. Per sweep it also
+    # counts the chains the FP32 kernels worked on: the forward kernels skip the chains held on
+    # the FP64 re-filter at the start of the sweep, the backward kernels every chain re-filtered
+    # whole in it.
     St = Sampler(descs, prec, fhmc.FH_FLAG_GRAPH | draw_flag)
     At, Pt = St.pack_aux(aux), St.pack_paths(paths)
     assert fhmc.lib.fh_debug_sweep_timing(St.plan, 1) == 0
     run_chain(St, At, Pt, 0, args.warmup, stream)
     seg = [0.0, 0.0, 0.0]
+    fwd_chains, bwd_chains = [], []
     with torch.cuda.stream(stream):
         for i in range(args.steps):
+            held = fhmc.fh_debug_rescue_holds(St.plan, len(descs))
+            fhmc.fh_debug_rescue(St.plan)  # the queue counters restart for this sweep
             St.sweep(At, Pt, args.warmup + i, 1, stream)
             for k, v in enumerate(fhmc.fh_debug_sweep_times(St.plan)):
                 seg[k] += v
+            whole = fhmc.fh_debug_rescue(St.plan)[3]
+            fwd_chains.append(int(np.sum(held == 0)))
+            bwd_chains.append(len(descs) - whole)
     torch.cuda.synchronize()
     if not (torch.equal(At, A) and torch.equal(Pt, P)):
         raise RuntimeError("the timing replay did not reproduce the timed chain")
@@ -478,14 +500,21 @@ def main():
     log("  per sweep: forward %.3f ms, backward %.3f ms, FP64 re-filter %.3f ms" %
         (fwd_ms, bwd_ms, rescue_ms))
     rsz = 8 if args.precision == "fp64" else 4
-    rows = sum(d.n_particles * (d.L_tau - 1) for d in descs)       # one block per worldline
-    N = descs[0].N
-    w_bytes = sum(2 * d.L_tau * d.N * rsz for d in descs)         # site potentials, both spins
+    d0 = descs[0]                                                  # every chain has this shape
+    rows = d0.n_particles * (d0.L_tau - 1)                         # per chain: one block each
+    N = d0.N
+    w_bytes = 2 * d0.L_tau * N * rsz                               # site potentials, both spins
     # backward: the full-row kernel reads every filter row; the windowed one reads the 7 x 7
     # window around the next slice's site (half-width 3 at dtau = 0.05), fallbacks aside
     read_per_row = N * rsz if args.full_row_draw else 49 * rsz
-    algo = {"forward": rows * N * rsz + w_bytes,
-            "backward": rows * (read_per_row + 4)}                 # + the drawn site (int32)
+    # per launch, averaged over the timed sweeps: the chains each launch worked on
+    fwd_avg = sum(fwd_chains) / args.steps
+    bwd_avg = sum(bwd_chains) / args.steps
+    algo = {"forward": round(fwd_avg * (rows * N * rsz + w_bytes)),
+            "backward": round(bwd_avg * rows * (read_per_row + 4))}  # + the drawn site (int32)
+    extra["fp32_kernel_chains_per_launch"] = {
+        "forward": fwd_avg, "backward": bwd_avg, "of": len(descs),
+        "last_3_sweeps": {"forward": fwd_chains[-3:], "backward": bwd_chains[-3:]}}
     times = {"forward": fwd_ms, "backward": bwd_ms}
     fwd_kernel = {"fp32_mfma3": "k_forward_mfma2", "fp64": "k_forward_dmfma"}.get(args.precision,
                                                                                  "k_forward_fft")
@@ -508,14 +537,14 @@ def main():
         # the same forward launch against the matrix cores: 24 bf16 MFMA 32x32x16 per
         # worldline-step (two circulant products, three-term splits, six products each); a
         # block of L_tau slices takes L_tau - 1 steps and one more product for its end weight
-        flops = sum(d.n_particles * d.L_tau for d in descs) * 24 * 32 * 32 * 16 * 2
+        flops = round(fwd_avg * d0.n_particles * d0.L_tau * 24 * 32 * 32 * 16 * 2)
         tf = flops / (times["forward"] / 1e3) / 1e12
         roofs["forward"]["matrix_cores"] = {
             "achieved": round(tf, 1), "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
             "frac": round(tf / BF16_PEAK_TFS, 4), "flops_per_launch": flops, "dtype": "bf16"}
     elif args.precision == "fp64":
         # FP64 circulant: 64 v_mfma_f64_16x16x4_f64 per worldline-step
-        flops = sum(d.n_particles * d.L_tau for d in descs) * 64 * 16 * 16 * 4 * 2
+        flops = round(fwd_avg * d0.n_particles * d0.L_tau * 64 * 16 * 16 * 4 * 2)
         tf = flops / (times["forward"] / 1e3) / 1e12
         roofs["forward"]["matrix_cores"] = {
             "achieved": round(tf, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",

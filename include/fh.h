@@ -95,7 +95,7 @@ enum fh_flags {
                             chains with L <= 32 use the circulant C f C on the FP64 matrix cores
                             (every product positive, so filter tails keep their relative
                             accuracy); larger L always use the FFT                             */
-    FH_FLAG_FULL_ROW_DRAW = 4 /* backward draws scan every site of the filter row. Without it a
+    FH_FLAG_FULL_ROW_DRAW = 4, /* backward draws scan every site of the filter row. Without it a
                             chain whose hopping kernel decays fast enough draws from the window
                             of sites within w <= 3 steps of the next slice's site and certifies
                             that the draw equals the full-row one (else scans the row): the
@@ -103,6 +103,17 @@ enum fh_flags {
                             3/20 of a backward pass's draws uncertified (clustered states), the
                             plan draws the following passes with the full-row kernels and
                             retries the window after 16 to 64 passes; the draws are the same */
+    FH_FLAG_GRAD_CHECKPOINT = 16 /* the adjoint (fh_logZ_grad, fh_kinetic_energy,
+                            fh_mala_field) keeps every K-th ring row, K = ceil(sqrt(L_tau)), and
+                            recomputes each segment of K rows from its checkpoint during the
+                            backward messages: about 2 sqrt(L_tau) rows per worldline instead
+                            of L_tau, for one more forward recursion; the results are the
+                            same bits. The filter workspace of the sweep (L_tau rows per
+                            worldline) is then allocated only by the first fh_forward_filter
+                            or fh_sweep, and fh_get_filters returns FH_ERR_STATE after the
+                            adjoint. Needs the matrix-core adjoint: FH_FP32_MFMA3, or FH_FP64
+                            without FH_FLAG_FFT_CONV, every chain with L <= 32 (else fh_init
+                            returns FH_ERR_UNSUPPORTED)                                       */
 };
 
 /* One chain. block_len: FFBS block length B (0 = L_tau, one block closing the ring);

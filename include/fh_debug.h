@@ -78,8 +78,8 @@ int fh_debug_backward_kernels(fh_plan plan, int32_t* n_windowed, int32_t* n_full
 int fh_debug_backward_adapt(fh_plan plan, int32_t enable, int32_t* full_row_passes_left);
 
 /* FP32 plans queue the blocks whose filters leave FP32's range (see the range note of fh.h),
- * and every block of a chain that had such a block in this or one of the two preceding forward
- * passes, for an FP64 re-filter and redraw. fh_debug_rescue synchronises the device and reports
+ * and every block of a chain that had such a block in this or one of the four preceding forward
+ * passes, for an FP64 re-filter and redraw (the FP32 forward kernels skip the chains held so). fh_debug_rescue synchronises the device and reports
  * the queue of the last forward pass (with what its backward pass added): last_count
  * (nullable) receives its length, whole_chains (nullable) the chains queued whole, total
  * (nullable) the blocks redrawn by every backward pass since the previous call (then reset to
@@ -87,6 +87,10 @@ int fh_debug_backward_adapt(fh_plan plan, int32_t enable, int32_t* full_row_pass
  * min(cap, last_count) queued blocks as (chain, particle, block). FP64 plans report 0. */
 int fh_debug_rescue(fh_plan plan, int32_t* last_count, int32_t* whole_chains, int64_t* total,
                     int32_t* list, int32_t cap);
+/* Synchronises the device and writes to holds (caller-owned host memory, [n_chains]) the forward
+ * passes each chain stays on the FP64 re-filter: a chain with L <= 32 and holds[c] > 0 is
+ * skipped by the next forward pass's FP32 kernels and re-filtered whole. FP64 plans write 0. */
+int fh_debug_rescue_holds(fh_plan plan, int32_t* holds);
 
 /* Per-sweep timing for the benchmark: with enable = 1, every sweep of fh_sweep records HIP events
  * of the plan around its forward-filter kernels, its backward-sampling kernels and the FP64

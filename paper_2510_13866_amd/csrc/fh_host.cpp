@@ -187,7 +187,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.draw_tasks, d.group_tasks, d.gpart, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
+                    d.draw_tasks, d.group_tasks, d.gpart, d.ckpt, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
                     d.rescue, d.rescue_list, d.rescue_ws, d.rescue_w, d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -242,7 +242,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (precision != FH_FP64 && precision != FH_FP32 && precision != FH_FP32_MFMA3)
         return FH_ERR_INVALID_ARG;
     if (flags & ~(uint32_t)(FH_FLAG_GRAPH | FH_FLAG_AUTOTUNE | FH_FLAG_FULL_ROW_DRAW |
-                            FH_FLAG_FFT_CONV))
+                            FH_FLAG_FFT_CONV | FH_FLAG_GRAD_CHECKPOINT))
         return FH_ERR_INVALID_ARG;
     for (int c = 0; c < n_chains; ++c) {
         int v = validate(descs[c], precision);
@@ -346,20 +346,36 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     // signal = two worldlines per group); FP32 plans run the matrix-core adjoint
     p->grad_dmfma = precision == FH_FP64 && !(flags & FH_FLAG_FFT_CONV);
     for (const ChainInfo& ci : p->chains) p->grad_dmfma = p->grad_dmfma && ci.L <= 32;
-    const int gsize = (precision == FH_FP32_MFMA3 || p->grad_dmfma) ? kGroup : 2;
-    int64_t gpart = 0;
+    const bool mfma_grad = precision == FH_FP32_MFMA3 || p->grad_dmfma;
+    // checkpoints are built into the matrix-core adjoints only (every chain with L <= 32)
+    const bool ckpt = (flags & FH_FLAG_GRAD_CHECKPOINT) != 0;
+    if (ckpt && !(mfma_grad && p->max_L <= 32)) {
+        delete p;
+        return FH_ERR_UNSUPPORTED;
+    }
+    const int gsize = mfma_grad ? kGroup : 2;
+    int64_t gpart = 0, ck_rows = 0;
+    for (int c = 0; c < n_chains; ++c) {  // checkpoint rows: ceil(L_tau / K) per worldline
+        ChainInfo& ci = p->chains[c];
+        ci.ck_k = (int32_t)ceil(sqrt((double)ci.L_tau));
+        ci.ck_n = (ci.L_tau + ci.ck_k - 1) / ci.ck_k;
+        ci.ck_row_off = ck_rows;
+        ck_rows += (int64_t)ci.np * ci.ck_n * ci.N;
+    }
     for (int c = 0; c < n_chains; ++c) {  // gradient groups in chain order (reduced per chain)
         ChainInfo& ci = p->chains[c];
         ci.g0 = (int32_t)groups.size();
         for (int spin = 0; spin < 2; ++spin) {
             int p0 = spin ? ci.n_up : 0, p1 = spin ? ci.np : ci.n_up;
             for (int q = p0; q < p1; q += gsize) {
-                groups.push_back({c, q, std::min(gsize, p1 - q), spin, gpart});
+                groups.push_back({c, q, std::min(gsize, p1 - q), spin, gpart, ck_rows});
                 gpart += (int64_t)ci.L_tau * ci.N;
+                ck_rows += (int64_t)kGroup * (ci.ck_k - 1) * ci.N;  // segment rows per wavefront
             }
         }
         ci.g1 = (int32_t)groups.size();
     }
+    p->ckpt_elems = ckpt ? ck_rows : 0;
     for (int c : order) {
         const ChainInfo& ci = p->chains[c];
         for (int spin = 0; spin < 2; ++spin) {
@@ -457,7 +473,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.cmat, sizeof(uint16_t) * p->cmat.size());
     if (e == hipSuccess) e = dalloc(&dv.W, rs * 2 * (size_t)aux);
     if (e == hipSuccess) e = dalloc(&dv.wshift, sizeof(double) * 2 * (size_t)slices);
-    if (e == hipSuccess) e = dalloc(&dv.filt, rs * (size_t)filt);
+    if (e == hipSuccess && !ckpt) e = dalloc(&dv.filt, rs * (size_t)filt);
+    if (e == hipSuccess && ckpt) e = dalloc(&dv.ckpt, rs * (size_t)p->ckpt_elems);
     if (e == hipSuccess) e = dalloc(&dv.blk_logz, sizeof(double) * (size_t)blk);
     if (e == hipSuccess) e = dalloc(&dv.dt, sizeof(double) * (size_t)part);
     if (e == hipSuccess) e = dalloc(&dv.fwd_tasks, sizeof(PairTask) * fwdf.size());
@@ -484,7 +501,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         e = dalloc(&dv.rescue, sizeof(int32_t) * words);
         if (e == hipSuccess) e = hipMemset(dv.rescue, 0, sizeof(int32_t) * words);
         if (e == hipSuccess) e = dalloc(&dv.rescue_list, sizeof(DrawTask) * draw.size());
-        if (e == hipSuccess)
+        if (e == hipSuccess && !ckpt)
             e = dalloc(&dv.rescue_ws, sizeof(double) * (size_t)p->n_rescue_slots * p->rescue_slot_elems);
         if (e == hipSuccess) e = dalloc(&dv.rescue_w, sizeof(double) * 2 * (size_t)aux);
     }
@@ -627,10 +644,25 @@ static hipError_t enqueue_forward(fh_plan p, const void* aux, const int32_t* pat
     return e;
 }
 
+// FH_FLAG_GRAD_CHECKPOINT plans allocate the filter workspace (and on FP32 plans the FP64
+// re-filter's rows) at the first call that runs a forward filter, after the work queued on s:
+// a plan used only for the adjoint never holds them.
+static hipError_t ensure_filters(fh_plan p, hipStream_t s) {
+    if (p->d.filt && (p->d.rescue_ws || !p->d.rescue)) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess && !p->d.filt)
+        e = hipMalloc(&p->d.filt, p->real_size * (size_t)std::max<int64_t>(p->filt_elems, 1));
+    if (e == hipSuccess && p->d.rescue && !p->d.rescue_ws)
+        e = hipMalloc(&p->d.rescue_ws,
+                      sizeof(double) * (size_t)p->n_rescue_slots * p->rescue_slot_elems);
+    return e;
+}
+
 int fh_forward_filter(fh_plan p, const void* aux, const int32_t* paths, uint64_t sweep,
                       double* logZ, fh_stream stream) {
     if (!p || !aux || !paths) return FH_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
+    FH_TRY(ensure_filters(p, s));
     FH_TRY(launch_set_sweep(p, sweep, s));
     FH_TRY(enqueue_forward(p, aux, paths, s));
     FH_TRY(launch_rescue(p, aux, const_cast<int32_t*>(paths), false, s));  // FP64 log Z, rows
@@ -790,6 +822,7 @@ int fh_sweep(fh_plan p, void* aux, int32_t* paths, uint64_t first_sweep, int32_t
     if (!p || !aux || !paths || n_sweeps < 0) return FH_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
     if (n_sweeps == 0) return FH_OK;
+    FH_TRY(ensure_filters(p, s));
     if ((p->flags & FH_FLAG_GRAPH) && !p->timing) {  // timed sweeps run eagerly (their events)
         if (!p->graph_exec || p->graph_aux != aux || p->graph_paths != paths) {
             // capture on the plan's stream after the caller's queued work is done
@@ -833,7 +866,7 @@ int fh_logZ_grad(fh_plan p, const void* aux, const int32_t* paths, int32_t ancho
         if (anchor_slice < 0 || anchor_slice >= c.L_tau) return FH_ERR_INVALID_ARG;
     FH_TRY(enqueue_logz_grad(p, aux, paths, anchor_slice, logZ, grad_aux, grad_t,
                              (hipStream_t)stream));
-    p->have_filters = true;
+    p->have_filters = p->d.ckpt == nullptr;  // with checkpoints the ring rows are not kept
     p->filters_are_ring = true;
     return FH_OK;
 }
@@ -848,7 +881,7 @@ int fh_kinetic_energy(fh_plan p, const void* aux, const int32_t* paths, int32_t 
     // d log Z_path / dt lands in energy (no field gradient, no log Z), then is scaled in place
     FH_TRY(enqueue_logz_grad(p, aux, paths, anchor_slice, nullptr, nullptr, energy, s));
     FH_TRY(launch_kinetic_scale(p, energy, s));
-    p->have_filters = true;
+    p->have_filters = p->d.ckpt == nullptr;
     p->filters_are_ring = true;
     return FH_OK;
 }
@@ -941,7 +974,7 @@ int fh_get_filters(fh_plan p, int32_t chain, int32_t particle, void* dst, int64_
     if (!p || chain < 0 || chain >= p->n_chains) return FH_ERR_INVALID_ARG;
     const ChainInfo& c = p->chains[chain];
     if (particle < 0 || particle >= c.np) return FH_ERR_INVALID_ARG;
-    if (!p->have_filters) return FH_ERR_STATE;
+    if (!p->have_filters || !p->d.filt) return FH_ERR_STATE;
     const int64_t rows = p->filters_are_ring ? c.L_tau : c.L_tau - c.nb;
     if (n_rows) *n_rows = rows;
     if (!dst) return FH_OK;
@@ -1179,6 +1212,16 @@ int fh_debug_rescue(fh_plan p, int32_t* last_count, int32_t* whole_chains, int64
             list[3 * i + 2] = t[i].block;
         }
     }
+    return FH_OK;
+}
+
+int fh_debug_rescue_holds(fh_plan p, int32_t* holds) {
+    if (!p || !holds) return FH_ERR_INVALID_ARG;
+    std::fill(holds, holds + p->n_chains, 0);
+    if (!p->d.rescue) return FH_OK;
+    FH_TRY(hipDeviceSynchronize());
+    FH_TRY(hipMemcpy(holds, p->d.rescue + kRescueChain + p->n_chains,
+                     sizeof(int32_t) * p->n_chains, hipMemcpyDeviceToHost));
     return FH_OK;
 }
 

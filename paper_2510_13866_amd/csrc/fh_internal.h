@@ -42,6 +42,11 @@ struct ChainInfo {
     float step_floor;
     double row_mass;
     int32_t whole_min;  // queued blocks of one pass above which the whole chain is queued
+    // FH_FLAG_GRAD_CHECKPOINT: the adjoint keeps ring rows j = 0, K, 2K, .. (K = ck_k =
+    // ceil(sqrt(L_tau)), ck_n = ceil(L_tau / K) of them per worldline) at
+    // ckpt[ck_row_off + (p ck_n + j / K) N] and recomputes each segment from its checkpoint
+    int64_t ck_row_off;
+    int32_t ck_k, ck_n;
 };
 
 // Offsets of the tables of one chain inside the double table buffer, relative to tab_off.
@@ -88,6 +93,7 @@ constexpr int kGroup = 4;
 struct GroupTask {
     int32_t chain, p0, count, spin;
     int64_t part_off;
+    int64_t seg_off;  // FH_FLAG_GRAD_CHECKPOINT: the group's segment rows [kWaves][K - 1][N]
 };
 
 // FP32 range. FP32 holds a value to full relative precision only down to ~2^-126, and the
@@ -104,15 +110,16 @@ struct GroupTask {
 // finds no positive weight (the draw's FP64 weights carry G exactly, so only the filter value
 // is in question). When a chain has a block queued in a forward pass (more than
 // whole_min), every block of the chain is re-filtered in FP64 in that pass and in the next
-// kRescueHold forward passes: on the way to a clustered state many blocks meet a floor and some
-// FP32 blocks drift without meeting one (a hop whose product underflows in one slice can move
-// log Z by 16 nats), while the blocks of a settled chain meet a floor all together or not at
-// all.
+// kRescueHold forward passes, which skip the chain's FP32 work: on the way to a clustered state
+// many blocks meet a floor and some FP32 blocks drift without meeting one (a hop whose product
+// underflows in one slice can move log Z by 16 nats), while the blocks of a settled chain meet a
+// floor all together or not at all. Every (kRescueHold + 1)-th pass of a held chain runs FP32
+// again to see whether it still needs FP64.
 constexpr int kWScaleLog2 = 100;
 constexpr int kRowExp = 20;
 constexpr float kRangeFloor = 0x1p-90f;
 constexpr double kRangeFloorD = 0x1p-90;
-constexpr int kRescueHold = 2;
+constexpr int kRescueHold = 4;
 // Size of the static scratch array of fh_measure_noalloc: 2^22 doubles (32 MiB) per GPU.
 constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // Rescue state words: [0] blocks queued in this pass, [1] blocks redrawn since the last read by
@@ -121,8 +128,9 @@ constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // (kRescueChain + n_chains + c), then one flag per (chain, particle, block) at
 // kRescueChain + 2 n_chains + blk_off + p nb + b (the `flags` pointer passed to the kernels).
 constexpr int kRescueChain = 4;
-// Wavefronts of the FP64 re-filter; each owns one slot of (B - 1) N doubles.
-constexpr int kRescueMaxSlots = 1024;
+// Wavefronts of the FP64 re-filter (two per SIMD of 256 CUs); each owns one slot of (B - 1) N
+// doubles.
+constexpr int kRescueMaxSlots = 2048;
 
 // Rescue state as the kernels see it: the words above, and the per-block flags.
 struct Rescue {
@@ -151,6 +159,12 @@ __device__ inline void rescue_push(const Rescue& r, const ChainInfo& c, int chai
 }
 __device__ inline bool rescue_queued(const Rescue& r, const ChainInfo& c, int p, int block) {
     return r.words && r.flags[c.blk_off + (int64_t)p * c.nb + block] != 0;
+}
+// The chain is held on the FP64 re-filter for this forward pass (k_rescue_expand queues it
+// whole whatever the FP32 pass finds): the FP32 forward kernels of chains with L <= 32 skip its
+// tasks.
+__device__ inline bool rescue_held(const Rescue& r, int chain) {
+    return r.words && r.words[kRescueChain + r.n_chains + chain] > 0;
 }
 
 // One autotuner timing: the radix order `plan` of lattice size L took `ms` per timing launch.
@@ -183,6 +197,8 @@ struct Device {
     DrawTask* draw32_tasks = nullptr;   // backward: worldline blocks of L = 32 chains
     DrawTask* draww_tasks = nullptr;    // backward, windowed draws (k_backward_win)
     DrawTask* drawx_tasks = nullptr;    // backward: the remaining chains (any L)
+    void* ckpt = nullptr;     // FH_FLAG_GRAD_CHECKPOINT: checkpoint and segment rows (plan
+                              // precision), in place of the ring rows in the filter workspace
     void* gpart = nullptr;    // matrix-core adjoints: per-group partial field gradients (plan
                               // precision: FP32 for FH_FP32_MFMA3, FP64 for the FP64 circulant)
     void* mala = nullptr;     // fh_mala_field: proposal, two gradients [3][aux_elems] in plan
@@ -234,6 +250,7 @@ struct fh_plan_s {
     bool bw_adapt = true;          // switch clustered chains to the full-row kernels
     int32_t n_full_only_tasks = 0; // backward tasks of chains that never use the window
     int64_t gpart_elems = 0;
+    int64_t ckpt_elems = 0;     // FH_FLAG_GRAD_CHECKPOINT: checkpoint + segment rows (elements)
     int32_t n_rescue_slots = 0;     // FP32 plans: wavefronts of k_rescue
     int64_t rescue_slot_elems = 0;  // doubles per slot: (B - 1) N of the largest L <= 32 chain
     int64_t total_sites = 0;  // sum of N over the chains

@@ -339,6 +339,8 @@ __global__ __launch_bounds__(kThreads) void k_forward_fft(
     FftLds<T> l = carve<T>(smem, maxN, maxL, false);
     const PairTask t = tasks[blockIdx.x];
     const ChainInfo& c = chains[t.chain];
+    // re-filtered whole in FP64 this pass (the whole workgroup leaves: no barrier is skipped)
+    if (c.L <= 32 && rescue_held(rsc, t.chain)) return;
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
     const bool has_b = t.p_b >= 0;
@@ -1305,7 +1307,7 @@ __device__ __attribute__((noinline)) void rescue_draws(const DrawTask& t, const 
 // FH_ERR_NONFINITE and keeps its sites. Every wavefront reads the queue length once and leaves
 // when its share is done.
 template <bool DRAW>
-__global__ __launch_bounds__(kThreads) void k_rescue(
+__global__ __launch_bounds__(kThreads, 2) void k_rescue(
     const ChainInfo* __restrict__ chains, const double* __restrict__ tables,
     const double* __restrict__ cmat64, const float* __restrict__ aux,
     const double* __restrict__ wshift, int64_t total_slices, int32_t* __restrict__ paths,

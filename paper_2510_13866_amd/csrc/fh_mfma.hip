@@ -32,6 +32,7 @@ typedef __attribute__((ext_vector_type(16))) float f32x16;
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+static_assert(kWaves == kGroup, "one adjoint worldline (and segment) per wavefront");
 
 __device__ inline int tile_row(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
 
@@ -145,6 +146,7 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
     const DrawTask t = tasks[task];
+    if (rescue_held(rsc, t.chain)) return;  // re-filtered whole in FP64 this pass
     const ChainInfo& c = chains[t.chain];
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
@@ -340,6 +342,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
     const PairTask t = tasks[task];
+    if (rescue_held(rsc, t.chain)) return;  // re-filtered whole in FP64 this pass
     const ChainInfo& c = chains[t.chain];
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
@@ -724,6 +727,7 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
     const PackTask t = tasks[task];
+    if (rescue_held(rsc, t.chain)) return;  // re-filtered whole in FP64 this pass
     const ChainInfo& c = chains[t.chain];
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
@@ -898,6 +902,50 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
     }
 }
 
+// One step of the adjoint's ring recursion for one worldline per wavefront:
+// F <- W~_l . (C F C) / total (W~ read from Wl, padded sites 0); returns 1 / total and sets
+// *bad when the total is not a positive finite number. The forward pass and the checkpoint
+// recompute share it, so the recomputed rows are the stored ones bit for bit.
+template <int LFIX>
+__device__ __forceinline__ float ring_step(f32x16& F, const float* Wl, const Split3& C,
+                                           const NegPairs& neg, int lane, int L, bool* bad) {
+    const int x = lane & 31;
+    const bool xin = LFIX ? true : x < L;
+    float w[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int y = tile_row(lane, v);
+        const bool in = LFIX ? true : (xin && y < L);
+        const float wv0 = Wl[in ? y * L + x : 0];
+        w[v] = in ? wv0 : 0.0f;
+    }
+    __builtin_amdgcn_sched_barrier(0);  // W in flight during the matrix work
+    const f32x16 X = circ_step(F, C, neg);
+    const f32x16 H = circ_step(X, C, neg);
+    float s = 0.0f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        F[v] = H[v] * w[v];
+        s += F[v];
+    }
+    const float tot = wave_sum_f32(s);
+    *bad = !(tot > 0.0f) || !isfinite(tot);
+    const float inv = __builtin_amdgcn_rcpf(tot);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) F[v] *= inv;
+    return inv;
+}
+
+template <int LFIX>
+__device__ __forceinline__ void ring_store(float* row, const f32x16& F, int lane, int L) {
+    const int x = lane & 31;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int y = tile_row(lane, v);
+        if (LFIX || (x < L && y < L)) row[y * L + x] = F[v];
+    }
+}
+
 // Adjoint of the forward filter over the ring anchored at `anchor` (one block of length L_tau,
 // closing on the anchor site e of the reconnected worldline, e = a without reconnection), on
 // the matrix cores. A workgroup takes up to kGroup worldlines of one (chain, spin), one per
@@ -911,14 +959,21 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
 // The marginals of the group are summed in LDS and written (times the spin's coefficient) to
 // the group's partial slab; k_gpart_reduce adds the slabs of a chain in a fixed order, so the
 // field gradient is the same on every call.
-template <int LFIX>
-__global__ __launch_bounds__(kThreads, 3) void k_grad_mfma(
+// With ckpt (FH_FLAG_GRAD_CHECKPOINT) the forward pass keeps only rows j = 0, K, 2K, .. (K =
+// ceil(sqrt(L_tau))); when the backward messages enter a segment sK .. sK + K - 1 from above,
+// every wavefront recomputes rows sK + 1 .. of it from checkpoint s with the same steps, into
+// its own K - 1 segment rows. The recomputed rows are bit-identical to the stored ones, so the
+// gradient is the same with and without checkpoints; rows held drop from L_tau to about
+// 2 sqrt(L_tau) per worldline, for one more forward recursion.
+template <int LFIX, bool CK>
+__global__ __launch_bounds__(kThreads, LFIX || !CK ? 3 : 2) void k_grad_mfma(
     const ChainInfo* __restrict__ chains, const GroupTask* __restrict__ groups,
     const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, float* __restrict__ filt, float* __restrict__ gpart,
     double* __restrict__ blk_logz, double* __restrict__ dt_out, int anchor,
-    const int32_t* __restrict__ perm, int32_t* status, const NegPairs neg) {
+    const int32_t* __restrict__ perm, int32_t* status, const NegPairs neg,
+    float* __restrict__ ckpt) {
     // beta tile of each wavefront with a halo row on each side: row y at (y + 1) * 32, row -1
     // repeats row L - 1 and row L repeats row 0, so the four-neighbour stencil reads at fixed
     // offsets from three per-lane bases
@@ -956,53 +1011,36 @@ __global__ __launch_bounds__(kThreads, 3) void k_grad_mfma(
     const bool xin = LFIX ? true : x < L;
     const int ax = a % L, ay = a / L, ex = e % L, ey = e / L;
     float* rows = filt + c.filt_off + (int64_t)p * L_tau * N;
-    // ---- forward pass over the ring, every row stored
+    constexpr bool ck = CK;  // ckpt is given exactly for CK
+    const int K = ck ? c.ck_k : 1;
+    float* ckrows = ck ? ckpt + c.ck_row_off + (int64_t)p * c.ck_n * N : nullptr;
+    float* seg = ck ? ckpt + g.seg_off + (int64_t)wv * (K - 1) * N : nullptr;
+    // ring row j: the filter workspace, or checkpoint j / K (j % K == 0) or row j % K - 1 of
+    // this wavefront's segment
+    auto ring_row = [&](int j) -> float* {
+        if (!ck) return rows + (int64_t)j * N;
+        const int sj = j / K, i = j - sj * K;
+        return i == 0 ? ckrows + (int64_t)sj * N : seg + (int64_t)(i - 1) * N;
+    };
+    // ---- forward pass over the ring, every row (every K-th with checkpoints) stored
     f32x16 F;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int y = tile_row(lane, v);
-        F[v] = (x == ax && y == ay) ? 1.0f : 0.0f;
-        if (real && (LFIX || (xin && y < L))) rows[y * L + x] = F[v];
-    }
+    for (int v = 0; v < 16; ++v) F[v] = (x == ax && tile_row(lane, v) == ay) ? 1.0f : 0.0f;
+    if (real) ring_store<LFIX>(ring_row(0), F, lane, L);
     double la = coef * (double)aux[c.aux_off + (int64_t)anchor * N + a];
     double prod = 1.0;
     for (int j = 1; j < L_tau; ++j) {
         const int l = (anchor + j) % L_tau;
-        const float* Wl = Wsp + (int64_t)l * N;
-        float w[16];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int y = tile_row(lane, v);
-            const bool in = LFIX ? true : (xin && y < L);
-            const float wv0 = Wl[in ? y * L + x : 0];
-            w[v] = in ? wv0 : 0.0f;
-        }
-        __builtin_amdgcn_sched_barrier(0);  // W in flight during the matrix work
-        const f32x16 X = circ_step(F, C, neg);
-        const f32x16 H = circ_step(X, C, neg);
-        float s = 0.0f;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            F[v] = H[v] * w[v];
-            s += F[v];
-        }
-        const float tot = wave_sum_f32(s);
-        if ((!(tot > 0.0f) || !isfinite(tot)) && real && lane == 0)
-            set_status(status, FH_ERR_NONFINITE, g.chain);
-        const float inv = __builtin_amdgcn_rcpf(tot);
+        bool bad;
+        const float inv = ring_step<LFIX>(F, Wsp + (int64_t)l * N, C, neg, lane, L, &bad);
+        if (bad && real && lane == 0) set_status(status, FH_ERR_NONFINITE, g.chain);
         prod *= (double)inv;
         if (!(prod > 1e-200 && prod < 1e200)) {
             la -= log(prod);
             prod = 1.0;
         }
         la += shift[l];
-        float* row = rows + (int64_t)j * N;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            F[v] *= inv;
-            const int y = tile_row(lane, v);
-            if (real && (LFIX || (xin && y < L))) row[y * L + x] = F[v];
-        }
+        if (real && j % K == 0) ring_store<LFIX>(ring_row(j), F, lane, L);
     }
     {
         const f32x16 X = circ_step(F, C, neg);
@@ -1030,8 +1068,27 @@ __global__ __launch_bounds__(kThreads, 3) void k_grad_mfma(
     float* btw = bt[wv] + 4 * (lane >> 5) * 32;  // row 4 (lane / 32) - 1 of the halo layout
     for (int j = L_tau - 1; j >= 0; --j) {
         const int l = (anchor + j) % L_tau;
+        if (ck && j % K != 0 && (j == L_tau - 1 || (j + 1) % K == 0)) {
+            // entering segment j / K from above: its rows from the checkpoint, every wavefront
+            // (shadows too) into its own segment rows
+            const int j0 = j - j % K;
+            const float* c0 = ring_row(j0);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int y = tile_row(lane, v);
+                const bool in = LFIX ? true : (xin && y < L);
+                const float f0 = c0[in ? y * L + x : 0];
+                F[v] = in ? f0 : 0.0f;
+            }
+            for (int i = j0 + 1; i <= j; ++i) {
+                bool bad;  // the forward pass reported it already
+                ring_step<LFIX>(F, Wsp + (int64_t)((anchor + i) % L_tau) * N, C, neg, lane, L,
+                                &bad);
+                ring_store<LFIX>(ring_row(i), F, lane, L);
+            }
+        }
         // this slice's filter row and W: issued before the matrix work, waited for after it
-        const float* row = rows + (int64_t)j * N;
+        const float* row = ring_row(j);
         const float* Wl = Wsp + (int64_t)l * N;
         float fj[16], wl[16];
 #pragma unroll
@@ -1112,14 +1169,16 @@ __global__ __launch_bounds__(kThreads, 3) void k_grad_mfma(
 
 // The adjoint of k_grad_mfma on the FP64 matrix cores (FP64 plans, every chain L <= 32): the
 // same ring, recursion, marginals and d/dt stencil, every product and sum in FP64 with the
-// circulant of k_forward_dmfma; ring rows stored as FP64 rows, group partial slabs in FP64.
+// circulant of k_forward_dmfma; ring rows stored as FP64 rows, group partial slabs in FP64;
+// the checkpoints of FH_FLAG_GRAD_CHECKPOINT as in k_grad_mfma.
+template <bool CK>
 __global__ __launch_bounds__(kThreads) void k_grad_dmfma(
     const ChainInfo* __restrict__ chains, const GroupTask* __restrict__ groups,
     const double* __restrict__ cmat64, const double* __restrict__ aux,
     const double* __restrict__ W, const double* __restrict__ wshift, int64_t aux_elems,
     int64_t total_slices, const int32_t* __restrict__ paths, double* __restrict__ filt,
     double* __restrict__ gpart, double* __restrict__ blk_logz, double* __restrict__ dt_out,
-    int anchor, const int32_t* __restrict__ perm, int32_t* status) {
+    int anchor, const int32_t* __restrict__ perm, int32_t* status, double* __restrict__ ckpt) {
     // beta tile of each wavefront with halo rows (row y at (y + 1) * 32; row -1 repeats row L - 1,
     // row L repeats row 0), and double-buffered marginal tiles, as in k_grad_mfma
     __shared__ double bt[kWaves][34 * 32];
@@ -1151,18 +1210,24 @@ __global__ __launch_bounds__(kThreads) void k_grad_dmfma(
     auto inside = [&](int q, int r) { return xo(q) < L && yo(q, r) < L; };
     const int ax = a % L, ay = a / L, ex = e % L, ey = e / L;
     double* rows = filt + c.filt_off + (int64_t)p * L_tau * N;
-    // ---- forward pass over the ring, every row stored
-    Tile64 F;
+    constexpr bool ck = CK;  // ckpt is given exactly for CK
+    const int K = ck ? c.ck_k : 1;
+    double* ckrows = ck ? ckpt + c.ck_row_off + (int64_t)p * c.ck_n * N : nullptr;
+    double* seg = ck ? ckpt + g.seg_off + (int64_t)wv * (K - 1) * N : nullptr;
+    auto ring_row = [&](int j) -> double* {
+        if (!ck) return rows + (int64_t)j * N;
+        const int sj = j / K, i = j - sj * K;
+        return i == 0 ? ckrows + (int64_t)sj * N : seg + (int64_t)(i - 1) * N;
+    };
+    auto store_row = [&](double* row, const Tile64& F) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            F.t[q][r] = (xo(q) == ax && yo(q, r) == ay) ? 1.0 : 0.0;
-            if (real && inside(q, r)) rows[yo(q, r) * L + xo(q)] = F.t[q][r];
-        }
-    double la = coef * aux[c.aux_off + (int64_t)anchor * N + a];
-    for (int j = 1; j < L_tau; ++j) {
-        const int l = (anchor + j) % L_tau;
+            for (int r = 0; r < 4; ++r)
+                if (inside(q, r)) row[yo(q, r) * L + xo(q)] = F.t[q][r];
+    };
+    // one step f~_j = W~_l . (C f~_{j-1} C) / total; returns the total
+    auto step = [&](int l, Tile64& F) -> double {
         const double* Wl = Wsp + (int64_t)l * N;
         double w[16];
 #pragma unroll
@@ -1183,15 +1248,25 @@ __global__ __launch_bounds__(kThreads) void k_grad_dmfma(
         if ((!(tot > 0.0) || !isfinite(tot)) && real && lane == 0)
             set_status(status, FH_ERR_NONFINITE, g.chain);
         const double inv = 1.0 / tot;
-        la += log(tot) + shift[l];
-        double* row = rows + (int64_t)j * N;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                F.t[q][r] *= inv;
-                if (real && inside(q, r)) row[yo(q, r) * L + xo(q)] = F.t[q][r];
-            }
+            for (int r = 0; r < 4; ++r) F.t[q][r] *= inv;
+        return tot;
+    };
+    // ---- forward pass over the ring, every row (every K-th with checkpoints) stored
+    Tile64 F;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) F.t[q][r] = (xo(q) == ax && yo(q, r) == ay) ? 1.0 : 0.0;
+    if (real) store_row(ring_row(0), F);
+    double la = coef * aux[c.aux_off + (int64_t)anchor * N + a];
+    for (int j = 1; j < L_tau; ++j) {
+        const int l = (anchor + j) % L_tau;
+        const double tot = step(l, F);
+        la += log(tot) + shift[l];
+        if (real && j % K == 0) store_row(ring_row(j), F);
     }
     {
         const Tile64 H = circ64(circ64(F, Cb), Cb);
@@ -1219,8 +1294,24 @@ __global__ __launch_bounds__(kThreads) void k_grad_dmfma(
     double* slab = gpart + g.part_off;
     for (int j = L_tau - 1; j >= 0; --j) {
         const int l = (anchor + j) % L_tau;
+        if (ck && j % K != 0 && (j == L_tau - 1 || (j + 1) % K == 0)) {
+            // entering segment j / K from above: its rows from the checkpoint (k_grad_mfma)
+            const int j0 = j - j % K;
+            const double* c0 = ring_row(j0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double f0 = c0[inside(q, r) ? yo(q, r) * L + xo(q) : 0];
+                    F.t[q][r] = inside(q, r) ? f0 : 0.0;
+                }
+            for (int i = j0 + 1; i <= j; ++i) {
+                step((anchor + i) % L_tau, F);
+                store_row(ring_row(i), F);
+            }
+        }
         // this slice's filter row and W: issued before the matrix work, waited for after it
-        const double* row = rows + (int64_t)j * N;
+        const double* row = ring_row(j);
         const double* Wl = Wsp + (int64_t)l * N;
         double fj[16], wl[16];
 #pragma unroll
@@ -1419,16 +1510,14 @@ hipError_t launch_grad_mfma(fh_plan p, const void* aux, const int32_t* paths, in
                             void* grad_aux, hipStream_t s) {
     bool all32 = true;
     for (const ChainInfo& c : p->chains) all32 = all32 && c.L == 32;
-    if (all32)
-        hipLaunchKernelGGL(k_grad_mfma<32>, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
-                           p->d.group_tasks, p->d.cmat, (const float*)aux, (const float*)p->d.W,
-                           p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt,
-                           (float*)p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm, p->d.status, kNegPairs);
-    else
-        hipLaunchKernelGGL(k_grad_mfma<0>, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
-                           p->d.group_tasks, p->d.cmat, (const float*)aux, (const float*)p->d.W,
-                           p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt,
-                           (float*)p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm, p->d.status, kNegPairs);
+    const bool ck = p->d.ckpt != nullptr;
+    auto kern = all32 ? (ck ? k_grad_mfma<32, true> : k_grad_mfma<32, false>)
+                      : (ck ? k_grad_mfma<0, true> : k_grad_mfma<0, false>);
+    hipLaunchKernelGGL(kern, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
+                       p->d.group_tasks, p->d.cmat, (const float*)aux, (const float*)p->d.W,
+                       p->d.wshift, p->aux_elems, p->total_slices, paths, (float*)p->d.filt,
+                       (float*)p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm,
+                       p->d.status, kNegPairs, (float*)p->d.ckpt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !grad_aux) return e;
     return launch_gpart_reduce(p, grad_aux, s);
@@ -1450,11 +1539,12 @@ hipError_t launch_gpart_reduce(fh_plan p, void* grad_aux, hipStream_t s) {
 
 hipError_t launch_grad_dmfma(fh_plan p, const void* aux, const int32_t* paths, int32_t anchor,
                              void* grad_aux, hipStream_t s) {
-    hipLaunchKernelGGL(k_grad_dmfma, dim3(p->n_groups), dim3(kThreads), 0, s, p->d.chains,
+    hipLaunchKernelGGL(p->d.ckpt ? k_grad_dmfma<true> : k_grad_dmfma<false>, dim3(p->n_groups),
+                       dim3(kThreads), 0, s, p->d.chains,
                        p->d.group_tasks, p->d.cmat64, (const double*)aux, (const double*)p->d.W,
                        p->d.wshift, p->aux_elems, p->total_slices, paths, (double*)p->d.filt,
                        (double*)p->d.gpart, p->d.blk_logz, p->d.dt, anchor, p->d.perm,
-                       p->d.status);
+                       p->d.status, (double*)p->d.ckpt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !grad_aux) return e;
     return launch_gpart_reduce(p, grad_aux, s);

@@ -45,6 +45,7 @@ FH_FLAG_GRAPH = 1
 FH_FLAG_AUTOTUNE = 2
 FH_FLAG_FULL_ROW_DRAW = 4
 FH_FLAG_FFT_CONV = 8
+FH_FLAG_GRAD_CHECKPOINT = 16
 
 
 class fh_chain_desc(ctypes.Structure):
@@ -107,6 +108,7 @@ _sig("fh_debug_inflate_window_bound", c_int32, c_void_p, c_double)
 _sig("fh_debug_backward_kernels", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32))
 _sig("fh_debug_forward_kernels", c_int32, c_void_p, POINTER(c_int32))
 _sig("fh_debug_backward_adapt", c_int32, c_void_p, c_int32, POINTER(c_int32))
+_sig("fh_debug_rescue_holds", c_int32, c_void_p, POINTER(c_int32))
 _sig("fh_debug_rescue", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int64),
      POINTER(c_int32), c_int32)
 _sig("fh_debug_sweep_timing", c_int32, c_void_p, c_int32)
@@ -285,6 +287,15 @@ def fh_debug_rescue(plan, cap=0):
                                buf.ctypes.data_as(POINTER(c_int32)), cap), "fh_debug_rescue")
     n = min(cap, last.value)
     return last.value, total.value, [tuple(int(v) for v in buf[i]) for i in range(n)], whole.value
+
+
+def fh_debug_rescue_holds(plan, n_chains):
+    """Per chain, the forward passes it stays on the FP64 re-filter (FP32 plans)."""
+    import numpy as np
+    buf = np.zeros(n_chains, dtype=np.int32)
+    _check(lib.fh_debug_rescue_holds(plan, buf.ctypes.data_as(POINTER(c_int32))),
+           "fh_debug_rescue_holds")
+    return buf
 
 
 def fh_debug_sweep_times(plan):

@@ -1104,6 +1104,68 @@ def test_logz_grad_mfma_full_lattice_repeatable(lib):
     S.close()
 
 
+@pytest.mark.parametrize("prec", ["mfma3", "fp64"])
+def test_logz_grad_checkpoint_parity(lib, prec):
+    """FH_FLAG_GRAD_CHECKPOINT at the gradient workload's shape (32x32, L_tau = 128: K = 12,
+    a ragged last segment of 8 rows) plus a 12x12 chain with L_tau = 16 (K = 4, segments that
+    divide the ring; the generic-L kernel): log Z, the field gradient and d/dt are the same
+    bits as without checkpoints (the recomputed rows are the stored ones), and match the
+    oracle; the checkpointed plan holds no ring rows for fh_get_filters, its filter workspace
+    comes with the first forward filter, and MALA moves agree too."""
+    fhmc, sampler = lib
+    d = synth.ChainDesc(L=32, L_tau=128, n_up=7, n_dn=6, hs_kind=synth.HS_GAUSS, block_len=0,
+                        t=1.0, U=4.0, dtau=0.05, seed=8)
+    descs = [d, synth.ChainDesc(L=12, L_tau=16, n_up=5, n_dn=4, hs_kind=synth.HS_HIRSCH,
+                                block_len=0, t=1.0, U=4.0, dtau=0.1, seed=9)]
+    flags = plan_flags(fhmc, prec)
+    Sp = sampler.Sampler(descs, PRECS[prec], flags)
+    Sc = sampler.Sampler(descs, PRECS[prec], flags | fhmc.FH_FLAG_GRAD_CHECKPOINT)
+    aux = [synth.initial_aux(d), synth.initial_aux(descs[1], rng_seed=78)]
+    paths = [synth.random_walk_paths(d, 5), synth.random_walk_paths(descs[1], 6)]
+    A, P = Sp.pack_aux(aux), Sp.pack_paths(paths)
+    for anchor in (11, 3):
+        lz1, g1, t1 = Sp.logz_grad(A, P, anchor)
+        lz2, g2, t2 = Sc.logz_grad(A, P, anchor)
+        assert Sp.status() == (0, -1) and Sc.status() == (0, -1)
+        assert torch.equal(lz1, lz2) and torch.equal(g1, g2) and torch.equal(t1, t2), anchor
+    gA = Sc.unpack_aux(g2)
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    for c, dc in enumerate(descs):
+        lz, g, gt, _ = ograd.logz_path_grad(dc, aux[c], paths[c], 3)
+        assert lz2[c].item() == pytest.approx(lz, rel=1e-12 if prec == "fp64" else 2e-6), c
+        assert np.linalg.norm(gA[c] - g) <= tol * np.linalg.norm(g), c
+        assert t2[c].item() == pytest.approx(gt, rel=tol), c
+    with pytest.raises(fhmc.FhError):
+        Sc.filters(0, 0)
+    e1, e2 = Sp.kinetic_energy(A, P, 5), Sc.kinetic_energy(A, P, 5)
+    assert np.array_equal(e1, e2)
+    if prec == "fp64":
+        Am = A.clone()
+        acc1 = Sp.mala_field(A, P, 4, 0.02, 11)
+        acc2 = Sc.mala_field(Am, P, 4, 0.02, 11)
+        assert np.array_equal(acc1, acc2) and torch.equal(A, Am)
+    # the sweep's workspace arrives with the first forward filter: same log Z as the plain plan
+    z1 = Sp.forward_filter(A, P, 2)
+    z2 = Sc.forward_filter(A, P, 2)
+    assert torch.equal(z1, z2)
+    assert np.array_equal(Sp.filters(1, 2), Sc.filters(1, 2))
+    Sp.close()
+    Sc.close()
+
+
+def test_grad_checkpoint_needs_the_matrix_core_adjoint(lib):
+    """The checkpointed adjoint exists for the matrix-core adjoints only."""
+    fhmc, sampler = lib
+    d = synth.config_small_fp64()[0]
+    for prec, extra in ((fhmc.FH_FP32, 0), (fhmc.FH_FP64, fhmc.FH_FLAG_FFT_CONV)):
+        with pytest.raises(fhmc.FhError):
+            sampler.Sampler([d], prec, extra | fhmc.FH_FLAG_GRAD_CHECKPOINT)
+    big = synth.ChainDesc(L=48, L_tau=8, n_up=3, n_dn=3, hs_kind=synth.HS_GAUSS, block_len=0,
+                          t=1.0, U=4.0, dtau=0.1, seed=1)
+    with pytest.raises(fhmc.FhError):
+        sampler.Sampler([big], fhmc.FH_FP64, fhmc.FH_FLAG_GRAD_CHECKPOINT)
+
+
 @pytest.mark.parametrize("prec", ["fp64fft", "fp32"])
 def test_logz_grad_fft_repeatable(lib, prec):
     """The FFT adjoints (worldlines in pairs, an odd one alone) write per-pair partial field
@@ -1261,15 +1323,19 @@ def test_windowed_draws_on_a_clustering_state(lib, prec):
     So.close()
     # which tier decided the draws of one more forward + backward on the clustered state
     s = 4
-    c = 0
-    d = descs[c]
-    before = Sw.unpack_paths(Pw)
     Sw.forward_filter(Aw, Pw, s)
-    rows = [Sw.filters(c, p) for p in range(0, d.n_up, 8)]
     Sw.backward_sample(Pw, s)
     assert Sw.status() == (0, -1)
-    # blocks redrawn from FP64 filters follow the FP64 rows, not the FP32 ones checked below
-    redone = {p for (cc, p, b) in fhmc.fh_debug_rescue(Sw.plan, cap=1 << 20)[2] if cc == c}
+    # blocks redrawn from FP64 filters follow the FP64 rows, not the FP32 ones checked below; on
+    # the FP32 plan a chain still held on the FP64 re-filter has all of them redrawn, so the
+    # first chain with single-block worldlines (B = L_tau) and FP32 draws left is checked
+    queue = fhmc.fh_debug_rescue(Sw.plan, cap=1 << 20)[2]
+    redone_in = lambda c: {p for (cc, p, b) in queue if cc == c}
+    c = next(c for c in (0, 2, 3) if set(range(0, descs[c].n_up, 8)) - redone_in(c))
+    say("  tiers checked on chain", c)
+    d = descs[c]
+    redone = redone_in(c)
+    rows = [Sw.filters(c, p) for p in range(0, d.n_up, 8)]
     after = Sw.unpack_paths(Pw)[c]
     g = np.zeros(d.L)
     P_D = ctypes.POINTER(ctypes.c_double)
@@ -1295,7 +1361,6 @@ def test_windowed_draws_on_a_clustering_state(lib, prec):
     assert tiers[1] > 0
     if prec == "fp64":
         assert tiers[0] > 0 and tiers[2] > 0
-    del before
     assert Sw.status() == (0, -1)
     assert Sf.status() == (0, -1)
     Sw.close()
