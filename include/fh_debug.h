@@ -87,6 +87,11 @@ int fh_debug_backward_adapt(fh_plan plan, int32_t enable, int32_t* full_row_pass
  * min(cap, last_count) queued blocks as (chain, particle, block). FP64 plans report 0. */
 int fh_debug_rescue(fh_plan plan, int32_t* last_count, int32_t* whole_chains, int64_t* total,
                     int32_t* list, int32_t cap);
+/* Overwrites every value of stored filter row `row` (numbered as fh_get_filters returns them) of
+ * (chain, particle) with `value`, in the plan's precision; the host's way to force a row whose
+ * backward weights are all zero. Needs stored filters (FH_ERR_STATE otherwise). Synchronous. */
+int fh_debug_fill_filter_row(fh_plan plan, int32_t chain, int32_t particle, int32_t row,
+                             double value);
 /* Synchronises the device and writes to holds (caller-owned host memory, [n_chains]) the forward
  * passes each chain stays on the FP64 re-filter: a chain with L <= 32 and holds[c] > 0 is
  * skipped by the next forward pass's FP32 kernels and re-filtered whole. FP64 plans write 0. */

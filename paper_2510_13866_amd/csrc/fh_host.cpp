@@ -1215,6 +1215,28 @@ int fh_debug_rescue(fh_plan p, int32_t* last_count, int32_t* whole_chains, int64
     return FH_OK;
 }
 
+int fh_debug_fill_filter_row(fh_plan p, int32_t chain, int32_t particle, int32_t row,
+                             double value) {
+    if (!p || chain < 0 || chain >= p->n_chains) return FH_ERR_INVALID_ARG;
+    const ChainInfo& c = p->chains[chain];
+    if (particle < 0 || particle >= c.np) return FH_ERR_INVALID_ARG;
+    if (!p->have_filters || !p->d.filt) return FH_ERR_STATE;
+    const int64_t rows = p->filters_are_ring ? c.L_tau : c.L_tau - c.nb;
+    if (row < 0 || row >= rows) return FH_ERR_INVALID_ARG;
+    FH_TRY(hipDeviceSynchronize());
+    const size_t off = (size_t)(c.filt_off + ((int64_t)particle * c.L_tau + row) * c.N);
+    if (p->real_size == 8) {
+        std::vector<double> v((size_t)c.N, value);
+        FH_TRY(hipMemcpy((double*)p->d.filt + off, v.data(), sizeof(double) * c.N,
+                         hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> v((size_t)c.N, (float)value);
+        FH_TRY(hipMemcpy((float*)p->d.filt + off, v.data(), sizeof(float) * c.N,
+                         hipMemcpyHostToDevice));
+    }
+    return FH_OK;
+}
+
 int fh_debug_rescue_holds(fh_plan p, int32_t* holds) {
     if (!p || !holds) return FH_ERR_INVALID_ARG;
     std::fill(holds, holds + p->n_chains, 0);

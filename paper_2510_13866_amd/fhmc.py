@@ -109,6 +109,7 @@ _sig("fh_debug_backward_kernels", c_int32, c_void_p, POINTER(c_int32), POINTER(c
 _sig("fh_debug_forward_kernels", c_int32, c_void_p, POINTER(c_int32))
 _sig("fh_debug_backward_adapt", c_int32, c_void_p, c_int32, POINTER(c_int32))
 _sig("fh_debug_rescue_holds", c_int32, c_void_p, POINTER(c_int32))
+_sig("fh_debug_fill_filter_row", c_int32, c_void_p, c_int32, c_int32, c_int32, c_double)
 _sig("fh_debug_rescue", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int64),
      POINTER(c_int32), c_int32)
 _sig("fh_debug_sweep_timing", c_int32, c_void_p, c_int32)

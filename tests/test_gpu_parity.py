@@ -1669,6 +1669,43 @@ def test_largest_lattice_parity(lib, prec):
     end_fp32_misses(misses)
 
 
+@pytest.mark.parametrize("full_row", [False, True])
+def test_zero_weight_row_is_reported(lib, full_row):
+    """A filter row forced to zero from the host (fh_debug_fill_filter_row). On the FP64 plan the
+    draw at that row finds no positive weight, neither in the window nor on the full row: the
+    plan reports FH_ERR_ZERO_WEIGHT for that chain, and every other worldline is drawn as by an
+    untouched plan. On the FP32 matrix-core plan the block is redrawn from FP64 filters instead
+    (no error), so the worldline's sites equal the untouched FP64 plan's."""
+    fhmc, sampler = lib
+    descs = [synth.ChainDesc(L=32, L_tau=16, n_up=4, n_dn=3, hs_kind=synth.HS_GAUSS,
+                             block_len=0, t=1.0, U=4.0, dtau=0.05, seed=341),
+             synth.config_small_fp64()[0]]
+    flags = fhmc.FH_FLAG_FULL_ROW_DRAW if full_row else 0
+    aux, paths = mixed_state(descs, seed=351)
+    s = 1
+    draws = {}
+    for name, prec, hit in (("ref", fhmc.FH_FP64, False), ("fp64", fhmc.FH_FP64, True),
+                            ("mfma3", fhmc.FH_FP32_MFMA3, True)):
+        S = sampler.Sampler(descs, prec, flags)
+        A, P = S.pack_aux(aux), S.pack_paths(paths)
+        S.forward_filter(A, P, s)
+        if hit:
+            assert fhmc.lib.fh_debug_fill_filter_row(S.plan, 0, 2, 5, 0.0) == 0
+        S.backward_sample(P, s)
+        draws[name] = (S.unpack_paths(P), S.status())
+        S.close()
+    ref, st = draws["ref"]
+    assert st == (0, -1)
+    got, st = draws["fp64"]
+    assert st == (fhmc.FH_ERR_ZERO_WEIGHT, 0), st
+    keep = [p for p in range(descs[0].n_particles) if p != 2]
+    assert np.array_equal(got[0][:, keep], ref[0][:, keep])
+    assert np.array_equal(got[1], ref[1])
+    got, st = draws["mfma3"]
+    assert st == (0, -1), st
+    assert np.array_equal(got[0][:, 2], ref[0][:, 2])
+
+
 def test_fp32_fft_l48_parity(lib):
     """L = 48 on the FP32 plan (the FP32 FFT; the matrix-core plan takes L <= 32 and L = 64 only)
     with 40-slice blocks: log Z against the oracle within its tail bound, filters held to 1e-5
