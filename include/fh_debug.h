@@ -92,6 +92,18 @@ int fh_debug_rescue(fh_plan plan, int32_t* last_count, int32_t* whole_chains, in
  * backward weights are all zero. Needs stored filters (FH_ERR_STATE otherwise). Synchronous. */
 int fh_debug_fill_filter_row(fh_plan plan, int32_t chain, int32_t particle, int32_t row,
                              double value);
+/* Shared forward filters (FP32 matrix-core plans, 32 x 32 chains): the worldlines of one
+ * (chain, spin, block) with the same start site share the stored rows of the lowest of them,
+ * their representative. Synchronises the device and copies the representative map of the last
+ * forward pass, one chain-local particle index per (chain, particle, block) at
+ * blk_off + p * n_blocks + b (chain after chain, fh_layout's particle order), to rep
+ * (caller-owned host memory, min(cap, *n) entries). *n receives the map's length: 0 when no
+ * chain of the plan shares filters (then every worldline reads its own rows). */
+int fh_debug_representatives(fh_plan plan, int32_t* rep, int64_t cap, int64_t* n);
+/* enable = 0: every worldline runs its own forward recursion (the representative map is the
+ * identity), the reference for tests that the shared filters change no result; 1 (the
+ * default): shared. Synchronous; drops the captured sweep and invalidates stored filters. */
+int fh_debug_share_filters(fh_plan plan, int32_t enable);
 /* Synchronises the device and writes to holds (caller-owned host memory, [n_chains]) the forward
  * passes each chain stays on the FP64 re-filter: a chain with L <= 32 and holds[c] > 0 is
  * skipped by the next forward pass's FP32 kernels and re-filtered whole. FP64 plans write 0. */

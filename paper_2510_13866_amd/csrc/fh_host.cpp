@@ -187,7 +187,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.draw_tasks, d.group_tasks, d.gpart, d.ckpt, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
+                    d.draw_tasks, d.group_tasks, d.gpart, d.ckpt, d.rep, d.blk_la, d.endrow, d.dedup_tasks, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
                     d.rescue, d.rescue_list, d.rescue_ws, d.rescue_w, d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -393,6 +393,20 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         return precision == FH_FP64 && !(flags & FH_FLAG_FFT_CONV) && p->chains[c].L <= 32;
     };
     std::vector<PairTask> fwdf;
+    // shared forward filters: the 32 x 32 chains of the matrix-core plan (one tile per worldline
+    // pair); k_dedup runs one workgroup per (chain, spin, block)
+    std::vector<DrawTask> dedup;
+    for (int c = 0; c < n_chains; ++c) {
+        ChainInfo& ci = p->chains[c];
+        ci.dedup = precision == FH_FP32_MFMA3 && ci.L == 32;
+        if (!ci.dedup) continue;
+        ci.end_off = p->end_elems;
+        p->end_elems += (int64_t)ci.np * ci.nb * ci.N;
+        for (int spin = 0; spin < 2; ++spin)
+            if ((spin ? ci.n_dn : ci.n_up) > 0)
+                for (int b = 0; b < ci.nb; ++b) dedup.push_back({c, spin, b, 0});
+    }
+    p->n_dedup_tasks = (int32_t)dedup.size();
     std::vector<DrawTask> fwdd;
     for (const PairTask& t : fwd)
         if (!dmfma(t.chain)) fwdf.push_back(t);
@@ -476,6 +490,23 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess && !ckpt) e = dalloc(&dv.filt, rs * (size_t)filt);
     if (e == hipSuccess && ckpt) e = dalloc(&dv.ckpt, rs * (size_t)p->ckpt_elems);
     if (e == hipSuccess) e = dalloc(&dv.blk_logz, sizeof(double) * (size_t)blk);
+    if (e == hipSuccess && !dedup.empty()) {
+        e = dalloc(&dv.rep, sizeof(int32_t) * (size_t)blk);
+        if (e == hipSuccess) e = dalloc(&dv.blk_la, sizeof(double) * (size_t)blk);
+        if (e == hipSuccess) e = dalloc(&dv.endrow, sizeof(float) * (size_t)p->end_elems);
+        if (e == hipSuccess) e = dalloc(&dv.dedup_tasks, sizeof(DrawTask) * dedup.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(dv.dedup_tasks, dedup.data(), sizeof(DrawTask) * dedup.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess) {  // every worldline its own representative until k_dedup runs
+            std::vector<int32_t> ident((size_t)blk);
+            for (const ChainInfo& ci : p->chains)
+                for (int64_t k = 0; k < (int64_t)ci.np * ci.nb; ++k)
+                    ident[(size_t)(ci.blk_off + k)] = (int32_t)(k / ci.nb);
+            e = hipMemcpy(dv.rep, ident.data(), sizeof(int32_t) * (size_t)blk,
+                          hipMemcpyHostToDevice);
+        }
+    }
     if (e == hipSuccess) e = dalloc(&dv.dt, sizeof(double) * (size_t)part);
     if (e == hipSuccess) e = dalloc(&dv.fwd_tasks, sizeof(PairTask) * fwdf.size());
     if (e == hipSuccess) e = dalloc(&dv.fwdd_tasks, sizeof(DrawTask) * fwdd.size());
@@ -632,6 +663,7 @@ static hipError_t enqueue_forward(fh_plan p, const void* aux, const int32_t* pat
     hipError_t e = launch_potentials(p, aux, s);
     if (e == hipSuccess) e = launch_rescue_reset(p, s);  // FP32 plans: empty re-filter queue
     if (e == hipSuccess) e = mark(p, 0, s);
+    if (e == hipSuccess) e = launch_dedup(p, paths, s);  // shared forward filters
     if (e != hipSuccess) return e;
     if (p->precision == FH_FP32_MFMA3) {
         e = launch_forward_mfma(p, aux, paths, s);
@@ -639,6 +671,7 @@ static hipError_t enqueue_forward(fh_plan p, const void* aux, const int32_t* pat
         e = launch_forward_dmfma(p, aux, paths, s);  // FP64 plans, chains with L <= 32
         if (e == hipSuccess && p->n_fwd_tasks > 0) e = launch_forward(p, aux, paths, s);
     }
+    if (e == hipSuccess) e = launch_member_logz(p, paths, s);
     if (e == hipSuccess) e = mark(p, 1, s);
     if (e == hipSuccess) e = launch_rescue_expand(p, s);  // FP32: chains re-filtered whole
     return e;
@@ -979,15 +1012,35 @@ int fh_get_filters(fh_plan p, int32_t chain, int32_t particle, void* dst, int64_
     if (n_rows) *n_rows = rows;
     if (!dst) return FH_OK;
     if (capacity < rows * c.N) return FH_ERR_INVALID_ARG;
-    const char* src = (const char*)p->d.filt +
-                      p->real_size * (size_t)(c.filt_off + (int64_t)particle * c.L_tau * c.N);
     hipStream_t s = (hipStream_t)stream;
-    if (!p->filters_are_ring && c.row_exp != 0)  // FP32 sweep rows hold f~ 2^row_exp
-        FH_TRY(launch_scale_copy((float*)dst, (const float*)src, rows * c.N,
-                                 (float)ldexp(1.0, -c.row_exp), s));
-    else
-        FH_TRY(hipMemcpyAsync(dst, src, p->real_size * (size_t)(rows * c.N),
-                              hipMemcpyDeviceToDevice, s));
+    // sweep rows of a chain with shared forward filters: block b's rows are its
+    // representative's
+    std::vector<int32_t> owner((size_t)c.nb, particle);
+    if (!p->filters_are_ring && c.dedup && p->d.rep) {
+        FH_TRY(hipStreamSynchronize(s));
+        FH_TRY(hipMemcpy(owner.data(), p->d.rep + c.blk_off + (int64_t)particle * c.nb,
+                         sizeof(int32_t) * c.nb, hipMemcpyDeviceToHost));
+    }
+    // ring rows: one block of L_tau rows; sweep rows: B - 1 (the last block: its length - 1)
+    const int nseg = p->filters_are_ring ? 1 : c.nb;
+    int64_t done = 0;
+    for (int b = 0; b < nseg; ++b) {
+        const int64_t cnt = p->filters_are_ring ? rows
+                          : (b < c.nb - 1 ? c.B : c.L_tau - (int64_t)(c.nb - 1) * c.B) - 1;
+        const int64_t from = c.filt_off + ((int64_t)owner[(size_t)b] * c.L_tau +
+                                           (int64_t)b * (c.B - 1)) * c.N;
+        const char* src = (const char*)p->d.filt + p->real_size * (size_t)from;
+        char* to = (char*)dst + p->real_size * (size_t)(done * c.N);
+        if (cnt > 0) {
+            if (!p->filters_are_ring && c.row_exp != 0)  // FP32 sweep rows hold f~ 2^row_exp
+                FH_TRY(launch_scale_copy((float*)to, (const float*)src, cnt * c.N,
+                                         (float)ldexp(1.0, -c.row_exp), s));
+            else
+                FH_TRY(hipMemcpyAsync(to, src, p->real_size * (size_t)(cnt * c.N),
+                                      hipMemcpyDeviceToDevice, s));
+        }
+        done += cnt;
+    }
     FH_TRY(hipStreamSynchronize(s));
     return FH_OK;
 }
@@ -1234,6 +1287,34 @@ int fh_debug_fill_filter_row(fh_plan p, int32_t chain, int32_t particle, int32_t
         FH_TRY(hipMemcpy((float*)p->d.filt + off, v.data(), sizeof(float) * c.N,
                          hipMemcpyHostToDevice));
     }
+    return FH_OK;
+}
+
+int fh_debug_share_filters(fh_plan p, int32_t enable) {
+    if (!p || (enable != 0 && enable != 1)) return FH_ERR_INVALID_ARG;
+    if (!p->d.rep) return FH_OK;
+    FH_TRY(hipDeviceSynchronize());
+    drop_graph(p);  // the captured sweep holds the sharing kernels or not
+    p->share_off = enable == 0;
+    if (p->share_off) {  // every worldline its own representative
+        std::vector<int32_t> ident((size_t)p->blk_elems);
+        for (const ChainInfo& ci : p->chains)
+            for (int64_t k = 0; k < (int64_t)ci.np * ci.nb; ++k)
+                ident[(size_t)(ci.blk_off + k)] = (int32_t)(k / ci.nb);
+        FH_TRY(hipMemcpy(p->d.rep, ident.data(), sizeof(int32_t) * ident.size(),
+                         hipMemcpyHostToDevice));
+    }
+    p->have_filters = false;
+    return FH_OK;
+}
+
+int fh_debug_representatives(fh_plan p, int32_t* rep, int64_t cap, int64_t* n) {
+    if (!p || cap < 0 || (cap > 0 && !rep)) return FH_ERR_INVALID_ARG;
+    if (n) *n = p->d.rep ? p->blk_elems : 0;
+    if (!p->d.rep || cap == 0) return FH_OK;
+    FH_TRY(hipDeviceSynchronize());
+    FH_TRY(hipMemcpy(rep, p->d.rep, sizeof(int32_t) * (size_t)std::min(cap, p->blk_elems),
+                     hipMemcpyDeviceToHost));
     return FH_OK;
 }
 

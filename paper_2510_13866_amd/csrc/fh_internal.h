@@ -47,6 +47,12 @@ struct ChainInfo {
     // ckpt[ck_row_off + (p ck_n + j / K) N] and recomputes each segment from its checkpoint
     int64_t ck_row_off;
     int32_t ck_k, ck_n;
+    // Shared forward filters (FP32 plans, 32 x 32 chains): the rows of a block depend only on the
+    // spin's W and the block's start site, so worldlines of one (spin, block) with the same start
+    // site share the rows of the lowest-numbered of them, their representative. dedup = 1 for
+    // such chains; end_off locates their per-(particle, block) end tiles [N].
+    int32_t dedup;
+    int64_t end_off;
 };
 
 // Offsets of the tables of one chain inside the double table buffer, relative to tab_off.
@@ -132,13 +138,21 @@ constexpr int kRescueChain = 4;
 // doubles.
 constexpr int kRescueMaxSlots = 2048;
 
-// Rescue state as the kernels see it: the words above, and the per-block flags.
+// Per-pass state of the FP32 plans as the kernels see it: the rescue words above, the per-block
+// flags, the queue, and the representative map of the shared forward filters (rep, per
+// (chain, particle, block) at blk_off + p nb + b: the worldline whose stored rows the block's
+// draws read; null where no chain shares, and on FP64 plans).
 struct Rescue {
     int32_t* words;   // null for FP64 plans
     int32_t* flags;   // words + kRescueChain + 2 n_chains
     DrawTask* list;
     int32_t n_chains;
+    const int32_t* rep;
 };
+// The worldline whose stored rows block `block` of worldline p reads.
+__device__ inline int row_owner(const Rescue& r, const ChainInfo& c, int p, int block) {
+    return r.rep ? r.rep[c.blk_off + (int64_t)p * c.nb + block] : p;
+}
 // Queues block (chain, p, block) for the FP64 re-filter once; called by one lane.
 __device__ inline bool rescue_enqueue(const Rescue& r, const ChainInfo& c, int chain, int p,
                                       int block) {
@@ -186,6 +200,13 @@ struct Device {
     double* wshift = nullptr; // [2][total slices]: log W = log W~ + wshift per (spin, slice)
     void* filt = nullptr;     // filter workspace, plan precision
     double* blk_logz = nullptr;
+    // shared forward filters (chains with dedup): representative map [blk_elems], the
+    // representatives' log Z before the end weight [blk_elems], end tiles [end_elems] f32, and
+    // the (chain, spin, block) tasks of k_dedup
+    int32_t* rep = nullptr;
+    double* blk_la = nullptr;
+    float* endrow = nullptr;
+    DrawTask* dedup_tasks = nullptr;
     double* dt = nullptr;     // per particle d log Z / d t
     PairTask* fwd_tasks = nullptr;
     DrawTask* draw_tasks = nullptr;
@@ -252,6 +273,9 @@ struct fh_plan_s {
     int64_t gpart_elems = 0;
     int64_t ckpt_elems = 0;     // FH_FLAG_GRAD_CHECKPOINT: checkpoint + segment rows (elements)
     int32_t n_rescue_slots = 0;     // FP32 plans: wavefronts of k_rescue
+    int32_t n_dedup_tasks = 0;      // (chain, spin, block) tasks of k_dedup (chains with dedup)
+    bool share_off = false;         // fh_debug_share_filters(plan, 0): every worldline its own rows
+    int64_t end_elems = 0;          // end tiles of the chains with dedup (f32 elements)
     int64_t rescue_slot_elems = 0;  // doubles per slot: (B - 1) N of the largest L <= 32 chain
     int64_t total_sites = 0;  // sum of N over the chains
     int32_t max_N = 0, max_L = 0, max_np = 0;
@@ -285,6 +309,7 @@ inline Rescue rescue_args(fh_plan p) {
     r.words = p->d.rescue;
     r.flags = p->d.rescue ? p->d.rescue + kRescueChain + 2 * p->n_chains : nullptr;
     r.list = p->d.rescue_list;
+    r.rep = p->d.rep;
     r.n_chains = p->n_chains;
     return r;
 }
@@ -302,6 +327,10 @@ hipError_t launch_logz_reduce(fh_plan p, double* logZ, hipStream_t s);
 hipError_t launch_backward(fh_plan p, int32_t* paths, hipStream_t s);
 // FP32 plans: clears the rescue queue (before a forward pass), queues whole chains (after it),
 // and re-filters (and, with draw, redraws) the queued blocks in FP64. No-ops for FP64 plans.
+// Before an FP32 forward pass: the representative map of the shared forward filters.
+hipError_t launch_dedup(fh_plan p, const int32_t* paths, hipStream_t s);
+// After it: log Z and end-weight floors of the worldlines that share a representative's rows.
+hipError_t launch_member_logz(fh_plan p, const int32_t* paths, hipStream_t s);
 hipError_t launch_rescue_reset(fh_plan p, hipStream_t s);
 hipError_t launch_rescue_expand(fh_plan p, hipStream_t s);  // after the FP32 forward pass
 hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, hipStream_t s);

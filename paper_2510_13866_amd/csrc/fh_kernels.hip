@@ -425,7 +425,8 @@ __global__ __launch_bounds__(kThreads) void k_backward(
     const int E = (N + 63) / 64;
     const int i0 = lane * E;
     const int i1 = min(i0 + E, N);
-    const T* rows = filt + c.filt_off + ((int64_t)t.p * c.L_tau + (int64_t)t.block * (c.B - 1)) * N;
+    const int ro = row_owner(rsc, c, t.p, t.block);  // shared forward filters
+    const T* rows = filt + c.filt_off + ((int64_t)ro * c.L_tau + (int64_t)t.block * (c.B - 1)) * N;
     for (int j = len - 1; j >= 1; --j) {
         const int l = (start + j) % c.L_tau;
         const T* f = rows + (int64_t)(j - 1) * N;
@@ -547,7 +548,8 @@ __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const doubl
     const int x0 = cnt > 0 ? i0 % L : 0, y0 = cnt > 0 ? i0 / L : 0;
     // the block's rows in the plan's workspace, or at rows_at (the FP64 re-filter's slot)
     const T* rows = rows_at ? rows_at
-                            : filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+                            : filt + c.filt_off + ((int64_t)row_owner(rsc, c, t.p, t.block) * L_tau +
+                                                   (int64_t)t.block * (c.B - 1)) * N;
     // row of draw j is rows + (j - 1) N; draws run j = len-1 .. 1
     auto load_row = [&](int j, T (&dst)[E]) {
         const T* r = rows + (int64_t)(j - 1) * N + i0;
@@ -733,7 +735,8 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
     int cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np +
                               (start + len >= L_tau ? qn : t.p)], 1024, status, t.chain);
     const int x0 = 16 * (lane & 1), y0 = lane >> 1;
-    const T* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * 1024 +
+    const int ro = row_owner(rsc, c, t.p, t.block);  // shared forward filters
+    const T* rows = filt + c.filt_off + ((int64_t)ro * L_tau + (int64_t)t.block * (c.B - 1)) * 1024 +
                     16 * lane;
     typedef T vec4 __attribute__((ext_vector_type(4)));
     auto load_row = [&](int j, T (&dst)[16]) {  // row of draw slice start + j, j clamped to >= 1
@@ -1082,7 +1085,8 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         qy[k] = qv[k] ? q / WW : 0;
         qx[k] = qv[k] ? q - qy[k] * WW : 0;
     }
-    const T* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+    const int ro = row_owner(rsc, c, t.p, t.block);  // shared forward filters
+    const T* rows = filt + c.filt_off + ((int64_t)ro * L_tau + (int64_t)t.block * (c.B - 1)) * N;
     // the outside bound scales with the row mass (2^row_exp on FP32 plans)
     const double gout = c.win_gout * c.row_mass * kWinMassBound;
     double ureg = 0.0;
@@ -1377,6 +1381,70 @@ __global__ __launch_bounds__(kThreads, 2) void k_rescue(
         rescue_draws(t, c, tables + tab_g(c), paths, perm, sweep, status, lane, slot);
         // the next block reuses the slot: its stores must follow these loads
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+    }
+}
+
+// Shared forward filters, before an FP32 forward pass: one workgroup per (chain, spin, block)
+// of the chains with dedup. The rows of a block depend only on the spin's W tables, the block's
+// slices and its start site, so every worldline of the (spin, block) is mapped to the lowest
+// worldline with the same start site (its representative; itself if it is the lowest); the
+// forward kernel runs the representatives only and the backward kernels read their rows.
+__global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict__ chains,
+                                                    const DrawTask* __restrict__ tasks,
+                                                    const int32_t* __restrict__ paths,
+                                                    const uint64_t* __restrict__ sweep_ptr,
+                                                    int32_t* __restrict__ rep) {
+    __shared__ int32_t first[1024];  // dedup chains are 32 x 32
+    const DrawTask t = tasks[blockIdx.x];  // t.p holds the spin
+    const ChainInfo& c = chains[t.chain];
+    int start, len;
+    block_of(c, *sweep_ptr, t.block, &start, &len);
+    const int p0 = t.p ? c.n_up : 0, p1 = t.p ? c.np : c.n_up;
+    for (int i = threadIdx.x; i < c.N; i += blockDim.x) first[i] = 0x7fffffff;
+    __syncthreads();
+    const int32_t* row = paths + c.path_off + (int64_t)start * c.np;
+    for (int q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
+        const int a = row[q];
+        if (a >= 0 && a < c.N) atomicMin(&first[a], q);
+    }
+    __syncthreads();
+    for (int q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
+        const int a = row[q];  // an invalid site keeps its own rows (the forward reports it)
+        rep[c.blk_off + (int64_t)q * c.nb + t.block] = (a >= 0 && a < c.N) ? first[a] : q;
+    }
+}
+
+// After the FP32 forward pass, one thread per (chain, particle, block) of the chains with dedup:
+// a worldline that shares its representative's rows takes the representative's log Z before
+// the end weight and reads its own end weight from the representative's end tile
+// (C f~ C)(e), exactly what its own recursion would have computed; an end weight below
+// kRangeFloor queues the block like the forward kernel's own check.
+__global__ void k_member_logz(const ChainInfo* __restrict__ chains, int n_chains,
+                              const int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
+                              const uint64_t* __restrict__ sweep_ptr,
+                              const double* __restrict__ blk_la, const float* __restrict__ endrow,
+                              double* __restrict__ blk_logz, int64_t blk_elems, int32_t* status,
+                              const Rescue rsc) {
+    const uint64_t sweep = *sweep_ptr;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < blk_elems;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int ci = find_chain(n_chains, i, [&](int k) { return chains[k].blk_off; });
+        const ChainInfo& c = chains[ci];
+        if (!c.dedup || rescue_held(rsc, ci)) continue;
+        const int64_t local = i - c.blk_off;
+        const int p = (int)(local / c.nb), b = (int)(local % c.nb);
+        const int rp = rsc.rep[i];
+        if (rp == p) continue;  // a representative: the forward kernel did it
+        int start, len;
+        block_of(c, sweep, b, &start, &len);
+        const int L_tau = c.L_tau;
+        const int qe = start + len >= L_tau ? perm[c.part_off + p] : p;  // reconnection
+        const int e = checked_site(
+            paths[c.path_off + (int64_t)((start + len) % L_tau) * c.np + qe], c.N, status, ci);
+        const int64_t ri = c.blk_off + (int64_t)rp * c.nb + b;
+        const float hv = endrow[c.end_off + ((int64_t)rp * c.nb + b) * c.N + e];
+        if (!(hv >= kRangeFloor)) rescue_push(rsc, c, ci, p, b);
+        blk_logz[i] = blk_la[ri] + log((double)hv);
     }
 }
 
@@ -2256,6 +2324,21 @@ __global__ void k_scale_f32(float* __restrict__ dst, const float* __restrict__ s
 
 hipError_t launch_scale_copy(float* dst, const float* src, int64_t n, float factor, hipStream_t s) {
     hipLaunchKernelGGL(k_scale_f32, dim3(grid_for(n)), dim3(kThreads), 0, s, dst, src, n, factor);
+    return hipGetLastError();
+}
+
+hipError_t launch_dedup(fh_plan p, const int32_t* paths, hipStream_t s) {
+    if (p->n_dedup_tasks == 0 || p->share_off) return hipSuccess;
+    hipLaunchKernelGGL(k_dedup, dim3((unsigned)p->n_dedup_tasks), dim3(kThreads), 0, s,
+                       p->d.chains, p->d.dedup_tasks, paths, p->d.sweep, p->d.rep);
+    return hipGetLastError();
+}
+
+hipError_t launch_member_logz(fh_plan p, const int32_t* paths, hipStream_t s) {
+    if (p->n_dedup_tasks == 0 || p->share_off) return hipSuccess;
+    hipLaunchKernelGGL(k_member_logz, dim3(grid_for(p->blk_elems)), dim3(kThreads), 0, s,
+                       p->d.chains, p->n_chains, paths, p->d.perm, p->d.sweep, p->d.blk_la,
+                       p->d.endrow, p->d.blk_logz, p->blk_elems, p->d.status, rescue_args(p));
     return hipGetLastError();
 }
 

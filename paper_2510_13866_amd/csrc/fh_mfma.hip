@@ -337,18 +337,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
     double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    const Rescue rsc, const NegPairs neg) {
+    const Rescue rsc, const NegPairs neg, double* __restrict__ blk_la,
+    float* __restrict__ endrow) {
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
     const PairTask t = tasks[task];
     if (rescue_held(rsc, t.chain)) return;  // re-filtered whole in FP64 this pass
     const ChainInfo& c = chains[t.chain];
+    // shared forward filters: only representatives run the recursion (k_member_logz completes
+    // the others' log Z from the representative's end tile)
+    const bool ra = !c.dedup || row_owner(rsc, c, t.p_a, t.block) == t.p_a;
+    const bool rb = t.p_b >= 0 && (!c.dedup || row_owner(rsc, c, t.p_b, t.block) == t.p_b);
+    if (!ra && !rb) return;
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
     const int L = LFIX ? LFIX : c.L, N = LFIX ? LFIX * LFIX : c.N, L_tau = c.L_tau;
-    const bool has_b = t.p_b >= 0;
-    const int pp[2] = {t.p_a, has_b ? t.p_b : t.p_a};  // a lone worldline is shadowed, not stored
+    const bool has_b = ra && rb;
+    const int q0 = ra ? t.p_a : t.p_b;
+    const int pp[2] = {q0, has_b ? t.p_b : q0};  // a lone worldline is shadowed, not stored
     const int spin = t.p_a >= c.n_up ? 1 : 0;
     const float* Wsp = W + spin * aux_elems + c.aux_off;
     const double* shift = wshift + spin * total_slices + c.slice_off;
@@ -492,6 +499,21 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
             rescue_push(rsc, c, t.chain, pp[1], t.block);
         blk_logz[c.blk_off + (int64_t)pp[0] * c.nb + t.block] = la0 + log((double)hv0);
         if (has_b) blk_logz[c.blk_off + (int64_t)pp[1] * c.nb + t.block] = la1 + log((double)hv1);
+    }
+    if (c.dedup) {  // what the worldlines sharing these rows need: log Z so far, the end tile
+        if (lane == 0) {
+            blk_la[c.blk_off + (int64_t)pp[0] * c.nb + t.block] = la0;
+            if (has_b) blk_la[c.blk_off + (int64_t)pp[1] * c.nb + t.block] = la1;
+        }
+        float* end0 = endrow + c.end_off + ((int64_t)pp[0] * c.nb + t.block) * N + lane_off;
+        float* end1 = endrow + c.end_off + ((int64_t)pp[1] * c.nb + t.block) * N + lane_off;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            if (inside(v)) {
+                end0[vrow(v) * L] = H0[v];
+                if (has_b) end1[vrow(v) * L] = H1[v];
+            }
+        }
     }
 }
 
@@ -1460,7 +1482,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
                            p->d.fwd32_tasks, p->n_fwd32_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
-                           rescue_args(p), kNegPairs);
+                           rescue_args(p), kNegPairs, p->d.blk_la, p->d.endrow);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

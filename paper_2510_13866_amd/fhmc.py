@@ -110,6 +110,8 @@ _sig("fh_debug_forward_kernels", c_int32, c_void_p, POINTER(c_int32))
 _sig("fh_debug_backward_adapt", c_int32, c_void_p, c_int32, POINTER(c_int32))
 _sig("fh_debug_rescue_holds", c_int32, c_void_p, POINTER(c_int32))
 _sig("fh_debug_fill_filter_row", c_int32, c_void_p, c_int32, c_int32, c_int32, c_double)
+_sig("fh_debug_representatives", c_int32, c_void_p, POINTER(c_int32), c_int64, POINTER(c_int64))
+_sig("fh_debug_share_filters", c_int32, c_void_p, c_int32)
 _sig("fh_debug_rescue", c_int32, c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int64),
      POINTER(c_int32), c_int32)
 _sig("fh_debug_sweep_timing", c_int32, c_void_p, c_int32)
@@ -297,6 +299,18 @@ def fh_debug_rescue_holds(plan, n_chains):
     _check(lib.fh_debug_rescue_holds(plan, buf.ctypes.data_as(POINTER(c_int32))),
            "fh_debug_rescue_holds")
     return buf
+
+
+def fh_debug_representatives(plan):
+    """The representative map of the shared forward filters (numpy int32, empty when the plan
+    shares none)."""
+    import numpy as np
+    n = c_int64()
+    _check(lib.fh_debug_representatives(plan, None, 0, byref(n)), "fh_debug_representatives")
+    buf = np.zeros(max(n.value, 1), dtype=np.int32)
+    _check(lib.fh_debug_representatives(plan, buf.ctypes.data_as(POINTER(c_int32)), n.value,
+                                        byref(n)), "fh_debug_representatives")
+    return buf[:n.value]
 
 
 def fh_debug_sweep_times(plan):

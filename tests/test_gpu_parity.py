@@ -1669,6 +1669,54 @@ def test_largest_lattice_parity(lib, prec):
     end_fp32_misses(misses)
 
 
+def test_shared_forward_filters_change_nothing(lib):
+    """Worldlines of one (spin, block) that start on the same site have the same forward rows;
+    the matrix-core plan runs the recursion once per start site (fh_debug_representatives) and
+    the others read those rows. From a clustered state (twelve sweeps of the benchmark's
+    chains, plus a chain with ragged 24-slice blocks), sweeps, log Z, filters and draws equal
+    those of the same plan with sharing off, bit for bit."""
+    fhmc, sampler = lib
+    descs = synth.config_32x32(4.0, 2) + [
+        synth.ChainDesc(L=32, L_tau=64, n_up=300, n_dn=200, hs_kind=synth.HS_GAUSS, block_len=24,
+                        t=1.0, U=6.0, dtau=0.05, seed=5)]
+    S = sampler.Sampler(descs, fhmc.FH_FP32_MFMA3, fhmc.FH_FLAG_GRAPH)
+    A = S.pack_aux([synth.initial_aux(d) for d in descs])
+    P = S.pack_paths([synth.initial_paths(d) for d in descs])
+    S.sweep(A, P, 0, 12)
+    assert S.status() == (0, -1)
+    rep = fhmc.fh_debug_representatives(S.plan)
+    own = np.concatenate([np.repeat(np.arange(d.n_particles), synth_blocks(d)) for d in descs])
+    assert len(rep) == len(own) and np.sum(rep != own) > len(own) // 2, np.sum(rep != own)
+    Sx = sampler.Sampler(descs, fhmc.FH_FP32_MFMA3, fhmc.FH_FLAG_GRAPH)
+    assert fhmc.lib.fh_debug_share_filters(Sx.plan, 0) == 0
+    Ax, Px = A.clone(), P.clone()
+    for s in range(12, 16):
+        S.sweep(A, P, s, 1)
+        Sx.sweep(Ax, Px, s, 1)
+        assert S.status() == Sx.status() == (0, -1), s
+        assert torch.equal(A, Ax) and torch.equal(P, Px), s
+    z, zx = S.forward_filter(A, P, 16), Sx.forward_filter(Ax, Px, 16)
+    assert torch.equal(z, zx)
+    for c, d in enumerate(descs):
+        for p in (0, 1, d.n_up - 1, d.n_up, d.n_particles - 1):
+            assert np.array_equal(S.filters(c, p), Sx.filters(c, p)), (c, p)
+    S.backward_sample(P, 16)
+    Sx.backward_sample(Px, 16)
+    assert torch.equal(P, Px)
+    assert fhmc.lib.fh_debug_share_filters(Sx.plan, 1) == 0  # back on: the same again
+    Sx.sweep(Ax, Px, 17, 1)
+    S.sweep(A, P, 17, 1)
+    assert torch.equal(A, Ax) and torch.equal(P, Px)
+    S.close()
+    Sx.close()
+
+
+def synth_blocks(d):
+    """FFBS blocks per worldline of a chain (the schedule's block count)."""
+    B = d.block_len or d.L_tau
+    return (d.L_tau + B - 1) // B
+
+
 @pytest.mark.parametrize("full_row", [False, True])
 def test_zero_weight_row_is_reported(lib, full_row):
     """A filter row forced to zero from the host (fh_debug_fill_filter_row). On the FP64 plan the
