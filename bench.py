@@ -477,8 +477,10 @@ def main():
     At, Pt = St.pack_aux(aux), St.pack_paths(paths)
     assert fhmc.lib.fh_debug_sweep_timing(St.plan, 1) == 0
     run_chain(St, At, Pt, 0, args.warmup, stream)
-    seg = [0.0, 0.0, 0.0]
-    fwd_chains, bwd_chains = [], []
+    seg = [0.0, 0.0, 0.0, 0.0]
+    fwd_chains, fwd_reps, bwd_chains = [], [], []
+    d0 = descs[0]                                                  # every chain has this shape
+    own = np.repeat(np.arange(d0.n_particles), 1)                  # one block per worldline
     with torch.cuda.stream(stream):
         for i in range(args.steps):
             held = fhmc.fh_debug_rescue_holds(St.plan, len(descs))
@@ -487,34 +489,52 @@ def main():
             for k, v in enumerate(fhmc.fh_debug_sweep_times(St.plan)):
                 seg[k] += v
             whole = fhmc.fh_debug_rescue(St.plan)[3]
+            # worldlines whose forward recursion ran: the representatives of the shared forward
+            # filters (every worldline on plans that share none), in the chains not held
+            rep = fhmc.fh_debug_representatives(St.plan)
+            shared = len(rep) > 0
+            n_rep = 0
+            for c in range(len(descs)):
+                if held[c] == 0:
+                    n_rep += (d0.n_particles if len(rep) == 0 else
+                              int(np.sum(rep[c * d0.n_particles:(c + 1) * d0.n_particles] == own)))
             fwd_chains.append(int(np.sum(held == 0)))
+            fwd_reps.append(n_rep)
             bwd_chains.append(len(descs) - whole)
     torch.cuda.synchronize()
     if not (torch.equal(At, A) and torch.equal(Pt, P)):
         raise RuntimeError("the timing replay did not reproduce the timed chain")
     St.close()
-    fwd_ms, bwd_ms, rescue_ms = (v / args.steps for v in seg)
-    extra["kernel_ms_per_sweep"] = {"forward": round(fwd_ms, 4), "backward": round(bwd_ms, 4),
-                                    "fp64_refilter": round(rescue_ms, 4),
-                                    "timing": "HIP events inside every timed sweep, averaged"}
-    log("  per sweep: forward %.3f ms, backward %.3f ms, FP64 re-filter %.3f ms" %
-        (fwd_ms, bwd_ms, rescue_ms))
+    fwd_ms, bwd_ms, rescue_ms, beside_ms = (v / args.steps for v in seg)
+    extra["kernel_ms_per_sweep"] = {
+        "forward": round(fwd_ms, 4), "backward": round(bwd_ms, 4),
+        "fp64_refilter": round(rescue_ms, 4), "fp64_refilter_beside": round(beside_ms, 4),
+        "timing": "HIP events inside every timed sweep, averaged; fp64_refilter_beside is the "
+                  "held chains' re-filter on the plan's side stream, concurrent with forward "
+                  "and backward"}
+    log("  per sweep: forward %.3f ms, backward %.3f ms, FP64 re-filter %.3f ms "
+        "(+ %.3f ms beside the FP32 passes)" % (fwd_ms, bwd_ms, rescue_ms, beside_ms))
     rsz = 8 if args.precision == "fp64" else 4
-    d0 = descs[0]                                                  # every chain has this shape
     rows = d0.n_particles * (d0.L_tau - 1)                         # per chain: one block each
     N = d0.N
     w_bytes = 2 * d0.L_tau * N * rsz                               # site potentials, both spins
     # backward: the full-row kernel reads every filter row; the windowed one reads the 7 x 7
     # window around the next slice's site (half-width 3 at dtau = 0.05), fallbacks aside
     read_per_row = N * rsz if args.full_row_draw else 49 * rsz
-    # per launch, averaged over the timed sweeps: the chains each launch worked on
+    # per launch, averaged over the timed sweeps: the chains each launch worked on, and the
+    # worldlines whose recursion the forward ran (rows written: L_tau - 1 per worldline plus the
+    # end tile of the shared filters)
     fwd_avg = sum(fwd_chains) / args.steps
+    rep_avg = sum(fwd_reps) / args.steps
     bwd_avg = sum(bwd_chains) / args.steps
-    algo = {"forward": round(fwd_avg * (rows * N * rsz + w_bytes)),
+    rows_per_rep = (d0.L_tau - 1) + (1 if shared else 0)
+    algo = {"forward": round(rep_avg * rows_per_rep * N * rsz + fwd_avg * w_bytes),
             "backward": round(bwd_avg * rows * (read_per_row + 4))}  # + the drawn site (int32)
     extra["fp32_kernel_chains_per_launch"] = {
-        "forward": fwd_avg, "backward": bwd_avg, "of": len(descs),
-        "last_3_sweeps": {"forward": fwd_chains[-3:], "backward": bwd_chains[-3:]}}
+        "forward": fwd_avg, "forward_worldlines": rep_avg, "backward": bwd_avg,
+        "of": len(descs), "worldlines_per_chain": d0.n_particles,
+        "last_3_sweeps": {"forward": fwd_chains[-3:], "forward_worldlines": fwd_reps[-3:],
+                          "backward": bwd_chains[-3:]}}
     times = {"forward": fwd_ms, "backward": bwd_ms}
     fwd_kernel = {"fp32_mfma3": "k_forward_mfma2", "fp64": "k_forward_dmfma"}.get(args.precision,
                                                                                  "k_forward_fft")
@@ -537,14 +557,14 @@ def main():
         # the same forward launch against the matrix cores: 24 bf16 MFMA 32x32x16 per
         # worldline-step (two circulant products, three-term splits, six products each); a
         # block of L_tau slices takes L_tau - 1 steps and one more product for its end weight
-        flops = round(fwd_avg * d0.n_particles * d0.L_tau * 24 * 32 * 32 * 16 * 2)
+        flops = round(rep_avg * d0.L_tau * 24 * 32 * 32 * 16 * 2)
         tf = flops / (times["forward"] / 1e3) / 1e12
         roofs["forward"]["matrix_cores"] = {
             "achieved": round(tf, 1), "peak": BF16_PEAK_TFS, "unit": "TFLOP/s",
             "frac": round(tf / BF16_PEAK_TFS, 4), "flops_per_launch": flops, "dtype": "bf16"}
     elif args.precision == "fp64":
         # FP64 circulant: 64 v_mfma_f64_16x16x4_f64 per worldline-step
-        flops = round(fwd_avg * d0.n_particles * d0.L_tau * 64 * 16 * 16 * 4 * 2)
+        flops = round(rep_avg * d0.L_tau * 64 * 16 * 16 * 4 * 2)
         tf = flops / (times["forward"] / 1e3) / 1e12
         roofs["forward"]["matrix_cores"] = {
             "achieved": round(tf, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",

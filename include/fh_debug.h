@@ -112,9 +112,12 @@ int fh_debug_rescue_holds(fh_plan plan, int32_t* holds);
 /* Per-sweep timing for the benchmark: with enable = 1, every sweep of fh_sweep records HIP events
  * of the plan around its forward-filter kernels, its backward-sampling kernels and the FP64
  * re-filter of out-of-range blocks (FP32 plans); the sweeps are then launched eagerly (the same
- * kernels on the same stream) instead of from the captured graph, whose event nodes cannot be
- * timed. fh_debug_sweep_times waits for the last sweep and writes the three durations in
- * milliseconds to ms[0..2] (caller-owned host memory). */
+ * kernels on the same streams) instead of from the captured graph, whose event nodes cannot be
+ * timed. fh_debug_sweep_times waits for the last sweep and writes four durations in
+ * milliseconds to ms[0..3] (caller-owned host memory): the forward kernels, the backward
+ * kernels, the FP64 re-filter on the caller's stream (including the wait for its phase A), and
+ * phase A, the re-filter of the chains held on FP64 on the plan's side stream, which runs beside
+ * the first two (0 on FP64 plans). */
 int fh_debug_sweep_timing(fh_plan plan, int32_t enable);
 int fh_debug_sweep_times(fh_plan plan, float* ms);
 

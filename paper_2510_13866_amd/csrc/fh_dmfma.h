@@ -58,13 +58,16 @@ __device__ inline int t64_y(int q, int r, int lane) { return 16 * (q >> 1) + 4 *
 // where la is log W_start(a), supplied by the caller. wtab(l, w) fills w[4 q + r] with W~ of
 // slice l at the lane's element (q, r) (any finite value at padded positions, where C f C is an
 // exact zero); put(j, q, r, v) receives element (q, r) of row f~_j, j = 1 .. len - 1, at the
-// lane's positions inside the L x L lattice only. Returns log Z; *ok becomes false when a
-// normaliser or the end weight is not a positive finite number.
-template <typename WTab, typename Put>
-__device__ inline double dmfma_block_forward(const double (&Cb)[16], int L, int L_tau, int start,
-                                             int len, int a, int e, double la,
-                                             const double* __restrict__ shift, WTab wtab, Put put,
-                                             bool* ok) {
+// lane's positions inside the L x L lattice only; put_end(q, r, v) the same elements of the end
+// tile C f~_{len-1} C, and *la_end log Z without the end weight (for worldlines that share these
+// rows but end elsewhere). Returns log Z; *ok becomes false when a normaliser or the end weight
+// is not a positive finite number.
+template <typename WTab, typename Put, typename PutEnd>
+__device__ inline double dmfma_block_forward_end(const double (&Cb)[16], int L, int L_tau,
+                                                 int start, int len, int a, int e, double la,
+                                                 const double* __restrict__ shift, WTab wtab,
+                                                 Put put, PutEnd put_end, double* la_end,
+                                                 bool* ok) {
     const int lane = threadIdx.x & 63;
     auto inside = [&](int q, int r) { return t64_x(q, lane) < L && t64_y(q, r, lane) < L; };
     const int ax = a % L, ay = a / L;
@@ -102,6 +105,12 @@ __device__ inline double dmfma_block_forward(const double (&Cb)[16], int L, int 
     }
     // end weight (C f~ C)(e)
     const Tile64 H = circ64(circ64(F, Cb), Cb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (inside(q, r)) put_end(q, r, H.t[q][r]);
+    *la_end = la;
     const int ex = e % L, ey = e / L;
     const int qe = 2 * (ey >> 4) + (ex >> 4), re = (ey & 15) >> 2;
     double hv = 0.0;
@@ -114,6 +123,17 @@ __device__ inline double dmfma_block_forward(const double (&Cb)[16], int L, int 
     good = good && hv > 0.0;
     *ok = good;
     return la + log(hv);
+}
+
+// dmfma_block_forward_end without the end tile.
+template <typename WTab, typename Put>
+__device__ inline double dmfma_block_forward(const double (&Cb)[16], int L, int L_tau, int start,
+                                             int len, int a, int e, double la,
+                                             const double* __restrict__ shift, WTab wtab, Put put,
+                                             bool* ok) {
+    double la_end;
+    return dmfma_block_forward_end(Cb, L, L_tau, start, len, a, e, la, shift, wtab, put,
+                                   [](int, int, double) {}, &la_end, ok);
 }
 
 }  // namespace fh

@@ -188,7 +188,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
                     d.draw_tasks, d.group_tasks, d.gpart, d.ckpt, d.rep, d.blk_la, d.endrow, d.dedup_tasks, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
-                    d.rescue, d.rescue_list, d.rescue_ws, d.rescue_w, d.status, d.sweep};
+                    d.rescue, d.rescue_list, d.rep_slot, d.rescue_ws, d.rescue_w, d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     d = fh::Device();
@@ -232,6 +232,13 @@ const char* fh_strerror(int code) {
         case FH_ERR_BAD_PATH: return "site index in paths out of range";
         default: return "unknown error";
     }
+}
+
+static void destroy_streams(fh_plan p) {
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+    if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+    if (p->join_ev) (void)hipEventDestroy(p->join_ev);
 }
 
 int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t precision,
@@ -471,7 +478,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         int64_t rescuable = 0;
         for (const ChainInfo& ci : p->chains)
             if (ci.L <= 32) {
-                p->rescue_slot_elems = std::max(p->rescue_slot_elems, (int64_t)(ci.B - 1) * ci.N);
+                // the block's rows and the end tile (phase A)
+                p->rescue_slot_elems = std::max(p->rescue_slot_elems, (int64_t)ci.B * ci.N);
                 rescuable += (int64_t)ci.np * ci.nb;
             }
         const int64_t waves = std::min<int64_t>(kRescueMaxSlots, std::max<int64_t>(rescuable, 1));
@@ -528,10 +536,11 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.perm_inv, sizeof(int32_t) * (size_t)part);
     if (e == hipSuccess) e = dalloc(&dv.sign, sizeof(int32_t) * (size_t)n_chains);
     if (e == hipSuccess && p->n_rescue_slots > 0) {
-        const size_t words = kRescueChain + 2 * (size_t)n_chains + (size_t)blk;
+        const size_t words = kRescueChain + 4 * (size_t)n_chains + (size_t)blk;
         e = dalloc(&dv.rescue, sizeof(int32_t) * words);
         if (e == hipSuccess) e = hipMemset(dv.rescue, 0, sizeof(int32_t) * words);
         if (e == hipSuccess) e = dalloc(&dv.rescue_list, sizeof(DrawTask) * draw.size());
+        if (e == hipSuccess) e = dalloc(&dv.rep_slot, sizeof(int32_t) * (size_t)blk);
         if (e == hipSuccess && !ckpt)
             e = dalloc(&dv.rescue_ws, sizeof(double) * (size_t)p->n_rescue_slots * p->rescue_slot_elems);
         if (e == hipSuccess) e = dalloc(&dv.rescue_w, sizeof(double) * 2 * (size_t)aux);
@@ -545,6 +554,11 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.sweep, sizeof(uint64_t));
     if (e == hipSuccess) e = hipMemcpy(dv.tables, p->tables.data(), sizeof(double) * p->tables.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess && dv.rescue) {  // FP32 plans: phase A of the re-filter beside the sweep
+        e = hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming);
+    }
     // the static scratch of fh_measure_noalloc on this device: an address that cannot be taken
     // only disables that entry point
     if (e == hipSuccess && scratch_address(&p->scratch) != hipSuccess) {
@@ -602,7 +616,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     }
     if (e != hipSuccess) {
         free_device(dv);
-        if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+        destroy_streams(p);
         delete p;
         (void)hipGetLastError();
         return hip_status(e);
@@ -618,7 +632,7 @@ int fh_destroy(fh_plan p) {
     for (hipEvent_t& ev : p->tev)
         if (ev) (void)hipEventDestroy(ev);
     free_device(p->d);
-    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    destroy_streams(p);
     delete p;
     return FH_OK;
 }
@@ -659,11 +673,12 @@ static hipError_t mark(fh_plan p, int k, hipStream_t s) {
     return p->timing ? hipEventRecord(p->tev[k], s) : hipSuccess;
 }
 
-static hipError_t enqueue_forward(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
-    hipError_t e = launch_potentials(p, aux, s);
-    if (e == hipSuccess) e = launch_rescue_reset(p, s);  // FP32 plans: empty re-filter queue
-    if (e == hipSuccess) e = mark(p, 0, s);
-    if (e == hipSuccess) e = launch_dedup(p, paths, s);  // shared forward filters
+// The forward kernels of a pass, from the shared-filter map (unless the caller ran it) to the
+// whole-chain queue.
+static hipError_t enqueue_forward_kernels(fh_plan p, const void* aux, const int32_t* paths,
+                                          hipStream_t s, bool dedup = true) {
+    hipError_t e = mark(p, 0, s);
+    if (e == hipSuccess && dedup) e = launch_dedup(p, paths, s);  // shared forward filters
     if (e != hipSuccess) return e;
     if (p->precision == FH_FP32_MFMA3) {
         e = launch_forward_mfma(p, aux, paths, s);
@@ -674,6 +689,13 @@ static hipError_t enqueue_forward(fh_plan p, const void* aux, const int32_t* pat
     if (e == hipSuccess) e = launch_member_logz(p, paths, s);
     if (e == hipSuccess) e = mark(p, 1, s);
     if (e == hipSuccess) e = launch_rescue_expand(p, s);  // FP32: chains re-filtered whole
+    return e;
+}
+
+static hipError_t enqueue_forward(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
+    hipError_t e = launch_potentials(p, aux, s);
+    if (e == hipSuccess) e = launch_rescue_reset(p, s);  // FP32 plans: empty re-filter queue
+    if (e == hipSuccess) e = enqueue_forward_kernels(p, aux, paths, s);
     return e;
 }
 
@@ -698,7 +720,7 @@ int fh_forward_filter(fh_plan p, const void* aux, const int32_t* paths, uint64_t
     FH_TRY(ensure_filters(p, s));
     FH_TRY(launch_set_sweep(p, sweep, s));
     FH_TRY(enqueue_forward(p, aux, paths, s));
-    FH_TRY(launch_rescue(p, aux, const_cast<int32_t*>(paths), false, s));  // FP64 log Z, rows
+    FH_TRY(launch_rescue(p, aux, const_cast<int32_t*>(paths), false, 0, s));  // FP64 log Z, rows
     if (logZ) FH_TRY(launch_logz_reduce(p, logZ, s));
     p->have_filters = true;
     p->filters_are_ring = false;
@@ -715,7 +737,7 @@ int fh_backward_sample(fh_plan p, int32_t* paths, uint64_t sweep, fh_stream stre
     hipStream_t s = (hipStream_t)stream;
     FH_TRY(launch_set_sweep(p, sweep, s));
     FH_TRY(launch_backward(p, paths, s));
-    FH_TRY(launch_rescue(p, p->last_aux, paths, true, s));  // blocks out of FP32's range
+    FH_TRY(launch_rescue(p, p->last_aux, paths, true, 0, s));  // blocks out of FP32's range
     return FH_OK;
 }
 
@@ -814,12 +836,33 @@ int fh_measure_noalloc(fh_plan p, const int32_t* paths, double* Sk, double* Cr, 
 }
 
 // One sweep reading its index from the device word, as recorded into a graph.
+// FP32 plans re-filter the chains held on FP64 (phase A) on the side stream, beside the FP32
+// forward and backward passes of the other chains; the blocks those passes queue follow on the
+// caller's stream once phase A has ended. The two touch disjoint chains: phase A writes the
+// held chains' sites and block log Z, which the FP32 kernels skip (held at the pass start, or
+// queued); the Gibbs draw reads every site after the join.
 static hipError_t enqueue_sweep_body(fh_plan p, void* aux, int32_t* paths, hipStream_t s) {
-    hipError_t e = enqueue_forward(p, aux, paths, s);
+    const bool split = p->side_stream != nullptr;
+    hipError_t e = launch_potentials(p, aux, s);
+    if (e == hipSuccess) e = launch_rescue_reset(p, s);
+    // the shared-filter map first: phase A sizes by it and reads it beside the forward pass
+    if (e == hipSuccess && split) e = launch_dedup(p, paths, s);
+    if (split) {
+        hipStream_t side = p->side_stream;
+        if (e == hipSuccess) e = launch_rescue_held(p, s);
+        if (e == hipSuccess) e = hipEventRecord(p->fork_ev, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, p->fork_ev, 0);
+        if (e == hipSuccess) e = mark(p, 5, side);
+        if (e == hipSuccess) e = launch_rescue(p, aux, paths, true, 1, side);
+        if (e == hipSuccess) e = mark(p, 6, side);
+        if (e == hipSuccess) e = hipEventRecord(p->join_ev, side);
+    }
+    if (e == hipSuccess) e = enqueue_forward_kernels(p, aux, paths, s, !split);
     if (e == hipSuccess) e = mark(p, 2, s);
     if (e == hipSuccess) e = launch_backward(p, paths, s);
     if (e == hipSuccess) e = mark(p, 3, s);
-    if (e == hipSuccess) e = launch_rescue(p, aux, paths, true, s);
+    if (e == hipSuccess && split) e = hipStreamWaitEvent(s, p->join_ev, 0);
+    if (e == hipSuccess) e = launch_rescue(p, aux, paths, true, split ? 2 : 0, s);
     if (e == hipSuccess) e = mark(p, 4, s);
     if (e == hipSuccess) e = launch_gibbs(p, paths, aux, s);
     return e;
@@ -1344,6 +1387,8 @@ int fh_debug_sweep_times(fh_plan p, float* ms) {
         const int a = k == 0 ? 0 : k + 1;
         FH_TRY(hipEventElapsedTime(&ms[k], p->tev[a], p->tev[a + 1]));
     }
+    ms[3] = 0.0f;
+    if (p->side_stream) FH_TRY(hipEventElapsedTime(&ms[3], p->tev[5], p->tev[6]));
     return FH_OK;
 }
 

@@ -129,13 +129,18 @@ constexpr int kRescueHold = 4;
 // Size of the static scratch array of fh_measure_noalloc: 2^22 doubles (32 MiB) per GPU.
 constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // Rescue state words: [0] blocks queued in this pass, [1] blocks redrawn since the last read by
-// fh_debug_rescue, [2] chains re-filtered whole in this pass, then per chain: blocks queued by
-// the kernels in this pass (kRescueChain + c) and forward passes left on FP64
-// (kRescueChain + n_chains + c), then one flag per (chain, particle, block) at
-// kRescueChain + 2 n_chains + blk_off + p nb + b (the `flags` pointer passed to the kernels).
-constexpr int kRescueChain = 4;
-// Wavefronts of the FP64 re-filter (two per SIMD of 256 CUs); each owns one slot of (B - 1) N
-// doubles.
+// fh_debug_rescue, [2] chains re-filtered whole in this pass, [3] length of the queue's phase A
+// (a sweep's held chains, queued before its FP32 forward pass and re-filtered beside the FP32
+// passes), [4] slots taken by phase A, then per chain: blocks queued by the kernels in this pass
+// (kRescueChain + c), forward passes left on FP64 (kRescueChain + n_chains + c), 1 if the chain
+// is in phase A (kRescueChain + 2 n_chains + c), the forward recursions its blocks need in this
+// pass (kRescueChain + 3 n_chains + c: the representatives of the shared filters), then one
+// flag per (chain, particle, block) at kRescueChain + 4 n_chains + blk_off + p nb + b (the
+// `flags` pointer passed to the kernels).
+constexpr int kRescueChain = 8;
+// Slots of the FP64 re-filter (two wavefronts per SIMD of 256 CUs), (B - 1) N doubles of rows
+// plus the end tile [N]. Phase 0 and 2 give each wavefront its own slot; phase A gives each
+// representative one (k_rescue_held admits held chains while their representatives fit).
 constexpr int kRescueMaxSlots = 2048;
 
 // Per-pass state of the FP32 plans as the kernels see it: the rescue words above, the per-block
@@ -144,7 +149,7 @@ constexpr int kRescueMaxSlots = 2048;
 // draws read; null where no chain shares, and on FP64 plans).
 struct Rescue {
     int32_t* words;   // null for FP64 plans
-    int32_t* flags;   // words + kRescueChain + 2 n_chains
+    int32_t* flags;   // words + kRescueChain + 4 n_chains
     DrawTask* list;
     int32_t n_chains;
     const int32_t* rep;
@@ -237,6 +242,7 @@ struct Device {
                                  // of the last windowed pass ([kBwCounts + chain])
     int32_t* rescue = nullptr;   // FP32 plans: rescue state words (kRescueFlags), else null
     DrawTask* rescue_list = nullptr;  // blocks queued for the FP64 re-filter, [n_draw_tasks]
+    int32_t* rep_slot = nullptr;      // phase A: the slot of each representative's block [blk]
     double* rescue_ws = nullptr;      // [n_rescue_slots][rescue_slot_elems] FP64 filter rows
     double* rescue_w = nullptr;       // [2][aux_elems] FP64 W~ of the chains with queued blocks
     int32_t* status = nullptr;   // [0] first error code, [1] its chain
@@ -290,9 +296,13 @@ struct fh_plan_s {
     const void* last_aux = nullptr;  // the field of the last fh_forward_filter (FP64 re-filter)
     void* scratch = nullptr;  // device address of the static scratch array on the plan's device
     // fh_debug_sweep_timing: events recorded around the forward kernels, the backward kernels and
-    // the FP64 re-filter of every sweep (inside the captured graph as well)
+    // the FP64 re-filter of every sweep, and around its phase A on the side stream
     bool timing = false;
-    hipEvent_t tev[6] = {};
+    hipEvent_t tev[8] = {};
+    // FP32 plans: a sweep re-filters the chains held on FP64 (phase A) on this stream, beside the
+    // FP32 forward and backward passes of the other chains on the caller's stream
+    hipStream_t side_stream = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     // graph cache for fh_sweep
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -307,7 +317,7 @@ namespace fh {
 inline Rescue rescue_args(fh_plan p) {
     Rescue r;
     r.words = p->d.rescue;
-    r.flags = p->d.rescue ? p->d.rescue + kRescueChain + 2 * p->n_chains : nullptr;
+    r.flags = p->d.rescue ? p->d.rescue + kRescueChain + 4 * p->n_chains : nullptr;
     r.list = p->d.rescue_list;
     r.rep = p->d.rep;
     r.n_chains = p->n_chains;
@@ -333,7 +343,13 @@ hipError_t launch_dedup(fh_plan p, const int32_t* paths, hipStream_t s);
 hipError_t launch_member_logz(fh_plan p, const int32_t* paths, hipStream_t s);
 hipError_t launch_rescue_reset(fh_plan p, hipStream_t s);
 hipError_t launch_rescue_expand(fh_plan p, hipStream_t s);  // after the FP32 forward pass
-hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, hipStream_t s);
+// Before a sweep's FP32 forward pass: queues the held chains whole as phase A.
+hipError_t launch_rescue_held(fh_plan p, hipStream_t s);
+// The FP64 re-filter of the queue: phase 0 all of it, 1 phase A, 2 the rest (after phase A).
+// Phase A runs the representatives' recursions into their slots, then every block's draws from
+// its representative's slot (launch_rescue with phase 1).
+hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, int phase,
+                         hipStream_t s);
 // Times every radix order of L (k_fft_tune) on stream s and returns the fastest in *best (the
 // default order unless another is faster by more than 2%); timings are appended to *log.
 hipError_t tune_radix_plan(fh_plan p, int L, const double* tw_dev, hipStream_t s,

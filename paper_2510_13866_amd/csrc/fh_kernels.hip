@@ -1299,8 +1299,10 @@ __device__ __attribute__((noinline)) void rescue_draws(const DrawTask& t, const 
 
 // FP64 re-filter and redraw of the blocks an FP32 pass queued because their filters left
 // FP32's range (kRangeFloor). The FP32 pass's rows for such a block hold values at FP32's floor
-// that decide its draws and log Z; FP64 holds them to ~2^-1022. One wavefront takes queued
-// blocks i = wid, wid + n_slots, ... in turn, with its own slot of FP64 rows:
+// that decide its draws and log Z; FP64 holds them to ~2^-1022. Phase 0 takes the whole queue,
+// phase 1 its phase A [0, words[3]) (a sweep's held chains, beside the FP32 passes), phase 2 the
+// rest (after phase 1 has ended). One wavefront takes queued blocks i = lo + wid,
+// lo + wid + n_slots, ... in turn, with its own slot of FP64 rows:
 //   forward: the block recursion of k_forward_dmfma on the FP64 circulant, with the FP64
 //            W~ = exp(coef aux - m_l) of k_rescue_potentials (the FP32 tables may hold zeros
 //            there); log Z to blk_logz; rows to the slot (DRAW), or else, rounded and scaled,
@@ -1318,14 +1320,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_rescue(
     const int32_t* __restrict__ perm, float* __restrict__ filt, double* __restrict__ blk_logz,
     const uint64_t* __restrict__ sweep_ptr, int32_t* status, const Rescue rsc,
     double* __restrict__ ws, int64_t slot_elems, int n_slots, const double* __restrict__ W64,
-    int64_t aux_elems) {
+    int64_t aux_elems, int phase) {
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
-    const int count = __builtin_amdgcn_readfirstlane(rsc.words[0]);
-    if (DRAW && wid == 0 && lane == 0 && count > 0) atomicAdd(&rsc.words[1], count);
+    // phase 1 reads only words[3]: the FP32 passes beside it still append to the queue
+    const int lo = phase == 2 ? __builtin_amdgcn_readfirstlane(rsc.words[3]) : 0;
+    const int hi = __builtin_amdgcn_readfirstlane(rsc.words[phase == 1 ? 3 : 0]);
+    if (DRAW && wid == 0 && lane == 0 && hi > lo) atomicAdd(&rsc.words[1], hi - lo);
     double* slot = ws + (int64_t)wid * slot_elems;
     const uint64_t sweep = *sweep_ptr;
-    for (int i = wid; i < count; i += n_slots) {
+    for (int i = lo + wid; i < hi; i += n_slots) {
         const DrawTask t = rsc.list[i];
         const ChainInfo& c = chains[t.chain];
         if (c.L > 32) {
@@ -1384,6 +1388,117 @@ __global__ __launch_bounds__(kThreads, 2) void k_rescue(
     }
 }
 
+// Phase A of the FP64 re-filter (the held chains, beside the FP32 passes), first kernel: the
+// forward recursion of each block whose worldline is its own representative (every block of a
+// chain without shared filters), one wavefront per block, into a slot of its own taken in queue
+// order (k_rescue_held admitted only chains whose recursions fit the slots): the rows, then the
+// end tile C f~ C. The block's log Z goes to blk_logz, log Z without the end weight to blk_la
+// (shared-filter chains), and the slot to rep_slot.
+__global__ __launch_bounds__(kThreads, 2) void k_rescue_share_fwd(
+    const ChainInfo* __restrict__ chains, const double* __restrict__ cmat64,
+    const float* __restrict__ aux, const double* __restrict__ wshift, int64_t total_slices,
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
+    double* __restrict__ blk_logz, double* __restrict__ blk_la,
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const Rescue rsc,
+    int32_t* __restrict__ rep_slot, double* __restrict__ ws, int64_t slot_elems, int n_waves,
+    const double* __restrict__ W64, int64_t aux_elems) {
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
+    const int hi = __builtin_amdgcn_readfirstlane(rsc.words[3]);
+    const uint64_t sweep = *sweep_ptr;
+    for (int i = wid; i < hi; i += n_waves) {
+        const DrawTask t = rsc.list[i];
+        const ChainInfo& c = chains[t.chain];
+        if (c.dedup && row_owner(rsc, c, t.p, t.block) != t.p) continue;  // shares these rows
+        int slot_id = 0;
+        if (lane == 0) slot_id = atomicAdd(&rsc.words[4], 1);
+        slot_id = __builtin_amdgcn_readfirstlane(__shfl(slot_id, 0, 64));
+        double* slot = ws + (int64_t)slot_id * slot_elems;
+        int start, len;
+        block_of(c, sweep, t.block, &start, &len);
+        const int L = c.L, N = c.N, L_tau = c.L_tau;
+        const int spin = t.p >= c.n_up ? 1 : 0;
+        const double coef = spin ? c.coef_dn : c.coef_up;
+        const double* shift = wshift + spin * total_slices + c.slice_off;
+        const int32_t* pc = paths + c.path_off;
+        const int qn = perm[c.part_off + t.p];  // the worldline slices >= L_tau belong to
+        const int a = checked_site(pc[(int64_t)start * c.np + t.p], N, status, t.chain);
+        const int e = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np +
+                                      (start + len >= L_tau ? qn : t.p)], N, status, t.chain);
+        double Cb[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) Cb[q] = cmat64[((int64_t)t.chain * 16 + q) * 64 + lane];
+        const double* Wl0 = W64 + spin * aux_elems + c.aux_off;
+        auto wtab = [&](int l, double (&w)[16]) {
+            const double* Wl = Wl0 + (int64_t)l * N;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {  // a padded position reads site 0, times 0
+                    const int x = t64_x(q, lane), y = t64_y(q, r, lane);
+                    w[4 * q + r] = Wl[(x < L && y < L) ? y * L + x : 0];
+                }
+        };
+        auto put = [&](int j, int q, int r, double v) {
+            slot[(int64_t)(j - 1) * N + t64_y(q, r, lane) * L + t64_x(q, lane)] = v;
+        };
+        double* end = slot + (int64_t)(c.B - 1) * N;  // after the longest block's rows
+        auto put_end = [&](int q, int r, double v) {
+            end[t64_y(q, r, lane) * L + t64_x(q, lane)] = v;
+        };
+        bool ok = true;
+        double la_end = 0.0;
+        const double lz = dmfma_block_forward_end(
+            Cb, L, L_tau, start, len, a, e, coef * (double)aux[c.aux_off + (int64_t)start * N + a],
+            shift, wtab, put, put_end, &la_end, &ok);
+        if (lane == 0) {
+            const int64_t bi = c.blk_off + (int64_t)t.p * c.nb + t.block;
+            if (!ok) set_status(status, FH_ERR_NONFINITE, t.chain);
+            blk_logz[bi] = lz;
+            if (c.dedup) blk_la[bi] = la_end;
+            rep_slot[bi] = slot_id;
+        }
+    }
+}
+
+// Phase A, second kernel: the draws of every queued block, one wavefront per block, from its
+// representative's slot (its own for a chain without shared filters), with the FP64 plans' rule
+// (rescue_draws); a block that shares rows also takes its log Z from the representative's log Z
+// without the end weight and the end tile at its own end site.
+__global__ __launch_bounds__(kThreads) void k_rescue_share_draw(
+    const ChainInfo* __restrict__ chains, const double* __restrict__ tables,
+    int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
+    double* __restrict__ blk_logz, const double* __restrict__ blk_la,
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const Rescue rsc,
+    const int32_t* __restrict__ rep_slot, const double* __restrict__ ws, int64_t slot_elems,
+    int n_waves) {
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
+    const int hi = __builtin_amdgcn_readfirstlane(rsc.words[3]);
+    if (wid == 0 && lane == 0 && hi > 0) atomicAdd(&rsc.words[1], hi);
+    const uint64_t sweep = *sweep_ptr;
+    for (int i = wid; i < hi; i += n_waves) {
+        const DrawTask t = rsc.list[i];
+        const ChainInfo& c = chains[t.chain];
+        const int ro = c.dedup ? row_owner(rsc, c, t.p, t.block) : t.p;
+        const int64_t ri = c.blk_off + (int64_t)ro * c.nb + t.block;
+        const double* slot = ws + (int64_t)rep_slot[ri] * slot_elems;
+        if (ro != t.p && lane == 0) {
+            int start, len;
+            block_of(c, sweep, t.block, &start, &len);
+            const int L_tau = c.L_tau;
+            const int qe = start + len >= L_tau ? perm[c.part_off + t.p] : t.p;  // reconnection
+            const int e = checked_site(
+                paths[c.path_off + (int64_t)((start + len) % L_tau) * c.np + qe], c.N, status,
+                t.chain);
+            const double hv = slot[(int64_t)(c.B - 1) * c.N + e];
+            if (!(hv > 0.0)) set_status(status, FH_ERR_NONFINITE, t.chain);
+            blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = blk_la[ri] + log(hv);
+        }
+        rescue_draws(t, c, tables + tab_g(c), paths, perm, sweep, status, lane, slot);
+    }
+}
+
 // Shared forward filters, before an FP32 forward pass: one workgroup per (chain, spin, block)
 // of the chains with dedup. The rows of a block depend only on the spin's W tables, the block's
 // slices and its start site, so every worldline of the (spin, block) is mapped to the lowest
@@ -1393,14 +1508,16 @@ __global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict_
                                                     const DrawTask* __restrict__ tasks,
                                                     const int32_t* __restrict__ paths,
                                                     const uint64_t* __restrict__ sweep_ptr,
-                                                    int32_t* __restrict__ rep) {
+                                                    int32_t* __restrict__ rep, const Rescue rsc) {
     __shared__ int32_t first[1024];  // dedup chains are 32 x 32
+    __shared__ int32_t n_rep;
     const DrawTask t = tasks[blockIdx.x];  // t.p holds the spin
     const ChainInfo& c = chains[t.chain];
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
     const int p0 = t.p ? c.n_up : 0, p1 = t.p ? c.np : c.n_up;
     for (int i = threadIdx.x; i < c.N; i += blockDim.x) first[i] = 0x7fffffff;
+    if (threadIdx.x == 0) n_rep = 0;
     __syncthreads();
     const int32_t* row = paths + c.path_off + (int64_t)start * c.np;
     for (int q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
@@ -1410,8 +1527,13 @@ __global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict_
     __syncthreads();
     for (int q = p0 + threadIdx.x; q < p1; q += blockDim.x) {
         const int a = row[q];  // an invalid site keeps its own rows (the forward reports it)
-        rep[c.blk_off + (int64_t)q * c.nb + t.block] = (a >= 0 && a < c.N) ? first[a] : q;
+        const int r = (a >= 0 && a < c.N) ? first[a] : q;
+        rep[c.blk_off + (int64_t)q * c.nb + t.block] = r;
+        if (r == q) atomicAdd(&n_rep, 1);
     }
+    __syncthreads();
+    // the chain's forward recursions in this pass (the FP64 re-filter's phase A sizes by them)
+    if (threadIdx.x == 0) atomicAdd(&rsc.words[kRescueChain + 3 * rsc.n_chains + t.chain], n_rep);
 }
 
 // After the FP32 forward pass, one thread per (chain, particle, block) of the chains with dedup:
@@ -1448,17 +1570,53 @@ __global__ void k_member_logz(const ChainInfo* __restrict__ chains, int n_chains
     }
 }
 
-// Before a forward pass: an empty queue, no block flagged, no chain counted (the per-chain
-// holds and the redrawn total stay).
+// Before a forward pass: an empty queue, no block flagged, no chain counted or in phase A (the
+// per-chain holds and the redrawn total stay).
 __global__ void k_rescue_reset(const Rescue rsc, int64_t n_flags) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (i == 0) {
         rsc.words[0] = 0;
         rsc.words[2] = 0;
+        rsc.words[3] = 0;
+        rsc.words[4] = 0;
     }
-    for (int64_t k = i; k < rsc.n_chains; k += stride) rsc.words[kRescueChain + k] = 0;
+    for (int64_t k = i; k < rsc.n_chains; k += stride) {
+        rsc.words[kRescueChain + k] = 0;
+        rsc.words[kRescueChain + 2 * rsc.n_chains + k] = 0;
+        rsc.words[kRescueChain + 3 * rsc.n_chains + k] = 0;
+    }
     for (int64_t k = i; k < n_flags; k += stride) rsc.flags[k] = 0;
+}
+
+// After k_rescue_reset and k_dedup, before a sweep's FP32 forward pass, one workgroup: every
+// block of each chain held on the FP64 re-filter (L <= 32) is queued, in chain order, as phase A,
+// and the chain is marked, while the chains' forward recursions (their representatives) fit the
+// n_slots slots; the FP32 kernels skip held chains and phase A re-filters them beside the FP32
+// passes (a held chain left out is queued whole after the forward pass, for phase 2). The queue
+// is empty before this kernel, so the entries are laid down in place.
+__global__ __launch_bounds__(kThreads) void k_rescue_held(const ChainInfo* __restrict__ chains,
+                                                          const Rescue rsc, int n_slots,
+                                                          int shared) {
+    int off = 0, slots = 0;
+    for (int ci = 0; ci < rsc.n_chains; ++ci) {
+        const ChainInfo& c = chains[ci];
+        if (c.L > 32 || !rescue_held(rsc, ci)) continue;
+        const int nblk = c.np * c.nb;
+        const int nrec = shared && c.dedup ? rsc.words[kRescueChain + 3 * rsc.n_chains + ci] : nblk;
+        if (slots + nrec > n_slots) continue;
+        slots += nrec;
+        for (int i = threadIdx.x; i < nblk; i += blockDim.x) {  // i = p nb + block
+            rsc.flags[c.blk_off + i] = 1;
+            rsc.list[off + i] = DrawTask{ci, i / c.nb, i % c.nb, 0};
+        }
+        if (threadIdx.x == 0) rsc.words[kRescueChain + 2 * rsc.n_chains + ci] = 1;
+        off += nblk;
+    }
+    if (threadIdx.x == 0) {
+        rsc.words[0] = off;
+        rsc.words[3] = off;
+    }
 }
 
 // After the FP32 forward pass, one workgroup per chain: a chain with more than whole_min blocks
@@ -1485,16 +1643,20 @@ __global__ __launch_bounds__(kThreads) void k_rescue_expand(const ChainInfo* __r
     }
 }
 
-// Before the FP64 re-filter, one workgroup per (chain, slice) of the chains with queued blocks:
+// Before the FP64 re-filter, one workgroup per (chain, slice) of the chains with blocks in the
+// phase's part of the queue (phase 0: queued; 1: in phase A; 2: queued, not in phase A):
 // W~ = exp(coef aux - m) in FP64 for both spins (the FP32 tables may hold zeros), with the
 // shift m of the FP32 tables.
 __global__ __launch_bounds__(kThreads) void k_rescue_potentials(
     const ChainInfo* __restrict__ chains, int n_chains, const float* __restrict__ aux,
     const double* __restrict__ wshift, double* __restrict__ W64, int64_t aux_elems,
-    int64_t total_slices, const Rescue rsc) {
+    int64_t total_slices, const Rescue rsc, int phase) {
     const int gs = blockIdx.x;
     const int ci = find_chain(n_chains, gs, [&](int i) { return chains[i].slice_off; });
-    if (rsc.words[kRescueChain + ci] == 0) return;  // nothing of this chain is queued
+    const bool in_a = rsc.words[kRescueChain + 2 * n_chains + ci] != 0;
+    const bool queued = phase == 1 ? in_a
+                                   : rsc.words[kRescueChain + ci] != 0 && !(phase == 2 && in_a);
+    if (!queued) return;  // nothing of this chain is in this phase
     const ChainInfo& c = chains[ci];
     const int64_t base = c.aux_off + (int64_t)(gs - c.slice_off) * c.N;
     const double mu = wshift[gs], md = wshift[total_slices + gs];
@@ -2330,7 +2492,7 @@ hipError_t launch_scale_copy(float* dst, const float* src, int64_t n, float fact
 hipError_t launch_dedup(fh_plan p, const int32_t* paths, hipStream_t s) {
     if (p->n_dedup_tasks == 0 || p->share_off) return hipSuccess;
     hipLaunchKernelGGL(k_dedup, dim3((unsigned)p->n_dedup_tasks), dim3(kThreads), 0, s,
-                       p->d.chains, p->d.dedup_tasks, paths, p->d.sweep, p->d.rep);
+                       p->d.chains, p->d.dedup_tasks, paths, p->d.sweep, p->d.rep, rescue_args(p));
     return hipGetLastError();
 }
 
@@ -2356,24 +2518,44 @@ hipError_t launch_rescue_expand(fh_plan p, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, hipStream_t s) {
+hipError_t launch_rescue_held(fh_plan p, hipStream_t s) {
+    if (!p->d.rescue) return hipSuccess;
+    hipLaunchKernelGGL(k_rescue_held, dim3(1), dim3(kThreads), 0, s, p->d.chains, rescue_args(p),
+                       p->n_rescue_slots, (int)(p->n_dedup_tasks > 0 && !p->share_off));
+    return hipGetLastError();
+}
+
+hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, int phase,
+                         hipStream_t s) {
     if (!p->d.rescue) return hipSuccess;
     hipLaunchKernelGGL(k_rescue_potentials, dim3((unsigned)p->total_slices), dim3(kThreads), 0, s,
                        p->d.chains, p->n_chains, (const float*)aux, p->d.wshift, p->d.rescue_w,
-                       p->aux_elems, p->total_slices, rescue_args(p));
+                       p->aux_elems, p->total_slices, rescue_args(p), phase);
     const unsigned blocks = (unsigned)(p->n_rescue_slots / kWaves);
-    if (draw)
+    if (draw && phase == 1) {  // representatives into their slots, then every block's draws
+        hipLaunchKernelGGL(k_rescue_share_fwd, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.cmat64, (const float*)aux, p->d.wshift, p->total_slices, paths,
+                           p->d.perm, p->d.blk_logz, p->d.blk_la, p->d.sweep, p->d.status,
+                           rescue_args(p), p->d.rep_slot, p->d.rescue_ws, p->rescue_slot_elems,
+                           p->n_rescue_slots, p->d.rescue_w, p->aux_elems);
+        hipLaunchKernelGGL(k_rescue_share_draw, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.tables, paths, p->d.perm, p->d.blk_logz, p->d.blk_la,
+                           p->d.sweep, p->d.status, rescue_args(p), p->d.rep_slot,
+                           p->d.rescue_ws, p->rescue_slot_elems, p->n_rescue_slots);
+    } else if (draw)
         hipLaunchKernelGGL(k_rescue<true>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.tables, p->d.cmat64, (const float*)aux, p->d.wshift,
                            p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
                            p->d.sweep, p->d.status, rescue_args(p), p->d.rescue_ws,
-                           p->rescue_slot_elems, p->n_rescue_slots, p->d.rescue_w, p->aux_elems);
+                           p->rescue_slot_elems, p->n_rescue_slots, p->d.rescue_w, p->aux_elems,
+                           phase);
     else
         hipLaunchKernelGGL(k_rescue<false>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.tables, p->d.cmat64, (const float*)aux, p->d.wshift,
                            p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
                            p->d.sweep, p->d.status, rescue_args(p), p->d.rescue_ws,
-                           p->rescue_slot_elems, p->n_rescue_slots, p->d.rescue_w, p->aux_elems);
+                           p->rescue_slot_elems, p->n_rescue_slots, p->d.rescue_w, p->aux_elems,
+                           phase);
     return hipGetLastError();
 }
 

@@ -314,7 +314,8 @@ def fh_debug_representatives(plan):
 
 
 def fh_debug_sweep_times(plan):
-    """(forward, backward, FP64 re-filter) milliseconds of the last sweep (timing enabled)."""
-    ms = (ctypes.c_float * 3)()
+    """(forward, backward, FP64 re-filter, its phase A beside the first two) milliseconds of the
+    last sweep (timing enabled)."""
+    ms = (ctypes.c_float * 4)()
     _check(lib.fh_debug_sweep_times(plan, ms), "fh_debug_sweep_times")
-    return ms[0], ms[1], ms[2]
+    return ms[0], ms[1], ms[2], ms[3]
