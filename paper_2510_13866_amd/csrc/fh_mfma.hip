@@ -129,6 +129,16 @@ __device__ inline float wave_sum_f32(float v) {
     return (r0 + r1) + (r2 + r3);
 }
 
+// Sum over a block's steps j = 1 .. len - 1 of the W shift of slice start + j less the rows'
+// scale: the shifts' part of log Z, wavefront-uniform. Taken once after the recursion, lanes in
+// parallel; a load of the shift inside the recursion stalls every step on it.
+__device__ inline double block_shift_sum(const double* __restrict__ shift, int start, int len,
+                                         int L_tau, double lsc, int lane) {
+    double m = 0.0;
+    for (int j = 1 + lane; j < len; j += 64) m += shift[(start + j) % L_tau];
+    return wave_sum_f64(m) - (double)(len - 1) * lsc;
+}
+
 // One wavefront per (chain, worldline, block): the forward recursion of one block
 //   f~_0 = delta_a; h_j = W~_{start+j} . (C f~_{j-1} C); c_j = sum h_j; f~_j = h_j / c_j
 //   log Z = coef aux_start(a) + sum_j (log c_j + m_{start+j}) + log (C f~_{len-1} C)(e)
@@ -192,6 +202,7 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     // rows hold f~ 2^row_exp (the FP32 range scaling), from f_0 = 2^row_exp delta_a on
     const float sc = ldexpf(1.0f, c.row_exp);
     const double lsc = c.row_exp * 0.69314718055994530942;
+    const float step_floor = c.step_floor;  // held in a register across the recursion
     f32x16 F;
 #pragma unroll
     for (int v = 0; v < 16; ++v) F[v] = (x == ax && tile_row(lane, v) == ay) ? sc : 0.0f;
@@ -215,7 +226,7 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
             s += F[v];
         }
         const float tot = wave_sum_f32(s);
-        low = low || !(tot >= c.step_floor) || !isfinite(tot);
+        low |= !(tot >= step_floor) | !isfinite(tot);
         // f~_j = h_j * inv, so the normaliser actually applied is exactly 1/inv: log Z takes
         // -log(inv), accumulated as an FP64 product folded into the log occasionally; the
         // rows carry the power of two sc on top
@@ -225,7 +236,6 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
             la -= log(prod);
             prod = 1.0;
         }
-        la += shift[l] - lsc;
         const float k = inv * sc;
         float* row = rows + (int64_t)(j - 1) * N + lane_off;
 #pragma unroll
@@ -241,6 +251,7 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
         step(1);
         for (int j = 2; j < len; ++j) step(j);
     }
+    la += block_shift_sum(shift, start, len, L_tau, lsc, lane);
     // end weight (C f~ C)(e)
     const f32x16 X = circ_step(F, C, neg);
     const f32x16 H = circ_step(X, C, neg);
@@ -398,6 +409,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     // rows hold f~ 2^row_exp (the FP32 range scaling), from f_0 = 2^row_exp delta_a on
     const float sc = ldexpf(1.0f, c.row_exp);
     const double lsc = c.row_exp * 0.69314718055994530942;
+    const float step_floor = c.step_floor;  // held in a register across the recursion
     f32x16 F0, F1;
     {
         const int ax0 = a[0] % L, ay0 = a[0] / L, ax1 = a[1] % L, ay1 = a[1] / L;
@@ -440,8 +452,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
         load_w((l + 1) % L_tau, wn);
         __builtin_amdgcn_sched_barrier(0);
         const float tot0 = wave_sum_f32(s0), tot1 = wave_sum_f32(s1);
-        low0 = low0 || !(tot0 >= c.step_floor) || !isfinite(tot0);
-        low1 = low1 || !(tot1 >= c.step_floor) || !isfinite(tot1);
+        low0 |= !(tot0 >= step_floor) | !isfinite(tot0);
+        low1 |= !(tot1 >= step_floor) | !isfinite(tot1);
         // f~_j = h_j * inv: the normaliser applied is exactly 1/inv (see k_forward_mfma)
         const float inv0 = __builtin_amdgcn_rcpf(tot0), inv1 = __builtin_amdgcn_rcpf(tot1);
         prod0 *= (double)inv0;
@@ -454,9 +466,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
             la1 -= log(prod1);
             prod1 = 1.0;
         }
-        const double m = shift[l] - lsc;
-        la0 += m;
-        la1 += m;
         const float k0 = inv0 * sc, k1 = inv1 * sc;
         float* row0 = rows0 + (int64_t)(j - 1) * N + lane_off;
         float* row1 = rows1 + (int64_t)(j - 1) * N + lane_off;
@@ -473,6 +482,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     if (len > 1) {
         step(1);
         for (int j = 2; j < len; ++j) step(j);
+    }
+    {
+        const double ms = block_shift_sum(shift, start, len, L_tau, lsc, lane);
+        la0 += ms;
+        la1 += ms;
     }
     // end weights (C f~ C)(e)
     const f32x16 X0 = circ_step(F0, C, neg);
@@ -612,6 +626,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
     // rows hold f~ 2^row_exp (the FP32 range scaling), from f_0 = 2^row_exp delta_a on
     const float sc = ldexpf(1.0f, c.row_exp);
     const double lsc = c.row_exp * 0.69314718055994530942;
+    const float step_floor = c.step_floor;  // held in a register across the recursion
     f32x16 F[2][2];
     {
         const int ax = a % L, ay = a / L;
@@ -649,7 +664,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
         load_w((l + 1) % L_tau, wn);  // the last step fetches a slice it does not use
         __builtin_amdgcn_sched_barrier(0);
         const float tot = wave_sum_f32(s);
-        low = low || !(tot >= c.step_floor) || !isfinite(tot);
+        low |= !(tot >= step_floor) | !isfinite(tot);
         // f~_j = h_j * inv: the normaliser applied is exactly 1/inv (see k_forward_mfma)
         const float inv = __builtin_amdgcn_rcpf(tot);
         prod *= (double)inv;
@@ -657,7 +672,6 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
             la -= log(prod);
             prod = 1.0;
         }
-        la += shift[l] - lsc;
         const float k = inv * sc;
         float* row = rows + (int64_t)(j - 1) * N + lane_off;
 #pragma unroll
@@ -670,6 +684,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
                     __builtin_nontemporal_store(F[R][S][v], row + 32 * (R * L + S) + vrow(v) * L);
                 }
     }
+    la += block_shift_sum(shift, start, len, L_tau, lsc, lane);
     // end weight (C f~ C)(e)
     f32x16 X[2][2], H[2][2];
     circ64_step(F, X, T, neg);
@@ -789,6 +804,7 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
     // rows hold f~ 2^row_exp (the FP32 range scaling), from f_0 = 2^row_exp delta_a on
     const float sc = ldexpf(1.0f, c.row_exp);
     const double lsc = c.row_exp * 0.69314718055994530942;
+    const float step_floor = c.step_floor;  // held in a register across the recursion
     f32x16 F[NT];
 #pragma unroll
     for (int T = 0; T < NT; ++T)
@@ -867,13 +883,12 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
                 mine = oti == T * P + I ? inv[T][I] : mine;
                 mtot = oti == T * P + I ? tot : mtot;
             }
-        low = low || !(mtot >= c.step_floor && mtot <= 3.402823466e38f);
+        low |= !(mtot >= step_floor && mtot <= 3.402823466e38f);
         // log Z -= log(inv): FP64 mantissa times 2^ex2, renormalised every step
         mant *= (double)mine;
         int e;
         mant = frexp(mant, &e);
         ex2 += e;
-        la += shift[l] - lsc;
         // byte offsets: lane part in a VGPR, row and register part in an SGPR
         const int rowj = (j - 1) * N;
 #pragma unroll
@@ -903,6 +918,7 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
         step(1);
         for (int j = 2; j < len; ++j) step(j);
     }
+    la += block_shift_sum(shift, start, len, L_tau, lsc, lane);
     // end weights (C f~ C)(e) of every slot: the owner reads its block's element at e
     f32x16 H[NT];
 #pragma unroll
