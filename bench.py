@@ -551,7 +551,14 @@ def main():
                     "traffic": measured_traffic(k, args.precision, knames[k]),
                     "kernel": names[k], "ms_per_launch": round(times[k], 4),
                     "algorithmic_bytes_per_launch": algo[k],
-                    "timing": "average over the timed sweeps"}
+                    "timing": "average over the timed sweeps",
+                    # a worldline's recursion (forward) or its draws (backward) are L_tau - 1
+                    # dependent steps; once the chain has clustered, the forward runs one
+                    # recursion per start site (the shared forward filters), so both launches
+                    # are then bound by that chain of steps, not by HBM
+                    "critical_path": {
+                        "dependent_steps": d0.L_tau - 1,
+                        "us_per_step": round(times[k] * 1e3 / (d0.L_tau - 1), 2)}}
         log("  %s %.3f ms/launch, %.0f GB/s algorithmic" % (names[k], times[k], gbs))
     if args.precision == "fp32_mfma3":
         # the same forward launch against the matrix cores: 24 bf16 MFMA 32x32x16 per
