@@ -136,4 +136,108 @@ __device__ inline double dmfma_block_forward(const double (&Cb)[16], int L, int 
                                    [](int, int, double) {}, &la_end, ok);
 }
 
+// Lattices of side L = 16 NT with NT = 3 or 4 (L = 48, 64) on the same instruction. The filter
+// is NT x NT tiles of 16 x 16, tile q = NT I + J holding rows 16 I .. and columns 16 J .., its
+// element (16 I + 4 r + lane / 16, 16 J + lane % 16) in register r, as above. C[k][j] =
+// g((k - j) mod L) is then block-circulant: its 16 x 16 block (K, J) depends only on
+// D = (K - J) mod NT, and the B operands are Cb[4 D + r], lane j + 16 k holding
+// g((16 D + 4 r + k - j) mod L):
+//   (X^T C)(I, J) = sum over K, r of mfma(X(K, I)[r], Cb[4 ((K - J) mod NT) + r]),
+// 4 NT^3 products per multiplication, every product and sum in FP64, as for L <= 32.
+template <int NT>
+struct TileBig {
+    f64x4 t[NT * NT];
+};
+
+template <int NT>
+__device__ inline void circ_big(const TileBig<NT>& X, const double (&Cb)[16], TileBig<NT>& Y) {
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+        for (int J = 0; J < NT; ++J) {
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int K = 0; K < NT; ++K)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                        X.t[NT * K + I][r], Cb[4 * ((K - J + NT) % NT) + r], acc, 0, 0, 0);
+            Y.t[NT * I + J] = acc;
+        }
+}
+
+// Site coordinates of element (tile q, register r) of a lane in the NT x NT tiling.
+template <int NT>
+__device__ inline int tb_x(int q, int lane) { return 16 * (q % NT) + (lane & 15); }
+template <int NT>
+__device__ inline int tb_y(int q, int r, int lane) { return 16 * (q / NT) + 4 * r + (lane >> 4); }
+
+// dmfma_block_forward_end for L = 16 NT: the same recursion, normaliser, log Z and outputs.
+// wtab(l, w) fills w[4 q + r] with W~ of slice l at the lane's element (q, r); every element is
+// a lattice site, so put and put_end see all of them.
+template <int NT, typename WTab, typename Put, typename PutEnd>
+__device__ inline double dmfma_big_block_forward_end(const double (&Cb)[16], int L_tau,
+                                                     int start, int len, int a, int e, double la,
+                                                     const double* __restrict__ shift, WTab wtab,
+                                                     Put put, PutEnd put_end, double* la_end,
+                                                     bool* ok) {
+    constexpr int L = 16 * NT, NQ = NT * NT;
+    const int lane = threadIdx.x & 63;
+    const int ax = a % L, ay = a / L;
+    TileBig<NT> F, X;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            F.t[q][r] = (tb_x<NT>(q, lane) == ax && tb_y<NT>(q, r, lane) == ay) ? 1.0 : 0.0;
+    bool good = true;
+    for (int j = 1; j < len; ++j) {
+        const int l = (start + j) % L_tau;
+        circ_big<NT>(F, Cb, X);
+        circ_big<NT>(X, Cb, F);
+        // W after the products: loaded before them, the slice would need 2 NT^2 more registers
+        double w[4 * NQ];
+        wtab(l, w);
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                F.t[q][r] *= w[4 * q + r];
+                sum += F.t[q][r];
+            }
+        const double tot = wave_sum_f64(sum);
+        good = good && tot > 0.0 && isfinite(tot);
+        const double inv = 1.0 / tot;
+        la += log(tot) + shift[l];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                F.t[q][r] *= inv;
+                put(j, q, r, F.t[q][r]);
+            }
+    }
+    // end weight (C f~ C)(e)
+    circ_big<NT>(F, Cb, X);
+    circ_big<NT>(X, Cb, F);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) put_end(q, r, F.t[q][r]);
+    *la_end = la;
+    const int ex = e % L, ey = e / L;
+    const int qe = NT * (ey >> 4) + (ex >> 4), re = (ey & 15) >> 2;
+    double hv = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (q == qe && r == re) hv = F.t[q][r];
+    hv = __shfl(hv, (ex & 15) + 16 * (ey & 3), 64);
+    good = good && hv > 0.0;
+    *ok = good;
+    return la + log(hv);
+}
+
 }  // namespace fh

@@ -87,6 +87,14 @@ double bf16_val(uint16_t b) {
 // B operands of the FP64 circulant for v_mfma_f64_16x16x4_f64: slot (4 K + r) * 2 + J, lane l
 // holds C[16 K + 4 r + l / 16][16 J + l % 16], C[k][j] = g((k - j) mod L) inside L x L, else 0.
 void build_cmat64(int L, const double* g, double* out) {
+    if (const int NT = big_nt(L)) {  // block-circulant operands: entry 4 D + r
+        for (int q = 0; q < 16; ++q)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int D = q / 4, r = q % 4, k = lane / 16, j = lane % 16;
+                out[q * 64 + lane] = D < NT ? g[((16 * D + 4 * r + k - j) % L + L) % L] : 0.0;
+            }
+        return;
+    }
     for (int K = 0; K < 2; ++K)
         for (int r = 0; r < 4; ++r)
             for (int J = 0; J < 2; ++J)
@@ -397,18 +405,23 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     }
     // FP64 plans: chains with L <= 32 on the FP64 circulant, the others on the FFT
     auto dmfma = [&](int c) {
-        return precision == FH_FP64 && !(flags & FH_FLAG_FFT_CONV) && p->chains[c].L <= 32;
+        return precision == FH_FP64 && !(flags & FH_FLAG_FFT_CONV) &&
+               fp64_circulant(p->chains[c].L);
     };
     std::vector<PairTask> fwdf;
     // shared forward filters: the 32 x 32 chains of the matrix-core plan (one tile per worldline
-    // pair); k_dedup runs one workgroup per (chain, spin, block)
+    // pair; dedup = 1), and, in the FP64 re-filter of held chains only, the 48 x 48 and 64 x 64
+    // chains of FP32 plans (dedup = 2); k_dedup runs one workgroup per (chain, spin, block)
     std::vector<DrawTask> dedup;
     for (int c = 0; c < n_chains; ++c) {
         ChainInfo& ci = p->chains[c];
-        ci.dedup = precision == FH_FP32_MFMA3 && ci.L == 32;
+        ci.dedup = (precision == FH_FP32_MFMA3 && ci.L == 32) ? 1
+                   : (precision != FH_FP64 && big_nt(ci.L) != 0) ? 2 : 0;
         if (!ci.dedup) continue;
-        ci.end_off = p->end_elems;
-        p->end_elems += (int64_t)ci.np * ci.nb * ci.N;
+        if (ci.dedup == 1) {
+            ci.end_off = p->end_elems;
+            p->end_elems += (int64_t)ci.np * ci.nb * ci.N;
+        }
         for (int spin = 0; spin < 2; ++spin)
             if ((spin ? ci.n_dn : ci.n_up) > 0)
                 for (int b = 0; b < ci.nb; ++b) dedup.push_back({c, spin, b, 0});
@@ -417,10 +430,14 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     std::vector<DrawTask> fwdd;
     for (const PairTask& t : fwd)
         if (!dmfma(t.chain)) fwdf.push_back(t);
-    for (const DrawTask& t : draw)
-        if (dmfma(t.chain)) fwdd.push_back(t);
+    for (int nt : {2, 4, 3})  // L <= 32, then 64, then 48 (one launch each)
+        for (const DrawTask& t : draw)
+            if (dmfma(t.chain) && (nt == 2 ? p->chains[t.chain].L <= 32
+                                           : big_nt(p->chains[t.chain].L) == nt)) {
+                fwdd.push_back(t);
+                (nt == 2 ? p->n_fwdd_tasks : nt == 4 ? p->n_fwdd4_tasks : p->n_fwdd3_tasks)++;
+            }
     p->n_fwd_tasks = (int32_t)fwdf.size();
-    p->n_fwdd_tasks = (int32_t)fwdd.size();
     p->n_draw_tasks = (int32_t)draw.size();
     std::vector<PairTask> fwd32;
     std::vector<DrawTask> fwdx, draw32, draww, drawx;
@@ -473,11 +490,13 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->gpart_elems = gpart;
 
     // FP32 plans: the FP64 re-filter of blocks that leave FP32's range, one slot of FP64 rows
-    // per wavefront, sized for the longest block of the chains with L <= 32
+    // per wavefront, sized for the longest block of the chains it takes (L <= 32, 48, 64)
     if (precision != FH_FP64) {
         int64_t rescuable = 0;
         for (const ChainInfo& ci : p->chains)
-            if (ci.L <= 32) {
+            if (fp64_circulant(ci.L)) {
+                p->rescue_l48 = p->rescue_l48 || ci.L == 48;
+                p->rescue_l64 = p->rescue_l64 || ci.L == 64;
                 // the block's rows and the end tile (phase A)
                 p->rescue_slot_elems = std::max(p->rescue_slot_elems, (int64_t)ci.B * ci.N);
                 rescuable += (int64_t)ci.np * ci.nb;
@@ -501,7 +520,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess && !dedup.empty()) {
         e = dalloc(&dv.rep, sizeof(int32_t) * (size_t)blk);
         if (e == hipSuccess) e = dalloc(&dv.blk_la, sizeof(double) * (size_t)blk);
-        if (e == hipSuccess) e = dalloc(&dv.endrow, sizeof(float) * (size_t)p->end_elems);
+        if (e == hipSuccess && p->end_elems > 0)
+            e = dalloc(&dv.endrow, sizeof(float) * (size_t)p->end_elems);
         if (e == hipSuccess) e = dalloc(&dv.dedup_tasks, sizeof(DrawTask) * dedup.size());
         if (e == hipSuccess)
             e = hipMemcpy(dv.dedup_tasks, dedup.data(), sizeof(DrawTask) * dedup.size(),
@@ -683,7 +703,7 @@ static hipError_t enqueue_forward_kernels(fh_plan p, const void* aux, const int3
     if (p->precision == FH_FP32_MFMA3) {
         e = launch_forward_mfma(p, aux, paths, s);
     } else {
-        e = launch_forward_dmfma(p, aux, paths, s);  // FP64 plans, chains with L <= 32
+        e = launch_forward_dmfma(p, aux, paths, s);  // FP64 plans: the FP64 circulant chains
         if (e == hipSuccess && p->n_fwd_tasks > 0) e = launch_forward(p, aux, paths, s);
     }
     if (e == hipSuccess) e = launch_member_logz(p, paths, s);

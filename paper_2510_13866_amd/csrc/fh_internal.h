@@ -47,10 +47,13 @@ struct ChainInfo {
     // ckpt[ck_row_off + (p ck_n + j / K) N] and recomputes each segment from its checkpoint
     int64_t ck_row_off;
     int32_t ck_k, ck_n;
-    // Shared forward filters (FP32 plans, 32 x 32 chains): the rows of a block depend only on the
-    // spin's W and the block's start site, so worldlines of one (spin, block) with the same start
-    // site share the rows of the lowest-numbered of them, their representative. dedup = 1 for
-    // such chains; end_off locates their per-(particle, block) end tiles [N].
+    // Shared forward filters: the rows of a block depend only on the spin's W and the block's
+    // start site, so worldlines of one (spin, block) with the same start site share the rows of
+    // the lowest-numbered of them, their representative. dedup = 1: 32 x 32 chains of the
+    // split-bf16 plan, in the FP32 passes and the FP64 re-filter's phase A; end_off locates their
+    // per-(particle, block) end tiles [N]. dedup = 2: 48 x 48 and 64 x 64 chains of FP32 plans,
+    // in phase A only (their FP32 passes keep one recursion per worldline, and their map is the
+    // identity while the chain is not held).
     int32_t dedup;
     int64_t end_off;
 };
@@ -64,6 +67,11 @@ inline int64_t tab_size(int L) { return 2 * (int64_t)L * L + L + 2 * L; }
 constexpr int kBwCounts = 4;  // offset of the per-chain counts in Device::bw_state
 constexpr int kCmatPerChain = 3 * 2 * 64 * 8;
 constexpr int kCmat64PerChain = 16 * 64;
+// Lattices above 32 that the FP64 circulant takes (fh_dmfma.h): L = 16 NT with NT = 3 or 4; 0
+// for every other L.
+FH_HD inline int big_nt(int L) { return L == 48 ? 3 : L == 64 ? 4 : 0; }
+// Chains whose blocks the FP64 re-filter can redo (L <= 32 or a big_nt lattice).
+FH_HD inline bool fp64_circulant(int L) { return L <= 32 || big_nt(L) != 0; }
 
 // Block of a sweep: start slice and length (the schedule of fh.h).
 FH_HD inline void block_of(const ChainInfo& c, uint64_t sweep, int b, int* start, int* len) {
@@ -142,6 +150,10 @@ constexpr int kRescueChain = 8;
 // plus the end tile [N]. Phase 0 and 2 give each wavefront its own slot; phase A gives each
 // representative one (k_rescue_held admits held chains while their representatives fit).
 constexpr int kRescueMaxSlots = 2048;
+constexpr int kDedupMaxN = 4096;  // sites of the largest chain with shared filters (64 x 64)
+// Shared forward filters: a chain whose representatives' rows (this pass) take at most this many
+// bytes writes them with cached stores, the rest with nontemporal ones.
+constexpr int64_t kCachedRowBytes = 16ll << 20;
 
 // Per-pass state of the FP32 plans as the kernels see it: the rescue words above, the per-block
 // flags, the queue, and the representative map of the shared forward filters (rep, per
@@ -200,7 +212,7 @@ struct Device {
     uint16_t* cmatp = nullptr; // per chain with L <= kPackMaxL: the block-diagonal operand, same layout
     uint16_t* cmatb = nullptr; // per chain with L = 64: the blocks T0 = C_00 and T1 = C_01, same layout
     double* cmat64 = nullptr;  // per chain: FP64 circulant B operands [16][64]
-    DrawTask* fwdd_tasks = nullptr;  // FP64 circulant forward: worldline blocks of L <= 32 chains
+    DrawTask* fwdd_tasks = nullptr;  // FP64 circulant forward: worldline blocks (L <= 32, 48, 64)
     void* W = nullptr;        // [2][sum L_tau*N] in plan precision (up, then down)
     double* wshift = nullptr; // [2][total slices]: log W = log W~ + wshift per (spin, slice)
     void* filt = nullptr;     // filter workspace, plan precision
@@ -272,6 +284,9 @@ struct fh_plan_s {
     int32_t max_N_x = 0;  // largest N among the chains of drawx_tasks
     int32_t n_draww_tasks = 0, n_drawx_tasks = 0;
     int32_t n_fwdd_tasks = 0;  // FP64 circulant forward tasks (the FFT takes n_fwd_tasks pairs)
+    // after them in fwdd_tasks: the tasks of the 64 x 64, then of the 48 x 48 chains
+    int32_t n_fwdd4_tasks = 0, n_fwdd3_tasks = 0;
+    bool rescue_l48 = false, rescue_l64 = false;  // FP32 plans: chains the big FP64 re-filter takes
     bool grad_dmfma = false;   // FP64 plan whose chains all have L <= 32: adjoint on the matrix cores
     double win_bound_scale = 1.0;  // test hook: >= 1 inflates every window bound
     bool bw_adapt = true;          // switch clustered chains to the full-row kernels

@@ -340,7 +340,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_fft(
     const PairTask t = tasks[blockIdx.x];
     const ChainInfo& c = chains[t.chain];
     // re-filtered whole in FP64 this pass (the whole workgroup leaves: no barrier is skipped)
-    if (c.L <= 32 && rescue_held(rsc, t.chain)) return;
+    if (fp64_circulant(c.L) && rescue_held(rsc, t.chain)) return;
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
     const bool has_b = t.p_b >= 0;
@@ -1309,11 +1309,13 @@ __device__ __attribute__((noinline)) void rescue_draws(const DrawTask& t, const 
 //            to the plan's FP32 rows (what fh_get_filters returns after fh_forward_filter);
 //   DRAW:    the block's sites from the slot's rows with k_backward's full-row rule and the same
 //            Philox uniforms, so the draws are those of an FP64 plan.
-// Only chains with L <= 32 have the FP64 circulant; a queued block of a larger lattice latches
+// NT = 2 takes the chains with L <= 32; NT = 3 and 4 the 48 x 48 and 64 x 64 chains (one
+// wavefront per SIMD: their tiles take 256 registers), each launch skipping the other chains'
+// blocks. A queued block of a lattice without the FP64 circulant (fp64_circulant) latches
 // FH_ERR_NONFINITE and keeps its sites. Every wavefront reads the queue length once and leaves
 // when its share is done.
-template <bool DRAW>
-__global__ __launch_bounds__(kThreads, 2) void k_rescue(
+template <bool DRAW, int NT>
+__global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_rescue(
     const ChainInfo* __restrict__ chains, const double* __restrict__ tables,
     const double* __restrict__ cmat64, const float* __restrict__ aux,
     const double* __restrict__ wshift, int64_t total_slices, int32_t* __restrict__ paths,
@@ -1326,19 +1328,22 @@ __global__ __launch_bounds__(kThreads, 2) void k_rescue(
     // phase 1 reads only words[3]: the FP32 passes beside it still append to the queue
     const int lo = phase == 2 ? __builtin_amdgcn_readfirstlane(rsc.words[3]) : 0;
     const int hi = __builtin_amdgcn_readfirstlane(rsc.words[phase == 1 ? 3 : 0]);
-    if (DRAW && wid == 0 && lane == 0 && hi > lo) atomicAdd(&rsc.words[1], hi - lo);
+    if (NT == 2 && DRAW && wid == 0 && lane == 0 && hi > lo) atomicAdd(&rsc.words[1], hi - lo);
     double* slot = ws + (int64_t)wid * slot_elems;
     const uint64_t sweep = *sweep_ptr;
     for (int i = lo + wid; i < hi; i += n_slots) {
         const DrawTask t = rsc.list[i];
         const ChainInfo& c = chains[t.chain];
-        if (c.L > 32) {
-            if (lane == 0) set_status(status, FH_ERR_NONFINITE, t.chain);
+        if (NT == 2 ? c.L > 32 : c.L != 16 * NT) {  // another launch's chain, or none's
+            if (NT == 2 && !fp64_circulant(c.L) && lane == 0)
+                set_status(status, FH_ERR_NONFINITE, t.chain);
             continue;
         }
         int start, len;
         block_of(c, sweep, t.block, &start, &len);
-        const int L = c.L, N = c.N, L_tau = c.L_tau;
+        // the 48 x 48 and 64 x 64 tilings take L as a constant (their site offsets fold into
+        // the stores' immediates instead of taking registers)
+        const int L = NT == 2 ? c.L : 16 * NT, N = NT == 2 ? c.N : 256 * NT * NT, L_tau = c.L_tau;
         const int spin = t.p >= c.n_up ? 1 : 0;
         const double coef = spin ? c.coef_dn : c.coef_up;
         const double* shift = wshift + spin * total_slices + c.slice_off;
@@ -1353,27 +1358,40 @@ __global__ __launch_bounds__(kThreads, 2) void k_rescue(
         for (int q = 0; q < 16; ++q) Cb[q] = cmat64[((int64_t)t.chain * 16 + q) * 64 + lane];
         float* frows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
         const double* Wl0 = W64 + spin * aux_elems + c.aux_off;
-        auto wtab = [&](int l, double (&w)[16]) {
+        // the site of the lane's element (q, r) of the tiling; padded positions (L < 32) read
+        // W at site 0, times an exact zero, and store nothing
+        auto site = [&](int q, int r) {
+            if constexpr (NT == 2) {
+                const int x = t64_x(q, lane), y = t64_y(q, r, lane);
+                return (x < L && y < L) ? y * L + x : -1;
+            } else {
+                return tb_y<NT>(q, r, lane) * L + tb_x<NT>(q, lane);
+            }
+        };
+        auto wtab = [&](int l, auto& w) {
             const double* Wl = Wl0 + (int64_t)l * N;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < (NT == 2 ? 4 : NT * NT); ++q)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {  // a padded position reads site 0, times 0
-                    const int x = t64_x(q, lane), y = t64_y(q, r, lane);
-                    w[4 * q + r] = Wl[(x < L && y < L) ? y * L + x : 0];
-                }
+                for (int r = 0; r < 4; ++r) w[4 * q + r] = Wl[max(site(q, r), 0)];
         };
         auto put = [&](int j, int q, int r, double v) {
-            const int64_t o = (int64_t)(j - 1) * N + t64_y(q, r, lane) * L + t64_x(q, lane);
+            const int64_t o = (int64_t)(j - 1) * N + site(q, r);
             if (DRAW)
                 slot[o] = v;                         // the rows the draws below read
             else
                 frows[o] = (float)(v * c.row_mass);  // the plan's rows (FP32 scaling)
         };
         bool ok = true;
-        const double lz = dmfma_block_forward(Cb, L, L_tau, start, len, a, e,
-                                              coef * (double)ax[(int64_t)start * N + a], shift,
-                                              wtab, put, &ok);
+        const double la0 = coef * (double)ax[(int64_t)start * N + a];
+        double lz;
+        if constexpr (NT == 2) {
+            lz = dmfma_block_forward(Cb, L, L_tau, start, len, a, e, la0, shift, wtab, put, &ok);
+        } else {
+            double la_end;
+            lz = dmfma_big_block_forward_end<NT>(Cb, L_tau, start, len, a, e, la0, shift, wtab,
+                                                 put, [](int, int, double) {}, &la_end, &ok);
+        }
         if (lane == 0) {
             if (!ok) set_status(status, FH_ERR_NONFINITE, t.chain);
             blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = lz;
@@ -1394,7 +1412,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_rescue(
 // order (k_rescue_held admitted only chains whose recursions fit the slots): the rows, then the
 // end tile C f~ C. The block's log Z goes to blk_logz, log Z without the end weight to blk_la
 // (shared-filter chains), and the slot to rep_slot.
-__global__ __launch_bounds__(kThreads, 2) void k_rescue_share_fwd(
+// NT as in k_rescue: one launch per tiling, each taking its own chains' representatives.
+template <int NT>
+__global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_rescue_share_fwd(
     const ChainInfo* __restrict__ chains, const double* __restrict__ cmat64,
     const float* __restrict__ aux, const double* __restrict__ wshift, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
@@ -1409,6 +1429,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_rescue_share_fwd(
     for (int i = wid; i < hi; i += n_waves) {
         const DrawTask t = rsc.list[i];
         const ChainInfo& c = chains[t.chain];
+        if (NT == 2 ? c.L > 32 : c.L != 16 * NT) continue;  // another launch's chain
         if (c.dedup && row_owner(rsc, c, t.p, t.block) != t.p) continue;  // shares these rows
         int slot_id = 0;
         if (lane == 0) slot_id = atomicAdd(&rsc.words[4], 1);
@@ -1416,7 +1437,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_rescue_share_fwd(
         double* slot = ws + (int64_t)slot_id * slot_elems;
         int start, len;
         block_of(c, sweep, t.block, &start, &len);
-        const int L = c.L, N = c.N, L_tau = c.L_tau;
+        const int L = NT == 2 ? c.L : 16 * NT, N = NT == 2 ? c.N : 256 * NT * NT, L_tau = c.L_tau;
         const int spin = t.p >= c.n_up ? 1 : 0;
         const double coef = spin ? c.coef_dn : c.coef_up;
         const double* shift = wshift + spin * total_slices + c.slice_off;
@@ -1429,28 +1450,38 @@ __global__ __launch_bounds__(kThreads, 2) void k_rescue_share_fwd(
 #pragma unroll
         for (int q = 0; q < 16; ++q) Cb[q] = cmat64[((int64_t)t.chain * 16 + q) * 64 + lane];
         const double* Wl0 = W64 + spin * aux_elems + c.aux_off;
-        auto wtab = [&](int l, double (&w)[16]) {
+        // the site of the lane's element (q, r); padded positions (L < 32) read W at site 0,
+        // times an exact zero, and store nothing
+        auto site = [&](int q, int r) {
+            if constexpr (NT == 2) {
+                const int x = t64_x(q, lane), y = t64_y(q, r, lane);
+                return (x < L && y < L) ? y * L + x : -1;
+            } else {
+                return tb_y<NT>(q, r, lane) * L + tb_x<NT>(q, lane);
+            }
+        };
+        auto wtab = [&](int l, auto& w) {
             const double* Wl = Wl0 + (int64_t)l * N;
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < (NT == 2 ? 4 : NT * NT); ++q)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {  // a padded position reads site 0, times 0
-                    const int x = t64_x(q, lane), y = t64_y(q, r, lane);
-                    w[4 * q + r] = Wl[(x < L && y < L) ? y * L + x : 0];
-                }
+                for (int r = 0; r < 4; ++r) w[4 * q + r] = Wl[max(site(q, r), 0)];
         };
         auto put = [&](int j, int q, int r, double v) {
-            slot[(int64_t)(j - 1) * N + t64_y(q, r, lane) * L + t64_x(q, lane)] = v;
+            slot[(int64_t)(j - 1) * N + site(q, r)] = v;
         };
         double* end = slot + (int64_t)(c.B - 1) * N;  // after the longest block's rows
-        auto put_end = [&](int q, int r, double v) {
-            end[t64_y(q, r, lane) * L + t64_x(q, lane)] = v;
-        };
+        auto put_end = [&](int q, int r, double v) { end[site(q, r)] = v; };
         bool ok = true;
         double la_end = 0.0;
-        const double lz = dmfma_block_forward_end(
-            Cb, L, L_tau, start, len, a, e, coef * (double)aux[c.aux_off + (int64_t)start * N + a],
-            shift, wtab, put, put_end, &la_end, &ok);
+        const double la0 = coef * (double)aux[c.aux_off + (int64_t)start * N + a];
+        double lz;
+        if constexpr (NT == 2)
+            lz = dmfma_block_forward_end(Cb, L, L_tau, start, len, a, e, la0, shift, wtab, put,
+                                         put_end, &la_end, &ok);
+        else
+            lz = dmfma_big_block_forward_end<NT>(Cb, L_tau, start, len, a, e, la0, shift, wtab,
+                                                 put, put_end, &la_end, &ok);
         if (lane == 0) {
             const int64_t bi = c.blk_off + (int64_t)t.p * c.nb + t.block;
             if (!ok) set_status(status, FH_ERR_NONFINITE, t.chain);
@@ -1509,13 +1540,18 @@ __global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict_
                                                     const int32_t* __restrict__ paths,
                                                     const uint64_t* __restrict__ sweep_ptr,
                                                     int32_t* __restrict__ rep, const Rescue rsc) {
-    __shared__ int32_t first[1024];  // dedup chains are 32 x 32
+    __shared__ int32_t first[kDedupMaxN];
     __shared__ int32_t n_rep;
     const DrawTask t = tasks[blockIdx.x];  // t.p holds the spin
     const ChainInfo& c = chains[t.chain];
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
     const int p0 = t.p ? c.n_up : 0, p1 = t.p ? c.np : c.n_up;
+    if (c.dedup == 2 && !rescue_held(rsc, t.chain)) {  // shares only in phase A: identity
+        for (int q = p0 + threadIdx.x; q < p1; q += blockDim.x)
+            rep[c.blk_off + (int64_t)q * c.nb + t.block] = q;
+        return;
+    }
     for (int i = threadIdx.x; i < c.N; i += blockDim.x) first[i] = 0x7fffffff;
     if (threadIdx.x == 0) n_rep = 0;
     __syncthreads();
@@ -1552,7 +1588,7 @@ __global__ void k_member_logz(const ChainInfo* __restrict__ chains, int n_chains
          i += (int64_t)gridDim.x * blockDim.x) {
         const int ci = find_chain(n_chains, i, [&](int k) { return chains[k].blk_off; });
         const ChainInfo& c = chains[ci];
-        if (!c.dedup || rescue_held(rsc, ci)) continue;
+        if (c.dedup != 1 || rescue_held(rsc, ci)) continue;
         const int64_t local = i - c.blk_off;
         const int p = (int)(local / c.nb), b = (int)(local % c.nb);
         const int rp = rsc.rep[i];
@@ -1590,7 +1626,8 @@ __global__ void k_rescue_reset(const Rescue rsc, int64_t n_flags) {
 }
 
 // After k_rescue_reset and k_dedup, before a sweep's FP32 forward pass, one workgroup: every
-// block of each chain held on the FP64 re-filter (L <= 32) is queued, in chain order, as phase A,
+// block of each chain held on the FP64 re-filter (fp64_circulant) is queued, in chain order, as
+// phase A,
 // and the chain is marked, while the chains' forward recursions (their representatives) fit the
 // n_slots slots; the FP32 kernels skip held chains and phase A re-filters them beside the FP32
 // passes (a held chain left out is queued whole after the forward pass, for phase 2). The queue
@@ -1601,7 +1638,7 @@ __global__ __launch_bounds__(kThreads) void k_rescue_held(const ChainInfo* __res
     int off = 0, slots = 0;
     for (int ci = 0; ci < rsc.n_chains; ++ci) {
         const ChainInfo& c = chains[ci];
-        if (c.L > 32 || !rescue_held(rsc, ci)) continue;
+        if (!fp64_circulant(c.L) || !rescue_held(rsc, ci)) continue;
         const int nblk = c.np * c.nb;
         const int nrec = shared && c.dedup ? rsc.words[kRescueChain + 3 * rsc.n_chains + ci] : nblk;
         if (slots + nrec > n_slots) continue;
@@ -2533,29 +2570,42 @@ hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, 
                        p->aux_elems, p->total_slices, rescue_args(p), phase);
     const unsigned blocks = (unsigned)(p->n_rescue_slots / kWaves);
     if (draw && phase == 1) {  // representatives into their slots, then every block's draws
-        hipLaunchKernelGGL(k_rescue_share_fwd, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           p->d.cmat64, (const float*)aux, p->d.wshift, p->total_slices, paths,
-                           p->d.perm, p->d.blk_logz, p->d.blk_la, p->d.sweep, p->d.status,
-                           rescue_args(p), p->d.rep_slot, p->d.rescue_ws, p->rescue_slot_elems,
-                           p->n_rescue_slots, p->d.rescue_w, p->aux_elems);
+        auto fwd = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                               p->d.cmat64, (const float*)aux, p->d.wshift, p->total_slices,
+                               paths, p->d.perm, p->d.blk_logz, p->d.blk_la, p->d.sweep,
+                               p->d.status, rescue_args(p), p->d.rep_slot, p->d.rescue_ws,
+                               p->rescue_slot_elems, p->n_rescue_slots, p->d.rescue_w,
+                               p->aux_elems);
+        };
+        fwd(k_rescue_share_fwd<2>);
+        if (p->rescue_l64) fwd(k_rescue_share_fwd<4>);
+        if (p->rescue_l48) fwd(k_rescue_share_fwd<3>);
         hipLaunchKernelGGL(k_rescue_share_draw, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.tables, paths, p->d.perm, p->d.blk_logz, p->d.blk_la,
                            p->d.sweep, p->d.status, rescue_args(p), p->d.rep_slot,
                            p->d.rescue_ws, p->rescue_slot_elems, p->n_rescue_slots);
-    } else if (draw)
-        hipLaunchKernelGGL(k_rescue<true>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           p->d.tables, p->d.cmat64, (const float*)aux, p->d.wshift,
-                           p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
-                           p->d.sweep, p->d.status, rescue_args(p), p->d.rescue_ws,
-                           p->rescue_slot_elems, p->n_rescue_slots, p->d.rescue_w, p->aux_elems,
-                           phase);
-    else
-        hipLaunchKernelGGL(k_rescue<false>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           p->d.tables, p->d.cmat64, (const float*)aux, p->d.wshift,
-                           p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
-                           p->d.sweep, p->d.status, rescue_args(p), p->d.rescue_ws,
-                           p->rescue_slot_elems, p->n_rescue_slots, p->d.rescue_w, p->aux_elems,
-                           phase);
+    } else {
+        // one launch per tiling: L <= 32, then the 64 x 64 and 48 x 48 chains, in stream order,
+        // so the launches take the same slots in turn
+        auto run = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                               p->d.tables, p->d.cmat64, (const float*)aux, p->d.wshift,
+                               p->total_slices, paths, p->d.perm, (float*)p->d.filt,
+                               p->d.blk_logz, p->d.sweep, p->d.status, rescue_args(p),
+                               p->d.rescue_ws, p->rescue_slot_elems, p->n_rescue_slots,
+                               p->d.rescue_w, p->aux_elems, phase);
+        };
+        if (draw) {
+            run(k_rescue<true, 2>);
+            if (p->rescue_l64) run(k_rescue<true, 4>);
+            if (p->rescue_l48) run(k_rescue<true, 3>);
+        } else {
+            run(k_rescue<false, 2>);
+            if (p->rescue_l64) run(k_rescue<false, 4>);
+            if (p->rescue_l48) run(k_rescue<false, 3>);
+        }
+    }
     return hipGetLastError();
 }
 

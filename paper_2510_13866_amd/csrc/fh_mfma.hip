@@ -332,6 +332,64 @@ __global__ __launch_bounds__(kThreads) void k_forward_dmfma(
     }
 }
 
+// k_forward_dmfma for the chains with L = 16 NT, NT = 3 or 4 (48 x 48, 64 x 64): the same
+// recursion on NT x NT tiles of 16 x 16 with the block-circulant operands (fh_dmfma.h). The
+// filter and its product take 2 NT^2 accumulator tiles (256 registers at NT = 4), so one
+// wavefront runs per SIMD.
+template <int NT>
+__global__ __launch_bounds__(kThreads, 1) void k_forward_dmfma_big(
+    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
+    const double* __restrict__ cmat64, const double* __restrict__ aux, const double* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, double* __restrict__ filt,
+    double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status) {
+    constexpr int L = 16 * NT, N = L * L, NQ = NT * NT;
+    const int lane = threadIdx.x & 63;
+    const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
+    if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
+    const DrawTask t = tasks[task];
+    const ChainInfo& c = chains[t.chain];
+    int start, len;
+    block_of(c, *sweep_ptr, t.block, &start, &len);
+    const int L_tau = c.L_tau;
+    const int spin = t.p >= c.n_up ? 1 : 0;
+    const double* Wsp = W + spin * aux_elems + c.aux_off;
+    const double* shift = wshift + spin * total_slices + c.slice_off;
+    const double coef = spin ? c.coef_dn : c.coef_up;
+    const int32_t* pc = paths + c.path_off;
+    int a = pc[(int64_t)start * c.np + t.p];
+    const int qe = start + len >= L_tau ? perm[c.part_off + t.p] : t.p;  // reconnection
+    int e = pc[(int64_t)((start + len) % L_tau) * c.np + qe];
+    if (a < 0 || a >= N || e < 0 || e >= N) {
+        if (lane == 0) set_status(status, FH_ERR_BAD_PATH, t.chain);
+        a = (a < 0 || a >= N) ? 0 : a;
+        e = (e < 0 || e >= N) ? 0 : e;
+    }
+    double Cb[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) Cb[q] = cmat64[((int64_t)t.chain * 16 + q) * 64 + lane];
+    const double la = coef * aux[c.aux_off + (int64_t)start * N + a];
+    double* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+    auto wtab = [&](int l, double (&w)[4 * NQ]) {
+        const double* Wl = Wsp + (int64_t)l * N;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w[4 * q + r] = Wl[tb_y<NT>(q, r, lane) * L + tb_x<NT>(q, lane)];
+    };
+    auto put = [&](int j, int q, int r, double v) {
+        rows[(int64_t)(j - 1) * N + tb_y<NT>(q, r, lane) * L + tb_x<NT>(q, lane)] = v;
+    };
+    bool ok = true;
+    double la_end;
+    const double lz = dmfma_big_block_forward_end<NT>(
+        Cb, L_tau, start, len, a, e, la, shift, wtab, put, [](int, int, double) {}, &la_end, &ok);
+    if (lane == 0) {
+        if (!ok) set_status(status, FH_ERR_NONFINITE, t.chain);
+        blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = lz;
+    }
+}
+
 // Two worldlines of the same (chain, spin, block) per wavefront: the W slice is shared and the
 // two GEMM chains are independent, so one worldline's bf16 splitting, normalisation and stores
 // overlap the other's matrix-core work. Same arithmetic as k_forward_mfma, step for step.
@@ -364,6 +422,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
     const int L = LFIX ? LFIX : c.L, N = LFIX ? LFIX * LFIX : c.N, L_tau = c.L_tau;
+    // a chain with few representatives (this pass's count from k_dedup) keeps its rows in the
+    // cache for the members that read them next; otherwise the rows stream past it
+    const int n_rep = c.dedup ? rsc.words[kRescueChain + 3 * rsc.n_chains + t.chain] : 0;
+    const bool cached = n_rep > 0 && (int64_t)n_rep * (c.B - 1) * N * 4 <= kCachedRowBytes;
     const bool has_b = ra && rb;
     const int q0 = ra ? t.p_a : t.p_b;
     const int pp[2] = {q0, has_b ? t.p_b : q0};  // a lone worldline is shadowed, not stored
@@ -474,8 +536,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
             F0[v] *= k0;
             F1[v] *= k1;
             if (inside(v)) {
-                __builtin_nontemporal_store(F0[v], row0 + vrow(v) * L);
-                __builtin_nontemporal_store(F1[v], row1 + vrow(v) * L);
+                if (cached) {
+                    row0[vrow(v) * L] = F0[v];
+                    row1[vrow(v) * L] = F1[v];
+                } else {
+                    __builtin_nontemporal_store(F0[v], row0 + vrow(v) * L);
+                    __builtin_nontemporal_store(F1[v], row1 + vrow(v) * L);
+                }
             }
         }
     };
@@ -581,6 +648,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
     const DrawTask t = tasks[task];
+    if (rescue_held(rsc, t.chain)) return;  // re-filtered whole in FP64 this pass
     const ChainInfo& c = chains[t.chain];
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
@@ -1481,12 +1549,27 @@ __global__ __launch_bounds__(kThreads) void k_gpart_reduce(const ChainInfo* __re
 }  // namespace
 
 hipError_t launch_forward_dmfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
-    if (p->n_fwdd_tasks == 0) return hipSuccess;
-    const unsigned blocks = (unsigned)((p->n_fwdd_tasks + kWaves - 1) / kWaves);
-    hipLaunchKernelGGL(k_forward_dmfma, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                       p->d.fwdd_tasks, p->n_fwdd_tasks, p->d.cmat64, (const double*)aux,
-                       (const double*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices, paths,
-                       p->d.perm, (double*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status);
+    // fwdd_tasks: the L <= 32 tasks, then those of the 64 x 64 chains, then of the 48 x 48 ones
+    const int32_t n2 = p->n_fwdd_tasks, n4 = p->n_fwdd4_tasks, n3 = p->n_fwdd3_tasks;
+    auto blocks = [](int32_t n) { return (unsigned)((n + kWaves - 1) / kWaves); };
+    if (n2 > 0)
+        hipLaunchKernelGGL(k_forward_dmfma, dim3(blocks(n2)), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.fwdd_tasks, n2, p->d.cmat64, (const double*)aux,
+                           (const double*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
+                           paths, p->d.perm, (double*)p->d.filt, p->d.blk_logz, p->d.sweep,
+                           p->d.status);
+    if (n4 > 0)
+        hipLaunchKernelGGL(k_forward_dmfma_big<4>, dim3(blocks(n4)), dim3(kThreads), 0, s,
+                           p->d.chains, p->d.fwdd_tasks + n2, n4, p->d.cmat64,
+                           (const double*)aux, (const double*)p->d.W, p->d.wshift, p->aux_elems,
+                           p->total_slices, paths, p->d.perm, (double*)p->d.filt, p->d.blk_logz,
+                           p->d.sweep, p->d.status);
+    if (n3 > 0)
+        hipLaunchKernelGGL(k_forward_dmfma_big<3>, dim3(blocks(n3)), dim3(kThreads), 0, s,
+                           p->d.chains, p->d.fwdd_tasks + n2 + n4, n3, p->d.cmat64,
+                           (const double*)aux, (const double*)p->d.W, p->d.wshift, p->aux_elems,
+                           p->total_slices, paths, p->d.perm, (double*)p->d.filt, p->d.blk_logz,
+                           p->d.sweep, p->d.status);
     return hipGetLastError();
 }
 

@@ -1420,11 +1420,12 @@ def oracle_block_draws(d, aux, paths, s, p, block):
     return slices, pos[0, 1:length], marg[0, 1:length]
 
 
-def check_fp32_state(fhmc, S, descs, aux, paths, s, rng):
+def check_fp32_state(fhmc, S, descs, aux, paths, s, rng, prec="mfma3"):
     """Forward and backward of sweep s on one state of an FP32 plan, against the oracle: log Z and
     filter rows of sampled worldlines (the queued ones among them), and the draws of sampled
     blocks the FP64 re-filter redrew (bit-exact up to certified near-ties). Returns the number
-    of blocks queued."""
+    of blocks queued. The re-filtered blocks are held to the split-bf16 path's 1e-5; the FP32
+    blocks of an FFT plan (prec "fp32") to FFT32_BOUND, with the FFT's log Z allowance."""
     A, P = S.pack_aux(aux), S.pack_paths(paths)
     lz = S.unpack_particles(S.forward_filter(A, P, s))
     assert S.status() == (0, -1)
@@ -1435,9 +1436,10 @@ def check_fp32_state(fhmc, S, descs, aux, paths, s, rng):
                         | set(qp[:: max(1, len(qp) // 12)][:12]))
         ax = aux[c].astype(np.float64)
         with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
-            ref_lz, ref_rows = oracle_forward(d, ax, paths[c], s, particles=np.array(sample))
+            ref_lz, ref_rows, tail = oracle_forward(d, ax, paths[c], s, particles=np.array(sample),
+                                                    with_tail=True)
         err = np.abs(lz[c][sample] - ref_lz)
-        tol = logz_tol("mfma3", ref_lz, 0.0, d.L_tau)
+        tol = logz_tol(prec, ref_lz, tail, d.L_tau)
         assert np.all(err <= tol), (s, c, err.max(), tol.min())
         qset = {(p, b) for (cc, p, b) in queued if cc == c}
         worst = {True: (0.0, None), False: (0.0, None)}
@@ -1452,7 +1454,8 @@ def check_fp32_state(fhmc, S, descs, aux, paths, s, rng):
         say("  sweep", s, "chain", c, ": filter error, re-filtered blocks", worst[True],
             ", FP32 blocks", worst[False])
         assert worst[True][0] <= FILTER_TOL["mfma3"], (s, c, worst)
-        assert worst[False][0] <= FILTER_TOL["mfma3"], (s, c, worst)
+        assert worst[False][0] <= (FILTER_TOL["mfma3"] if prec == "mfma3" else FFT32_BOUND), \
+            (s, c, worst)
     S.backward_sample(P, s)
     assert S.status() == (0, -1)
     last_all, _, queued, _ = fhmc.fh_debug_rescue(S.plan, cap=1 << 20)
@@ -1508,6 +1511,50 @@ def test_fp32_chain_through_collapse(lib):
     say("  chains re-filtered whole per sweep:", whole)
     say("  largest same-spin occupancy after 20 sweeps:", occ)
     assert sum(redrawn) > 0      # the chains passed through out-of-range states
+    assert checked > 0           # and such a state was compared with the oracle
+    S.close()
+
+
+# the lattices above 32 that the FP64 re-filter takes on 16 x 16 tiles: 64 x 64 on the split-bf16
+# plan, 48 x 48 on the FP32 FFT plan (the only FP32 path at L = 48); and the states compared
+# with the oracle: from the 64 x 64 chain's third sweep on, its clustered fields overflow the
+# oracle's plain FP64 exp(a sigma)
+BIG_COLLAPSE = {
+    "l64_mfma3": ("mfma3", synth.half_filled(64, 40, synth.HS_GAUSS, 6.0, 0.05, seed=1), (1, 2)),
+    "l48_fp32": ("fp32", synth.half_filled(48, 40, synth.HS_GAUSS, 6.0, 0.05, seed=2), (1, 2, 3))}
+
+
+@pytest.mark.parametrize("case", sorted(BIG_COLLAPSE))
+def test_big_lattice_chain_through_collapse(lib, case):
+    """Eight unrestored sweeps of a 64 x 64 (split-bf16 plan) or 48 x 48 (FP32 FFT plan) Gaussian
+    chain, captured in a graph, through states whose filters leave FP32's range: the FP64
+    re-filter takes these lattices on 16 x 16 tiles of the FP64 matrix cores, so the status
+    stays clean after every sweep, and the queued blocks match the oracle (log Z, filters,
+    draws) on the states before the first sweeps."""
+    fhmc, sampler = lib
+    prec, d, checks = BIG_COLLAPSE[case]
+    descs = [d]
+    say("big lattice collapse", case)
+    S = sampler.Sampler(descs, PRECS[prec], fhmc.FH_FLAG_GRAPH)
+    aux = [synth.initial_aux(d).astype(np.float32)]
+    paths = [synth.initial_paths(d)]
+    A, P = S.pack_aux(aux), S.pack_paths(paths)
+    rng = np.random.default_rng(11)
+    redrawn, checked = [], 0
+    for s in range(8):
+        if s in checks:
+            Sc = sampler.Sampler(descs, PRECS[prec])
+            ax = S.unpack_aux(A)
+            say("  sweep", s, ": largest |field|", float(np.abs(ax[0]).max()))
+            checked += check_fp32_state(fhmc, Sc, descs, ax, S.unpack_paths(P), s, rng, prec) > 0
+            Sc.close()
+        S.sweep(A, P, s, 1)
+        assert S.status() == (0, -1), s
+        redrawn.append(fhmc.fh_debug_rescue(S.plan)[1])
+        say("  after sweep", s, ": largest a |field|",
+            float(np.abs(S.unpack_aux(A)[0]).max()) * np.sqrt(abs(d.U) * d.dtau))
+    say("  blocks redrawn in FP64 per sweep:", redrawn)
+    assert sum(redrawn) > 0      # the chain passed through out-of-range states
     assert checked > 0           # and such a state was compared with the oracle
     S.close()
 
@@ -1621,11 +1668,12 @@ def test_u0_fermion_energy_from_device_gradients(lib, prec, L):
     S.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp64fft", "fp32"])
 def test_largest_lattice_parity(lib, prec):
-    """L = 64 (N = 4096, the largest lattice): FFT forward against the oracle (log Z, filters)
-    and the windowed backward draws against the full-row kernel for N > 1024 and, in FP64,
-    against the oracle's draw rule."""
+    """L = 64 (N = 4096, the largest lattice) and L = 48: the forward (FP64 plans: the FP64
+    circulant on 16 x 16 tiles, or the FP64 FFT; FP32 plan: the FP32 FFT) against the oracle
+    (log Z, filters), and the windowed backward draws against the full-row kernel for N > 1024
+    and, in FP64, against the oracle's draw rule."""
     fhmc, sampler = lib
     descs = [synth.ChainDesc(L=64, L_tau=6, n_up=3, n_dn=2, hs_kind=synth.HS_GAUSS, block_len=0,
                              t=1.0, U=4.0, dtau=0.05, seed=301),
@@ -1633,8 +1681,8 @@ def test_largest_lattice_parity(lib, prec):
                              t=1.0, U=4.0, dtau=0.05, seed=302)]
     say("largest lattice parity", prec)
     aux, paths = mixed_state(descs, seed=311)
-    Sw = sampler.Sampler(descs, PRECS[prec])
-    Sf = sampler.Sampler(descs, PRECS[prec], fhmc.FH_FLAG_FULL_ROW_DRAW)
+    Sw = sampler.Sampler(descs, PRECS[prec], plan_flags(fhmc, prec))
+    Sf = sampler.Sampler(descs, PRECS[prec], plan_flags(fhmc, prec, fhmc.FH_FLAG_FULL_ROW_DRAW))
     Aw, Pw = Sw.pack_aux(aux), Sw.pack_paths(paths)
     Af, Pf = Sf.pack_aux(aux), Sf.pack_paths(paths)
     s = 1
@@ -1654,7 +1702,7 @@ def test_largest_lattice_parity(lib, prec):
     gw, gf = Sw.unpack_paths(Pw), Sf.unpack_paths(Pf)
     for c, d in enumerate(descs):
         assert np.array_equal(gw[c], gf[c]), c
-        if prec == "fp64":
+        if prec.startswith("fp64"):
             Gm = lattice.transfer_matrix(d.L, d.t, d.dtau)
             W_up, W_dn = hs.potentials(aux[c], d.hs_kind, d.U, d.dtau)
             ref = paths[c].astype(np.int64).copy()
@@ -1829,9 +1877,14 @@ def test_mfma_circulant_at_l64_parity(lib):
 def test_fp64_circulant_resolves_deep_filter_tails(lib):
     """Block ends placed anywhere on the lattice sit deep in the filter's tail, where an FFT
     convolution (accurate to ~eps * max per site) cannot resolve them. The FP64 circulant keeps
-    every product positive, so its log Z matches the oracle with no tail allowance at all."""
+    every product positive, so its log Z matches the oracle with no tail allowance at all, on
+    the padded 32 x 32 tile (L <= 32) and on the 16 x 16 tilings of L = 48 and 64."""
     fhmc, sampler = lib
-    descs = [d for d in MIXED if d.L >= 6]
+    descs = [d for d in MIXED if d.L >= 6] + [
+        synth.ChainDesc(L=64, L_tau=12, n_up=3, n_dn=2, hs_kind=synth.HS_GAUSS, block_len=5,
+                        t=1.0, U=4.0, dtau=0.05, seed=421),
+        synth.ChainDesc(L=48, L_tau=10, n_up=2, n_dn=3, hs_kind=synth.HS_HIRSCH, block_len=0,
+                        t=1.0, U=4.0, dtau=0.05, seed=422)]
     say("fp64 circulant deep tails")
     S = sampler.Sampler(descs, fhmc.FH_FP64)
     aux = [synth.initial_aux(d, rng_seed=400 + i) for i, d in enumerate(descs)]
