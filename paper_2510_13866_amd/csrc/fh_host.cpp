@@ -556,7 +556,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.perm_inv, sizeof(int32_t) * (size_t)part);
     if (e == hipSuccess) e = dalloc(&dv.sign, sizeof(int32_t) * (size_t)n_chains);
     if (e == hipSuccess && p->n_rescue_slots > 0) {
-        const size_t words = kRescueChain + 4 * (size_t)n_chains + (size_t)blk;
+        const size_t words = kRescueChain + kRescuePerChain * (size_t)n_chains + (size_t)blk;
         e = dalloc(&dv.rescue, sizeof(int32_t) * words);
         if (e == hipSuccess) e = hipMemset(dv.rescue, 0, sizeof(int32_t) * words);
         if (e == hipSuccess) e = dalloc(&dv.rescue_list, sizeof(DrawTask) * draw.size());

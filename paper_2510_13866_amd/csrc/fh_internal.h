@@ -127,13 +127,15 @@ struct GroupTask {
 // kRescueHold forward passes, which skip the chain's FP32 work: on the way to a clustered state
 // many blocks meet a floor and some FP32 blocks drift without meeting one (a hop whose product
 // underflows in one slice can move log Z by 16 nats), while the blocks of a settled chain meet a
-// floor all together or not at all. Every (kRescueHold + 1)-th pass of a held chain runs FP32
-// again to see whether it still needs FP64.
+// floor all together or not at all. When its hold has run out, a chain runs FP32 again to see
+// whether it still needs FP64; each such retry that fails doubles the next hold, up to
+// kRescueHoldMax passes, and a pass that needs no FP64 resets it to kRescueHold (k_rescue_reset).
 constexpr int kWScaleLog2 = 100;
 constexpr int kRowExp = 20;
 constexpr float kRangeFloor = 0x1p-90f;
 constexpr double kRangeFloorD = 0x1p-90;
 constexpr int kRescueHold = 4;
+constexpr int kRescueHoldMax = 64;
 // Size of the static scratch array of fh_measure_noalloc: 2^22 doubles (32 MiB) per GPU.
 constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // Rescue state words: [0] blocks queued in this pass, [1] blocks redrawn since the last read by
@@ -142,15 +144,21 @@ constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // passes), [4] slots taken by phase A, then per chain: blocks queued by the kernels in this pass
 // (kRescueChain + c), forward passes left on FP64 (kRescueChain + n_chains + c), 1 if the chain
 // is in phase A (kRescueChain + 2 n_chains + c), the forward recursions its blocks need in this
-// pass (kRescueChain + 3 n_chains + c: the representatives of the shared filters), then one
-// flag per (chain, particle, block) at kRescueChain + 4 n_chains + blk_off + p nb + b (the
-// `flags` pointer passed to the kernels).
+// pass (kRescueChain + 3 n_chains + c: the representatives of the shared filters), the hold at
+// the start of the previous pass (kRescueChain + 4 n_chains + c) and the length of the next
+// hold (kRescueChain + 5 n_chains + c), then one flag per (chain, particle, block) at
+// kRescueChain + kRescuePerChain n_chains + blk_off + p nb + b (the `flags` pointer passed to
+// the kernels).
 constexpr int kRescueChain = 8;
+constexpr int kRescuePerChain = 6;
 // Slots of the FP64 re-filter (two wavefronts per SIMD of 256 CUs), (B - 1) N doubles of rows
 // plus the end tile [N]. Phase 0 and 2 give each wavefront its own slot; phase A gives each
 // representative one (k_rescue_held admits held chains while their representatives fit).
 constexpr int kRescueMaxSlots = 2048;
 constexpr int kDedupMaxN = 4096;  // sites of the largest chain with shared filters (64 x 64)
+// Phase A's draws need no slot of their own: k_rescue_share_draw keeps this many wavefronts per
+// SIMD (its register budget) and is launched with twice the slot count of them.
+constexpr int kShareDrawWaves = 4;
 // Shared forward filters: a chain whose representatives' rows (this pass) take at most this many
 // bytes writes them with cached stores, the rest with nontemporal ones.
 constexpr int64_t kCachedRowBytes = 16ll << 20;
@@ -161,7 +169,7 @@ constexpr int64_t kCachedRowBytes = 16ll << 20;
 // draws read; null where no chain shares, and on FP64 plans).
 struct Rescue {
     int32_t* words;   // null for FP64 plans
-    int32_t* flags;   // words + kRescueChain + 4 n_chains
+    int32_t* flags;   // words + kRescueChain + kRescuePerChain n_chains
     DrawTask* list;
     int32_t n_chains;
     const int32_t* rep;
@@ -179,8 +187,9 @@ __device__ inline bool rescue_enqueue(const Rescue& r, const ChainInfo& c, int c
     return true;
 }
 // A kernel found block (chain, p, block) out of FP32's range: queue it, count it for its chain
-// and hold the chain on the FP64 re-filter for the next kRescueHold forward passes (a backward
-// pass queues after the chain's blocks were expanded for this one).
+// and hold the chain on the FP64 re-filter for the next kRescueHold forward passes, or longer
+// after failed retries (k_rescue_reset; a backward pass queues after the chain's blocks were
+// expanded for this one).
 __device__ inline void rescue_push(const Rescue& r, const ChainInfo& c, int chain, int p,
                                    int block) {
     if (rescue_enqueue(r, c, chain, p, block)) {
@@ -332,7 +341,7 @@ namespace fh {
 inline Rescue rescue_args(fh_plan p) {
     Rescue r;
     r.words = p->d.rescue;
-    r.flags = p->d.rescue ? p->d.rescue + kRescueChain + 4 * p->n_chains : nullptr;
+    r.flags = p->d.rescue ? p->d.rescue + kRescueChain + kRescuePerChain * p->n_chains : nullptr;
     r.list = p->d.rescue_list;
     r.rep = p->d.rep;
     r.n_chains = p->n_chains;

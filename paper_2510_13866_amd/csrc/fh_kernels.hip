@@ -1256,6 +1256,8 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
 // the FP64 plans' backward kernels, taken on the certified window of half-width win_w, else on
 // the wider one, else on the full row (fh_window.h), so the sites are those of an FP64 plan.
 // Kept out of line: inlined into k_rescue next to the FP64 forward recursion, the compiler fails.
+// CTX tells the callers apart, so that each copy is compiled for its caller's register budget.
+template <int CTX>
 __device__ __attribute__((noinline)) void rescue_draws(const DrawTask& t, const ChainInfo& c,
                                                        const double* g, int32_t* paths,
                                                        const int32_t* perm, uint64_t sweep,
@@ -1400,7 +1402,7 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_rescue(
         // the slot's rows were stored by this wavefront's lanes: make them visible to its loads
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
         // the full-row rule of the FP64 plans' backward kernel, on the slot's rows
-        rescue_draws(t, c, tables + tab_g(c), paths, perm, sweep, status, lane, slot);
+        rescue_draws<0>(t, c, tables + tab_g(c), paths, perm, sweep, status, lane, slot);
         // the next block reuses the slot: its stores must follow these loads
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
     }
@@ -1496,7 +1498,7 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_rescue_share_fwd(
 // representative's slot (its own for a chain without shared filters), with the FP64 plans' rule
 // (rescue_draws); a block that shares rows also takes its log Z from the representative's log Z
 // without the end weight and the end tile at its own end site.
-__global__ __launch_bounds__(kThreads) void k_rescue_share_draw(
+__global__ __launch_bounds__(kThreads, kShareDrawWaves) void k_rescue_share_draw(
     const ChainInfo* __restrict__ chains, const double* __restrict__ tables,
     int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
     double* __restrict__ blk_logz, const double* __restrict__ blk_la,
@@ -1526,7 +1528,7 @@ __global__ __launch_bounds__(kThreads) void k_rescue_share_draw(
             if (!(hv > 0.0)) set_status(status, FH_ERR_NONFINITE, t.chain);
             blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = blk_la[ri] + log(hv);
         }
-        rescue_draws(t, c, tables + tab_g(c), paths, perm, sweep, status, lane, slot);
+        rescue_draws<1>(t, c, tables + tab_g(c), paths, perm, sweep, status, lane, slot);
     }
 }
 
@@ -1617,10 +1619,26 @@ __global__ void k_rescue_reset(const Rescue rsc, int64_t n_flags) {
         rsc.words[3] = 0;
         rsc.words[4] = 0;
     }
-    for (int64_t k = i; k < rsc.n_chains; k += stride) {
+    const int n = rsc.n_chains;
+    for (int64_t k = i; k < n; k += stride) {
         rsc.words[kRescueChain + k] = 0;
-        rsc.words[kRescueChain + 2 * rsc.n_chains + k] = 0;
-        rsc.words[kRescueChain + 3 * rsc.n_chains + k] = 0;
+        rsc.words[kRescueChain + 2 * n + k] = 0;
+        rsc.words[kRescueChain + 3 * n + k] = 0;
+        // the hold: a chain that entered the previous pass in FP32 and left it held failed its
+        // retry (or first met a floor): hold it for the current length, and double that for
+        // the next failure; a pass in FP32 that queued nothing resets the length
+        int hold = rsc.words[kRescueChain + n + k];
+        const int hold0 = rsc.words[kRescueChain + 4 * n + k];
+        int len = max(rsc.words[kRescueChain + 5 * n + k], kRescueHold);
+        if (hold0 == 0 && hold > 0) {
+            hold = len;
+            len = min(2 * len, kRescueHoldMax);
+        } else if (hold0 == 0) {
+            len = kRescueHold;
+        }
+        rsc.words[kRescueChain + n + k] = hold;
+        rsc.words[kRescueChain + 4 * n + k] = hold;
+        rsc.words[kRescueChain + 5 * n + k] = len;
     }
     for (int64_t k = i; k < n_flags; k += stride) rsc.flags[k] = 0;
 }
@@ -1658,7 +1676,7 @@ __global__ __launch_bounds__(kThreads) void k_rescue_held(const ChainInfo* __res
 
 // After the FP32 forward pass, one workgroup per chain: a chain with more than whole_min blocks
 // queued in this pass, or still held from an earlier such pass, has all its blocks queued for the
-// FP64 re-filter; its hold then counts down (kRescueHold passes after the last such pass).
+// FP64 re-filter; its hold then counts down (k_rescue_reset sets its length at the next pass).
 __global__ __launch_bounds__(kThreads) void k_rescue_expand(const ChainInfo* __restrict__ chains,
                                                             const Rescue rsc) {
     const int ci = blockIdx.x;
@@ -2581,10 +2599,12 @@ hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, 
         fwd(k_rescue_share_fwd<2>);
         if (p->rescue_l64) fwd(k_rescue_share_fwd<4>);
         if (p->rescue_l48) fwd(k_rescue_share_fwd<3>);
-        hipLaunchKernelGGL(k_rescue_share_draw, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
-                           p->d.tables, paths, p->d.perm, p->d.blk_logz, p->d.blk_la,
-                           p->d.sweep, p->d.status, rescue_args(p), p->d.rep_slot,
-                           p->d.rescue_ws, p->rescue_slot_elems, p->n_rescue_slots);
+        // the draws take no slot: twice the slot count of wavefronts, four per SIMD
+        const int draw_waves = 2 * p->n_rescue_slots;
+        hipLaunchKernelGGL(k_rescue_share_draw, dim3((unsigned)(draw_waves / kWaves)),
+                           dim3(kThreads), 0, s, p->d.chains, p->d.tables, paths, p->d.perm,
+                           p->d.blk_logz, p->d.blk_la, p->d.sweep, p->d.status, rescue_args(p),
+                           p->d.rep_slot, p->d.rescue_ws, p->rescue_slot_elems, draw_waves);
     } else {
         // one launch per tiling: L <= 32, then the 64 x 64 and 48 x 48 chains, in stream order,
         // so the launches take the same slots in turn
