@@ -195,7 +195,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.draw_tasks, d.group_tasks, d.gpart, d.ckpt, d.rep, d.blk_la, d.endrow, d.dedup_tasks, d.fwd32_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
+                    d.draw_tasks, d.group_tasks, d.gpart, d.ckpt, d.rep, d.blk_la, d.endrow, d.dedup_tasks, d.fwd32_tasks, d.fwd32c_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
                     d.rescue, d.rescue_list, d.rep_slot, d.rescue_ws, d.rescue_w, d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -542,6 +542,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     if (e == hipSuccess) e = dalloc(&dv.draw_tasks, sizeof(DrawTask) * draw.size());
     if (e == hipSuccess) e = dalloc(&dv.group_tasks, sizeof(GroupTask) * groups.size());
     if (e == hipSuccess) e = dalloc(&dv.fwd32_tasks, sizeof(PairTask) * fwd32.size());
+    if (e == hipSuccess && p->end_elems > 0 && !fwd32.empty())  // 32 x 32 chains share filters
+        e = dalloc(&dv.fwd32c_tasks, sizeof(PairTask) * fwd32.size());
     if (e == hipSuccess) e = dalloc(&dv.fwdx_tasks, sizeof(DrawTask) * fwdx.size());
     if (e == hipSuccess) e = dalloc(&dv.fwdp_tasks, sizeof(PackTask) * fwdp.size());
     if (e == hipSuccess) e = dalloc(&dv.cmatp, sizeof(uint16_t) * p->cmatp.size());

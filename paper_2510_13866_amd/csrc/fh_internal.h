@@ -141,7 +141,8 @@ constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // Rescue state words: [0] blocks queued in this pass, [1] blocks redrawn since the last read by
 // fh_debug_rescue, [2] chains re-filtered whole in this pass, [3] length of the queue's phase A
 // (a sweep's held chains, queued before its FP32 forward pass and re-filtered beside the FP32
-// passes), [4] slots taken by phase A, then per chain: blocks queued by the kernels in this pass
+// passes), [4] slots taken by phase A, [5] entries of the dense list of representative pairs
+// (k_dedup), then per chain: blocks queued by the kernels in this pass
 // (kRescueChain + c), forward passes left on FP64 (kRescueChain + n_chains + c), 1 if the chain
 // is in phase A (kRescueChain + 2 n_chains + c), the forward recursions its blocks need in this
 // pass (kRescueChain + 3 n_chains + c: the representatives of the shared filters), the hold at
@@ -238,6 +239,7 @@ struct Device {
     DrawTask* draw_tasks = nullptr;
     GroupTask* group_tasks = nullptr;
     PairTask* fwd32_tasks = nullptr;    // MFMA forward: worldline pairs of L = 32 chains
+    PairTask* fwd32c_tasks = nullptr;   // the dense representative pairs k_dedup lists (as many)
     DrawTask* fwdx_tasks = nullptr;     // MFMA forward: single worldlines of 16 < L < 32 chains
     PackTask* fwdp_tasks = nullptr;
     DrawTask* fwd64_tasks = nullptr;    // MFMA forward: single worldlines of L = 64 chains     // MFMA forward, packed: P = 2 tasks, then P = 4 tasks

@@ -1537,13 +1537,20 @@ __global__ __launch_bounds__(kThreads, kShareDrawWaves) void k_rescue_share_draw
 // slices and its start site, so every worldline of the (spin, block) is mapped to the lowest
 // worldline with the same start site (its representative; itself if it is the lowest); the
 // forward kernel runs the representatives only and the backward kernels read their rows.
+// For dedup = 1 chains not held this pass it also appends the (spin, block)'s representatives,
+// in worldline order and two to a task, to the dense list cpairs (count in words[5]), which the
+// split-bf16 forward then takes from the front: its active wavefronts are the first ones
+// dispatched, spread over the XCDs, instead of sitting at fixed grid positions that map a whole
+// settled batch onto a few compute units.
 __global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict__ chains,
                                                     const DrawTask* __restrict__ tasks,
                                                     const int32_t* __restrict__ paths,
                                                     const uint64_t* __restrict__ sweep_ptr,
-                                                    int32_t* __restrict__ rep, const Rescue rsc) {
+                                                    int32_t* __restrict__ rep, const Rescue rsc,
+                                                    PairTask* __restrict__ cpairs) {
     __shared__ int32_t first[kDedupMaxN];
-    __shared__ int32_t n_rep;
+    __shared__ int32_t rlist[kDedupMaxN];
+    __shared__ int32_t n_rep, c_base;
     const DrawTask t = tasks[blockIdx.x];  // t.p holds the spin
     const ChainInfo& c = chains[t.chain];
     int start, len;
@@ -1572,6 +1579,29 @@ __global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict_
     __syncthreads();
     // the chain's forward recursions in this pass (the FP64 re-filter's phase A sizes by them)
     if (threadIdx.x == 0) atomicAdd(&rsc.words[kRescueChain + 3 * rsc.n_chains + t.chain], n_rep);
+    if (!cpairs || c.dedup != 1 || rescue_held(rsc, t.chain)) return;  // whole workgroup
+    // the representatives in worldline order (first wavefront), then their pairs
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        int cnt = 0;
+        for (int q0 = p0; q0 < p1; q0 += 64) {
+            const int q = q0 + lane;
+            bool is_rep = false;
+            if (q < p1) {
+                const int a = row[q];
+                is_rep = !(a >= 0 && a < c.N) || first[a] == q;
+            }
+            const uint64_t m = __ballot(is_rep);
+            if (is_rep) rlist[cnt + __popcll(m & ((1ull << lane) - 1))] = q;
+            cnt += __popcll(m);
+        }
+        if (lane == 0) c_base = atomicAdd(&rsc.words[5], (cnt + 1) / 2);
+    }
+    __syncthreads();
+    const int npairs = (n_rep + 1) / 2;
+    for (int i = threadIdx.x; i < npairs; i += blockDim.x)
+        cpairs[c_base + i] =
+            PairTask{t.chain, rlist[2 * i], 2 * i + 1 < n_rep ? rlist[2 * i + 1] : -1, t.block};
 }
 
 // After the FP32 forward pass, one thread per (chain, particle, block) of the chains with dedup:
@@ -1618,6 +1648,7 @@ __global__ void k_rescue_reset(const Rescue rsc, int64_t n_flags) {
         rsc.words[2] = 0;
         rsc.words[3] = 0;
         rsc.words[4] = 0;
+        rsc.words[5] = 0;
     }
     const int n = rsc.n_chains;
     for (int64_t k = i; k < n; k += stride) {
@@ -2547,7 +2578,8 @@ hipError_t launch_scale_copy(float* dst, const float* src, int64_t n, float fact
 hipError_t launch_dedup(fh_plan p, const int32_t* paths, hipStream_t s) {
     if (p->n_dedup_tasks == 0 || p->share_off) return hipSuccess;
     hipLaunchKernelGGL(k_dedup, dim3((unsigned)p->n_dedup_tasks), dim3(kThreads), 0, s,
-                       p->d.chains, p->d.dedup_tasks, paths, p->d.sweep, p->d.rep, rescue_args(p));
+                       p->d.chains, p->d.dedup_tasks, paths, p->d.sweep, p->d.rep, rescue_args(p),
+                       p->d.fwd32c_tasks);
     return hipGetLastError();
 }
 

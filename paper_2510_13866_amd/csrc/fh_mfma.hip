@@ -212,10 +212,12 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     // W of the next slice is loaded right after the stores of this one, so that its wait (one
     // step of matrix work later) finds the stores, which may be skipped for padded lanes and so
     // are not counted ahead of time, long retired
-    float wn[16];
-    load_w((start + 1) % L_tau, wn);
+    // two W buffers that swap roles every step (one buffer would make the loop's back edge copy
+    // the loaded slice into it, waiting for the load)
+    float wa[16], wb[16];
+    load_w((start + 1) % L_tau, wa);
     bool low = false;  // the block left FP32's range: queued for the FP64 re-filter
-    auto step = [&](int j) {
+    auto step = [&](int j, const float (&wn)[16], float (&wf)[16]) {
         const int l = (start + j) % L_tau;
         const f32x16 X = circ_step(F, C, neg);
         const f32x16 H = circ_step(X, C, neg);
@@ -244,12 +246,17 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
             if (inside(v)) __builtin_nontemporal_store(F[v], row + vrow(v) * L);
         }
         __builtin_amdgcn_sched_barrier(0);
-        load_w((l + 1) % L_tau, wn);  // the last step fetches a slice it does not use
+        load_w((l + 1) % L_tau, wf);  // the last step fetches a slice it does not use
         __builtin_amdgcn_sched_barrier(0);
     };
     if (len > 1) {
-        step(1);
-        for (int j = 2; j < len; ++j) step(j);
+        step(1, wa, wb);
+        int j = 2;
+        for (; j + 1 < len; j += 2) {
+            step(j, wb, wa);
+            step(j + 1, wa, wb);
+        }
+        if (j < len) step(j, wb, wa);
     }
     la += block_shift_sum(shift, start, len, L_tau, lsc, lane);
     // end weight (C f~ C)(e)
@@ -407,11 +414,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
     double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
     const Rescue rsc, const NegPairs neg, double* __restrict__ blk_la,
-    float* __restrict__ endrow) {
+    float* __restrict__ endrow, const PairTask* __restrict__ ctasks,
+    const int32_t* __restrict__ ccount) {
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
-    if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
-    const PairTask t = tasks[task];
+    // with the dense list of representative pairs (k_dedup), wavefront i takes its entry i
+    if (task >= (ccount ? *ccount : n_tasks)) return;  // whole wavefront; no barriers here
+    const PairTask t = ccount ? ctasks[task] : tasks[task];
     if (rescue_held(rsc, t.chain)) return;  // re-filtered whole in FP64 this pass
     const ChainInfo& c = chains[t.chain];
     // shared forward filters: only representatives run the recursion (k_member_logz completes
@@ -488,15 +497,20 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const int64_t rowoff = (int64_t)t.block * (c.B - 1);
     float* rows0 = filt + c.filt_off + ((int64_t)pp[0] * L_tau + rowoff) * N;
     float* rows1 = filt + c.filt_off + ((int64_t)pp[1] * L_tau + rowoff) * N;
-    float wn[16];
-    load_w((start + 1) % L_tau, wn);
+    // W of the current slice and of the next two, in three buffers that rotate every step: a
+    // slice is loaded two steps before its use, so its load latency (longer than a step) is
+    // hidden; with a single buffer the loop's back edge would copy the freshly loaded slice into
+    // it and wait for the load in every step
+    float wa[16], wb[16], wc[16];
+    load_w((start + 1) % L_tau, wa);
+    load_w((start + 2) % L_tau, wb);
     bool low0 = false, low1 = false;  // a worldline left FP32's range: FP64 re-filter
-    // One step: uses wn (this slice's W) and refills it with the next slice's W before the
-    // stores. The first step is peeled off the loop so that on entry to the loop, as on every
-    // later pass, the stores of the previous step sit between wn's loads and their use, and the
+    // One step: uses wn (this slice's W) and loads the W of the slice after next into wf
+    // before the stores. The first step is peeled off the loop so that on entry to the loop, as on every
+    // later pass, the stores of the previous step sit between wf's loads and their use, and the
     // wait before the W multiply leaves those stores in flight. A lone worldline's shadow stores
     // the same values to the same row, which keeps the store count (and that wait) uniform.
-    auto step = [&](int j) {
+    auto step = [&](int j, const float (&wn)[16], float (&wf)[16]) {
         const int l = (start + j) % L_tau;
         const f32x16 X0 = circ_step(F0, C, neg);
         const f32x16 X1 = circ_step(F1, C, neg);
@@ -510,8 +524,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
             s0 += F0[v];
             s1 += F1[v];
         }
-        // next slice's W (the last step fetches one slice it does not use; always in bounds)
-        load_w((l + 1) % L_tau, wn);
+        // the W of the slice after next (the last two steps fetch slices they do not use;
+        // always in bounds)
+        load_w((l + 2) % L_tau, wf);
         __builtin_amdgcn_sched_barrier(0);
         const float tot0 = wave_sum_f32(s0), tot1 = wave_sum_f32(s1);
         low0 |= !(tot0 >= step_floor) | !isfinite(tot0);
@@ -547,8 +562,15 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
         }
     };
     if (len > 1) {
-        step(1);
-        for (int j = 2; j < len; ++j) step(j);
+        step(1, wa, wc);
+        int j = 2;
+        for (; j + 2 < len; j += 3) {
+            step(j, wb, wa);
+            step(j + 1, wc, wb);
+            step(j + 2, wa, wc);
+        }
+        if (j < len) step(j, wb, wa);
+        if (j + 1 < len) step(j + 1, wc, wb);
     }
     {
         const double ms = block_shift_sum(shift, start, len, L_tau, lsc, lane);
@@ -917,9 +939,11 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
         for (int v = 0; v < 16; ++v) dst[v] = inside(v) ? Wl[cv(v) * L] : Wsp[(int64_t)l * N];
     };
     bool low = false;  // the owner's worldline left FP32's range: FP64 re-filter
-    float wn[16];
-    load_w((start + 1) % L_tau, wn);
-    auto step = [&](int j) {
+    // two W buffers that swap roles every step (one buffer would make the loop's back edge copy
+    // the loaded slice into it, waiting for the load)
+    float wa[16], wb[16];
+    load_w((start + 1) % L_tau, wa);
+    auto step = [&](int j, const float (&wn)[16], float (&wf)[16]) {
         const int l = (start + j) % L_tau;
         f32x16 H[NT];
 #pragma unroll
@@ -938,7 +962,7 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
                 F[T][v] = H[T][v] * wn[v];
                 sm[T][v / RPB] += F[T][v];
             }
-        load_w((l + 1) % L_tau, wn);  // the last step fetches a slice it does not use
+        load_w((l + 1) % L_tau, wf);  // the last step fetches a slice it does not use
         __builtin_amdgcn_sched_barrier(0);
         float inv[NT][P], mine = 1.0f, mtot = 1.0f;
 #pragma unroll
@@ -983,8 +1007,13 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
         }
     };
     if (len > 1) {
-        step(1);
-        for (int j = 2; j < len; ++j) step(j);
+        step(1, wa, wb);
+        int j = 2;
+        for (; j + 1 < len; j += 2) {
+            step(j, wb, wa);
+            step(j + 1, wa, wb);
+        }
+        if (j < len) step(j, wb, wa);
     }
     la += block_shift_sum(shift, start, len, L_tau, lsc, lane);
     // end weights (C f~ C)(e) of every slot: the owner reads its block's element at e
@@ -1581,7 +1610,9 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
                            p->d.fwd32_tasks, p->n_fwd32_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
-                           rescue_args(p), kNegPairs, p->d.blk_la, p->d.endrow);
+                           rescue_args(p), kNegPairs, p->d.blk_la, p->d.endrow,
+                           p->d.fwd32c_tasks,
+                           p->d.fwd32c_tasks && !p->share_off ? p->d.rescue + 5 : nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
