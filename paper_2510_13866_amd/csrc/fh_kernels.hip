@@ -1272,10 +1272,31 @@ __device__ __attribute__((noinline)) void rescue_draws(const DrawTask& t, const 
     int cur = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np +
                               (start + len >= L_tau ? qn : t.p)], N, status, t.chain);
     int err = 0;
-    for (int j = len - 1; j >= 1; --j) {
-        const int l = (start + j) % L_tau;
-        const u64x4 rnd = philox4x64_10((uint64_t)t.p, (uint64_t)l, sweep, kTagPath, c.seed, 0);
-        const double u = u01_from(rnd.x0);
+    // Draw s sets slice start + (nd - s). Uniforms are made 64 draws at a time (lane k that of
+    // draw s + k) and drawn sites stored 64 at a time (lane k keeps that of draw s + k): a
+    // store per draw would make each draw's window loads wait for it (loads and stores retire
+    // in order), and a Philox evaluation per draw would sit on the chain of dependent draws.
+    const int nd = len - 1;
+    double ureg = 0.0;
+    int pend = 0;
+    auto flush = [&](int sb) {
+        const int sd = sb + lane;
+        if (sd < nd) {
+            const int jd = nd - sd;
+            pc[(int64_t)((start + jd) % L_tau) * c.np + (start + jd >= L_tau ? qn : t.p)] = pend;
+        }
+    };
+    for (int s = 0; s < nd; ++s) {
+        const int j = nd - s;
+        if ((s & 63) == 0) {
+            if (s > 0) flush(s - 64);
+            const int jj = j - lane;
+            ureg = 0.0;
+            if (jj >= 1)
+                ureg = u01_from(philox4x64_10((uint64_t)t.p, (uint64_t)((start + jj) % L_tau),
+                                              sweep, kTagPath, c.seed, 0).x0);
+        }
+        const double u = readlane_f64(ureg, s & 63);
         const double* row = rows + (int64_t)(j - 1) * N;
         const int cx = cur % L, cy = cur / L;
         int site = -1;
@@ -1293,9 +1314,10 @@ __device__ __attribute__((noinline)) void rescue_draws(const DrawTask& t, const 
             site = wave_row_draw(row, N, L, cx, cy, g, u, cur, lane, &bad);
             if (bad != 0 && err == 0) err = bad;
         }
-        if (lane == 0) pc[(int64_t)l * c.np + (start + j >= L_tau ? qn : t.p)] = site;
+        if (lane == (s & 63)) pend = site;
         cur = site;
     }
+    if (nd > 0) flush((nd - 1) & ~63);
     if (err != 0 && lane == 0) set_status(status, err, t.chain);
 }
 
