@@ -196,7 +196,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
                     d.draw_tasks, d.group_tasks, d.gpart, d.ckpt, d.rep, d.blk_la, d.endrow, d.dedup_tasks, d.fwd32_tasks, d.fwd32c_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
-                    d.rescue, d.rescue_list, d.rep_slot, d.rescue_ws, d.rescue_w, d.status, d.sweep};
+                    d.rescue, d.rescue_list, d.rep_slot, d.arep, d.rescue_ws, d.rescue_w, d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     d = fh::Device();
@@ -563,6 +563,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         if (e == hipSuccess) e = hipMemset(dv.rescue, 0, sizeof(int32_t) * words);
         if (e == hipSuccess) e = dalloc(&dv.rescue_list, sizeof(DrawTask) * draw.size());
         if (e == hipSuccess) e = dalloc(&dv.rep_slot, sizeof(int32_t) * (size_t)blk);
+        if (e == hipSuccess) e = dalloc(&dv.arep, sizeof(DrawTask) * (size_t)p->n_rescue_slots);
         if (e == hipSuccess && !ckpt)
             e = dalloc(&dv.rescue_ws, sizeof(double) * (size_t)p->n_rescue_slots * p->rescue_slot_elems);
         if (e == hipSuccess) e = dalloc(&dv.rescue_w, sizeof(double) * 2 * (size_t)aux);

@@ -142,7 +142,8 @@ constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // fh_debug_rescue, [2] chains re-filtered whole in this pass, [3] length of the queue's phase A
 // (a sweep's held chains, queued before its FP32 forward pass and re-filtered beside the FP32
 // passes), [4] slots taken by phase A, [5] entries of the dense list of representative pairs
-// (k_dedup), then per chain: blocks queued by the kernels in this pass
+// (k_dedup), [6] entries of phase A's dense list of representatives (k_rescue_held), then per
+// chain: blocks queued by the kernels in this pass
 // (kRescueChain + c), forward passes left on FP64 (kRescueChain + n_chains + c), 1 if the chain
 // is in phase A (kRescueChain + 2 n_chains + c), the forward recursions its blocks need in this
 // pass (kRescueChain + 3 n_chains + c: the representatives of the shared filters), the hold at
@@ -266,6 +267,7 @@ struct Device {
     int32_t* rescue = nullptr;   // FP32 plans: rescue state words (kRescueFlags), else null
     DrawTask* rescue_list = nullptr;  // blocks queued for the FP64 re-filter, [n_draw_tasks]
     int32_t* rep_slot = nullptr;      // phase A: the slot of each representative's block [blk]
+    DrawTask* arep = nullptr;         // phase A: its representatives, densely [n_rescue_slots]
     double* rescue_ws = nullptr;      // [n_rescue_slots][rescue_slot_elems] FP64 filter rows
     double* rescue_w = nullptr;       // [2][aux_elems] FP64 W~ of the chains with queued blocks
     int32_t* status = nullptr;   // [0] first error code, [1] its chain

@@ -1430,38 +1430,207 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_rescue(
     }
 }
 
-// Phase A of the FP64 re-filter (the held chains, beside the FP32 passes), first kernel: the
-// forward recursion of each block whose worldline is its own representative (every block of a
-// chain without shared filters), one wavefront per block, into a slot of its own taken in queue
-// order (k_rescue_held admitted only chains whose recursions fit the slots): the rows, then the
-// end tile C f~ C. The block's log Z goes to blk_logz, log Z without the end weight to blk_la
-// (shared-filter chains), and the slot to rep_slot.
-// NT as in k_rescue: one launch per tiling, each taking its own chains' representatives.
-template <int NT>
-__global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_rescue_share_fwd(
+// Phase A of the FP64 re-filter (the held chains, beside the FP32 passes), first kernels: the
+// forward recursion of each representative in the dense list arep (k_rescue_held; every block
+// of a chain without shared filters), into a slot of its own (k_rescue_held admitted only
+// chains whose recursions fit the slots): the rows, then the end tile C f~ C. The block's log Z
+// goes to blk_logz, log Z without the end weight to blk_la (shared-filter chains), and the slot
+// to rep_slot.
+//
+// Lattices with L <= 32: one workgroup of four wavefronts per representative. Wavefront q owns
+// the 16 x 16 tile q = 2 I + J of the padded 32 x 32 filter (fh_dmfma.h): every wavefront holds
+// the whole filter F, forms the two tiles X(0, I), X(1, I) of X = F^T C that its tile of
+// H = X^T C needs, then that tile: 24 products per step where one wavefront takes 64. The four
+// W-weighted tiles meet in LDS, and every wavefront sums all of them in the order of
+// dmfma_block_forward_end, so the normaliser, the rows, the end tile and log Z are bit for bit
+// those of the one-wavefront recursion (k_rescue).
+__global__ __launch_bounds__(kThreads, 1) void k_rescue_share_fwd4(
     const ChainInfo* __restrict__ chains, const double* __restrict__ cmat64,
     const float* __restrict__ aux, const double* __restrict__ wshift, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
     double* __restrict__ blk_logz, double* __restrict__ blk_la,
     const uint64_t* __restrict__ sweep_ptr, int32_t* status, const Rescue rsc,
-    int32_t* __restrict__ rep_slot, double* __restrict__ ws, int64_t slot_elems, int n_waves,
-    const double* __restrict__ W64, int64_t aux_elems) {
+    const DrawTask* __restrict__ arep, int32_t* __restrict__ rep_slot, double* __restrict__ ws,
+    int64_t slot_elems, const double* __restrict__ W64, int64_t aux_elems) {
+    static_assert(kWaves == 4, "one wavefront per 16 x 16 tile of the 32 x 32 filter");
+    __shared__ f64x4 xch[2][4][64];  // the W-weighted tiles of a step, double-buffered
+    __shared__ int32_t slot_sh;
+    const int lane = threadIdx.x & 63;
+    const int wq = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // this wavefront's tile
+    const int I = wq >> 1, J = wq & 1;
+    const int n = __builtin_amdgcn_readfirstlane(rsc.words[6]);
+    const uint64_t sweep = *sweep_ptr;
+    int buf = 0;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const DrawTask t = arep[i];
+        const ChainInfo& c = chains[t.chain];
+        if (c.L > 32) continue;  // the 16 x 16 tilings take it (the whole workgroup skips)
+        if (threadIdx.x == 0) slot_sh = atomicAdd(&rsc.words[4], 1);
+        __syncthreads();
+        const int slot_id = slot_sh;
+        double* slot = ws + (int64_t)slot_id * slot_elems;
+        int start, len;
+        block_of(c, sweep, t.block, &start, &len);
+        const int L = c.L, N = c.N, L_tau = c.L_tau;
+        const int spin = t.p >= c.n_up ? 1 : 0;
+        const double coef = spin ? c.coef_dn : c.coef_up;
+        const double* shift = wshift + spin * total_slices + c.slice_off;
+        const int32_t* pc = paths + c.path_off;
+        const int qn = perm[c.part_off + t.p];  // the worldline slices >= L_tau belong to
+        const int a = checked_site(pc[(int64_t)start * c.np + t.p], N, status, t.chain);
+        const int e = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np +
+                                      (start + len >= L_tau ? qn : t.p)], N, status, t.chain);
+        // the B operands this wavefront's products take: column block I of C for X(K, I),
+        // column block J for its tile of H (loaded by index, not picked from registers at a
+        // run-time index, which would put them in scratch)
+        double CbI[8], CbJ[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            CbI[k] = cmat64[((int64_t)t.chain * 16 + k * 2 + I) * 64 + lane];
+            CbJ[k] = cmat64[((int64_t)t.chain * 16 + k * 2 + J) * 64 + lane];
+        }
+        const double* Wl0 = W64 + spin * aux_elems + c.aux_off;
+        // this wavefront's elements: site of register r of tile wq (-1 where padded; W is read
+        // at site 0 there and multiplies an exact zero)
+        int site[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int x = t64_x(wq, lane), y = t64_y(wq, r, lane);
+            site[r] = (x < L && y < L) ? y * L + x : -1;
+        }
+        auto load_w = [&](int l, double (&w)[4]) {
+            const double* Wl = Wl0 + (int64_t)l * N;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) w[r] = Wl[max(site[r], 0)];
+        };
+        // this wavefront's tile of H = (F^T C)^T C = C F C
+        auto own_tile = [&](const Tile64& F) {
+            f64x4 X[2];
+#pragma unroll
+            for (int K = 0; K < 2; ++K) {
+                f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int K2 = 0; K2 < 2; ++K2)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(F.t[2 * K2 + K][r],
+                                                                   CbI[4 * K2 + r], acc, 0, 0, 0);
+                X[K] = acc;
+            }
+            f64x4 H = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int K = 0; K < 2; ++K)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    H = __builtin_amdgcn_mfma_f64_16x16x4f64(X[K][r], CbJ[4 * K + r], H, 0, 0, 0);
+            return H;
+        };
+        Tile64 F;
+        const int ax = a % L, ay = a / L;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                F.t[q][r] = (t64_x(q, lane) == ax && t64_y(q, r, lane) == ay) ? 1.0 : 0.0;
+        double la = coef * (double)aux[c.aux_off + (int64_t)start * N + a];
+        bool good = true;
+        // W of the next slice loaded one step ahead, in two buffers that swap roles
+        double wa[4], wb[4];
+        load_w((start + 1) % L_tau, wa);
+        auto step = [&](int j, const double (&w)[4], double (&wf)[4]) {
+            const int l = (start + j) % L_tau;
+            const f64x4 H = own_tile(F);
+            load_w((l + 1) % L_tau, wf);  // the last step fetches a slice it does not use
+            f64x4 P;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) P[r] = H[r] * w[r];
+            xch[buf][wq][lane] = P;
+            __syncthreads();
+            double sum = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const f64x4 v = xch[buf][q][lane];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    F.t[q][r] = v[r];
+                    sum += v[r];
+                }
+            }
+            buf ^= 1;
+            const double tot = wave_sum_f64(sum);
+            good = good && tot > 0.0 && isfinite(tot);
+            const double inv = 1.0 / tot;
+            la += log(tot) + shift[l];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) F.t[q][r] *= inv;
+            // this wavefront's tile of the row: its own products scaled as F.t[wq] (read from
+            // the products it holds, as F.t[wq] at a run-time index would live in scratch)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (site[r] >= 0) slot[(int64_t)(j - 1) * N + site[r]] = P[r] * inv;
+        };
+        int j = 1;
+        for (; j + 1 < len; j += 2) {
+            step(j, wa, wb);
+            step(j + 1, wb, wa);
+        }
+        if (j < len) step(j, wa, wb);
+        // end weight (C f~ C)(e): the end tile, and the element at e from its tile's wavefront
+        const f64x4 H = own_tile(F);
+        double* end = slot + (int64_t)(c.B - 1) * N;  // after the longest block's rows
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (site[r] >= 0) end[site[r]] = H[r];
+        const int ex = e % L, ey = e / L;
+        if (wq == 2 * (ey >> 4) + (ex >> 4)) {
+            const int re = (ey & 15) >> 2;
+            double hv = 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r == re) hv = H[r];
+            hv = __shfl(hv, (ex & 15) + 16 * (ey & 3), 64);
+            if (lane == 0) {
+                const int64_t bi = c.blk_off + (int64_t)t.p * c.nb + t.block;
+                if (!(good && hv > 0.0)) set_status(status, FH_ERR_NONFINITE, t.chain);
+                blk_logz[bi] = la + log(hv);
+                if (c.dedup) blk_la[bi] = la;
+                rep_slot[bi] = slot_id;
+            }
+        }
+        __syncthreads();  // slot_sh and the exchange buffers are free for the next representative
+    }
+}
+
+// The 48 x 48 and 64 x 64 chains' representatives (NT = 3, 4, fh_dmfma.h), one wavefront each,
+// wavefront w taking entries w, w + n_waves, ... of arep.
+template <int NT>
+__global__ __launch_bounds__(kThreads, 1) void k_rescue_share_fwd(
+    const ChainInfo* __restrict__ chains, const double* __restrict__ cmat64,
+    const float* __restrict__ aux, const double* __restrict__ wshift, int64_t total_slices,
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm,
+    double* __restrict__ blk_logz, double* __restrict__ blk_la,
+    const uint64_t* __restrict__ sweep_ptr, int32_t* status, const Rescue rsc,
+    const DrawTask* __restrict__ arep, int32_t* __restrict__ rep_slot, double* __restrict__ ws,
+    int64_t slot_elems, int n_waves, const double* __restrict__ W64, int64_t aux_elems) {
+    static_assert(NT == 3 || NT == 4, "the 16 x 16 tilings");
+    constexpr int L = 16 * NT, N = L * L;
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
-    const int hi = __builtin_amdgcn_readfirstlane(rsc.words[3]);
+    const int n = __builtin_amdgcn_readfirstlane(rsc.words[6]);
     const uint64_t sweep = *sweep_ptr;
-    for (int i = wid; i < hi; i += n_waves) {
-        const DrawTask t = rsc.list[i];
+    for (int i = wid; i < n; i += n_waves) {
+        const DrawTask t = arep[i];
         const ChainInfo& c = chains[t.chain];
-        if (NT == 2 ? c.L > 32 : c.L != 16 * NT) continue;  // another launch's chain
-        if (c.dedup && row_owner(rsc, c, t.p, t.block) != t.p) continue;  // shares these rows
+        if (c.L != L) continue;  // another launch's chain
         int slot_id = 0;
         if (lane == 0) slot_id = atomicAdd(&rsc.words[4], 1);
         slot_id = __builtin_amdgcn_readfirstlane(__shfl(slot_id, 0, 64));
         double* slot = ws + (int64_t)slot_id * slot_elems;
         int start, len;
         block_of(c, sweep, t.block, &start, &len);
-        const int L = NT == 2 ? c.L : 16 * NT, N = NT == 2 ? c.N : 256 * NT * NT, L_tau = c.L_tau;
+        const int L_tau = c.L_tau;
         const int spin = t.p >= c.n_up ? 1 : 0;
         const double coef = spin ? c.coef_dn : c.coef_up;
         const double* shift = wshift + spin * total_slices + c.slice_off;
@@ -1474,22 +1643,13 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_rescue_share_fwd(
 #pragma unroll
         for (int q = 0; q < 16; ++q) Cb[q] = cmat64[((int64_t)t.chain * 16 + q) * 64 + lane];
         const double* Wl0 = W64 + spin * aux_elems + c.aux_off;
-        // the site of the lane's element (q, r); padded positions (L < 32) read W at site 0,
-        // times an exact zero, and store nothing
-        auto site = [&](int q, int r) {
-            if constexpr (NT == 2) {
-                const int x = t64_x(q, lane), y = t64_y(q, r, lane);
-                return (x < L && y < L) ? y * L + x : -1;
-            } else {
-                return tb_y<NT>(q, r, lane) * L + tb_x<NT>(q, lane);
-            }
-        };
-        auto wtab = [&](int l, auto& w) {
+        auto site = [&](int q, int r) { return tb_y<NT>(q, r, lane) * L + tb_x<NT>(q, lane); };
+        auto wtab = [&](int l, double (&w)[4 * NT * NT]) {
             const double* Wl = Wl0 + (int64_t)l * N;
 #pragma unroll
-            for (int q = 0; q < (NT == 2 ? 4 : NT * NT); ++q)
+            for (int q = 0; q < NT * NT; ++q)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) w[4 * q + r] = Wl[max(site(q, r), 0)];
+                for (int r = 0; r < 4; ++r) w[4 * q + r] = Wl[site(q, r)];
         };
         auto put = [&](int j, int q, int r, double v) {
             slot[(int64_t)(j - 1) * N + site(q, r)] = v;
@@ -1499,13 +1659,8 @@ __global__ __launch_bounds__(kThreads, NT == 2 ? 2 : 1) void k_rescue_share_fwd(
         bool ok = true;
         double la_end = 0.0;
         const double la0 = coef * (double)aux[c.aux_off + (int64_t)start * N + a];
-        double lz;
-        if constexpr (NT == 2)
-            lz = dmfma_block_forward_end(Cb, L, L_tau, start, len, a, e, la0, shift, wtab, put,
-                                         put_end, &la_end, &ok);
-        else
-            lz = dmfma_big_block_forward_end<NT>(Cb, L_tau, start, len, a, e, la0, shift, wtab,
-                                                 put, put_end, &la_end, &ok);
+        const double lz = dmfma_big_block_forward_end<NT>(Cb, L_tau, start, len, a, e, la0, shift,
+                                                          wtab, put, put_end, &la_end, &ok);
         if (lane == 0) {
             const int64_t bi = c.blk_off + (int64_t)t.p * c.nb + t.block;
             if (!ok) set_status(status, FH_ERR_NONFINITE, t.chain);
@@ -1671,6 +1826,7 @@ __global__ void k_rescue_reset(const Rescue rsc, int64_t n_flags) {
         rsc.words[3] = 0;
         rsc.words[4] = 0;
         rsc.words[5] = 0;
+        rsc.words[6] = 0;
     }
     const int n = rsc.n_chains;
     for (int64_t k = i; k < n; k += stride) {
@@ -1705,18 +1861,22 @@ __global__ void k_rescue_reset(const Rescue rsc, int64_t n_flags) {
 // is empty before this kernel, so the entries are laid down in place.
 __global__ __launch_bounds__(kThreads) void k_rescue_held(const ChainInfo* __restrict__ chains,
                                                           const Rescue rsc, int n_slots,
-                                                          int shared) {
+                                                          int shared, DrawTask* __restrict__ arep) {
     int off = 0, slots = 0;
     for (int ci = 0; ci < rsc.n_chains; ++ci) {
         const ChainInfo& c = chains[ci];
         if (!fp64_circulant(c.L) || !rescue_held(rsc, ci)) continue;
         const int nblk = c.np * c.nb;
-        const int nrec = shared && c.dedup ? rsc.words[kRescueChain + 3 * rsc.n_chains + ci] : nblk;
+        const bool share = shared && c.dedup;
+        const int nrec = share ? rsc.words[kRescueChain + 3 * rsc.n_chains + ci] : nblk;
         if (slots + nrec > n_slots) continue;
         slots += nrec;
         for (int i = threadIdx.x; i < nblk; i += blockDim.x) {  // i = p nb + block
             rsc.flags[c.blk_off + i] = 1;
             rsc.list[off + i] = DrawTask{ci, i / c.nb, i % c.nb, 0};
+            // the representatives, in no particular order (at most n_slots of them)
+            if (!share || rsc.rep[c.blk_off + i] == i / c.nb)
+                arep[atomicAdd(&rsc.words[6], 1)] = DrawTask{ci, i / c.nb, i % c.nb, 0};
         }
         if (threadIdx.x == 0) rsc.words[kRescueChain + 2 * rsc.n_chains + ci] = 1;
         off += nblk;
@@ -2630,7 +2790,8 @@ hipError_t launch_rescue_expand(fh_plan p, hipStream_t s) {
 hipError_t launch_rescue_held(fh_plan p, hipStream_t s) {
     if (!p->d.rescue) return hipSuccess;
     hipLaunchKernelGGL(k_rescue_held, dim3(1), dim3(kThreads), 0, s, p->d.chains, rescue_args(p),
-                       p->n_rescue_slots, (int)(p->n_dedup_tasks > 0 && !p->share_off));
+                       p->n_rescue_slots, (int)(p->n_dedup_tasks > 0 && !p->share_off),
+                       p->d.arep);
     return hipGetLastError();
 }
 
@@ -2642,15 +2803,20 @@ hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, 
                        p->aux_elems, p->total_slices, rescue_args(p), phase);
     const unsigned blocks = (unsigned)(p->n_rescue_slots / kWaves);
     if (draw && phase == 1) {  // representatives into their slots, then every block's draws
+        // L <= 32: a workgroup per representative; 48 x 48, 64 x 64: a wavefront each
+        hipLaunchKernelGGL(k_rescue_share_fwd4, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.cmat64, (const float*)aux, p->d.wshift, p->total_slices, paths,
+                           p->d.perm, p->d.blk_logz, p->d.blk_la, p->d.sweep, p->d.status,
+                           rescue_args(p), p->d.arep, p->d.rep_slot, p->d.rescue_ws,
+                           p->rescue_slot_elems, p->d.rescue_w, p->aux_elems);
         auto fwd = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                                p->d.cmat64, (const float*)aux, p->d.wshift, p->total_slices,
                                paths, p->d.perm, p->d.blk_logz, p->d.blk_la, p->d.sweep,
-                               p->d.status, rescue_args(p), p->d.rep_slot, p->d.rescue_ws,
-                               p->rescue_slot_elems, p->n_rescue_slots, p->d.rescue_w,
-                               p->aux_elems);
+                               p->d.status, rescue_args(p), p->d.arep, p->d.rep_slot,
+                               p->d.rescue_ws, p->rescue_slot_elems, p->n_rescue_slots,
+                               p->d.rescue_w, p->aux_elems);
         };
-        fwd(k_rescue_share_fwd<2>);
         if (p->rescue_l64) fwd(k_rescue_share_fwd<4>);
         if (p->rescue_l48) fwd(k_rescue_share_fwd<3>);
         // the draws take no slot: twice the slot count of wavefronts, four per SIMD
