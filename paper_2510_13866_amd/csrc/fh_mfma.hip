@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "fh_dmfma.h"
 #include "fh_internal.h"
 
@@ -437,7 +439,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const bool cached = n_rep > 0 && (int64_t)n_rep * (c.B - 1) * N * 4 <= kCachedRowBytes;
     const bool has_b = ra && rb;
     const int q0 = ra ? t.p_a : t.p_b;
-    const int pp[2] = {q0, has_b ? t.p_b : q0};  // a lone worldline is shadowed, not stored
+    const int pp[2] = {q0, has_b ? t.p_b : q0};  // a lone worldline runs alone (PAIR false)
     const int spin = t.p_a >= c.n_up ? 1 : 0;
     const float* Wsp = W + spin * aux_elems + c.aux_off;
     const double* shift = wshift + spin * total_slices + c.slice_off;
@@ -481,143 +483,165 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const float sc = ldexpf(1.0f, c.row_exp);
     const double lsc = c.row_exp * 0.69314718055994530942;
     const float step_floor = c.step_floor;  // held in a register across the recursion
-    f32x16 F0, F1;
-    {
-        const int ax0 = a[0] % L, ay0 = a[0] / L, ax1 = a[1] % L, ay1 = a[1] / L;
+    // PAIR: two worldlines share the wavefront; a lone worldline (a representative without a
+    // partner of its spin and block, the rule on a clustered state) runs alone, with half the
+    // matrix and vector work per step, and the same arithmetic
+    auto run = [&](auto pair) {
+        constexpr bool PAIR = decltype(pair)::value;
+        f32x16 F0, F1;
+        {
+            const int ax0 = a[0] % L, ay0 = a[0] / L, ax1 = a[1] % L, ay1 = a[1] / L;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int y = tile_row(lane, v);
-            F0[v] = (x == ax0 && y == ay0) ? sc : 0.0f;
-            F1[v] = (x == ax1 && y == ay1) ? sc : 0.0f;
+            for (int v = 0; v < 16; ++v) {
+                const int y = tile_row(lane, v);
+                F0[v] = (x == ax0 && y == ay0) ? sc : 0.0f;
+                if constexpr (PAIR) F1[v] = (x == ax1 && y == ay1) ? sc : 0.0f;
+            }
         }
-    }
-    double la0 = coef * (double)aux[c.aux_off + (int64_t)start * N + a[0]] - lsc;
-    double la1 = coef * (double)aux[c.aux_off + (int64_t)start * N + a[1]] - lsc;
-    double prod0 = 1.0, prod1 = 1.0;
-    const int64_t rowoff = (int64_t)t.block * (c.B - 1);
-    float* rows0 = filt + c.filt_off + ((int64_t)pp[0] * L_tau + rowoff) * N;
-    float* rows1 = filt + c.filt_off + ((int64_t)pp[1] * L_tau + rowoff) * N;
-    // W of the current slice and of the next two, in three buffers that rotate every step: a
-    // slice is loaded two steps before its use, so its load latency (longer than a step) is
-    // hidden; with a single buffer the loop's back edge would copy the freshly loaded slice into
-    // it and wait for the load in every step
-    float wa[16], wb[16], wc[16];
-    load_w((start + 1) % L_tau, wa);
-    load_w((start + 2) % L_tau, wb);
-    bool low0 = false, low1 = false;  // a worldline left FP32's range: FP64 re-filter
-    // One step: uses wn (this slice's W) and loads the W of the slice after next into wf
-    // before the stores. The first step is peeled off the loop so that on entry to the loop, as on every
-    // later pass, the stores of the previous step sit between wf's loads and their use, and the
-    // wait before the W multiply leaves those stores in flight. A lone worldline's shadow stores
-    // the same values to the same row, which keeps the store count (and that wait) uniform.
-    auto step = [&](int j, const float (&wn)[16], float (&wf)[16]) {
-        const int l = (start + j) % L_tau;
-        const f32x16 X0 = circ_step(F0, C, neg);
-        const f32x16 X1 = circ_step(F1, C, neg);
-        const f32x16 H0 = circ_step(X0, C, neg);
-        const f32x16 H1 = circ_step(X1, C, neg);
-        float s0 = 0.0f, s1 = 0.0f;
+        double la0 = coef * (double)aux[c.aux_off + (int64_t)start * N + a[0]] - lsc;
+        double la1 = PAIR ? coef * (double)aux[c.aux_off + (int64_t)start * N + a[1]] - lsc : 0.0;
+        double prod0 = 1.0, prod1 = 1.0;
+        const int64_t rowoff = (int64_t)t.block * (c.B - 1);
+        float* rows0 = filt + c.filt_off + ((int64_t)pp[0] * L_tau + rowoff) * N;
+        float* rows1 = filt + c.filt_off + ((int64_t)pp[1] * L_tau + rowoff) * N;
+        // W of the current slice and of the next two, in three buffers that rotate every step:
+        // a slice is loaded two steps before its use, so its load latency (longer than a step)
+        // is hidden; with a single buffer the loop's back edge would copy the freshly loaded
+        // slice into it and wait for the load in every step
+        float wa[16], wb[16], wc[16];
+        load_w((start + 1) % L_tau, wa);
+        load_w((start + 2) % L_tau, wb);
+        bool low0 = false, low1 = false;  // a worldline left FP32's range: FP64 re-filter
+        // One step: uses wn (this slice's W) and loads the W of the slice after next into wf
+        // before the stores, so that the wait before a W multiply leaves the stores in flight.
+        auto step = [&](int j, const float (&wn)[16], float (&wf)[16]) {
+            const int l = (start + j) % L_tau;
+            f32x16 H0, H1;
+            {
+                const f32x16 X0 = circ_step(F0, C, neg);
+                f32x16 X1;
+                if constexpr (PAIR) X1 = circ_step(F1, C, neg);
+                H0 = circ_step(X0, C, neg);
+                if constexpr (PAIR) H1 = circ_step(X1, C, neg);
+            }
+            float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            F0[v] = H0[v] * wn[v];
-            F1[v] = H1[v] * wn[v];
-            s0 += F0[v];
-            s1 += F1[v];
-        }
-        // the W of the slice after next (the last two steps fetch slices they do not use;
-        // always in bounds)
-        load_w((l + 2) % L_tau, wf);
-        __builtin_amdgcn_sched_barrier(0);
-        const float tot0 = wave_sum_f32(s0), tot1 = wave_sum_f32(s1);
-        low0 |= !(tot0 >= step_floor) | !isfinite(tot0);
-        low1 |= !(tot1 >= step_floor) | !isfinite(tot1);
-        // f~_j = h_j * inv: the normaliser applied is exactly 1/inv (see k_forward_mfma)
-        const float inv0 = __builtin_amdgcn_rcpf(tot0), inv1 = __builtin_amdgcn_rcpf(tot1);
-        prod0 *= (double)inv0;
-        prod1 *= (double)inv1;
-        if (!(prod0 > 1e-200 && prod0 < 1e200)) {
-            la0 -= log(prod0);
-            prod0 = 1.0;
-        }
-        if (!(prod1 > 1e-200 && prod1 < 1e200)) {
-            la1 -= log(prod1);
-            prod1 = 1.0;
-        }
-        const float k0 = inv0 * sc, k1 = inv1 * sc;
-        float* row0 = rows0 + (int64_t)(j - 1) * N + lane_off;
-        float* row1 = rows1 + (int64_t)(j - 1) * N + lane_off;
+            for (int v = 0; v < 16; ++v) {
+                F0[v] = H0[v] * wn[v];
+                s0 += F0[v];
+                if constexpr (PAIR) {
+                    F1[v] = H1[v] * wn[v];
+                    s1 += F1[v];
+                }
+            }
+            // the W of the slice after next (the last two steps fetch slices they do not use;
+            // always in bounds)
+            load_w((l + 2) % L_tau, wf);
+            __builtin_amdgcn_sched_barrier(0);
+            const float tot0 = wave_sum_f32(s0), tot1 = PAIR ? wave_sum_f32(s1) : 1.0f;
+            low0 |= !(tot0 >= step_floor) | !isfinite(tot0);
+            if constexpr (PAIR) low1 |= !(tot1 >= step_floor) | !isfinite(tot1);
+            // f~_j = h_j * inv: the normaliser applied is exactly 1/inv (see k_forward_mfma)
+            const float inv0 = __builtin_amdgcn_rcpf(tot0);
+            const float inv1 = PAIR ? __builtin_amdgcn_rcpf(tot1) : 1.0f;
+            prod0 *= (double)inv0;
+            if (!(prod0 > 1e-200 && prod0 < 1e200)) {
+                la0 -= log(prod0);
+                prod0 = 1.0;
+            }
+            if constexpr (PAIR) {
+                prod1 *= (double)inv1;
+                if (!(prod1 > 1e-200 && prod1 < 1e200)) {
+                    la1 -= log(prod1);
+                    prod1 = 1.0;
+                }
+            }
+            const float k0 = inv0 * sc, k1 = inv1 * sc;
+            float* row0 = rows0 + (int64_t)(j - 1) * N + lane_off;
+            float* row1 = rows1 + (int64_t)(j - 1) * N + lane_off;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            F0[v] *= k0;
-            F1[v] *= k1;
-            if (inside(v)) {
-                if (cached) {
-                    row0[vrow(v) * L] = F0[v];
-                    row1[vrow(v) * L] = F1[v];
-                } else {
-                    __builtin_nontemporal_store(F0[v], row0 + vrow(v) * L);
-                    __builtin_nontemporal_store(F1[v], row1 + vrow(v) * L);
+            for (int v = 0; v < 16; ++v) {
+                F0[v] *= k0;
+                if constexpr (PAIR) F1[v] *= k1;
+                if (inside(v)) {
+                    if (cached) {
+                        row0[vrow(v) * L] = F0[v];
+                        if constexpr (PAIR) row1[vrow(v) * L] = F1[v];
+                    } else {
+                        __builtin_nontemporal_store(F0[v], row0 + vrow(v) * L);
+                        if constexpr (PAIR) __builtin_nontemporal_store(F1[v], row1 + vrow(v) * L);
+                    }
+                }
+            }
+        };
+        if (len > 1) {
+            step(1, wa, wc);
+            int j = 2;
+            for (; j + 2 < len; j += 3) {
+                step(j, wb, wa);
+                step(j + 1, wc, wb);
+                step(j + 2, wa, wc);
+            }
+            if (j < len) step(j, wb, wa);
+            if (j + 1 < len) step(j + 1, wc, wb);
+        }
+        {
+            const double ms = block_shift_sum(shift, start, len, L_tau, lsc, lane);
+            la0 += ms;
+            la1 += ms;
+        }
+        // end weights (C f~ C)(e)
+        f32x16 H0, H1;
+        {
+            const f32x16 X0 = circ_step(F0, C, neg);
+            f32x16 X1;
+            if constexpr (PAIR) X1 = circ_step(F1, C, neg);
+            H0 = circ_step(X0, C, neg);
+            if constexpr (PAIR) H1 = circ_step(X1, C, neg);
+        }
+        float hv0 = 0.0f, hv1 = 0.0f;
+        {
+            const int ex0 = e[0] % L, ey0 = e[0] / L, ex1 = e[1] % L, ey1 = e[1] / L;
+            const int ve0 = (ey0 >> 3) * 4 + (ey0 & 3), ve1 = (ey1 >> 3) * 4 + (ey1 & 3);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                if (v == ve0) hv0 = H0[v];
+                if constexpr (PAIR)
+                    if (v == ve1) hv1 = H1[v];
+            }
+            hv0 = __shfl(hv0, ex0 + 32 * ((ey0 >> 2) & 1), 64);
+            if constexpr (PAIR) hv1 = __shfl(hv1, ex1 + 32 * ((ey1 >> 2) & 1), 64);
+        }
+        la0 -= log(prod0);
+        if constexpr (PAIR) la1 -= log(prod1);
+        if (lane == 0) {
+            if (low0 || !(hv0 >= kRangeFloor)) rescue_push(rsc, c, t.chain, pp[0], t.block);
+            blk_logz[c.blk_off + (int64_t)pp[0] * c.nb + t.block] = la0 + log((double)hv0);
+            if constexpr (PAIR) {
+                if (low1 || !(hv1 >= kRangeFloor)) rescue_push(rsc, c, t.chain, pp[1], t.block);
+                blk_logz[c.blk_off + (int64_t)pp[1] * c.nb + t.block] = la1 + log((double)hv1);
+            }
+        }
+        if (c.dedup) {  // what the worldlines sharing these rows need: log Z so far, end tile
+            if (lane == 0) {
+                blk_la[c.blk_off + (int64_t)pp[0] * c.nb + t.block] = la0;
+                if constexpr (PAIR) blk_la[c.blk_off + (int64_t)pp[1] * c.nb + t.block] = la1;
+            }
+            float* end0 = endrow + c.end_off + ((int64_t)pp[0] * c.nb + t.block) * N + lane_off;
+            float* end1 = endrow + c.end_off + ((int64_t)pp[1] * c.nb + t.block) * N + lane_off;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                if (inside(v)) {
+                    end0[vrow(v) * L] = H0[v];
+                    if constexpr (PAIR) end1[vrow(v) * L] = H1[v];
                 }
             }
         }
     };
-    if (len > 1) {
-        step(1, wa, wc);
-        int j = 2;
-        for (; j + 2 < len; j += 3) {
-            step(j, wb, wa);
-            step(j + 1, wc, wb);
-            step(j + 2, wa, wc);
-        }
-        if (j < len) step(j, wb, wa);
-        if (j + 1 < len) step(j + 1, wc, wb);
-    }
-    {
-        const double ms = block_shift_sum(shift, start, len, L_tau, lsc, lane);
-        la0 += ms;
-        la1 += ms;
-    }
-    // end weights (C f~ C)(e)
-    const f32x16 X0 = circ_step(F0, C, neg);
-    const f32x16 X1 = circ_step(F1, C, neg);
-    const f32x16 H0 = circ_step(X0, C, neg);
-    const f32x16 H1 = circ_step(X1, C, neg);
-    float hv0 = 0.0f, hv1 = 0.0f;
-    {
-        const int ex0 = e[0] % L, ey0 = e[0] / L, ex1 = e[1] % L, ey1 = e[1] / L;
-        const int ve0 = (ey0 >> 3) * 4 + (ey0 & 3), ve1 = (ey1 >> 3) * 4 + (ey1 & 3);
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            if (v == ve0) hv0 = H0[v];
-            if (v == ve1) hv1 = H1[v];
-        }
-        hv0 = __shfl(hv0, ex0 + 32 * ((ey0 >> 2) & 1), 64);
-        hv1 = __shfl(hv1, ex1 + 32 * ((ey1 >> 2) & 1), 64);
-    }
-    la0 -= log(prod0);
-    la1 -= log(prod1);
-    if (lane == 0) {
-        if (low0 || !(hv0 >= kRangeFloor)) rescue_push(rsc, c, t.chain, pp[0], t.block);
-        if (has_b && (low1 || !(hv1 >= kRangeFloor)))
-            rescue_push(rsc, c, t.chain, pp[1], t.block);
-        blk_logz[c.blk_off + (int64_t)pp[0] * c.nb + t.block] = la0 + log((double)hv0);
-        if (has_b) blk_logz[c.blk_off + (int64_t)pp[1] * c.nb + t.block] = la1 + log((double)hv1);
-    }
-    if (c.dedup) {  // what the worldlines sharing these rows need: log Z so far, the end tile
-        if (lane == 0) {
-            blk_la[c.blk_off + (int64_t)pp[0] * c.nb + t.block] = la0;
-            if (has_b) blk_la[c.blk_off + (int64_t)pp[1] * c.nb + t.block] = la1;
-        }
-        float* end0 = endrow + c.end_off + ((int64_t)pp[0] * c.nb + t.block) * N + lane_off;
-        float* end1 = endrow + c.end_off + ((int64_t)pp[1] * c.nb + t.block) * N + lane_off;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            if (inside(v)) {
-                end0[vrow(v) * L] = H0[v];
-                if (has_b) end1[vrow(v) * L] = H1[v];
-            }
-        }
-    }
+    if (has_b)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
 }
 
 // L = 64 on the same matrix cores: the 64 x 64 filter in four 32 x 32 sub-tiles X_RS (rows

@@ -1759,6 +1759,36 @@ def test_shared_forward_filters_change_nothing(lib):
     Sx.close()
 
 
+def test_fp64_refilter_phase_a_equals_one_wavefront(lib):
+    """A chain held on the FP64 re-filter is redone, within a sweep, in phase A: one recursion
+    per start site, four wavefronts to a 32 x 32 recursion, beside the FP32 passes. Run as
+    fh_forward_filter, fh_backward_sample and fh_gibbs_aux, the same pass redoes every block of
+    the chain on its own, one wavefront each (k_rescue). From a clustered state of the
+    benchmark's chains with a held chain, both give the same fields and paths, bit for bit."""
+    fhmc, sampler = lib
+    descs = synth.config_32x32(4.0, 16)
+    S = sampler.Sampler(descs, fhmc.FH_FP32_MFMA3, fhmc.FH_FLAG_GRAPH)
+    Se = sampler.Sampler(descs, fhmc.FH_FP32_MFMA3, fhmc.FH_FLAG_GRAPH)
+    A = S.pack_aux([synth.initial_aux(d) for d in descs])
+    P = S.pack_paths([synth.initial_paths(d) for d in descs])
+    Ae, Pe = A.clone(), P.clone()
+    S.sweep(A, P, 0, 12)
+    Se.sweep(Ae, Pe, 0, 12)
+    assert S.status() == Se.status() == (0, -1)
+    assert torch.equal(A, Ae) and torch.equal(P, Pe)
+    holds = fhmc.fh_debug_rescue_holds(S.plan, len(descs))
+    say("  holds after 12 sweeps:", list(holds))
+    assert max(holds) > 0  # a chain is held: the next sweep re-filters it in phase A
+    S.sweep(A, P, 12, 1)
+    Se.forward_filter(Ae, Pe, 12)
+    Se.backward_sample(Pe, 12)
+    Se.gibbs_aux(Pe, Ae, 12)
+    assert S.status() == Se.status() == (0, -1)
+    assert torch.equal(P, Pe) and torch.equal(A, Ae)
+    S.close()
+    Se.close()
+
+
 def synth_blocks(d):
     """FFBS blocks per worldline of a chain (the schedule's block count)."""
     B = d.block_len or d.L_tau
