@@ -49,8 +49,9 @@ struct ChainInfo {
     int32_t ck_k, ck_n;
     // Shared forward filters: the rows of a block depend only on the spin's W and the block's
     // start site, so worldlines of one (spin, block) with the same start site share the rows of
-    // the lowest-numbered of them, their representative. dedup = 1: 32 x 32 chains of the
-    // split-bf16 plan, in the FP32 passes and the FP64 re-filter's phase A; end_off locates their
+    // the lowest-numbered of them, their representative. dedup = 1: 32 x 32 and padded
+    // (16 < L < 32) chains of the split-bf16 plan, in the FP32 passes and the FP64 re-filter's
+    // phase A; end_off locates their
     // per-(particle, block) end tiles [N]. dedup = 2: 48 x 48 and 64 x 64 chains of FP32 plans,
     // in phase A only (their FP32 passes keep one recursion per worldline, and their map is the
     // identity while the chain is not held).
@@ -142,8 +143,8 @@ constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // fh_debug_rescue, [2] chains re-filtered whole in this pass, [3] length of the queue's phase A
 // (a sweep's held chains, queued before its FP32 forward pass and re-filtered beside the FP32
 // passes), [4] slots taken by phase A, [5] entries of the dense list of representative pairs
-// (k_dedup), [6] entries of phase A's dense list of representatives (k_rescue_held), then per
-// chain: blocks queued by the kernels in this pass
+// (k_dedup), [6] entries of phase A's dense list of representatives (k_rescue_held), [7] entries
+// of the dense list of the padded lattices' representatives (k_dedup), then per chain: blocks queued by the kernels in this pass
 // (kRescueChain + c), forward passes left on FP64 (kRescueChain + n_chains + c), 1 if the chain
 // is in phase A (kRescueChain + 2 n_chains + c), the forward recursions its blocks need in this
 // pass (kRescueChain + 3 n_chains + c: the representatives of the shared filters), the hold at
@@ -241,6 +242,7 @@ struct Device {
     GroupTask* group_tasks = nullptr;
     PairTask* fwd32_tasks = nullptr;    // MFMA forward: worldline pairs of L = 32 chains
     PairTask* fwd32c_tasks = nullptr;   // the dense representative pairs k_dedup lists (as many)
+    DrawTask* fwdxc_tasks = nullptr;    // the same for the padded lattices' single worldlines
     DrawTask* fwdx_tasks = nullptr;     // MFMA forward: single worldlines of 16 < L < 32 chains
     PackTask* fwdp_tasks = nullptr;
     DrawTask* fwd64_tasks = nullptr;    // MFMA forward: single worldlines of L = 64 chains     // MFMA forward, packed: P = 2 tasks, then P = 4 tasks

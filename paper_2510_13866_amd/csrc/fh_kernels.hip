@@ -1724,7 +1724,8 @@ __global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict_
                                                     const int32_t* __restrict__ paths,
                                                     const uint64_t* __restrict__ sweep_ptr,
                                                     int32_t* __restrict__ rep, const Rescue rsc,
-                                                    PairTask* __restrict__ cpairs) {
+                                                    PairTask* __restrict__ cpairs,
+                                                    DrawTask* __restrict__ csingles) {
     __shared__ int32_t first[kDedupMaxN];
     __shared__ int32_t rlist[kDedupMaxN];
     __shared__ int32_t n_rep, c_base;
@@ -1756,7 +1757,10 @@ __global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict_
     __syncthreads();
     // the chain's forward recursions in this pass (the FP64 re-filter's phase A sizes by them)
     if (threadIdx.x == 0) atomicAdd(&rsc.words[kRescueChain + 3 * rsc.n_chains + t.chain], n_rep);
-    if (!cpairs || c.dedup != 1 || rescue_held(rsc, t.chain)) return;  // whole workgroup
+    // the 32 x 32 chains' representatives go to cpairs, two to a task; the padded lattices'
+    // (16 < L < 32, one worldline to a wavefront) to csingles (count in words[7])
+    const bool pairs = c.L == 32;
+    if (c.dedup != 1 || (pairs ? !cpairs : !csingles) || rescue_held(rsc, t.chain)) return;
     // the representatives in worldline order (first wavefront), then their pairs
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
@@ -1772,13 +1776,19 @@ __global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict_
             if (is_rep) rlist[cnt + __popcll(m & ((1ull << lane) - 1))] = q;
             cnt += __popcll(m);
         }
-        if (lane == 0) c_base = atomicAdd(&rsc.words[5], (cnt + 1) / 2);
+        if (lane == 0) c_base = pairs ? atomicAdd(&rsc.words[5], (cnt + 1) / 2)
+                                      : atomicAdd(&rsc.words[7], cnt);
     }
     __syncthreads();
-    const int npairs = (n_rep + 1) / 2;
-    for (int i = threadIdx.x; i < npairs; i += blockDim.x)
-        cpairs[c_base + i] =
-            PairTask{t.chain, rlist[2 * i], 2 * i + 1 < n_rep ? rlist[2 * i + 1] : -1, t.block};
+    if (pairs) {
+        const int npairs = (n_rep + 1) / 2;
+        for (int i = threadIdx.x; i < npairs; i += blockDim.x)
+            cpairs[c_base + i] = PairTask{t.chain, rlist[2 * i],
+                                          2 * i + 1 < n_rep ? rlist[2 * i + 1] : -1, t.block};
+    } else {
+        for (int i = threadIdx.x; i < n_rep; i += blockDim.x)
+            csingles[c_base + i] = DrawTask{t.chain, rlist[i], t.block, 0};
+    }
 }
 
 // After the FP32 forward pass, one thread per (chain, particle, block) of the chains with dedup:
@@ -1827,6 +1837,7 @@ __global__ void k_rescue_reset(const Rescue rsc, int64_t n_flags) {
         rsc.words[4] = 0;
         rsc.words[5] = 0;
         rsc.words[6] = 0;
+        rsc.words[7] = 0;
     }
     const int n = rsc.n_chains;
     for (int64_t k = i; k < n; k += stride) {
@@ -2761,7 +2772,7 @@ hipError_t launch_dedup(fh_plan p, const int32_t* paths, hipStream_t s) {
     if (p->n_dedup_tasks == 0 || p->share_off) return hipSuccess;
     hipLaunchKernelGGL(k_dedup, dim3((unsigned)p->n_dedup_tasks), dim3(kThreads), 0, s,
                        p->d.chains, p->d.dedup_tasks, paths, p->d.sweep, p->d.rep, rescue_args(p),
-                       p->d.fwd32c_tasks);
+                       p->d.fwd32c_tasks, p->d.fwdxc_tasks);
     return hipGetLastError();
 }
 

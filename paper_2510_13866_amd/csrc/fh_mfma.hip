@@ -153,16 +153,25 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
     double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    const Rescue rsc, const NegPairs neg) {
+    const Rescue rsc, const NegPairs neg, double* __restrict__ blk_la,
+    float* __restrict__ endrow, const DrawTask* __restrict__ ctasks,
+    const int32_t* __restrict__ ccount) {
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
-    if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
-    const DrawTask t = tasks[task];
+    // with the dense list of representatives (k_dedup), wavefront i takes its entry i
+    if (task >= (ccount ? *ccount : n_tasks)) return;  // whole wavefront; no barriers here
+    const DrawTask t = ccount ? ctasks[task] : tasks[task];
     if (rescue_held(rsc, t.chain)) return;  // re-filtered whole in FP64 this pass
     const ChainInfo& c = chains[t.chain];
+    // shared forward filters: only representatives run the recursion
+    if (c.dedup && row_owner(rsc, c, t.p, t.block) != t.p) return;
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
     const int L = LFIX ? LFIX : c.L, N = LFIX ? LFIX * LFIX : c.N, L_tau = c.L_tau;
+    // a chain with few representatives keeps its rows in the cache for the members that read
+    // them next (as in k_forward_mfma2)
+    const int n_rep = c.dedup ? rsc.words[kRescueChain + 3 * rsc.n_chains + t.chain] : 0;
+    const bool cached = n_rep > 0 && (int64_t)n_rep * (c.B - 1) * N * 4 <= kCachedRowBytes;
     const int spin = t.p >= c.n_up ? 1 : 0;
     const float* Wsp = W + spin * aux_elems + c.aux_off;
     const double* shift = wshift + spin * total_slices + c.slice_off;
@@ -245,7 +254,12 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             F[v] *= k;
-            if (inside(v)) __builtin_nontemporal_store(F[v], row + vrow(v) * L);
+            if (inside(v)) {
+                if (cached)
+                    row[vrow(v) * L] = F[v];
+                else
+                    __builtin_nontemporal_store(F[v], row + vrow(v) * L);
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
         load_w((l + 1) % L_tau, wf);  // the last step fetches a slice it does not use
@@ -276,6 +290,13 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     if (lane == 0) {
         if (low || !(hv >= kRangeFloor)) rescue_push(rsc, c, t.chain, t.p, t.block);
         blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log((double)hv);
+    }
+    if (c.dedup) {  // what the worldlines sharing these rows need: log Z so far, the end tile
+        if (lane == 0) blk_la[c.blk_off + (int64_t)t.p * c.nb + t.block] = la;
+        float* end = endrow + c.end_off + ((int64_t)t.p * c.nb + t.block) * N + lane_off;
+#pragma unroll
+        for (int v = 0; v < 16; ++v)
+            if (inside(v)) end[vrow(v) * L] = H[v];
     }
 }
 
@@ -1646,7 +1667,8 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
                            p->d.fwdx_tasks, p->n_fwdx_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
-                           rescue_args(p), kNegPairs);
+                           rescue_args(p), kNegPairs, p->d.blk_la, p->d.endrow, p->d.fwdxc_tasks,
+                           p->d.fwdxc_tasks && !p->share_off ? p->d.rescue + 7 : nullptr);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
