@@ -13,8 +13,8 @@ include the transitional ones, whose out-of-range blocks the FP32 plan re-filter
 then the settled state; `per_sweep_ms` gives both parts, and the same chain is also run at
 U = 2 and U = 6.
 
-Prints one JSON line. `roofline` is for the dominant kernel (the forward filter), timed with HIP
-events on the stream it runs on; `cpu_baseline` times the FP64 oracle on host cores on a
+Prints one JSON line. `roofline` is for the dominant kernel (the longer of the forward filter and
+the backward sampler per sweep), timed with HIP events on the stream it runs on; `cpu_baseline` times the FP64 oracle on host cores on a
 bounded sample (one chain, six sweeps) and scales it to the same unit. `err_vs_fp64_plain`
 compares the FP32 plan's log Z and filters with the FP64 plain path's on the same GPU and the
 same states (the initial one and a transitional one).
