@@ -1865,34 +1865,77 @@ __global__ void k_rescue_reset(const Rescue rsc, int64_t n_flags) {
 
 // After k_rescue_reset and k_dedup, before a sweep's FP32 forward pass, one workgroup: every
 // block of each chain held on the FP64 re-filter (fp64_circulant) is queued, in chain order, as
-// phase A,
-// and the chain is marked, while the chains' forward recursions (their representatives) fit the
-// n_slots slots; the FP32 kernels skip held chains and phase A re-filters them beside the FP32
-// passes (a held chain left out is queued whole after the forward pass, for phase 2). The queue
-// is empty before this kernel, so the entries are laid down in place.
+// phase A, and the chain is marked, while the running total of the held chains' forward
+// recursions (their representatives) fits the n_slots slots; the FP32 kernels skip held chains
+// and phase A re-filters them beside the FP32 passes (a held chain left out is queued whole after
+// the forward pass, for phase 2). The queue is empty before this kernel, so the entries are laid
+// down in place. Phase A also gets the dense list of its representatives, arep.
 __global__ __launch_bounds__(kThreads) void k_rescue_held(const ChainInfo* __restrict__ chains,
                                                           const Rescue rsc, int n_slots,
                                                           int shared, DrawTask* __restrict__ arep) {
+    // one thread per chain, kThreads chains at a time: block-wide inclusive scans of the held
+    // chains' recursions (admission: the running total fits the slots) and of the admitted
+    // chains' blocks (their place in the queue)
+    __shared__ int scan_rec[kThreads], scan_blk[kThreads], adm_share[kThreads];
+    const int tid = threadIdx.x, n = rsc.n_chains;
     int off = 0, slots = 0;
-    for (int ci = 0; ci < rsc.n_chains; ++ci) {
-        const ChainInfo& c = chains[ci];
-        if (!fp64_circulant(c.L) || !rescue_held(rsc, ci)) continue;
-        const int nblk = c.np * c.nb;
-        const bool share = shared && c.dedup;
-        const int nrec = share ? rsc.words[kRescueChain + 3 * rsc.n_chains + ci] : nblk;
-        if (slots + nrec > n_slots) continue;
-        slots += nrec;
-        for (int i = threadIdx.x; i < nblk; i += blockDim.x) {  // i = p nb + block
-            rsc.flags[c.blk_off + i] = 1;
-            rsc.list[off + i] = DrawTask{ci, i / c.nb, i % c.nb, 0};
-            // the representatives, in no particular order (at most n_slots of them)
-            if (!share || rsc.rep[c.blk_off + i] == i / c.nb)
-                arep[atomicAdd(&rsc.words[6], 1)] = DrawTask{ci, i / c.nb, i % c.nb, 0};
+    for (int c0 = 0; c0 < n; c0 += kThreads) {
+        const int ci = c0 + tid;
+        bool held = false;
+        int nblk = 0, nrec = 0;
+        bool share = false;
+        if (ci < n) {
+            const ChainInfo& c = chains[ci];
+            held = fp64_circulant(c.L) && rescue_held(rsc, ci);
+            nblk = c.np * c.nb;
+            share = shared && c.dedup;
+            nrec = held ? (share ? rsc.words[kRescueChain + 3 * n + ci] : nblk) : 0;
         }
-        if (threadIdx.x == 0) rsc.words[kRescueChain + 2 * rsc.n_chains + ci] = 1;
-        off += nblk;
+        scan_rec[tid] = nrec;
+        __syncthreads();
+        for (int d = 1; d < kThreads; d <<= 1) {  // inclusive scan of the recursions
+            const int v = tid >= d ? scan_rec[tid - d] : 0;
+            __syncthreads();
+            scan_rec[tid] += v;
+            __syncthreads();
+        }
+        const bool admit = held && slots + scan_rec[tid] <= n_slots;
+        scan_blk[tid] = admit ? nblk : 0;
+        adm_share[tid] = admit ? (share ? 2 : 1) : 0;
+        __syncthreads();
+        for (int d = 1; d < kThreads; d <<= 1) {  // inclusive scan of the admitted blocks
+            const int v = tid >= d ? scan_blk[tid - d] : 0;
+            __syncthreads();
+            scan_blk[tid] += v;
+            __syncthreads();
+        }
+        if (admit) rsc.words[kRescueChain + 2 * n + ci] = 1;
+        // the admitted chains' blocks, one chain after another, by the whole workgroup
+        for (int k = 0; k < kThreads && c0 + k < n; ++k) {
+            if (!adm_share[k]) continue;
+            const int ck = c0 + k;
+            const ChainInfo& c = chains[ck];
+            const int nb_k = c.np * c.nb, base = off + scan_blk[k] - nb_k;
+            for (int i = tid; i < nb_k; i += kThreads) {  // i = p nb + block
+                rsc.flags[c.blk_off + i] = 1;
+                rsc.list[base + i] = DrawTask{ck, i / c.nb, i % c.nb, 0};
+                // the representatives, in no particular order (at most n_slots of them)
+                if (adm_share[k] == 1 || rsc.rep[c.blk_off + i] == i / c.nb)
+                    arep[atomicAdd(&rsc.words[6], 1)] = DrawTask{ck, i / c.nb, i % c.nb, 0};
+            }
+        }
+        // the chunk's admitted recursions: the admitted chains are the held ones up to the last
+        // admitted, whose inclusive scan is their total
+        __shared__ int adm_rec;
+        if (tid == 0) adm_rec = 0;
+        __syncthreads();
+        if (admit) atomicMax(&adm_rec, scan_rec[tid]);
+        __syncthreads();
+        slots += adm_rec;
+        off += scan_blk[kThreads - 1];
+        __syncthreads();  // the scans' storage and adm_rec are reused by the next chunk
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         rsc.words[0] = off;
         rsc.words[3] = off;
     }
