@@ -506,6 +506,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
                 p->rescue_slot_elems = std::max(p->rescue_slot_elems, (int64_t)ci.B * ci.N);
                 rescuable += (int64_t)ci.np * ci.nb;
             }
+        p->rescuable_blocks = rescuable;
         const int64_t waves = std::min<int64_t>(kRescueMaxSlots, std::max<int64_t>(rescuable, 1));
         p->n_rescue_slots = (int32_t)((waves + 3) / 4 * 4);
         p->rescue_slot_elems = std::max<int64_t>(p->rescue_slot_elems, 1);

@@ -170,6 +170,16 @@ constexpr int64_t kCachedRowBytes = 16ll << 20;
 // flags, the queue, and the representative map of the shared forward filters (rep, per
 // (chain, particle, block) at blk_off + p nb + b: the worldline whose stored rows the block's
 // draws read; null where no chain shares, and on FP64 plans).
+// Phase A's FP64 rows as the windowed backward kernel reads them when it draws the held chains'
+// blocks (k_backward_win with SLOT): the slot of each representative's block, the slots, and the
+// log Z pieces of the worldlines that share a representative's rows.
+struct SlotRows {
+    const int32_t* rep_slot;
+    const double* ws;
+    int64_t slot_elems;
+    double* blk_logz;
+    const double* blk_la;
+};
 struct Rescue {
     int32_t* words;   // null for FP64 plans
     int32_t* flags;   // words + kRescueChain + kRescuePerChain n_chains
@@ -309,6 +319,7 @@ struct fh_plan_s {
     int64_t gpart_elems = 0;
     int64_t ckpt_elems = 0;     // FH_FLAG_GRAD_CHECKPOINT: checkpoint + segment rows (elements)
     int32_t n_rescue_slots = 0;     // FP32 plans: wavefronts of k_rescue
+    int64_t rescuable_blocks = 0;   // FP32 plans: blocks of the chains the FP64 re-filter takes
     int32_t n_dedup_tasks = 0;      // (chain, spin, block) tasks of k_dedup (chains with dedup)
     bool share_off = false;         // fh_debug_share_filters(plan, 0): every worldline its own rows
     int64_t end_elems = 0;          // end tiles of the chains with dedup (f32 elements)

@@ -1032,12 +1032,18 @@ __device__ int wave_window_draw(const T* __restrict__ row, int L, int cx, int cy
 // Lane li of a group computes
 // the Philox uniform of draw s0 + li once per 16 draws. Every load address is in bounds for any
 // lane (inactive groups read chain 0's first row), so loads are unconditional and values masked.
-template <typename T>
+// SLOT (T = double): the draws of phase A of the FP64 re-filter, the held chains' blocks in the
+// queue's phase A part, from their representatives' FP64 rows in the re-filter's slots (windowed
+// chains; k_rescue_share_draw takes the others). The rule is the FP64 plans', so the sites equal
+// those of k_rescue's draws; a worldline that shares its representative's rows also gets its
+// log Z from the representative's end tile.
+template <typename T, bool SLOT = false>
 __global__ __launch_bounds__(kThreads) void k_backward_win(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const double* __restrict__ tables, const T* __restrict__ filt, int32_t* __restrict__ paths,
     const int32_t* __restrict__ perm, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    int32_t* __restrict__ bw_state, int count_uncertified, const Rescue rsc) {
+    int32_t* __restrict__ bw_state, int count_uncertified, const Rescue rsc, const SlotRows sr) {
+    static_assert(!SLOT || sizeof(T) == 8, "phase A's rows are FP64");
     constexpr int G = kThreads / kWinLanes;
     constexpr int K = kWinPerLane;
     // g(d) for d in (-L, L): gsh[grp][kWinMaxL + d], so a signed offset indexes it directly
@@ -1047,11 +1053,12 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     const int gbase = lane64 - li;  // the group's first lane in the wavefront
     const int task = blockIdx.x * G + grp;
     // while the plan is on the full-row kernels, they draw these tasks
-    const bool listed = task < n_tasks && bw_state[0] == 0;
-    const DrawTask t = listed ? tasks[task] : DrawTask{0, 0, 0, 0};
+    const bool listed = SLOT ? task < rsc.words[3] : task < n_tasks && bw_state[0] == 0;
+    const DrawTask t = listed ? (SLOT ? rsc.list[task] : tasks[task]) : DrawTask{0, 0, 0, 0};
     const ChainInfo& c = chains[t.chain];
-    // a block queued for the FP64 re-filter is drawn by k_rescue
-    const bool active = listed && !rescue_queued(rsc, c, t.p, t.block);
+    // a block queued for the FP64 re-filter is drawn by k_rescue (SLOT: by this kernel when its
+    // chain is windowed)
+    const bool active = SLOT ? listed && c.win_on : listed && !rescue_queued(rsc, c, t.p, t.block);
     // an inactive group draws nothing; on a one-site lattice its table fill and loads stay minimal
     const int L = active ? c.L : 1, N = active ? c.N : 1, L_tau = c.L_tau, w = c.win_w;
     double* g = gsh[grp] + kWinMaxL;  // g[d] = g(d mod L) for -L < d < L
@@ -1086,9 +1093,16 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         qx[k] = qv[k] ? q - qy[k] * WW : 0;
     }
     const int ro = row_owner(rsc, c, t.p, t.block);  // shared forward filters
-    const T* rows = filt + c.filt_off + ((int64_t)ro * L_tau + (int64_t)t.block * (c.B - 1)) * N;
-    // the outside bound scales with the row mass (2^row_exp on FP32 plans)
-    const double gout = c.win_gout * c.row_mass * kWinMassBound;
+    const int64_t ri = c.blk_off + (int64_t)ro * c.nb + t.block;
+    const T* rows;
+    if constexpr (SLOT)  // the representative's slot (inactive groups read slot 0)
+        rows = (const T*)(sr.ws + (active ? (int64_t)sr.rep_slot[ri] * sr.slot_elems : 0));
+    else
+        rows = filt + c.filt_off + ((int64_t)ro * L_tau + (int64_t)t.block * (c.B - 1)) * N;
+    // the outside bound scales with the row mass (2^row_exp on FP32 plans; phase A's FP64 rows
+    // are normalised)
+    const double mass = SLOT ? 1.0 : c.row_mass;
+    const double gout = c.win_gout * mass * kWinMassBound;
     double ureg = 0.0;
     int err = 0;  // the first error of the block, reported once after the loop
     int n_unc = 0;  // draws the first window did not certify (kept by lane 0 of the group)
@@ -1183,7 +1197,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         const bool cert = gm != 0 && (packed >> 16) != 0;
         // FP32 plans: a site drawn from a filter value below kRangeFloor is redrawn in FP64
         const double fpick = __shfl(fp, gbase + src, 64);
-        if (rsc.words && real && cert && !(fpick >= kRangeFloorD)) halt = true;
+        if (!SLOT && rsc.words && real && cert && !(fpick >= kRangeFloorD)) halt = true;
         int nx = packed & 255, ny = (packed >> 8) & 255;
         bool need_row = false;
         n_unc += (real && !cert) ? 1 : 0;
@@ -1202,12 +1216,12 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
                 rowg, __builtin_amdgcn_readlane(L, g0), __builtin_amdgcn_readlane(cx, g0),
                 __builtin_amdgcn_readlane(cy, g0), kWin2W,
                 gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)] + kWinMaxL, readlane_f64(u, g0),
-                readlane_f64(c.win_gout2 * c.row_mass * kWinMassBound, g0), lane64, &f2);
+                readlane_f64(c.win_gout2 * mass * kWinMassBound, g0), lane64, &f2);
             if ((lane64 >> 4) == (g0 >> 4)) {
                 if (p2 >> 16) {
                     nx = p2 & 255;
                     ny = (p2 >> 8) & 255;
-                    if (rsc.words && !(f2 >= kRangeFloorD)) halt = true;
+                    if (!SLOT && rsc.words && !(f2 >= kRangeFloorD)) halt = true;
                 } else {
                     need_row = true;
                 }
@@ -1228,7 +1242,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
                 rowg, __builtin_amdgcn_readlane(N, g0), Lg, __builtin_amdgcn_readlane(cx, g0),
                 __builtin_amdgcn_readlane(cy, g0), gsh[(threadIdx.x >> 6) * 4 + (g0 >> 4)] + kWinMaxL,
                 readlane_f64(u, g0), __builtin_amdgcn_readlane(cur, g0), lane64, &bad,
-                rsc.words != nullptr);
+                !SLOT && rsc.words != nullptr);
             if ((lane64 >> 4) == (g0 >> 4)) {
                 nx = chosen % Lg;
                 ny = chosen / Lg;
@@ -1250,6 +1264,15 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
     if (err != 0 && li == 0) set_status(status, err, t.chain);  // the block's first error
     if (count_uncertified && active && li == 0 && n_unc > 0)
         atomicAdd(&bw_state[kBwCounts + t.chain], n_unc);
+    if constexpr (SLOT) {  // a worldline sharing its representative's rows: its own end weight
+        if (active && li == 0 && ro != t.p) {
+            const int e = checked_site(pc[(int64_t)((start + len) % L_tau) * c.np +
+                                          (start + len >= L_tau ? qn : t.p)], N, status, t.chain);
+            const double hv = (double)rows[(int64_t)(c.B - 1) * N + e];  // the end tile
+            if (!(hv > 0.0)) set_status(status, FH_ERR_NONFINITE, t.chain);
+            sr.blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = sr.blk_la[ri] + log(hv);
+        }
+    }
 }
 
 // The draws of one re-filtered block from its FP64 rows, by the whole wavefront: the rule of
@@ -1690,6 +1713,7 @@ __global__ __launch_bounds__(kThreads, kShareDrawWaves) void k_rescue_share_draw
     for (int i = wid; i < hi; i += n_waves) {
         const DrawTask t = rsc.list[i];
         const ChainInfo& c = chains[t.chain];
+        if (c.win_on) continue;  // the windowed kernel draws it (k_backward_win with SLOT)
         const int ro = c.dedup ? row_owner(rsc, c, t.p, t.block) : t.p;
         const int64_t ri = c.blk_off + (int64_t)ro * c.nb + t.block;
         const double* slot = ws + (int64_t)rep_slot[ri] * slot_elems;
@@ -2748,12 +2772,12 @@ hipError_t launch_backward_kernels(fh_plan p, int32_t* paths, hipStream_t s) {
             hipLaunchKernelGGL(k_backward_win<double>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draww_tasks, p->n_draww_tasks, p->d.tables,
                                (const double*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state,
-                               p->bw_adapt ? 1 : 0, rescue_args(p));
+                               p->bw_adapt ? 1 : 0, rescue_args(p), SlotRows{});
         else
             hipLaunchKernelGGL(k_backward_win<float>, dim3(blocks), dim3(kThreads), 0, s,
                                p->d.chains, p->d.draww_tasks, p->n_draww_tasks, p->d.tables,
                                (const float*)p->d.filt, paths, p->d.perm, p->d.sweep, p->d.status, p->d.bw_state,
-                               p->bw_adapt ? 1 : 0, rescue_args(p));
+                               p->bw_adapt ? 1 : 0, rescue_args(p), SlotRows{});
     }
     if (p->n_draw32_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_draw32_tasks + kWaves - 1) / kWaves);
@@ -2873,7 +2897,15 @@ hipError_t launch_rescue(fh_plan p, const void* aux, int32_t* paths, bool draw, 
         };
         if (p->rescue_l64) fwd(k_rescue_share_fwd<4>);
         if (p->rescue_l48) fwd(k_rescue_share_fwd<3>);
-        // the draws take no slot: twice the slot count of wavefronts, four per SIMD
+        // the draws: windowed chains four blocks to a wavefront from the slots' FP64 rows, the
+        // others one block to a wavefront (they take no slot: twice the slot count of them)
+        const unsigned wblocks = (unsigned)((p->rescuable_blocks + kThreads / kWinLanes - 1) /
+                                            (kThreads / kWinLanes));
+        hipLaunchKernelGGL((k_backward_win<double, true>), dim3(wblocks), dim3(kThreads), 0, s,
+                           p->d.chains, nullptr, 0, p->d.tables, nullptr, paths, p->d.perm,
+                           p->d.sweep, p->d.status, p->d.bw_state, 0, rescue_args(p),
+                           SlotRows{p->d.rep_slot, p->d.rescue_ws, p->rescue_slot_elems,
+                                    p->d.blk_logz, p->d.blk_la});
         const int draw_waves = 2 * p->n_rescue_slots;
         hipLaunchKernelGGL(k_rescue_share_draw, dim3((unsigned)(draw_waves / kWaves)),
                            dim3(kThreads), 0, s, p->d.chains, p->d.tables, paths, p->d.perm,
