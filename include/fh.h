@@ -69,7 +69,8 @@ enum fh_precision {
     FH_FP32 = 1,      /* FP32 FFT convolution and filters; FP64 normaliser and CDF            */
     FH_FP32_MFMA3 = 2 /* FP32 filters, convolution as the separable real circulant on MFMA
                          with three-term split-bf16 products; FP64 normaliser and CDF;
-                         L <= 32 or L = 64 (fh_logZ_grad and fh_mala_field: L <= 32)          */
+                         32 < L < 64 zero-padded to 64 (fh_logZ_grad and fh_mala_field:
+                         L <= 32)                                                             */
 };
 /* Range of the FP32 plans. A filter row is normalised to sum 1; FP32 holds its values to full
  * relative precision only down to ~2^-110 (bf16 splitting) or ~2^-126. Strong, clustered fields
@@ -82,8 +83,9 @@ enum fh_precision {
  * queued blocks in FP64: the forward recursion on the FP64 circulant with W computed in FP64 from
  * the field (its log Z replaces the FP32 one, its rows rounded to FP32 replace the stored rows),
  * and, in fh_backward_sample and fh_sweep, the block's draws from the FP64 rows with the same
- * rule and uniforms as an FH_FP64 plan. Only chains with L <= 32 have this FP64 re-filter; a
- * queued block of a larger lattice latches FH_ERR_NONFINITE and keeps its sites. */
+ * rule and uniforms as an FH_FP64 plan. Only chains with L <= 32, L = 48 or L = 64 have this
+ * FP64 re-filter; a queued block of another lattice latches FH_ERR_NONFINITE and keeps its
+ * sites. */
 
 enum fh_flags {
     FH_FLAG_NONE = 0,
@@ -92,9 +94,9 @@ enum fh_flags {
                             the device (FFT precisions) and keeps the fastest; without it the
                             default order (4s, then a 2, then 3s) is used                    */
     FH_FLAG_FFT_CONV = 8, /* FH_FP64 plans convolve every chain with the FP64 FFT. Without it
-                            chains with L <= 32 use the circulant C f C on the FP64 matrix cores
-                            (every product positive, so filter tails keep their relative
-                            accuracy); larger L always use the FFT                             */
+                            chains with L <= 32, 48 or 64 use the circulant C f C on the FP64
+                            matrix cores (every product positive, so filter tails keep their
+                            relative accuracy); other L > 32 always use the FFT                */
     FH_FLAG_FULL_ROW_DRAW = 4, /* backward draws scan every site of the filter row. Without it a
                             chain whose hopping kernel decays fast enough draws from the window
                             of sites within w <= 3 steps of the next slice's site and certifies
@@ -119,7 +121,7 @@ enum fh_flags {
 /* One chain. block_len: FFBS block length B (0 = L_tau, one block closing the ring);
  * blocks of a sweep s start at o_s + j*B (mod L_tau), o_s = (s*floor(B/2)) mod L_tau,
  * the last one shorter when B does not divide L_tau; endpoints stay fixed within a sweep.
- * Requirements: L in {2..64} with L = 2^a 3^b (L <= 32 or L = 64 for FH_FP32_MFMA3), L_tau >= 2,
+ * Requirements: L in {2..64} with L = 2^a 3^b, L_tau >= 2,
  * n_up, n_dn >= 0 with n_up + n_dn >= 1, block_len = 0 or 2 <= block_len <= L_tau,
  * t > 0, dtau > 0, U finite (U >= 0 for FH_HS_HIRSCH), all finite. */
 typedef struct {

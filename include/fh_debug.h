@@ -123,8 +123,10 @@ int fh_debug_sweep_times(fh_plan plan, float* ms);
 
 /* Forward work items of an FH_FP32_MFMA3 plan, by kernel: counts[0] worldline pairs of L = 32
  * chains, counts[1] single padded worldlines (16 < L < 32), counts[2] packed tasks of 2 x 2
- * worldlines per tile (8 < L <= 16), counts[3] packed tasks of 4 x 4 (L <= 8). counts holds 4
- * int32 written by the call (caller-owned host memory). */
+ * worldlines per tile (8 < L <= 16), counts[3] packed tasks of 4 x 4 (L <= 8), counts[4] single
+ * worldlines of L = 64 chains on four 32 x 32 sub-tiles, counts[5] single worldlines of
+ * 32 < L < 64 chains on the same sub-tiles, zero-padded. counts holds 6 int32 written by the
+ * call (caller-owned host memory). */
 int fh_debug_forward_kernels(fh_plan plan, int32_t* counts);
 
 #ifdef __cplusplus

@@ -130,15 +130,15 @@ void build_cmat(int L, const double* g, uint16_t* out, int bs = 32) {
             }
 }
 
-// The two distinct 32 x 32 blocks of the L = 64 circulant g((i - j) mod 64), in the operand
-// layout of build_cmat: blk 0 is C_00 = C_11, blk 1 is C_01 = C_10 (columns shifted by 32).
-void build_cmat_block64(const double* g, int blk, uint16_t* out) {
+// A 32 x 32 block C_KJ (rows 32 K .., columns 32 J ..) of the circulant g((i - j) mod L) of a
+// lattice with 32 < L <= 64, zero-padded to 64 x 64, in the operand layout of build_cmat.
+void build_cmat_block(int L, const double* g, int K, int J, uint16_t* out) {
     for (int q = 0; q < 2; ++q)
         for (int lane = 0; lane < 64; ++lane)
             for (int e = 0; e < 8; ++e) {
-                const int R = 16 * q + 8 * (e / 4) + 4 * (lane / 32) + e % 4;
-                const int n = lane % 32 + 32 * blk;
-                const double v = g[((R - n) % 64 + 64) % 64];
+                const int R = 32 * K + 16 * q + 8 * (e / 4) + 4 * (lane / 32) + e % 4;
+                const int n = 32 * J + lane % 32;
+                const double v = (R < L && n < L) ? g[((R - n) % L + L) % L] : 0.0;
                 const uint16_t h = bf16_rne((float)v);
                 const double r1 = v - bf16_val(h);
                 const uint16_t m = bf16_rne((float)r1);
@@ -147,6 +147,15 @@ void build_cmat_block64(const double* g, int blk, uint16_t* out) {
                 const uint16_t terms[3] = {h, m, l};
                 for (int t = 0; t < 3; ++t) out[((t * 2 + q) * 64 + lane) * 8 + e] = terms[t];
             }
+}
+
+// The operand blocks of a chain with 32 < L <= 64 (kCmatPerChain values each, four per chain):
+// L = 64 has two distinct blocks, C_00 = C_11 and C_01 = C_10 (-32 = 32 mod 64); a padded
+// lattice has four, C_KJ at 2 K + J.
+void build_cmat_blocks(int L, const double* g, uint16_t* out) {
+    if (L <= 32 || L > 64) return;
+    for (int b = 0; b < (L == 64 ? 2 : 4); ++b)
+        build_cmat_block(L, g, b >> 1, b & 1, out + (size_t)kCmatPerChain * b);
 }
 
 bool is_fin(double v) { return std::isfinite(v); }
@@ -164,7 +173,6 @@ int validate(const fh_chain_desc& d, int precision) {
         return FH_ERR_INVALID_ARG;
     if (d.hs_kind == FH_HS_HIRSCH && d.U < 0) return FH_ERR_INVALID_ARG;
     if (!default_radix_plan(d.L, &rp)) return FH_ERR_UNSUPPORTED;
-    if (precision == FH_FP32_MFMA3 && d.L > 32 && d.L != 64) return FH_ERR_UNSUPPORTED;
     return FH_OK;
 }
 
@@ -324,7 +332,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->tables.assign(tab, 0.0);
     p->cmat.assign((size_t)kCmatPerChain * n_chains, 0);
     p->cmatp.assign((size_t)kCmatPerChain * n_chains, 0);
-    p->cmatb.assign((size_t)2 * kCmatPerChain * n_chains, 0);
+    p->cmatb.assign((size_t)4 * kCmatPerChain * n_chains, 0);
     p->cmat64.assign((size_t)kCmat64PerChain * n_chains, 0.0);
     std::vector<char> windowed((size_t)n_chains, 0);
     for (int c = 0; c < n_chains; ++c) {
@@ -334,10 +342,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         if (ci.L <= kPackMaxL)
             build_cmat(ci.L, p->tables.data() + tab_g(ci), p->cmatp.data() + (size_t)kCmatPerChain * c,
                        32 / pack_blocks(ci.L));
-        if (ci.L == 64)
-            for (int b = 0; b < 2; ++b)
-                build_cmat_block64(p->tables.data() + tab_g(ci),
-                                   b, p->cmatb.data() + (size_t)kCmatPerChain * (2 * c + b));
+        build_cmat_blocks(ci.L, p->tables.data() + tab_g(ci),
+                          p->cmatb.data() + (size_t)4 * kCmatPerChain * c);
         build_cmat64(descs[c].L, p->tables.data() + tab_g(ci),
                      p->cmat64.data() + (size_t)kCmat64PerChain * c);
         windowed[c] = win_select(p->tables.data() + tab_g(ci), ci.L, &ci.win_w, &ci.win_gout) &&
@@ -447,7 +453,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     std::vector<PairTask> fwd32;
     std::vector<DrawTask> fwdx, draw32, draww, drawx;
     std::vector<PackTask> fwdp2, fwdp4;
-    std::vector<DrawTask> fwd64;
+    std::vector<DrawTask> fwd64, fwd64p;
     // small lattices whose filter region (FP32) fits the packed kernel's 31-bit byte offsets
     auto packed = [&](int c) {
         const ChainInfo& ci = p->chains[c];
@@ -470,6 +476,7 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     // per sweep, bw_state decides which of the two kernels draws them (the other skips them).
     for (const DrawTask& t : draw) {
         if (p->chains[t.chain].L == 64) fwd64.push_back(t);
+        else if (p->chains[t.chain].L > 32 && precision == FH_FP32_MFMA3) fwd64p.push_back(t);
         else if (p->chains[t.chain].L != 32 && !packed(t.chain) && p->chains[t.chain].L <= 32)
             fwdx.push_back(t);
         if (windowed[t.chain]) draww.push_back(t);
@@ -485,6 +492,8 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     p->n_fwdx_tasks = (int32_t)fwdx.size();
     p->n_fwdp2_tasks = (int32_t)fwdp2.size();
     p->n_fwd64_tasks = (int32_t)fwd64.size();
+    p->n_fwd64p_tasks = (int32_t)fwd64p.size();
+    fwd64.insert(fwd64.end(), fwd64p.begin(), fwd64p.end());  // the padded tasks follow
     p->n_fwdp4_tasks = (int32_t)fwdp4.size();
     std::vector<PackTask> fwdp(fwdp2);
     fwdp.insert(fwdp.end(), fwdp4.begin(), fwdp4.end());
@@ -1035,10 +1044,8 @@ int fh_set_hopping(fh_plan p, const double* t) {
         if (ci.L <= kPackMaxL)
             build_cmat(ci.L, p->tables.data() + tab_g(ci), p->cmatp.data() + (size_t)kCmatPerChain * c,
                        32 / pack_blocks(ci.L));
-        if (ci.L == 64)
-            for (int b = 0; b < 2; ++b)
-                build_cmat_block64(p->tables.data() + tab_g(ci),
-                                   b, p->cmatb.data() + (size_t)kCmatPerChain * (2 * c + b));
+        build_cmat_blocks(ci.L, p->tables.data() + tab_g(ci),
+                          p->cmatb.data() + (size_t)4 * kCmatPerChain * c);
         build_cmat64(p->descs[c].L, p->tables.data() + tab_g(ci),
                      p->cmat64.data() + (size_t)kCmat64PerChain * c);
         // the window keeps its width; its outside bound follows the new kernel
@@ -1429,6 +1436,8 @@ int fh_debug_forward_kernels(fh_plan p, int32_t* counts) {
     counts[1] = p->n_fwdx_tasks;
     counts[2] = p->n_fwdp2_tasks;
     counts[3] = p->n_fwdp4_tasks;
+    counts[4] = p->n_fwd64_tasks;
+    counts[5] = p->n_fwd64p_tasks;
     return FH_OK;
 }
 

@@ -232,7 +232,7 @@ struct Device {
     double* tables = nullptr;
     uint16_t* cmat = nullptr;  // per chain: split-bf16 circulant operand [3][2][64][8]
     uint16_t* cmatp = nullptr; // per chain with L <= kPackMaxL: the block-diagonal operand, same layout
-    uint16_t* cmatb = nullptr; // per chain with L = 64: the blocks T0 = C_00 and T1 = C_01, same layout
+    uint16_t* cmatb = nullptr; // per chain with 32 < L <= 64: four blocks C_KJ (L = 64: C_00, C_01), same layout
     double* cmat64 = nullptr;  // per chain: FP64 circulant B operands [16][64]
     DrawTask* fwdd_tasks = nullptr;  // FP64 circulant forward: worldline blocks (L <= 32, 48, 64)
     void* W = nullptr;        // [2][sum L_tau*N] in plan precision (up, then down)
@@ -306,6 +306,7 @@ struct fh_plan_s {
     int32_t n_fwd32_tasks = 0, n_fwdx_tasks = 0, n_draw32_tasks = 0;
     int32_t n_fwdp2_tasks = 0, n_fwdp4_tasks = 0;
     int32_t n_fwd64_tasks = 0;
+    int32_t n_fwd64p_tasks = 0;  // 32 < L < 64 on FP32_MFMA3, after the L = 64 tasks in fwd64_tasks
     int32_t max_N_x = 0;  // largest N among the chains of drawx_tasks
     int32_t n_draww_tasks = 0, n_drawx_tasks = 0;
     int32_t n_fwdd_tasks = 0;  // FP64 circulant forward tasks (the FFT takes n_fwd_tasks pairs)

@@ -672,8 +672,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
 // distinct 32 x 32 blocks: C_00 = C_11 (T0) and C_01 = C_10 (T1, since -32 = 32 mod 64), so the
 // operand holds two split blocks. Same arithmetic per product as the 32 x 32 tile: every
 // product positive, FP32 accumulation, filters within the same bound.
+// PAD (32 < L < 64, zero-padded to 64): the four blocks C_KJ differ (T[2 K + J]), each the
+// circulant g((k - j) mod L) restricted to k, j < L.
+template <bool PAD>
 __device__ inline void circ64_step(const f32x16 (&X)[2][2], f32x16 (&Y)[2][2],
-                                   const Split3 (&T)[2], const NegPairs& n) {
+                                   const Split3 (&T)[PAD ? 4 : 2], const NegPairs& n) {
 #pragma unroll
     for (int I = 0; I < 2; ++I)
 #pragma unroll
@@ -688,7 +691,7 @@ __device__ inline void circ64_step(const f32x16 (&X)[2][2], f32x16 (&Y)[2][2],
                 split3_chunk(X[K][I], q, h, m, l, n);
 #pragma unroll
                 for (int J = 0; J < 2; ++J) {
-                    const Split3& C = T[K == J ? 0 : 1];
+                    const Split3& C = T[PAD ? 2 * K + J : (K == J ? 0 : 1)];
                     f32x16 acc = Y[I][J];
                     acc = mfma(l, C.h[q], acc);
                     acc = mfma(m, C.m[q], acc);
@@ -702,7 +705,10 @@ __device__ inline void circ64_step(const f32x16 (&X)[2][2], f32x16 (&Y)[2][2],
 }
 
 // The forward recursion of k_forward_mfma for L = 64 chains, one wavefront per (chain,
-// worldline, block); rows stored as 4096 FP32 values, log Z as in k_forward_mfma.
+// worldline, block); rows stored as 4096 FP32 values, log Z as in k_forward_mfma. PAD: the
+// chains with 32 < L < 64 on the same four sub-tiles, zero-padded to 64 x 64 (the padding stays
+// an exact zero: C is zero outside L x L), with the four distinct operand blocks.
+template <bool PAD>
 __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
     const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const uint16_t* __restrict__ cmatb, const float* __restrict__ aux, const float* __restrict__ W,
@@ -710,13 +716,15 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
     double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
     const Rescue rsc, const NegPairs neg) {
-    constexpr int L = 64, N = 4096;
+    constexpr int NB = PAD ? 4 : 2;  // operand blocks
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
     const DrawTask t = tasks[task];
-    if (rescue_held(rsc, t.chain)) return;  // re-filtered whole in FP64 this pass
     const ChainInfo& c = chains[t.chain];
+    // re-filtered whole in FP64 this pass (lattices with the FP64 circulant)
+    if ((!PAD || fp64_circulant(c.L)) && rescue_held(rsc, t.chain)) return;
+    const int L = PAD ? c.L : 64, N = PAD ? c.N : 4096;
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
     const int L_tau = c.L_tau;
@@ -733,10 +741,10 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
         a = (a < 0 || a >= N) ? 0 : a;
         e = (e < 0 || e >= N) ? 0 : e;
     }
-    Split3 T[2];
+    Split3 T[NB];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const uint4* cm = (const uint4*)(cmatb + ((size_t)t.chain * 2 + b) * 3 * 2 * 64 * 8);
+    for (int b = 0; b < NB; ++b) {
+        const uint4* cm = (const uint4*)(cmatb + ((size_t)t.chain * 4 + b) * 3 * 2 * 64 * 8);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             T[b].h[q] = __builtin_bit_cast(bf16x8, cm[(0 * 2 + q) * 64 + lane]);
@@ -749,14 +757,20 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
     // lane_off + 32 (R L + S) + vrow(v) L of a row
     const int lane_off = 4 * (lane >> 5) * L + x;
     auto vrow = [](int v) { return 8 * (v >> 2) + (v & 3); };
+    auto inside = [&](int R, int S, int v) {
+        return !PAD || (32 * S + x < L && 32 * R + 4 * (lane >> 5) + vrow(v) < L);
+    };
     auto load_w = [&](int l, float (&dst)[2][2][16]) {
-        const float* Wl = Wsp + (int64_t)l * N + lane_off;
+        const float* Wl = Wsp + (int64_t)l * N;
+        // a padded position reads the slice's first site and multiplies an exact zero
 #pragma unroll
         for (int R = 0; R < 2; ++R)
 #pragma unroll
             for (int S = 0; S < 2; ++S)
 #pragma unroll
-                for (int v = 0; v < 16; ++v) dst[R][S][v] = Wl[32 * (R * L + S) + vrow(v) * L];
+                for (int v = 0; v < 16; ++v)
+                    dst[R][S][v] =
+                        Wl[inside(R, S, v) ? lane_off + 32 * (R * L + S) + vrow(v) * L : 0];
     };
     // rows hold f~ 2^row_exp (the FP32 range scaling), from f_0 = 2^row_exp delta_a on
     const float sc = ldexpf(1.0f, c.row_exp);
@@ -777,15 +791,17 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
     double prod = 1.0;
     float* rows = filt + c.filt_off + ((int64_t)t.p * L_tau + (int64_t)t.block * (c.B - 1)) * N;
     // W of the next slice is loaded before this slice's stores (loads and stores retire in
-    // order), so its wait one step later does not wait for them
+    // order), so its wait one step later does not wait for them; the padded variant, whose four
+    // operand blocks take the registers of that prefetch, loads it between the two products
     float wn[2][2][16];
-    load_w((start + 1) % L_tau, wn);
+    if constexpr (!PAD) load_w((start + 1) % L_tau, wn);
     bool low = false;  // the block left FP32's range (the FP64 re-filter takes L <= 32 only)
     for (int j = 1; j < len; ++j) {
         const int l = (start + j) % L_tau;
         f32x16 X[2][2], H[2][2];
-        circ64_step(F, X, T, neg);
-        circ64_step(X, H, T, neg);
+        circ64_step<PAD>(F, X, T, neg);
+        if constexpr (PAD) load_w(l, wn);  // in flight during the second product
+        circ64_step<PAD>(X, H, T, neg);
         float s = 0.0f;
 #pragma unroll
         for (int R = 0; R < 2; ++R)
@@ -796,7 +812,7 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
                     F[R][S][v] = H[R][S][v] * wn[R][S][v];
                     s += F[R][S][v];
                 }
-        load_w((l + 1) % L_tau, wn);  // the last step fetches a slice it does not use
+        if constexpr (!PAD) load_w((l + 1) % L_tau, wn);  // the last step fetches a slice it does not use
         __builtin_amdgcn_sched_barrier(0);
         const float tot = wave_sum_f32(s);
         low |= !(tot >= step_floor) | !isfinite(tot);
@@ -816,14 +832,15 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
                     F[R][S][v] *= k;
-                    __builtin_nontemporal_store(F[R][S][v], row + 32 * (R * L + S) + vrow(v) * L);
+                    if (inside(R, S, v))
+                        __builtin_nontemporal_store(F[R][S][v], row + 32 * (R * L + S) + vrow(v) * L);
                 }
     }
     la += block_shift_sum(shift, start, len, L_tau, lsc, lane);
     // end weight (C f~ C)(e)
     f32x16 X[2][2], H[2][2];
-    circ64_step(F, X, T, neg);
-    circ64_step(X, H, T, neg);
+    circ64_step<PAD>(F, X, T, neg);
+    circ64_step<PAD>(X, H, T, neg);
     const int ex = e % L, ey = e / L;
     const int Re = ey >> 5, Se = ex >> 5, ty = ey & 31, tx = ex & 31;
     const int ve = (ty >> 3) * 4 + (ty & 3);
@@ -1674,11 +1691,22 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
     }
     if (p->n_fwd64_tasks > 0) {  // L = 64: four sub-tiles per worldline
         const unsigned blocks = (unsigned)((p->n_fwd64_tasks + kWaves - 1) / kWaves);
-        hipLaunchKernelGGL(k_forward_mfma64, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+        hipLaunchKernelGGL(k_forward_mfma64<false>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwd64_tasks, p->n_fwd64_tasks, p->d.cmatb, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
                            rescue_args(p), kNegPairs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // 32 < L < 64, padded to the 64 x 64 sub-tiles: after the L = 64 tasks in fwd64_tasks
+    if (p->n_fwd64p_tasks > 0) {
+        const unsigned blocks = (unsigned)((p->n_fwd64p_tasks + kWaves - 1) / kWaves);
+        hipLaunchKernelGGL(k_forward_mfma64<true>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
+                           p->d.fwd64_tasks + p->n_fwd64_tasks, p->n_fwd64p_tasks, p->d.cmatb,
+                           (const float*)aux, (const float*)p->d.W, p->d.wshift, p->aux_elems,
+                           p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
+                           p->d.sweep, p->d.status, rescue_args(p), kNegPairs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

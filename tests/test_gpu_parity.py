@@ -226,7 +226,7 @@ def test_packed_small_lattice_forward_parity(lib):
     descs = PACKED
     say("packed forward parity", [(d.L, d.L_tau, d.n_up, d.n_dn, d.block_len) for d in descs])
     S = sampler.Sampler(descs, PRECS["mfma3"])
-    counts = (ctypes.c_int32 * 4)()
+    counts = (ctypes.c_int32 * 6)()
     assert fhmc.lib.fh_debug_forward_kernels(S.plan, counts) == 0
 
     def n_tasks(sel, per):
@@ -1265,9 +1265,8 @@ def test_windowed_draws_equal_full_row_draws(lib, prec):
     same filters and uniforms; the FP64 FFT path adds a 48 x 48 chain (N > 1024)."""
     fhmc, sampler = lib
     descs = list(WINDOW_BATCH)
-    if prec != "mfma3":
-        descs.append(synth.ChainDesc(L=48, L_tau=12, n_up=3, n_dn=2, hs_kind=synth.HS_GAUSS,
-                                     block_len=5, t=1.0, U=4.0, dtau=0.05, seed=64))
+    descs.append(synth.ChainDesc(L=48, L_tau=12, n_up=3, n_dn=2, hs_kind=synth.HS_GAUSS,
+                                 block_len=5, t=1.0, U=4.0, dtau=0.05, seed=64))
     say("windowed vs full-row draws", prec)
     aux, paths = mixed_state(descs, seed=171)
     plans = {"window": sampler.Sampler(descs, PRECS[prec]),
@@ -1516,18 +1515,19 @@ def test_fp32_chain_through_collapse(lib):
 
 
 # the lattices above 32 that the FP64 re-filter takes on 16 x 16 tiles: 64 x 64 on the split-bf16
-# plan, 48 x 48 on the FP32 FFT plan (the only FP32 path at L = 48); and the states compared
-# with the oracle: from the 64 x 64 chain's third sweep on, its clustered fields overflow the
-# oracle's plain FP64 exp(a sigma)
+# plan, 48 x 48 on the FP32 FFT plan and on the split-bf16 plan's padded sub-tiles; and the
+# states compared with the oracle: from the 64 x 64 chain's third sweep on, its clustered fields
+# overflow the oracle's plain FP64 exp(a sigma)
 BIG_COLLAPSE = {
     "l64_mfma3": ("mfma3", synth.half_filled(64, 40, synth.HS_GAUSS, 6.0, 0.05, seed=1), (1, 2)),
-    "l48_fp32": ("fp32", synth.half_filled(48, 40, synth.HS_GAUSS, 6.0, 0.05, seed=2), (1, 2, 3))}
+    "l48_fp32": ("fp32", synth.half_filled(48, 40, synth.HS_GAUSS, 6.0, 0.05, seed=2), (1, 2, 3)),
+    "l48_mfma3": ("mfma3", synth.half_filled(48, 40, synth.HS_GAUSS, 6.0, 0.05, seed=3), (1, 2, 3))}
 
 
 @pytest.mark.parametrize("case", sorted(BIG_COLLAPSE))
 def test_big_lattice_chain_through_collapse(lib, case):
-    """Eight unrestored sweeps of a 64 x 64 (split-bf16 plan) or 48 x 48 (FP32 FFT plan) Gaussian
-    chain, captured in a graph, through states whose filters leave FP32's range: the FP64
+    """Eight unrestored sweeps of a 64 x 64 (split-bf16 plan) or 48 x 48 (FP32 FFT or split-bf16
+    plan) Gaussian chain, captured in a graph, through states whose filters leave FP32's range: the FP64
     re-filter takes these lattices on 16 x 16 tiles of the FP64 matrix cores, so the status
     stays clean after every sweep, and the queued blocks match the oracle (log Z, filters,
     draws) on the states before the first sweeps."""
@@ -1837,7 +1837,7 @@ def test_zero_weight_row_is_reported(lib, full_row):
 
 
 def test_fp32_fft_l48_parity(lib):
-    """L = 48 on the FP32 plan (the FP32 FFT; the matrix-core plan takes L <= 32 and L = 64 only)
+    """L = 48 on the FP32 plan (the FP32 FFT)
     with 40-slice blocks: log Z against the oracle within its tail bound, filters held to 1e-5
     (rows above it end the test as an expected failure, see FFT32_BOUND)."""
     fhmc, sampler = lib
@@ -1880,9 +1880,10 @@ def test_mfma_circulant_at_l64_parity(lib):
     aux, paths = mixed_state(descs, seed=411)
     Sw = sampler.Sampler(descs, PRECS["mfma3"])
     Sf = sampler.Sampler(descs, PRECS["mfma3"], fhmc.FH_FLAG_FULL_ROW_DRAW)
-    counts = (ctypes.c_int32 * 4)()
+    counts = (ctypes.c_int32 * 6)()
     assert fhmc.lib.fh_debug_forward_kernels(Sw.plan, counts) == 0
     assert counts[1] == 0          # no L = 64 task on the padded 32 x 32 kernel
+    assert counts[4] == 5 + 4 * 2 and counts[5] == 0
     Aw, Pw = Sw.pack_aux(aux), Sw.pack_paths(paths)
     Af, Pf = Sf.pack_aux(aux), Sf.pack_paths(paths)
     for s in (0, 1):
@@ -1904,6 +1905,53 @@ def test_mfma_circulant_at_l64_parity(lib):
         assert np.array_equal(gw[c], gf[c]), c
     with pytest.raises(fhmc.FhError):
         Sw.logz_grad(Aw, Pw, 0)
+    Sw.close()
+    Sf.close()
+
+
+def test_mfma_padded_big_lattice_parity(lib):
+    """32 < L < 64 (36, 48, 54) on the FP32 matrix-core path: the 64 x 64 sub-tiles of the
+    L = 64 kernel, zero-padded, with four distinct circulant blocks, next to an L = 64 chain:
+    filters and log Z against the oracle over two block schedules, windowed draws equal to the
+    full-row kernel's, every such chain routed to the padded kernel."""
+    fhmc, sampler = lib
+    descs = [synth.ChainDesc(L=48, L_tau=6, n_up=3, n_dn=2, hs_kind=synth.HS_GAUSS, block_len=0,
+                             t=1.0, U=4.0, dtau=0.05, seed=421),
+             synth.ChainDesc(L=36, L_tau=7, n_up=2, n_dn=2, hs_kind=synth.HS_HIRSCH, block_len=4,
+                             t=1.0, U=4.0, dtau=0.0625, seed=422),
+             synth.ChainDesc(L=54, L_tau=5, n_up=2, n_dn=1, hs_kind=synth.HS_GAUSS, block_len=3,
+                             t=1.0, U=6.0, dtau=0.05, seed=423),
+             synth.ChainDesc(L=64, L_tau=4, n_up=1, n_dn=1, hs_kind=synth.HS_GAUSS, block_len=0,
+                             t=1.0, U=4.0, dtau=0.05, seed=424)]
+    say("mfma padded 64 x 64 sub-tiles", [d.L for d in descs])
+    aux, paths = mixed_state(descs, seed=431)
+    Sw = sampler.Sampler(descs, PRECS["mfma3"])
+    Sf = sampler.Sampler(descs, PRECS["mfma3"], fhmc.FH_FLAG_FULL_ROW_DRAW)
+    counts = (ctypes.c_int32 * 6)()
+    assert fhmc.lib.fh_debug_forward_kernels(Sw.plan, counts) == 0
+    n_blocks = [-(-d.L_tau // (d.block_len or d.L_tau)) for d in descs]
+    assert counts[5] == sum(d.n_particles * b for d, b in zip(descs, n_blocks) if d.L < 64)
+    assert counts[4] == descs[3].n_particles * n_blocks[3]
+    assert counts[1] == 0
+    Aw, Pw = Sw.pack_aux(aux), Sw.pack_paths(paths)
+    Af, Pf = Sf.pack_aux(aux), Sf.pack_paths(paths)
+    for s in (0, 1):
+        logZ = Sw.unpack_particles(Sw.forward_filter(Aw, Pw, s))
+        assert Sw.status() == (0, -1)
+        for c, d in enumerate(descs):
+            ref_lz, ref_rows = oracle_forward(d, aux[c], paths[c], s)
+            err = np.abs(logZ[c] - ref_lz)
+            assert np.all(err <= logz_tol("mfma3", ref_lz, 0.0, d.L_tau)), (c, s, err)
+            for p in range(d.n_particles):
+                assert rel_row_err(Sw.filters(c, p), ref_rows[p]) <= FILTER_TOL["mfma3"], (c, p, s)
+    s = 1
+    Sw.backward_sample(Pw, s)
+    Sf.forward_filter(Af, Pf, s)
+    Sf.backward_sample(Pf, s)
+    assert Sw.status() == (0, -1) and Sf.status() == (0, -1)
+    gw, gf = Sw.unpack_paths(Pw), Sf.unpack_paths(Pf)
+    for c in range(len(descs)):
+        assert np.array_equal(gw[c], gf[c]), c
     Sw.close()
     Sf.close()
 

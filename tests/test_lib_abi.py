@@ -139,10 +139,6 @@ def test_init_validates_before_touching_the_device(fhmc):
     with pytest.raises(fhmc.FhError) as e:
         fhmc.fh_init([good], fhmc.FH_FP64, flags=0x100)
     assert e.value.code == fhmc.FH_ERR_INVALID_ARG
-    import dataclasses
-    with pytest.raises(fhmc.FhError) as e:
-        fhmc.fh_init([dataclasses.replace(good, L=48)], fhmc.FH_FP32_MFMA3)
-    assert e.value.code == fhmc.FH_ERR_UNSUPPORTED
 
 
 def test_null_plan_calls_are_rejected(fhmc):
