@@ -203,7 +203,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_device(fh::Device& d) {
     void* ptrs[] = {d.chains, d.tables, d.cmat, d.cmat64, d.fwdd_tasks, d.W, d.wshift, d.filt, d.blk_logz, d.dt, d.fwd_tasks,
-                    d.draw_tasks, d.group_tasks, d.gpart, d.ckpt, d.rep, d.blk_la, d.endrow, d.dedup_tasks, d.fwd32_tasks, d.fwd32c_tasks, d.fwdxc_tasks, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
+                    d.draw_tasks, d.group_tasks, d.gpart, d.ckpt, d.rep, d.blk_la, d.endrow, d.dedup_tasks, d.fwd32_tasks, d.fwd32c_tasks, d.fwdxc_tasks, d.fwdpc_tasks, d.prep, d.fwdx_tasks, d.fwdp_tasks, d.cmatp, d.cmatb, d.fwd64_tasks, d.draw32_tasks, d.draww_tasks, d.drawx_tasks, d.meas, d.mala, d.perm, d.perm_inv, d.sign, d.bw_state,
                     d.rescue, d.rescue_list, d.rep_slot, d.arep, d.rescue_ws, d.rescue_w, d.status, d.sweep};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -422,11 +422,12 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
     std::vector<DrawTask> dedup;
     for (int c = 0; c < n_chains; ++c) {
         ChainInfo& ci = p->chains[c];
-        // the split-bf16 plan's 32 x 32 chains and its padded lattices (16 < L < 32, or small
-        // ones too large to pack), one tile per worldline
-        const bool padded = ci.L < 32 && !(ci.L <= kPackMaxL &&
-                                           (int64_t)ci.np * ci.L_tau * ci.N * 4 < ((int64_t)1 << 31));
-        ci.dedup = (precision == FH_FP32_MFMA3 && (ci.L == 32 || padded)) ? 1
+        // the split-bf16 plan's chains with L <= 32: 32 x 32 tiles, padded lattices (16 < L < 32,
+        // or small ones too large to pack), one tile per worldline, and packed small lattices
+        const bool packs = ci.L <= kPackMaxL &&
+                           (int64_t)ci.np * ci.L_tau * ci.N * 4 < ((int64_t)1 << 31);
+        ci.pack = (precision == FH_FP32_MFMA3 && packs) ? pack_blocks(ci.L) : 0;
+        ci.dedup = (precision == FH_FP32_MFMA3 && ci.L <= 32) ? 1
                    : (precision != FH_FP64 && big_nt(ci.L) != 0) ? 2 : 0;
         if (!ci.dedup) continue;
         if (ci.dedup == 1) {
@@ -561,6 +562,13 @@ int fh_init(fh_plan* out, const fh_chain_desc* descs, int32_t n_chains, int32_t 
         e = dalloc(&dv.fwd32c_tasks, sizeof(PairTask) * fwd32.size());
     if (e == hipSuccess && p->end_elems > 0 && !fwdx.empty())  // so do the padded lattices
         e = dalloc(&dv.fwdxc_tasks, sizeof(DrawTask) * fwdx.size());
+    if (e == hipSuccess && p->end_elems > 0 && !fwdp.empty()) {  // and the packed ones
+        int64_t n_prep = 0;
+        for (const ChainInfo& ci : p->chains)
+            if (ci.pack) n_prep += (int64_t)ci.np * ci.nb;
+        e = dalloc(&dv.fwdpc_tasks, sizeof(PackTask) * fwdp.size());
+        if (e == hipSuccess) e = dalloc(&dv.prep, sizeof(int32_t) * (size_t)n_prep);
+    }
     if (e == hipSuccess) e = dalloc(&dv.fwdx_tasks, sizeof(DrawTask) * fwdx.size());
     if (e == hipSuccess) e = dalloc(&dv.fwdp_tasks, sizeof(PackTask) * fwdp.size());
     if (e == hipSuccess) e = dalloc(&dv.cmatp, sizeof(uint16_t) * p->cmatp.size());

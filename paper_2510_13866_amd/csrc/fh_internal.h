@@ -49,13 +49,14 @@ struct ChainInfo {
     int32_t ck_k, ck_n;
     // Shared forward filters: the rows of a block depend only on the spin's W and the block's
     // start site, so worldlines of one (spin, block) with the same start site share the rows of
-    // the lowest-numbered of them, their representative. dedup = 1: 32 x 32 and padded
-    // (16 < L < 32) chains of the split-bf16 plan, in the FP32 passes and the FP64 re-filter's
-    // phase A; end_off locates their
-    // per-(particle, block) end tiles [N]. dedup = 2: 48 x 48 and 64 x 64 chains of FP32 plans,
+    // the lowest-numbered of them, their representative. dedup = 1: every chain with L <= 32 of
+    // the split-bf16 plan (32 x 32, padded and packed tiles), in the FP32 passes and the FP64
+    // re-filter's phase A; end_off locates their per-(particle, block) end tiles [N].
+    // dedup = 2: 48 x 48 and 64 x 64 chains of FP32 plans,
     // in phase A only (their FP32 passes keep one recursion per worldline, and their map is the
     // identity while the chain is not held).
     int32_t dedup;
+    int32_t pack;  // the packed forward's P (4: L <= 8, 2: L <= 16) on the split-bf16 plan, else 0
     int64_t end_off;
 };
 
@@ -144,7 +145,9 @@ constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // (a sweep's held chains, queued before its FP32 forward pass and re-filtered beside the FP32
 // passes), [4] slots taken by phase A, [5] entries of the dense list of representative pairs
 // (k_dedup), [6] entries of phase A's dense list of representatives (k_rescue_held), [7] entries
-// of the dense list of the padded lattices' representatives (k_dedup), then per chain: blocks queued by the kernels in this pass
+// of the dense list of the padded lattices' representatives (k_dedup), [8] and [9] entries of
+// the dense lists of packed tiles of representatives (P = 2 and P = 4, k_dedup), [10]
+// representatives listed for those tiles, [11] unused, then per chain: blocks queued by the kernels in this pass
 // (kRescueChain + c), forward passes left on FP64 (kRescueChain + n_chains + c), 1 if the chain
 // is in phase A (kRescueChain + 2 n_chains + c), the forward recursions its blocks need in this
 // pass (kRescueChain + 3 n_chains + c: the representatives of the shared filters), the hold at
@@ -152,7 +155,7 @@ constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // hold (kRescueChain + 5 n_chains + c), then one flag per (chain, particle, block) at
 // kRescueChain + kRescuePerChain n_chains + blk_off + p nb + b (the `flags` pointer passed to
 // the kernels).
-constexpr int kRescueChain = 8;
+constexpr int kRescueChain = 12;
 constexpr int kRescuePerChain = 6;
 // Slots of the FP64 re-filter (two wavefronts per SIMD of 256 CUs), (B - 1) N doubles of rows
 // plus the end tile [N]. Phase 0 and 2 give each wavefront its own slot; phase A gives each
@@ -255,6 +258,10 @@ struct Device {
     DrawTask* fwdxc_tasks = nullptr;    // the same for the padded lattices' single worldlines
     DrawTask* fwdx_tasks = nullptr;     // MFMA forward: single worldlines of 16 < L < 32 chains
     PackTask* fwdp_tasks = nullptr;
+    // the packed tiles of representatives k_dedup lists (P = 2 from the front, P = 4 from
+    // n_fwdp2_tasks on; PackTask.p0 indexes prep) and the representatives they hold
+    PackTask* fwdpc_tasks = nullptr;
+    int32_t* prep = nullptr;
     DrawTask* fwd64_tasks = nullptr;    // MFMA forward: single worldlines of L = 64 chains     // MFMA forward, packed: P = 2 tasks, then P = 4 tasks
     DrawTask* draw32_tasks = nullptr;   // backward: worldline blocks of L = 32 chains
     DrawTask* draww_tasks = nullptr;    // backward, windowed draws (k_backward_win)

@@ -1742,17 +1742,21 @@ __global__ __launch_bounds__(kThreads, kShareDrawWaves) void k_rescue_share_draw
 // in worldline order and two to a task, to the dense list cpairs (count in words[5]), which the
 // split-bf16 forward then takes from the front: its active wavefronts are the first ones
 // dispatched, spread over the XCDs, instead of sitting at fixed grid positions that map a whole
-// settled batch onto a few compute units.
+// settled batch onto a few compute units. Packed lattices (pack = P) list their representatives
+// in prep (count in words[10]) and P^2 of them to a tile in cpack (P = 2: from the front, count
+// in words[8]; P = 4: from n_p2 on, count in words[9]).
 __global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict__ chains,
                                                     const DrawTask* __restrict__ tasks,
                                                     const int32_t* __restrict__ paths,
                                                     const uint64_t* __restrict__ sweep_ptr,
                                                     int32_t* __restrict__ rep, const Rescue rsc,
                                                     PairTask* __restrict__ cpairs,
-                                                    DrawTask* __restrict__ csingles) {
+                                                    DrawTask* __restrict__ csingles,
+                                                    PackTask* __restrict__ cpack, int n_p2,
+                                                    int32_t* __restrict__ prep) {
     __shared__ int32_t first[kDedupMaxN];
     __shared__ int32_t rlist[kDedupMaxN];
-    __shared__ int32_t n_rep, c_base;
+    __shared__ int32_t n_rep, c_base, p_base;
     const DrawTask t = tasks[blockIdx.x];  // t.p holds the spin
     const ChainInfo& c = chains[t.chain];
     int start, len;
@@ -1782,9 +1786,13 @@ __global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict_
     // the chain's forward recursions in this pass (the FP64 re-filter's phase A sizes by them)
     if (threadIdx.x == 0) atomicAdd(&rsc.words[kRescueChain + 3 * rsc.n_chains + t.chain], n_rep);
     // the 32 x 32 chains' representatives go to cpairs, two to a task; the padded lattices'
-    // (16 < L < 32, one worldline to a wavefront) to csingles (count in words[7])
+    // (16 < L < 32, one worldline to a wavefront) to csingles (count in words[7]); the packed
+    // ones to cpack
     const bool pairs = c.L == 32;
-    if (c.dedup != 1 || (pairs ? !cpairs : !csingles) || rescue_held(rsc, t.chain)) return;
+    const int PP = c.pack * c.pack;  // worldlines per packed tile
+    if (c.dedup != 1 || (pairs ? !cpairs : c.pack ? !cpack : !csingles) ||
+        rescue_held(rsc, t.chain))
+        return;
     // the representatives in worldline order (first wavefront), then their pairs
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
@@ -1800,11 +1808,24 @@ __global__ __launch_bounds__(kThreads) void k_dedup(const ChainInfo* __restrict_
             if (is_rep) rlist[cnt + __popcll(m & ((1ull << lane) - 1))] = q;
             cnt += __popcll(m);
         }
-        if (lane == 0) c_base = pairs ? atomicAdd(&rsc.words[5], (cnt + 1) / 2)
-                                      : atomicAdd(&rsc.words[7], cnt);
+        if (lane == 0) {
+            if (pairs) {
+                c_base = atomicAdd(&rsc.words[5], (cnt + 1) / 2);
+            } else if (c.pack) {
+                p_base = atomicAdd(&rsc.words[10], cnt);
+                c_base = atomicAdd(&rsc.words[c.pack == 2 ? 8 : 9], (cnt + PP - 1) / PP) +
+                         (c.pack == 2 ? 0 : n_p2);
+            } else {
+                c_base = atomicAdd(&rsc.words[7], cnt);
+            }
+        }
     }
     __syncthreads();
-    if (pairs) {
+    if (c.pack) {
+        for (int i = threadIdx.x; i < n_rep; i += blockDim.x) prep[p_base + i] = rlist[i];
+        for (int k = threadIdx.x; k * PP < n_rep; k += blockDim.x)
+            cpack[c_base + k] = PackTask{t.chain, p_base + k * PP, min(PP, n_rep - k * PP), t.block};
+    } else if (pairs) {
         const int npairs = (n_rep + 1) / 2;
         for (int i = threadIdx.x; i < npairs; i += blockDim.x)
             cpairs[c_base + i] = PairTask{t.chain, rlist[2 * i],
@@ -1862,6 +1883,9 @@ __global__ void k_rescue_reset(const Rescue rsc, int64_t n_flags) {
         rsc.words[5] = 0;
         rsc.words[6] = 0;
         rsc.words[7] = 0;
+        rsc.words[8] = 0;
+        rsc.words[9] = 0;
+        rsc.words[10] = 0;
     }
     const int n = rsc.n_chains;
     for (int64_t k = i; k < n; k += stride) {
@@ -2839,7 +2863,8 @@ hipError_t launch_dedup(fh_plan p, const int32_t* paths, hipStream_t s) {
     if (p->n_dedup_tasks == 0 || p->share_off) return hipSuccess;
     hipLaunchKernelGGL(k_dedup, dim3((unsigned)p->n_dedup_tasks), dim3(kThreads), 0, s,
                        p->d.chains, p->d.dedup_tasks, paths, p->d.sweep, p->d.rep, rescue_args(p),
-                       p->d.fwd32c_tasks, p->d.fwdxc_tasks);
+                       p->d.fwd32c_tasks, p->d.fwdxc_tasks, p->d.fwdpc_tasks, p->n_fwdp2_tasks,
+                       p->d.prep);
     return hipGetLastError();
 }
 

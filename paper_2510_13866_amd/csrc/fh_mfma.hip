@@ -897,10 +897,15 @@ __device__ inline float block_sum(float v) {
 // k_forward_mfma2; one tile doubles the wavefronts of a small batch).
 //
 // Slots. Slot s = T P^2 + I P + J (tile T, block (I, J)) of a task holds worldline
-// p0 + min(s, n - 1); slots past n repeat the last worldline and are neither stored nor
-// counted. Each block's normaliser comes from a segmented wavefront sum; the slot's log Z is
-// kept by its owner lane BS J + T P + I (first half of the wavefront) as an FP64 mantissa and a
-// binary exponent, renormalised every step, so no log is taken inside the loop.
+// wl(min(s, n - 1)), wl(k) = p0 + k; slots past n repeat the last worldline and are neither
+// stored nor counted. Each block's normaliser comes from a segmented wavefront sum; the slot's
+// log Z is kept by its owner lane BS J + T P + I (first half of the wavefront) as an FP64
+// mantissa and a binary exponent, renormalised every step, so no log is taken inside the loop.
+// Shared forward filters: with the dense list of tiles of representatives (k_dedup), wavefront
+// i takes its entry i and wl(k) = prep[p0 + k]; each representative also leaves its log Z before
+// the end weight and its end tile for the worldlines that share its rows (k_member_logz). A
+// worldline's arithmetic does not depend on its slot: the other blocks contribute exact zeros,
+// and every block sums its terms in the same order.
 template <int P, int NT>
 __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
     const ChainInfo* __restrict__ chains, const PackTask* __restrict__ tasks, int n_tasks,
@@ -908,20 +913,23 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
     double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
-    const Rescue rsc, const NegPairs neg) {
+    const Rescue rsc, const NegPairs neg, double* __restrict__ blk_la,
+    float* __restrict__ endrow, const PackTask* __restrict__ ctasks,
+    const int32_t* __restrict__ ccount, const int32_t* __restrict__ prep) {
     constexpr int BS = 32 / P;   // block side
     constexpr int PP = P * P;    // worldlines per tile
     constexpr int RPB = 16 / P;  // registers of one block row band per lane
     const int lane = threadIdx.x & 63;
     const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
-    if (task >= n_tasks) return;  // whole wavefront; no barriers in this kernel
-    const PackTask t = tasks[task];
+    if (task >= (ccount ? *ccount : n_tasks)) return;  // whole wavefront; no barriers here
+    const PackTask t = ccount ? ctasks[task] : tasks[task];
     if (rescue_held(rsc, t.chain)) return;  // re-filtered whole in FP64 this pass
     const ChainInfo& c = chains[t.chain];
+    auto wl = [&](int k) { return ccount ? prep[t.p0 + k] : t.p0 + k; };
     int start, len;
     block_of(c, *sweep_ptr, t.block, &start, &len);
     const int L = c.L, N = c.N, L_tau = c.L_tau;
-    const int spin = t.p0 >= c.n_up ? 1 : 0;
+    const int spin = wl(0) >= c.n_up ? 1 : 0;
     const float* Wsp = W + spin * aux_elems + c.aux_off;
     const double* shift = wshift + spin * total_slices + c.slice_off;
     const double coef = spin ? c.coef_dn : c.coef_up;
@@ -963,7 +971,7 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
 #pragma unroll
         for (int I = 0; I < P; ++I) {
             const int s = T * PP + I * P + J;
-            const int pw = t.p0 + (s < t.n ? s : t.n - 1);
+            const int pw = wl(s < t.n ? s : t.n - 1);
             int a = pc[(int64_t)start * c.np + pw];
             a = (a < 0 || a >= N) ? 0 : a;  // reported by the owner lane below
             const int ax = a % L, ay = a / L;
@@ -981,8 +989,9 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
     int oe = 0;
     double la = 0.0, mant = 1.0;
     int ex2 = 0;
+    const int opw = owner ? wl(os) : 0;
     if (owner) {
-        const int pw = t.p0 + os;
+        const int pw = opw;
         const int a = pc[(int64_t)start * c.np + pw];
         const int qe = start + len >= L_tau ? perm[c.part_off + pw] : pw;  // reconnection
         oe = pc[(int64_t)((start + len) % L_tau) * c.np + qe];
@@ -1092,10 +1101,25 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
             const float h = __shfl(H[T][v], src, 64);
             if (v == ve && T == oT) hv = h;
         }
+    const double la_end = la - (log(mant) + (double)ex2 * 0.69314718055994530942);
     if (owner) {
-        if (low || !(hv >= kRangeFloor)) rescue_push(rsc, c, t.chain, t.p0 + os, t.block);
-        const double lz = la - (log(mant) + (double)ex2 * 0.69314718055994530942) + log((double)hv);
-        blk_logz[c.blk_off + (int64_t)(t.p0 + os) * c.nb + t.block] = lz;
+        if (low || !(hv >= kRangeFloor)) rescue_push(rsc, c, t.chain, opw, t.block);
+        blk_logz[c.blk_off + (int64_t)opw * c.nb + t.block] = la_end + log((double)hv);
+        if (c.dedup) blk_la[c.blk_off + (int64_t)opw * c.nb + t.block] = la_end;
+    }
+    if (c.dedup) {  // the end tiles of the slots, for the worldlines that share their rows
+#pragma unroll
+        for (int T = 0; T < NT; ++T)
+#pragma unroll
+            for (int I = 0; I < P; ++I) {
+                const int s = T * PP + I * P + J;
+                if (!ok[T][I]) continue;
+                float* end = endrow + c.end_off + ((int64_t)wl(s) * c.nb + t.block) * N +
+                             4 * hl * L + lx;
+#pragma unroll
+                for (int v = I * RPB; v < (I + 1) * RPB; ++v)
+                    if (4 * hl + cv(v) < L) end[cv(v) * L] = H[T][v];
+            }
     }
 }
 
@@ -1710,14 +1734,17 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    // small lattices, packed block-diagonally: L <= 16 two-by-two, L <= 8 four-by-four
+    // small lattices, packed block-diagonally: L <= 16 two-by-two, L <= 8 four-by-four; with
+    // shared filters, tiles of representatives from k_dedup's dense lists
+    const bool shared_packs = p->d.fwdpc_tasks && !p->share_off;
     if (p->n_fwdp2_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_fwdp2_tasks + kWaves - 1) / kWaves);
         hipLaunchKernelGGL((k_forward_pack<2, kPackTiles>), dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwdp_tasks, p->n_fwdp2_tasks, p->d.cmatp, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
                            paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep, p->d.status,
-                           rescue_args(p), kNegPairs);
+                           rescue_args(p), kNegPairs, p->d.blk_la, p->d.endrow, p->d.fwdpc_tasks,
+                           shared_packs ? p->d.rescue + 8 : nullptr, p->d.prep);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1727,7 +1754,9 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
                            p->d.fwdp_tasks + p->n_fwdp2_tasks, p->n_fwdp4_tasks, p->d.cmatp,
                            (const float*)aux, (const float*)p->d.W, p->d.wshift, p->aux_elems,
                            p->total_slices, paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz,
-                           p->d.sweep, p->d.status, rescue_args(p), kNegPairs);
+                           p->d.sweep, p->d.status, rescue_args(p), kNegPairs, p->d.blk_la,
+                           p->d.endrow, p->d.fwdpc_tasks + p->n_fwdp2_tasks,
+                           shared_packs ? p->d.rescue + 9 : nullptr, p->d.prep);
     }
     return hipGetLastError();
 }

@@ -1721,14 +1721,19 @@ def test_shared_forward_filters_change_nothing(lib):
     """Worldlines of one (spin, block) that start on the same site have the same forward rows;
     the matrix-core plan runs the recursion once per start site (fh_debug_representatives) and
     the others read those rows. From a clustered state (twelve sweeps of the benchmark's
-    chains, a chain with ragged 24-slice blocks and a padded 24 x 24 lattice), sweeps, log Z,
-    filters and draws equal those of the same plan with sharing off, bit for bit."""
+    chains, a chain with ragged 24-slice blocks, a padded 24 x 24 lattice and packed 12 x 12 and
+    8 x 8 lattices), sweeps, log Z, filters and draws equal those of the same plan with sharing
+    off, bit for bit."""
     fhmc, sampler = lib
+    packed = [synth.ChainDesc(L=12, L_tau=40, n_up=72, n_dn=70, hs_kind=synth.HS_GAUSS,
+                              block_len=16, t=1.0, U=6.0, dtau=0.05, seed=7),
+              synth.ChainDesc(L=8, L_tau=40, n_up=32, n_dn=31, hs_kind=synth.HS_HIRSCH,
+                              block_len=0, t=1.0, U=6.0, dtau=0.05, seed=8)]
     descs = synth.config_32x32(4.0, 2) + [
         synth.ChainDesc(L=32, L_tau=64, n_up=300, n_dn=200, hs_kind=synth.HS_GAUSS, block_len=24,
                         t=1.0, U=6.0, dtau=0.05, seed=5),
         synth.ChainDesc(L=24, L_tau=48, n_up=200, n_dn=150, hs_kind=synth.HS_GAUSS, block_len=0,
-                        t=1.0, U=6.0, dtau=0.05, seed=6)]
+                        t=1.0, U=6.0, dtau=0.05, seed=6)] + packed
     S = sampler.Sampler(descs, fhmc.FH_FP32_MFMA3, fhmc.FH_FLAG_GRAPH)
     A = S.pack_aux([synth.initial_aux(d) for d in descs])
     P = S.pack_paths([synth.initial_paths(d) for d in descs])
@@ -1737,8 +1742,9 @@ def test_shared_forward_filters_change_nothing(lib):
     rep = fhmc.fh_debug_representatives(S.plan)
     own = np.concatenate([np.repeat(np.arange(d.n_particles), synth_blocks(d)) for d in descs])
     assert len(rep) == len(own) and np.sum(rep != own) > len(own) // 2, np.sum(rep != own)
-    tail = len(own) - descs[-1].n_particles * synth_blocks(descs[-1])
-    assert np.sum(rep[tail:] != own[tail:]) > 0  # the padded lattice shares rows too
+    ends = np.cumsum([d.n_particles * synth_blocks(d) for d in descs])
+    for k in (-3, -2, -1):  # the padded and packed lattices share rows too
+        assert np.sum(rep[ends[k - 1]:ends[k]] != own[ends[k - 1]:ends[k]]) > 0, k
     Sx = sampler.Sampler(descs, fhmc.FH_FP32_MFMA3, fhmc.FH_FLAG_GRAPH)
     assert fhmc.lib.fh_debug_share_filters(Sx.plan, 0) == 0
     Ax, Px = A.clone(), P.clone()
