@@ -147,8 +147,8 @@ __device__ inline double block_shift_sum(const double* __restrict__ shift, int s
 // storing f~_j (j >= 1) as FP32 rows of N values, like the FFT path. LFIX = 32 compiles the
 // common full-tile case with constant offsets; LFIX = 0 handles any L <= 32 by zero padding.
 template <int LFIX>
-__global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
-    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
+__device__ __forceinline__ void forward_mfma_body(
+    int task, const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
     const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
@@ -157,7 +157,6 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     float* __restrict__ endrow, const DrawTask* __restrict__ ctasks,
     const int32_t* __restrict__ ccount) {
     const int lane = threadIdx.x & 63;
-    const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     // with the dense list of representatives (k_dedup), wavefront i takes its entry i
     if (task >= (ccount ? *ccount : n_tasks)) return;  // whole wavefront; no barriers here
     const DrawTask t = ccount ? ctasks[task] : tasks[task];
@@ -300,6 +299,22 @@ __global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
     }
 }
 
+template <int LFIX>
+__global__ __launch_bounds__(kThreads, LFIX ? 4 : 2) void k_forward_mfma(
+    const ChainInfo* __restrict__ chains, const DrawTask* __restrict__ tasks, int n_tasks,
+    const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
+    double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
+    const Rescue rsc, const NegPairs neg, double* __restrict__ blk_la,
+    float* __restrict__ endrow, const DrawTask* __restrict__ ctasks,
+    const int32_t* __restrict__ ccount) {
+    forward_mfma_body<LFIX>(
+        __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6)), chains, tasks,
+        n_tasks, cmat, aux, W, wshift, aux_elems, total_slices, paths, perm, filt, blk_logz,
+        sweep_ptr, status, rsc, neg, blk_la, endrow, ctasks, ccount);
+}
+
 // ---- FP64 circulant on the FP64 matrix cores (fh_dmfma.h) ----------------------------------
 
 // One wavefront per (chain, worldline, block) of an FP64 plan with L <= 32: the forward
@@ -430,8 +445,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_forward_dmfma_big(
 // those loads are long done and the stores may still be in flight. Task, chain, slice and row
 // bases are wavefront-uniform (scalar registers), so a store is one lane offset plus a constant.
 template <int LFIX>
-__global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
-    const ChainInfo* __restrict__ chains, const PairTask* __restrict__ tasks, int n_tasks,
+__device__ __forceinline__ void forward_mfma2_body(
+    int task, const ChainInfo* __restrict__ chains, const PairTask* __restrict__ tasks, int n_tasks,
     const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
@@ -440,7 +455,6 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     float* __restrict__ endrow, const PairTask* __restrict__ ctasks,
     const int32_t* __restrict__ ccount) {
     const int lane = threadIdx.x & 63;
-    const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     // with the dense list of representative pairs (k_dedup), wavefront i takes its entry i
     if (task >= (ccount ? *ccount : n_tasks)) return;  // whole wavefront; no barriers here
     const PairTask t = ccount ? ctasks[task] : tasks[task];
@@ -663,6 +677,22 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
         run(std::true_type{});
     else
         run(std::false_type{});
+}
+
+template <int LFIX>
+__global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
+    const ChainInfo* __restrict__ chains, const PairTask* __restrict__ tasks, int n_tasks,
+    const uint16_t* __restrict__ cmat, const float* __restrict__ aux, const float* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
+    double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
+    const Rescue rsc, const NegPairs neg, double* __restrict__ blk_la,
+    float* __restrict__ endrow, const PairTask* __restrict__ ctasks,
+    const int32_t* __restrict__ ccount) {
+    forward_mfma2_body<LFIX>(
+        __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6)), chains, tasks,
+        n_tasks, cmat, aux, W, wshift, aux_elems, total_slices, paths, perm, filt, blk_logz,
+        sweep_ptr, status, rsc, neg, blk_la, endrow, ctasks, ccount);
 }
 
 // L = 64 on the same matrix cores: the 64 x 64 filter in four 32 x 32 sub-tiles X_RS (rows
@@ -907,8 +937,8 @@ __device__ inline float block_sum(float v) {
 // worldline's arithmetic does not depend on its slot: the other blocks contribute exact zeros,
 // and every block sums its terms in the same order.
 template <int P, int NT>
-__global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
-    const ChainInfo* __restrict__ chains, const PackTask* __restrict__ tasks, int n_tasks,
+__device__ __forceinline__ void forward_pack_body(
+    int task, const ChainInfo* __restrict__ chains, const PackTask* __restrict__ tasks, int n_tasks,
     const uint16_t* __restrict__ cmatp, const float* __restrict__ aux, const float* __restrict__ W,
     const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
     const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
@@ -920,7 +950,6 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
     constexpr int PP = P * P;    // worldlines per tile
     constexpr int RPB = 16 / P;  // registers of one block row band per lane
     const int lane = threadIdx.x & 63;
-    const int task = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
     if (task >= (ccount ? *ccount : n_tasks)) return;  // whole wavefront; no barriers here
     const PackTask t = ccount ? ctasks[task] : tasks[task];
     if (rescue_held(rsc, t.chain)) return;  // re-filtered whole in FP64 this pass
@@ -1121,6 +1150,22 @@ __global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
                     if (4 * hl + cv(v) < L) end[cv(v) * L] = H[T][v];
             }
     }
+}
+
+template <int P, int NT>
+__global__ __launch_bounds__(kThreads, NT == 1 ? 4 : 2) void k_forward_pack(
+    const ChainInfo* __restrict__ chains, const PackTask* __restrict__ tasks, int n_tasks,
+    const uint16_t* __restrict__ cmatp, const float* __restrict__ aux, const float* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
+    double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
+    const Rescue rsc, const NegPairs neg, double* __restrict__ blk_la,
+    float* __restrict__ endrow, const PackTask* __restrict__ ctasks,
+    const int32_t* __restrict__ ccount, const int32_t* __restrict__ prep) {
+    forward_pack_body<P, NT>(
+        __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6)), chains, tasks,
+        n_tasks, cmatp, aux, W, wshift, aux_elems, total_slices, paths, perm, filt, blk_logz,
+        sweep_ptr, status, rsc, neg, blk_la, endrow, ctasks, ccount, prep);
 }
 
 // One step of the adjoint's ring recursion for one worldline per wavefront:
@@ -1661,6 +1706,59 @@ __global__ __launch_bounds__(kThreads) void k_gpart_reduce(const ChainInfo* __re
     }
 }
 
+// The forward kernel classes of a split-bf16 plan whose chains take several of them (32 x 32
+// pairs, padded tiles, packed 2 x 2 and 4 x 4 tiles) in one launch: workgroups [0, b1) run the
+// pair kernel's tasks, [b1, b2) the padded tiles', [b2, b3) the 2 x 2 packed tiles', the rest
+// the 4 x 4 ones', each class with the arithmetic of its own kernel. Once the chains cluster,
+// each class is a few recursions of up to L_tau - 1 dependent steps; side by side, the pass
+// takes the longest of them instead of their sum.
+struct FwdClasses {
+    const PairTask* pairs;
+    const PairTask* cpairs;
+    const int32_t* n_cpairs;
+    const DrawTask* singles;
+    const DrawTask* csingles;
+    const int32_t* n_csingles;
+    const PackTask* pack2;
+    const PackTask* cpack2;
+    const int32_t* n_cpack2;
+    const PackTask* pack4;
+    const PackTask* cpack4;
+    const int32_t* n_cpack4;
+    int32_t n_pairs, n_singles, n_pack2, n_pack4;
+    int32_t b1, b2, b3;
+};
+
+__global__ __launch_bounds__(kThreads, 2) void k_forward_classes(
+    const ChainInfo* __restrict__ chains, const uint16_t* __restrict__ cmat,
+    const uint16_t* __restrict__ cmatp, const float* __restrict__ aux, const float* __restrict__ W,
+    const double* __restrict__ wshift, int64_t aux_elems, int64_t total_slices,
+    const int32_t* __restrict__ paths, const int32_t* __restrict__ perm, float* __restrict__ filt,
+    double* __restrict__ blk_logz, const uint64_t* __restrict__ sweep_ptr, int32_t* status,
+    const Rescue rsc, const NegPairs neg, double* __restrict__ blk_la,
+    float* __restrict__ endrow, const int32_t* __restrict__ prep, const FwdClasses fc) {
+    const int b = blockIdx.x, w = threadIdx.x >> 6;
+    auto task = [&](int b0) { return __builtin_amdgcn_readfirstlane((b - b0) * kWaves + w); };
+    if (b < fc.b1)
+        forward_mfma2_body<32>(task(0), chains, fc.pairs, fc.n_pairs, cmat, aux, W, wshift,
+                               aux_elems, total_slices, paths, perm, filt, blk_logz, sweep_ptr,
+                               status, rsc, neg, blk_la, endrow, fc.cpairs, fc.n_cpairs);
+    else if (b < fc.b2)
+        forward_mfma_body<0>(task(fc.b1), chains, fc.singles, fc.n_singles, cmat, aux, W, wshift,
+                             aux_elems, total_slices, paths, perm, filt, blk_logz, sweep_ptr,
+                             status, rsc, neg, blk_la, endrow, fc.csingles, fc.n_csingles);
+    else if (b < fc.b3)
+        forward_pack_body<2, kPackTiles>(task(fc.b2), chains, fc.pack2, fc.n_pack2, cmatp, aux, W,
+                                         wshift, aux_elems, total_slices, paths, perm, filt,
+                                         blk_logz, sweep_ptr, status, rsc, neg, blk_la, endrow,
+                                         fc.cpack2, fc.n_cpack2, prep);
+    else
+        forward_pack_body<4, kPackTiles>(task(fc.b3), chains, fc.pack4, fc.n_pack4, cmatp, aux, W,
+                                         wshift, aux_elems, total_slices, paths, perm, filt,
+                                         blk_logz, sweep_ptr, status, rsc, neg, blk_la, endrow,
+                                         fc.cpack4, fc.n_cpack4, prep);
+}
+
 }  // namespace
 
 hipError_t launch_forward_dmfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
@@ -1689,8 +1787,43 @@ hipError_t launch_forward_dmfma(fh_plan p, const void* aux, const int32_t* paths
 }
 
 hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths, hipStream_t s) {
+    const bool shared_packs = p->d.fwdpc_tasks && !p->share_off;
+    auto blocks_for = [](int32_t n) { return (int32_t)((n + kWaves - 1) / kWaves); };
+    const int classes = (p->n_fwd32_tasks > 0) + (p->n_fwdx_tasks > 0) + (p->n_fwdp2_tasks > 0) +
+                        (p->n_fwdp4_tasks > 0);
+    if (classes > 1) {  // one launch for every class but the 64 x 64 sub-tiles
+        FwdClasses fc;
+        fc.pairs = p->d.fwd32_tasks;
+        fc.cpairs = p->d.fwd32c_tasks;
+        fc.n_cpairs = p->d.fwd32c_tasks && !p->share_off ? p->d.rescue + 5 : nullptr;
+        fc.singles = p->d.fwdx_tasks;
+        fc.csingles = p->d.fwdxc_tasks;
+        fc.n_csingles = p->d.fwdxc_tasks && !p->share_off ? p->d.rescue + 7 : nullptr;
+        fc.pack2 = p->d.fwdp_tasks;
+        fc.cpack2 = p->d.fwdpc_tasks;
+        fc.n_cpack2 = shared_packs ? p->d.rescue + 8 : nullptr;
+        fc.pack4 = p->d.fwdp_tasks + p->n_fwdp2_tasks;
+        fc.cpack4 = p->d.fwdpc_tasks ? p->d.fwdpc_tasks + p->n_fwdp2_tasks : nullptr;
+        fc.n_cpack4 = shared_packs ? p->d.rescue + 9 : nullptr;
+        fc.n_pairs = p->n_fwd32_tasks;
+        fc.n_singles = p->n_fwdx_tasks;
+        fc.n_pack2 = p->n_fwdp2_tasks;
+        fc.n_pack4 = p->n_fwdp4_tasks;
+        fc.b1 = blocks_for(p->n_fwd32_tasks);
+        fc.b2 = fc.b1 + blocks_for(p->n_fwdx_tasks);
+        fc.b3 = fc.b2 + blocks_for(p->n_fwdp2_tasks);
+        const int32_t blocks = fc.b3 + blocks_for(p->n_fwdp4_tasks);
+        hipLaunchKernelGGL(k_forward_classes, dim3((unsigned)blocks), dim3(kThreads), 0, s,
+                           p->d.chains, p->d.cmat, p->d.cmatp, (const float*)aux,
+                           (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
+                           paths, p->d.perm, (float*)p->d.filt, p->d.blk_logz, p->d.sweep,
+                           p->d.status, rescue_args(p), kNegPairs, p->d.blk_la, p->d.endrow,
+                           p->d.prep, fc);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     // L = 32 chains: worldline pairs per wavefront; other chains: one padded tile each
-    if (p->n_fwd32_tasks > 0) {
+    if (classes == 1 && p->n_fwd32_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_fwd32_tasks + kWaves - 1) / kWaves);
         hipLaunchKernelGGL(k_forward_mfma2<32>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwd32_tasks, p->n_fwd32_tasks, p->d.cmat, (const float*)aux,
@@ -1702,7 +1835,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (p->n_fwdx_tasks > 0) {
+    if (classes == 1 && p->n_fwdx_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_fwdx_tasks + kWaves - 1) / kWaves);
         hipLaunchKernelGGL(k_forward_mfma<0>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwdx_tasks, p->n_fwdx_tasks, p->d.cmat, (const float*)aux,
@@ -1736,8 +1869,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
     }
     // small lattices, packed block-diagonally: L <= 16 two-by-two, L <= 8 four-by-four; with
     // shared filters, tiles of representatives from k_dedup's dense lists
-    const bool shared_packs = p->d.fwdpc_tasks && !p->share_off;
-    if (p->n_fwdp2_tasks > 0) {
+    if (classes == 1 && p->n_fwdp2_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_fwdp2_tasks + kWaves - 1) / kWaves);
         hipLaunchKernelGGL((k_forward_pack<2, kPackTiles>), dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwdp_tasks, p->n_fwdp2_tasks, p->d.cmatp, (const float*)aux,
@@ -1748,7 +1880,7 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (p->n_fwdp4_tasks > 0) {
+    if (classes == 1 && p->n_fwdp4_tasks > 0) {
         const unsigned blocks = (unsigned)((p->n_fwdp4_tasks + kWaves - 1) / kWaves);
         hipLaunchKernelGGL((k_forward_pack<4, kPackTiles>), dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwdp_tasks + p->n_fwdp2_tasks, p->n_fwdp4_tasks, p->d.cmatp,
