@@ -1162,7 +1162,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         incl += dpp_f64<0x114>(incl);
         incl += dpp_f64<0x118>(incl);
         const double excl = dpp_f64<0x111>(incl);  // the previous lane's inclusive sum (0 first)
-        const double T_in = __shfl(incl, gbase + 15, 64);
+        const double T_in = dpp_f64<0x15F>(incl);  // row_newbcast:15, the group's total
         const double tau = u * T_in;
         const bool fin = T_in > 0.0 && isfinite(T_in);
         const uint32_t gm =
@@ -1193,11 +1193,19 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
             }
         const bool cert_l = li == src && pick >= 0 &&
                             win_certified(c_lo, c_hi, tau, gout + kWinSlack * T_in);
-        const int packed = __shfl((cert_l ? 1 << 16 : 0) | (py << 8) | px, gbase + src, 64);
-        const bool cert = gm != 0 && (packed >> 16) != 0;
-        // FP32 plans: a site drawn from a filter value below kRangeFloor is redrawn in FP64
-        const double fpick = __shfl(fp, gbase + src, 64);
-        if (!SLOT && rsc.words && real && cert && !(fpick >= kRangeFloorD)) halt = true;
+        // the source lane's draw to its group: only that lane contributes to an OR scan over
+        // the group's DPP row, whose last lane then broadcasts it (no LDS round trip). Bit 17:
+        // the drawn site's filter value is below kRangeFloor (FP32 plans redraw it in FP64).
+        int mine = li == src ? (cert_l ? 1 << 16 : 0) | (!(fp >= kRangeFloorD) ? 1 << 17 : 0) |
+                                   (py << 8) | px
+                             : 0;
+        mine |= __builtin_amdgcn_mov_dpp(mine, 0x111, 0xF, 0xF, true);  // row_shr:1
+        mine |= __builtin_amdgcn_mov_dpp(mine, 0x112, 0xF, 0xF, true);  // row_shr:2
+        mine |= __builtin_amdgcn_mov_dpp(mine, 0x114, 0xF, 0xF, true);  // row_shr:4
+        mine |= __builtin_amdgcn_mov_dpp(mine, 0x118, 0xF, 0xF, true);  // row_shr:8
+        const int packed = __builtin_amdgcn_mov_dpp(mine, 0x15F, 0xF, 0xF, false);
+        const bool cert = gm != 0 && ((packed >> 16) & 1) != 0;
+        if (!SLOT && rsc.words && real && cert && ((packed >> 17) & 1)) halt = true;
         int nx = packed & 255, ny = (packed >> 8) & 255;
         bool need_row = false;
         n_unc += (real && !cert) ? 1 : 0;
