@@ -157,6 +157,8 @@ constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // the kernels).
 constexpr int kRescueChain = 12;
 constexpr int kRescuePerChain = 6;
+// XCDs of the MI355X; a launch deals its workgroups to them in turn.
+constexpr int kXcds = 8;
 // Slots of the FP64 re-filter (two wavefronts per SIMD of 256 CUs), (B - 1) N doubles of rows
 // plus the end tile [N]. Phase 0 and 2 give each wavefront its own slot; phase A gives each
 // representative one (k_rescue_held admits held chains while their representatives fit).

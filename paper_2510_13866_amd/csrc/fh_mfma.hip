@@ -689,8 +689,20 @@ __global__ __launch_bounds__(kThreads, 2) void k_forward_mfma2(
     const Rescue rsc, const NegPairs neg, double* __restrict__ blk_la,
     float* __restrict__ endrow, const PairTask* __restrict__ ctasks,
     const int32_t* __restrict__ ccount) {
+    // With the dense list the grid has kXcds spare workgroups. Phase A's FP64 recursions
+    // (k_rescue_share_fwd4, one workgroup per representative, the first ones of their launch)
+    // run beside this pass; workgroups are dealt to the XCDs in turn, so leaving as many leading
+    // workgroups empty as there are such representatives (when fewer than kXcds) keeps this
+    // pass's recursions off their XCDs, where a wavefront of each on one SIMD would share its
+    // matrix core.
+    int b = blockIdx.x;
+    if (ccount) {
+        const int n_a = rsc.words ? rsc.words[6] : 0;
+        b -= n_a < kXcds ? n_a : 0;
+        if (b < 0) return;
+    }
     forward_mfma2_body<LFIX>(
-        __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6)), chains, tasks,
+        __builtin_amdgcn_readfirstlane(b * kWaves + (threadIdx.x >> 6)), chains, tasks,
         n_tasks, cmat, aux, W, wshift, aux_elems, total_slices, paths, perm, filt, blk_logz,
         sweep_ptr, status, rsc, neg, blk_la, endrow, ctasks, ccount);
 }
@@ -1824,7 +1836,9 @@ hipError_t launch_forward_mfma(fh_plan p, const void* aux, const int32_t* paths,
     }
     // L = 32 chains: worldline pairs per wavefront; other chains: one padded tile each
     if (classes == 1 && p->n_fwd32_tasks > 0) {
-        const unsigned blocks = (unsigned)((p->n_fwd32_tasks + kWaves - 1) / kWaves);
+        const bool dense = p->d.fwd32c_tasks && !p->share_off;
+        const unsigned blocks =
+            (unsigned)((p->n_fwd32_tasks + kWaves - 1) / kWaves + (dense ? kXcds : 0));
         hipLaunchKernelGGL(k_forward_mfma2<32>, dim3(blocks), dim3(kThreads), 0, s, p->d.chains,
                            p->d.fwd32_tasks, p->n_fwd32_tasks, p->d.cmat, (const float*)aux,
                            (const float*)p->d.W, p->d.wshift, p->aux_elems, p->total_slices,
