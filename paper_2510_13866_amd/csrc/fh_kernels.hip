@@ -1152,8 +1152,10 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int dx = cx - xs[k], dy = cy - ys[k];  // in (-L, L)
-            const double fk = (real && qv[k]) ? (double)fv[k] : 0.0;
-            acc += (fk > 0.0 ? fk : 0.0) * (g[dy] * g[dx]);
+            // max(f, 0) of the window's filter values (0 off the window and for NaN), selected
+            // in the rows' own precision
+            const T fk = (real && qv[k] && fv[k] > T(0)) ? fv[k] : T(0);
+            acc += (double)fk * (g[dy] * g[dx]);
             P[k] = acc;
         }
         double incl = acc;  // inclusive scan over the group's 16 lanes (one DPP row)
@@ -1168,30 +1170,27 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         const uint32_t gm =
             (uint32_t)(__ballot(real && fin && incl > tau && acc > 0.0) >> gbase) & 0xFFFFu;
         const int src = gm ? __ffs((int)gm) - 1 : 0;
-        int pick = -1;
-        double c_lo = excl, c_hi = 0.0;
+        // The lane's cumulative sums E[k + 1] = excl + P[k] rise with k (nonnegative terms,
+        // monotone rounding), so the first rank whose sum exceeds tau is the number of sums not
+        // above it (K: none); the bracket (E[pick], E[pick + 1]) and the site follow from it by
+        // a two-level select (K = 4).
+        static_assert(K == 4, "the selects below take four ranks");
+        double E[K + 1];
+        E[0] = excl;
+        int pick = 0;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const double ck = excl + P[k];
-            if (pick < 0) {
-                if (ck > tau) {
-                    pick = k;
-                    c_hi = ck;
-                } else {
-                    c_lo = ck;
-                }
-            }
+            E[k + 1] = excl + P[k];
+            pick += E[k + 1] > tau ? 0 : 1;
         }
-        int px = xs[0], py = ys[0];
-        double fp = (double)fv[0];
-#pragma unroll
-        for (int k = 1; k < K; ++k)
-            if (k == pick) {
-                px = xs[k];
-                py = ys[k];
-                fp = (double)fv[k];
-            }
-        const bool cert_l = li == src && pick >= 0 &&
+        const bool q1 = (pick & 2) != 0, q0 = (pick & 1) != 0;
+        auto sel = [&](auto a0, auto a1, auto a2, auto a3) {
+            return q1 ? (q0 ? a3 : a2) : (q0 ? a1 : a0);
+        };
+        const double c_lo = sel(E[0], E[1], E[2], E[3]), c_hi = sel(E[1], E[2], E[3], E[4]);
+        const int px = sel(xs[0], xs[1], xs[2], xs[3]), py = sel(ys[0], ys[1], ys[2], ys[3]);
+        const double fp = (double)sel(fv[0], fv[1], fv[2], fv[3]);
+        const bool cert_l = li == src && pick < K &&
                             win_certified(c_lo, c_hi, tau, gout + kWinSlack * T_in);
         // the source lane's draw to its group: only that lane contributes to an OR scan over
         // the group's DPP row, whose last lane then broadcasts it (no LDS round trip). Bit 17:
