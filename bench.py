@@ -453,16 +453,23 @@ def main():
         for (c, _, _) in last:
             per_chain[c] += 1
         log("  U=%g: blocks queued for FP64 in the last sweep, per chain: %s" % (U, per_chain))
-        return S, A, P, ms, each, redrawn
+        causes = fhmc.fh_debug_rescue_causes(S.plan)
+        log("  U=%g: blocks queued since the start, by floor (step, end, draw, fft): %s" %
+            (U, list(causes)))
+        return S, A, P, ms, each, redrawn, causes
 
-    S, A, P, ms, each, redrawn = chain(args.U, prec, draw_flag, args.warmup, args.steps)
+    S, A, P, ms, each, redrawn, causes = chain(args.U, prec, draw_flag, args.warmup, args.steps)
     ms_step = ms / args.steps
     value = sites * args.steps / (ms / 1e3)
     n_blocks = sum(d.n_particles for d in descs) * args.steps
     log("  %.3f ms/sweep, %.3e site-slice updates/s; blocks redrawn in FP64: %d of %d" %
         (ms_step, value, redrawn, n_blocks))
     extra = {"per_sweep_ms": chain_summary(each, args.warmup),
-             "blocks_redrawn_fp64": {"count": int(redrawn), "of": int(n_blocks)}}
+             "blocks_redrawn_fp64": {"count": int(redrawn), "of": int(n_blocks)},
+             "fp64_queue_causes": {"step_floor": int(causes[0]), "end_weight": int(causes[1]),
+                                   "draw_floor": int(causes[2]), "fft_forward": int(causes[3]),
+                                   "counted": "blocks queued by the FP32 kernels since the "
+                                              "plan was made, warmup included"}}
     log("  per sweep: %s" % extra["per_sweep_ms"])
 
     # The kernels of the timed sweeps, timed with HIP events the library records in each sweep
@@ -594,12 +601,13 @@ def main():
         for U in (2.0, 4.0, 6.0):
             if U == args.U:
                 continue
-            So, _, _, msu, eachu, redu = chain(U, prec, draw_flag, args.warmup, args.steps)
+            So, _, _, msu, eachu, redu, causu = chain(U, prec, draw_flag, args.warmup, args.steps)
             So.close()
             extra["U=%g" % U] = {"ms_per_step": round(msu / args.steps, 4),
                                  "value": sites * args.steps / (msu / 1e3),
                                  "per_sweep_ms": chain_summary(eachu, args.warmup),
-                                 "blocks_redrawn_fp64": int(redu)}
+                                 "blocks_redrawn_fp64": int(redu),
+                                 "fp64_queue_causes": [int(x) for x in causu]}
             log("  U=%g: %.3f ms/sweep" % (U, msu / args.steps))
     if not args.no_error and args.precision != "fp64":
         # the FP32 plan against the FP64 plain path on the initial state and on the state after
@@ -615,7 +623,7 @@ def main():
         log("  error vs the FP64 plain path: %s" % errs)
 
     if not args.no_plain and args.precision != "fp64":
-        S64, _, _, ms64, each64, _ = chain(args.U, fhmc.FH_FP64, 0, args.warmup, args.steps)
+        S64, _, _, ms64, each64, _, _ = chain(args.U, fhmc.FH_FP64, 0, args.warmup, args.steps)
         S64.close()
         ms64 /= args.steps
         extra["fp64_plain"] = {"ms_per_step": round(ms64, 4),

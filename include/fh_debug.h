@@ -109,6 +109,14 @@ int fh_debug_share_filters(fh_plan plan, int32_t enable);
  * skipped by the next forward pass's FP32 kernels and re-filtered whole. FP64 plans write 0. */
 int fh_debug_rescue_holds(fh_plan plan, int32_t* holds);
 
+/* FP32 plans: why the kernels queued blocks for the FP64 re-filter, counted since fh_init (a
+ * block met by several floors, or in several passes, counts each time): counts[0] a forward
+ * step's W-weighted mass below the step floor (or not finite), counts[1] an end weight below
+ * the range floor, counts[2] a backward draw at a site whose filter value is below the range
+ * floor (or with no positive weight), counts[3] the FP32 FFT forward (either floor). counts
+ * holds 4 int32 written by the call (caller-owned host memory; zeros on FP64 plans). */
+int fh_debug_rescue_causes(fh_plan plan, int32_t* counts);
+
 /* Per-sweep timing for the benchmark: with enable = 1, every sweep of fh_sweep records HIP events
  * of the plan around its forward-filter kernels, its backward-sampling kernels and the FP64
  * re-filter of out-of-range blocks (FP32 plans); the sweeps are then launched eagerly (the same

@@ -1417,6 +1417,16 @@ int fh_debug_rescue_holds(fh_plan p, int32_t* holds) {
     return FH_OK;
 }
 
+int fh_debug_rescue_causes(fh_plan p, int32_t* counts) {
+    if (!p || !counts) return FH_ERR_INVALID_ARG;
+    std::fill(counts, counts + 4, 0);
+    if (!p->d.rescue) return FH_OK;
+    FH_TRY(hipDeviceSynchronize());
+    FH_TRY(hipMemcpy(counts, p->d.rescue + kRescueCause, sizeof(int32_t) * 4,
+                     hipMemcpyDeviceToHost));
+    return FH_OK;
+}
+
 int fh_debug_sweep_timing(fh_plan p, int32_t enable) {
     if (!p || (enable != 0 && enable != 1)) return FH_ERR_INVALID_ARG;
     FH_TRY(hipDeviceSynchronize());

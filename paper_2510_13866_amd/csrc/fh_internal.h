@@ -147,7 +147,9 @@ constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // (k_dedup), [6] entries of phase A's dense list of representatives (k_rescue_held), [7] entries
 // of the dense list of the padded lattices' representatives (k_dedup), [8] and [9] entries of
 // the dense lists of packed tiles of representatives (P = 2 and P = 4, k_dedup), [10]
-// representatives listed for those tiles, [11] unused, then per chain: blocks queued by the kernels in this pass
+// representatives listed for those tiles, [11 + k] the blocks queued for floor k since the
+// plan was made (kCause*: never cleared, read by fh_debug_rescue_causes), [15] unused, then per
+// chain: blocks queued by the kernels in this pass
 // (kRescueChain + c), forward passes left on FP64 (kRescueChain + n_chains + c), 1 if the chain
 // is in phase A (kRescueChain + 2 n_chains + c), the forward recursions its blocks need in this
 // pass (kRescueChain + 3 n_chains + c: the representatives of the shared filters), the hold at
@@ -155,7 +157,12 @@ constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 // hold (kRescueChain + 5 n_chains + c), then one flag per (chain, particle, block) at
 // kRescueChain + kRescuePerChain n_chains + blk_off + p nb + b (the `flags` pointer passed to
 // the kernels).
-constexpr int kRescueChain = 12;
+constexpr int kRescueChain = 16;
+// Why a kernel queued a block (rescue words 11 + cause): a forward step's W-weighted mass below
+// step_floor (or not finite), an end weight below kRangeFloor, a backward draw at a site whose
+// filter value is below kRangeFloor (or with no positive weight), an FFT forward (either floor).
+constexpr int kRescueCause = 11;
+constexpr int kCauseStep = 0, kCauseEnd = 1, kCauseDraw = 2, kCauseFft = 3;
 constexpr int kRescuePerChain = 6;
 // XCDs of the MI355X; a launch deals its workgroups to them in turn.
 constexpr int kXcds = 8;
@@ -209,7 +216,8 @@ __device__ inline bool rescue_enqueue(const Rescue& r, const ChainInfo& c, int c
 // after failed retries (k_rescue_reset; a backward pass queues after the chain's blocks were
 // expanded for this one).
 __device__ inline void rescue_push(const Rescue& r, const ChainInfo& c, int chain, int p,
-                                   int block) {
+                                   int block, int cause) {
+    atomicAdd(&r.words[kRescueCause + cause], 1);
     if (rescue_enqueue(r, c, chain, p, block)) {
         atomicAdd(&r.words[kRescueChain + chain], 1);
         atomicMax(&r.words[kRescueChain + r.n_chains + chain], kRescueHold);

@@ -369,8 +369,8 @@ __global__ __launch_bounds__(kThreads) void k_forward_fft(
     if (threadIdx.x == 0) {
         blk_logz[c.blk_off + (int64_t)t.p_a * c.nb + t.block] = lza;
         if (has_b) blk_logz[c.blk_off + (int64_t)t.p_b * c.nb + t.block] = lzb;
-        if (low[0]) rescue_push(rsc, c, t.chain, t.p_a, t.block);
-        if (has_b && low[1]) rescue_push(rsc, c, t.chain, t.p_b, t.block);
+        if (low[0]) rescue_push(rsc, c, t.chain, t.p_a, t.block, kCauseFft);
+        if (has_b && low[1]) rescue_push(rsc, c, t.chain, t.p_b, t.block, kCauseFft);
     }
 }
 
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kThreads) void k_backward(
         int chosen = cur;
         if (rsc.words && (!(total > 0.0) || !isfinite(total))) {
             // no usable FP32 weight: the block is redrawn from FP64 filters
-            if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
+            if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block, kCauseDraw);
             return;
         }
         if (!(total > 0.0) || !isfinite(total)) {
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(kThreads) void k_backward(
             if (chosen < 0) chosen = cur;
             // FP32 plans: a site drawn from a filter value near FP32's floor (kRangeFloor)
             if (rsc.words && !((double)f[chosen] >= kRangeFloorD)) {
-                if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
+                if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block, kCauseDraw);
                 return;
             }
         }
@@ -637,7 +637,7 @@ __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const doubl
         int chosen = cur;
         if (rsc.words && (!(total > 0.0) || !isfinite(total))) {
             // no usable FP32 weight: the block is redrawn from FP64 filters
-            if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
+            if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block, kCauseDraw);
             return;
         }
         if (!(total > 0.0) || !isfinite(total)) {
@@ -677,7 +677,7 @@ __device__ void backward_task(const DrawTask& t, const ChainInfo& c, const doubl
             }
             // FP32 plans: a site drawn from a filter value near FP32's floor (kRangeFloor)
             if (rsc.words && !(fsel >= kRangeFloorD)) {
-                if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
+                if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block, kCauseDraw);
                 return;
             }
         }
@@ -834,7 +834,7 @@ __global__ __launch_bounds__(kThreads, sizeof(T) == 4 ? 4 : 3) void k_backward_l
             }
             if (low && real) {
                 halted = true;  // an FP32 value near FP32's floor decides it: FP64 redraw
-                if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
+                if (lane == 0) rescue_push(rsc, c, t.chain, t.p, t.block, kCauseDraw);
             }
             chosen = real ? chosen : cur;
             pc[(int64_t)((start + j) % L_tau) * c.np + (start + j >= L_tau ? qn : t.p)] = chosen;
@@ -1267,7 +1267,7 @@ __global__ __launch_bounds__(kThreads) void k_backward_win(
         if (li == (s & 15)) pend = cur;
     }
     if (nd_max > 0) flush((nd_max - 1) & ~15);
-    if (halt && li == 0) rescue_push(rsc, c, t.chain, t.p, t.block);
+    if (halt && li == 0) rescue_push(rsc, c, t.chain, t.p, t.block, kCauseDraw);
     if (err != 0 && li == 0) set_status(status, err, t.chain);  // the block's first error
     if (count_uncertified && active && li == 0 && n_unc > 0)
         atomicAdd(&bw_state[kBwCounts + t.chain], n_unc);
@@ -1872,7 +1872,7 @@ __global__ void k_member_logz(const ChainInfo* __restrict__ chains, int n_chains
             paths[c.path_off + (int64_t)((start + len) % L_tau) * c.np + qe], c.N, status, ci);
         const int64_t ri = c.blk_off + (int64_t)rp * c.nb + b;
         const float hv = endrow[c.end_off + ((int64_t)rp * c.nb + b) * c.N + e];
-        if (!(hv >= kRangeFloor)) rescue_push(rsc, c, ci, p, b);
+        if (!(hv >= kRangeFloor)) rescue_push(rsc, c, ci, p, b, kCauseEnd);
         blk_logz[i] = blk_la[ri] + log((double)hv);
     }
 }

@@ -287,7 +287,8 @@ __device__ __forceinline__ void forward_mfma_body(
     hv = __shfl(hv, le, 64);
     la -= log(prod);
     if (lane == 0) {
-        if (low || !(hv >= kRangeFloor)) rescue_push(rsc, c, t.chain, t.p, t.block);
+        if (low || !(hv >= kRangeFloor))
+            rescue_push(rsc, c, t.chain, t.p, t.block, low ? kCauseStep : kCauseEnd);
         blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log((double)hv);
     }
     if (c.dedup) {  // what the worldlines sharing these rows need: log Z so far, the end tile
@@ -650,10 +651,12 @@ __device__ __forceinline__ void forward_mfma2_body(
         la0 -= log(prod0);
         if constexpr (PAIR) la1 -= log(prod1);
         if (lane == 0) {
-            if (low0 || !(hv0 >= kRangeFloor)) rescue_push(rsc, c, t.chain, pp[0], t.block);
+            if (low0 || !(hv0 >= kRangeFloor))
+                rescue_push(rsc, c, t.chain, pp[0], t.block, low0 ? kCauseStep : kCauseEnd);
             blk_logz[c.blk_off + (int64_t)pp[0] * c.nb + t.block] = la0 + log((double)hv0);
             if constexpr (PAIR) {
-                if (low1 || !(hv1 >= kRangeFloor)) rescue_push(rsc, c, t.chain, pp[1], t.block);
+                if (low1 || !(hv1 >= kRangeFloor))
+                    rescue_push(rsc, c, t.chain, pp[1], t.block, low1 ? kCauseStep : kCauseEnd);
                 blk_logz[c.blk_off + (int64_t)pp[1] * c.nb + t.block] = la1 + log((double)hv1);
             }
         }
@@ -897,7 +900,8 @@ __global__ __launch_bounds__(kThreads) void k_forward_mfma64(
     hv = __shfl(hv, tx + 32 * ((ty >> 2) & 1), 64);
     la -= log(prod);
     if (lane == 0) {
-        if (low || !(hv >= kRangeFloor)) rescue_push(rsc, c, t.chain, t.p, t.block);
+        if (low || !(hv >= kRangeFloor))
+            rescue_push(rsc, c, t.chain, t.p, t.block, low ? kCauseStep : kCauseEnd);
         blk_logz[c.blk_off + (int64_t)t.p * c.nb + t.block] = la + log((double)hv);
     }
 }
@@ -1144,7 +1148,8 @@ __device__ __forceinline__ void forward_pack_body(
         }
     const double la_end = la - (log(mant) + (double)ex2 * 0.69314718055994530942);
     if (owner) {
-        if (low || !(hv >= kRangeFloor)) rescue_push(rsc, c, t.chain, opw, t.block);
+        if (low || !(hv >= kRangeFloor))
+            rescue_push(rsc, c, t.chain, opw, t.block, low ? kCauseStep : kCauseEnd);
         blk_logz[c.blk_off + (int64_t)opw * c.nb + t.block] = la_end + log((double)hv);
         if (c.dedup) blk_la[c.blk_off + (int64_t)opw * c.nb + t.block] = la_end;
     }

@@ -109,6 +109,7 @@ _sig("fh_debug_backward_kernels", c_int32, c_void_p, POINTER(c_int32), POINTER(c
 _sig("fh_debug_forward_kernels", c_int32, c_void_p, POINTER(c_int32))
 _sig("fh_debug_backward_adapt", c_int32, c_void_p, c_int32, POINTER(c_int32))
 _sig("fh_debug_rescue_holds", c_int32, c_void_p, POINTER(c_int32))
+_sig("fh_debug_rescue_causes", c_int32, c_void_p, POINTER(c_int32))
 _sig("fh_debug_fill_filter_row", c_int32, c_void_p, c_int32, c_int32, c_int32, c_double)
 _sig("fh_debug_representatives", c_int32, c_void_p, POINTER(c_int32), c_int64, POINTER(c_int64))
 _sig("fh_debug_share_filters", c_int32, c_void_p, c_int32)
@@ -290,6 +291,16 @@ def fh_debug_rescue(plan, cap=0):
                                buf.ctypes.data_as(POINTER(c_int32)), cap), "fh_debug_rescue")
     n = min(cap, last.value)
     return last.value, total.value, [tuple(int(v) for v in buf[i]) for i in range(n)], whole.value
+
+
+def fh_debug_rescue_causes(plan):
+    """Blocks queued for the FP64 re-filter since fh_init, by floor: (step mass, end weight,
+    backward draw, FP32 FFT forward)."""
+    import numpy as np
+    buf = np.zeros(4, dtype=np.int32)
+    _check(lib.fh_debug_rescue_causes(plan, buf.ctypes.data_as(POINTER(c_int32))),
+           "fh_debug_rescue_causes")
+    return buf
 
 
 def fh_debug_rescue_holds(plan, n_chains):

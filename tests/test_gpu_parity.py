@@ -1554,7 +1554,10 @@ def test_big_lattice_chain_through_collapse(lib, case):
         say("  after sweep", s, ": largest a |field|",
             float(np.abs(S.unpack_aux(A)[0]).max()) * np.sqrt(abs(d.U) * d.dtau))
     say("  blocks redrawn in FP64 per sweep:", redrawn)
+    causes = fhmc.fh_debug_rescue_causes(S.plan)
+    say("  queued by floor (step, end, draw, fft):", list(causes))
     assert sum(redrawn) > 0      # the chain passed through out-of-range states
+    assert causes.sum() > 0      # and the kernels say which floor queued them
     assert checked > 0           # and such a state was compared with the oracle
     S.close()
 
