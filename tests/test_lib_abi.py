@@ -145,6 +145,8 @@ def test_null_plan_calls_are_rejected(fhmc):
     assert fhmc.lib.fh_destroy(None) == fhmc.FH_ERR_INVALID_ARG
     assert fhmc.lib.fh_sweep(None, None, None, 0, 1, None) == fhmc.FH_ERR_INVALID_ARG
     assert fhmc.lib.fh_get_status(None, None, None) == fhmc.FH_ERR_INVALID_ARG
+    assert fhmc.lib.fh_debug_rescue_causes(None, None) == fhmc.FH_ERR_INVALID_ARG
+    assert fhmc.lib.fh_debug_forward_kernels(None, None) == fhmc.FH_ERR_INVALID_ARG
     assert fhmc.fh_strerror(fhmc.FH_ERR_STATE) == "call order violated"
 
 
