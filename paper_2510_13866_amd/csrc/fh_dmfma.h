@@ -41,9 +41,29 @@ __device__ inline Tile64 circ64(const Tile64& X, const double (&Cb)[16]) {
     return Y;
 }
 
+// A 64-bit lane exchange by DPP (every lane has its source lane under these controls).
+template <int CTRL>
+__device__ inline double dpp_swap_f64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32));
+}
+__device__ inline double lane_f64(double v, int lane) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, (uint64_t)lo | ((uint64_t)hi << 32));
+}
+// Sum over the wavefront, the same bits in every lane: each 16-lane row by DPP exchanges (an
+// addition and its mirror give the same bits), then the four row sums in one fixed order. No
+// LDS round trip (the FP64 recursions wait on this sum every step).
 __device__ inline double wave_sum_f64(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_swap_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_swap_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_swap_f64<0x141>(v);  // row_half_mirror
+    v += dpp_swap_f64<0x140>(v);  // row_mirror
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 // Tile coordinates of element (tile q, register r) of a lane: x = 16 (q & 1) + lane % 16,
